@@ -1,0 +1,184 @@
+"""Seeded synthetic canonical tensors shaped like the paper's workloads.
+
+This module only *builds inputs*: side matrices U^(l) (n x R, column-major,
+column nu = canonical vector u_nu^(l)) and weights xi.  It holds none of the
+reduction's arithmetic (no norms, Grams, SVDs, projections or cores), so both
+the HIP path and the CPU oracle may draw their inputs from it.
+
+Workload shapes follow the paper's own sources of large-rank canonical tensors:
+  * sums of Gaussians sampled on a uniform grid (Section 4.1, the sinc /
+    Laplace-Gauss route to radial kernels, eqs. eqn:laplace, eqn:sinc_Newt);
+  * the Newton kernel 1/|x| as a Gaussian sum, from the Laplace-Gauss identity
+    1/z = (2/sqrt(pi)) int_0^inf exp(-z^2 t^2) dt (eq. eqn:Laplace_Newton);
+  * Hadamard products of canonical tensors, whose rank is the product of the
+    factors' ranks (Section 4.2, Lemma 4.3; Section 3, eq. eq:rho_ten).
+
+Grid: cell centres x_i = -b + (i + 1/2) * 2b/n, i = 0..n-1 (the paper samples
+at "centers of discretization intervals", Section 3; mesh h = 2b/n, Section 4.1).
+
+Random numbers come from numpy's counter-based Philox generator keyed by
+(workload id, seed), so every machine draws the same stream.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# workload ids used as the first Philox key word
+WL_SMALL_GAUSS = 0      # n=64, R=200 Gaussian sum
+WL_NEWTON_CENTRES = 1   # n=1024, R=4096: 128 charges x 32-term 1/|x| sum
+WL_HADAMARD = 2         # n=512, R=90000 Hadamard product of two 300-term sums
+WL_BATCH = 3            # 256 uneven (n, R) problems
+WL_RANKNET = 4          # rank-proposal training / evaluation draws
+WL_LOWRANK = 10         # exactly-low-rank test inputs
+WL_RANDOM = 11          # dense random test inputs
+
+
+def rng(workload: int, seed: int) -> np.random.Generator:
+    """Philox stream keyed by (workload, seed)."""
+    return np.random.Generator(np.random.Philox(key=[int(workload), int(seed)]))
+
+
+def grid(n: int, b: float = 10.0) -> np.ndarray:
+    """Cell centres of a uniform n-cell grid on [-b, b]."""
+    h = 2.0 * b / n
+    return -b + (np.arange(n, dtype=np.float64) + 0.5) * h
+
+
+@dataclass
+class CanonicalInput:
+    """A d=3 canonical tensor A = sum_nu xi_nu u1_nu (x) u2_nu (x) u3_nu."""
+    U: list            # three float64 arrays, shape (n, R), Fortran order
+    xi: np.ndarray     # float64, shape (R,)
+    eps: float
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.U[0].shape[0])
+
+    @property
+    def R(self) -> int:
+        return int(self.U[0].shape[1])
+
+
+def gaussian_side_matrices(x: np.ndarray, alpha: np.ndarray, centres: np.ndarray) -> list:
+    """u_nu^(l)(i) = exp(-alpha_nu (x_i - c_{nu,l})^2) for l = 0, 1, 2.
+
+    alpha: (R,), centres: (R, 3).  Returns three (n, R) Fortran-ordered arrays.
+    """
+    out = []
+    for l in range(3):
+        d = x[:, None] - centres[None, :, l]
+        out.append(np.asfortranarray(np.exp(-alpha[None, :] * d * d)))
+    return out
+
+
+def small_gaussian_sum(seed: int = 0, n: int = 64, R: int = 200, b: float = 10.0,
+                       eps: float = 1e-6) -> CanonicalInput:
+    """n=64 grid on [-10,10]^3, R Gaussians exp(-a_k |x-c_k|^2) factored per axis,
+    a_k log-uniform in [0.5, 50], c_k uniform in [-5,5]^3, xi_k uniform in [0.5, 1.5]."""
+    g = rng(WL_SMALL_GAUSS, seed)
+    alpha = np.exp(g.uniform(math.log(0.5), math.log(50.0), size=R))
+    centres = g.uniform(-5.0, 5.0, size=(R, 3))
+    xi = g.uniform(0.5, 1.5, size=R)
+    U = gaussian_side_matrices(grid(n, b), alpha, centres)
+    return CanonicalInput(U, xi, eps, name=f"gauss-n{n}-R{R}",
+                          meta=dict(alpha=alpha, centres=centres, b=b))
+
+
+def newton_gaussian_sum(K: int = 32, lo: float = 1e-2, hi: float = 1e4):
+    """K-term Gaussian sum for 1/|x| with exponents log-spaced in [lo, hi].
+
+    From 1/z = (1/sqrt(pi)) int exp(-z^2 e^s) e^{s/2} ds (substitute t^2 = e^s in
+    the Laplace-Gauss identity for the Newton kernel) and the trapezoid rule in
+    s with step h: alpha_k = e^{s_k}, w_k = h sqrt(alpha_k) / sqrt(pi).
+    All weights are positive.
+    """
+    s = np.linspace(math.log(lo), math.log(hi), K)
+    h = s[1] - s[0]
+    alpha = np.exp(s)
+    w = h * np.sqrt(alpha) / math.sqrt(math.pi)
+    return alpha, w
+
+
+def newton_centres(seed: int = 0, n: int = 1024, n_centres: int = 128, K: int = 32,
+                   b: float = 10.0, box: float = 6.0, eps: float = 1e-5,
+                   workload: int = WL_NEWTON_CENTRES) -> CanonicalInput:
+    """sum_c q_c / |x - c| over n_centres random centres in [-box, box]^3 with
+    random charges q_c = +-1, each 1/|x-c| a K-term Gaussian sum: R = n_centres*K."""
+    g = rng(workload, seed)
+    centres_c = g.uniform(-box, box, size=(n_centres, 3))
+    q = np.where(g.uniform(size=n_centres) < 0.5, -1.0, 1.0)
+    alpha_k, w_k = newton_gaussian_sum(K)
+    alpha = np.tile(alpha_k, n_centres)
+    centres = np.repeat(centres_c, K, axis=0)
+    xi = np.repeat(q, K) * np.tile(w_k, n_centres)
+    U = gaussian_side_matrices(grid(n, b), alpha, centres)
+    return CanonicalInput(U, xi, eps, name=f"newton-n{n}-R{n_centres * K}",
+                          meta=dict(alpha=alpha, centres=centres, q=q, b=b))
+
+
+def hadamard_product(seed: int = 0, n: int = 512, R_each: int = 300, b: float = 10.0,
+                     eps: float = 1e-4) -> CanonicalInput:
+    """Pointwise product of two Gaussian sums of R_each terms (each drawn like
+    small_gaussian_sum): columns u_a * w_b for all (a, b), weights xi_a * eta_b,
+    so R = R_each^2 (the rank-multiplying Hadamard product of canonical tensors)."""
+    g = rng(WL_HADAMARD, seed)
+    x = grid(n, b)
+    parts = []
+    for _ in range(2):
+        alpha = np.exp(g.uniform(math.log(0.5), math.log(50.0), size=R_each))
+        centres = g.uniform(-5.0, 5.0, size=(R_each, 3))
+        xi = g.uniform(0.5, 1.5, size=R_each)
+        parts.append((gaussian_side_matrices(x, alpha, centres), xi))
+    (Ua, xa), (Ub, xb) = parts
+    U = []
+    for l in range(3):
+        P = (Ua[l][:, :, None] * Ub[l][:, None, :]).reshape(n, R_each * R_each)
+        U.append(np.asfortranarray(P))
+    xi = (xa[:, None] * xb[None, :]).reshape(-1)
+    return CanonicalInput(U, xi, eps, name=f"hadamard-n{n}-R{R_each * R_each}")
+
+
+def batch_shapes(seed: int = 0, count: int = 256):
+    """(n, R) for the uneven batch: n uniform in {128,...,2048}, R log-uniform in [64, 8192]."""
+    g = rng(WL_BATCH, seed)
+    ns = g.choice(np.array([128, 256, 512, 1024, 2048]), size=count)
+    Rs = np.rint(np.exp(g.uniform(math.log(64), math.log(8192), size=count))).astype(int)
+    return [(int(a), int(c)) for a, c in zip(ns, Rs)]
+
+
+def batch_problem(seed: int, index: int, n: int, R: int, eps: float = 1e-5) -> CanonicalInput:
+    """One problem of the uneven batch: the first R terms of ceil(R/32) charges x 32
+    Gaussian terms (the n=1024, R=4096 construction at another size)."""
+    nc = (R + 31) // 32
+    full = newton_centres(seed=seed * 4096 + index, n=n, n_centres=nc, eps=eps,
+                          workload=WL_BATCH)
+    U = [np.asfortranarray(u[:, :R]) for u in full.U]
+    return CanonicalInput(U, full.xi[:R].copy(), eps, name=f"batch{index}-n{n}-R{R}")
+
+
+def exactly_low_rank(seed: int, n: int, R: int, ranks=(3, 4, 5), eps: float = 1e-8,
+                     signed: bool = True) -> CanonicalInput:
+    """U^(l) = Q_l C_l with Q_l (n x r_l) orthonormal and C_l (r_l x R) Gaussian, so
+    every side matrix has rank exactly r_l (up to rounding)."""
+    g = rng(WL_LOWRANK, seed)
+    U = []
+    for r in ranks:
+        Q, _ = np.linalg.qr(g.standard_normal((n, r)))
+        C = g.standard_normal((r, R))
+        U.append(np.asfortranarray(Q @ C))
+    xi = g.standard_normal(R) if signed else g.uniform(0.5, 1.5, size=R)
+    return CanonicalInput(U, xi, eps, name=f"lowrank-n{n}-R{R}-r{ranks}")
+
+
+def random_dense(seed: int, n: int, R: int, eps: float = 1e-3) -> CanonicalInput:
+    """Gaussian random side matrices and weights (no structure, slow singular decay)."""
+    g = rng(WL_RANDOM, seed)
+    U = [np.asfortranarray(g.standard_normal((n, R))) for _ in range(3)]
+    xi = g.standard_normal(R)
+    return CanonicalInput(U, xi, eps, name=f"random-n{n}-R{R}")

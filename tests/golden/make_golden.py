@@ -1,0 +1,81 @@
+"""Write the stored expected values for the full-size parity tests.
+
+Every value written here comes from the CPU oracle (oracle/) on inputs from the
+seeded generators; nothing is read from the GPU path.
+
+    python tests/golden/make_golden.py newton1024 [seed]
+
+newton1024: n=1024 grid on [-10,10]^3, R=4096 = 128 random +-1 charges x a
+32-term Gaussian sum for 1/|x| (exponents log-spaced in [1e-2, 1e4]), eps=1e-5.
+Stores ranks, all singular values per mode, |A|, |xi'|, tau, tails at the cut,
+the Theorem 2.3 bound, the exact error (Gram identity) and sampled core entries
+at indices whose singular vectors are well separated.
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_2201_12663_amd import inputs  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def separated(sigma, r, rel_gap=1e-4):
+    """Indices k < r whose squared singular value is apart from its neighbours
+    by more than rel_gap * sigma_1^2 (their singular vectors are well defined)."""
+    s2 = sigma ** 2
+    out = []
+    for k in range(r):
+        lo = s2[k - 1] - s2[k] if k > 0 else np.inf
+        hi = s2[k] - s2[k + 1] if k + 1 < len(s2) else np.inf
+        if min(lo, hi) > rel_gap * s2[0]:
+            out.append(k)
+    return out
+
+
+def newton1024(seed=0):
+    t0 = time.time()
+    ci = inputs.newton_centres(seed)
+    res = oracle.rhosvd(ci.U, ci.xi, ci.eps, with_core=False)
+    Ut, xip, _, _ = oracle.normalize(ci.U, ci.xi)
+    t1 = time.time()
+    err = oracle.error_gram(Ut, xip, res.Z)
+    t2 = time.time()
+    g = np.random.default_rng(1234)
+    sep = [separated(res.sigma[l], res.ranks[l]) for l in range(3)]
+    picks = [np.sort(g.choice(sep[l], size=min(12, len(sep[l])), replace=False)) for l in range(3)]
+    sub = oracle.core([res.V[l][picks[l], :] for l in range(3)], res.xip)
+    samples = []
+    for a, j1 in enumerate(picks[0]):
+        for b, j2 in enumerate(picks[1]):
+            for c, j3 in enumerate(picks[2]):
+                if (a + b + c) % 7 == 0:
+                    samples.append([int(j1), int(j2), int(j3), float(sub[a, b, c])])
+    out = dict(
+        workload="newton-n1024-R4096", seed=seed, eps=ci.eps,
+        ranks=list(res.ranks), a_norm=res.a_norm, xi_norm=res.xi_norm, tau=res.tau,
+        tail_at_rank=[float(res.tails[l][res.ranks[l]]) for l in range(3)],
+        tail_below_rank=[float(res.tails[l][res.ranks[l] - 1]) for l in range(3)],
+        bound=res.bound, error=err, sweeps=res.sweeps,
+        sigma=[[float(x) for x in res.sigma[l]] for l in range(3)],
+        beta_samples=samples,
+        z_sign_rule="largest-magnitude entry of each column positive",
+        seconds=dict(reduce=t1 - t0, error=t2 - t1),
+    )
+    path = os.path.join(HERE, f"newton1024_seed{seed}.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(path, out["ranks"], "err/|A|", err / res.a_norm, "secs", out["seconds"])
+
+
+if __name__ == "__main__":
+    which = sys.argv[1] if len(sys.argv) > 1 else "newton1024"
+    seed = int(sys.argv[2]) if len(sys.argv) > 2 else 0
+    {"newton1024": newton1024}[which](seed)

@@ -1,0 +1,214 @@
+"""Checks that pin the CPU oracle to facts fixed by the paper and by mathematics,
+not by the oracle itself.  Each check takes the oracle module (or a patched copy
+with a planted mistake) and returns None on success or raises AssertionError.
+
+Pins:
+  svd_known_spectrum   X = QL diag(s) QR^T with chosen s: singular values and
+                       singular subspaces are known in closed form
+  svd_vs_lapack        a library SVD (LAPACK) on random matrices
+  lowrank_exact        U^(l) = Q_l C_l has rank r_l exactly: ranks reproduced and
+                       the Tucker reconstruction is exact to rounding
+  brute_force_error    n <= 32: materialize A and A_r, compare errors, check the
+                       relative error against eps (Theorem 2.3 guarantee)
+  hosvd_special_case   constant xi and two orthonormal factor matrices: the
+                       RHOSVD subspaces equal truncated-HOSVD subspaces of the
+                       full tensor (textbook HOSVD via SVDs of unfoldings)
+  projection_identity  V V^T = diag(sigma_1^2..sigma_r^2)   (Z0^T U = D0 V0^T)
+  pythagoras           |beta|^2 + err^2 = |A|^2 (A_r is an orthogonal projection)
+  theorem23            err <= |xi'| sum_l t_{l,r_l} on signed random inputs
+  corollary24          (A) one orthonormal side matrix: |A| = |xi'|;
+                       (B) non-negative data: |xi'| <= |A|
+  degenerate           R = 1 and identical columns give rank (1,1,1), beta = +-xi'
+  invariances          term permutation, column rescaling with compensated xi,
+                       orthogonal row transform of one mode
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from paper_2201_12663_amd import inputs
+
+
+def _orth(g, n, k):
+    Q, _ = np.linalg.qr(g.standard_normal((n, k)))
+    return Q
+
+
+def _proj_dist(Za, Zb):
+    return float(np.linalg.norm(Za @ Za.T - Zb @ Zb.T, 2))
+
+
+def svd_known_spectrum(orc):
+    g = inputs.rng(inputs.WL_RANDOM, 101)
+    for (p, q) in [(40, 90), (90, 40), (33, 33)]:
+        m = min(p, q)
+        s = np.geomspace(1.0, 1e-9, m)
+        s[5] = s[4] * (1 - 1e-3)            # a close pair
+        QL, QR = _orth(g, p, m), _orth(g, q, m)
+        X = QL @ np.diag(s) @ QR.T
+        sig, Z, _ = orc.svd_left(X)
+        assert sig.shape == (m,) and Z.shape == (p, m)
+        rel = np.abs(sig - s) / s
+        # Jacobi after QR: absolute error ~ u * sigma_1
+        assert np.all(np.abs(sig - s) <= 1e-13 * s[0] + 1e-12 * s), rel.max()
+        # left subspaces of the leading k singular values (gap >= ~3x for k != 5)
+        for k in (1, 3, 10):
+            assert _proj_dist(Z[:, :k], QL[:, :k]) < 1e-10, k
+        assert np.max(np.abs(Z.T @ Z - np.eye(m))) < 1e-12
+
+
+def svd_vs_lapack(orc):
+    g = inputs.rng(inputs.WL_RANDOM, 102)
+    for (p, q) in [(17, 50), (50, 17), (64, 200)]:
+        X = g.standard_normal((p, q))
+        sig, Z, _ = orc.svd_left(X)
+        Ul, sl, _ = np.linalg.svd(X, full_matrices=False)
+        assert np.allclose(sig, sl, rtol=1e-12, atol=1e-13 * sl[0])
+        # sign-free comparison of each singular vector (random spectra are simple)
+        for k in range(min(p, q)):
+            assert abs(abs(Z[:, k] @ Ul[:, k]) - 1.0) < 1e-9, k
+
+
+def lowrank_exact(orc):
+    for (n, R, ranks) in [(20, 50, (3, 4, 5)), (30, 12, (2, 5, 7)), (25, 25, (1, 6, 9))]:
+        ci = inputs.exactly_low_rank(7, n, R, ranks=ranks, eps=1e-8)
+        res = orc.rhosvd(ci.U, ci.xi, ci.eps)
+        assert tuple(res.ranks) == tuple(ranks), (res.ranks, ranks)
+        Ut, xip, _, _ = orc.normalize(ci.U, ci.xi)
+        A = orc.full_tensor(Ut, xip)
+        Ar = orc.reconstruct(res.beta, res.Z)
+        assert np.linalg.norm((A - Ar).ravel()) <= 1e-12 * np.linalg.norm(A.ravel())
+
+
+def brute_force_error(orc):
+    for seed in (1, 2):
+        ci = inputs.small_gaussian_sum(seed, n=24, R=60, eps=1e-4)
+        res = orc.rhosvd(ci.U, ci.xi, ci.eps)
+        Ut, xip, _, _ = orc.normalize(ci.U, ci.xi)
+        A = orc.full_tensor(Ut, xip)
+        anorm = float(np.linalg.norm(A.ravel()))
+        assert abs(anorm - res.a_norm) <= 1e-12 * anorm
+        e_brute = float(np.linalg.norm((A - orc.reconstruct(res.beta, res.Z)).ravel()))
+        e_gram = orc.error_gram(Ut, xip, res.Z)
+        assert abs(e_brute - e_gram) <= 1e-9 * e_brute + 1e-13 * anorm
+        assert e_brute <= ci.eps * anorm
+        assert 0 < res.ranks[0] < 24
+
+
+def hosvd_special_case(orc):
+    g = inputs.rng(inputs.WL_RANDOM, 103)
+    n, R, c = 16, 10, 1.7
+    U1 = g.standard_normal((n, R))
+    U1 /= np.linalg.norm(U1, axis=0)          # unit columns keep xi' = xi constant
+    U2 = _orth(g, n, R)
+    U3 = _orth(g, n, R)
+    xi = np.full(R, c)
+    res = orc.rhosvd([U1, U2, U3], xi, eps=1e-3)
+    Ut, xip, _, _ = orc.normalize([U1, U2, U3], xi)
+    A = orc.full_tensor(Ut, xip)
+    for l in range(3):
+        unf = np.moveaxis(A, l, 0).reshape(n, -1)
+        Ul, sl, _ = np.linalg.svd(unf, full_matrices=False)
+        # unfolding singular values = c * sigma(U~^(l))
+        m = len(res.sigma[l])
+        assert np.allclose(sl[:m], c * res.sigma[l], rtol=1e-10, atol=1e-12 * sl[0])
+        r = res.ranks[l]
+        if r < m and res.sigma[l][r - 1] > 1.01 * res.sigma[l][r]:
+            assert _proj_dist(res.Z[l], Ul[:, :r]) < 1e-8
+
+
+def projection_identity(orc):
+    ci = inputs.small_gaussian_sum(3, n=40, R=120, eps=1e-5)
+    res = orc.rhosvd(ci.U, ci.xi, ci.eps)
+    for l in range(3):
+        VVt = res.V[l] @ res.V[l].T
+        s2 = res.sigma[l][: res.ranks[l]] ** 2
+        assert np.allclose(VVt, np.diag(s2), atol=1e-12 * s2[0]), l
+        assert np.max(np.abs(res.Z[l].T @ res.Z[l] - np.eye(res.ranks[l]))) < 1e-12
+
+
+def pythagoras(orc):
+    for ci in (inputs.small_gaussian_sum(4, n=20, R=50, eps=1e-3),
+               inputs.random_dense(5, n=12, R=30, eps=0.3)):
+        res = orc.rhosvd(ci.U, ci.xi, ci.eps)
+        Ut, xip, _, _ = orc.normalize(ci.U, ci.xi)
+        A = orc.full_tensor(Ut, xip)
+        err = float(np.linalg.norm((A - orc.reconstruct(res.beta, res.Z)).ravel()))
+        b2 = float(np.sum(res.beta ** 2))
+        a2 = float(np.sum(A ** 2))
+        assert abs(b2 + err ** 2 - a2) <= 1e-11 * a2
+
+
+def theorem23(orc):
+    g = inputs.rng(inputs.WL_RANDOM, 107)
+    for seed, eps in [(0, 1e-2), (1, 1e-3), (2, 1e-4), (3, 3e-2)]:
+        ci = inputs.small_gaussian_sum(30 + seed, n=16, R=40, eps=eps)
+        xi = ci.xi * np.where(g.uniform(size=40) < 0.5, -1.0, 1.0)   # signed terms
+        res = orc.rhosvd(ci.U, xi, eps)
+        assert min(res.ranks) < 16                                   # truncation happened
+        Ut, xip, _, _ = orc.normalize(ci.U, xi)
+        err = float(np.linalg.norm((orc.full_tensor(Ut, xip)
+                                    - orc.reconstruct(res.beta, res.Z)).ravel()))
+        # the bound itself, recomputed from the singular values directly
+        b = res.xi_norm * sum(math.sqrt(float(np.sum(res.sigma[l][res.ranks[l]:] ** 2)))
+                              for l in range(3))
+        assert abs(b - res.bound) <= 1e-12 * max(b, 1.0)
+        slack = 1e-12 * res.a_norm
+        assert err <= b + slack
+        assert err <= eps * res.a_norm + slack
+
+
+def corollary24(orc):
+    g = inputs.rng(inputs.WL_RANDOM, 104)
+    n, R = 14, 9
+    U1 = _orth(g, n, R)
+    U2, U3 = g.standard_normal((n, R)), g.standard_normal((n, R))
+    xi = g.standard_normal(R)
+    Ut, xip, _, _ = orc.normalize([U1, U2, U3], xi)
+    a = float(np.linalg.norm(orc.full_tensor(Ut, xip).ravel()))
+    assert abs(a - np.linalg.norm(xip)) <= 1e-12 * a
+    ci = inputs.small_gaussian_sum(6, n=16, R=40)
+    Ut, xip, _, _ = orc.normalize(ci.U, ci.xi)
+    assert np.linalg.norm(xip) <= float(np.linalg.norm(orc.full_tensor(Ut, xip).ravel()))
+
+
+def degenerate(orc):
+    g = inputs.rng(inputs.WL_RANDOM, 105)
+    U = [g.standard_normal((11, 1)) for _ in range(3)]
+    res = orc.rhosvd(U, np.array([-2.5]), eps=1e-6)
+    assert res.ranks == (1, 1, 1)
+    nrm = np.prod([np.linalg.norm(u) for u in U])
+    assert abs(abs(res.beta[0, 0, 0]) - 2.5 * nrm) <= 1e-12 * 2.5 * nrm
+    v = [g.standard_normal(9) for _ in range(3)]
+    U = [np.repeat(x[:, None], 7, axis=1) for x in v]
+    res = orc.rhosvd(U, np.arange(1.0, 8.0), eps=1e-8)
+    assert res.ranks == (1, 1, 1)
+    assert abs(abs(res.beta[0, 0, 0]) - 28.0 * np.prod([np.linalg.norm(x) for x in v])) < 1e-10 * 28 * 50
+
+
+def invariances(orc):
+    ci = inputs.small_gaussian_sum(8, n=20, R=40, eps=1e-4)
+    base = orc.rhosvd(ci.U, ci.xi, ci.eps)
+    A0 = orc.reconstruct(base.beta, base.Z)
+    g = inputs.rng(inputs.WL_RANDOM, 106)
+    perm = g.permutation(40)
+    res = orc.rhosvd([u[:, perm] for u in ci.U], ci.xi[perm], ci.eps)
+    assert res.ranks == base.ranks
+    assert np.allclose(orc.reconstruct(res.beta, res.Z), A0, atol=1e-10 * np.abs(A0).max())
+    scale = g.uniform(0.1, 10.0, size=(3, 40))
+    res = orc.rhosvd([ci.U[l] * scale[l] for l in range(3)], ci.xi / np.prod(scale, axis=0), ci.eps)
+    assert res.ranks == base.ranks
+    assert np.allclose(orc.reconstruct(res.beta, res.Z), A0, atol=1e-10 * np.abs(A0).max())
+    Q = _orth(g, 20, 20)
+    res = orc.rhosvd([Q @ ci.U[0], ci.U[1], ci.U[2]], ci.xi, ci.eps)
+    assert res.ranks == base.ranks
+    for l in range(3):
+        assert np.allclose(res.sigma[l], base.sigma[l], atol=1e-13 * base.sigma[l][0])
+    assert _proj_dist(res.Z[0], Q @ base.Z[0]) < 1e-8
+
+
+ALL = [svd_known_spectrum, svd_vs_lapack, lowrank_exact, brute_force_error,
+       hosvd_special_case, projection_identity, pythagoras, theorem23, corollary24,
+       degenerate, invariances]

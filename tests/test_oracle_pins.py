@@ -1,0 +1,116 @@
+"""The CPU oracle against what the paper and mathematics fix (see tests/pins.py),
+plus planted mistakes showing that each class of plausible error fails a pin."""
+import numpy as np
+import pytest
+
+import pins
+
+
+@pytest.mark.parametrize("check", pins.ALL, ids=[c.__name__ for c in pins.ALL])
+def test_pin(orc, check):
+    check(orc)
+
+
+def test_all_terms_dropped(orc):
+    g = np.random.default_rng(0)
+    U = [g.standard_normal((8, 5)) for _ in range(3)]
+    res = orc.rhosvd(U, np.zeros(5), eps=1e-6)
+    assert res.ranks == (0, 0, 0)
+
+
+def test_zero_column_term_is_dropped(orc):
+    from paper_2201_12663_amd import inputs
+    ci = inputs.small_gaussian_sum(9, n=16, R=30, eps=1e-5)
+    U = [u.copy() for u in ci.U]
+    U[1][:, 7] = 0.0                       # term 7 now contributes nothing
+    full = orc.rhosvd(U, ci.xi, ci.eps)
+    keep = np.arange(30) != 7
+    ref = orc.rhosvd([u[:, keep] for u in U], ci.xi[keep], ci.eps)
+    assert full.ranks == ref.ranks
+    for l in range(3):
+        assert np.allclose(full.sigma[l][:29], ref.sigma[l][:29], atol=1e-13)
+    A0 = orc.reconstruct(ref.beta, ref.Z)
+    assert np.allclose(orc.reconstruct(full.beta, full.Z), A0, atol=1e-11 * np.abs(A0).max())
+
+
+def test_tails_and_rank_rule(orc):
+    s = np.array([4.0, 2.0, 1.0, 0.5])
+    t = orc.tails(s)
+    assert np.allclose(t, [np.sqrt(21.25), np.sqrt(5.25), np.sqrt(1.25), 0.5, 0.0])
+    assert orc.choose_rank(t, 0.5) == 3          # tie at the cut is kept (t_r <= tau)
+    assert orc.choose_rank(t, 0.49) == 4
+    assert orc.choose_rank(t, 100.0) == 1        # never below rank 1
+
+
+def test_anorm_gram_matches_brute(orc):
+    from paper_2201_12663_amd import inputs
+    ci = inputs.random_dense(30, n=9, R=14)
+    Ut, xip, _, _ = orc.normalize(ci.U, ci.xi)
+    a = float(np.linalg.norm(orc.full_tensor(Ut, xip).ravel()))
+    assert abs(orc.anorm_gram(Ut, xip) - a) <= 1e-12 * a
+
+
+# ----------------------------------------------------------------------------
+# planted mistakes: each must make at least one pin fail
+# ----------------------------------------------------------------------------
+def _fails(orc, checks):
+    for c in checks:
+        try:
+            c(orc)
+        except (AssertionError, ValueError):
+            return True
+    return False
+
+
+def test_planted_dropped_term_in_core(orc, monkeypatch):
+    real = orc.core
+
+    def bad_core(V, xip):
+        x = xip.copy()
+        x[-1] = 0.0
+        return real(V, x)
+    monkeypatch.setattr(orc, "core", bad_core)
+    assert _fails(orc, [pins.lowrank_exact, pins.pythagoras, pins.brute_force_error])
+
+
+def test_planted_swapped_modes_in_core(orc, monkeypatch):
+    real = orc.core
+    monkeypatch.setattr(orc, "core", lambda V, xip: real([V[0], V[2], V[1]], xip).transpose(0, 2, 1)
+                        if V[1].shape[0] == V[2].shape[0] else real([V[0], V[2], V[1]], xip))
+    assert _fails(orc, [pins.brute_force_error, pins.lowrank_exact])
+
+
+def test_planted_off_by_one_tail(orc, monkeypatch):
+    def bad_tails(sigma):
+        sq = sigma[::-1] ** 2
+        acc = np.concatenate([np.cumsum(sq)[::-1], [0.0]])
+        return np.sqrt(np.concatenate([acc[:1], acc[:-1]]))   # t_r includes sigma_r
+    monkeypatch.setattr(orc, "tails", bad_tails)
+    assert _fails(orc, [pins.theorem23, pins.lowrank_exact])
+
+
+def test_planted_unfolded_norms(orc, monkeypatch):
+    real = orc.normalize
+
+    def bad_normalize(U, xi):
+        Ut, xip, keep, s = real(U, xi)
+        return Ut, np.where(keep, xi, 0.0), keep, s     # norms not folded into xi
+    monkeypatch.setattr(orc, "normalize", bad_normalize)
+    assert _fails(orc, [pins.degenerate, pins.invariances])
+
+
+def test_planted_unsorted_vectors(orc, monkeypatch):
+    real = orc.svd_left
+
+    def bad_svd(X, max_sweeps=60):
+        s, Z, sw = real(X, max_sweeps)
+        Z = Z.copy()
+        Z[:, [0, 1]] = Z[:, [1, 0]]            # vectors out of step with sigma
+        return s, Z, sw
+    monkeypatch.setattr(orc, "svd_left", bad_svd)
+    assert _fails(orc, [pins.svd_known_spectrum, pins.projection_identity])
+
+
+def test_planted_transposed_projection(orc, monkeypatch):
+    monkeypatch.setattr(orc, "project", lambda Z, Ut: (Ut.T @ Z).T[:, ::-1])
+    assert _fails(orc, [pins.projection_identity, pins.lowrank_exact])
