@@ -1,0 +1,156 @@
+/*
+ * rhosvd.h — C-ABI of the MI355X (gfx950) Reduced HOSVD library.
+ *
+ * The Reduced HOSVD (Khoromskaia & Khoromskij, Section 2.1, Definition 2.1)
+ * turns a d=3 canonical tensor
+ *     A = sum_nu xi_nu u1_nu (x) u2_nu (x) u3_nu            (eq. eqn:can_A3)
+ * with side matrices U^(l) = [u^(l)_1 .. u^(l)_R] (n x R) into a rank-(r1,r2,r3)
+ * orthogonal Tucker tensor  A_r = beta x_1 Z^(1) x_2 Z^(2) x_3 Z^(3):
+ *   1. each side matrix is normalized column by column and its singular value
+ *      decomposition U^(l) = Z D V^T is truncated at epsilon   (eqs. eqn:SVD_Ul, eq:svdr)
+ *   2. V^(l) = Z^(l)T U^(l) projects the side matrices     (Definition 2.1, Proposition 2.2)
+ *   3. the core beta_(1) = V^(1) diag(xi') (V^(3) (.) V^(2))^T  (Proposition 2.2)
+ *
+ * Truncation rule (the paper leaves it open): tau = eps * |A|_F / (3 |xi'|_2),
+ * r_l = min{ r >= 1 : (sum_{k>r} sigma_{l,k}^2)^(1/2) <= tau }.  Theorem 2.3 then
+ * guarantees |A - A_r|_F <= eps |A|_F.
+ *
+ * Conventions
+ *   - All matrices are column-major.  U^(l): n x R, leading dimension n, column nu
+ *     is the canonical vector u^(l)_nu.  Z^(l): n x r_l, leading dimension n.
+ *     beta: r1*r2*r3 doubles, entry (j1,j2,j3) at j1 + r1*(j2 + r2*j3).
+ *   - Every data pointer is a DEVICE pointer unless marked "host".  Inputs are
+ *     read-only and must stay valid until the stream has finished the call.
+ *   - All work is enqueued on the stream given at rhosvd_create.  rhosvd_reduce
+ *     synchronizes with that stream once (to return the ranks on the host);
+ *     rhosvd_get does not synchronize.
+ *   - A handle owns its device workspace (grown on demand, reused across
+ *     calls, released by rhosvd_destroy).  A handle is not thread-safe and must
+ *     not be used by two calls at once.
+ *   - Functions never throw; they return a status.  rhosvd_last_error gives a
+ *     human-readable message for the last failing call on a handle.
+ */
+#ifndef RHOSVD_H
+#define RHOSVD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RHOSVD_OK = 0,
+    RHOSVD_ERR_ARG = -1,        /* bad size, null pointer, eps <= 0, unknown option */
+    RHOSVD_ERR_NONFINITE = -2,  /* an input entry (U or xi) is NaN or infinite */
+    RHOSVD_ERR_ALLOC = -3,      /* device workspace allocation failed */
+    RHOSVD_ERR_DEVICE = -4,     /* a HIP runtime call failed */
+    RHOSVD_ERR_NOCONV = -5,     /* the eigensolver hit its sweep cap */
+    RHOSVD_ERR_STATE = -6,      /* rhosvd_get/inspection without a successful rhosvd_reduce */
+    RHOSVD_ERR_UNSUPPORTED = -7 /* size or option outside what this build supports */
+} rhosvd_status;
+
+/* Arithmetic of the projection and core contractions.  The column norms, the
+ * Gram matrix, the eigensolver, the truncation decision and Z are FP64 in
+ * every mode. */
+typedef enum {
+    RHOSVD_FP64 = 0,    /* FP64 MFMA */
+    RHOSVD_FP32 = 1,    /* FP32 MFMA, FP32 accumulation */
+    RHOSVD_BF16X3 = 2   /* core: a = a_hi + a_lo in bf16, a*b ~ hi*hi + hi*lo + lo*hi,
+                           FP32 accumulation (bf16 MFMA); projection in FP32 MFMA */
+} rhosvd_precision;
+
+typedef struct {
+    int32_t precision;       /* rhosvd_precision */
+    int32_t max_eig_sweeps;  /* cap on eigensolver sweeps; <= 0 selects the default (30) */
+    int32_t profile;         /* nonzero: time each phase with HIP events (see rhosvd_phase_ms) */
+    int32_t reserved[5];     /* must be zero */
+} rhosvd_options;
+
+typedef struct {
+    double xi_norm;      /* |xi'|_2 after normalization */
+    double a_norm;       /* |A|_F (exact, from the Gram identity) */
+    double tau;          /* truncation threshold on the tails */
+    double bound;        /* Theorem 2.3: |xi'| * sum_l tail[l] */
+    double tail[3];      /* t_{l, r_l} = (sum_{k > r_l} sigma_{l,k}^2)^(1/2) */
+    int32_t ranks[3];
+    int32_t m;           /* min(n, R): number of singular values per mode */
+    int32_t eig_sweeps;  /* eigensolver sweeps used */
+    int32_t dropped;     /* terms dropped because xi = 0 or a column is zero */
+} rhosvd_report;
+
+typedef struct rhosvd_ctx* rhosvd_handle;
+
+/* Create a handle bound to a HIP stream (hipStream_t passed as void*; NULL is
+ * the default stream).  opt may be NULL (FP64, default sweep cap).
+ * Errors: RHOSVD_ERR_ARG (out == NULL, bad option), RHOSVD_ERR_DEVICE. */
+rhosvd_status rhosvd_create(rhosvd_handle* out, void* hip_stream, const rhosvd_options* opt);
+
+/* Release the handle and its workspace (waits for the handle's stream). */
+rhosvd_status rhosvd_destroy(rhosvd_handle h);
+
+/* Change the options of an existing handle (same rules as rhosvd_create). */
+rhosvd_status rhosvd_set_options(rhosvd_handle h, const rhosvd_options* opt);
+
+/*
+ * Phase 1 of a reduction (Definition 2.1 up to the ranks): normalization, the
+ * |A| identity, Gram matrices on the min(n,R) side, FP64 eigensolver,
+ * truncation, Z and the projections V^(l).
+ *   n, R     : grid size and canonical rank, 1 <= n <= 2048, R >= 1
+ *   U1..U3   : device, n x R each (column-major, ld = n)
+ *   xi       : device, R weights
+ *   eps      : relative accuracy, > 0
+ *   ranks    : HOST int32[3], receives (r1, r2, r3); (0,0,0) when every term is dropped
+ * Synchronizes with the handle's stream once.  On error nothing is retained.
+ * Errors: ARG, NONFINITE, ALLOC, DEVICE, NOCONV, UNSUPPORTED.
+ */
+rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R,
+                            const double* U1, const double* U2, const double* U3,
+                            const double* xi, double eps, int32_t ranks[3]);
+
+/*
+ * Phase 2: the Khatri-Rao core and the copy-out into caller buffers sized from
+ * the ranks of the last successful rhosvd_reduce on this handle.
+ *   Z1..Z3 : device, n x r_l each (column-major), or NULL to skip
+ *   beta   : device, r1*r2*r3 doubles (Fortran order), or NULL to skip the core
+ *   sigma  : device, r1+r2+r3 doubles (kept singular values, mode by mode), or NULL
+ *   report : HOST, or NULL
+ * Enqueued on the handle's stream; does not synchronize.
+ * Errors: STATE (no reduction), DEVICE.
+ */
+rhosvd_status rhosvd_get(rhosvd_handle h, double* Z1, double* Z2, double* Z3,
+                         double* beta, double* sigma, rhosvd_report* report);
+
+/*
+ * Inspection of the last reduction (for tests and the mixed Tucker-canonical
+ * format of Proposition 2.2, whose core is the rank-R canonical tensor with
+ * factors V^(l)).  All outputs are device pointers; these calls enqueue copies.
+ *   rhosvd_get_xi       : xi' (R doubles; zero for dropped terms)
+ *   rhosvd_get_spectrum : all m singular values of mode l, descending (m doubles)
+ *   rhosvd_get_v        : V^(l) = Z^(l)T U~^(l) as an r_l x R column-major matrix
+ *                         (converted to FP64 when the projection ran in FP32)
+ * Errors: STATE, ARG (l outside 0..2), DEVICE.
+ */
+rhosvd_status rhosvd_get_xi(rhosvd_handle h, double* xip);
+rhosvd_status rhosvd_get_spectrum(rhosvd_handle h, int32_t l, double* sigma_all);
+rhosvd_status rhosvd_get_v(rhosvd_handle h, int32_t l, double* V);
+
+/* Phase times in milliseconds of the last rhosvd_reduce / rhosvd_get when the
+ * handle was created with profile != 0 (synchronizes with the stream):
+ *   0 norms, 1 |A| identity, 2 Gram, 3 eigensolver, 4 truncation + Z,
+ *   5 projection, 6 core.  Returns -1 for an unknown phase or when profiling is off. */
+double rhosvd_phase_ms(rhosvd_handle h, int32_t phase);
+
+/* Message describing the last error on this handle ("" if none); valid until
+ * the next call on the handle.  h may be NULL (message of the last failed create). */
+const char* rhosvd_last_error(rhosvd_handle h);
+
+/* Library version string. */
+const char* rhosvd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RHOSVD_H */

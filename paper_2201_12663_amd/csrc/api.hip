@@ -1,0 +1,507 @@
+// C-ABI of the Reduced HOSVD library: handle, workspace and the reduction's
+// orchestration (declared in include/rhosvd.h).
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "../../include/rhosvd.h"
+#include "common.hpp"
+#include "kernels.hpp"
+
+#define RHOSVD_VERSION "0.1.0"
+
+namespace {
+
+constexpr int NPHASE = 7;
+constexpr int NEV = 9;            // 0..6 bracket the reduce phases, 7..8 the core
+constexpr int DEFAULT_SWEEPS = 30;
+constexpr double JACOBI_TOL = 4.0 * 1.1102230246251565e-16;   // rotation threshold / |G|_F
+constexpr int RPAD_CORE = 128;                                 // V row padding (core tiles)
+
+std::string g_create_error;
+
+size_t a256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+}  // namespace
+
+struct rhosvd_ctx {
+    hipStream_t stream = nullptr;
+    rhosvd_options opt{};
+    std::string err;
+    // workspace (grow-only)
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    int* host = nullptr;   // pinned host staging (ranks, flags, sweeps)
+    double* hostd = nullptr;
+    // layout of the last reduction
+    int64_t n = 0, R = 0, n_pad = 0, R_pad = 0, m = 0, m_pad = 0, zr_pad = 0;
+    double* Ut[3] = {};
+    double* xip = nullptr;
+    int* flags = nullptr;
+    double* G[3] = {};
+    double* W[3] = {};
+    double* gram_part = nullptr;
+    int gram_splits = 1;
+    double* anorm_part = nullptr;
+    int64_t anorm_ntiles = 0;
+    void* jac = nullptr;
+    size_t jac_bytes = 0;
+    int* sweeps_dev = nullptr;
+    double* sigma[3] = {};
+    int* order[3] = {};
+    double* tails[3] = {};
+    int* ranks_dev = nullptr;
+    double* scal = nullptr;
+    double* Z[3] = {};
+    void* V[3] = {};
+    int vprec = 0;
+    bool rside = false;                  // R < n: Gram on the R side
+    double* Wr[3] = {};                  // R < n: W_r Lambda_r^-1/2 (R_pad x zr_pad)
+    double* Zraw[3] = {};                // R < n: U~ W_r Lambda_r^-1/2 (n_pad x zr_pad)
+    double* M2[3] = {};                  // R < n: Z^T Z and its eigenvectors (zr_pad^2 each)
+    double* P2[3] = {};
+    double* S2[3] = {};
+    void* jac2 = nullptr;
+    size_t jac2_bytes = 0;
+    // results
+    bool have = false;
+    int ranks[3] = {0, 0, 0};
+    int r_pad[3] = {0, 0, 0};
+    double xi_norm = 0, a_norm = 0, tau = 0;
+    int sweeps = 0, dropped = 0;
+    // profiling
+    hipEvent_t ev[NEV] = {};
+    bool ev_ok = false;
+    float phase_ms[NPHASE] = {};
+    bool reduce_timed = false, get_timed = false;
+};
+
+namespace {
+
+rhosvd_status fail(rhosvd_ctx* h, rhosvd_status s, const std::string& msg) {
+    if (h) h->err = msg;
+    return s;
+}
+
+#define CK(h, expr)                                                                          \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(h, RHOSVD_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+rhosvd_status check_options(const rhosvd_options* o, std::string& msg) {
+    if (!o) return RHOSVD_OK;
+    if (o->precision < 0 || o->precision > 2) { msg = "unknown precision"; return RHOSVD_ERR_ARG; }
+    for (int i = 0; i < 5; ++i)
+        if (o->reserved[i] != 0) { msg = "reserved option fields must be zero"; return RHOSVD_ERR_ARG; }
+    return RHOSVD_OK;
+}
+
+void apply_options(rhosvd_ctx* h, const rhosvd_options* o) {
+    if (o) h->opt = *o;
+    else memset(&h->opt, 0, sizeof(h->opt));
+    if (h->opt.max_eig_sweeps <= 0) h->opt.max_eig_sweeps = DEFAULT_SWEEPS;
+}
+
+void mark(rhosvd_ctx* h, int i) {
+    if (h->opt.profile && h->ev_ok) hipEventRecord(h->ev[i], h->stream);
+}
+
+// carve the workspace for (n, R, precision); grows the allocation when needed
+rhosvd_status layout(rhosvd_ctx* h, int64_t n, int64_t R) {
+    h->n = n;
+    h->R = R;
+    h->n_pad = round_up(n, PAD_N);
+    h->R_pad = round_up(R, PAD_R);
+    h->m = n < R ? n : R;
+    h->rside = R < n;
+    h->m_pad = h->rside ? h->R_pad : h->n_pad;   // Gram on the min(n, R) side
+    h->zr_pad = round_up(h->m, RPAD_CORE);       // max padded rank
+    const int64_t np = h->n_pad, Rp = h->R_pad, mp = h->m_pad;
+    const int esz = (h->opt.precision == RHOSVD_FP64) ? 8 : 4;
+    // split-K for the Gram when there are few output tiles
+    const int64_t tiles = 3 * (mp / 64) * (mp / 64 + 1) / 2;
+    int splits = (int)ceil_div(512, tiles);
+    const int64_t kmax = Rp / 256;               // keep >= 256 terms per split
+    if (splits > kmax) splits = (int)kmax;
+    if (splits < 1) splits = 1;
+    h->gram_splits = splits;
+    const int64_t rt = Rp / 64;
+    h->anorm_ntiles = rt * (rt + 1) / 2;
+    h->jac_bytes = jacobi_work_bytes(3, (int)mp, h->opt.max_eig_sweeps);
+
+    size_t off = 0;
+    size_t o_Ut = off;    off += a256((size_t)np * Rp * 8) * 3;
+    size_t o_xip = off;   off += a256((size_t)Rp * 8);
+    size_t o_flags = off; off += a256(64);
+    size_t o_G = off;     off += a256((size_t)mp * mp * 8) * 3;
+    size_t o_W = off;     off += a256((size_t)mp * mp * 8) * 3;
+    size_t o_gp = off;    off += (splits > 1) ? a256((size_t)splits * 3 * np * np * 8) : 0;
+    size_t o_ap = off;    off += a256((size_t)h->anorm_ntiles * 8);
+    size_t o_jac = off;   off += a256(h->jac_bytes);
+    size_t o_sw = off;    off += a256(16);
+    size_t o_sig = off;   off += a256((size_t)(mp + 1) * 8) * 3;
+    size_t o_ord = off;   off += a256((size_t)mp * 4) * 3;
+    size_t o_tl = off;    off += a256((size_t)(mp + 1) * 8) * 3;
+    size_t o_rk = off;    off += a256(64);
+    size_t o_sc = off;    off += a256(64);
+    size_t o_Z = off;     off += a256((size_t)np * h->zr_pad * 8) * 3;
+    size_t o_V = off;     off += a256((size_t)h->zr_pad * Rp * esz) * 3;
+    const int64_t zp = h->zr_pad;
+    h->jac2_bytes = h->rside ? jacobi_work_bytes(3, (int)zp, h->opt.max_eig_sweeps) : 0;
+    size_t o_Wr = off;    off += h->rside ? a256((size_t)Rp * zp * 8) * 3 : 0;
+    size_t o_Zr = off;    off += h->rside ? a256((size_t)np * zp * 8) * 3 : 0;
+    size_t o_M2 = off;    off += h->rside ? a256((size_t)zp * zp * 8) * 9 : 0;
+    size_t o_j2 = off;    off += h->rside ? a256(h->jac2_bytes) : 0;
+    if (off > h->ws_bytes) {
+        if (h->ws) { hipStreamSynchronize(h->stream); hipFree(h->ws); h->ws = nullptr; h->ws_bytes = 0; }
+        hipError_t e = hipMalloc((void**)&h->ws, off);
+        if (e != hipSuccess) {
+            h->ws = nullptr;
+            return fail(h, RHOSVD_ERR_ALLOC, "workspace allocation of " + std::to_string(off) + " bytes failed");
+        }
+        h->ws_bytes = off;
+    }
+    char* b = h->ws;
+    for (int l = 0; l < 3; ++l) {
+        h->Ut[l] = (double*)(b + o_Ut + l * a256((size_t)np * Rp * 8));
+        h->G[l] = (double*)(b + o_G + l * a256((size_t)mp * mp * 8));
+        h->W[l] = (double*)(b + o_W + l * a256((size_t)mp * mp * 8));
+        h->sigma[l] = (double*)(b + o_sig + l * a256((size_t)(mp + 1) * 8));
+        h->order[l] = (int*)(b + o_ord + l * a256((size_t)mp * 4));
+        h->tails[l] = (double*)(b + o_tl + l * a256((size_t)(mp + 1) * 8));
+        h->Z[l] = (double*)(b + o_Z + l * a256((size_t)np * h->zr_pad * 8));
+        h->V[l] = (void*)(b + o_V + l * a256((size_t)h->zr_pad * Rp * esz));
+    }
+    if (h->rside) {
+        for (int l = 0; l < 3; ++l) {
+            h->Wr[l] = (double*)(b + o_Wr + l * a256((size_t)Rp * zp * 8));
+            h->Zraw[l] = (double*)(b + o_Zr + l * a256((size_t)np * zp * 8));
+            h->M2[l] = (double*)(b + o_M2 + (3 * l + 0) * a256((size_t)zp * zp * 8));
+            h->P2[l] = (double*)(b + o_M2 + (3 * l + 1) * a256((size_t)zp * zp * 8));
+            h->S2[l] = (double*)(b + o_M2 + (3 * l + 2) * a256((size_t)zp * zp * 8));
+        }
+        h->jac2 = (void*)(b + o_j2);
+    }
+    h->xip = (double*)(b + o_xip);
+    h->flags = (int*)(b + o_flags);
+    h->gram_part = (splits > 1) ? (double*)(b + o_gp) : nullptr;
+    h->anorm_part = (double*)(b + o_ap);
+    h->jac = (void*)(b + o_jac);
+    h->sweeps_dev = (int*)(b + o_sw);
+    h->ranks_dev = (int*)(b + o_rk);
+    h->scal = (double*)(b + o_sc);
+    h->vprec = h->opt.precision;
+    return RHOSVD_OK;
+}
+
+// R < n: Z = U~ W_r Lambda_r^(-1/2) (the left singular vectors from the right
+// ones), then re-orthonormalized in FP64 by Z <- Z (Z^T Z)^(-1/2) (symmetric
+// orthogonalization; Z^T Z = P diag(mu) P^T from the same eigensolver) and
+// sign-normalized.
+rhosvd_status form_z_rside(rhosvd_ctx* h) {
+    hipStream_t st = h->stream;
+    const int64_t np = h->n_pad, Rp = h->R_pad, zp = h->zr_pad;
+    int rmp = 0;
+    for (int l = 0; l < 3; ++l) rmp = h->r_pad[l] > rmp ? h->r_pad[l] : rmp;
+    for (int l = 0; l < 3; ++l) {
+        const int r = h->ranks[l], rp = h->r_pad[l];
+        CK(h, launch_gather_scaled((int)h->m_pad, r, rp, h->W[l], h->order[l], h->sigma[l], h->Wr[l], st));
+        CK(h, hipMemsetAsync(h->Zraw[l], 0, (size_t)np * zp * 8, st));
+        CK(h, launch_gemm64(false, true, np, rp, Rp, h->Ut[l], np, h->Wr[l], Rp, h->Zraw[l], np, 1.0, st));
+        CK(h, launch_gemm64(true, true, rp, rp, np, h->Zraw[l], np, h->Zraw[l], np, h->M2[l], rmp, 1.0, st));
+        CK(h, launch_pad_identity(r, rmp, h->M2[l], st));
+    }
+    JacobiProblem jp{};
+    for (int l = 0; l < 3; ++l) { jp.G[l] = h->M2[l]; jp.W[l] = h->P2[l]; }
+    jp.nmat = 3;
+    jp.m_pad = rmp;
+    jp.max_sweeps = h->opt.max_eig_sweeps;
+    jp.tol = JACOBI_TOL;
+    CK(h, launch_jacobi(jp, h->jac2, h->jac2_bytes, h->sweeps_dev + 1, st));
+    for (int l = 0; l < 3; ++l) {
+        // S = P diag(mu^-1/2) P^T ;  Z = Zraw S
+        CK(h, hipMemcpyAsync(h->S2[l], h->P2[l], (size_t)rmp * rmp * 8, hipMemcpyDeviceToDevice, st));
+        CK(h, launch_scale_cols_invsqrt(rmp, h->M2[l], h->S2[l], st));
+        CK(h, launch_gemm64(false, false, rmp, rmp, rmp, h->S2[l], rmp, h->P2[l], rmp, h->M2[l], rmp, 1.0, st));
+        CK(h, launch_gemm64(false, true, np, rmp, rmp, h->Zraw[l], np, h->M2[l], rmp, h->Z[l], np, 1.0, st));
+        CK(h, launch_sign_cols((int)h->n, (int)np, h->ranks[l], h->Z[l], st));
+        // the projection reads r_pad[l] columns: zero those beyond the rank
+        if (h->r_pad[l] > h->ranks[l])
+            CK(h, hipMemsetAsync(h->Z[l] + (int64_t)h->ranks[l] * np, 0,
+                                 (size_t)(h->r_pad[l] - h->ranks[l]) * np * 8, st));
+    }
+    return RHOSVD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rhosvd_version(void) { return RHOSVD_VERSION; }
+
+const char* rhosvd_last_error(rhosvd_handle h) {
+    return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+rhosvd_status rhosvd_create(rhosvd_handle* out, void* hip_stream, const rhosvd_options* opt) {
+    if (!out) { g_create_error = "out is NULL"; return RHOSVD_ERR_ARG; }
+    *out = nullptr;
+    std::string msg;
+    rhosvd_status s = check_options(opt, msg);
+    if (s != RHOSVD_OK) { g_create_error = msg; return s; }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        g_create_error = "no HIP device";
+        return RHOSVD_ERR_DEVICE;
+    }
+    rhosvd_ctx* h = new rhosvd_ctx();
+    h->stream = (hipStream_t)hip_stream;
+    apply_options(h, opt);
+    if (hipHostMalloc((void**)&h->host, 256, hipHostMallocDefault) != hipSuccess) {
+        delete h;
+        g_create_error = "pinned host allocation failed";
+        return RHOSVD_ERR_ALLOC;
+    }
+    h->hostd = (double*)(h->host + 32);
+    h->ev_ok = true;
+    for (int i = 0; i < NEV; ++i)
+        if (hipEventCreate(&h->ev[i]) != hipSuccess) h->ev_ok = false;
+    *out = h;
+    return RHOSVD_OK;
+}
+
+rhosvd_status rhosvd_destroy(rhosvd_handle h) {
+    if (!h) return RHOSVD_ERR_ARG;
+    hipStreamSynchronize(h->stream);
+    if (h->ws) hipFree(h->ws);
+    if (h->host) hipHostFree(h->host);
+    for (int i = 0; i < NEV; ++i)
+        if (h->ev[i]) hipEventDestroy(h->ev[i]);
+    delete h;
+    return RHOSVD_OK;
+}
+
+rhosvd_status rhosvd_set_options(rhosvd_handle h, const rhosvd_options* opt) {
+    if (!h) return RHOSVD_ERR_ARG;
+    std::string msg;
+    rhosvd_status s = check_options(opt, msg);
+    if (s != RHOSVD_OK) return fail(h, s, msg);
+    apply_options(h, opt);
+    h->have = false;
+    return RHOSVD_OK;
+}
+
+rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R, const double* U1, const double* U2,
+                            const double* U3, const double* xi, double eps, int32_t ranks[3]) {
+    if (!h) return RHOSVD_ERR_ARG;
+    h->have = false;
+    h->err.clear();
+    if (!U1 || !U2 || !U3 || !xi || !ranks) return fail(h, RHOSVD_ERR_ARG, "null pointer argument");
+    if (n < 1 || R < 1) return fail(h, RHOSVD_ERR_ARG, "n and R must be >= 1");
+    if (!(eps > 0.0) || !isfinite(eps)) return fail(h, RHOSVD_ERR_ARG, "eps must be finite and > 0");
+    if ((n < R ? n : R) > 2048) return fail(h, RHOSVD_ERR_UNSUPPORTED, "min(n, R) > 2048 is not supported by this build");
+    if (n > 65536) return fail(h, RHOSVD_ERR_UNSUPPORTED, "n > 65536 is not supported by this build");
+    rhosvd_status s = layout(h, n, R);
+    if (s != RHOSVD_OK) return s;
+    hipStream_t st = h->stream;
+    const double* U[3] = {U1, U2, U3};
+    mark(h, 0);
+    CK(h, hipMemsetAsync(h->flags, 0, 64, st));
+    CK(h, launch_colnorm(n, R, h->n_pad, h->R_pad, U, xi, h->Ut, h->xip, h->flags, st));
+    mark(h, 1);
+    int64_t nt = 0;
+    // |A| identity; when R < n the same tiles are the Grams U~^T U~ on the R side
+    CK(h, launch_anorm_partials(h->n_pad, h->R_pad, h->Ut, h->xip, h->anorm_part, &nt,
+                                h->rside ? h->G : nullptr, st));
+    mark(h, 2);
+    if (!h->rside)
+        CK(h, launch_gram_nt(h->n_pad, h->R_pad, h->Ut, h->G, h->gram_part, h->gram_splits, st));
+    mark(h, 3);
+    JacobiProblem jp{};
+    for (int l = 0; l < 3; ++l) { jp.G[l] = h->G[l]; jp.W[l] = h->W[l]; }
+    jp.nmat = 3;
+    jp.m_pad = (int)h->m_pad;
+    jp.max_sweeps = h->opt.max_eig_sweeps;
+    jp.tol = JACOBI_TOL;
+    CK(h, launch_jacobi(jp, h->jac, h->jac_bytes, h->sweeps_dev, st));
+    mark(h, 4);
+    TruncArgs ta{};
+    for (int l = 0; l < 3; ++l) {
+        ta.G[l] = h->G[l];
+        ta.W[l] = h->W[l];
+        ta.sigma[l] = h->sigma[l];
+        ta.order[l] = h->order[l];
+        ta.tails[l] = h->tails[l];
+    }
+    ta.m = (int)h->m;
+    ta.m_pad = (int)h->m_pad;
+    ta.n = (int)n;
+    ta.n_pad = (int)h->n_pad;
+    ta.xip = h->xip;
+    ta.R_pad = h->R_pad;
+    ta.anorm_part = h->anorm_part;
+    ta.anorm_ntiles = h->anorm_ntiles;
+    ta.eps = eps;
+    ta.ranks = h->ranks_dev;
+    ta.scal = h->scal;
+    CK(h, launch_truncate(ta, st));
+    // the one host synchronization: ranks, flags, sweeps and norms
+    CK(h, hipMemcpyAsync(h->host, h->ranks_dev, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
+    CK(h, hipMemcpyAsync(h->host + 4, h->flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    CK(h, hipMemcpyAsync(h->host + 8, h->sweeps_dev, sizeof(int), hipMemcpyDeviceToHost, st));
+    CK(h, hipMemcpyAsync(h->hostd, h->scal, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    CK(h, hipStreamSynchronize(st));
+    if (h->host[4]) return fail(h, RHOSVD_ERR_NONFINITE, "input contains NaN or Inf");
+    h->sweeps = h->host[8];
+    if (h->sweeps < 0) return fail(h, RHOSVD_ERR_NOCONV, "eigensolver hit its sweep cap");
+    h->dropped = h->host[5];
+    h->xi_norm = h->hostd[0];
+    h->a_norm = h->hostd[1];
+    h->tau = h->hostd[2];
+    for (int l = 0; l < 3; ++l) {
+        h->ranks[l] = h->host[l];
+        h->r_pad[l] = (int)round_up(h->ranks[l] > 0 ? h->ranks[l] : 1, RPAD_CORE);
+    }
+    // a5/a6: Z and the projections V = Z^T U~ (FP64 MFMA; rounded to FP32 for the mixed core)
+    if (!h->rside) {
+        for (int l = 0; l < 3; ++l) {
+            const int r = h->ranks[l];
+            if (r < 1) continue;
+            CK(h, launch_form_z((int)n, (int)h->n_pad, r, h->r_pad[l], h->W[l], (int)h->m_pad, h->order[l], h->Z[l], st));
+        }
+    } else if (h->ranks[0] > 0) {
+        rhosvd_status zs = form_z_rside(h);
+        if (zs != RHOSVD_OK) return zs;
+    }
+    mark(h, 5);
+    for (int l = 0; l < 3; ++l) {
+        if (h->ranks[l] < 1) continue;
+        if (h->vprec == RHOSVD_FP64)
+            CK(h, launch_project(h->n_pad, h->R_pad, h->r_pad[l], h->Z[l], h->Ut[l], (double*)h->V[l], nullptr, st));
+        else
+            CK(h, launch_project(h->n_pad, h->R_pad, h->r_pad[l], h->Z[l], h->Ut[l], nullptr, (float*)h->V[l], st));
+    }
+    mark(h, 6);
+    h->reduce_timed = true;
+    h->get_timed = false;
+    for (int l = 0; l < 3; ++l) ranks[l] = h->ranks[l];
+    h->have = true;
+    return RHOSVD_OK;
+}
+
+rhosvd_status rhosvd_get(rhosvd_handle h, double* Z1, double* Z2, double* Z3, double* beta, double* sigma,
+                         rhosvd_report* report) {
+    if (!h) return RHOSVD_ERR_ARG;
+    if (!h->have) return fail(h, RHOSVD_ERR_STATE, "no successful rhosvd_reduce on this handle");
+    hipStream_t st = h->stream;
+    const bool any = h->ranks[0] > 0 && h->ranks[1] > 0 && h->ranks[2] > 0;
+    if (h->opt.profile && h->ev_ok) hipEventRecord(h->ev[7], st);
+    if (beta && any) {
+        CoreArgs ca{};
+        for (int l = 0; l < 3; ++l) {
+            ca.r[l] = h->ranks[l];
+            ca.r_pad[l] = h->r_pad[l];
+            ca.V[l] = h->V[l];
+        }
+        ca.R_pad = h->R_pad;
+        ca.xip = h->xip;
+        ca.beta = beta;
+        ca.prec = h->vprec;
+        CK(h, launch_core(ca, st));
+    }
+    if (h->opt.profile && h->ev_ok) hipEventRecord(h->ev[8], st);
+    h->get_timed = true;
+    double* Zo[3] = {Z1, Z2, Z3};
+    int64_t off = 0;
+    for (int l = 0; l < 3; ++l) {
+        const int r = h->ranks[l];
+        if (Zo[l] && r > 0)
+            CK(h, hipMemcpy2DAsync(Zo[l], (size_t)h->n * 8, h->Z[l], (size_t)h->n_pad * 8, (size_t)h->n * 8, (size_t)r,
+                                   hipMemcpyDeviceToDevice, st));
+        if (sigma && r > 0)
+            CK(h, hipMemcpyAsync(sigma + off, h->sigma[l], (size_t)r * 8, hipMemcpyDeviceToDevice, st));
+        off += r;
+    }
+    if (report) {
+        // tails at the ranks need one small read; only done when a report is requested
+        double tl[3] = {0, 0, 0};
+        for (int l = 0; l < 3; ++l)
+            if (h->ranks[l] > 0)
+                CK(h, hipMemcpyAsync(h->hostd + 4 + l, h->tails[l] + h->ranks[l], 8, hipMemcpyDeviceToHost, st));
+        CK(h, hipStreamSynchronize(st));
+        for (int l = 0; l < 3; ++l) tl[l] = h->ranks[l] > 0 ? h->hostd[4 + l] : 0.0;
+        memset(report, 0, sizeof(*report));
+        report->xi_norm = h->xi_norm;
+        report->a_norm = h->a_norm;
+        report->tau = h->tau;
+        for (int l = 0; l < 3; ++l) {
+            report->tail[l] = tl[l];
+            report->ranks[l] = h->ranks[l];
+        }
+        report->bound = h->xi_norm * (tl[0] + tl[1] + tl[2]);
+        report->m = (int)h->m;
+        report->eig_sweeps = h->sweeps;
+        report->dropped = h->dropped;
+    }
+    return RHOSVD_OK;
+}
+
+rhosvd_status rhosvd_get_xi(rhosvd_handle h, double* xip) {
+    if (!h) return RHOSVD_ERR_ARG;
+    if (!h->have) return fail(h, RHOSVD_ERR_STATE, "no successful rhosvd_reduce on this handle");
+    if (!xip) return fail(h, RHOSVD_ERR_ARG, "null pointer");
+    CK(h, hipMemcpyAsync(xip, h->xip, (size_t)h->R * 8, hipMemcpyDeviceToDevice, h->stream));
+    return RHOSVD_OK;
+}
+
+rhosvd_status rhosvd_get_spectrum(rhosvd_handle h, int32_t l, double* sigma_all) {
+    if (!h) return RHOSVD_ERR_ARG;
+    if (!h->have) return fail(h, RHOSVD_ERR_STATE, "no successful rhosvd_reduce on this handle");
+    if (l < 0 || l > 2 || !sigma_all) return fail(h, RHOSVD_ERR_ARG, "mode must be 0..2, pointer non-null");
+    CK(h, hipMemcpyAsync(sigma_all, h->sigma[l], (size_t)h->m * 8, hipMemcpyDeviceToDevice, h->stream));
+    return RHOSVD_OK;
+}
+
+__global__ void k_v_to_f64(int r, int ldv, int64_t R, const float* __restrict__ V, double* __restrict__ out) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)r * R; e += (int64_t)gridDim.x * blockDim.x) {
+        int64_t j = e % r, nu = e / r;
+        out[e] = (double)V[j + nu * ldv];
+    }
+}
+
+rhosvd_status rhosvd_get_v(rhosvd_handle h, int32_t l, double* V) {
+    if (!h) return RHOSVD_ERR_ARG;
+    if (!h->have) return fail(h, RHOSVD_ERR_STATE, "no successful rhosvd_reduce on this handle");
+    if (l < 0 || l > 2 || !V) return fail(h, RHOSVD_ERR_ARG, "mode must be 0..2, pointer non-null");
+    const int r = h->ranks[l];
+    if (r < 1) return RHOSVD_OK;
+    if (h->vprec == RHOSVD_FP64) {
+        CK(h, hipMemcpy2DAsync(V, (size_t)r * 8, h->V[l], (size_t)h->r_pad[l] * 8, (size_t)r * 8, (size_t)h->R,
+                               hipMemcpyDeviceToDevice, h->stream));
+    } else {
+        hipLaunchKernelGGL(k_v_to_f64, dim3(1024), dim3(256), 0, h->stream, r, h->r_pad[l], h->R,
+                           (const float*)h->V[l], V);
+        CK(h, hipGetLastError());
+    }
+    return RHOSVD_OK;
+}
+
+double rhosvd_phase_ms(rhosvd_handle h, int32_t phase) {
+    if (!h || !h->opt.profile || !h->ev_ok || phase < 0 || phase >= NPHASE) return -1.0;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return -1.0;
+    float ms = -1.0f;
+    if (phase < 6) {
+        if (!h->reduce_timed) return -1.0;
+        if (hipEventElapsedTime(&ms, h->ev[phase], h->ev[phase + 1]) != hipSuccess) return -1.0;
+    } else {
+        if (!h->get_timed) return -1.0;
+        if (hipEventElapsedTime(&ms, h->ev[7], h->ev[8]) != hipSuccess) return -1.0;
+    }
+    return (double)ms;
+}
+
+}  // extern "C"

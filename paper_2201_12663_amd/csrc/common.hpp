@@ -1,0 +1,84 @@
+// Shared device helpers for the gfx950 kernels of the Reduced HOSVD library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+
+#define WAVE 64
+
+// ---------------------------------------------------------------------------
+// MFMA fragment layouts (CDNA3/CDNA4, 16x16 output tiles, one wave):
+//   A operand (16 x K):  lane l holds rows  (l % 16), k-group (l / 16)
+//   B operand (K x 16):  lane l holds cols  (l % 16), k-group (l / 16)
+//   C/D (16 x 16), register i = 0..3 of lane l holds column l % 16 and row
+//       f64 16x16x4:              4*i + l/16   (rows interleaved across lane groups)
+//       f32 16x16x4, bf16 16x16x32: 4*(l/16) + i (4 consecutive rows per lane)
+// f64/f32 16x16x4: k-group g = single k index g (4 k per instruction)
+// bf16 16x16x32:   k-group g = k indices 8g .. 8g+7 (8 bf16 per lane)
+// (checked on gfx950 with one-hot operands)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ d4_t mfma_f64(double a, double b, d4_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4_t mfma_f32(float a, float b, f4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4_t mfma_bf16(bf8_t a, bf8_t b, f4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ int c_row64(int lane, int i) { return 4 * i + (lane >> 4); }
+__device__ __forceinline__ int c_row32(int lane, int i) { return 4 * (lane >> 4) + i; }
+__device__ __forceinline__ int c_col(int lane) { return lane & 15; }
+
+// ---------------------------------------------------------------------------
+// wave reductions (64 lanes)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
+    return v;
+}
+__device__ __forceinline__ int wave_or(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, WAVE);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Grid-wide barrier for kernels launched cooperatively (every block resident).
+// count/gen live in device memory, zero-initialised before the launch.
+// All threads fence their writes at device scope before arriving, and after
+// leaving, so data written before the barrier is visible to every block after.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void grid_barrier(unsigned* count, unsigned* gen, unsigned nblocks) {
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned g = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned arrived = __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == nblocks - 1) {
+            __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g)
+                __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    __syncthreads();
+    __threadfence();
+}
+
+// ---------------------------------------------------------------------------
+// host-side launch helpers
+// ---------------------------------------------------------------------------
+__host__ __device__ static inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ static inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }

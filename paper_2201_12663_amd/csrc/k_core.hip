@@ -1,0 +1,274 @@
+// a7: the Khatri-Rao core contraction (Proposition 2.2)
+//     beta[j1, j2, j3] = sum_nu xi'_nu V1[j1,nu] V2[j2,nu] V3[j3,nu]
+// as one MFMA GEMM  beta_(1) = (V1 diag(xi')) * (V3 (.) V2)^T  with M = r1,
+// N = r2*r3, K = R.  The Khatri-Rao operand is never stored: each K-chunk of
+// V2 and V3 (16 rows each) is staged in LDS and the B fragments are formed in
+// registers as V2[j2,nu]*V3[j3,nu].
+//
+// Workgroup tile: TM rows of j1 x 256 columns = 16 (j2) x 16 (j3); 4 waves, wave
+// w owns columns j3 in [4w, 4w+4).  K chunks are double-buffered in LDS with the
+// next chunk's global loads in flight during the current chunk's MFMAs.
+// Tiles are assigned XCD-contiguously: block b runs on XCD b % 8, and each XCD
+// gets one contiguous range of tiles, ordered so neighbouring tiles share V1 rows.
+//
+// Variants: FP64 (v_mfma_f64_16x16x4, TM=64), FP32 (v_mfma_f32_16x16x4, TM=64)
+// and BF16x3 (v_mfma_f32_16x16x32_bf16, TM=128): a = a_hi + a_lo, b = b_hi + b_lo
+// in bf16, a*b ~ a_hi b_hi + a_hi b_lo + a_lo b_hi, FP32 accumulation.
+#include <hip/hip_runtime.h>
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace {
+
+constexpr int NXCD = 8;
+constexpr int TN2 = 16, TN3 = 16;
+
+__device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t per) {
+    return (bid % NXCD) * per + bid / NXCD;
+}
+
+template <typename T>
+__device__ __forceinline__ void store_beta(double* __restrict__ beta, int r1, int r2, int r3, int j1, int j2,
+                                           int j3, T v) {
+    if (j1 < r1 && j2 < r2 && j3 < r3) beta[(int64_t)j1 + (int64_t)r1 * ((int64_t)j2 + (int64_t)r2 * j3)] = (double)v;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 / FP32 variant, TM = 64, KC = 16
+// ---------------------------------------------------------------------------
+template <typename T>
+struct MF;
+template <>
+struct MF<double> {
+    typedef d4_t acc_t;
+    static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) { return mfma_f64(a, b, c); }
+    static __device__ __forceinline__ int row(int lane, int i) { return c_row64(lane, i); }
+};
+template <>
+struct MF<float> {
+    typedef f4_t acc_t;
+    static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) { return mfma_f32(a, b, c); }
+    static __device__ __forceinline__ int row(int lane, int i) { return c_row32(lane, i); }
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_core_std(int r1, int r2, int r3, int ld1, int ld2, int ld3,
+                                                  int64_t Kp, const T* __restrict__ V1,
+                                                  const T* __restrict__ V2, const T* __restrict__ V3,
+                                                  const double* __restrict__ xip, double* __restrict__ beta,
+                                                  int MT, int N2T, int N3T, int64_t per) {
+    constexpr int TM = 64, KC = 16;
+    typedef typename MF<T>::acc_t acc_t;
+    __shared__ T sA[2][KC][TM];
+    __shared__ T s2[2][KC][TN2];
+    __shared__ T s3[2][KC][TN3];
+    const int64_t ntile = (int64_t)MT * N2T * N3T;
+    const int64_t tile = xcd_tile(blockIdx.x, per);
+    if (tile >= ntile) return;
+    const int NT = N2T * N3T;
+    const int mt = (int)(tile / NT), nt = (int)(tile % NT);
+    const int n3t = nt / N2T, n2t = nt % N2T;
+    const int m0 = mt * TM, b2 = n2t * TN2, b3 = n3t * TN3;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+
+    // staging maps: A 64 x 16 (4 per thread), V2/V3 16 x 16 (1 each)
+    const int ai = t & 63, ak = t >> 6;
+    const int vi = t & 15, vk = t >> 4;
+    T ra[4], rv2, rv3;
+    auto gload = [&](int64_t k0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t k = k0 + ak + 4 * q;
+            ra[q] = V1[(int64_t)(m0 + ai) + k * ld1] * (T)xip[k];
+        }
+        rv2 = V2[(int64_t)(b2 + vi) + (k0 + vk) * ld2];
+        rv3 = V3[(int64_t)(b3 + vi) + (k0 + vk) * ld3];
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sA[buf][ak + 4 * q][ai] = ra[q];
+        s2[buf][vk][vi] = rv2;
+        s3[buf][vk][vi] = rv3;
+    };
+
+    acc_t acc[4][4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) acc[f][g] = acc_t{0, 0, 0, 0};
+
+    const int64_t nchunk = Kp / KC;
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int64_t c = 0; c < nchunk; ++c) {
+        const int buf = (int)(c & 1);
+        if (c + 1 < nchunk) gload((c + 1) * KC);
+#pragma unroll
+        for (int kk = 0; kk < KC / 4; ++kk) {
+            const int k = 4 * kk + (lane >> 4);
+            T a[4], b[4];
+#pragma unroll
+            for (int f = 0; f < 4; ++f) a[f] = sA[buf][k][16 * f + (lane & 15)];
+            const T v2 = s2[buf][k][lane & 15];
+#pragma unroll
+            for (int g = 0; g < 4; ++g) b[g] = v2 * s3[buf][k][4 * w + g];
+#pragma unroll
+            for (int f = 0; f < 4; ++f)
+#pragma unroll
+                for (int g = 0; g < 4; ++g) acc[f][g] = MF<T>::mma(a[f], b[g], acc[f][g]);
+        }
+        if (c + 1 < nchunk) lstore(buf ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                store_beta(beta, r1, r2, r3, m0 + 16 * f + MF<T>::row(lane, i), b2 + c_col(lane), b3 + 4 * w + g,
+                           acc[f][g][i]);
+}
+
+// ---------------------------------------------------------------------------
+// BF16x3 variant, TM = 128, KC = 32.  V_l are FP32.
+// ---------------------------------------------------------------------------
+constexpr int BTM = 128, BKC = 32, BLDA = BKC + 8;   // bf16 elements per LDS row of A
+
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
+    hi = (__bf16)x;
+    lo = (__bf16)(x - (float)hi);
+}
+
+__global__ __launch_bounds__(256) void k_core_bf16x3(int r1, int r2, int r3, int ld1, int ld2, int ld3,
+                                                     int64_t Kp, const float* __restrict__ V1,
+                                                     const float* __restrict__ V2, const float* __restrict__ V3,
+                                                     const double* __restrict__ xip, double* __restrict__ beta,
+                                                     int MT, int N2T, int N3T, int64_t per) {
+    __shared__ __attribute__((aligned(16))) __bf16 sAh[2][BTM * BLDA];
+    __shared__ __attribute__((aligned(16))) __bf16 sAl[2][BTM * BLDA];
+    __shared__ float s2[2][BKC][TN2];
+    __shared__ float s3[2][BKC][TN3];
+    const int64_t ntile = (int64_t)MT * N2T * N3T;
+    const int64_t tile = xcd_tile(blockIdx.x, per);
+    if (tile >= ntile) return;
+    const int NT = N2T * N3T;
+    const int mt = (int)(tile / NT), nt = (int)(tile % NT);
+    const int n3t = nt / N2T, n2t = nt % N2T;
+    const int m0 = mt * BTM, b2 = n2t * TN2, b3 = n3t * TN3;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+
+    // staging: A 128 x 32 (16 per thread), V2/V3 32 x 16 (2 each)
+    const int ai = t & 127, ak = t >> 7;           // k = ak + 2q
+    const int vi = t & 15, vk = t >> 4;            // k = vk, vk + 16
+    float ra[16], rv2[2], rv3[2];
+    auto gload = [&](int64_t k0) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int64_t k = k0 + ak + 2 * q;
+            ra[q] = V1[(int64_t)(m0 + ai) + k * ld1] * (float)xip[k];
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            rv2[q] = V2[(int64_t)(b2 + vi) + (k0 + vk + 16 * q) * ld2];
+            rv3[q] = V3[(int64_t)(b3 + vi) + (k0 + vk + 16 * q) * ld3];
+        }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            __bf16 h, l;
+            split_bf16(ra[q], h, l);
+            sAh[buf][ai * BLDA + ak + 2 * q] = h;
+            sAl[buf][ai * BLDA + ak + 2 * q] = l;
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            s2[buf][vk + 16 * q][vi] = rv2[q];
+            s3[buf][vk + 16 * q][vi] = rv3[q];
+        }
+    };
+
+    f4_t acc[8][4];
+#pragma unroll
+    for (int f = 0; f < 8; ++f)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) acc[f][g] = f4_t{0.f, 0.f, 0.f, 0.f};
+
+    const int64_t nchunk = Kp / BKC;
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    const int kg = 8 * (lane >> 4);   // this lane's 8 k indices
+    for (int64_t c = 0; c < nchunk; ++c) {
+        const int buf = (int)(c & 1);
+        if (c + 1 < nchunk) gload((c + 1) * BKC);
+        // B fragments: 8 k values of column (j2 = lane%16, j3 = 4w+g), split hi/lo
+        bf8_t bh[4], bl[4];
+        float v2[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v2[e] = s2[buf][kg + e][lane & 15];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                __bf16 h, l;
+                split_bf16(v2[e] * s3[buf][kg + e][4 * w + g], h, l);
+                bh[g][e] = h;
+                bl[g][e] = l;
+            }
+        }
+#pragma unroll
+        for (int f = 0; f < 8; ++f) {
+            const int row = 16 * f + (lane & 15);
+            const bf8_t ah = *reinterpret_cast<const bf8_t*>(&sAh[buf][row * BLDA + kg]);
+            const bf8_t al = *reinterpret_cast<const bf8_t*>(&sAl[buf][row * BLDA + kg]);
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                acc[f][g] = mfma_bf16(ah, bh[g], acc[f][g]);
+                acc[f][g] = mfma_bf16(ah, bl[g], acc[f][g]);
+                acc[f][g] = mfma_bf16(al, bh[g], acc[f][g]);
+            }
+        }
+        if (c + 1 < nchunk) lstore(buf ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int f = 0; f < 8; ++f)
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                store_beta(beta, r1, r2, r3, m0 + 16 * f + c_row32(lane, i), b2 + c_col(lane), b3 + 4 * w + g,
+                           acc[f][g][i]);
+}
+
+}  // namespace
+
+hipError_t launch_core(const CoreArgs& a, hipStream_t st) {
+    if (a.r[0] < 1 || a.r[1] < 1 || a.r[2] < 1) return hipSuccess;
+    const int TMv = (a.prec == 2) ? BTM : 64;
+    const int KCv = (a.prec == 2) ? BKC : 16;
+    if (a.R_pad % KCv != 0) return hipErrorInvalidValue;
+    const int MT = (int)ceil_div(a.r[0], TMv), N2T = (int)ceil_div(a.r[1], TN2), N3T = (int)ceil_div(a.r[2], TN3);
+    // the kernels read whole tiles: padded rows must exist (and be zero)
+    if (a.r_pad[0] < MT * TMv || a.r_pad[1] < N2T * TN2 || a.r_pad[2] < N3T * TN3) return hipErrorInvalidValue;
+    const int64_t ntile = (int64_t)MT * N2T * N3T;
+    const int64_t per = ceil_div(ntile, NXCD);
+    dim3 grid((unsigned)(per * NXCD));
+    if (a.prec == 0) {
+        hipLaunchKernelGGL(k_core_std<double>, grid, dim3(256), 0, st, a.r[0], a.r[1], a.r[2], a.r_pad[0], a.r_pad[1],
+                           a.r_pad[2], a.R_pad, (const double*)a.V[0], (const double*)a.V[1],
+                           (const double*)a.V[2], a.xip, a.beta, MT, N2T, N3T, per);
+    } else if (a.prec == 1) {
+        hipLaunchKernelGGL(k_core_std<float>, grid, dim3(256), 0, st, a.r[0], a.r[1], a.r[2], a.r_pad[0], a.r_pad[1],
+                           a.r_pad[2], a.R_pad, (const float*)a.V[0], (const float*)a.V[1],
+                           (const float*)a.V[2], a.xip, a.beta, MT, N2T, N3T, per);
+    } else {
+        hipLaunchKernelGGL(k_core_bf16x3, grid, dim3(256), 0, st, a.r[0], a.r[1], a.r[2], a.r_pad[0], a.r_pad[1],
+                           a.r_pad[2], a.R_pad, (const float*)a.V[0], (const float*)a.V[1],
+                           (const float*)a.V[2], a.xip, a.beta, MT, N2T, N3T, per);
+    }
+    return hipGetLastError();
+}

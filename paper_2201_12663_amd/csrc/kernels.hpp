@@ -1,0 +1,104 @@
+// Host-side launchers of the gfx950 kernels (internal to the library).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+// Padding granularities shared by the workspace layout and the kernels.
+constexpr int PAD_N = 64;    // rows of U~, Z and the Gram side (n, m)
+constexpr int PAD_R = 64;    // canonical terms (columns of U~, K of the core)
+constexpr int PAD_V = 64;    // rows r_l of V^(l)
+constexpr int JB = 16;       // eigensolver block size (pairs of blocks = 32 indices)
+
+// a1: scaled column norms, xi' and normalized side matrices (all three modes).
+// U_l: n x R (ld n); Ut_l: n_pad x R_pad (ld n_pad), zero padded; xip: R_pad.
+// flags[0] |= 1 on a non-finite input; flags[1] += number of dropped terms.
+hipError_t launch_colnorm(int64_t n, int64_t R, int64_t n_pad, int64_t R_pad,
+                          const double* const U[3], const double* xi,
+                          double* const Ut[3], double* xip, int* flags, hipStream_t st);
+
+// a2: G_l = U~_l U~_l^T (n_pad x n_pad, col-major) for l = 0..2, split over K.
+// part: workspace of splits * 3 * n_pad^2 doubles (unused when splits == 1).
+hipError_t launch_gram_nt(int64_t n_pad, int64_t R_pad, double* const Ut[3], double* const G[3],
+                          double* part, int splits, hipStream_t st);
+
+// |A|^2 = xi'^T (G1 o G2 o G3) xi' with G_l = U~_l^T U~_l, per-tile partial sums
+// written to part (ntiles doubles); the caller reduces them in a fixed order.
+// When Gr is non-null the three R_pad x R_pad Grams U~_l^T U~_l are written too
+// (the Gram on the R side, used when R < n).
+hipError_t launch_anorm_partials(int64_t n_pad, int64_t R_pad, double* const Ut[3],
+                                 const double* xip, double* part, int64_t* ntiles, double* const Gr[3],
+                                 hipStream_t st);
+
+// Generic FP64 MFMA GEMM on padded operands, C = alpha A B (col-major C).
+//   a_kcontig: A(i,k) = A[k + i*lda], else A[i + k*lda]
+//   b_kcontig: B(k,j) = B[k + j*ldb], else B[j + k*ldb]
+hipError_t launch_gemm64(bool a_kcontig, bool b_kcontig, int64_t M, int64_t N, int64_t K, const double* A,
+                         int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc, double alpha,
+                         hipStream_t st);
+// R < n helpers (Z = U~ W Lambda^-1/2 and its re-orthonormalization)
+hipError_t launch_gather_scaled(int m_pad, int r, int r_pad, const double* W, const int* order,
+                                const double* sigma, double* Wr, hipStream_t st);
+hipError_t launch_pad_identity(int r, int mp, double* M, hipStream_t st);
+hipError_t launch_scale_cols_invsqrt(int mp, const double* D, double* P, hipStream_t st);
+hipError_t launch_sign_cols(int n, int n_pad, int r, double* Z, hipStream_t st);
+
+// a6: V_l = Z_l^T U~_l (r_pad x R_pad, col-major ld r_pad); Z_l: n_pad x r_pad (ld n_pad).
+// out_f64 or out_f32 (one of them non-null).
+hipError_t launch_project(int64_t n_pad, int64_t R_pad, int64_t r_pad, const double* Z,
+                          const double* Ut, double* out_f64, float* out_f32, hipStream_t st);
+
+// a3: block Jacobi eigensolver on up to 3 symmetric matrices of one size
+// (cooperative launch).  G is overwritten (its diagonal holds the eigenvalues),
+// W receives the eigenvectors.  Returns the sweeps used in *sweeps (host) after
+// a stream synchronization is done by the caller (sweeps_dev).
+struct JacobiProblem {
+    double* G[3];
+    double* W[3];
+    int nmat;
+    int m_pad;        // multiple of 2*JB
+    int max_sweeps;
+    double tol;       // rotation threshold = tol * |G|_F
+};
+hipError_t launch_jacobi(const JacobiProblem& p, void* work, size_t work_bytes,
+                         int* sweeps_dev, hipStream_t st);
+size_t jacobi_work_bytes(int nmat, int m_pad, int max_sweeps);
+
+// a4/a5: norms finalize, sort, tails, ranks, sign-normalized Z (per mode).
+struct TruncArgs {
+    const double* G[3];     // diagonal = eigenvalues
+    const double* W[3];     // eigenvectors
+    int m;                  // valid eigenpairs (min(n, R))
+    int m_pad;
+    int n;
+    int n_pad;
+    const double* xip;      // R_pad
+    int64_t R_pad;
+    const double* anorm_part;
+    int64_t anorm_ntiles;
+    double eps;
+    // outputs
+    double* sigma[3];       // m each, descending
+    int* order[3];          // m each: column of W for the k-th largest
+    double* tails[3];       // m + 1 each
+    int* ranks;             // 3 ints
+    double* scal;           // [0] xi_norm, [1] a_norm, [2] tau
+};
+hipError_t launch_truncate(const TruncArgs& a, hipStream_t st);
+
+// Z_l (n_pad x r_pad, ld n_pad) from W columns order[0..r-1], sign-normalized,
+// zero beyond r rows/cols.  Also an optional FP32 copy.
+hipError_t launch_form_z(int n, int n_pad, int r, int r_pad, const double* W, int ldw,
+                         const int* order, double* Z, hipStream_t st);
+
+// a7: beta[j1 + r1 (j2 + r2 j3)] = sum_nu xi'_nu V1[j1,nu] V2[j2,nu] V3[j3,nu].
+// V_l: col-major (r_pad_l x R_pad), xip: R_pad.  prec 0 = f64, 1 = f32, 2 = bf16x3.
+struct CoreArgs {
+    int r[3];
+    int r_pad[3];
+    int64_t R_pad;
+    const void* V[3];
+    const double* xip;
+    double* beta;
+    int prec;
+};
+hipError_t launch_core(const CoreArgs& a, hipStream_t st);

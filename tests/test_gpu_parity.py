@@ -1,0 +1,198 @@
+"""Parity of the HIP path (through the C-ABI) with the CPU oracle.
+
+Sizes span several tiles with ragged tails (n, R not multiples of 64; ranks not
+multiples of the core tiles).  Full-size n=1024, R=4096 parity is against stored
+oracle values (tests/golden/newton1024_seed0.json, written by make_golden.py)
+plus properties that hold at any size.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2201_12663_amd import inputs
+import gpu_cases as gc
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _flush(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    import torch
+    from paper_2201_12663_amd import rhosvd
+    assert torch.cuda.is_available()
+    rhosvd.load()
+
+
+CASES = [
+    ("gauss n64 R200", lambda: inputs.small_gaussian_sum(0)),
+    ("gauss n100 R333", lambda: inputs.small_gaussian_sum(1, n=100, R=333, eps=1e-5)),
+    ("newton n160 R640", lambda: inputs.newton_centres(2, n=160, n_centres=20, eps=1e-5)),
+    ("lowrank n70 R150", lambda: inputs.exactly_low_rank(3, 70, 150, ranks=(3, 7, 12), eps=1e-8)),
+    # R < n: Gram on the R side, Z = U~ W Lambda^-1/2 re-orthonormalized in FP64
+    ("gauss n200 R90 (R<n)", lambda: inputs.small_gaussian_sum(11, n=200, R=90, eps=1e-5)),
+    ("newton n300 R160 (R<n)", lambda: inputs.newton_centres(12, n=300, n_centres=5, eps=1e-5)),
+]
+
+
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_fp64_parity(orc, name, make):
+    ci = make()
+    _flush(f"case {name}: n={ci.n} R={ci.R} eps={ci.eps}")
+    o = orc.rhosvd(ci.U, ci.xi, ci.eps)
+    g = gc.run_gpu(ci, "fp64")
+    gc.compare_fp64(g, o, ci)
+    err = gc.recon_error(orc, ci, g["Z"], g["beta"])
+    assert err <= ci.eps * o.a_norm * (1 + 1e-9)
+    assert err <= g["report"]["bound"] * (1 + 1e-9) + 1e-12 * o.a_norm
+
+
+def test_exactly_low_rank_r_side(orc):
+    ci = inputs.exactly_low_rank(5, 130, 40, ranks=(4, 6, 3), eps=1e-4)
+    g = gc.run_gpu(ci, "fp64")
+    assert g["ranks"] == (4, 6, 3)
+    Ut, xip, _, _ = orc.normalize(ci.U, ci.xi)
+    a = orc.anorm_gram(Ut, xip)
+    assert gc.recon_error(orc, ci, g["Z"]) <= 1e-11 * a
+
+
+def test_exactly_low_rank_reconstruction(orc):
+    # eps well above the FP64 Gram's noise floor: tau^2 >> (m - r) u |G|, so the
+    # exact ranks must come out (at eps = 1e-8 the noise eigenvalues of the Gram
+    # exceed tau^2 and the ranks may only grow, see the parity case above)
+    ci = inputs.exactly_low_rank(4, 48, 90, ranks=(2, 5, 9), eps=1e-4)
+    g = gc.run_gpu(ci, "fp64")
+    assert g["ranks"] == (2, 5, 9)
+    err = gc.recon_error(orc, ci, g["Z"], g["beta"])
+    Ut, xip, _, _ = orc.normalize(ci.U, ci.xi)
+    a = float(np.linalg.norm(orc.full_tensor(Ut, xip).ravel()))
+    assert err <= 1e-12 * a
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_mixed_precision_parity(orc, prec):
+    ci = inputs.small_gaussian_sum(5, n=96, R=300, eps=1e-5)
+    _flush(f"mixed {prec}")
+    o = orc.rhosvd(ci.U, ci.xi, ci.eps)
+    g64 = gc.run_gpu(ci, "fp64")
+    g = gc.run_gpu(ci, prec)
+    # Gram, eigensolver and truncation are FP64 in every mode: identical ranks and Z
+    assert g["ranks"] == g64["ranks"]
+    for l in range(3):
+        assert np.array_equal(g["Z"][l], g64["Z"][l])
+    err = gc.recon_error(orc, ci, g["Z"], g["beta"])
+    assert err <= (ci.eps + 1e-6) * o.a_norm
+    db = np.linalg.norm((g["beta"] - g64["beta"]).ravel()) / o.a_norm
+    assert db <= (1e-5 if prec == "bf16x3" else 1e-6), db
+
+
+def test_degenerate_single_term(orc):
+    g0 = np.random.default_rng(1)
+    U = [np.asfortranarray(g0.standard_normal((37, 1))) for _ in range(3)]
+    ci = inputs.CanonicalInput(U, np.array([-2.5]), 1e-6)
+    g = gc.run_gpu(ci, "fp64")
+    assert g["ranks"] == (1, 1, 1)
+    nrm = np.prod([np.linalg.norm(u) for u in U])
+    assert abs(abs(g["beta"][0, 0, 0]) - 2.5 * nrm) <= 1e-12 * 2.5 * nrm
+
+
+def test_dropped_terms_and_all_dropped(orc):
+    ci = inputs.small_gaussian_sum(6, n=40, R=80, eps=1e-5)
+    U = [u.copy() for u in ci.U]
+    U[2][:, 5] = 0.0
+    xi = ci.xi.copy()
+    xi[9] = 0.0
+    ci2 = inputs.CanonicalInput(U, xi, ci.eps)
+    o = orc.rhosvd(U, xi, ci.eps)
+    g = gc.run_gpu(ci2, "fp64")
+    assert g["report"]["dropped"] == 2
+    assert g["xip"][5] == 0.0 and g["xip"][9] == 0.0
+    gc.compare_fp64(g, o, ci2)
+    ci3 = inputs.CanonicalInput(U, np.zeros(80), ci.eps)
+    g3 = gc.run_gpu(ci3, "fp64")
+    assert g3["ranks"] == (0, 0, 0)
+
+
+def test_nonfinite_input_is_rejected():
+    import torch
+    from paper_2201_12663_amd import rhosvd
+    ci = inputs.small_gaussian_sum(7, n=32, R=50)
+    U = [u.copy() for u in ci.U]
+    U[1][3, 4] = np.nan
+    Ud = [rhosvd.to_device(u) for u in U]
+    xi = torch.from_numpy(ci.xi).cuda()
+    red = rhosvd.Reducer()
+    with pytest.raises(rhosvd.RhosvdError) as e:
+        red.reduce(Ud[0], Ud[1], Ud[2], xi, 1e-6)
+    assert e.value.status == -2
+    with pytest.raises(rhosvd.RhosvdError) as e:
+        red.reduce(Ud[0], Ud[1], Ud[2], xi, -1.0)
+    assert e.value.status == -1
+    with pytest.raises(rhosvd.RhosvdError) as e:
+        red.get()
+    assert e.value.status == -6
+    red.close()
+
+
+def test_deterministic_repeat():
+    ci = inputs.small_gaussian_sum(8, n=128, R=400, eps=1e-5)
+    a = gc.run_gpu(ci, "fp64")
+    b = gc.run_gpu(ci, "fp64")
+    assert a["ranks"] == b["ranks"]
+    assert np.array_equal(a["beta"], b["beta"])
+    for l in range(3):
+        assert np.array_equal(a["Z"][l], b["Z"][l])
+
+
+def test_full_size_newton1024_vs_golden(orc):
+    """n=1024, R=4096, eps=1e-5: the configuration the benchmark times."""
+    gold = json.load(open(os.path.join(HERE, "golden", "newton1024_seed0.json")))
+    ci = inputs.newton_centres(0)
+    _flush("full size n=1024 R=4096")
+    g = gc.run_gpu(ci, "fp64")
+    rep = g["report"]
+    assert abs(rep["a_norm"] - gold["a_norm"]) <= 1e-10 * gold["a_norm"]
+    assert abs(rep["xi_norm"] - gold["xi_norm"]) <= 1e-12 * gold["xi_norm"]
+    for l in range(3):
+        so = np.array(gold["sigma"][l])
+        s1 = so[0]
+        d2 = np.abs(g["spectra"][l] ** 2 - so ** 2)
+        assert np.all(d2 <= gc.eig_tol(ci.n, ci.R) * s1 ** 2), (l, d2.max() / s1 ** 2)
+        tails = np.sqrt(np.concatenate([np.cumsum((so ** 2)[::-1])[::-1], [0.0]]))
+        if gc.cut_margin_ok(tails, gold["ranks"][l], gold["tau"], s1):
+            assert g["ranks"][l] == gold["ranks"][l]
+        r = g["ranks"][l]
+        Z = g["Z"][l]
+        assert np.max(np.abs(Z.T @ Z - np.eye(r))) <= 1e-11
+    # sampled core entries (oracle's sign convention; separated singular vectors)
+    if list(g["ranks"]) == gold["ranks"]:
+        for j1, j2, j3, v in gold["beta_samples"]:
+            assert abs(g["beta"][j1, j2, j3] - v) <= 1e-9 * gold["xi_norm"], (j1, j2, j3)
+    err = gc.recon_error(orc, ci, g["Z"])
+    assert err <= ci.eps * gold["a_norm"]
+    assert err <= rep["bound"] * (1 + 1e-9)
+    _flush(f"full size: ranks {g['ranks']} rel err {err / gold['a_norm']:.3e}")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_full_size_newton1024_mixed(orc, prec):
+    import torch
+    ci = inputs.newton_centres(0)
+    _flush(f"full size mixed {prec}")
+    g64 = gc.run_gpu(ci, "fp64")
+    g = gc.run_gpu(ci, prec)
+    assert g["ranks"] == g64["ranks"]
+    err_z = gc.recon_error(orc, ci, g["Z"])
+    a = g64["report"]["a_norm"]
+    db = float(np.linalg.norm((g["beta"] - g64["beta"]).ravel()))
+    # A - A_r is orthogonal to the Tucker subspace, the core error lies inside it
+    err = float(np.sqrt(err_z ** 2 + db ** 2))
+    _flush(f"{prec}: rel err {err / a:.3e} (core part {db / a:.3e})")
+    assert err <= (ci.eps + 1e-6) * a
