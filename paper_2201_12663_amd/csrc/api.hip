@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 
 #include "../../include/rhosvd.h"
@@ -16,8 +17,7 @@ namespace {
 
 constexpr int NPHASE = 7;
 constexpr int NEV = 9;            // 0..6 bracket the reduce phases, 7..8 the core
-constexpr int DEFAULT_SWEEPS = 30;
-constexpr double JACOBI_TOL = 4.0 * 1.1102230246251565e-16;   // rotation threshold / |G|_F
+constexpr int DEFAULT_SWEEPS = 30;   // kept for the options ABI; the eigensolver has no sweep cap
 constexpr int RPAD_CORE = 128;                                 // V row padding (core tiles)
 
 std::string g_create_error;
@@ -37,39 +37,53 @@ struct rhosvd_ctx {
     double* hostd = nullptr;
     // layout of the last reduction
     int64_t n = 0, R = 0, n_pad = 0, R_pad = 0, m = 0, m_pad = 0, zr_pad = 0;
-    double* Ut[3] = {};
-    double* xip = nullptr;
+    bool rside = false;                  // R < n: Gram on the R side
+    double* Ut[3] = {};                  // normalized side matrices (n_pad x R_pad)
+    double* xip = nullptr;               // xi' (R_pad)
     int* flags = nullptr;
-    double* G[3] = {};
-    double* W[3] = {};
+    double* G[3] = {};                   // Gram (m_pad^2) -> Householder vectors
+    double* W[3] = {};                   // eigenvectors of the tridiagonal matrix
+    double* Qn[3] = {};                  // eigensolver workspace (m_pad^2 each)
+    double* Mg[3] = {};
+    double* lam[3] = {};                 // eigenvalues (m_pad)
+    double* dd[3] = {};
+    double* ee[3] = {};
+    double* htau[3] = {};                // Householder scalars
+    double* Tw[3] = {};                  // compact-WY factors of the back-transformation
+    double* pb[3] = {};
+    void* eigw = nullptr;
+    size_t eigw_bytes = 0;
     double* gram_part = nullptr;
     int gram_splits = 1;
     double* anorm_part = nullptr;
     int64_t anorm_ntiles = 0;
-    void* jac = nullptr;
-    size_t jac_bytes = 0;
-    int* sweeps_dev = nullptr;
     double* sigma[3] = {};
     int* order[3] = {};
     double* tails[3] = {};
     int* ranks_dev = nullptr;
     double* scal = nullptr;
-    double* Z[3] = {};
-    void* V[3] = {};
+    double* Z[3] = {};                   // n_pad x zr_pad
+    void* V[3] = {};                     // zr_pad x R_pad (FP64 or FP32)
     int vprec = 0;
-    bool rside = false;                  // R < n: Gram on the R side
-    double* Wr[3] = {};                  // R < n: W_r Lambda_r^-1/2 (R_pad x zr_pad)
-    double* Zraw[3] = {};                // R < n: U~ W_r Lambda_r^-1/2 (n_pad x zr_pad)
-    double* M2[3] = {};                  // R < n: Z^T Z and its eigenvectors (zr_pad^2 each)
-    double* P2[3] = {};
+    // R < n: Z = U~ W_r Lambda_r^-1/2, re-orthonormalized by (Z^T Z)^-1/2
+    double* Wr[3] = {};                  // R_pad x zr_pad
+    double* Zraw[3] = {};                // n_pad x zr_pad
+    double* M2[3] = {};                  // zr_pad^2: Z^T Z (-> reflectors), then S
+    double* P2[3] = {};                  // eigenvectors of the tridiagonal of Z^T Z
+    double* Qn2[3] = {};
+    double* Mg2[3] = {};
+    double* Pf[3] = {};                  // eigenvectors of Z^T Z
     double* S2[3] = {};
-    void* jac2 = nullptr;
-    size_t jac2_bytes = 0;
+    double* lam2[3] = {};
+    double* dd2[3] = {};
+    double* ee2[3] = {};
+    double* tau2[3] = {};
+    double* pb2[3] = {};
     // results
     bool have = false;
     int ranks[3] = {0, 0, 0};
     int r_pad[3] = {0, 0, 0};
-    double xi_norm = 0, a_norm = 0, tau = 0;
+    double xi_norm = 0, a_norm = 0, tau = 0;   // report values
     int sweeps = 0, dropped = 0;
     // profiling
     hipEvent_t ev[NEV] = {};
@@ -110,7 +124,68 @@ void mark(rhosvd_ctx* h, int i) {
     if (h->opt.profile && h->ev_ok) hipEventRecord(h->ev[i], h->stream);
 }
 
-// carve the workspace for (n, R, precision); grows the allocation when needed
+// Workspace carving: the same walk runs twice, first to size, then to assign.
+struct Carve {
+    char* base;
+    size_t off = 0;
+    template <class T>
+    T* take(size_t count) {
+        T* p = base ? (T*)(base + off) : nullptr;
+        off += a256(count * sizeof(T));
+        return p;
+    }
+};
+
+size_t carve_all(rhosvd_ctx* h, char* base) {
+    Carve c{base};
+    const int64_t np = h->n_pad, Rp = h->R_pad, mp = h->m_pad, zp = h->zr_pad;
+    const int esz = (h->opt.precision == RHOSVD_FP64) ? 8 : 4;
+    for (int l = 0; l < 3; ++l) {
+        h->Ut[l] = c.take<double>((size_t)np * Rp);
+        h->G[l] = c.take<double>((size_t)mp * mp);
+        h->W[l] = c.take<double>((size_t)mp * mp);
+        h->Qn[l] = c.take<double>((size_t)mp * mp);
+        h->Mg[l] = c.take<double>((size_t)mp * mp);
+        h->lam[l] = c.take<double>(mp);
+        h->dd[l] = c.take<double>(mp);
+        h->ee[l] = c.take<double>(mp);
+        h->htau[l] = c.take<double>(mp);
+        h->pb[l] = c.take<double>(mp);
+        h->Tw[l] = c.take<double>(backtransform_work_doubles((int)std::max(mp, zp)));
+        h->sigma[l] = c.take<double>(mp + 1);
+        h->order[l] = c.take<int>(mp);
+        h->tails[l] = c.take<double>(mp + 1);
+        h->Z[l] = c.take<double>((size_t)np * zp);
+        h->V[l] = (void*)c.take<char>((size_t)zp * Rp * esz);
+    }
+    h->xip = c.take<double>(Rp);
+    h->flags = c.take<int>(16);
+    h->gram_part = (h->gram_splits > 1) ? c.take<double>((size_t)h->gram_splits * 3 * np * np) : nullptr;
+    h->anorm_part = c.take<double>(h->anorm_ntiles);
+    h->ranks_dev = c.take<int>(16);
+    h->scal = c.take<double>(8);
+    h->eigw = (void*)c.take<char>(h->eigw_bytes);
+    if (h->rside) {
+        for (int l = 0; l < 3; ++l) {
+            h->Wr[l] = c.take<double>((size_t)Rp * zp);
+            h->Zraw[l] = c.take<double>((size_t)np * zp);
+            h->M2[l] = c.take<double>((size_t)zp * zp);
+            h->P2[l] = c.take<double>((size_t)zp * zp);
+            h->Qn2[l] = c.take<double>((size_t)zp * zp);
+            h->Mg2[l] = c.take<double>((size_t)zp * zp);
+            h->Pf[l] = c.take<double>((size_t)zp * zp);
+            h->S2[l] = c.take<double>((size_t)zp * zp);
+            h->lam2[l] = c.take<double>(zp);
+            h->dd2[l] = c.take<double>(zp);
+            h->ee2[l] = c.take<double>(zp);
+            h->tau2[l] = c.take<double>(zp);
+            h->pb2[l] = c.take<double>(zp);
+        }
+    }
+    return c.off;
+}
+
+// lay out the workspace for (n, R, precision); grows the allocation when needed
 rhosvd_status layout(rhosvd_ctx* h, int64_t n, int64_t R) {
     h->n = n;
     h->R = R;
@@ -120,8 +195,7 @@ rhosvd_status layout(rhosvd_ctx* h, int64_t n, int64_t R) {
     h->rside = R < n;
     h->m_pad = h->rside ? h->R_pad : h->n_pad;   // Gram on the min(n, R) side
     h->zr_pad = round_up(h->m, RPAD_CORE);       // max padded rank
-    const int64_t np = h->n_pad, Rp = h->R_pad, mp = h->m_pad;
-    const int esz = (h->opt.precision == RHOSVD_FP64) ? 8 : 4;
+    const int64_t mp = h->m_pad, Rp = h->R_pad;
     // split-K for the Gram when there are few output tiles
     const int64_t tiles = 3 * (mp / 64) * (mp / 64 + 1) / 2;
     int splits = (int)ceil_div(512, tiles);
@@ -131,76 +205,26 @@ rhosvd_status layout(rhosvd_ctx* h, int64_t n, int64_t R) {
     h->gram_splits = splits;
     const int64_t rt = Rp / 64;
     h->anorm_ntiles = rt * (rt + 1) / 2;
-    h->jac_bytes = jacobi_work_bytes(3, (int)mp, h->opt.max_eig_sweeps);
-
-    size_t off = 0;
-    size_t o_Ut = off;    off += a256((size_t)np * Rp * 8) * 3;
-    size_t o_xip = off;   off += a256((size_t)Rp * 8);
-    size_t o_flags = off; off += a256(64);
-    size_t o_G = off;     off += a256((size_t)mp * mp * 8) * 3;
-    size_t o_W = off;     off += a256((size_t)mp * mp * 8) * 3;
-    size_t o_gp = off;    off += (splits > 1) ? a256((size_t)splits * 3 * np * np * 8) : 0;
-    size_t o_ap = off;    off += a256((size_t)h->anorm_ntiles * 8);
-    size_t o_jac = off;   off += a256(h->jac_bytes);
-    size_t o_sw = off;    off += a256(16);
-    size_t o_sig = off;   off += a256((size_t)(mp + 1) * 8) * 3;
-    size_t o_ord = off;   off += a256((size_t)mp * 4) * 3;
-    size_t o_tl = off;    off += a256((size_t)(mp + 1) * 8) * 3;
-    size_t o_rk = off;    off += a256(64);
-    size_t o_sc = off;    off += a256(64);
-    size_t o_Z = off;     off += a256((size_t)np * h->zr_pad * 8) * 3;
-    size_t o_V = off;     off += a256((size_t)h->zr_pad * Rp * esz) * 3;
-    const int64_t zp = h->zr_pad;
-    h->jac2_bytes = h->rside ? jacobi_work_bytes(3, (int)zp, h->opt.max_eig_sweeps) : 0;
-    size_t o_Wr = off;    off += h->rside ? a256((size_t)Rp * zp * 8) * 3 : 0;
-    size_t o_Zr = off;    off += h->rside ? a256((size_t)np * zp * 8) * 3 : 0;
-    size_t o_M2 = off;    off += h->rside ? a256((size_t)zp * zp * 8) * 9 : 0;
-    size_t o_j2 = off;    off += h->rside ? a256(h->jac2_bytes) : 0;
-    if (off > h->ws_bytes) {
+    h->eigw_bytes = eig_work_bytes(3, (int)h->m);
+    if (h->rside) h->eigw_bytes = std::max(h->eigw_bytes, eig_work_bytes(3, (int)h->zr_pad));
+    const size_t need = carve_all(h, nullptr);
+    if (need > h->ws_bytes) {
         if (h->ws) { hipStreamSynchronize(h->stream); hipFree(h->ws); h->ws = nullptr; h->ws_bytes = 0; }
-        hipError_t e = hipMalloc((void**)&h->ws, off);
+        hipError_t e = hipMalloc((void**)&h->ws, need);
         if (e != hipSuccess) {
             h->ws = nullptr;
-            return fail(h, RHOSVD_ERR_ALLOC, "workspace allocation of " + std::to_string(off) + " bytes failed");
+            return fail(h, RHOSVD_ERR_ALLOC, "workspace allocation of " + std::to_string(need) + " bytes failed");
         }
-        h->ws_bytes = off;
+        h->ws_bytes = need;
     }
-    char* b = h->ws;
-    for (int l = 0; l < 3; ++l) {
-        h->Ut[l] = (double*)(b + o_Ut + l * a256((size_t)np * Rp * 8));
-        h->G[l] = (double*)(b + o_G + l * a256((size_t)mp * mp * 8));
-        h->W[l] = (double*)(b + o_W + l * a256((size_t)mp * mp * 8));
-        h->sigma[l] = (double*)(b + o_sig + l * a256((size_t)(mp + 1) * 8));
-        h->order[l] = (int*)(b + o_ord + l * a256((size_t)mp * 4));
-        h->tails[l] = (double*)(b + o_tl + l * a256((size_t)(mp + 1) * 8));
-        h->Z[l] = (double*)(b + o_Z + l * a256((size_t)np * h->zr_pad * 8));
-        h->V[l] = (void*)(b + o_V + l * a256((size_t)h->zr_pad * Rp * esz));
-    }
-    if (h->rside) {
-        for (int l = 0; l < 3; ++l) {
-            h->Wr[l] = (double*)(b + o_Wr + l * a256((size_t)Rp * zp * 8));
-            h->Zraw[l] = (double*)(b + o_Zr + l * a256((size_t)np * zp * 8));
-            h->M2[l] = (double*)(b + o_M2 + (3 * l + 0) * a256((size_t)zp * zp * 8));
-            h->P2[l] = (double*)(b + o_M2 + (3 * l + 1) * a256((size_t)zp * zp * 8));
-            h->S2[l] = (double*)(b + o_M2 + (3 * l + 2) * a256((size_t)zp * zp * 8));
-        }
-        h->jac2 = (void*)(b + o_j2);
-    }
-    h->xip = (double*)(b + o_xip);
-    h->flags = (int*)(b + o_flags);
-    h->gram_part = (splits > 1) ? (double*)(b + o_gp) : nullptr;
-    h->anorm_part = (double*)(b + o_ap);
-    h->jac = (void*)(b + o_jac);
-    h->sweeps_dev = (int*)(b + o_sw);
-    h->ranks_dev = (int*)(b + o_rk);
-    h->scal = (double*)(b + o_sc);
+    carve_all(h, h->ws);
     h->vprec = h->opt.precision;
     return RHOSVD_OK;
 }
 
 // R < n: Z = U~ W_r Lambda_r^(-1/2) (the left singular vectors from the right
 // ones), then re-orthonormalized in FP64 by Z <- Z (Z^T Z)^(-1/2) (symmetric
-// orthogonalization; Z^T Z = P diag(mu) P^T from the same eigensolver) and
+// orthogonalization, Z^T Z = P diag(mu) P^T from the same eigensolver) and
 // sign-normalized.
 rhosvd_status form_z_rside(rhosvd_ctx* h) {
     hipStream_t st = h->stream;
@@ -209,27 +233,33 @@ rhosvd_status form_z_rside(rhosvd_ctx* h) {
     for (int l = 0; l < 3; ++l) rmp = h->r_pad[l] > rmp ? h->r_pad[l] : rmp;
     for (int l = 0; l < 3; ++l) {
         const int r = h->ranks[l], rp = h->r_pad[l];
-        CK(h, launch_gather_scaled((int)h->m_pad, r, rp, h->W[l], h->order[l], h->sigma[l], h->Wr[l], st));
+        CK(h, hipMemsetAsync(h->Wr[l], 0, (size_t)Rp * zp * 8, st));
+        CK(h, launch_backtransform((int)h->m, (int)h->m_pad, h->G[l], h->htau[l], h->W[l], h->order[l], r, h->Wr[l],
+                                   (int)Rp, (int)Rp, h->Tw[l], st));
+        CK(h, launch_gather_scaled((int)Rp, r, rp, h->Wr[l], nullptr, h->sigma[l], h->Wr[l], st));
         CK(h, hipMemsetAsync(h->Zraw[l], 0, (size_t)np * zp * 8, st));
         CK(h, launch_gemm64(false, true, np, rp, Rp, h->Ut[l], np, h->Wr[l], Rp, h->Zraw[l], np, 1.0, st));
-        CK(h, launch_gemm64(true, true, rp, rp, np, h->Zraw[l], np, h->Zraw[l], np, h->M2[l], rmp, 1.0, st));
-        CK(h, launch_pad_identity(r, rmp, h->M2[l], st));
+        CK(h, launch_gemm64(true, true, rp, rp, np, h->Zraw[l], np, h->Zraw[l], np, h->M2[l], zp, 1.0, st));
+        CK(h, launch_pad_identity(r, rmp, (int)zp, h->M2[l], st));
     }
-    JacobiProblem jp{};
-    for (int l = 0; l < 3; ++l) { jp.G[l] = h->M2[l]; jp.W[l] = h->P2[l]; }
-    jp.nmat = 3;
-    jp.m_pad = rmp;
-    jp.max_sweeps = h->opt.max_eig_sweeps;
-    jp.tol = JACOBI_TOL;
-    CK(h, launch_jacobi(jp, h->jac2, h->jac2_bytes, h->sweeps_dev + 1, st));
+    EigProblem ep{};
     for (int l = 0; l < 3; ++l) {
-        // S = P diag(mu^-1/2) P^T ;  Z = Zraw S
-        CK(h, hipMemcpyAsync(h->S2[l], h->P2[l], (size_t)rmp * rmp * 8, hipMemcpyDeviceToDevice, st));
-        CK(h, launch_scale_cols_invsqrt(rmp, h->M2[l], h->S2[l], st));
-        CK(h, launch_gemm64(false, false, rmp, rmp, rmp, h->S2[l], rmp, h->P2[l], rmp, h->M2[l], rmp, 1.0, st));
-        CK(h, launch_gemm64(false, true, np, rmp, rmp, h->Zraw[l], np, h->M2[l], rmp, h->Z[l], np, 1.0, st));
+        ep.G[l] = h->M2[l]; ep.lam[l] = h->lam2[l]; ep.Q[l] = h->P2[l]; ep.Qn[l] = h->Qn2[l];
+        ep.M[l] = h->Mg2[l]; ep.d[l] = h->dd2[l]; ep.e[l] = h->ee2[l]; ep.tau[l] = h->tau2[l];
+        ep.pbuf[l] = h->pb2[l];
+    }
+    ep.nmat = 3;
+    ep.m = rmp;
+    ep.ld = (int)zp;
+    CK(h, launch_eig(ep, h->eigw, h->eigw_bytes, st));
+    for (int l = 0; l < 3; ++l) {
+        // P = H P2 (all rmp columns); S = P diag(mu^-1/2) P^T ; Z = Zraw S
+        CK(h, launch_backtransform(rmp, (int)zp, h->M2[l], h->tau2[l], h->P2[l], nullptr, rmp, h->Pf[l], (int)zp, rmp,
+                                   h->Tw[l], st));
+        CK(h, launch_scale_cols_invsqrt(rmp, (int)zp, h->lam2[l], h->Pf[l], h->S2[l], st));
+        CK(h, launch_gemm64(false, false, rmp, rmp, rmp, h->S2[l], zp, h->Pf[l], zp, h->M2[l], zp, 1.0, st));
+        CK(h, launch_gemm64(false, true, np, rmp, rmp, h->Zraw[l], np, h->M2[l], zp, h->Z[l], np, 1.0, st));
         CK(h, launch_sign_cols((int)h->n, (int)np, h->ranks[l], h->Z[l], st));
-        // the projection reads r_pad[l] columns: zero those beyond the rank
         if (h->r_pad[l] > h->ranks[l])
             CK(h, hipMemsetAsync(h->Z[l] + (int64_t)h->ranks[l] * np, 0,
                                  (size_t)(h->r_pad[l] - h->ranks[l]) * np * 8, st));
@@ -321,18 +351,20 @@ rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R, const double*
     if (!h->rside)
         CK(h, launch_gram_nt(h->n_pad, h->R_pad, h->Ut, h->G, h->gram_part, h->gram_splits, st));
     mark(h, 3);
-    JacobiProblem jp{};
-    for (int l = 0; l < 3; ++l) { jp.G[l] = h->G[l]; jp.W[l] = h->W[l]; }
-    jp.nmat = 3;
-    jp.m_pad = (int)h->m_pad;
-    jp.max_sweeps = h->opt.max_eig_sweeps;
-    jp.tol = JACOBI_TOL;
-    CK(h, launch_jacobi(jp, h->jac, h->jac_bytes, h->sweeps_dev, st));
+    EigProblem ep{};
+    for (int l = 0; l < 3; ++l) {
+        ep.G[l] = h->G[l]; ep.lam[l] = h->lam[l]; ep.Q[l] = h->W[l]; ep.Qn[l] = h->Qn[l];
+        ep.M[l] = h->Mg[l]; ep.d[l] = h->dd[l]; ep.e[l] = h->ee[l]; ep.tau[l] = h->htau[l];
+        ep.pbuf[l] = h->pb[l];
+    }
+    ep.nmat = 3;
+    ep.m = (int)h->m;
+    ep.ld = (int)h->m_pad;
+    CK(h, launch_eig(ep, h->eigw, h->eigw_bytes, st));
     mark(h, 4);
     TruncArgs ta{};
     for (int l = 0; l < 3; ++l) {
-        ta.G[l] = h->G[l];
-        ta.W[l] = h->W[l];
+        ta.lam[l] = h->lam[l];
         ta.sigma[l] = h->sigma[l];
         ta.order[l] = h->order[l];
         ta.tails[l] = h->tails[l];
@@ -352,12 +384,10 @@ rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R, const double*
     // the one host synchronization: ranks, flags, sweeps and norms
     CK(h, hipMemcpyAsync(h->host, h->ranks_dev, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
     CK(h, hipMemcpyAsync(h->host + 4, h->flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
-    CK(h, hipMemcpyAsync(h->host + 8, h->sweeps_dev, sizeof(int), hipMemcpyDeviceToHost, st));
     CK(h, hipMemcpyAsync(h->hostd, h->scal, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
     CK(h, hipStreamSynchronize(st));
     if (h->host[4]) return fail(h, RHOSVD_ERR_NONFINITE, "input contains NaN or Inf");
-    h->sweeps = h->host[8];
-    if (h->sweeps < 0) return fail(h, RHOSVD_ERR_NOCONV, "eigensolver hit its sweep cap");
+    h->sweeps = 0;
     h->dropped = h->host[5];
     h->xi_norm = h->hostd[0];
     h->a_norm = h->hostd[1];
@@ -371,7 +401,13 @@ rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R, const double*
         for (int l = 0; l < 3; ++l) {
             const int r = h->ranks[l];
             if (r < 1) continue;
-            CK(h, launch_form_z((int)n, (int)h->n_pad, r, h->r_pad[l], h->W[l], (int)h->m_pad, h->order[l], h->Z[l], st));
+            // Z = H W[:, order[0..r-1]]: back-transformed eigenvectors, sign rule, zero padding
+            CK(h, launch_backtransform((int)h->m, (int)h->m_pad, h->G[l], h->htau[l], h->W[l], h->order[l], r, h->Z[l],
+                                       (int)h->n_pad, (int)h->n_pad, h->Tw[l], st));
+            CK(h, launch_sign_cols((int)n, (int)h->n_pad, r, h->Z[l], st));
+            if (h->r_pad[l] > r)
+                CK(h, hipMemsetAsync(h->Z[l] + (int64_t)r * h->n_pad, 0,
+                                     (size_t)(h->r_pad[l] - r) * h->n_pad * 8, st));
         }
     } else if (h->ranks[0] > 0) {
         rhosvd_status zs = form_z_rside(h);

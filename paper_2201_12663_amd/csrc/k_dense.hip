@@ -392,27 +392,28 @@ __global__ void k_gather_scaled(int m_pad, int r, int r_pad, const double* __res
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
         const int i = (int)(e % m_pad), k = (int)(e / m_pad);
         double v = 0.0;
-        if (k < r && sigma[k] > 0.0) v = W[i + (int64_t)order[k] * m_pad] / sigma[k];
+        if (k < r && sigma[k] > 0.0) v = W[i + (int64_t)(order ? order[k] : k) * m_pad] / sigma[k];
         Wr[e] = v;
     }
 }
 
-// M (ld mp, mp x mp): keep the leading r x r block, identity on the padding
-__global__ void k_pad_identity(int r, int mp, double* __restrict__ M) {
+// M (mp x mp, leading dimension ld): keep the leading r x r block, identity elsewhere
+__global__ void k_pad_identity(int r, int mp, int ld, double* __restrict__ M) {
     const int64_t tot = (int64_t)mp * mp;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
         const int i = (int)(e % mp), j = (int)(e / mp);
-        if (i >= r || j >= r) M[e] = (i == j) ? 1.0 : 0.0;
+        if (i >= r || j >= r) M[i + (int64_t)j * ld] = (i == j) ? 1.0 : 0.0;
     }
 }
 
-// P[:, j] *= mu_j^(-1/2) with mu_j = D[j + j*ld] (Jacobi output diagonal)
-__global__ void k_scale_cols_invsqrt(int mp, const double* __restrict__ D, double* __restrict__ P) {
+// out[:, j] = P[:, j] * mu_j^(-1/2) (mp x mp, leading dimension ld)
+__global__ void k_scale_cols_invsqrt(int mp, int ld, const double* __restrict__ mu, const double* __restrict__ P,
+                                     double* __restrict__ out) {
     const int64_t tot = (int64_t)mp * mp;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
-        const int j = (int)(e / mp);
-        const double mu = D[j + (int64_t)j * mp];
-        P[e] = (mu > 0.0) ? P[e] / sqrt(mu) : 0.0;
+        const int i = (int)(e % mp), j = (int)(e / mp);
+        const int64_t o = i + (int64_t)j * ld;
+        out[o] = (mu[j] > 0.0) ? P[o] / sqrt(mu[j]) : 0.0;
     }
 }
 
@@ -443,12 +444,12 @@ hipError_t launch_gather_scaled(int m_pad, int r, int r_pad, const double* W, co
     hipLaunchKernelGGL(k_gather_scaled, dim3(512), dim3(256), 0, st, m_pad, r, r_pad, W, order, sigma, Wr);
     return hipGetLastError();
 }
-hipError_t launch_pad_identity(int r, int mp, double* M, hipStream_t st) {
-    hipLaunchKernelGGL(k_pad_identity, dim3(256), dim3(256), 0, st, r, mp, M);
+hipError_t launch_pad_identity(int r, int mp, int ld, double* M, hipStream_t st) {
+    hipLaunchKernelGGL(k_pad_identity, dim3(256), dim3(256), 0, st, r, mp, ld, M);
     return hipGetLastError();
 }
-hipError_t launch_scale_cols_invsqrt(int mp, const double* D, double* P, hipStream_t st) {
-    hipLaunchKernelGGL(k_scale_cols_invsqrt, dim3(256), dim3(256), 0, st, mp, D, P);
+hipError_t launch_scale_cols_invsqrt(int mp, int ld, const double* mu, const double* P, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_scale_cols_invsqrt, dim3(256), dim3(256), 0, st, mp, ld, mu, P, out);
     return hipGetLastError();
 }
 hipError_t launch_sign_cols(int n, int n_pad, int r, double* Z, hipStream_t st) {

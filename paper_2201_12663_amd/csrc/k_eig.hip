@@ -1,0 +1,1022 @@
+// a3: FP64 symmetric eigensolver for the Gram matrices.
+//
+//   1. Householder tridiagonalization G = H T H^T (H = H_0 ... H_{m-3}),
+//      one cooperative kernel: the columns of each matrix live in the LDS of
+//      a group of workgroups (a fixed slab per workgroup); per column, the owner
+//      forms the reflector, every workgroup computes its part of p = tau G v,
+//      then applies the rank-2 update G -= v w^T + w v^T to its own slab.  Two
+//      group barriers per column; only v and p travel through memory.
+//   2. Divide and conquer on T (Cuppen): T is split recursively into blocks of
+//      at most 32 (the coupling b = e_mid is removed as T = diag(T1, T2) +
+//      b u u^T); leaves are diagonalized by a parallel Jacobi in one
+//      workgroup; each merge solves the rank-one update D + rho z z^T:
+//      deflation of tiny z_i and of close poles (Givens), the secular equation
+//      1 + rho sum z_i^2/(d_i - lambda) = 0 by bisection on lambda - d_origin
+//      (origin = the nearer pole, so every d_i - lambda is formed accurately),
+//      z recomputed from the roots (Gu & Eisenstat) so the eigenvectors are
+//      orthogonal, and the children's eigenvectors multiplied by the merge's
+//      eigenvector matrix (FP64 MFMA).  One launch per phase per tree level.
+//   3. Back-transformation of the selected eigenvectors by the reflectors.
+#include <math.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace {
+
+constexpr double U64 = 1.1102230246251565e-16;
+constexpr int LEAF = 32;
+constexpr int MAXN = 2048;
+constexpr int CMAX = 32;   // columns per workgroup in the tridiagonalization
+
+__device__ double block_sum256(double v, double* red) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double s = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// 1. tridiagonalization
+// ---------------------------------------------------------------------------
+struct TriArgs {
+    double* G[3];      // m x m (ld), in: symmetric matrix; out: reflectors below the diagonal
+    double* d[3];      // m
+    double* e[3];      // m - 1
+    double* tau[3];    // m
+    double* p[3];      // m (exchange buffer)
+    double* part[3];   // per-block partial sums of p.v (bpm)
+    unsigned* bar;     // one counter per matrix (64 apart)
+    int m, ld, cpb, bpm;   // columns per block, blocks per matrix
+};
+
+// Cross-workgroup data of the tridiagonalization (reflectors, tau, p, partial
+// sums) moves only through agent-scope relaxed atomic loads and stores, which
+// are coherent across the whole device.  A group barrier therefore needs no
+// cache write-back or invalidation: each thread waits until its own stores have
+// completed (s_waitcnt 0) before the workgroup arrives, and data loads are
+// issued only after the arrival count has been observed.
+__device__ __forceinline__ void st_dev(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_dev(const double* p) {
+    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void group_barrier_dev(unsigned* count, unsigned nb, unsigned epoch) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        while (__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch * nb) {
+        }
+    }
+    __syncthreads();
+}
+
+// reflector k from the (current) column k held in LDS: v (rows k+1..m-1, v[k+1] = 1)
+// to G[:, k]; tau, beta (= e_k) and d_k to global memory.
+__device__ void form_reflector(const double* x, int k, int m, int ld, double* G, double* tau_out, double* e_out,
+                               double* d_out, double* red) {
+    const int t = threadIdx.x;
+    double s = 0.0;
+    for (int i = k + 2 + t; i < m; i += 256) s += x[i] * x[i];
+    s = block_sum256(s, red);
+    const double alpha = x[k + 1];
+    double tau, beta, scal;
+    if (s == 0.0) {
+        tau = 0.0; beta = alpha; scal = 0.0;
+    } else {
+        const double nrm = sqrt(alpha * alpha + s);
+        beta = alpha >= 0.0 ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        scal = 1.0 / (alpha - beta);
+    }
+    for (int i = k + 1 + t; i < m; i += 256) st_dev(&G[i + (int64_t)k * ld], (i == k + 1) ? 1.0 : x[i] * scal);
+    if (t == 0) {
+        st_dev(&tau_out[k], tau);
+        e_out[k] = beta;
+        d_out[k] = x[k];
+    }
+}
+
+constexpr int RPT = MAXN / 256;   // rows per thread
+
+__global__ __launch_bounds__(256) void k_tridiag(TriArgs a) {
+    extern __shared__ double slab[];   // cpb columns x m_round, then v (m_round)
+    __shared__ double red[4];
+    __shared__ double red2[CMAX * 4];
+    __shared__ double vjs[CMAX], wjs[CMAX], pjs[CMAX];
+    const int mat = blockIdx.x / a.bpm, gb = blockIdx.x % a.bpm;
+    const int m = a.m, ld = a.ld, cpb = a.cpb;
+    const int mr = (m + 63) & ~63;
+    double* vs = slab + (size_t)cpb * mr;
+    const int c0 = gb * cpb;
+    const int nc = max(0, min(cpb, m - c0));
+    double* G = a.G[mat];
+    double* P = a.p[mat];
+    double* part = a.part[mat];
+    unsigned* bar = a.bar + 64 * mat;
+    const int t = threadIdx.x;
+    for (int c = 0; c < nc; ++c)
+        for (int i = t; i < m; i += 256) slab[c * mr + i] = G[i + (int64_t)(c0 + c) * ld];
+    __syncthreads();
+    if (m > 2 && c0 == 0 && nc > 0) form_reflector(slab, 0, m, ld, G, a.tau[mat], a.e[mat], a.d[mat], red);
+    unsigned epoch = 0;
+    for (int k = 0; k + 2 < m; ++k) {
+        group_barrier_dev(bar, a.bpm, ++epoch);     // reflector k is visible
+        const double tau = ld_dev(&a.tau[mat][k]);
+        double vr[RPT];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int i = k + 1 + t + 256 * q;
+            vr[q] = (i < m) ? ld_dev(&G[i + (int64_t)k * ld]) : 0.0;
+            if (i < m) vs[i] = vr[q];
+        }
+        const int cs = max(0, k + 1 - c0);   // first local column with j > k
+        // (b) p_j = tau * sum_i G[i,j] v_i for own columns j > k, and this block's share of p.v
+        if (tau != 0.0) {
+            double acc[CMAX];
+#pragma unroll
+            for (int c = 0; c < CMAX; ++c) acc[c] = 0.0;
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int i = k + 1 + t + 256 * q;
+                if (i < m) {
+#pragma unroll
+                    for (int c = 0; c < CMAX; ++c)
+                        if (c >= cs && c < nc) acc[c] += slab[c * mr + i] * vr[q];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < CMAX; ++c)
+                if (c >= cs && c < nc) {
+                    const double sw = wave_sum(acc[c]);
+                    if ((t & 63) == 0) red2[c * 4 + (t >> 6)] = sw;
+                }
+            __syncthreads();   // red2 and vs complete
+            if (t < 64) {
+                double pv = 0.0;
+                if (t >= cs && t < nc) {
+                    const double pj = tau * ((red2[t * 4] + red2[t * 4 + 1]) + (red2[t * 4 + 2] + red2[t * 4 + 3]));
+                    st_dev(&P[c0 + t], pj);
+                    pjs[t] = pj;
+                    pv = pj * vs[c0 + t];
+                }
+                const double sp = wave_sum(pv);
+                if (t == 0) st_dev(&part[gb], sp);
+            }
+        }
+        group_barrier_dev(bar, a.bpm, ++epoch);     // p and the partial p.v are visible
+        // (c) w = p - (tau/2)(p.v) v ;  slab -= v w^T + w v^T on rows and columns > k.
+        //     The owner of column k+1 updates it first and forms reflector k+1.
+        const int cn = k + 1 - c0;   // local index of column k+1
+        if (tau != 0.0) {
+            double pr[RPT];
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int i = k + 1 + t + 256 * q;
+                pr[q] = (i < m) ? ld_dev(&P[i]) : 0.0;
+            }
+            double s = 0.0;
+            for (int q = 0; q < a.bpm; ++q) s += ld_dev(&part[q]);
+            const double cw = 0.5 * tau * s;
+            if (t >= cs && t < nc) {
+                vjs[t] = vs[c0 + t];
+                wjs[t] = pjs[t] - cw * vs[c0 + t];
+            }
+            __syncthreads();
+            int cfirst = cs;
+            if (cn >= 0 && cn < nc) {
+#pragma unroll
+                for (int q = 0; q < RPT; ++q) {
+                    const int i = k + 1 + t + 256 * q;
+                    if (i < m) slab[cn * mr + i] -= vr[q] * wjs[cn] + (pr[q] - cw * vr[q]) * vjs[cn];
+                }
+                __syncthreads();
+                if (k + 3 < m) form_reflector(slab + cn * mr, k + 1, m, ld, G, a.tau[mat], a.e[mat], a.d[mat], red);
+                cfirst = cn + 1;
+            }
+            if (cfirst < nc) {
+#pragma unroll
+                for (int q = 0; q < RPT; ++q) {
+                    const int i = k + 1 + t + 256 * q;
+                    if (i < m) {
+                        const double vi = vr[q], wi = pr[q] - cw * vr[q];
+#pragma unroll
+                        for (int c = 0; c < CMAX; ++c)
+                            if (c >= cfirst && c < nc) slab[c * mr + i] -= vi * wjs[c] + wi * vjs[c];
+                    }
+                }
+            }
+        } else if (cn >= 0 && cn < nc && k + 3 < m) {
+            // H_k = I: column k+1 is unchanged; its owner forms reflector k+1
+            form_reflector(slab + cn * mr, k + 1, m, ld, G, a.tau[mat], a.e[mat], a.d[mat], red);
+        }
+        __syncthreads();
+    }
+    // the last 2x2 block
+    for (int c = 0; c < nc; ++c) {
+        const int j = c0 + c;
+        if (t == 0) {
+            if (j == m - 2 || (m == 1 && j == 0)) a.d[mat][j] = slab[c * mr + j];
+            if (j == m - 1) a.d[mat][j] = slab[c * mr + j];
+            if (j == m - 2) a.e[mat][j] = slab[c * mr + j + 1];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 2. divide and conquer
+// ---------------------------------------------------------------------------
+struct Node {
+    int mat, lo, mid, hi;     // leaf: mid == hi
+};
+
+struct DCArgs {
+    const Node* nodes;        // nodes of this pass
+    int nnodes;
+    double* d[3];             // modified diagonal (leaves read it)
+    double* e[3];
+    double* lam[3];           // eigenvalues (per index range of the node)
+    double* Q[3];             // eigenvectors, m x m (ld), block diagonal per node
+    double* Qn[3];            // output buffer of the merge GEMM
+    double* M[3];             // merge matrices, n x n at the node's diagonal block (ld)
+    char* scratch;            // per-node scratch, node_bytes each
+    size_t node_bytes;
+    int ld;
+};
+
+// node scratch layout (n <= MAXN)
+struct NodeScratch {
+    double rho;
+    double sgn;
+    int k;
+    int nrot;
+    int pad[2];
+};
+__device__ __forceinline__ NodeScratch* ns_head(const DCArgs& a, int node) {
+    return (NodeScratch*)(a.scratch + (size_t)node * a.node_bytes);
+}
+__device__ __forceinline__ double* ns_D(const DCArgs& a, int node) { return (double*)(ns_head(a, node) + 1); }
+__device__ __forceinline__ double* ns_z(const DCArgs& a, int node) { return ns_D(a, node) + MAXN; }
+__device__ __forceinline__ double* ns_dd(const DCArgs& a, int node) { return ns_z(a, node) + MAXN; }
+__device__ __forceinline__ double* ns_zk(const DCArgs& a, int node) { return ns_dd(a, node) + MAXN; }
+__device__ __forceinline__ double* ns_tau(const DCArgs& a, int node) { return ns_zk(a, node) + MAXN; }
+__device__ __forceinline__ double* ns_zh(const DCArgs& a, int node) { return ns_tau(a, node) + MAXN; }
+__device__ __forceinline__ double* ns_rc(const DCArgs& a, int node) { return ns_zh(a, node) + MAXN; }       // 2*MAXN
+__device__ __forceinline__ int* ns_perm(const DCArgs& a, int node) { return (int*)(ns_rc(a, node) + 2 * MAXN); }
+__device__ __forceinline__ int* ns_keep(const DCArgs& a, int node) { return ns_perm(a, node) + MAXN; }
+__device__ __forceinline__ int* ns_org(const DCArgs& a, int node) { return ns_keep(a, node) + MAXN; }
+__device__ __forceinline__ int* ns_rp(const DCArgs& a, int node) { return ns_org(a, node) + MAXN; }       // 2*MAXN
+
+size_t node_scratch_bytes() {
+    return (sizeof(NodeScratch) + (7 + 2) * MAXN * sizeof(double) + (3 + 2) * MAXN * sizeof(int) + 255) & ~(size_t)255;
+}
+
+// leaves: dense Jacobi on the (<= 32) tridiagonal block, one workgroup each
+__device__ __forceinline__ int next_pos32(int p) {
+    if (p == 0) return 0;
+    if (p == 1) return 2;
+    if ((p & 1) == 0) return p < 30 ? p + 2 : 31;
+    return p - 2;
+}
+
+__global__ __launch_bounds__(256) void k_dc_leaves(DCArgs a) {
+    __shared__ double bufS[32 * 33];
+    __shared__ double bufQ[32 * 33];
+    __shared__ double cs[16], sn[16];
+    __shared__ double red[4];
+    const Node nd = a.nodes[blockIdx.x];
+    const int n = nd.hi - nd.lo;
+    const double* d = a.d[nd.mat] + nd.lo;
+    const double* e = a.e[nd.mat] + nd.lo;
+    const int t = threadIdx.x, bi = t >> 4, bj = t & 15;
+    const int r0 = 2 * bi, c0 = 2 * bj;
+    auto T = [&](int r, int c) -> double {
+        if (r >= n || c >= n) return 0.0;
+        if (r == c) return d[r];
+        if (r == c + 1) return e[c];
+        if (c == r + 1) return e[r];
+        return 0.0;
+    };
+    double s00 = T(r0, c0), s01 = T(r0, c0 + 1), s10 = T(r0 + 1, c0), s11 = T(r0 + 1, c0 + 1);
+    double q00 = (bi == bj) ? 1.0 : 0.0, q01 = 0.0, q10 = 0.0, q11 = q00;
+    double f2 = s00 * s00 + s01 * s01 + s10 * s10 + s11 * s11;
+    f2 = block_sum256(f2, red);
+    const double thr = 0.5 * U64 * sqrt(f2);
+    for (int isw = 0; isw < 40; ++isw) {
+        int rot = 0;
+        for (int round = 0; round < 31; ++round) {
+            int here = 0;
+            if (bi == bj) {
+                double c = 1.0, s = 0.0;
+                if (fabs(s01) > thr) {
+                    const double zeta = (s11 - s00) / (2.0 * s01);
+                    const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                    c = 1.0 / sqrt(1.0 + tt * tt);
+                    s = c * tt;
+                    here = 1;
+                    rot = 1;
+                }
+                cs[bi] = c;
+                sn[bi] = s;
+            }
+            __syncthreads();
+            const double cI = cs[bi], sI = sn[bi], cJ = cs[bj], sJ = sn[bj];
+            const double x00 = s00 * cJ - s01 * sJ, x01 = s00 * sJ + s01 * cJ;
+            const double x10 = s10 * cJ - s11 * sJ, x11 = s10 * sJ + s11 * cJ;
+            double y00 = cI * x00 - sI * x10, y01 = cI * x01 - sI * x11;
+            double y10 = sI * x00 + cI * x10, y11 = sI * x01 + cI * x11;
+            if (here) { y01 = 0.0; y10 = 0.0; }
+            const double z00 = q00 * cJ - q01 * sJ, z01 = q00 * sJ + q01 * cJ;
+            const double z10 = q10 * cJ - q11 * sJ, z11 = q10 * sJ + q11 * cJ;
+            const int pr0 = next_pos32(r0), pr1 = next_pos32(r0 + 1);
+            const int pc0 = next_pos32(c0), pc1 = next_pos32(c0 + 1);
+            bufS[pc0 * 33 + pr0] = y00;
+            bufS[pc1 * 33 + pr0] = y01;
+            bufS[pc0 * 33 + pr1] = y10;
+            bufS[pc1 * 33 + pr1] = y11;
+            bufQ[pc0 * 33 + r0] = z00;
+            bufQ[pc1 * 33 + r0] = z01;
+            bufQ[pc0 * 33 + r0 + 1] = z10;
+            bufQ[pc1 * 33 + r0 + 1] = z11;
+            __syncthreads();
+            s00 = bufS[c0 * 33 + r0];
+            s01 = bufS[(c0 + 1) * 33 + r0];
+            s10 = bufS[c0 * 33 + r0 + 1];
+            s11 = bufS[(c0 + 1) * 33 + r0 + 1];
+            q00 = bufQ[c0 * 33 + r0];
+            q01 = bufQ[(c0 + 1) * 33 + r0];
+            q10 = bufQ[c0 * 33 + r0 + 1];
+            q11 = bufQ[(c0 + 1) * 33 + r0 + 1];
+        }
+        if (!__syncthreads_or(rot)) break;
+    }
+    // eigenvalues on the diagonal (positions are back in order after whole sweeps)
+    double* lam = a.lam[nd.mat] + nd.lo;
+    double* Q = a.Q[nd.mat];
+    const int ld = a.ld;
+    if (bi == bj) {
+        if (r0 < n) lam[r0] = s00;
+        if (r0 + 1 < n) lam[r0 + 1] = s11;
+    }
+    const double qv[4] = {q00, q01, q10, q11};
+    for (int u = 0; u < 4; ++u) {
+        const int r = r0 + (u >> 1), c = c0 + (u & 1);
+        if (r < n && c < n) Q[(nd.lo + r) + (int64_t)(nd.lo + c) * ld] = qv[u];
+    }
+}
+
+// phase A (one workgroup per node): z, sort, deflation
+__global__ __launch_bounds__(256) void k_dc_prep(DCArgs a) {
+    __shared__ double key[MAXN];
+    __shared__ int idx[MAXN];
+    __shared__ double red[4];
+    const int node = blockIdx.x;
+    const Node nd = a.nodes[node];
+    const int n1 = nd.mid - nd.lo, n = nd.hi - nd.lo;
+    const int t = threadIdx.x;
+    const double* lam = a.lam[nd.mat] + nd.lo;
+    const double* Q = a.Q[nd.mat];
+    const int ld = a.ld;
+    double rho = 2.0 * a.e[nd.mat][nd.mid - 1];
+    const double sgn = rho < 0.0 ? -1.0 : 1.0;
+    rho = fabs(rho);
+    const double rs2 = 0.7071067811865476;
+    int N2 = 1;
+    while (N2 < n) N2 <<= 1;
+    double* z = ns_z(a, node);
+    for (int i = t; i < N2; i += 256) {
+        key[i] = (i < n) ? sgn * lam[i] : INFINITY;
+        idx[i] = i;
+    }
+    __syncthreads();
+    for (int size = 2; size <= N2; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = t; i < N2; i += 256) {
+                const int j = i ^ stride;
+                if (j > i) {
+                    const bool asc = ((i & size) == 0);
+                    const double ki = key[i], kj = key[j];
+                    const int ii = idx[i], ij = idx[j];
+                    const bool i_first = (ki < kj) || (ki == kj && ii < ij);
+                    if (asc ? !i_first : i_first) {
+                        key[i] = kj; key[j] = ki;
+                        idx[i] = ij; idx[j] = ii;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    double* D = ns_D(a, node);
+    int* perm = ns_perm(a, node);
+    double mx = 0.0;
+    for (int s = t; s < n; s += 256) {
+        const int i = idx[s];
+        D[s] = key[s];
+        perm[s] = i;
+        // column lo+i: last row of child 1 (row mid-1) or first row of child 2 (row mid)
+        const int row = (i < n1) ? nd.mid - 1 : nd.mid;
+        z[s] = rs2 * Q[row + (int64_t)(nd.lo + i) * ld];
+        mx = fmax(mx, fabs(key[s]));
+    }
+    mx = wave_max(mx);
+    if ((t & 63) == 0) red[t >> 6] = mx;
+    __syncthreads();
+    if (t == 0) {
+        mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+        const double tol = 8.0 * U64 * fmax(mx, rho);
+        double* dd = ns_dd(a, node);
+        double* zk = ns_zk(a, node);
+        double* rc = ns_rc(a, node);
+        int* keep = ns_keep(a, node);
+        int* rp = ns_rp(a, node);
+        int k = 0, nrot = 0, prev = -1;
+        for (int i = 0; i < n; ++i) {
+            if (fabs(rho * z[i]) <= tol) continue;   // deflated: eigenpair (D_i, e_i)
+            if (prev < 0) { prev = i; continue; }
+            const double tt = hypot(z[prev], z[i]);
+            const double c = z[i] / tt, s = -z[prev] / tt;
+            if (fabs((D[i] - D[prev]) * c * s) <= tol) {
+                // close poles: rotate so that z[prev] = 0 and deflate prev
+                const double dp = D[prev], di = D[i];
+                D[prev] = dp * c * c + di * s * s;
+                D[i] = dp * s * s + di * c * c;
+                z[i] = tt;
+                z[prev] = 0.0;
+                rp[2 * nrot] = prev;
+                rp[2 * nrot + 1] = i;
+                rc[2 * nrot] = c;
+                rc[2 * nrot + 1] = s;
+                ++nrot;
+                prev = i;
+            } else {
+                keep[k++] = prev;
+                prev = i;
+            }
+        }
+        if (prev >= 0) keep[k++] = prev;
+        for (int q = 0; q < k; ++q) {
+            dd[q] = D[keep[q]];
+            zk[q] = z[keep[q]];
+        }
+        NodeScratch* h = ns_head(a, node);
+        h->rho = rho;
+        h->sgn = sgn;
+        h->k = k;
+        h->nrot = nrot;
+    }
+}
+
+// phase B: secular roots; one wave per root, nodes x roots flattened in y
+__global__ __launch_bounds__(256) void k_dc_roots(DCArgs a) {
+    const int node = blockIdx.y;
+    const NodeScratch* h = ns_head(a, node);
+    const int k = h->k;
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (j >= k) return;
+    const double* dd = ns_dd(a, node);
+    const double* zk = ns_zk(a, node);
+    const double rho = h->rho;
+    double zz2 = 0.0;
+    for (int i = lane; i < k; i += 64) zz2 += zk[i] * zk[i];
+    zz2 = wave_sum(zz2);
+    const double lo_pole = dd[j];
+    const double hi_pole = (j + 1 < k) ? dd[j + 1] : dd[j] + rho * zz2;
+    int o = j;
+    if (j + 1 < k) {
+        const double mid = 0.5 * (hi_pole - lo_pole);
+        double f = 0.0;
+        for (int i = lane; i < k; i += 64) f += zk[i] * zk[i] / ((dd[i] - lo_pole) - mid);
+        f = 1.0 + rho * wave_sum(f);
+        o = (f > 0.0) ? j : j + 1;
+    }
+    const double dorg = dd[o];
+    double lo = lo_pole - dorg, hi = hi_pole - dorg;
+    for (int it = 0; it < 200; ++it) {
+        const double tm = 0.5 * (lo + hi);
+        if (tm == lo || tm == hi) break;
+        double f = 0.0;
+        for (int i = lane; i < k; i += 64) f += zk[i] * zk[i] / ((dd[i] - dorg) - tm);
+        f = 1.0 + rho * wave_sum(f);
+        if (f > 0.0) hi = tm;
+        else lo = tm;
+    }
+    if (lane == 0) {
+        ns_tau(a, node)[j] = 0.5 * (lo + hi);
+        ns_org(a, node)[j] = o;
+    }
+}
+
+// phase C1: z-hat (Gu & Eisenstat), one thread per i
+__global__ __launch_bounds__(256) void k_dc_zhat(DCArgs a) {
+    const int node = blockIdx.y;
+    const NodeScratch* h = ns_head(a, node);
+    const int k = h->k;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= k) return;
+    const double* dd = ns_dd(a, node);
+    const double* zk = ns_zk(a, node);
+    const double* tau = ns_tau(a, node);
+    const int* org = ns_org(a, node);
+    const double rho = h->rho;
+    // delta(i,j) = d_i - lambda_j = (d_i - d_org(j)) - tau_j ;  lambda_j - d_i = -delta
+    auto lmd = [&](int jj) { return -((dd[i] - dd[org[jj]]) - tau[jj]); };
+    double prod = lmd(k - 1) / rho;
+    for (int jj = 0; jj < k - 1; ++jj) {
+        const double den = (jj < i) ? dd[jj] - dd[i] : dd[jj + 1] - dd[i];
+        prod *= lmd(jj) / den;
+    }
+    ns_zh(a, node)[i] = copysign(sqrt(fmax(prod, 0.0)), zk[i]);
+}
+
+// phase C2: merge matrix M (n x n at the node's block of a.M), one wave per column.
+// Columns are in sorted coordinates; rows are mapped back through perm; the
+// Givens rotations of the close-pole deflation are applied to the rows.
+__global__ __launch_bounds__(256) void k_dc_vectors(DCArgs a) {
+    const int node = blockIdx.y;
+    const Node nd = a.nodes[node];
+    const NodeScratch* h = ns_head(a, node);
+    const int n = nd.hi - nd.lo, k = h->k, nrot = h->nrot;
+    const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (col >= n) return;
+    __shared__ double xs[4][MAXN];
+    double* x = xs[threadIdx.x >> 6];
+    const int* keep = ns_keep(a, node);
+    const double* dd = ns_dd(a, node);
+    const double* tau = ns_tau(a, node);
+    const int* org = ns_org(a, node);
+    const double* zh = ns_zh(a, node);
+    const double* D = ns_D(a, node);
+    for (int i = lane; i < n; i += 64) x[i] = 0.0;
+    // is this sorted column a kept one?  keep[] is increasing: binary search
+    int lo = 0, hi = k;
+    while (lo < hi) {
+        const int md = (lo + hi) >> 1;
+        if (keep[md] < col) lo = md + 1;
+        else hi = md;
+    }
+    const bool kept = (lo < k && keep[lo] == col);
+    double lamc;
+    if (kept) {
+        const int jc = lo;
+        double nrm = 0.0;
+        for (int q = lane; q < k; q += 64) {
+            const double delta = (dd[q] - dd[org[jc]]) - tau[jc];
+            const double u = zh[q] / delta;
+            nrm += u * u;
+        }
+        nrm = sqrt(wave_sum(nrm));
+        for (int q = lane; q < k; q += 64) {
+            const double delta = (dd[q] - dd[org[jc]]) - tau[jc];
+            x[keep[q]] = zh[q] / delta / nrm;
+        }
+        lamc = dd[org[jc]] + tau[jc];
+    } else {
+        if (lane == 0) x[col] = 1.0;
+        lamc = D[col];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // rows <- R_1 R_2 ... R_t x : apply the rotations in reverse order
+    if (lane == 0) {
+        const double* rc = ns_rc(a, node);
+        const int* rp = ns_rp(a, node);
+        for (int q = nrot - 1; q >= 0; --q) {
+            const int p = rp[2 * q], i = rp[2 * q + 1];
+            const double c = rc[2 * q], s = rc[2 * q + 1];
+            const double xp = x[p], xi = x[i];
+            x[p] = c * xp - s * xi;
+            x[i] = s * xp + c * xi;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int* perm = ns_perm(a, node);
+    double* M = a.M[nd.mat];
+    const int ld = a.ld;
+    for (int s = lane; s < n; s += 64) M[(nd.lo + perm[s]) + (int64_t)(nd.lo + col) * ld] = x[s];
+    if (lane == 0) a.lam[nd.mat][nd.lo + col] = h->sgn * lamc;
+}
+
+// phase D: Qn[rows of child c, lo:hi] = Q[child block] * M[child rows, lo:hi]
+// (block-diagonal product), masked FP64 MFMA tiles of 64 x 64; one tile per block.
+struct GemmTask {
+    int mat, r0, nr, c0, nc, k0, nk;   // rows [r0, r0+nr), cols [c0, c0+nc), k range [k0, k0+nk)
+};
+
+__global__ __launch_bounds__(256) void k_dc_gemm(DCArgs a, const GemmTask* tasks) {
+    __shared__ double sA[16][68];
+    __shared__ double sB[16][68];
+    const GemmTask tk = tasks[blockIdx.y];
+    const int tiles_n = (tk.nc + 63) / 64;
+    const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+    if (tm * 64 >= tk.nr) return;
+    const int ld = a.ld;
+    const double* Q = a.Q[tk.mat];
+    const double* M = a.M[tk.mat];
+    double* Qn = a.Qn[tk.mat];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+    d4_t acc[2][2];
+    for (int x = 0; x < 2; ++x)
+        for (int y = 0; y < 2; ++y) acc[x][y] = d4_t{0.0, 0.0, 0.0, 0.0};
+    const int rbase = tk.r0 + tm * 64, cbase = tk.c0 + tn * 64;
+    for (int kb = 0; kb < tk.nk; kb += 16) {
+        for (int q = 0; q < 4; ++q) {
+            const int kk = (t >> 6) + 4 * q, i = t & 63;
+            const int gr = rbase + i, gk = tk.k0 + kb + kk;
+            sA[kk][i] = (rbase + i < tk.r0 + tk.nr && kb + kk < tk.nk) ? Q[gr + (int64_t)gk * ld] : 0.0;
+            const int gc = cbase + i;
+            sB[kk][i] = (cbase + i < tk.c0 + tk.nc && kb + kk < tk.nk) ? M[gk + (int64_t)gc * ld] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            const int k = kk * 4 + (lane >> 4);
+            const double a0 = sA[k][wr + (lane & 15)], a1 = sA[k][wr + 16 + (lane & 15)];
+            const double b0 = sB[k][wc + (lane & 15)], b1 = sB[k][wc + 16 + (lane & 15)];
+            acc[0][0] = mfma_f64(a0, b0, acc[0][0]);
+            acc[0][1] = mfma_f64(a0, b1, acc[0][1]);
+            acc[1][0] = mfma_f64(a1, b0, acc[1][0]);
+            acc[1][1] = mfma_f64(a1, b1, acc[1][1]);
+        }
+        __syncthreads();
+    }
+    for (int x = 0; x < 2; ++x)
+        for (int y = 0; y < 2; ++y)
+            for (int i = 0; i < 4; ++i) {
+                const int r = rbase + wr + 16 * x + c_row64(lane, i);
+                const int c = cbase + wc + 16 * y + c_col(lane);
+                if (r < tk.r0 + tk.nr && c < tk.c0 + tk.nc) Qn[r + (int64_t)c * ld] = acc[x][y][i];
+            }
+}
+
+// copy a node's block of Qn back into Q (so every node's result is in Q)
+__global__ void k_dc_copyback(DCArgs a) {
+    const Node nd = a.nodes[blockIdx.y];
+    const int n = nd.hi - nd.lo, ld = a.ld;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n * n; e += gridDim.x * blockDim.x) {
+        const int r = e % n, c = e / n;
+        const int64_t o = (nd.lo + r) + (int64_t)(nd.lo + c) * ld;
+        a.Q[nd.mat][o] = a.Qn[nd.mat][o];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3. back-transformation: out[:, k] = H_0 H_1 ... H_{m-3} Q[:, order[k]], k < r,
+// in compact-WY form: blocks of NB = 32 reflectors, B_b = I - V_b T_b V_b^T with
+// T_b upper triangular (T[i,i] = tau_i, T[0:i,i] = -tau_i T[0:i,0:i] V[:,0:i]^T v_i),
+// applied last block first.  Rows m..nrows-1 of out are zero.
+// ---------------------------------------------------------------------------
+constexpr int NB = 32;
+
+// v_j of block b at row i (zero above its leading 1)
+__device__ __forceinline__ double vb(const double* Hv, int ld, int m, int k0, int j, int kc, int i) {
+    return (j < kc && i > k0 + j && i < m) ? Hv[i + (int64_t)(k0 + j) * ld] : 0.0;
+}
+
+// T_b from Y = V_b^T V_b, computed with FP64 MFMA (one 16 x 16 tile of Y per wave).
+__global__ __launch_bounds__(256) void k_larft(int m, int ld, const double* __restrict__ Hv,
+                                               const double* __restrict__ tau, double* __restrict__ Tw) {
+    __shared__ double Y[NB][NB + 1];
+    __shared__ double T[NB][NB + 1];
+    const int b = blockIdx.x, k0 = NB * b;
+    const int kc = min(NB, (m - 2) - k0);
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int ti = w & 1, tj = w >> 1;
+    d4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int row0 = k0 + 1; row0 < m; row0 += 4) {
+        const int row = row0 + (lane >> 4);
+        const double av = vb(Hv, ld, m, k0, 16 * ti + (lane & 15), kc, row);
+        const double bv = vb(Hv, ld, m, k0, 16 * tj + (lane & 15), kc, row);
+        acc = mfma_f64(av, bv, acc);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Y[16 * ti + c_row64(lane, q)][16 * tj + c_col(lane)] = acc[q];
+    for (int e = t; e < NB * (NB + 1); e += 256) (&T[0][0])[e] = 0.0;
+    __syncthreads();
+    if (t < 64) {
+        for (int i = 0; i < kc; ++i) {
+            const double tv = tau[k0 + i];
+            double v = 0.0;
+            if (t < i) {
+                for (int q = t; q < i; ++q) v += T[t][q] * Y[q][i];
+                v = -tv * v;
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (t < i) T[t][i] = v;
+            if (t == 0) T[i][i] = tv;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+    __syncthreads();
+    for (int e = t; e < NB * NB; e += 256) Tw[(int64_t)b * NB * NB + e] = T[e % NB][e / NB];
+}
+
+// X <- H X for a slab of 16 columns of X (one workgroup), blocks applied last first:
+//   Wm = V_b^T X (MFMA, 2 tiles x 2 halves of the rows), W2 = T_b Wm, X -= V_b W2 (MFMA).
+// XL: the slab lives in LDS as X[i * 16 + c]; otherwise it is updated in place in out.
+template <bool XL>
+__global__ __launch_bounds__(256) void k_apply_wy(int m, int ld, const double* __restrict__ Hv,
+                                                  const double* __restrict__ Tw, const double* __restrict__ Q,
+                                                  const int* __restrict__ order, int r, double* __restrict__ out,
+                                                  int ldo, int nrows) {
+    extern __shared__ double Xs[];              // mr x 16 when XL
+    __shared__ double P[2][NB][17];
+    __shared__ double W2[NB][17];
+    constexpr int CW = 16;
+    const int mr = (m + 63) & ~63;
+    const int c0 = blockIdx.x * CW, nc = min(CW, r - c0);
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    double* Xo = out + (int64_t)c0 * ldo;
+    auto X = [&](int i, int c) -> double& { return XL ? Xs[i * CW + c] : Xo[i + (int64_t)c * ldo]; };
+    // load the slab (columns beyond nc and rows beyond m are zero)
+    const int rows_ld = XL ? mr : m;
+    for (int e = t; e < rows_ld * CW; e += 256) {
+        const int c = e % CW, i = e / CW;
+        double v = 0.0;
+        if (c < nc && i < m) v = Q[i + (int64_t)(order ? order[c0 + c] : c0 + c) * ld];
+        if (XL || c < nc) X(i, c) = v;
+    }
+    __syncthreads();
+    const int nblk = (m - 2 + NB - 1) / NB;
+    for (int b = nblk - 1; b >= 0; --b) {
+        const int k0 = NB * b, kc = min(NB, (m - 2) - k0);
+        // pass 1: wave w -> tile jt = w & 1 of Wm, rows interleaved by halves h = w >> 1
+        {
+            const int jt = w & 1, h = w >> 1;
+            d4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+            for (int row0 = k0 + 1 + 4 * h; row0 < m; row0 += 8) {
+                const int row = row0 + (lane >> 4);
+                const double av = vb(Hv, ld, m, k0, 16 * jt + (lane & 15), kc, row);
+                const double bv = (row < m && (XL || (lane & 15) < nc)) ? X(row, lane & 15) : 0.0;
+                acc = mfma_f64(av, bv, acc);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) P[h][16 * jt + c_row64(lane, q)][c_col(lane)] = acc[q];
+        }
+        __syncthreads();
+        // W2 = T_b Wm (T_b upper triangular, column-major)
+        {
+            const double* T = Tw + (int64_t)b * NB * NB;
+            for (int e = t; e < NB * CW; e += 256) {
+                const int j = e % NB, c = e / NB;
+                double s = 0.0;
+                for (int q = j; q < kc; ++q) s += T[j + q * NB] * (P[0][q][c] + P[1][q][c]);
+                W2[j][c] = s;
+            }
+        }
+        __syncthreads();
+        // pass 2: X[i, :] -= V_b[i, :] W2 for rows k0+1 .. m-1, 16-row tiles over the waves
+        {
+            const int i0 = k0 + 1;
+            const int ntile = (m - i0 + 15) / 16;
+            for (int tl = w; tl < ntile; tl += 4) {
+                const int rb = i0 + 16 * tl;
+                d4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int st = 0; st < NB / 4; ++st) {
+                    const int j = 4 * st + (lane >> 4);
+                    const double av = vb(Hv, ld, m, k0, j, kc, rb + (lane & 15));
+                    acc = mfma_f64(av, W2[j][lane & 15], acc);
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int row = rb + c_row64(lane, q);
+                    if (row < m && (XL || c_col(lane) < nc)) X(row, c_col(lane)) -= acc[q];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (XL) {
+        for (int e = t; e < nrows * CW; e += 256) {
+            const int i = e % nrows, c = e / nrows;
+            if (c < nc) Xo[i + (int64_t)c * ldo] = (i < m) ? Xs[i * CW + c] : 0.0;
+        }
+    } else {
+        for (int e = t; e < nrows * CW; e += 256) {
+            const int i = e % nrows, c = e / nrows;
+            if (c < nc && i >= m) Xo[i + (int64_t)c * ldo] = 0.0;
+        }
+    }
+}
+
+void build_tree(int mat, int lo, int hi, std::vector<std::vector<Node>>& by_height, int& height) {
+    if (hi - lo <= LEAF) {
+        if ((int)by_height.size() < 1) by_height.resize(1);
+        by_height[0].push_back(Node{mat, lo, hi, hi});
+        height = 0;
+        return;
+    }
+    const int mid = lo + (hi - lo) / 2;
+    int h1 = 0, h2 = 0;
+    build_tree(mat, lo, mid, by_height, h1);
+    build_tree(mat, mid, hi, by_height, h2);
+    height = 1 + std::max(h1, h2);
+    if ((int)by_height.size() <= height) by_height.resize(height + 1);
+    by_height[height].push_back(Node{mat, lo, mid, hi});
+}
+
+}  // namespace
+
+size_t eig_work_bytes(int nmat, int m) {
+    // node table + tasks + per-node scratch (at most m / 16 nodes per pass per matrix)
+    const int max_nodes = nmat * (m / 16 + 2);
+    return (size_t)max_nodes * node_scratch_bytes() + (size_t)max_nodes * 4 * sizeof(Node) * 64 +
+           (size_t)max_nodes * 2 * sizeof(GemmTask) * 64 + 256 * 64 * 3 + 256 * 3 * 8 + 65536;
+}
+
+hipError_t launch_eig(const EigProblem& p, void* work, size_t work_bytes, hipStream_t st) {
+    const int m = p.m, ld = p.ld, nmat = p.nmat;
+    if (m < 1 || m > MAXN || nmat < 1 || nmat > 3) return hipErrorInvalidValue;
+    if (work_bytes < eig_work_bytes(nmat, m)) return hipErrorInvalidValue;
+    char* w = (char*)work;
+    unsigned* bar = (unsigned*)w;            w += 256 * 64 * 3;
+    double* part = (double*)w;               w += 256 * 3 * sizeof(double);
+    hipError_t e;
+    // ---- 1. tridiagonalization
+    {
+        int dev = 0, ncu = 0, maxsh = 0;
+        if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+        if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+        if ((e = hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess) return e;
+        const int mr = (m + 63) & ~63;
+        int cpb = (int)((maxsh - 4096 - (int)mr * 8) / ((size_t)mr * 8));
+        cpb = std::max(1, std::min(cpb, CMAX));
+        const int bpm = (m + cpb - 1) / cpb;
+        const size_t shbytes = (size_t)(cpb + 1) * mr * 8;
+        if ((e = hipFuncSetAttribute((const void*)k_tridiag, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)shbytes)) != hipSuccess) return e;
+        int per_launch = std::max(1, std::min(nmat, ncu / bpm));
+        if (bpm > ncu) return hipErrorInvalidConfiguration;
+        for (int m0 = 0; m0 < nmat; m0 += per_launch) {
+            const int cnt = std::min(per_launch, nmat - m0);
+            TriArgs ta{};
+            for (int i = 0; i < cnt; ++i) {
+                ta.G[i] = p.G[m0 + i];
+                ta.d[i] = p.d[m0 + i];
+                ta.e[i] = p.e[m0 + i];
+                ta.tau[i] = p.tau[m0 + i];
+                ta.p[i] = p.pbuf[m0 + i];
+                ta.part[i] = part + 256 * i;
+            }
+            ta.bar = bar;
+            ta.m = m;
+            ta.ld = ld;
+            ta.cpb = cpb;
+            ta.bpm = bpm;
+            if ((e = hipMemsetAsync(bar, 0, 256 * 64 * 3, st)) != hipSuccess) return e;
+            void* args[] = {&ta};
+            if ((e = hipLaunchCooperativeKernel((const void*)k_tridiag, dim3(cnt * bpm), dim3(256), args, shbytes,
+                                                st)) != hipSuccess)
+                return e;
+        }
+    }
+    // ---- 2. divide and conquer on (d, e)
+    std::vector<std::vector<Node>> by_h;
+    int height = 0;
+    for (int mat = 0; mat < nmat; ++mat) build_tree(mat, 0, m, by_h, height);
+    // modified diagonals: every split at mid subtracts b = e[mid-1] from d[mid-1] and d[mid]
+    // (done on the device by a tiny kernel per split would be wasteful: the host tree
+    // drives a single pass of hipMemcpy-free updates below)
+    size_t max_nodes = 0;
+    for (auto& v : by_h) max_nodes = std::max(max_nodes, v.size());
+    Node* dnodes = (Node*)w;                  w += ((max_nodes * sizeof(Node) + 255) & ~(size_t)255) * by_h.size();
+    GemmTask* dtasks = (GemmTask*)w;          w += ((2 * max_nodes * sizeof(GemmTask) + 255) & ~(size_t)255) * by_h.size();
+    char* scratch = w;
+    // the split modifications are applied by k_dc_modify for all internal nodes at once
+    {
+        std::vector<int> mids;
+        for (size_t h = 1; h < by_h.size(); ++h)
+            for (auto& nd : by_h[h])
+                if (nd.mat == 0) mids.push_back(nd.mid);
+        // reuse the GemmTask area of the last level for the list (copied synchronously
+        // into a small static region of the work buffer)
+        int* dmids = (int*)(scratch);   // scratch is free until the first prep pass
+        if (!mids.empty()) {
+            if ((e = hipMemcpyAsync(dmids, mids.data(), mids.size() * sizeof(int), hipMemcpyHostToDevice, st)) != hipSuccess)
+                return e;
+            extern hipError_t launch_dc_modify(double* const d[3], const double* const e[3], int nmat,
+                                               const int* mids, int nmids, hipStream_t st);
+            if ((e = launch_dc_modify(p.d, p.e, nmat, dmids, (int)mids.size(), st)) != hipSuccess) return e;
+        }
+    }
+    DCArgs da{};
+    for (int i = 0; i < nmat; ++i) {
+        da.d[i] = p.d[i];
+        da.e[i] = p.e[i];
+        da.lam[i] = p.lam[i];
+        da.Q[i] = p.Q[i];
+        da.Qn[i] = p.Qn[i];
+        da.M[i] = p.M[i];
+    }
+    da.scratch = scratch;
+    da.node_bytes = node_scratch_bytes();
+    da.ld = ld;
+    for (size_t h = 0; h < by_h.size(); ++h) {
+        auto& nodes = by_h[h];
+        Node* nd_dev = dnodes + h * ((max_nodes * sizeof(Node) + 255) / sizeof(Node));
+        if ((e = hipMemcpyAsync(nd_dev, nodes.data(), nodes.size() * sizeof(Node), hipMemcpyHostToDevice, st)) != hipSuccess)
+            return e;
+        da.nodes = nd_dev;
+        da.nnodes = (int)nodes.size();
+        if (h == 0) {
+            hipLaunchKernelGGL(k_dc_leaves, dim3((unsigned)nodes.size()), dim3(256), 0, st, da);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            continue;
+        }
+        int maxn = 0;
+        for (auto& nd : nodes) maxn = std::max(maxn, nd.hi - nd.lo);
+        hipLaunchKernelGGL(k_dc_prep, dim3((unsigned)nodes.size()), dim3(256), 0, st, da);
+        hipLaunchKernelGGL(k_dc_roots, dim3((unsigned)((maxn + 3) / 4), (unsigned)nodes.size()), dim3(256), 0, st, da);
+        hipLaunchKernelGGL(k_dc_zhat, dim3((unsigned)((maxn + 255) / 256), (unsigned)nodes.size()), dim3(256), 0, st, da);
+        hipLaunchKernelGGL(k_dc_vectors, dim3((unsigned)((maxn + 3) / 4), (unsigned)nodes.size()), dim3(256), 0, st, da);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        std::vector<GemmTask> tasks;
+        int max_tiles = 0;
+        for (auto& nd : nodes) {
+            const int n1 = nd.mid - nd.lo, n2 = nd.hi - nd.mid, n = nd.hi - nd.lo;
+            tasks.push_back(GemmTask{nd.mat, nd.lo, n1, nd.lo, n, nd.lo, n1});
+            tasks.push_back(GemmTask{nd.mat, nd.mid, n2, nd.lo, n, nd.mid, n2});
+            max_tiles = std::max(max_tiles, ((std::max(n1, n2) + 63) / 64) * ((n + 63) / 64));
+        }
+        GemmTask* tk_dev = dtasks + h * ((2 * max_nodes * sizeof(GemmTask) + 255) / sizeof(GemmTask));
+        if ((e = hipMemcpyAsync(tk_dev, tasks.data(), tasks.size() * sizeof(GemmTask), hipMemcpyHostToDevice, st)) != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(k_dc_gemm, dim3((unsigned)max_tiles, (unsigned)tasks.size()), dim3(256), 0, st, da,
+                           (const GemmTask*)tk_dev);
+        hipLaunchKernelGGL(k_dc_copyback, dim3(256, (unsigned)nodes.size()), dim3(256), 0, st, da);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+__global__ void k_dc_modify(double* d0, double* d1, double* d2, const double* e0, const double* e1,
+                            const double* e2, int nmat, const int* mids, int nmids) {
+    const int mat = blockIdx.y;
+    double* d = mat == 0 ? d0 : (mat == 1 ? d1 : d2);
+    const double* e = mat == 0 ? e0 : (mat == 1 ? e1 : e2);
+    // every index is touched by at most one split from each side; apply sequentially
+    // in one thread per matrix (nmids <= m/16)
+    if (threadIdx.x == 0 && blockIdx.x == 0 && mat < nmat) {
+        for (int q = 0; q < nmids; ++q) {
+            const int mid = mids[q];
+            const double b = e[mid - 1];
+            d[mid - 1] -= b;
+            d[mid] -= b;
+        }
+    }
+}
+
+hipError_t launch_dc_modify(double* const d[3], const double* const e[3], int nmat, const int* mids, int nmids,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_dc_modify, dim3(1, (unsigned)nmat), dim3(64), 0, st, d[0], nmat > 1 ? d[1] : d[0],
+                       nmat > 2 ? d[2] : d[0], e[0], nmat > 1 ? e[1] : e[0], nmat > 2 ? e[2] : e[0], nmat, mids, nmids);
+    return hipGetLastError();
+}
+
+size_t backtransform_work_doubles(int m) { return (size_t)((m + NB - 1) / NB + 1) * NB * NB; }
+
+hipError_t launch_backtransform(int m, int ld, const double* Hv, const double* tau, const double* Q, const int* order,
+                                int r, double* out, int ldo, int nrows, double* Tw, hipStream_t st) {
+    if (r < 1) return hipSuccess;
+    if (m > MAXN || nrows < m || ldo < nrows) return hipErrorInvalidValue;
+    hipError_t e;
+    const int mr = (m + 63) & ~63;
+    const size_t sh = (size_t)16 * mr * sizeof(double);
+    const bool xl = sh <= 128 * 1024;
+    const int nblk = m >= 3 ? (m - 2 + NB - 1) / NB : 0;
+    if (nblk > 0) {
+        hipLaunchKernelGGL(k_larft, dim3((unsigned)nblk), dim3(256), 0, st, m, ld, Hv, tau, Tw);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (xl) {
+        if ((e = hipFuncSetAttribute((const void*)k_apply_wy<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)sh)) != hipSuccess)
+            return e;
+        hipLaunchKernelGGL((k_apply_wy<true>), dim3((unsigned)((r + 15) / 16)), dim3(256), sh, st, m, ld, Hv, Tw, Q,
+                           order, r, out, ldo, nrows);
+    } else {
+        hipLaunchKernelGGL((k_apply_wy<false>), dim3((unsigned)((r + 15) / 16)), dim3(256), 0, st, m, ld, Hv, Tw, Q,
+                           order, r, out, ldo, nrows);
+    }
+    return hipGetLastError();
+}
+

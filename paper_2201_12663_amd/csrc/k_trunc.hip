@@ -1,4 +1,4 @@
-// a4/a5: truncation (sort, tails, ranks) and sign-normalized Z.
+// a4: truncation (sort, tails, ranks).
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -46,9 +46,9 @@ __global__ __launch_bounds__(TB) void k_truncate(TruncArgs a) {
     // eigenvalues, padded to a power of two with -inf
     int N2 = 1;
     while (N2 < a.m) N2 <<= 1;
-    const double* G = a.G[mode];
+    const double* lam = a.lam[mode];
     for (int i = t; i < N2; i += TB) {
-        key[i] = (i < a.m) ? G[(int64_t)i * a.m_pad + i] : -INFINITY;
+        key[i] = (i < a.m) ? lam[i] : -INFINITY;
         idx[i] = i;
     }
     __syncthreads();
@@ -102,47 +102,10 @@ __global__ __launch_bounds__(TB) void k_truncate(TruncArgs a) {
     }
 }
 
-// Z[:, k] = +-W[:, order[k]] for k < r (largest-magnitude entry positive, lowest
-// index on ties); rows >= n and columns r..r_pad-1 are zero.  One wave per column.
-__global__ __launch_bounds__(256) void k_form_z(int n, int n_pad, int r, int r_pad, const double* __restrict__ W,
-                                                int ldw, const int* __restrict__ order, double* __restrict__ Z) {
-    const int lane = threadIdx.x & 63;
-    const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (k >= r_pad) return;
-    double* z = Z + (int64_t)k * n_pad;
-    if (k >= r) {
-        for (int i = lane; i < n_pad; i += 64) z[i] = 0.0;
-        return;
-    }
-    const double* w = W + (int64_t)order[k] * ldw;
-    double best = -1.0;
-    int bi = 0x7fffffff;
-    for (int i = lane; i < n; i += 64) {
-        double a = fabs(w[i]);
-        if (a > best) { best = a; bi = i; }   // first (lowest) index per lane wins ties
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        double ob = __shfl_xor(best, o, 64);
-        int oi = __shfl_xor(bi, o, 64);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-    }
-    const double sgn = (w[bi] < 0.0) ? -1.0 : 1.0;
-    for (int i = lane; i < n_pad; i += 64) z[i] = (i < n) ? sgn * w[i] : 0.0;
-}
-
 }  // namespace
 
 hipError_t launch_truncate(const TruncArgs& a, hipStream_t st) {
     if (a.m < 1 || a.m > MAXM) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_truncate, dim3(3), dim3(TB), 0, st, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_form_z(int n, int n_pad, int r, int r_pad, const double* W, int ldw,
-                         const int* order, double* Z, hipStream_t st) {
-    if (r_pad < 1) return hipSuccess;
-    hipLaunchKernelGGL(k_form_z, dim3((unsigned)ceil_div(r_pad, 4)), dim3(256), 0, st, n, n_pad, r, r_pad,
-                       W, ldw, order, Z);
     return hipGetLastError();
 }

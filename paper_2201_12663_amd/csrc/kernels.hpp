@@ -6,8 +6,6 @@
 // Padding granularities shared by the workspace layout and the kernels.
 constexpr int PAD_N = 64;    // rows of U~, Z and the Gram side (n, m)
 constexpr int PAD_R = 64;    // canonical terms (columns of U~, K of the core)
-constexpr int PAD_V = 64;    // rows r_l of V^(l)
-constexpr int JB = 16;       // eigensolver block size (pairs of blocks = 32 indices)
 
 // a1: scaled column norms, xi' and normalized side matrices (all three modes).
 // U_l: n x R (ld n); Ut_l: n_pad x R_pad (ld n_pad), zero padded; xip: R_pad.
@@ -38,8 +36,8 @@ hipError_t launch_gemm64(bool a_kcontig, bool b_kcontig, int64_t M, int64_t N, i
 // R < n helpers (Z = U~ W Lambda^-1/2 and its re-orthonormalization)
 hipError_t launch_gather_scaled(int m_pad, int r, int r_pad, const double* W, const int* order,
                                 const double* sigma, double* Wr, hipStream_t st);
-hipError_t launch_pad_identity(int r, int mp, double* M, hipStream_t st);
-hipError_t launch_scale_cols_invsqrt(int mp, const double* D, double* P, hipStream_t st);
+hipError_t launch_pad_identity(int r, int mp, int ld, double* M, hipStream_t st);
+hipError_t launch_scale_cols_invsqrt(int mp, int ld, const double* mu, const double* P, double* out, hipStream_t st);
 hipError_t launch_sign_cols(int n, int n_pad, int r, double* Z, hipStream_t st);
 
 // a6: V_l = Z_l^T U~_l (r_pad x R_pad, col-major ld r_pad); Z_l: n_pad x r_pad (ld n_pad).
@@ -47,26 +45,34 @@ hipError_t launch_sign_cols(int n, int n_pad, int r, double* Z, hipStream_t st);
 hipError_t launch_project(int64_t n_pad, int64_t R_pad, int64_t r_pad, const double* Z,
                           const double* Ut, double* out_f64, float* out_f32, hipStream_t st);
 
-// a3: block Jacobi eigensolver on up to 3 symmetric matrices of one size
-// (cooperative launch).  G is overwritten (its diagonal holds the eigenvalues),
-// W receives the eigenvectors.  Returns the sweeps used in *sweeps (host) after
-// a stream synchronization is done by the caller (sweeps_dev).
-struct JacobiProblem {
+// a3: FP64 eigensolver (Householder tridiagonalization + divide and conquer) for
+// up to 3 symmetric m x m matrices (ld), m <= 2048.  G is overwritten by the
+// Householder vectors (column k holds v_k in rows k+1..m-1); lam receives the
+// eigenvalues (unsorted) and Q the eigenvectors of the tridiagonal matrix T
+// (eigenvectors of G = H Q, see launch_backtransform).
+struct EigProblem {
     double* G[3];
-    double* W[3];
-    int nmat;
-    int m_pad;        // multiple of 2*JB
-    int max_sweeps;
-    double tol;       // rotation threshold = tol * |G|_F
+    int nmat, m, ld;
+    double* lam[3];      // m
+    double* Q[3];        // ld x ld
+    double* Qn[3];       // ld x ld workspace
+    double* M[3];        // ld x ld workspace
+    double* d[3];        // m
+    double* e[3];        // m
+    double* tau[3];      // m
+    double* pbuf[3];     // m
 };
-hipError_t launch_jacobi(const JacobiProblem& p, void* work, size_t work_bytes,
-                         int* sweeps_dev, hipStream_t st);
-size_t jacobi_work_bytes(int nmat, int m_pad, int max_sweeps);
+size_t eig_work_bytes(int nmat, int m);
+hipError_t launch_eig(const EigProblem& p, void* work, size_t work_bytes, hipStream_t st);
+// out[:, k] = H Q[:, order[k]] for k < r (order NULL: identity), rows >= m zero up to nrows.
+// Tw: workspace of backtransform_work_doubles(m) doubles (the compact-WY T factors).
+size_t backtransform_work_doubles(int m);
+hipError_t launch_backtransform(int m, int ld, const double* Hv, const double* tau, const double* Q, const int* order,
+                                int r, double* out, int ldo, int nrows, double* Tw, hipStream_t st);
 
-// a4/a5: norms finalize, sort, tails, ranks, sign-normalized Z (per mode).
+// a4/a5: norms finalize, sort, tails, ranks (per mode).
 struct TruncArgs {
-    const double* G[3];     // diagonal = eigenvalues
-    const double* W[3];     // eigenvectors
+    const double* lam[3];   // eigenvalues (any order)
     int m;                  // valid eigenpairs (min(n, R))
     int m_pad;
     int n;
@@ -84,11 +90,6 @@ struct TruncArgs {
     double* scal;           // [0] xi_norm, [1] a_norm, [2] tau
 };
 hipError_t launch_truncate(const TruncArgs& a, hipStream_t st);
-
-// Z_l (n_pad x r_pad, ld n_pad) from W columns order[0..r-1], sign-normalized,
-// zero beyond r rows/cols.  Also an optional FP32 copy.
-hipError_t launch_form_z(int n, int n_pad, int r, int r_pad, const double* W, int ldw,
-                         const int* order, double* Z, hipStream_t st);
 
 // a7: beta[j1 + r1 (j2 + r2 j3)] = sum_nu xi'_nu V1[j1,nu] V2[j2,nu] V3[j3,nu].
 // V_l: col-major (r_pad_l x R_pad), xip: R_pad.  prec 0 = f64, 1 = f32, 2 = bf16x3.
