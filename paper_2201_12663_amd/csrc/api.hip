@@ -50,7 +50,6 @@ struct rhosvd_ctx {
     double* ee[3] = {};
     double* htau[3] = {};                // Householder scalars
     double* Tw[3] = {};                  // compact-WY factors of the back-transformation
-    double* pb[3] = {};
     void* eigw = nullptr;
     size_t eigw_bytes = 0;
     double* gram_part = nullptr;
@@ -78,7 +77,6 @@ struct rhosvd_ctx {
     double* dd2[3] = {};
     double* ee2[3] = {};
     double* tau2[3] = {};
-    double* pb2[3] = {};
     // results
     bool have = false;
     int ranks[3] = {0, 0, 0};
@@ -150,7 +148,6 @@ size_t carve_all(rhosvd_ctx* h, char* base) {
         h->dd[l] = c.take<double>(mp);
         h->ee[l] = c.take<double>(mp);
         h->htau[l] = c.take<double>(mp);
-        h->pb[l] = c.take<double>(mp);
         h->Tw[l] = c.take<double>(backtransform_work_doubles((int)std::max(mp, zp)));
         h->sigma[l] = c.take<double>(mp + 1);
         h->order[l] = c.take<int>(mp);
@@ -179,7 +176,6 @@ size_t carve_all(rhosvd_ctx* h, char* base) {
             h->dd2[l] = c.take<double>(zp);
             h->ee2[l] = c.take<double>(zp);
             h->tau2[l] = c.take<double>(zp);
-            h->pb2[l] = c.take<double>(zp);
         }
     }
     return c.off;
@@ -231,11 +227,15 @@ rhosvd_status form_z_rside(rhosvd_ctx* h) {
     const int64_t np = h->n_pad, Rp = h->R_pad, zp = h->zr_pad;
     int rmp = 0;
     for (int l = 0; l < 3; ++l) rmp = h->r_pad[l] > rmp ? h->r_pad[l] : rmp;
+    BtJob jobs[3];
+    for (int l = 0; l < 3; ++l) {
+        CK(h, hipMemsetAsync(h->Wr[l], 0, (size_t)Rp * zp * 8, st));
+        jobs[l] = BtJob{(int)h->m, (int)h->m_pad, h->G[l], h->htau[l], h->W[l], h->order[l], h->ranks[l], nullptr,
+                        h->Wr[l], (int)Rp, (int)Rp, h->Tw[l]};
+    }
+    CK(h, launch_backtransform(jobs, 3, st));
     for (int l = 0; l < 3; ++l) {
         const int r = h->ranks[l], rp = h->r_pad[l];
-        CK(h, hipMemsetAsync(h->Wr[l], 0, (size_t)Rp * zp * 8, st));
-        CK(h, launch_backtransform((int)h->m, (int)h->m_pad, h->G[l], h->htau[l], h->W[l], h->order[l], r, h->Wr[l],
-                                   (int)Rp, (int)Rp, h->Tw[l], st));
         CK(h, launch_gather_scaled((int)Rp, r, rp, h->Wr[l], nullptr, h->sigma[l], h->Wr[l], st));
         CK(h, hipMemsetAsync(h->Zraw[l], 0, (size_t)np * zp * 8, st));
         CK(h, launch_gemm64(false, true, np, rp, Rp, h->Ut[l], np, h->Wr[l], Rp, h->Zraw[l], np, 1.0, st));
@@ -246,16 +246,18 @@ rhosvd_status form_z_rside(rhosvd_ctx* h) {
     for (int l = 0; l < 3; ++l) {
         ep.G[l] = h->M2[l]; ep.lam[l] = h->lam2[l]; ep.Q[l] = h->P2[l]; ep.Qn[l] = h->Qn2[l];
         ep.M[l] = h->Mg2[l]; ep.d[l] = h->dd2[l]; ep.e[l] = h->ee2[l]; ep.tau[l] = h->tau2[l];
-        ep.pbuf[l] = h->pb2[l];
     }
     ep.nmat = 3;
+    ep.abort_w = h->flags + 2;
     ep.m = rmp;
     ep.ld = (int)zp;
     CK(h, launch_eig(ep, h->eigw, h->eigw_bytes, st));
+    // P = H P2 (all rmp columns); S = P diag(mu^-1/2) P^T ; Z = Zraw S
+    for (int l = 0; l < 3; ++l)
+        jobs[l] = BtJob{rmp, (int)zp, h->M2[l], h->tau2[l], h->P2[l], nullptr, rmp, nullptr, h->Pf[l], (int)zp, rmp,
+                        h->Tw[l]};
+    CK(h, launch_backtransform(jobs, 3, st));
     for (int l = 0; l < 3; ++l) {
-        // P = H P2 (all rmp columns); S = P diag(mu^-1/2) P^T ; Z = Zraw S
-        CK(h, launch_backtransform(rmp, (int)zp, h->M2[l], h->tau2[l], h->P2[l], nullptr, rmp, h->Pf[l], (int)zp, rmp,
-                                   h->Tw[l], st));
         CK(h, launch_scale_cols_invsqrt(rmp, (int)zp, h->lam2[l], h->Pf[l], h->S2[l], st));
         CK(h, launch_gemm64(false, false, rmp, rmp, rmp, h->S2[l], zp, h->Pf[l], zp, h->M2[l], zp, 1.0, st));
         CK(h, launch_gemm64(false, true, np, rmp, rmp, h->Zraw[l], np, h->M2[l], zp, h->Z[l], np, 1.0, st));
@@ -355,9 +357,9 @@ rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R, const double*
     for (int l = 0; l < 3; ++l) {
         ep.G[l] = h->G[l]; ep.lam[l] = h->lam[l]; ep.Q[l] = h->W[l]; ep.Qn[l] = h->Qn[l];
         ep.M[l] = h->Mg[l]; ep.d[l] = h->dd[l]; ep.e[l] = h->ee[l]; ep.tau[l] = h->htau[l];
-        ep.pbuf[l] = h->pb[l];
     }
     ep.nmat = 3;
+    ep.abort_w = h->flags + 2;
     ep.m = (int)h->m;
     ep.ld = (int)h->m_pad;
     CK(h, launch_eig(ep, h->eigw, h->eigw_bytes, st));
@@ -383,10 +385,11 @@ rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R, const double*
     CK(h, launch_truncate(ta, st));
     // the one host synchronization: ranks, flags, sweeps and norms
     CK(h, hipMemcpyAsync(h->host, h->ranks_dev, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
-    CK(h, hipMemcpyAsync(h->host + 4, h->flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    CK(h, hipMemcpyAsync(h->host + 4, h->flags, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
     CK(h, hipMemcpyAsync(h->hostd, h->scal, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
     CK(h, hipStreamSynchronize(st));
     if (h->host[4]) return fail(h, RHOSVD_ERR_NONFINITE, "input contains NaN or Inf");
+    if (h->host[6]) return fail(h, RHOSVD_ERR_DEVICE, "eigensolver: a cross-workgroup wait ran out");
     h->sweeps = 0;
     h->dropped = h->host[5];
     h->xi_norm = h->hostd[0];
@@ -398,12 +401,15 @@ rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R, const double*
     }
     // a5/a6: Z and the projections V = Z^T U~ (FP64 MFMA; rounded to FP32 for the mixed core)
     if (!h->rside) {
+        // Z = H W[:, order[0..r-1]]: back-transformed eigenvectors, sign rule, zero padding
+        BtJob jobs[3];
+        for (int l = 0; l < 3; ++l)
+            jobs[l] = BtJob{(int)h->m, (int)h->m_pad, h->G[l], h->htau[l], h->W[l], h->order[l], h->ranks[l], nullptr,
+                            h->Z[l], (int)h->n_pad, (int)h->n_pad, h->Tw[l]};
+        CK(h, launch_backtransform(jobs, 3, st));
         for (int l = 0; l < 3; ++l) {
             const int r = h->ranks[l];
             if (r < 1) continue;
-            // Z = H W[:, order[0..r-1]]: back-transformed eigenvectors, sign rule, zero padding
-            CK(h, launch_backtransform((int)h->m, (int)h->m_pad, h->G[l], h->htau[l], h->W[l], h->order[l], r, h->Z[l],
-                                       (int)h->n_pad, (int)h->n_pad, h->Tw[l], st));
             CK(h, launch_sign_cols((int)n, (int)h->n_pad, r, h->Z[l], st));
             if (h->r_pad[l] > r)
                 CK(h, hipMemsetAsync(h->Z[l] + (int64_t)r * h->n_pad, 0,
@@ -468,7 +474,9 @@ rhosvd_status rhosvd_get(rhosvd_handle h, double* Z1, double* Z2, double* Z3, do
         for (int l = 0; l < 3; ++l)
             if (h->ranks[l] > 0)
                 CK(h, hipMemcpyAsync(h->hostd + 4 + l, h->tails[l] + h->ranks[l], 8, hipMemcpyDeviceToHost, st));
+        CK(h, hipMemcpyAsync(h->host + 8, h->flags + 2, sizeof(int), hipMemcpyDeviceToHost, st));
         CK(h, hipStreamSynchronize(st));
+        if (h->host[8]) return fail(h, RHOSVD_ERR_DEVICE, "eigensolver: a cross-workgroup wait ran out");
         for (int l = 0; l < 3; ++l) tl[l] = h->ranks[l] > 0 ? h->hostd[4 + l] : 0.0;
         memset(report, 0, sizeof(*report));
         report->xi_norm = h->xi_norm;

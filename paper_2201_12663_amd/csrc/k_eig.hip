@@ -45,45 +45,103 @@ __device__ double block_sum256(double v, double* red) {
 // ---------------------------------------------------------------------------
 // 1. tridiagonalization
 // ---------------------------------------------------------------------------
+// Matrices of one tridiagonalization launch: matrix q owns blocks
+// [blk0, blk0 + bpm), each holding cpb consecutive columns in LDS.
+struct TriMat {
+    double* G;          // m x m (ld): in the symmetric matrix, out the reflectors below the diagonal
+    double* d;          // m
+    double* e;          // m - 1
+    double* tau;        // m
+    uint64_t* x;        // exchange area, tri_xwords(m) words, zero before the launch
+    int m, ld, cpb, bpm, blk0;
+};
+constexpr int TRI_MAXMAT = 24;
 struct TriArgs {
-    double* G[3];      // m x m (ld), in: symmetric matrix; out: reflectors below the diagonal
-    double* d[3];      // m
-    double* e[3];      // m - 1
-    double* tau[3];    // m
-    double* p[3];      // m (exchange buffer)
-    double* part[3];   // per-block partial sums of p.v (bpm)
-    unsigned* bar;     // one counter per matrix (64 apart)
-    int m, ld, cpb, bpm;   // columns per block, blocks per matrix
+    TriMat mat[TRI_MAXMAT];
+    int nmat;
+    int* abort_w;       // set to 1 when an exchange wait ran out
 };
 
-// Cross-workgroup data of the tridiagonalization (reflectors, tau, p, partial
-// sums) moves only through agent-scope relaxed atomic loads and stores, which
-// are coherent across the whole device.  A group barrier therefore needs no
-// cache write-back or invalidation: each thread waits until its own stores have
-// completed (s_waitcnt 0) before the workgroup arrives, and data loads are
-// issued only after the arrival count has been observed.
-__device__ __forceinline__ void st_dev(double* p, double v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__host__ __device__ constexpr size_t tri_xwords(int m) { return (size_t)8 * ((m + 63) & ~63) + 4 * 256 + 8; }
+
+// Cross-workgroup exchange of the tridiagonalization.  A double travels as two
+// 64-bit words {32 data bits, 32 flag bits}, each written by one agent-scope
+// atomic store; a reader polls the words until both carry the flag of the
+// current column step, so the data needs no separate barrier or cache
+// maintenance.  Buffers alternate by the parity of the step: a slot is
+// rewritten two steps later, after every reader has provably consumed it.
+// Every wait is bounded: past the spin limit the reader raises the launch's
+// abort word, all other waits end at once and the host reports an error.
+constexpr int SPIN_LIMIT = 1 << 22;
+
+__device__ __forceinline__ void ll_put(uint64_t* w, double v, uint32_t flag) {
+    const uint64_t bits = (uint64_t)__double_as_longlong(v);
+    __hip_atomic_store(w, (bits & 0xffffffffull) | ((uint64_t)flag << 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(w + 1, (bits >> 32) | ((uint64_t)flag << 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ double ld_dev(const double* p) {
-    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ uint64_t ll_ld(const uint64_t* w) {
+    return __hip_atomic_load(const_cast<uint64_t*>(w), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void group_barrier_dev(unsigned* count, unsigned nb, unsigned epoch) {
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        while (__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch * nb) {
-        }
-    }
-    __syncthreads();
+__device__ __forceinline__ double ll_val(uint64_t lo, uint64_t hi) {
+    return __longlong_as_double((long long)((lo & 0xffffffffull) | (hi << 32)));
 }
 
-// reflector k from the (current) column k held in LDS: v (rows k+1..m-1, v[k+1] = 1)
-// to G[:, k]; tau, beta (= e_k) and d_k to global memory.
-__device__ void form_reflector(const double* x, int k, int m, int ld, double* G, double* tau_out, double* e_out,
-                               double* d_out, double* red) {
-    const int t = threadIdx.x;
+// Receive N values (entries idx[q] of the word array, q < N, skipped when idx < 0).
+template <int N>
+__device__ __forceinline__ void ll_get(const uint64_t* base, const int (&idx)[N], double (&out)[N], uint32_t flag,
+                                       int* abort_w) {
+    bool ready[N];
+#pragma unroll
+    for (int q = 0; q < N; ++q) ready[q] = idx[q] < 0;
+    for (int spin = 0;; ++spin) {
+        uint64_t lo[N], hi[N];
+#pragma unroll
+        for (int q = 0; q < N; ++q)
+            if (!ready[q]) {
+                lo[q] = ll_ld(base + 2 * idx[q]);
+                hi[q] = ll_ld(base + 2 * idx[q] + 1);
+            }
+        bool all = true;
+#pragma unroll
+        for (int q = 0; q < N; ++q)
+            if (!ready[q]) {
+                if ((uint32_t)(lo[q] >> 32) == flag && (uint32_t)(hi[q] >> 32) == flag) {
+                    out[q] = ll_val(lo[q], hi[q]);
+                    ready[q] = true;
+                } else {
+                    all = false;
+                }
+            }
+        if (all) return;
+        if ((spin & 63) == 63) {
+            if (__hip_atomic_load(abort_w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || spin > SPIN_LIMIT) {
+                __hip_atomic_store(abort_w, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+                for (int q = 0; q < N; ++q)
+                    if (!ready[q]) out[q] = 0.0;
+                return;
+            }
+        }
+    }
+}
+
+// word offsets inside a matrix's exchange area
+__device__ __forceinline__ uint64_t* xv(const TriMat& M, int par) { return M.x + (size_t)par * 2 * ((M.m + 63) & ~63); }
+__device__ __forceinline__ uint64_t* xp(const TriMat& M, int par) {
+    return M.x + (size_t)4 * ((M.m + 63) & ~63) + (size_t)par * 2 * ((M.m + 63) & ~63);
+}
+__device__ __forceinline__ uint64_t* xpart(const TriMat& M, int par) {
+    return M.x + (size_t)8 * ((M.m + 63) & ~63) + (size_t)par * 2 * 256;
+}
+__device__ __forceinline__ uint64_t* xtau(const TriMat& M, int par) {
+    return M.x + (size_t)8 * ((M.m + 63) & ~63) + 4 * 256 + 2 * par;
+}
+
+// reflector k from the (current) column k held in LDS: v (rows k+1..m-1,
+// v[k+1] = 1) and tau are sent for step k; G[:, k], tau, e_k = beta and d_k are
+// stored for the later kernels.
+__device__ void form_reflector(const double* x, int k, const TriMat& M, double* red) {
+    const int t = threadIdx.x, m = M.m;
     double s = 0.0;
     for (int i = k + 2 + t; i < m; i += 256) s += x[i] * x[i];
     s = block_sum256(s, red);
@@ -97,50 +155,81 @@ __device__ void form_reflector(const double* x, int k, int m, int ld, double* G,
         tau = (beta - alpha) / beta;
         scal = 1.0 / (alpha - beta);
     }
-    for (int i = k + 1 + t; i < m; i += 256) st_dev(&G[i + (int64_t)k * ld], (i == k + 1) ? 1.0 : x[i] * scal);
+    const uint32_t flag = (uint32_t)k + 1;
+    uint64_t* vx = xv(M, k & 1);
+    for (int i = k + 1 + t; i < m; i += 256) {
+        const double v = (i == k + 1) ? 1.0 : x[i] * scal;
+        ll_put(vx + 2 * i, v, flag);
+        M.G[i + (int64_t)k * M.ld] = v;
+    }
     if (t == 0) {
-        st_dev(&tau_out[k], tau);
-        e_out[k] = beta;
-        d_out[k] = x[k];
+        ll_put(xtau(M, k & 1), tau, flag);
+        M.tau[k] = tau;
+        M.e[k] = beta;
+        M.d[k] = x[k];
     }
 }
 
 constexpr int RPT = MAXN / 256;   // rows per thread
 
+// One-sided Householder tridiagonalization H^T G H = T, column-distributed:
+// step k broadcasts v_k, every block forms p_j = tau (G v)_j for its columns,
+// the p_j and the per-block sums of p_j v_j are all-gathered, and each block
+// applies G <- G - v w^T - w v^T with w = p - (tau/2)(p.v) v to its columns.
+// The owner of column k+1 updates it first and forms reflector k+1.
 __global__ __launch_bounds__(256) void k_tridiag(TriArgs a) {
     extern __shared__ double slab[];   // cpb columns x m_round, then v (m_round)
     __shared__ double red[4];
     __shared__ double red2[CMAX * 4];
     __shared__ double vjs[CMAX], wjs[CMAX], pjs[CMAX];
-    const int mat = blockIdx.x / a.bpm, gb = blockIdx.x % a.bpm;
-    const int m = a.m, ld = a.ld, cpb = a.cpb;
+    __shared__ double parts[256];
+    __shared__ double cw_s, tau_s;
+    int q0 = 0;
+    while (q0 + 1 < a.nmat && (int)blockIdx.x >= a.mat[q0 + 1].blk0) ++q0;
+    const TriMat& M = a.mat[q0];
+    const int gb = blockIdx.x - M.blk0;
+    if (gb >= M.bpm) return;
+    const int m = M.m, ld = M.ld, cpb = M.cpb;
     const int mr = (m + 63) & ~63;
     double* vs = slab + (size_t)cpb * mr;
     const int c0 = gb * cpb;
     const int nc = max(0, min(cpb, m - c0));
-    double* G = a.G[mat];
-    double* P = a.p[mat];
-    double* part = a.part[mat];
-    unsigned* bar = a.bar + 64 * mat;
     const int t = threadIdx.x;
     for (int c = 0; c < nc; ++c)
-        for (int i = t; i < m; i += 256) slab[c * mr + i] = G[i + (int64_t)(c0 + c) * ld];
+        for (int i = t; i < m; i += 256) slab[c * mr + i] = M.G[i + (int64_t)(c0 + c) * ld];
     __syncthreads();
-    if (m > 2 && c0 == 0 && nc > 0) form_reflector(slab, 0, m, ld, G, a.tau[mat], a.e[mat], a.d[mat], red);
-    unsigned epoch = 0;
+    if (m > 2 && c0 == 0 && nc > 0) form_reflector(slab, 0, M, red);
     for (int k = 0; k + 2 < m; ++k) {
-        group_barrier_dev(bar, a.bpm, ++epoch);     // reflector k is visible
-        const double tau = ld_dev(&a.tau[mat][k]);
+        const int par = k & 1;
+        const uint32_t flag = (uint32_t)k + 1;
+        // receive v_k (this thread's rows) and tau_k
         double vr[RPT];
+        {
+            int idx[RPT];
 #pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-            const int i = k + 1 + t + 256 * q;
-            vr[q] = (i < m) ? ld_dev(&G[i + (int64_t)k * ld]) : 0.0;
-            if (i < m) vs[i] = vr[q];
+            for (int q = 0; q < RPT; ++q) {
+                const int i = k + 1 + t + 256 * q;
+                idx[q] = (i < m) ? i : -1;
+                vr[q] = 0.0;
+            }
+            ll_get<RPT>(xv(M, par), idx, vr, flag, a.abort_w);
+#pragma unroll
+            for (int q = 0; q < RPT; ++q)
+                if (idx[q] >= 0) vs[idx[q]] = vr[q];
+            if (t == 0) {
+                int ti[1] = {0};
+                double tv[1] = {0.0};
+                ll_get<1>(xtau(M, par), ti, tv, flag, a.abort_w);
+                tau_s = tv[0];
+            }
         }
+        __syncthreads();   // vs and tau_s
+        const double tau = tau_s;
         const int cs = max(0, k + 1 - c0);   // first local column with j > k
-        // (b) p_j = tau * sum_i G[i,j] v_i for own columns j > k, and this block's share of p.v
-        if (tau != 0.0) {
+        const int cn = k + 1 - c0;           // local index of column k+1
+        {
+            // p_j = tau sum_i G[i,j] v_i for own columns j > k (exchanged even when
+            // tau = 0: the all-gather of p orders the reuse of the step buffers)
             double acc[CMAX];
 #pragma unroll
             for (int c = 0; c < CMAX; ++c) acc[c] = 0.0;
@@ -159,33 +248,44 @@ __global__ __launch_bounds__(256) void k_tridiag(TriArgs a) {
                     const double sw = wave_sum(acc[c]);
                     if ((t & 63) == 0) red2[c * 4 + (t >> 6)] = sw;
                 }
-            __syncthreads();   // red2 and vs complete
+            __syncthreads();
             if (t < 64) {
                 double pv = 0.0;
                 if (t >= cs && t < nc) {
                     const double pj = tau * ((red2[t * 4] + red2[t * 4 + 1]) + (red2[t * 4 + 2] + red2[t * 4 + 3]));
-                    st_dev(&P[c0 + t], pj);
+                    ll_put(xp(M, par) + 2 * (c0 + t), pj, flag);
                     pjs[t] = pj;
                     pv = pj * vs[c0 + t];
                 }
                 const double sp = wave_sum(pv);
-                if (t == 0) st_dev(&part[gb], sp);
+                if (t == 0) ll_put(xpart(M, par) + 2 * gb, sp, flag);
             }
-        }
-        group_barrier_dev(bar, a.bpm, ++epoch);     // p and the partial p.v are visible
-        // (c) w = p - (tau/2)(p.v) v ;  slab -= v w^T + w v^T on rows and columns > k.
-        //     The owner of column k+1 updates it first and forms reflector k+1.
-        const int cn = k + 1 - c0;   // local index of column k+1
-        if (tau != 0.0) {
+            // receive p (this thread's rows) and the per-block partial sums
             double pr[RPT];
+            {
+                int idx[RPT];
 #pragma unroll
-            for (int q = 0; q < RPT; ++q) {
-                const int i = k + 1 + t + 256 * q;
-                pr[q] = (i < m) ? ld_dev(&P[i]) : 0.0;
+                for (int q = 0; q < RPT; ++q) {
+                    const int i = k + 1 + t + 256 * q;
+                    idx[q] = (i < m) ? i : -1;
+                    pr[q] = 0.0;
+                }
+                ll_get<RPT>(xp(M, par), idx, pr, flag, a.abort_w);
+                if (t < M.bpm) {
+                    int pi[1] = {t};
+                    double pvv[1] = {0.0};
+                    ll_get<1>(xpart(M, par), pi, pvv, flag, a.abort_w);
+                    parts[t] = pvv[0];
+                }
             }
-            double s = 0.0;
-            for (int q = 0; q < a.bpm; ++q) s += ld_dev(&part[q]);
-            const double cw = 0.5 * tau * s;
+            __syncthreads();
+            if (t == 0) {
+                double s = 0.0;
+                for (int q = 0; q < M.bpm; ++q) s += parts[q];
+                cw_s = 0.5 * tau * s;
+            }
+            __syncthreads();
+            const double cw = cw_s;
             if (t >= cs && t < nc) {
                 vjs[t] = vs[c0 + t];
                 wjs[t] = pjs[t] - cw * vs[c0 + t];
@@ -199,7 +299,7 @@ __global__ __launch_bounds__(256) void k_tridiag(TriArgs a) {
                     if (i < m) slab[cn * mr + i] -= vr[q] * wjs[cn] + (pr[q] - cw * vr[q]) * vjs[cn];
                 }
                 __syncthreads();
-                if (k + 3 < m) form_reflector(slab + cn * mr, k + 1, m, ld, G, a.tau[mat], a.e[mat], a.d[mat], red);
+                if (k + 3 < m) form_reflector(slab + cn * mr, k + 1, M, red);
                 cfirst = cn + 1;
             }
             if (cfirst < nc) {
@@ -214,21 +314,22 @@ __global__ __launch_bounds__(256) void k_tridiag(TriArgs a) {
                     }
                 }
             }
-        } else if (cn >= 0 && cn < nc && k + 3 < m) {
-            // H_k = I: column k+1 is unchanged; its owner forms reflector k+1
-            form_reflector(slab + cn * mr, k + 1, m, ld, G, a.tau[mat], a.e[mat], a.d[mat], red);
         }
         __syncthreads();
     }
-    // the last 2x2 block
+    // the last 2 x 2 block
     for (int c = 0; c < nc; ++c) {
         const int j = c0 + c;
         if (t == 0) {
-            if (j == m - 2 || (m == 1 && j == 0)) a.d[mat][j] = slab[c * mr + j];
-            if (j == m - 1) a.d[mat][j] = slab[c * mr + j];
-            if (j == m - 2) a.e[mat][j] = slab[c * mr + j + 1];
+            if (j == m - 2 || (m == 1 && j == 0)) M.d[j] = slab[c * mr + j];
+            if (j == m - 1) M.d[j] = slab[c * mr + j];
+            if (j == m - 2) M.e[j] = slab[c * mr + j + 1];
         }
     }
+}
+
+__global__ void k_zero_words(uint64_t* p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -688,21 +789,29 @@ __device__ __forceinline__ double vb(const double* Hv, int ld, int m, int k0, in
 }
 
 // T_b from Y = V_b^T V_b, computed with FP64 MFMA (one 16 x 16 tile of Y per wave).
-__global__ __launch_bounds__(256) void k_larft(int m, int ld, const double* __restrict__ Hv,
-                                               const double* __restrict__ tau, double* __restrict__ Tw) {
+// grid: (blocks of the largest job, jobs)
+__global__ __launch_bounds__(256) void k_larft(BtJobs J) {
     __shared__ double Y[NB][NB + 1];
     __shared__ double T[NB][NB + 1];
+    const BtJob& jb = J.job[blockIdx.y];
+    const int m = jb.m, ld = jb.ld;
+    const double* __restrict__ Hv = jb.Hv;
     const int b = blockIdx.x, k0 = NB * b;
+    if (m < 3 || k0 >= m - 2) return;
     const int kc = min(NB, (m - 2) - k0);
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int ti = w & 1, tj = w >> 1;
     d4_t acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-    for (int row0 = k0 + 1; row0 < m; row0 += 4) {
-        const int row = row0 + (lane >> 4);
-        const double av = vb(Hv, ld, m, k0, 16 * ti + (lane & 15), kc, row);
-        const double bv = vb(Hv, ld, m, k0, 16 * tj + (lane & 15), kc, row);
-        acc = mfma_f64(av, bv, acc);
+    for (int row0 = k0 + 1; row0 < m; row0 += 32) {
+        double av[8], bv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int row = row0 + 4 * u + (lane >> 4);
+            av[u] = vb(Hv, ld, m, k0, 16 * ti + (lane & 15), kc, row);
+            bv[u] = vb(Hv, ld, m, k0, 16 * tj + (lane & 15), kc, row);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = mfma_f64(av[u], bv[u], acc);
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) Y[16 * ti + c_row64(lane, q)][16 * tj + c_col(lane)] = acc[q];
@@ -710,7 +819,7 @@ __global__ __launch_bounds__(256) void k_larft(int m, int ld, const double* __re
     __syncthreads();
     if (t < 64) {
         for (int i = 0; i < kc; ++i) {
-            const double tv = tau[k0 + i];
+            const double tv = jb.tau[k0 + i];
             double v = 0.0;
             if (t < i) {
                 for (int q = t; q < i; ++q) v += T[t][q] * Y[q][i];
@@ -725,48 +834,56 @@ __global__ __launch_bounds__(256) void k_larft(int m, int ld, const double* __re
         }
     }
     __syncthreads();
-    for (int e = t; e < NB * NB; e += 256) Tw[(int64_t)b * NB * NB + e] = T[e % NB][e / NB];
+    for (int e = t; e < NB * NB; e += 256) jb.Tw[(int64_t)b * NB * NB + e] = T[e % NB][e / NB];
 }
 
 // X <- H X for a slab of 16 columns of X (one workgroup), blocks applied last first:
 //   Wm = V_b^T X (MFMA, 2 tiles x 2 halves of the rows), W2 = T_b Wm, X -= V_b W2 (MFMA).
 // XL: the slab lives in LDS as X[i * 16 + c]; otherwise it is updated in place in out.
+// grid: (slabs of the largest job, jobs); slabs at or beyond the job's rank exit.
 template <bool XL>
-__global__ __launch_bounds__(256) void k_apply_wy(int m, int ld, const double* __restrict__ Hv,
-                                                  const double* __restrict__ Tw, const double* __restrict__ Q,
-                                                  const int* __restrict__ order, int r, double* __restrict__ out,
-                                                  int ldo, int nrows) {
+__global__ __launch_bounds__(256) void k_apply_wy(BtJobs J) {
     extern __shared__ double Xs[];              // mr x 16 when XL
     __shared__ double P[2][NB][17];
     __shared__ double W2[NB][17];
     constexpr int CW = 16;
+    const BtJob& jb = J.job[blockIdx.y];
+    const int m = jb.m, ld = jb.ld, ldo = jb.ldo, nrows = jb.nrows;
+    const int r = jb.r_dev ? min(*jb.r_dev, jb.r) : jb.r;
+    const double* __restrict__ Hv = jb.Hv;
     const int mr = (m + 63) & ~63;
-    const int c0 = blockIdx.x * CW, nc = min(CW, r - c0);
+    const int c0 = blockIdx.x * CW;
+    if (c0 >= r) return;
+    const int nc = min(CW, r - c0);
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    double* Xo = out + (int64_t)c0 * ldo;
+    double* Xo = jb.out + (int64_t)c0 * ldo;
     auto X = [&](int i, int c) -> double& { return XL ? Xs[i * CW + c] : Xo[i + (int64_t)c * ldo]; };
     // load the slab (columns beyond nc and rows beyond m are zero)
     const int rows_ld = XL ? mr : m;
     for (int e = t; e < rows_ld * CW; e += 256) {
         const int c = e % CW, i = e / CW;
         double v = 0.0;
-        if (c < nc && i < m) v = Q[i + (int64_t)(order ? order[c0 + c] : c0 + c) * ld];
+        if (c < nc && i < m) v = jb.Q[i + (int64_t)(jb.order ? jb.order[c0 + c] : c0 + c) * ld];
         if (XL || c < nc) X(i, c) = v;
     }
     __syncthreads();
-    const int nblk = (m - 2 + NB - 1) / NB;
+    const int nblk = m >= 3 ? (m - 2 + NB - 1) / NB : 0;
     for (int b = nblk - 1; b >= 0; --b) {
         const int k0 = NB * b, kc = min(NB, (m - 2) - k0);
         // pass 1: wave w -> tile jt = w & 1 of Wm, rows interleaved by halves h = w >> 1
         {
             const int jt = w & 1, h = w >> 1;
             d4_t acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-            for (int row0 = k0 + 1 + 4 * h; row0 < m; row0 += 8) {
-                const int row = row0 + (lane >> 4);
-                const double av = vb(Hv, ld, m, k0, 16 * jt + (lane & 15), kc, row);
-                const double bv = (row < m && (XL || (lane & 15) < nc)) ? X(row, lane & 15) : 0.0;
-                acc = mfma_f64(av, bv, acc);
+            for (int row0 = k0 + 1 + 4 * h; row0 < m; row0 += 64) {
+                double av[8], bv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int row = row0 + 8 * u + (lane >> 4);
+                    av[u] = vb(Hv, ld, m, k0, 16 * jt + (lane & 15), kc, row);
+                    bv[u] = (row < m && (XL || (lane & 15) < nc)) ? X(row, lane & 15) : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) acc = mfma_f64(av[u], bv[u], acc);
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q) P[h][16 * jt + c_row64(lane, q)][c_col(lane)] = acc[q];
@@ -774,7 +891,7 @@ __global__ __launch_bounds__(256) void k_apply_wy(int m, int ld, const double* _
         __syncthreads();
         // W2 = T_b Wm (T_b upper triangular, column-major)
         {
-            const double* T = Tw + (int64_t)b * NB * NB;
+            const double* T = jb.Tw + (int64_t)b * NB * NB;
             for (int e = t; e < NB * CW; e += 256) {
                 const int j = e % NB, c = e / NB;
                 double s = 0.0;
@@ -783,19 +900,30 @@ __global__ __launch_bounds__(256) void k_apply_wy(int m, int ld, const double* _
             }
         }
         __syncthreads();
-        // pass 2: X[i, :] -= V_b[i, :] W2 for rows k0+1 .. m-1, 16-row tiles over the waves
+        // pass 2: X[i, :] -= V_b[i, :] W2 for rows k0+1 .. m-1, 16-row tiles over the waves;
+        // the reflector values of the next tile are loaded before this tile's MFMAs
         {
             const int i0 = k0 + 1;
             const int ntile = (m - i0 + 15) / 16;
+            double an[NB / 4];
+            if (w < ntile) {
+#pragma unroll
+                for (int st = 0; st < NB / 4; ++st)
+                    an[st] = vb(Hv, ld, m, k0, 4 * st + (lane >> 4), kc, i0 + 16 * w + (lane & 15));
+            }
             for (int tl = w; tl < ntile; tl += 4) {
                 const int rb = i0 + 16 * tl;
+                double av[NB / 4];
+#pragma unroll
+                for (int st = 0; st < NB / 4; ++st) av[st] = an[st];
+                if (tl + 4 < ntile) {
+#pragma unroll
+                    for (int st = 0; st < NB / 4; ++st)
+                        an[st] = vb(Hv, ld, m, k0, 4 * st + (lane >> 4), kc, rb + 64 + (lane & 15));
+                }
                 d4_t acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int st = 0; st < NB / 4; ++st) {
-                    const int j = 4 * st + (lane >> 4);
-                    const double av = vb(Hv, ld, m, k0, j, kc, rb + (lane & 15));
-                    acc = mfma_f64(av, W2[j][lane & 15], acc);
-                }
+                for (int st = 0; st < NB / 4; ++st) acc = mfma_f64(av[st], W2[4 * st + (lane >> 4)][lane & 15], acc);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int row = rb + c_row64(lane, q);
@@ -840,7 +968,7 @@ size_t eig_work_bytes(int nmat, int m) {
     // node table + tasks + per-node scratch (at most m / 16 nodes per pass per matrix)
     const int max_nodes = nmat * (m / 16 + 2);
     return (size_t)max_nodes * node_scratch_bytes() + (size_t)max_nodes * 4 * sizeof(Node) * 64 +
-           (size_t)max_nodes * 2 * sizeof(GemmTask) * 64 + 256 * 64 * 3 + 256 * 3 * 8 + 65536;
+           (size_t)max_nodes * 2 * sizeof(GemmTask) * 64 + (size_t)nmat * tri_xwords(m) * 8 + 65536;
 }
 
 hipError_t launch_eig(const EigProblem& p, void* work, size_t work_bytes, hipStream_t st) {
@@ -848,8 +976,7 @@ hipError_t launch_eig(const EigProblem& p, void* work, size_t work_bytes, hipStr
     if (m < 1 || m > MAXN || nmat < 1 || nmat > 3) return hipErrorInvalidValue;
     if (work_bytes < eig_work_bytes(nmat, m)) return hipErrorInvalidValue;
     char* w = (char*)work;
-    unsigned* bar = (unsigned*)w;            w += 256 * 64 * 3;
-    double* part = (double*)w;               w += 256 * 3 * sizeof(double);
+    uint64_t* xbase = (uint64_t*)w;          w += ((size_t)nmat * tri_xwords(m) * 8 + 255) & ~(size_t)255;
     hipError_t e;
     // ---- 1. tridiagonalization
     {
@@ -858,31 +985,36 @@ hipError_t launch_eig(const EigProblem& p, void* work, size_t work_bytes, hipStr
         if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
         if ((e = hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess) return e;
         const int mr = (m + 63) & ~63;
-        int cpb = (int)((maxsh - 4096 - (int)mr * 8) / ((size_t)mr * 8));
+        int cpb = (int)((maxsh - 8192 - (int)mr * 8) / ((size_t)mr * 8));
         cpb = std::max(1, std::min(cpb, CMAX));
         const int bpm = (m + cpb - 1) / cpb;
         const size_t shbytes = (size_t)(cpb + 1) * mr * 8;
+        if (bpm > ncu || bpm > 256) return hipErrorInvalidConfiguration;
         if ((e = hipFuncSetAttribute((const void*)k_tridiag, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)shbytes)) != hipSuccess) return e;
-        int per_launch = std::max(1, std::min(nmat, ncu / bpm));
-        if (bpm > ncu) return hipErrorInvalidConfiguration;
+        const size_t nwords = (size_t)nmat * tri_xwords(m);
+        hipLaunchKernelGGL(k_zero_words, dim3((unsigned)std::min<size_t>(1024, (nwords + 255) / 256)), dim3(256), 0, st,
+                           xbase, nwords);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        const int per_launch = std::max(1, std::min(std::min(nmat, ncu / bpm), TRI_MAXMAT));
         for (int m0 = 0; m0 < nmat; m0 += per_launch) {
             const int cnt = std::min(per_launch, nmat - m0);
             TriArgs ta{};
             for (int i = 0; i < cnt; ++i) {
-                ta.G[i] = p.G[m0 + i];
-                ta.d[i] = p.d[m0 + i];
-                ta.e[i] = p.e[m0 + i];
-                ta.tau[i] = p.tau[m0 + i];
-                ta.p[i] = p.pbuf[m0 + i];
-                ta.part[i] = part + 256 * i;
+                TriMat& M = ta.mat[i];
+                M.G = p.G[m0 + i];
+                M.d = p.d[m0 + i];
+                M.e = p.e[m0 + i];
+                M.tau = p.tau[m0 + i];
+                M.x = xbase + (size_t)(m0 + i) * tri_xwords(m);
+                M.m = m;
+                M.ld = ld;
+                M.cpb = cpb;
+                M.bpm = bpm;
+                M.blk0 = i * bpm;
             }
-            ta.bar = bar;
-            ta.m = m;
-            ta.ld = ld;
-            ta.cpb = cpb;
-            ta.bpm = bpm;
-            if ((e = hipMemsetAsync(bar, 0, 256 * 64 * 3, st)) != hipSuccess) return e;
+            ta.nmat = cnt;
+            ta.abort_w = p.abort_w;
             void* args[] = {&ta};
             if ((e = hipLaunchCooperativeKernel((const void*)k_tridiag, dim3(cnt * bpm), dim3(256), args, shbytes,
                                                 st)) != hipSuccess)
@@ -994,29 +1126,38 @@ hipError_t launch_dc_modify(double* const d[3], const double* const e[3], int nm
 
 size_t backtransform_work_doubles(int m) { return (size_t)((m + NB - 1) / NB + 1) * NB * NB; }
 
-hipError_t launch_backtransform(int m, int ld, const double* Hv, const double* tau, const double* Q, const int* order,
-                                int r, double* out, int ldo, int nrows, double* Tw, hipStream_t st) {
-    if (r < 1) return hipSuccess;
-    if (m > MAXN || nrows < m || ldo < nrows) return hipErrorInvalidValue;
+hipError_t launch_backtransform(const BtJob* jobs, int njobs, hipStream_t st) {
     hipError_t e;
-    const int mr = (m + 63) & ~63;
-    const size_t sh = (size_t)16 * mr * sizeof(double);
-    const bool xl = sh <= 128 * 1024;
-    const int nblk = m >= 3 ? (m - 2 + NB - 1) / NB : 0;
-    if (nblk > 0) {
-        hipLaunchKernelGGL(k_larft, dim3((unsigned)nblk), dim3(256), 0, st, m, ld, Hv, tau, Tw);
+    for (int j0 = 0; j0 < njobs; j0 += BT_MAXJOB) {
+        const int cnt = std::min(BT_MAXJOB, njobs - j0);
+        BtJobs J{};
+        int mmax = 0, rmax = 0;
+        for (int i = 0; i < cnt; ++i) {
+            const BtJob& jb = jobs[j0 + i];
+            if (jb.m < 1 || jb.m > MAXN || jb.nrows < jb.m || jb.ldo < jb.nrows || jb.ld < jb.m) return hipErrorInvalidValue;
+            J.job[i] = jb;
+            mmax = std::max(mmax, jb.m);
+            rmax = std::max(rmax, jb.r);
+        }
+        if (rmax < 1) continue;
+        const int nblk = mmax >= 3 ? (mmax - 2 + NB - 1) / NB : 0;
+        if (nblk > 0) {
+            hipLaunchKernelGGL(k_larft, dim3((unsigned)nblk, (unsigned)cnt), dim3(256), 0, st, J);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        const int mr = (mmax + 63) & ~63;
+        const size_t sh = (size_t)16 * mr * sizeof(double);
+        const dim3 grid((unsigned)((rmax + 15) / 16), (unsigned)cnt);
+        if (sh <= 128 * 1024) {
+            if ((e = hipFuncSetAttribute((const void*)k_apply_wy<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)sh)) != hipSuccess)
+                return e;
+            hipLaunchKernelGGL((k_apply_wy<true>), grid, dim3(256), sh, st, J);
+        } else {
+            hipLaunchKernelGGL((k_apply_wy<false>), grid, dim3(256), 0, st, J);
+        }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if (xl) {
-        if ((e = hipFuncSetAttribute((const void*)k_apply_wy<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)sh)) != hipSuccess)
-            return e;
-        hipLaunchKernelGGL((k_apply_wy<true>), dim3((unsigned)((r + 15) / 16)), dim3(256), sh, st, m, ld, Hv, Tw, Q,
-                           order, r, out, ldo, nrows);
-    } else {
-        hipLaunchKernelGGL((k_apply_wy<false>), dim3((unsigned)((r + 15) / 16)), dim3(256), 0, st, m, ld, Hv, Tw, Q,
-                           order, r, out, ldo, nrows);
-    }
-    return hipGetLastError();
+    return hipSuccess;
 }
 

@@ -60,15 +60,34 @@ struct EigProblem {
     double* d[3];        // m
     double* e[3];        // m
     double* tau[3];      // m
-    double* pbuf[3];     // m
+    int* abort_w;        // device int, set to 1 when a cross-workgroup wait of the
+                         // tridiagonalization ran out (the results are then invalid)
 };
 size_t eig_work_bytes(int nmat, int m);
 hipError_t launch_eig(const EigProblem& p, void* work, size_t work_bytes, hipStream_t st);
-// out[:, k] = H Q[:, order[k]] for k < r (order NULL: identity), rows >= m zero up to nrows.
-// Tw: workspace of backtransform_work_doubles(m) doubles (the compact-WY T factors).
+// Back-transformation jobs: out[:, k] = H Q[:, order[k]] for k < r (order NULL:
+// identity), H = H_0 ... H_{m-3} from the reflectors left in Hv by launch_eig,
+// rows m .. nrows-1 of out set to zero.  r = min(*r_dev, r) when r_dev is set
+// (the rank is then known only on the device; r is the capacity).
+// Tw: backtransform_work_doubles(m) doubles per job (the compact-WY T factors).
+struct BtJob {
+    int m, ld;
+    const double* Hv;
+    const double* tau;
+    const double* Q;
+    const int* order;
+    int r;
+    const int* r_dev;
+    double* out;
+    int ldo, nrows;
+    double* Tw;
+};
+constexpr int BT_MAXJOB = 16;
+struct BtJobs {
+    BtJob job[BT_MAXJOB];
+};
 size_t backtransform_work_doubles(int m);
-hipError_t launch_backtransform(int m, int ld, const double* Hv, const double* tau, const double* Q, const int* order,
-                                int r, double* out, int ldo, int nrows, double* Tw, hipStream_t st);
+hipError_t launch_backtransform(const BtJob* jobs, int njobs, hipStream_t st);
 
 // a4/a5: norms finalize, sort, tails, ranks (per mode).
 struct TruncArgs {
