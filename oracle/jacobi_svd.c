@@ -95,12 +95,20 @@ static void apply_q(int64_t N, int64_t m, const double* Y, const double* tau,
 
 /* One-sided Jacobi on the columns of B (m x m, ld = m); J (m x m) accumulates
  * the rotations starting from the identity.  Returns sweeps used, or -1 if the
- * cap was hit before convergence. */
+ * cap was hit before convergence.
+ * A pair (p, q) is orthogonal enough when |b_p . b_q| <= m u |b_p| |b_q|, or
+ * when |b_p . b_q| <= (2 m u |B|_F)^2: below that floor a rotation cannot move
+ * any singular value above about 2 m u |B|_F, the part of the spectrum that FP64
+ * data determines at all; without the floor, pairs of columns that are pure
+ * rounding noise can keep failing the relative test forever. */
 static int jacobi_columns(int64_t m, double* B, double* J, int max_sweeps) {
     memset(J, 0, sizeof(double) * (size_t)m * (size_t)m);
     for (int64_t i = 0; i < m; ++i) J[IDX(i, i, m)] = 1.0;
     if (m < 2) return 0;
     const double tol = (double)m * ldexp(1.0, -53);
+    double fro2 = 0.0;                  /* |B|_F^2 (rotations preserve it) */
+    for (int64_t j = 0; j < m; ++j) fro2 += dot(B + IDX(0, j, m), B + IDX(0, j, m), m);
+    const double floor_g = 4.0 * tol * tol * fro2;
     int64_t slots = (m % 2 == 0) ? m : m + 1;     /* odd m: one dummy slot */
     int64_t* ring = (int64_t*)malloc(sizeof(int64_t) * (size_t)slots);
     if (!ring) return -2;
@@ -121,7 +129,7 @@ static int jacobi_columns(int64_t m, double* B, double* J, int max_sweeps) {
                 double* bq = B + IDX(0, q, m);
                 double a = dot(bp, bp, m), b = dot(bq, bq, m), g = dot(bp, bq, m);
                 if (a == 0.0 || b == 0.0) continue;
-                if (fabs(g) <= tol * sqrt(a) * sqrt(b)) continue;
+                if (fabs(g) <= tol * sqrt(a) * sqrt(b) || fabs(g) <= floor_g) continue;
                 /* rotation [bp bq] <- [bp bq] [[c, s], [-s, c]] zeroing bp.bq */
                 double zeta = (b - a) / (2.0 * g);
                 double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
