@@ -48,7 +48,8 @@ typedef enum {
     RHOSVD_ERR_DEVICE = -4,     /* a HIP runtime call failed */
     RHOSVD_ERR_NOCONV = -5,     /* the eigensolver hit its sweep cap */
     RHOSVD_ERR_STATE = -6,      /* rhosvd_get/inspection without a successful rhosvd_reduce */
-    RHOSVD_ERR_UNSUPPORTED = -7 /* size or option outside what this build supports */
+    RHOSVD_ERR_UNSUPPORTED = -7, /* size or option outside what this build supports */
+    RHOSVD_ERR_CAPACITY = -8     /* batched: a rank exceeds cap_rank, or r1 r2 r3 exceeds cap_beta */
 } rhosvd_status;
 
 /* Arithmetic of the projection and core contractions.  The column norms, the
@@ -135,6 +136,58 @@ rhosvd_status rhosvd_get(rhosvd_handle h, double* Z1, double* Z2, double* Z3,
 rhosvd_status rhosvd_get_xi(rhosvd_handle h, double* xip);
 rhosvd_status rhosvd_get_spectrum(rhosvd_handle h, int32_t l, double* sigma_all);
 rhosvd_status rhosvd_get_v(rhosvd_handle h, int32_t l, double* V);
+
+/*
+ * Batched reductions: many independent problems of uneven n and R in one pass.
+ * The reductions of a batch are the same as rhosvd_reduce + rhosvd_get would
+ * compute one by one (same options and precision as the handle), but no call
+ * waits for the host: every phase is one launch over the whole batch, the
+ * ranks stay on the device, and the Khatri-Rao cores of all problems run as one
+ * persistent launch.  The first call with a given descriptor list (the bytes
+ * of the array) lays out the workspace, uploads its tables and records the pass
+ * into a HIP graph; later calls with an identical list replay that graph with
+ * one launch on the handle's stream.  A new list replaces the cached plan
+ * (synchronizing with the stream first).
+ *
+ * Per problem (all pointers DEVICE pointers; caller-owned; valid until the
+ * stream has finished the call):
+ *   n, R       : 1 <= n, R; min(n, R) <= 2048
+ *   U1..U3, xi : inputs as for rhosvd_reduce
+ *   eps        : > 0
+ *   cap_rank   : >= 1, the columns available in each Z output; ranks above it
+ *                give RHOSVD_ERR_CAPACITY for that problem (Z, beta not written)
+ *   cap_beta   : doubles available in beta (>= 1 when beta is set)
+ *   Z1..Z3     : n x cap_rank outputs (ld n, first r_l columns written), or all NULL
+ *   beta       : r1*r2*r3 output (Fortran order), or NULL (ranks and Z only)
+ *   result     : int32[8]: r1, r2, r3, status (rhosvd_status of this problem:
+ *                OK, ERR_NONFINITE, ERR_CAPACITY, or ERR_DEVICE when an
+ *                eigensolver wait ran out), dropped terms, 3 reserved
+ *   reserved0  : must be zero
+ * Returns (host): OK once the pass is enqueued (per-problem outcomes are in
+ * result), ARG for a bad descriptor (message names the problem), UNSUPPORTED,
+ * ALLOC, DEVICE.  A handle serves one batch at a time.
+ */
+typedef struct {
+    int64_t n, R;
+    const double* U1;
+    const double* U2;
+    const double* U3;
+    const double* xi;
+    double eps;
+    int32_t cap_rank;
+    int32_t reserved0;
+    int64_t cap_beta;
+    double* Z1;
+    double* Z2;
+    double* Z3;
+    double* beta;
+    int32_t* result;
+} rhosvd_problem;
+
+rhosvd_status rhosvd_reduce_batched(rhosvd_handle h, int32_t count, const rhosvd_problem* problems);
+
+/* 1 when the last batched call ran as a graph replay, 0 when it ran eagerly. */
+int32_t rhosvd_batch_uses_graph(rhosvd_handle h);
 
 /* Phase times in milliseconds of the last rhosvd_reduce / rhosvd_get when the
  * handle was created with profile != 0 (synchronizes with the stream):

@@ -7,7 +7,6 @@
 #include <algorithm>
 #include <string>
 
-#include "../../include/rhosvd.h"
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -50,8 +49,11 @@ struct rhosvd_ctx {
     double* ee[3] = {};
     double* htau[3] = {};                // Householder scalars
     double* Tw[3] = {};                  // compact-WY factors of the back-transformation
-    void* eigw = nullptr;
-    size_t eigw_bytes = 0;
+    // eigensolver plans (Gram matrices; R < n re-orthonormalization) and their work memory
+    EigPlan* plan[2] = {nullptr, nullptr};
+    size_t plan_key[2][4] = {};
+    void* plan_w[2] = {nullptr, nullptr};
+    size_t plan_wbytes[2] = {0, 0};
     double* gram_part = nullptr;
     int gram_splits = 1;
     double* anorm_part = nullptr;
@@ -83,6 +85,8 @@ struct rhosvd_ctx {
     int r_pad[3] = {0, 0, 0};
     double xi_norm = 0, a_norm = 0, tau = 0;   // report values
     int sweeps = 0, dropped = 0;
+    // batched reductions: the plan of the last descriptor list
+    BatchPlan* batch = nullptr;
     // profiling
     hipEvent_t ev[NEV] = {};
     bool ev_ok = false;
@@ -161,7 +165,6 @@ size_t carve_all(rhosvd_ctx* h, char* base) {
     h->anorm_part = c.take<double>(h->anorm_ntiles);
     h->ranks_dev = c.take<int>(16);
     h->scal = c.take<double>(8);
-    h->eigw = (void*)c.take<char>(h->eigw_bytes);
     if (h->rside) {
         for (int l = 0; l < 3; ++l) {
             h->Wr[l] = c.take<double>((size_t)Rp * zp);
@@ -201,8 +204,6 @@ rhosvd_status layout(rhosvd_ctx* h, int64_t n, int64_t R) {
     h->gram_splits = splits;
     const int64_t rt = Rp / 64;
     h->anorm_ntiles = rt * (rt + 1) / 2;
-    h->eigw_bytes = eig_work_bytes(3, (int)h->m);
-    if (h->rside) h->eigw_bytes = std::max(h->eigw_bytes, eig_work_bytes(3, (int)h->zr_pad));
     const size_t need = carve_all(h, nullptr);
     if (need > h->ws_bytes) {
         if (h->ws) { hipStreamSynchronize(h->stream); hipFree(h->ws); h->ws = nullptr; h->ws_bytes = 0; }
@@ -215,6 +216,39 @@ rhosvd_status layout(rhosvd_ctx* h, int64_t n, int64_t R) {
     }
     carve_all(h, h->ws);
     h->vprec = h->opt.precision;
+    return RHOSVD_OK;
+}
+
+// (Re)build eigensolver plan `which` when the matrix list changed; the plan's
+// tables are uploaded once and reused by every later call with the same layout.
+rhosvd_status ensure_plan(rhosvd_ctx* h, int which, const EigMat* mats, int nmat) {
+    const size_t key[4] = {(size_t)mats[0].m, (size_t)mats[0].ld, (size_t)mats[0].G, (size_t)nmat};
+    if (h->plan[which] && memcmp(key, h->plan_key[which], sizeof(key)) == 0) return RHOSVD_OK;
+    if (h->plan[which]) {
+        hipStreamSynchronize(h->stream);   // its tables may still be in use
+        eig_plan_destroy(h->plan[which]);
+        h->plan[which] = nullptr;
+    }
+    size_t need = 0;
+    EigPlan* P = eig_plan_create(mats, nmat, &need);
+    if (!P) return fail(h, RHOSVD_ERR_UNSUPPORTED, "eigensolver plan: matrix sizes not supported on this device");
+    if (need > h->plan_wbytes[which]) {
+        if (h->plan_w[which]) { hipStreamSynchronize(h->stream); hipFree(h->plan_w[which]); h->plan_w[which] = nullptr; }
+        h->plan_wbytes[which] = 0;
+        if (hipMalloc(&h->plan_w[which], need) != hipSuccess) {
+            h->plan_w[which] = nullptr;
+            eig_plan_destroy(P);
+            return fail(h, RHOSVD_ERR_ALLOC, "eigensolver work allocation failed");
+        }
+        h->plan_wbytes[which] = need;
+    }
+    hipError_t e = eig_plan_bind(P, h->plan_w[which], h->stream);
+    if (e != hipSuccess) {
+        eig_plan_destroy(P);
+        return fail(h, RHOSVD_ERR_DEVICE, std::string("eigensolver plan upload: ") + hipGetErrorString(e));
+    }
+    h->plan[which] = P;
+    memcpy(h->plan_key[which], key, sizeof(key));
     return RHOSVD_OK;
 }
 
@@ -242,16 +276,12 @@ rhosvd_status form_z_rside(rhosvd_ctx* h) {
         CK(h, launch_gemm64(true, true, rp, rp, np, h->Zraw[l], np, h->Zraw[l], np, h->M2[l], zp, 1.0, st));
         CK(h, launch_pad_identity(r, rmp, (int)zp, h->M2[l], st));
     }
-    EigProblem ep{};
-    for (int l = 0; l < 3; ++l) {
-        ep.G[l] = h->M2[l]; ep.lam[l] = h->lam2[l]; ep.Q[l] = h->P2[l]; ep.Qn[l] = h->Qn2[l];
-        ep.M[l] = h->Mg2[l]; ep.d[l] = h->dd2[l]; ep.e[l] = h->ee2[l]; ep.tau[l] = h->tau2[l];
-    }
-    ep.nmat = 3;
-    ep.abort_w = h->flags + 2;
-    ep.m = rmp;
-    ep.ld = (int)zp;
-    CK(h, launch_eig(ep, h->eigw, h->eigw_bytes, st));
+    EigMat em[3];
+    for (int l = 0; l < 3; ++l)
+        em[l] = EigMat{h->M2[l], h->lam2[l], h->P2[l], h->Qn2[l], h->Mg2[l], h->dd2[l], h->ee2[l], h->tau2[l], rmp, (int)zp};
+    rhosvd_status ps = ensure_plan(h, 1, em, 3);
+    if (ps != RHOSVD_OK) return ps;
+    CK(h, eig_plan_enqueue(h->plan[1], h->flags + 2, st));
     // P = H P2 (all rmp columns); S = P diag(mu^-1/2) P^T ; Z = Zraw S
     for (int l = 0; l < 3; ++l)
         jobs[l] = BtJob{rmp, (int)zp, h->M2[l], h->tau2[l], h->P2[l], nullptr, rmp, nullptr, h->Pf[l], (int)zp, rmp,
@@ -310,6 +340,11 @@ rhosvd_status rhosvd_destroy(rhosvd_handle h) {
     if (!h) return RHOSVD_ERR_ARG;
     hipStreamSynchronize(h->stream);
     if (h->ws) hipFree(h->ws);
+    if (h->batch) batch_plan_destroy(h->batch);
+    for (int i = 0; i < 2; ++i) {
+        if (h->plan[i]) eig_plan_destroy(h->plan[i]);
+        if (h->plan_w[i]) hipFree(h->plan_w[i]);
+    }
     if (h->host) hipHostFree(h->host);
     for (int i = 0; i < NEV; ++i)
         if (h->ev[i]) hipEventDestroy(h->ev[i]);
@@ -353,16 +388,13 @@ rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R, const double*
     if (!h->rside)
         CK(h, launch_gram_nt(h->n_pad, h->R_pad, h->Ut, h->G, h->gram_part, h->gram_splits, st));
     mark(h, 3);
-    EigProblem ep{};
-    for (int l = 0; l < 3; ++l) {
-        ep.G[l] = h->G[l]; ep.lam[l] = h->lam[l]; ep.Q[l] = h->W[l]; ep.Qn[l] = h->Qn[l];
-        ep.M[l] = h->Mg[l]; ep.d[l] = h->dd[l]; ep.e[l] = h->ee[l]; ep.tau[l] = h->htau[l];
-    }
-    ep.nmat = 3;
-    ep.abort_w = h->flags + 2;
-    ep.m = (int)h->m;
-    ep.ld = (int)h->m_pad;
-    CK(h, launch_eig(ep, h->eigw, h->eigw_bytes, st));
+    EigMat em[3];
+    for (int l = 0; l < 3; ++l)
+        em[l] = EigMat{h->G[l], h->lam[l], h->W[l], h->Qn[l], h->Mg[l], h->dd[l], h->ee[l], h->htau[l], (int)h->m,
+                       (int)h->m_pad};
+    s = ensure_plan(h, 0, em, 3);
+    if (s != RHOSVD_OK) return s;
+    CK(h, eig_plan_enqueue(h->plan[0], h->flags + 2, st));
     mark(h, 4);
     TruncArgs ta{};
     for (int l = 0; l < 3; ++l) {
@@ -533,6 +565,29 @@ rhosvd_status rhosvd_get_v(rhosvd_handle h, int32_t l, double* V) {
     }
     return RHOSVD_OK;
 }
+
+rhosvd_status rhosvd_reduce_batched(rhosvd_handle h, int32_t count, const rhosvd_problem* problems) {
+    if (!h) return RHOSVD_ERR_ARG;
+    h->err.clear();
+    std::string msg;
+    const int vs = batch_validate(problems, count, msg);
+    if (vs != RHOSVD_OK) return fail(h, (rhosvd_status)vs, msg);
+    if (!batch_plan_matches(h->batch, problems, count, h->opt.precision)) {
+        // earlier work on the stream may still use the old plan's memory
+        CK(h, hipStreamSynchronize(h->stream));
+        if (h->batch) {
+            batch_plan_destroy(h->batch);
+            h->batch = nullptr;
+        }
+        std::string err;
+        h->batch = batch_plan_create(problems, count, h->opt.precision, err);
+        if (!h->batch) return fail(h, RHOSVD_ERR_ALLOC, err);
+    }
+    CK(h, batch_plan_run(h->batch, h->stream));
+    return RHOSVD_OK;
+}
+
+int32_t rhosvd_batch_uses_graph(rhosvd_handle h) { return (h && batch_plan_uses_graph(h->batch)) ? 1 : 0; }
 
 double rhosvd_phase_ms(rhosvd_handle h, int32_t phase) {
     if (!h || !h->opt.profile || !h->ev_ok || phase < 0 || phase >= NPHASE) return -1.0;

@@ -52,19 +52,15 @@ struct MF<float> {
 };
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_core_std(int r1, int r2, int r3, int ld1, int ld2, int ld3,
-                                                  int64_t Kp, const T* __restrict__ V1,
-                                                  const T* __restrict__ V2, const T* __restrict__ V3,
-                                                  const double* __restrict__ xip, double* __restrict__ beta,
-                                                  int MT, int N2T, int N3T, int64_t per) {
+__device__ void core_tile_std(int r1, int r2, int r3, int ld1, int ld2, int ld3, int64_t Kp,
+                              const T* __restrict__ V1, const T* __restrict__ V2, const T* __restrict__ V3,
+                              const double* __restrict__ xip, double* __restrict__ beta, int N2T, int N3T,
+                              int64_t tile) {
     constexpr int TM = 64, KC = 16;
     typedef typename MF<T>::acc_t acc_t;
     __shared__ T sA[2][KC][TM];
     __shared__ T s2[2][KC][TN2];
     __shared__ T s3[2][KC][TN3];
-    const int64_t ntile = (int64_t)MT * N2T * N3T;
-    const int64_t tile = xcd_tile(blockIdx.x, per);
-    if (tile >= ntile) return;
     const int NT = N2T * N3T;
     const int mt = (int)(tile / NT), nt = (int)(tile % NT);
     const int n3t = nt / N2T, n2t = nt % N2T;
@@ -131,6 +127,17 @@ __global__ __launch_bounds__(256) void k_core_std(int r1, int r2, int r3, int ld
                            acc[f][g][i]);
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_core_std(int r1, int r2, int r3, int ld1, int ld2, int ld3,
+                                                  int64_t Kp, const T* __restrict__ V1,
+                                                  const T* __restrict__ V2, const T* __restrict__ V3,
+                                                  const double* __restrict__ xip, double* __restrict__ beta,
+                                                  int MT, int N2T, int N3T, int64_t per) {
+    const int64_t tile = xcd_tile(blockIdx.x, per);
+    if (tile >= (int64_t)MT * N2T * N3T) return;
+    core_tile_std<T>(r1, r2, r3, ld1, ld2, ld3, Kp, V1, V2, V3, xip, beta, N2T, N3T, tile);
+}
+
 // ---------------------------------------------------------------------------
 // BF16x3 variant, TM = 128, KC = 32.  V_l are FP32.
 // ---------------------------------------------------------------------------
@@ -141,18 +148,14 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
     lo = (__bf16)(x - (float)hi);
 }
 
-__global__ __launch_bounds__(256) void k_core_bf16x3(int r1, int r2, int r3, int ld1, int ld2, int ld3,
-                                                     int64_t Kp, const float* __restrict__ V1,
-                                                     const float* __restrict__ V2, const float* __restrict__ V3,
-                                                     const double* __restrict__ xip, double* __restrict__ beta,
-                                                     int MT, int N2T, int N3T, int64_t per) {
+__device__ void core_tile_bf16x3(int r1, int r2, int r3, int ld1, int ld2, int ld3, int64_t Kp,
+                                 const float* __restrict__ V1, const float* __restrict__ V2,
+                                 const float* __restrict__ V3, const double* __restrict__ xip,
+                                 double* __restrict__ beta, int N2T, int N3T, int64_t tile) {
     __shared__ __attribute__((aligned(16))) __bf16 sAh[2][BTM * BLDA];
     __shared__ __attribute__((aligned(16))) __bf16 sAl[2][BTM * BLDA];
     __shared__ float s2[2][BKC][TN2];
     __shared__ float s3[2][BKC][TN3];
-    const int64_t ntile = (int64_t)MT * N2T * N3T;
-    const int64_t tile = xcd_tile(blockIdx.x, per);
-    if (tile >= ntile) return;
     const int NT = N2T * N3T;
     const int mt = (int)(tile / NT), nt = (int)(tile % NT);
     const int n3t = nt / N2T, n2t = nt % N2T;
@@ -244,6 +247,72 @@ __global__ __launch_bounds__(256) void k_core_bf16x3(int r1, int r2, int r3, int
                            acc[f][g][i]);
 }
 
+__global__ __launch_bounds__(256) void k_core_bf16x3(int r1, int r2, int r3, int ld1, int ld2, int ld3,
+                                                     int64_t Kp, const float* __restrict__ V1,
+                                                     const float* __restrict__ V2, const float* __restrict__ V3,
+                                                     const double* __restrict__ xip, double* __restrict__ beta,
+                                                     int MT, int N2T, int N3T, int64_t per) {
+    const int64_t tile = xcd_tile(blockIdx.x, per);
+    if (tile >= (int64_t)MT * N2T * N3T) return;
+    core_tile_bf16x3(r1, r2, r3, ld1, ld2, ld3, Kp, V1, V2, V3, xip, beta, N2T, N3T, tile);
+}
+
+// ---------------------------------------------------------------------------
+// Batched cores: the plan kernel counts each eligible problem's tiles (status 0,
+// beta requested, all ranks >= 1) and writes the prefix sums; the persistent
+// kernel's workgroups then take tiles from a shared counter until none is left.
+// work[0]: counter, work[1]: total tiles, work[2 .. np+2]: prefix.
+// ---------------------------------------------------------------------------
+__global__ void k_core_plan_b(const BProb* __restrict__ P, int np, int tm, int64_t* __restrict__ work) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int64_t acc = 0;
+    for (int p = 0; p < np; ++p) {
+        const BProb& q = P[p];
+        work[2 + p] = acc;
+        const int r1 = q.ranks[0], r2 = q.ranks[1], r3 = q.ranks[2];
+        if (q.ranks[3] == 0 && q.beta && r1 > 0 && r2 > 0 && r3 > 0)
+            acc += ceil_div(r1, tm) * ceil_div(r2, TN2) * ceil_div(r3, TN3);
+    }
+    work[2 + np] = acc;
+    work[1] = acc;
+    work[0] = 0;
+}
+
+template <int PREC>
+__global__ __launch_bounds__(256) void k_core_persist_b(const BProb* __restrict__ P, int np,
+                                                        int64_t* __restrict__ work) {
+    __shared__ int64_t s_tile;
+    const int64_t total = work[1];
+    const int64_t* pre = work + 2;
+    for (;;) {
+        if (threadIdx.x == 0)
+            s_tile = (int64_t)atomicAdd((unsigned long long*)&work[0], 1ull);
+        __syncthreads();
+        const int64_t tile = s_tile;
+        __syncthreads();
+        if (tile >= total) break;
+        int lo = 0, hi = np;   // largest p with pre[p] <= tile
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (pre[mid] <= tile) lo = mid;
+            else hi = mid;
+        }
+        const BProb& q = P[lo];
+        const int r1 = q.ranks[0], r2 = q.ranks[1], r3 = q.ranks[2];
+        const int N2T = (int)ceil_div(r2, TN2), N3T = (int)ceil_div(r3, TN3);
+        const int64_t local = tile - pre[lo];
+        if (PREC == 0)
+            core_tile_std<double>(r1, r2, r3, q.rcap_pad, q.rcap_pad, q.rcap_pad, q.R_pad, (const double*)q.V[0],
+                                  (const double*)q.V[1], (const double*)q.V[2], q.xip, q.beta, N2T, N3T, local);
+        else if (PREC == 1)
+            core_tile_std<float>(r1, r2, r3, q.rcap_pad, q.rcap_pad, q.rcap_pad, q.R_pad, (const float*)q.V[0],
+                                 (const float*)q.V[1], (const float*)q.V[2], q.xip, q.beta, N2T, N3T, local);
+        else
+            core_tile_bf16x3(r1, r2, r3, q.rcap_pad, q.rcap_pad, q.rcap_pad, q.R_pad, (const float*)q.V[0],
+                             (const float*)q.V[1], (const float*)q.V[2], q.xip, q.beta, N2T, N3T, local);
+    }
+}
+
 }  // namespace
 
 hipError_t launch_core(const CoreArgs& a, hipStream_t st) {
@@ -271,4 +340,25 @@ hipError_t launch_core(const CoreArgs& a, hipStream_t st) {
                            (const float*)a.V[2], a.xip, a.beta, MT, N2T, N3T, per);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_core_b(const BProb* P, int np, int prec, int64_t* work, int grid, hipStream_t st) {
+    if (np < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_core_plan_b, dim3(1), dim3(64), 0, st, P, np, prec == 2 ? BTM : 64, work);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (prec == 0) hipLaunchKernelGGL(k_core_persist_b<0>, dim3((unsigned)grid), dim3(256), 0, st, P, np, work);
+    else if (prec == 1) hipLaunchKernelGGL(k_core_persist_b<1>, dim3((unsigned)grid), dim3(256), 0, st, P, np, work);
+    else hipLaunchKernelGGL(k_core_persist_b<2>, dim3((unsigned)grid), dim3(256), 0, st, P, np, work);
+    return hipGetLastError();
+}
+
+int core_b_max_grid(int prec) {
+    int dev = 0, ncu = 0, occ = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 256;
+    const void* f = prec == 0 ? (const void*)k_core_persist_b<0>
+                              : (prec == 1 ? (const void*)k_core_persist_b<1> : (const void*)k_core_persist_b<2>);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, 256, 0) != hipSuccess || occ < 1) occ = 1;
+    return ncu * occ;
 }

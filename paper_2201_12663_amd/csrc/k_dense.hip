@@ -8,16 +8,11 @@
 // xi'_nu = xi_nu * s1 * s2 * s3; a term with xi = 0 or a zero column is dropped
 // (xi' = 0, normalized columns zero).  Padded rows/terms are written as zero.
 // ===========================================================================
-__global__ __launch_bounds__(256) void k_colnorm(int64_t n, int64_t R, int64_t n_pad, int64_t R_pad,
-                                                 const double* __restrict__ U0,
-                                                 const double* __restrict__ U1,
-                                                 const double* __restrict__ U2,
-                                                 const double* __restrict__ xi,
-                                                 double* __restrict__ T0, double* __restrict__ T1,
-                                                 double* __restrict__ T2, double* __restrict__ xip,
-                                                 int* __restrict__ flags) {
+__device__ void colnorm_term(int64_t n, int64_t R, int64_t n_pad, int64_t R_pad, const double* __restrict__ U0,
+                             const double* __restrict__ U1, const double* __restrict__ U2,
+                             const double* __restrict__ xi, double* __restrict__ T0, double* __restrict__ T1,
+                             double* __restrict__ T2, double* __restrict__ xip, int* __restrict__ flags, int64_t nu) {
     const int lane = threadIdx.x & 63;
-    const int64_t nu = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (nu >= R_pad) return;
     const double* U[3] = {U0, U1, U2};
     double* T[3] = {T0, T1, T2};
@@ -64,6 +59,18 @@ __global__ __launch_bounds__(256) void k_colnorm(int64_t n, int64_t R, int64_t n
         if (bad) atomicOr(&flags[0], 1);
         if (!keep) atomicAdd(&flags[1], 1);
     }
+}
+
+__global__ __launch_bounds__(256) void k_colnorm(int64_t n, int64_t R, int64_t n_pad, int64_t R_pad,
+                                                 const double* __restrict__ U0,
+                                                 const double* __restrict__ U1,
+                                                 const double* __restrict__ U2,
+                                                 const double* __restrict__ xi,
+                                                 double* __restrict__ T0, double* __restrict__ T1,
+                                                 double* __restrict__ T2, double* __restrict__ xip,
+                                                 int* __restrict__ flags) {
+    colnorm_term(n, R, n_pad, R_pad, U0, U1, U2, xi, T0, T1, T2, xip, flags,
+                 (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6));
 }
 
 hipError_t launch_colnorm(int64_t n, int64_t R, int64_t n_pad, int64_t R_pad,
@@ -146,23 +153,17 @@ __device__ __forceinline__ void zero_acc(d4_t acc[2][2]) {
 // mirrors the tile into the upper triangle.
 // grid: (tile pairs, splits, mode)
 // ===========================================================================
-__global__ __launch_bounds__(256) void k_gram(int64_t n_pad, int64_t R_pad, const double* __restrict__ T0,
-                                              const double* __restrict__ T1, const double* __restrict__ T2,
-                                              double* __restrict__ G0, double* __restrict__ G1,
-                                              double* __restrict__ G2, double* __restrict__ part, int splits) {
+__device__ void gram_tile(int64_t n_pad, int64_t R_pad, const double* __restrict__ T, double* __restrict__ G,
+                          double* __restrict__ part, int splits, int64_t t, int split, int mode) {
     __shared__ double sA[KC * LDS_STRIDE];
     __shared__ double sB[KC * LDS_STRIDE];
-    const int mode = blockIdx.z;
-    const double* T = mode == 0 ? T0 : (mode == 1 ? T1 : T2);
-    double* G = mode == 0 ? G0 : (mode == 1 ? G1 : G2);
     // lower-triangle tile (ti >= tj) from the linear index
-    const int64_t t = blockIdx.x;
     int64_t ti = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
     while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
     while (ti * (ti + 1) / 2 > t) --ti;
     const int64_t tj = t - ti * (ti + 1) / 2;
     const int64_t chunk = round_up(ceil_div(R_pad, splits), KC);
-    const int64_t k0 = blockIdx.y * chunk, k1 = (k0 + chunk < R_pad) ? k0 + chunk : R_pad;
+    const int64_t k0 = split * chunk, k1 = (k0 + chunk < R_pad) ? k0 + chunk : R_pad;
     d4_t acc[2][2];
     zero_acc(acc);
     if (k0 < k1)
@@ -184,7 +185,7 @@ __global__ __launch_bounds__(256) void k_gram(int64_t n_pad, int64_t R_pad, cons
                     G[c + r * n_pad] = v;
                 }
     } else {
-        double* P = part + ((int64_t)blockIdx.y * 3 + mode) * n_pad * n_pad;
+        double* P = part + ((int64_t)split * 3 + mode) * n_pad * n_pad;
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -196,6 +197,16 @@ __global__ __launch_bounds__(256) void k_gram(int64_t n_pad, int64_t R_pad, cons
                     P[r + c * n_pad] = acc[a][b][i];
                 }
     }
+}
+
+__global__ __launch_bounds__(256) void k_gram(int64_t n_pad, int64_t R_pad, const double* __restrict__ T0,
+                                              const double* __restrict__ T1, const double* __restrict__ T2,
+                                              double* __restrict__ G0, double* __restrict__ G1,
+                                              double* __restrict__ G2, double* __restrict__ part, int splits) {
+    const int mode = blockIdx.z;
+    const double* T = mode == 0 ? T0 : (mode == 1 ? T1 : T2);
+    double* G = mode == 0 ? G0 : (mode == 1 ? G1 : G2);
+    gram_tile(n_pad, R_pad, T, G, part, splits, blockIdx.x, blockIdx.y, mode);
 }
 
 __global__ void k_gram_reduce(int64_t n_pad, const double* __restrict__ part, int splits,
@@ -232,15 +243,13 @@ hipError_t launch_gram_nt(int64_t n_pad, int64_t R_pad, double* const Ut[3], dou
 // formed with FP64 MFMA, multiplied entrywise, weighted, and reduced to one
 // partial sum per tile (off-diagonal tiles count twice).
 // ===========================================================================
-__global__ __launch_bounds__(256) void k_anorm(int64_t n_pad, int64_t R_pad, const double* __restrict__ T0,
-                                               const double* __restrict__ T1, const double* __restrict__ T2,
-                                               const double* __restrict__ xip, double* __restrict__ part,
-                                               double* __restrict__ G0, double* __restrict__ G1,
-                                               double* __restrict__ G2) {
+__device__ void anorm_tile(int64_t n_pad, int64_t R_pad, const double* __restrict__ T0,
+                           const double* __restrict__ T1, const double* __restrict__ T2,
+                           const double* __restrict__ xip, double* __restrict__ part, double* __restrict__ G0,
+                           double* __restrict__ G1, double* __restrict__ G2, int64_t t) {
     __shared__ double sA[KC * LDS_STRIDE];
     __shared__ double sB[KC * LDS_STRIDE];
     __shared__ double red[4];
-    const int64_t t = blockIdx.x;
     int64_t ti = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
     while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
     while (ti * (ti + 1) / 2 > t) --ti;
@@ -293,6 +302,14 @@ __global__ __launch_bounds__(256) void k_anorm(int64_t n_pad, int64_t R_pad, con
     }
 }
 
+__global__ __launch_bounds__(256) void k_anorm(int64_t n_pad, int64_t R_pad, const double* __restrict__ T0,
+                                               const double* __restrict__ T1, const double* __restrict__ T2,
+                                               const double* __restrict__ xip, double* __restrict__ part,
+                                               double* __restrict__ G0, double* __restrict__ G1,
+                                               double* __restrict__ G2) {
+    anorm_tile(n_pad, R_pad, T0, T1, T2, xip, part, G0, G1, G2, blockIdx.x);
+}
+
 hipError_t launch_anorm_partials(int64_t n_pad, int64_t R_pad, double* const Ut[3],
                                  const double* xip, double* part, int64_t* ntiles, double* const Gr[3],
                                  hipStream_t st) {
@@ -308,12 +325,11 @@ hipError_t launch_anorm_partials(int64_t n_pad, int64_t R_pad, double* const Ut[
 // Z: n_pad x r_pad (ld n_pad) -> A(j,i) = Z[i + j*n_pad] (K-contiguous);
 // U~: n_pad x R_pad -> B(i,nu) = U~[i + nu*n_pad] (K-contiguous).
 // ===========================================================================
-__global__ __launch_bounds__(256) void k_project(int64_t n_pad, int64_t R_pad, int64_t r_pad,
-                                                 const double* __restrict__ Z, const double* __restrict__ T,
-                                                 double* __restrict__ out64, float* __restrict__ out32) {
+__device__ void project_tile(int64_t n_pad, int64_t R_pad, int64_t r_pad, const double* __restrict__ Z,
+                             const double* __restrict__ T, double* __restrict__ out64, float* __restrict__ out32,
+                             int64_t tm, int64_t tn) {
     __shared__ double sA[KC * LDS_STRIDE];
     __shared__ double sB[KC * LDS_STRIDE];
-    const int64_t tm = blockIdx.y, tn = blockIdx.x;
     d4_t acc[2][2];
     zero_acc(acc);
     tile64_f64<true, true>(Z, n_pad, T, n_pad, tm * T64, tn * T64, 0, n_pad, sA, sB, acc);
@@ -330,6 +346,12 @@ __global__ __launch_bounds__(256) void k_project(int64_t n_pad, int64_t R_pad, i
                 if (out64) out64[j + nu * r_pad] = acc[a][b][i];
                 else out32[j + nu * r_pad] = (float)acc[a][b][i];
             }
+}
+
+__global__ __launch_bounds__(256) void k_project(int64_t n_pad, int64_t R_pad, int64_t r_pad,
+                                                 const double* __restrict__ Z, const double* __restrict__ T,
+                                                 double* __restrict__ out64, float* __restrict__ out32) {
+    project_tile(n_pad, R_pad, r_pad, Z, T, out64, out32, blockIdx.y, blockIdx.x);
 }
 
 hipError_t launch_project(int64_t n_pad, int64_t R_pad, int64_t r_pad, const double* Z,
@@ -387,7 +409,8 @@ hipError_t launch_gemm64(bool a_kcontig, bool b_kcontig, int64_t M, int64_t N, i
 // Wr[:, k] = W[:, order[k]] / sigma_k for k < r; zero columns r..r_pad-1 (ld = m_pad)
 __global__ void k_gather_scaled(int m_pad, int r, int r_pad, const double* __restrict__ W,
                                 const int* __restrict__ order, const double* __restrict__ sigma,
-                                double* __restrict__ Wr) {
+                                double* __restrict__ Wr, const int* __restrict__ r_dev) {
+    if (r_dev) r = min(r, *r_dev);
     const int64_t tot = (int64_t)m_pad * r_pad;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
         const int i = (int)(e % m_pad), k = (int)(e / m_pad);
@@ -398,7 +421,8 @@ __global__ void k_gather_scaled(int m_pad, int r, int r_pad, const double* __res
 }
 
 // M (mp x mp, leading dimension ld): keep the leading r x r block, identity elsewhere
-__global__ void k_pad_identity(int r, int mp, int ld, double* __restrict__ M) {
+__global__ void k_pad_identity(int r, int mp, int ld, double* __restrict__ M, const int* __restrict__ r_dev) {
+    if (r_dev) r = min(r, *r_dev);
     const int64_t tot = (int64_t)mp * mp;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
         const int i = (int)(e % mp), j = (int)(e / mp);
@@ -440,12 +464,12 @@ __global__ __launch_bounds__(256) void k_sign_cols(int n, int n_pad, int r, doub
 }
 
 hipError_t launch_gather_scaled(int m_pad, int r, int r_pad, const double* W, const int* order,
-                                const double* sigma, double* Wr, hipStream_t st) {
-    hipLaunchKernelGGL(k_gather_scaled, dim3(512), dim3(256), 0, st, m_pad, r, r_pad, W, order, sigma, Wr);
+                                const double* sigma, double* Wr, hipStream_t st, const int* r_dev) {
+    hipLaunchKernelGGL(k_gather_scaled, dim3(512), dim3(256), 0, st, m_pad, r, r_pad, W, order, sigma, Wr, r_dev);
     return hipGetLastError();
 }
-hipError_t launch_pad_identity(int r, int mp, int ld, double* M, hipStream_t st) {
-    hipLaunchKernelGGL(k_pad_identity, dim3(256), dim3(256), 0, st, r, mp, ld, M);
+hipError_t launch_pad_identity(int r, int mp, int ld, double* M, hipStream_t st, const int* r_dev) {
+    hipLaunchKernelGGL(k_pad_identity, dim3(256), dim3(256), 0, st, r, mp, ld, M, r_dev);
     return hipGetLastError();
 }
 hipError_t launch_scale_cols_invsqrt(int mp, int ld, const double* mu, const double* P, double* out, hipStream_t st) {
@@ -455,5 +479,105 @@ hipError_t launch_scale_cols_invsqrt(int mp, int ld, const double* mu, const dou
 hipError_t launch_sign_cols(int n, int n_pad, int r, double* Z, hipStream_t st) {
     if (r < 1) return hipSuccess;
     hipLaunchKernelGGL(k_sign_cols, dim3((unsigned)ceil_div(r, 4)), dim3(256), 0, st, n, n_pad, r, Z);
+    return hipGetLastError();
+}
+
+// ===========================================================================
+// Batched variants: one launch covers every problem of a batch.  The grid is
+// flattened; pre[p] .. pre[p+1]-1 are problem p's blocks (pre[0] = 0).
+// ===========================================================================
+__device__ __forceinline__ int find_problem(const int64_t* __restrict__ pre, int np, int64_t b) {
+    int lo = 0, hi = np;   // largest p with pre[p] <= b
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pre[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_colnorm_b(const BProb* __restrict__ P, const int64_t* __restrict__ pre, int np) {
+    const int p = find_problem(pre, np, blockIdx.x);
+    const BProb& q = P[p];
+    const int64_t nu = (blockIdx.x - pre[p]) * 4 + (threadIdx.x >> 6);
+    colnorm_term(q.n, q.R, q.n_pad, q.R_pad, q.U[0], q.U[1], q.U[2], q.xi, q.Ut[0], q.Ut[1], q.Ut[2], q.xip, q.flags,
+                 nu);
+}
+
+__global__ __launch_bounds__(256) void k_anorm_b(const BProb* __restrict__ P, const int64_t* __restrict__ pre, int np) {
+    const int p = find_problem(pre, np, blockIdx.x);
+    const BProb& q = P[p];
+    anorm_tile(q.n_pad, q.R_pad, q.Ut[0], q.Ut[1], q.Ut[2], q.xip, q.anorm_part, q.rside ? q.G[0] : nullptr,
+               q.rside ? q.G[1] : nullptr, q.rside ? q.G[2] : nullptr, blockIdx.x - pre[p]);
+}
+
+__global__ __launch_bounds__(256) void k_gram_b(const BProb* __restrict__ P, const int64_t* __restrict__ pre, int np) {
+    const int p = find_problem(pre, np, blockIdx.x);
+    const BProb& q = P[p];
+    const int64_t nt = q.n_pad / T64, per = nt * (nt + 1) / 2;
+    const int64_t local = blockIdx.x - pre[p];
+    const int mode = (int)(local / per);
+    gram_tile(q.n_pad, q.R_pad, q.Ut[mode], q.G[mode], nullptr, 1, local % per, 0, mode);
+}
+
+// V_l = Z_l^T U~_l for the row tiles below round_up(min(r_l, rcap), 128)
+__global__ __launch_bounds__(256) void k_project_b(const BProb* __restrict__ P, const int64_t* __restrict__ pre, int np,
+                                                   int f32) {
+    const int p = find_problem(pre, np, blockIdx.x);
+    const BProb& q = P[p];
+    const int64_t TMc = q.rcap_pad / T64, TN = q.R_pad / T64;
+    const int64_t local = blockIdx.x - pre[p];
+    const int mode = (int)(local / (TMc * TN));
+    const int64_t rem = local % (TMc * TN);
+    const int64_t tm = rem / TN, tn = rem % TN;
+    const int r = min(q.ranks[mode], q.rcap);
+    if (q.ranks[3] != 0 || r < 1 || tm * T64 >= round_up(r, 128)) return;
+    project_tile(q.n_pad, q.R_pad, q.rcap_pad, q.Z[mode], q.Ut[mode], f32 ? nullptr : (double*)q.V[mode],
+                 f32 ? (float*)q.V[mode] : nullptr, tm, tn);
+}
+
+// sign rule on columns k < min(r, rcap) of Z_l, zero columns up to rcap_pad
+__global__ __launch_bounds__(256) void k_sign_b(const BProb* __restrict__ P, const int64_t* __restrict__ pre, int np) {
+    const int p = find_problem(pre, np, blockIdx.x);
+    const BProb& q = P[p];
+    const int64_t per = q.rcap_pad / 4;
+    const int64_t local = blockIdx.x - pre[p];
+    const int mode = (int)(local / per);
+    const int k = (int)((local % per) * 4 + (threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int r = min(q.ranks[mode], q.rcap);
+    double* z = q.Z[mode] + (int64_t)k * q.n_pad;
+    if (k >= r) {
+        for (int i = lane; i < q.n_pad; i += 64) z[i] = 0.0;
+        return;
+    }
+    double best = -1.0;
+    int bi = 0x7fffffff;
+    for (int i = lane; i < q.n; i += 64) {
+        double a = fabs(z[i]);
+        if (a > best) { best = a; bi = i; }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        double ob = __shfl_xor(best, o, 64);
+        int oi = __shfl_xor(bi, o, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    const double sgn = (z[bi] < 0.0) ? -1.0 : 1.0;
+    for (int i = lane; i < q.n_pad; i += 64) z[i] = (i < q.n) ? sgn * z[i] : 0.0;
+}
+
+hipError_t launch_batched_dense(int which, const BProb* P, const int64_t* pre, int np, int64_t nblocks, int f32,
+                                hipStream_t st) {
+    if (nblocks < 1) return hipSuccess;
+    const dim3 grid((unsigned)nblocks), blk(256);
+    switch (which) {
+        case BK_COLNORM: hipLaunchKernelGGL(k_colnorm_b, grid, blk, 0, st, P, pre, np); break;
+        case BK_ANORM: hipLaunchKernelGGL(k_anorm_b, grid, blk, 0, st, P, pre, np); break;
+        case BK_GRAM: hipLaunchKernelGGL(k_gram_b, grid, blk, 0, st, P, pre, np); break;
+        case BK_PROJECT: hipLaunchKernelGGL(k_project_b, grid, blk, 0, st, P, pre, np, f32); break;
+        case BK_SIGN: hipLaunchKernelGGL(k_sign_b, grid, blk, 0, st, P, pre, np); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }

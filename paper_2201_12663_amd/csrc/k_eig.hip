@@ -4,8 +4,9 @@
 //      one cooperative kernel: the columns of each matrix live in the LDS of
 //      a group of workgroups (a fixed slab per workgroup); per column, the owner
 //      forms the reflector, every workgroup computes its part of p = tau G v,
-//      then applies the rank-2 update G -= v w^T + w v^T to its own slab.  Two
-//      group barriers per column; only v and p travel through memory.
+//      then applies the rank-2 update G -= v w^T + w v^T to its own slab.  Per
+//      column, v is broadcast and p all-gathered through flag-tagged words;
+//      nothing else travels through memory.
 //   2. Divide and conquer on T (Cuppen): T is split recursively into blocks of
 //      at most 32 (the coupling b = e_mid is removed as T = diag(T1, T2) +
 //      b u u^T); leaves are diagonalized by a parallel Jacobi in one
@@ -18,6 +19,8 @@
 //      eigenvector matrix (FP64 MFMA).  One launch per phase per tree level.
 //   3. Back-transformation of the selected eigenvectors by the reflectors.
 #include <math.h>
+
+#include <string.h>
 
 #include <algorithm>
 #include <vector>
@@ -337,23 +340,18 @@ __global__ void k_zero_words(uint64_t* p, size_t n) {
 // ---------------------------------------------------------------------------
 struct Node {
     int mat, lo, mid, hi;     // leaf: mid == hi
+    long long soff;           // byte offset of the node's scratch (merge nodes)
 };
 
 struct DCArgs {
     const Node* nodes;        // nodes of this pass
     int nnodes;
-    double* d[3];             // modified diagonal (leaves read it)
-    double* e[3];
-    double* lam[3];           // eigenvalues (per index range of the node)
-    double* Q[3];             // eigenvectors, m x m (ld), block diagonal per node
-    double* Qn[3];            // output buffer of the merge GEMM
-    double* M[3];             // merge matrices, n x n at the node's diagonal block (ld)
-    char* scratch;            // per-node scratch, node_bytes each
-    size_t node_bytes;
-    int ld;
+    const EigMat* mats;       // matrix table
+    char* scratch;            // per-node scratch (node_scratch_bytes(n) each)
 };
 
-// node scratch layout (n <= MAXN)
+// node scratch: header, then 8 arrays of n doubles (D, z, dd, zk, tau, zh, rc x 2)
+// and 5 arrays of n ints (perm, keep, org, rp x 2)
 struct NodeScratch {
     double rho;
     double sgn;
@@ -361,24 +359,24 @@ struct NodeScratch {
     int nrot;
     int pad[2];
 };
+__host__ __device__ constexpr size_t node_scratch_bytes(int n) {
+    return (sizeof(NodeScratch) + (size_t)8 * n * sizeof(double) + (size_t)5 * n * sizeof(int) + 255) & ~(size_t)255;
+}
 __device__ __forceinline__ NodeScratch* ns_head(const DCArgs& a, int node) {
-    return (NodeScratch*)(a.scratch + (size_t)node * a.node_bytes);
+    return (NodeScratch*)(a.scratch + a.nodes[node].soff);
 }
+__device__ __forceinline__ int ns_n(const DCArgs& a, int node) { return a.nodes[node].hi - a.nodes[node].lo; }
 __device__ __forceinline__ double* ns_D(const DCArgs& a, int node) { return (double*)(ns_head(a, node) + 1); }
-__device__ __forceinline__ double* ns_z(const DCArgs& a, int node) { return ns_D(a, node) + MAXN; }
-__device__ __forceinline__ double* ns_dd(const DCArgs& a, int node) { return ns_z(a, node) + MAXN; }
-__device__ __forceinline__ double* ns_zk(const DCArgs& a, int node) { return ns_dd(a, node) + MAXN; }
-__device__ __forceinline__ double* ns_tau(const DCArgs& a, int node) { return ns_zk(a, node) + MAXN; }
-__device__ __forceinline__ double* ns_zh(const DCArgs& a, int node) { return ns_tau(a, node) + MAXN; }
-__device__ __forceinline__ double* ns_rc(const DCArgs& a, int node) { return ns_zh(a, node) + MAXN; }       // 2*MAXN
-__device__ __forceinline__ int* ns_perm(const DCArgs& a, int node) { return (int*)(ns_rc(a, node) + 2 * MAXN); }
-__device__ __forceinline__ int* ns_keep(const DCArgs& a, int node) { return ns_perm(a, node) + MAXN; }
-__device__ __forceinline__ int* ns_org(const DCArgs& a, int node) { return ns_keep(a, node) + MAXN; }
-__device__ __forceinline__ int* ns_rp(const DCArgs& a, int node) { return ns_org(a, node) + MAXN; }       // 2*MAXN
-
-size_t node_scratch_bytes() {
-    return (sizeof(NodeScratch) + (7 + 2) * MAXN * sizeof(double) + (3 + 2) * MAXN * sizeof(int) + 255) & ~(size_t)255;
-}
+__device__ __forceinline__ double* ns_z(const DCArgs& a, int node) { return ns_D(a, node) + ns_n(a, node); }
+__device__ __forceinline__ double* ns_dd(const DCArgs& a, int node) { return ns_D(a, node) + 2 * ns_n(a, node); }
+__device__ __forceinline__ double* ns_zk(const DCArgs& a, int node) { return ns_D(a, node) + 3 * ns_n(a, node); }
+__device__ __forceinline__ double* ns_tau(const DCArgs& a, int node) { return ns_D(a, node) + 4 * ns_n(a, node); }
+__device__ __forceinline__ double* ns_zh(const DCArgs& a, int node) { return ns_D(a, node) + 5 * ns_n(a, node); }
+__device__ __forceinline__ double* ns_rc(const DCArgs& a, int node) { return ns_D(a, node) + 6 * ns_n(a, node); }   // 2n
+__device__ __forceinline__ int* ns_perm(const DCArgs& a, int node) { return (int*)(ns_D(a, node) + 8 * ns_n(a, node)); }
+__device__ __forceinline__ int* ns_keep(const DCArgs& a, int node) { return ns_perm(a, node) + ns_n(a, node); }
+__device__ __forceinline__ int* ns_org(const DCArgs& a, int node) { return ns_perm(a, node) + 2 * ns_n(a, node); }
+__device__ __forceinline__ int* ns_rp(const DCArgs& a, int node) { return ns_perm(a, node) + 3 * ns_n(a, node); }    // 2n
 
 // leaves: dense Jacobi on the (<= 32) tridiagonal block, one workgroup each
 __device__ __forceinline__ int next_pos32(int p) {
@@ -395,8 +393,9 @@ __global__ __launch_bounds__(256) void k_dc_leaves(DCArgs a) {
     __shared__ double red[4];
     const Node nd = a.nodes[blockIdx.x];
     const int n = nd.hi - nd.lo;
-    const double* d = a.d[nd.mat] + nd.lo;
-    const double* e = a.e[nd.mat] + nd.lo;
+    const EigMat& mt = a.mats[nd.mat];
+    const double* d = mt.d + nd.lo;
+    const double* e = mt.e + nd.lo;
     const int t = threadIdx.x, bi = t >> 4, bj = t & 15;
     const int r0 = 2 * bi, c0 = 2 * bj;
     auto T = [&](int r, int c) -> double {
@@ -460,9 +459,9 @@ __global__ __launch_bounds__(256) void k_dc_leaves(DCArgs a) {
         if (!__syncthreads_or(rot)) break;
     }
     // eigenvalues on the diagonal (positions are back in order after whole sweeps)
-    double* lam = a.lam[nd.mat] + nd.lo;
-    double* Q = a.Q[nd.mat];
-    const int ld = a.ld;
+    double* lam = mt.lam + nd.lo;
+    double* Q = mt.Q;
+    const int ld = mt.ld;
     if (bi == bj) {
         if (r0 < n) lam[r0] = s00;
         if (r0 + 1 < n) lam[r0 + 1] = s11;
@@ -483,10 +482,11 @@ __global__ __launch_bounds__(256) void k_dc_prep(DCArgs a) {
     const Node nd = a.nodes[node];
     const int n1 = nd.mid - nd.lo, n = nd.hi - nd.lo;
     const int t = threadIdx.x;
-    const double* lam = a.lam[nd.mat] + nd.lo;
-    const double* Q = a.Q[nd.mat];
-    const int ld = a.ld;
-    double rho = 2.0 * a.e[nd.mat][nd.mid - 1];
+    const EigMat& mt = a.mats[nd.mat];
+    const double* lam = mt.lam + nd.lo;
+    const double* Q = mt.Q;
+    const int ld = mt.ld;
+    double rho = 2.0 * mt.e[nd.mid - 1];
     const double sgn = rho < 0.0 ? -1.0 : 1.0;
     rho = fabs(rho);
     const double rs2 = 0.7071067811865476;
@@ -705,10 +705,11 @@ __global__ __launch_bounds__(256) void k_dc_vectors(DCArgs a) {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const int* perm = ns_perm(a, node);
-    double* M = a.M[nd.mat];
-    const int ld = a.ld;
+    const EigMat& mt = a.mats[nd.mat];
+    double* M = mt.M;
+    const int ld = mt.ld;
     for (int s = lane; s < n; s += 64) M[(nd.lo + perm[s]) + (int64_t)(nd.lo + col) * ld] = x[s];
-    if (lane == 0) a.lam[nd.mat][nd.lo + col] = h->sgn * lamc;
+    if (lane == 0) mt.lam[nd.lo + col] = h->sgn * lamc;
 }
 
 // phase D: Qn[rows of child c, lo:hi] = Q[child block] * M[child rows, lo:hi]
@@ -724,10 +725,11 @@ __global__ __launch_bounds__(256) void k_dc_gemm(DCArgs a, const GemmTask* tasks
     const int tiles_n = (tk.nc + 63) / 64;
     const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
     if (tm * 64 >= tk.nr) return;
-    const int ld = a.ld;
-    const double* Q = a.Q[tk.mat];
-    const double* M = a.M[tk.mat];
-    double* Qn = a.Qn[tk.mat];
+    const EigMat& mt = a.mats[tk.mat];
+    const int ld = mt.ld;
+    const double* Q = mt.Q;
+    const double* M = mt.M;
+    double* Qn = mt.Qn;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
     d4_t acc[2][2];
@@ -767,11 +769,12 @@ __global__ __launch_bounds__(256) void k_dc_gemm(DCArgs a, const GemmTask* tasks
 // copy a node's block of Qn back into Q (so every node's result is in Q)
 __global__ void k_dc_copyback(DCArgs a) {
     const Node nd = a.nodes[blockIdx.y];
-    const int n = nd.hi - nd.lo, ld = a.ld;
+    const EigMat& mt = a.mats[nd.mat];
+    const int n = nd.hi - nd.lo, ld = mt.ld;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n * n; e += gridDim.x * blockDim.x) {
         const int r = e % n, c = e / n;
         const int64_t o = (nd.lo + r) + (int64_t)(nd.lo + c) * ld;
-        a.Q[nd.mat][o] = a.Qn[nd.mat][o];
+        mt.Q[o] = mt.Qn[o];
     }
 }
 
@@ -949,7 +952,7 @@ __global__ __launch_bounds__(256) void k_apply_wy(BtJobs J) {
 void build_tree(int mat, int lo, int hi, std::vector<std::vector<Node>>& by_height, int& height) {
     if (hi - lo <= LEAF) {
         if ((int)by_height.size() < 1) by_height.resize(1);
-        by_height[0].push_back(Node{mat, lo, hi, hi});
+        by_height[0].push_back(Node{mat, lo, hi, hi, 0});
         height = 0;
         return;
     }
@@ -959,169 +962,244 @@ void build_tree(int mat, int lo, int hi, std::vector<std::vector<Node>>& by_heig
     build_tree(mat, mid, hi, by_height, h2);
     height = 1 + std::max(h1, h2);
     if ((int)by_height.size() <= height) by_height.resize(height + 1);
-    by_height[height].push_back(Node{mat, lo, mid, hi});
+    by_height[height].push_back(Node{mat, lo, mid, hi, 0});
 }
+
+// the coupling of every split at mid is removed from the diagonal: d[mid-1] -= b,
+// d[mid] -= b with b = e[mid-1].  Splits touch disjoint entries (children have at
+// least LEAF/2 rows), so one thread per split.
+__global__ void k_dc_modify(const EigMat* __restrict__ mats, const int2* __restrict__ mids, int nmids) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nmids) return;
+    const EigMat& mt = mats[mids[q].x];
+    const int mid = mids[q].y;
+    const double b = mt.e[mid - 1];
+    mt.d[mid - 1] -= b;
+    mt.d[mid] -= b;
+}
+
+size_t a256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 }  // namespace
 
-size_t eig_work_bytes(int nmat, int m) {
-    // node table + tasks + per-node scratch (at most m / 16 nodes per pass per matrix)
-    const int max_nodes = nmat * (m / 16 + 2);
-    return (size_t)max_nodes * node_scratch_bytes() + (size_t)max_nodes * 4 * sizeof(Node) * 64 +
-           (size_t)max_nodes * 2 * sizeof(GemmTask) * 64 + (size_t)nmat * tri_xwords(m) * 8 + 65536;
+// A plan holds everything about the eigensolver's launches that depends only on
+// the matrix sizes and addresses: the packing of the tridiagonalization into
+// cooperative launches, the divide-and-conquer trees, and the device tables
+// (matrix table, split list, node and GEMM task lists per tree level).
+struct EigPlan {
+    std::vector<EigMat> mats;
+    // tridiagonalization
+    struct TriLaunch {
+        std::vector<int> mats;   // indices into mats
+        int cpb;                 // columns per workgroup (set by the largest m of the launch)
+        size_t shbytes;
+        int nblocks;
+        TriArgs args;
+    };
+    std::vector<TriLaunch> tri;
+    std::vector<size_t> xoff;    // word offset of each matrix's exchange area
+    size_t xwords = 0;
+    // divide and conquer
+    std::vector<std::vector<Node>> levels;
+    std::vector<std::vector<GemmTask>> tasks;
+    std::vector<int2> mids;
+    // device layout (byte offsets into the bound work area)
+    size_t off_mats = 0, off_mids = 0, off_x = 0, off_scratch = 0, total = 0;
+    std::vector<size_t> off_nodes, off_tasks;
+    size_t scratch_bytes = 0;
+    std::vector<char> blob;      // host copy of the tables (mats, mids, nodes, tasks)
+    size_t blob_bytes = 0;
+    char* work = nullptr;
+};
+
+static int tri_cpb(int m, int maxsh) {
+    const int mr = (m + 63) & ~63;
+    int cpb = (int)((maxsh - 8192 - mr * 8) / ((size_t)mr * 8));
+    return std::max(1, std::min(cpb, CMAX));
 }
 
-hipError_t launch_eig(const EigProblem& p, void* work, size_t work_bytes, hipStream_t st) {
-    const int m = p.m, ld = p.ld, nmat = p.nmat;
-    if (m < 1 || m > MAXN || nmat < 1 || nmat > 3) return hipErrorInvalidValue;
-    if (work_bytes < eig_work_bytes(nmat, m)) return hipErrorInvalidValue;
-    char* w = (char*)work;
-    uint64_t* xbase = (uint64_t*)w;          w += ((size_t)nmat * tri_xwords(m) * 8 + 255) & ~(size_t)255;
+EigPlan* eig_plan_create(const EigMat* mats, int nmat, size_t* work_bytes) {
+    if (nmat < 1) return nullptr;
+    for (int i = 0; i < nmat; ++i)
+        if (mats[i].m < 1 || mats[i].m > MAXN || mats[i].ld < mats[i].m) return nullptr;
+    int dev = 0, ncu = 0, maxsh = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return nullptr;
+    if (hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return nullptr;
+    EigPlan* P = new EigPlan();
+    P->mats.assign(mats, mats + nmat);
+    // ---- tridiagonalization: largest matrices first, packed while every block of
+    // a launch can be resident at once (occupancy of the launch's LDS size)
+    std::vector<int> ord(nmat);
+    for (int i = 0; i < nmat; ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return mats[x].m > mats[y].m; });
+    P->xoff.resize(nmat);
+    for (int i = 0; i < nmat; ++i) {
+        P->xoff[i] = P->xwords;
+        P->xwords += tri_xwords(mats[i].m);
+    }
+    for (size_t q = 0; q < ord.size();) {
+        EigPlan::TriLaunch L;
+        const int m0 = mats[ord[q]].m;
+        const int mr = (m0 + 63) & ~63;
+        const int cpb0 = tri_cpb(m0, maxsh);
+        L.cpb = cpb0;
+        L.shbytes = (size_t)(cpb0 + 1) * mr * 8;
+        if (hipFuncSetAttribute((const void*)k_tridiag, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.shbytes) !=
+            hipSuccess) { delete P; return nullptr; }
+        int occ = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_tridiag, 256, L.shbytes) != hipSuccess ||
+            occ < 1) { delete P; return nullptr; }
+        const int cap = occ * ncu;
+        int blocks = 0;
+        while (q < ord.size() && (int)L.mats.size() < TRI_MAXMAT) {
+            const int mi = mats[ord[q]].m;
+            // every matrix of the launch uses the launch's columns per block
+            const int bpm = (mi + cpb0 - 1) / cpb0;
+            if (bpm > 256 || bpm > cap) { delete P; return nullptr; }
+            if (blocks + bpm > cap) break;
+            L.mats.push_back(ord[q]);
+            blocks += bpm;
+            ++q;
+        }
+        L.nblocks = blocks;
+        P->tri.push_back(L);
+    }
+    // ---- divide and conquer trees, levels across all matrices
+    for (int i = 0; i < nmat; ++i) {
+        int h = 0;
+        build_tree(i, 0, mats[i].m, P->levels, h);
+    }
+    for (size_t h = 1; h < P->levels.size(); ++h)
+        for (auto& nd : P->levels[h]) P->mids.push_back(int2{nd.mat, nd.mid});
+    size_t scratch = 0;
+    P->tasks.resize(P->levels.size());
+    for (size_t h = 1; h < P->levels.size(); ++h) {
+        size_t off = 0;
+        for (auto& nd : P->levels[h]) {
+            nd.soff = (long long)off;
+            off += node_scratch_bytes(nd.hi - nd.lo);
+            const int n1 = nd.mid - nd.lo, n2 = nd.hi - nd.mid, n = nd.hi - nd.lo;
+            P->tasks[h].push_back(GemmTask{nd.mat, nd.lo, n1, nd.lo, n, nd.lo, n1});
+            P->tasks[h].push_back(GemmTask{nd.mat, nd.mid, n2, nd.lo, n, nd.mid, n2});
+        }
+        scratch = std::max(scratch, off);
+    }
+    P->scratch_bytes = scratch;
+    // ---- device layout: tables blob, exchange words, node scratch
+    size_t o = 0;
+    P->off_mats = o;  o += a256(nmat * sizeof(EigMat));
+    P->off_mids = o;  o += a256(std::max<size_t>(1, P->mids.size()) * sizeof(int2));
+    P->off_nodes.resize(P->levels.size());
+    P->off_tasks.resize(P->levels.size());
+    for (size_t h = 0; h < P->levels.size(); ++h) {
+        P->off_nodes[h] = o;  o += a256(P->levels[h].size() * sizeof(Node));
+        P->off_tasks[h] = o;  o += a256(std::max<size_t>(1, P->tasks[h].size()) * sizeof(GemmTask));
+    }
+    P->blob_bytes = o;
+    P->blob.assign(o, 0);
+    memcpy(P->blob.data() + P->off_mats, P->mats.data(), nmat * sizeof(EigMat));
+    if (!P->mids.empty()) memcpy(P->blob.data() + P->off_mids, P->mids.data(), P->mids.size() * sizeof(int2));
+    for (size_t h = 0; h < P->levels.size(); ++h) {
+        memcpy(P->blob.data() + P->off_nodes[h], P->levels[h].data(), P->levels[h].size() * sizeof(Node));
+        if (!P->tasks[h].empty())
+            memcpy(P->blob.data() + P->off_tasks[h], P->tasks[h].data(), P->tasks[h].size() * sizeof(GemmTask));
+    }
+    P->off_x = o;        o += a256(P->xwords * sizeof(uint64_t));
+    P->off_scratch = o;  o += a256(std::max<size_t>(scratch, 256));
+    P->total = o;
+    *work_bytes = o;
+    return P;
+}
+
+void eig_plan_destroy(EigPlan* P) { delete P; }
+
+hipError_t eig_plan_bind(EigPlan* P, void* work, hipStream_t st) {
+    P->work = (char*)work;
+    uint64_t* xbase = (uint64_t*)(P->work + P->off_x);
+    for (auto& L : P->tri) {
+        memset(&L.args, 0, sizeof(L.args));
+        int blk = 0;
+        const int cpb = L.cpb;
+        for (size_t i = 0; i < L.mats.size(); ++i) {
+            const EigMat& E = P->mats[L.mats[i]];
+            TriMat& M = L.args.mat[i];
+            M.G = E.G;
+            M.d = E.d;
+            M.e = E.e;
+            M.tau = E.tau;
+            M.x = xbase + P->xoff[L.mats[i]];
+            M.m = E.m;
+            M.ld = E.ld;
+            M.cpb = cpb;
+            M.bpm = (E.m + cpb - 1) / cpb;
+            M.blk0 = blk;
+            blk += M.bpm;
+        }
+        L.args.nmat = (int)L.mats.size();
+    }
+    return hipMemcpyAsync(P->work, P->blob.data(), P->blob_bytes, hipMemcpyHostToDevice, st);
+}
+
+hipError_t eig_plan_enqueue(const EigPlan* P, int* abort_w, hipStream_t st, bool cooperative) {
     hipError_t e;
-    // ---- 1. tridiagonalization
-    {
-        int dev = 0, ncu = 0, maxsh = 0;
-        if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
-        if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-        if ((e = hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess) return e;
-        const int mr = (m + 63) & ~63;
-        int cpb = (int)((maxsh - 8192 - (int)mr * 8) / ((size_t)mr * 8));
-        cpb = std::max(1, std::min(cpb, CMAX));
-        const int bpm = (m + cpb - 1) / cpb;
-        const size_t shbytes = (size_t)(cpb + 1) * mr * 8;
-        if (bpm > ncu || bpm > 256) return hipErrorInvalidConfiguration;
+    if (!P->work) return hipErrorInvalidValue;
+    // 1. tridiagonalization
+    hipLaunchKernelGGL(k_zero_words, dim3((unsigned)std::min<size_t>(1024, (P->xwords + 255) / 256)), dim3(256), 0,
+                       st, (uint64_t*)(P->work + P->off_x), P->xwords);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    for (const auto& L : P->tri) {
+        TriArgs ta = L.args;
+        ta.abort_w = abort_w;
         if ((e = hipFuncSetAttribute((const void*)k_tridiag, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)shbytes)) != hipSuccess) return e;
-        const size_t nwords = (size_t)nmat * tri_xwords(m);
-        hipLaunchKernelGGL(k_zero_words, dim3((unsigned)std::min<size_t>(1024, (nwords + 255) / 256)), dim3(256), 0, st,
-                           xbase, nwords);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        const int per_launch = std::max(1, std::min(std::min(nmat, ncu / bpm), TRI_MAXMAT));
-        for (int m0 = 0; m0 < nmat; m0 += per_launch) {
-            const int cnt = std::min(per_launch, nmat - m0);
-            TriArgs ta{};
-            for (int i = 0; i < cnt; ++i) {
-                TriMat& M = ta.mat[i];
-                M.G = p.G[m0 + i];
-                M.d = p.d[m0 + i];
-                M.e = p.e[m0 + i];
-                M.tau = p.tau[m0 + i];
-                M.x = xbase + (size_t)(m0 + i) * tri_xwords(m);
-                M.m = m;
-                M.ld = ld;
-                M.cpb = cpb;
-                M.bpm = bpm;
-                M.blk0 = i * bpm;
-            }
-            ta.nmat = cnt;
-            ta.abort_w = p.abort_w;
+                                     (int)L.shbytes)) != hipSuccess)
+            return e;
+        if (cooperative) {
             void* args[] = {&ta};
-            if ((e = hipLaunchCooperativeKernel((const void*)k_tridiag, dim3(cnt * bpm), dim3(256), args, shbytes,
+            if ((e = hipLaunchCooperativeKernel((const void*)k_tridiag, dim3(L.nblocks), dim3(256), args, L.shbytes,
                                                 st)) != hipSuccess)
                 return e;
+        } else {
+            hipLaunchKernelGGL(k_tridiag, dim3(L.nblocks), dim3(256), L.shbytes, st, ta);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
         }
     }
-    // ---- 2. divide and conquer on (d, e)
-    std::vector<std::vector<Node>> by_h;
-    int height = 0;
-    for (int mat = 0; mat < nmat; ++mat) build_tree(mat, 0, m, by_h, height);
-    // modified diagonals: every split at mid subtracts b = e[mid-1] from d[mid-1] and d[mid]
-    // (done on the device by a tiny kernel per split would be wasteful: the host tree
-    // drives a single pass of hipMemcpy-free updates below)
-    size_t max_nodes = 0;
-    for (auto& v : by_h) max_nodes = std::max(max_nodes, v.size());
-    Node* dnodes = (Node*)w;                  w += ((max_nodes * sizeof(Node) + 255) & ~(size_t)255) * by_h.size();
-    GemmTask* dtasks = (GemmTask*)w;          w += ((2 * max_nodes * sizeof(GemmTask) + 255) & ~(size_t)255) * by_h.size();
-    char* scratch = w;
-    // the split modifications are applied by k_dc_modify for all internal nodes at once
-    {
-        std::vector<int> mids;
-        for (size_t h = 1; h < by_h.size(); ++h)
-            for (auto& nd : by_h[h])
-                if (nd.mat == 0) mids.push_back(nd.mid);
-        // reuse the GemmTask area of the last level for the list (copied synchronously
-        // into a small static region of the work buffer)
-        int* dmids = (int*)(scratch);   // scratch is free until the first prep pass
-        if (!mids.empty()) {
-            if ((e = hipMemcpyAsync(dmids, mids.data(), mids.size() * sizeof(int), hipMemcpyHostToDevice, st)) != hipSuccess)
-                return e;
-            extern hipError_t launch_dc_modify(double* const d[3], const double* const e[3], int nmat,
-                                               const int* mids, int nmids, hipStream_t st);
-            if ((e = launch_dc_modify(p.d, p.e, nmat, dmids, (int)mids.size(), st)) != hipSuccess) return e;
-        }
+    // 2. divide and conquer
+    const EigMat* dmats = (const EigMat*)(P->work + P->off_mats);
+    if (!P->mids.empty()) {
+        hipLaunchKernelGGL(k_dc_modify, dim3((unsigned)((P->mids.size() + 255) / 256)), dim3(256), 0, st, dmats,
+                           (const int2*)(P->work + P->off_mids), (int)P->mids.size());
+        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     DCArgs da{};
-    for (int i = 0; i < nmat; ++i) {
-        da.d[i] = p.d[i];
-        da.e[i] = p.e[i];
-        da.lam[i] = p.lam[i];
-        da.Q[i] = p.Q[i];
-        da.Qn[i] = p.Qn[i];
-        da.M[i] = p.M[i];
-    }
-    da.scratch = scratch;
-    da.node_bytes = node_scratch_bytes();
-    da.ld = ld;
-    for (size_t h = 0; h < by_h.size(); ++h) {
-        auto& nodes = by_h[h];
-        Node* nd_dev = dnodes + h * ((max_nodes * sizeof(Node) + 255) / sizeof(Node));
-        if ((e = hipMemcpyAsync(nd_dev, nodes.data(), nodes.size() * sizeof(Node), hipMemcpyHostToDevice, st)) != hipSuccess)
-            return e;
-        da.nodes = nd_dev;
+    da.mats = dmats;
+    da.scratch = P->work + P->off_scratch;
+    for (size_t h = 0; h < P->levels.size(); ++h) {
+        const auto& nodes = P->levels[h];
+        da.nodes = (const Node*)(P->work + P->off_nodes[h]);
         da.nnodes = (int)nodes.size();
         if (h == 0) {
             hipLaunchKernelGGL(k_dc_leaves, dim3((unsigned)nodes.size()), dim3(256), 0, st, da);
             if ((e = hipGetLastError()) != hipSuccess) return e;
             continue;
         }
-        int maxn = 0;
-        for (auto& nd : nodes) maxn = std::max(maxn, nd.hi - nd.lo);
+        int maxn = 0, max_tiles = 0;
+        for (auto& nd : nodes) {
+            const int n1 = nd.mid - nd.lo, n2 = nd.hi - nd.mid, n = nd.hi - nd.lo;
+            maxn = std::max(maxn, n);
+            max_tiles = std::max(max_tiles, ((std::max(n1, n2) + 63) / 64) * ((n + 63) / 64));
+        }
         hipLaunchKernelGGL(k_dc_prep, dim3((unsigned)nodes.size()), dim3(256), 0, st, da);
         hipLaunchKernelGGL(k_dc_roots, dim3((unsigned)((maxn + 3) / 4), (unsigned)nodes.size()), dim3(256), 0, st, da);
         hipLaunchKernelGGL(k_dc_zhat, dim3((unsigned)((maxn + 255) / 256), (unsigned)nodes.size()), dim3(256), 0, st, da);
         hipLaunchKernelGGL(k_dc_vectors, dim3((unsigned)((maxn + 3) / 4), (unsigned)nodes.size()), dim3(256), 0, st, da);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        std::vector<GemmTask> tasks;
-        int max_tiles = 0;
-        for (auto& nd : nodes) {
-            const int n1 = nd.mid - nd.lo, n2 = nd.hi - nd.mid, n = nd.hi - nd.lo;
-            tasks.push_back(GemmTask{nd.mat, nd.lo, n1, nd.lo, n, nd.lo, n1});
-            tasks.push_back(GemmTask{nd.mat, nd.mid, n2, nd.lo, n, nd.mid, n2});
-            max_tiles = std::max(max_tiles, ((std::max(n1, n2) + 63) / 64) * ((n + 63) / 64));
-        }
-        GemmTask* tk_dev = dtasks + h * ((2 * max_nodes * sizeof(GemmTask) + 255) / sizeof(GemmTask));
-        if ((e = hipMemcpyAsync(tk_dev, tasks.data(), tasks.size() * sizeof(GemmTask), hipMemcpyHostToDevice, st)) != hipSuccess)
-            return e;
-        hipLaunchKernelGGL(k_dc_gemm, dim3((unsigned)max_tiles, (unsigned)tasks.size()), dim3(256), 0, st, da,
-                           (const GemmTask*)tk_dev);
+        hipLaunchKernelGGL(k_dc_gemm, dim3((unsigned)max_tiles, (unsigned)P->tasks[h].size()), dim3(256), 0, st, da,
+                           (const GemmTask*)(P->work + P->off_tasks[h]));
         hipLaunchKernelGGL(k_dc_copyback, dim3(256, (unsigned)nodes.size()), dim3(256), 0, st, da);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
-}
-
-__global__ void k_dc_modify(double* d0, double* d1, double* d2, const double* e0, const double* e1,
-                            const double* e2, int nmat, const int* mids, int nmids) {
-    const int mat = blockIdx.y;
-    double* d = mat == 0 ? d0 : (mat == 1 ? d1 : d2);
-    const double* e = mat == 0 ? e0 : (mat == 1 ? e1 : e2);
-    // every index is touched by at most one split from each side; apply sequentially
-    // in one thread per matrix (nmids <= m/16)
-    if (threadIdx.x == 0 && blockIdx.x == 0 && mat < nmat) {
-        for (int q = 0; q < nmids; ++q) {
-            const int mid = mids[q];
-            const double b = e[mid - 1];
-            d[mid - 1] -= b;
-            d[mid] -= b;
-        }
-    }
-}
-
-hipError_t launch_dc_modify(double* const d[3], const double* const e[3], int nmat, const int* mids, int nmids,
-                            hipStream_t st) {
-    hipLaunchKernelGGL(k_dc_modify, dim3(1, (unsigned)nmat), dim3(64), 0, st, d[0], nmat > 1 ? d[1] : d[0],
-                       nmat > 2 ? d[2] : d[0], e[0], nmat > 1 ? e[1] : e[0], nmat > 2 ? e[2] : e[0], nmat, mids, nmids);
-    return hipGetLastError();
 }
 
 size_t backtransform_work_doubles(int m) { return (size_t)((m + NB - 1) / NB + 1) * NB * NB; }

@@ -24,31 +24,33 @@ __device__ double block_sum(double v, double* red) {
     return s;
 }
 
-// one block per mode
-__global__ __launch_bounds__(TB) void k_truncate(TruncArgs a) {
+// one block per mode: sorted spectrum, tails, rank; mode 0 also writes the norms
+__device__ void truncate_mode(int mode, const double* __restrict__ lam, int m, const double* __restrict__ xip,
+                              int64_t R_pad, const double* __restrict__ anorm_part, int64_t anorm_ntiles, double eps,
+                              double* __restrict__ sigma, int* __restrict__ order, double* __restrict__ tails,
+                              int* __restrict__ ranks, double* __restrict__ scal) {
     __shared__ double key[MAXM];
     __shared__ int idx[MAXM];
     __shared__ double scan[MAXM + 1];
     __shared__ double red[40];
     __shared__ int rmin;
-    const int mode = blockIdx.x, t = threadIdx.x;
+    const int t = threadIdx.x;
 
     // |xi'|^2 and |A|^2 (same fixed order in every block)
     double v = 0.0;
-    for (int64_t i = t; i < a.R_pad; i += TB) v += a.xip[i] * a.xip[i];
+    for (int64_t i = t; i < R_pad; i += TB) v += xip[i] * xip[i];
     const double xi2 = block_sum(v, red);
     v = 0.0;
-    for (int64_t i = t; i < a.anorm_ntiles; i += TB) v += a.anorm_part[i];
+    for (int64_t i = t; i < anorm_ntiles; i += TB) v += anorm_part[i];
     const double a2 = block_sum(v, red);
     const double xi_norm = sqrt(xi2), a_norm = sqrt(fmax(a2, 0.0));
-    const double tau = (xi_norm > 0.0) ? a.eps * a_norm / (3.0 * xi_norm) : 0.0;
+    const double tau = (xi_norm > 0.0) ? eps * a_norm / (3.0 * xi_norm) : 0.0;
 
     // eigenvalues, padded to a power of two with -inf
     int N2 = 1;
-    while (N2 < a.m) N2 <<= 1;
-    const double* lam = a.lam[mode];
+    while (N2 < m) N2 <<= 1;
     for (int i = t; i < N2; i += TB) {
-        key[i] = (i < a.m) ? lam[i] : -INFINITY;
+        key[i] = (i < m) ? lam[i] : -INFINITY;
         idx[i] = i;
     }
     __syncthreads();
@@ -73,33 +75,69 @@ __global__ __launch_bounds__(TB) void k_truncate(TruncArgs a) {
         }
     }
     // suffix sums of max(lambda, 0): scan[r] = sum_{k >= r} lambda_k, scan[m] = 0
-    for (int i = t; i <= a.m; i += TB) scan[i] = (i < a.m) ? fmax(key[i], 0.0) : 0.0;
+    for (int i = t; i <= m; i += TB) scan[i] = (i < m) ? fmax(key[i], 0.0) : 0.0;
     __syncthreads();
-    for (int off = 1; off < a.m; off <<= 1) {
+    for (int off = 1; off < m; off <<= 1) {
         double add[2];
         int cnt = 0;
-        for (int i = t; i < a.m; i += TB) add[cnt++] = (i + off < a.m) ? scan[i + off] : 0.0;
+        for (int i = t; i < m; i += TB) add[cnt++] = (i + off < m) ? scan[i + off] : 0.0;
         __syncthreads();
         cnt = 0;
-        for (int i = t; i < a.m; i += TB) scan[i] += add[cnt++];
+        for (int i = t; i < m; i += TB) scan[i] += add[cnt++];
         __syncthreads();
     }
-    if (t == 0) rmin = a.m;
+    if (t == 0) rmin = m;
     __syncthreads();
     // r = min{ r >= 1 : t_r <= tau }, t_r = sqrt(scan[r])
-    for (int r = 1 + t; r <= a.m; r += TB)
+    for (int r = 1 + t; r <= m; r += TB)
         if (sqrt(scan[r]) <= tau) atomicMin(&rmin, r);
     __syncthreads();
     const int r = (xi_norm > 0.0) ? rmin : 0;
-    for (int i = t; i < a.m; i += TB) {
-        a.sigma[mode][i] = sqrt(fmax(key[i], 0.0));
-        a.order[mode][i] = idx[i];
+    for (int i = t; i < m; i += TB) {
+        sigma[i] = sqrt(fmax(key[i], 0.0));
+        order[i] = idx[i];
     }
-    for (int i = t; i <= a.m; i += TB) a.tails[mode][i] = sqrt(scan[i]);
+    for (int i = t; i <= m; i += TB) tails[i] = sqrt(scan[i]);
     if (t == 0) {
-        a.ranks[mode] = r;
-        if (mode == 0) { a.scal[0] = xi_norm; a.scal[1] = a_norm; a.scal[2] = tau; }
+        ranks[mode] = r;
+        if (mode == 0) { scal[0] = xi_norm; scal[1] = a_norm; scal[2] = tau; }
     }
+}
+
+__global__ __launch_bounds__(TB) void k_truncate(TruncArgs a) {
+    const int mode = blockIdx.x;
+    truncate_mode(mode, a.lam[mode], a.m, a.xip, a.R_pad, a.anorm_part, a.anorm_ntiles, a.eps, a.sigma[mode],
+                  a.order[mode], a.tails[mode], a.ranks, a.scal);
+}
+
+// batched: grid (3, problems); problems with non-finite input are skipped
+__global__ __launch_bounds__(TB) void k_truncate_b(const BProb* __restrict__ P) {
+    const int mode = blockIdx.x;
+    const BProb& q = P[blockIdx.y];
+    if (q.flags[0] != 0) {
+        if (threadIdx.x == 0) q.ranks[mode] = 0;
+        return;
+    }
+    truncate_mode(mode, q.lam[mode], q.m, q.xip, q.R_pad, q.anorm_part, q.anorm_ntiles, q.eps, q.sigma[mode],
+                  q.order[mode], q.tails[mode], q.ranks, q.scal);
+}
+
+// status word per problem (one thread each)
+__global__ void k_status_b(const BProb* __restrict__ P, int np) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    const BProb& q = P[p];
+    int st = 0;
+    if (q.flags[0] != 0) st = -2;                  // non-finite input
+    else if (*q.abort_w != 0) st = -4;             // eigensolver wait ran out
+    else {
+        const int64_t r1 = q.ranks[0], r2 = q.ranks[1], r3 = q.ranks[2];
+        const bool zcap = (q.Zo[0] || q.Zo[1] || q.Zo[2]) && (r1 > q.cap_rank || r2 > q.cap_rank || r3 > q.cap_rank);
+        const bool rcap = r1 > q.rcap || r2 > q.rcap || r3 > q.rcap;
+        const bool bcap = q.beta && r1 * r2 * r3 > q.cap_beta;
+        if (zcap || rcap || bcap) st = -8;          // capacity
+    }
+    q.ranks[3] = st;
 }
 
 }  // namespace
@@ -107,5 +145,12 @@ __global__ __launch_bounds__(TB) void k_truncate(TruncArgs a) {
 hipError_t launch_truncate(const TruncArgs& a, hipStream_t st) {
     if (a.m < 1 || a.m > MAXM) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_truncate, dim3(3), dim3(TB), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_truncate_b(const BProb* P, int np, hipStream_t st) {
+    if (np < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_truncate_b, dim3(3, (unsigned)np), dim3(TB), 0, st, P);
+    hipLaunchKernelGGL(k_status_b, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, P, np);
     return hipGetLastError();
 }

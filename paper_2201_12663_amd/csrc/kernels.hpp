@@ -3,6 +3,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
+#include "../../include/rhosvd.h"
+
 // Padding granularities shared by the workspace layout and the kernels.
 constexpr int PAD_N = 64;    // rows of U~, Z and the Gram side (n, m)
 constexpr int PAD_R = 64;    // canonical terms (columns of U~, K of the core)
@@ -34,9 +38,10 @@ hipError_t launch_gemm64(bool a_kcontig, bool b_kcontig, int64_t M, int64_t N, i
                          int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc, double alpha,
                          hipStream_t st);
 // R < n helpers (Z = U~ W Lambda^-1/2 and its re-orthonormalization)
+// r_dev (nullable): the rank is min(*r_dev, r) (known only on the device)
 hipError_t launch_gather_scaled(int m_pad, int r, int r_pad, const double* W, const int* order,
-                                const double* sigma, double* Wr, hipStream_t st);
-hipError_t launch_pad_identity(int r, int mp, int ld, double* M, hipStream_t st);
+                                const double* sigma, double* Wr, hipStream_t st, const int* r_dev = nullptr);
+hipError_t launch_pad_identity(int r, int mp, int ld, double* M, hipStream_t st, const int* r_dev = nullptr);
 hipError_t launch_scale_cols_invsqrt(int mp, int ld, const double* mu, const double* P, double* out, hipStream_t st);
 hipError_t launch_sign_cols(int n, int n_pad, int r, double* Z, hipStream_t st);
 
@@ -46,25 +51,36 @@ hipError_t launch_project(int64_t n_pad, int64_t R_pad, int64_t r_pad, const dou
                           const double* Ut, double* out_f64, float* out_f32, hipStream_t st);
 
 // a3: FP64 eigensolver (Householder tridiagonalization + divide and conquer) for
-// up to 3 symmetric m x m matrices (ld), m <= 2048.  G is overwritten by the
-// Householder vectors (column k holds v_k in rows k+1..m-1); lam receives the
-// eigenvalues (unsorted) and Q the eigenvectors of the tridiagonal matrix T
-// (eigenvectors of G = H Q, see launch_backtransform).
-struct EigProblem {
-    double* G[3];
-    int nmat, m, ld;
-    double* lam[3];      // m
-    double* Q[3];        // ld x ld
-    double* Qn[3];       // ld x ld workspace
-    double* M[3];        // ld x ld workspace
-    double* d[3];        // m
-    double* e[3];        // m
-    double* tau[3];      // m
-    int* abort_w;        // device int, set to 1 when a cross-workgroup wait of the
-                         // tridiagonalization ran out (the results are then invalid)
+// a list of symmetric matrices of order m <= 2048 (each its own m and ld).  G is
+// overwritten by the Householder vectors (column k holds v_k in rows k+1..m-1);
+// lam receives the eigenvalues (unsorted) and Q the eigenvectors of the
+// tridiagonal matrix T (eigenvectors of G = H Q, see launch_backtransform).
+struct EigMat {
+    double* G;      // m x m (ld)
+    double* lam;    // m
+    double* Q;      // ld x m
+    double* Qn;     // ld x m workspace
+    double* M;      // ld x m workspace
+    double* d;      // m
+    double* e;      // m
+    double* tau;    // m
+    int m, ld;
 };
-size_t eig_work_bytes(int nmat, int m);
-hipError_t launch_eig(const EigProblem& p, void* work, size_t work_bytes, hipStream_t st);
+// A plan fixes the launches and device tables for one list of matrices:
+// create (host only; returns the bytes of device work memory it needs), bind
+// (assigns that memory and enqueues the upload of its tables on st; the plan
+// keeps the host copy alive), enqueue (kernel launches only, so it may be
+// recorded into a graph once bound).  abort_w: a device int set to 1 when a
+// cross-workgroup wait of the tridiagonalization ran out (results invalid).
+struct EigPlan;
+EigPlan* eig_plan_create(const EigMat* mats, int nmat, size_t* work_bytes);
+hipError_t eig_plan_bind(EigPlan* plan, void* work, hipStream_t st);
+// cooperative: launch the tridiagonalization cooperatively (the runtime checks that
+// all workgroups are resident); otherwise residency rests on the plan's packing,
+// which never exceeds the device's occupancy for the launch.
+hipError_t eig_plan_enqueue(const EigPlan* plan, int* abort_w, hipStream_t st, bool cooperative = true);
+void eig_plan_destroy(EigPlan* plan);
+
 // Back-transformation jobs: out[:, k] = H Q[:, order[k]] for k < r (order NULL:
 // identity), H = H_0 ... H_{m-3} from the reflectors left in Hv by launch_eig,
 // rows m .. nrows-1 of out set to zero.  r = min(*r_dev, r) when r_dev is set
@@ -122,3 +138,61 @@ struct CoreArgs {
     int prec;
 };
 hipError_t launch_core(const CoreArgs& a, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Batched reductions: one descriptor per problem in device memory.  Sizes are
+// fixed on the host; the ranks exist only on the device (ranks[0..2]), and the
+// status word ranks[3] (0, or a negative rhosvd_status) gates the later phases.
+// ---------------------------------------------------------------------------
+struct BProb {
+    int n, R, n_pad, R_pad;
+    int m, m_pad, rside, rcap, rcap_pad, cap_rank;   // rcap = min(cap_rank, m)
+    double eps;
+    const double* U[3];
+    const double* xi;
+    double* Ut[3];         // n_pad x R_pad
+    double* xip;           // R_pad
+    int* flags;            // [0] non-finite input, [1] dropped terms
+    const int* abort_w;    // eigensolver abort word of the batch
+    double* G[3];          // m_pad x m_pad Gram (n or R side) -> reflectors
+    double* lam[3];        // m_pad eigenvalues
+    double* W[3];          // eigenvectors of the tridiagonal matrices
+    double* anorm_part;
+    int64_t anorm_ntiles;
+    double* sigma[3];      // m_pad + 1
+    int* order[3];         // m_pad
+    double* tails[3];      // m_pad + 1
+    double* scal;          // xi_norm, a_norm, tau
+    int* ranks;            // [0..2] ranks, [3] status
+    double* Z[3];          // n_pad x rcap_pad
+    void* V[3];            // rcap_pad x R_pad (FP64, or FP32 for the mixed cores)
+    double* Zo[3];         // caller outputs, n x cap_rank (ld n), or null
+    double* beta;          // caller output or null
+    int64_t cap_beta;
+    int* result;           // caller's int32[8]: r1, r2, r3, status
+};
+enum { BK_COLNORM = 0, BK_ANORM = 1, BK_GRAM = 2, BK_PROJECT = 3, BK_SIGN = 4 };
+// Flattened launch of one batched dense phase: pre (device, np + 1 entries) holds
+// each problem's first block, nblocks = pre[np].  f32: V in FP32 (projection).
+hipError_t launch_batched_dense(int which, const BProb* P, const int64_t* pre, int np, int64_t nblocks, int f32,
+                                hipStream_t st);
+// truncation of every problem and mode (grid 3 x np), then the per-problem status:
+// non-finite input, eigensolver abort, or ranks beyond the capacities.
+hipError_t launch_truncate_b(const BProb* P, int np, hipStream_t st);
+// Khatri-Rao cores of every problem with status 0 and a beta output, as one
+// persistent launch: a device-side plan counts each problem's tiles from its
+// ranks, workgroups take tiles from a shared counter.  work: 2 * (np + 2) int64.
+hipError_t launch_core_b(const BProb* P, int np, int prec, int64_t* work, int grid, hipStream_t st);
+// workgroups of the persistent core that fit on the device at once
+int core_b_max_grid(int prec);
+// copy Z to the caller's buffers and write the result words (ranks, status)
+hipError_t launch_finish_b(const BProb* P, int np, hipStream_t st);
+
+// Batch plans (batch.hip): validation, layout + uploads + graph capture, replay.
+struct BatchPlan;
+int batch_validate(const rhosvd_problem* probs, int count, std::string& msg);   // rhosvd_status
+BatchPlan* batch_plan_create(const rhosvd_problem* probs, int count, int prec, std::string& err);
+bool batch_plan_matches(const BatchPlan* plan, const rhosvd_problem* probs, int count, int prec);
+hipError_t batch_plan_run(BatchPlan* plan, hipStream_t st);
+bool batch_plan_uses_graph(const BatchPlan* plan);
+void batch_plan_destroy(BatchPlan* plan);

@@ -19,12 +19,12 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
 PHASES = ["norms", "anorm", "gram", "eig", "trunc_z", "project", "core"]
 
 STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_NONFINITE", -3: "ERR_ALLOC", -4: "ERR_DEVICE",
-          -5: "ERR_NOCONV", -6: "ERR_STATE", -7: "ERR_UNSUPPORTED"}
+          -5: "ERR_NOCONV", -6: "ERR_STATE", -7: "ERR_UNSUPPORTED", -8: "ERR_CAPACITY"}
 
 # every symbol include/rhosvd.h declares
 EXPORTS = ["rhosvd_create", "rhosvd_destroy", "rhosvd_set_options", "rhosvd_reduce", "rhosvd_get",
-           "rhosvd_get_xi", "rhosvd_get_spectrum", "rhosvd_get_v", "rhosvd_phase_ms",
-           "rhosvd_last_error", "rhosvd_version"]
+           "rhosvd_get_xi", "rhosvd_get_spectrum", "rhosvd_get_v", "rhosvd_reduce_batched",
+           "rhosvd_batch_uses_graph", "rhosvd_phase_ms", "rhosvd_last_error", "rhosvd_version"]
 
 
 class Options(ctypes.Structure):
@@ -36,6 +36,15 @@ class Report(ctypes.Structure):
     _fields_ = [("xi_norm", ctypes.c_double), ("a_norm", ctypes.c_double), ("tau", ctypes.c_double),
                 ("bound", ctypes.c_double), ("tail", ctypes.c_double * 3), ("ranks", ctypes.c_int32 * 3),
                 ("m", ctypes.c_int32), ("eig_sweeps", ctypes.c_int32), ("dropped", ctypes.c_int32)]
+
+
+class Problem(ctypes.Structure):
+    """rhosvd_problem: one reduction of a batch (device pointers)."""
+    _fields_ = [("n", ctypes.c_int64), ("R", ctypes.c_int64), ("U1", ctypes.c_void_p), ("U2", ctypes.c_void_p),
+                ("U3", ctypes.c_void_p), ("xi", ctypes.c_void_p), ("eps", ctypes.c_double),
+                ("cap_rank", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("cap_beta", ctypes.c_int64),
+                ("Z1", ctypes.c_void_p), ("Z2", ctypes.c_void_p), ("Z3", ctypes.c_void_p),
+                ("beta", ctypes.c_void_p), ("result", ctypes.c_void_p)]
 
 
 class RhosvdError(RuntimeError):
@@ -63,13 +72,16 @@ def load():
         lib.rhosvd_get_xi.argtypes = [vp, vp]
         lib.rhosvd_get_spectrum.argtypes = [vp, i32, vp]
         lib.rhosvd_get_v.argtypes = [vp, i32, vp]
+        lib.rhosvd_reduce_batched.argtypes = [vp, i32, ctypes.POINTER(Problem)]
+        lib.rhosvd_batch_uses_graph.argtypes = [vp]
+        lib.rhosvd_batch_uses_graph.restype = i32
         lib.rhosvd_phase_ms.argtypes = [vp, i32]
         lib.rhosvd_phase_ms.restype = dbl
         lib.rhosvd_last_error.argtypes = [vp]
         lib.rhosvd_last_error.restype = ctypes.c_char_p
         lib.rhosvd_version.restype = ctypes.c_char_p
         for f in ("rhosvd_create", "rhosvd_destroy", "rhosvd_set_options", "rhosvd_reduce", "rhosvd_get",
-                  "rhosvd_get_xi", "rhosvd_get_spectrum", "rhosvd_get_v"):
+                  "rhosvd_get_xi", "rhosvd_get_spectrum", "rhosvd_get_v", "rhosvd_reduce_batched"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -219,6 +231,88 @@ class Reducer:
 
     def phase_ms(self):
         return {name: float(self.lib.rhosvd_phase_ms(self.h, i)) for i, name in enumerate(PHASES)}
+
+    # ---- batched reductions
+    def batch_descriptors(self, problems, results, outputs=None, cap_rank=None):
+        """Descriptor array for rhosvd_reduce_batched.
+
+        problems: list of (U1, U2, U3, xi, eps) with column-major CUDA tensors.
+        results:  (count, 8) int32 CUDA tensor (ranks, status, dropped).
+        outputs:  None (ranks only), or a list of (Z1, Z2, Z3, beta_flat) per problem
+                  (Z_l: (n, cap) column-major float64, beta_flat: float64 or None).
+        cap_rank: per-problem rank caps when outputs is None (default min(n, R))."""
+        import torch
+        if not (results.is_cuda and results.dtype == torch.int32 and results.is_contiguous()
+                and tuple(results.shape) == (len(problems), 8)):
+            raise ValueError("results: expected a contiguous (count, 8) int32 CUDA tensor")
+        arr = (Problem * len(problems))()
+        for i, (U1, U2, U3, xi, eps) in enumerate(problems):
+            n, R = U1.shape
+            d = arr[i]
+            d.n, d.R = n, R
+            d.U1, d.U2, d.U3 = (_colmajor(U1, "U1").value, _colmajor(U2, "U2").value, _colmajor(U3, "U3").value)
+            if not (xi.is_cuda and xi.dtype == torch.float64 and xi.is_contiguous() and xi.numel() == R):
+                raise ValueError("xi: expected a contiguous float64 CUDA tensor of length R")
+            d.xi = xi.data_ptr()
+            d.eps = float(eps)
+            d.result = results[i].data_ptr()
+            if outputs is None:
+                d.cap_rank = int(cap_rank[i]) if cap_rank is not None else min(n, R)
+            else:
+                Z1, Z2, Z3, b = outputs[i]
+                d.cap_rank = int(Z1.shape[1])
+                if Z1.shape[1] > 0:
+                    for Z in (Z1, Z2, Z3):
+                        if tuple(Z.shape) != (n, d.cap_rank):
+                            raise ValueError("Z outputs must be (n, cap_rank)")
+                    d.Z1, d.Z2, d.Z3 = (_colmajor(Z1, "Z1").value, _colmajor(Z2, "Z2").value,
+                                        _colmajor(Z3, "Z3").value)
+                if d.cap_rank < 1:
+                    d.cap_rank = 1
+                if b is not None and b.numel() > 0:
+                    d.beta = b.data_ptr()
+                    d.cap_beta = int(b.numel())
+        return arr
+
+    def reduce_batched_raw(self, descriptors):
+        """Enqueue one batched pass (see include/rhosvd.h)."""
+        self._check(self.lib.rhosvd_reduce_batched(self.h, len(descriptors), descriptors))
+
+    def batch_uses_graph(self):
+        return bool(self.lib.rhosvd_batch_uses_graph(self.h))
+
+    def reduce_batched(self, problems, beta=True):
+        """Batched reductions with outputs sized exactly: a ranks-only pass, then
+        the full pass into freshly allocated Z (and beta).  Returns a list of
+        dicts (ranks, status, dropped, Z, beta) and the descriptor array of the
+        full pass (replaying it reuses the recorded graph)."""
+        import torch
+        count = len(problems)
+        res = torch.zeros((count, 8), dtype=torch.int32, device="cuda")
+        self.reduce_batched_raw(self.batch_descriptors(problems, res))
+        ranks = res.cpu().numpy()
+        outs = []
+        for i, (U1, _, _, _, _) in enumerate(problems):
+            n = U1.shape[0]
+            r = [int(x) for x in ranks[i, :3]]
+            cap = max(1, max(r))
+            Zs = [colmajor_empty(n, cap) for _ in range(3)]
+            b = torch.empty(max(1, r[0] * r[1] * r[2]), dtype=torch.float64, device="cuda") if beta else None
+            outs.append((Zs[0], Zs[1], Zs[2], b))
+        res2 = torch.zeros((count, 8), dtype=torch.int32, device="cuda")
+        desc = self.batch_descriptors(problems, res2, outputs=outs)
+        self.reduce_batched_raw(desc)
+        rr = res2.cpu().numpy()
+        out = []
+        for i in range(count):
+            r = tuple(int(x) for x in rr[i, :3])
+            Z1, Z2, Z3, b = outs[i]
+            bt = None
+            if b is not None and all(x > 0 for x in r):
+                bt = b[: r[0] * r[1] * r[2]].view(r[2], r[1], r[0]).permute(2, 1, 0)
+            out.append(dict(ranks=r, status=int(rr[i, 3]), dropped=int(rr[i, 4]),
+                            Z=[Z1[:, :r[0]], Z2[:, :r[1]], Z3[:, :r[2]]], beta=bt))
+        return out, desc, res2, outs
 
 
 def reduce(U1, U2, U3, xi, eps, precision="fp64", **kw):

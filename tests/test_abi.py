@@ -50,3 +50,37 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(rhosvd.Options) == 32
     # 4 doubles + 3 doubles + 3 int32 + 3 int32 = 56 + 24 = 80
     assert ctypes.sizeof(rhosvd.Report) == 80
+
+
+def test_null_handle_batched(lib):
+    assert lib.rhosvd_reduce_batched(None, 1, None) == -1
+    assert lib.rhosvd_batch_uses_graph(None) == 0
+
+
+def test_struct_offsets_match_a_c_compiler(tmp_path):
+    """Compile the header with the host C compiler and compare every field offset
+    of the public structs with the ctypes mirrors of the binding."""
+    import shutil
+    import subprocess
+    from paper_2201_12663_amd import rhosvd
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = {"rhosvd_options": rhosvd.Options, "rhosvd_report": rhosvd.Report,
+               "rhosvd_problem": rhosvd.Problem}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rhosvd.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
