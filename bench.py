@@ -14,7 +14,13 @@ eps + 1e-6 of |A| in this run: the truncation part is bounded by Theorem 2.3 (th
 library's report), the core part is measured against the FP64 path's core, and
 the two are orthogonal.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+The line also carries "batched": the uneven batch (256 problems, n uniform in
+{128,...,2048}, R log-uniform in [64, 8192], each the first R terms of ceil(R/32)
+charges x 32 Gaussian terms, eps = 1e-5) as one graph-recorded batched pass
+(FP32-MFMA cores, FP64 eigensolver), timed over replays, next to the plain FP64
+single-problem path over the same problems.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-batch]
 """
 from __future__ import annotations
 
@@ -92,6 +98,80 @@ def cpu_baseline(ci):
                         "estimated %.1f s per reduction" % (r, {k: round(v, 2) for k, v in t.items()}, total)))
 
 
+def bench_batched(args):
+    """The uneven batch as one batched pass (graph replay), and the plain FP64
+    single-problem path over the same problems for comparison."""
+    import numpy as np
+    import torch
+    from paper_2201_12663_amd import inputs, rhosvd
+    shapes = inputs.batch_shapes(seed=0, count=args.batch_count)
+    t0 = time.perf_counter()
+    probs = []
+    for i, (n, R) in enumerate(shapes):
+        a, c, xi = inputs.batch_problem_params(0, i, n, R)
+        U = inputs.gaussian_side_matrices_torch(n, a, c)
+        probs.append((U[0], U[1], U[2], torch.from_numpy(xi).cuda(), 1e-5))
+    torch.cuda.synchronize()
+    log(f"batch: {len(probs)} problems generated on the device in {time.perf_counter() - t0:.1f} s")
+    red = rhosvd.Reducer(precision=args.batch_precision, beta_fp32=args.batch_precision != "fp64")
+    t0 = time.perf_counter()
+    out, desc, res, outs = red.reduce_batched(probs)
+    torch.cuda.synchronize()
+    first_s = time.perf_counter() - t0
+    rr = res.cpu().numpy()
+    ranks = [tuple(int(x) for x in rr[i, :3]) for i in range(len(probs))]
+    status = [int(rr[i, 3]) for i in range(len(probs))]
+    beta_gb = sum(r[0] * r[1] * r[2] for r in ranks) * outs[0][3].element_size() / 1e9
+    log(f"batch: sizing + first pass {first_s:.1f} s (graph recorded: {red.batch_uses_graph()}), "
+        f"beta outputs {beta_gb:.1f} GB, statuses {sorted(set(status))}")
+    for _ in range(args.batch_warmup):
+        red.reduce_batched_raw(desc)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.batch_steps):
+        red.reduce_batched_raw(desc)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.batch_steps
+    core_flops = float(sum(2.0 * r[0] * r[1] * r[2] * R for r, (n, R) in zip(ranks, shapes)))
+    result = dict(
+        workload=("uneven batch: %d problems, n uniform in {128,...,2048}, R log-uniform in [64, 8192], "
+                  "charges x 32-term Gaussian sums for 1/|x|, eps=1e-5" % len(probs)),
+        precision=args.batch_precision, problems=len(probs), steps=args.batch_steps,
+        ms_per_batch=round(ms, 3), reductions_per_s=round(len(probs) / (ms * 1e-3), 3),
+        graph=red.batch_uses_graph(), all_ok=all(s == 0 for s in status),
+        core_flops=core_flops, core_tflops_whole_pass=round(core_flops / (ms * 1e-3) / 1e12, 2),
+        beta_gb=round(beta_gb, 2), max_rank=max(max(r) for r in ranks))
+    log(f"batch: {ms:.1f} ms per batch -> {result['reductions_per_s']} reductions/s")
+    red.close()
+    if args.batch_fp64_baseline:
+        # the plain FP64 path, one problem at a time; every core goes into one
+        # FP64 buffer sized for the largest problem (the batch's outputs stay alive)
+        red64 = rhosvd.Reducer(precision="fp64")
+        big = torch.empty(max(r[0] * r[1] * r[2] for r in ranks) + 1, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        same = 0
+        for i, p in enumerate(probs):
+            r = red64.reduce(*p)
+            same += tuple(r) == ranks[i]
+            if all(x > 0 for x in r) and r[0] * r[1] * r[2] <= big.numel():
+                red64.core_only(big)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t0
+        red64.close()
+        result["plain_fp64"] = dict(s_per_batch=round(t64, 3), reductions_per_s=round(len(probs) / t64, 3),
+                                    ranks_equal=same)
+        result["speedup_vs_plain_fp64"] = round(t64 / (ms * 1e-3), 3)
+        del big
+        log(f"batch: plain FP64 one by one {t64:.1f} s ({same}/{len(probs)} ranks equal)")
+    del outs, out
+    torch.cuda.empty_cache()
+    return result
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +179,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--paths", default="fp64,fp32,bf16x3")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--batch-steps", type=int, default=2)
+    ap.add_argument("--batch-warmup", type=int, default=1)
+    ap.add_argument("--batch-precision", default="fp32")
+    ap.add_argument("--no-batch-fp64-baseline", dest="batch_fp64_baseline", action="store_false")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build's path runs on a single MI355X "
@@ -179,6 +265,8 @@ def main():
                      "flops_per_launch": 2.0 * rb["ranks"][0] * rb["ranks"][1] * rb["ranks"][2] * ci.R
                      * (3 if best == "bf16x3" else 1)},
     }
+    if not args.no_batch:
+        line["batched"] = bench_batched(args)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample)")
         line["cpu_baseline"] = cpu_baseline(ci)

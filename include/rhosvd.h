@@ -64,9 +64,11 @@ typedef enum {
 
 typedef struct {
     int32_t precision;       /* rhosvd_precision */
-    int32_t max_eig_sweeps;  /* cap on eigensolver sweeps; <= 0 selects the default (30) */
+    int32_t max_eig_sweeps;  /* unused (the eigensolver is not iterative); any value */
     int32_t profile;         /* nonzero: time each phase with HIP events (see rhosvd_phase_ms) */
-    int32_t reserved[5];     /* must be zero */
+    int32_t beta_fp32;       /* nonzero: beta is written as float (r1*r2*r3 floats) instead of
+                                double, halving its size; meant for the FP32 and BF16x3 cores */
+    int32_t reserved[4];     /* must be zero */
 } rhosvd_options;
 
 typedef struct {
@@ -114,14 +116,15 @@ rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R,
  * Phase 2: the Khatri-Rao core and the copy-out into caller buffers sized from
  * the ranks of the last successful rhosvd_reduce on this handle.
  *   Z1..Z3 : device, n x r_l each (column-major), or NULL to skip
- *   beta   : device, r1*r2*r3 doubles (Fortran order), or NULL to skip the core
+ *   beta   : device, r1*r2*r3 doubles (floats with the beta_fp32 option), Fortran
+ *            order, or NULL to skip the core
  *   sigma  : device, r1+r2+r3 doubles (kept singular values, mode by mode), or NULL
  *   report : HOST, or NULL
  * Enqueued on the handle's stream; does not synchronize.
  * Errors: STATE (no reduction), DEVICE.
  */
 rhosvd_status rhosvd_get(rhosvd_handle h, double* Z1, double* Z2, double* Z3,
-                         double* beta, double* sigma, rhosvd_report* report);
+                         void* beta, double* sigma, rhosvd_report* report);
 
 /*
  * Inspection of the last reduction (for tests and the mixed Tucker-canonical
@@ -156,9 +159,10 @@ rhosvd_status rhosvd_get_v(rhosvd_handle h, int32_t l, double* V);
  *   eps        : > 0
  *   cap_rank   : >= 1, the columns available in each Z output; ranks above it
  *                give RHOSVD_ERR_CAPACITY for that problem (Z, beta not written)
- *   cap_beta   : doubles available in beta (>= 1 when beta is set)
+ *   cap_beta   : entries available in beta (>= 1 when beta is set)
  *   Z1..Z3     : n x cap_rank outputs (ld n, first r_l columns written), or all NULL
- *   beta       : r1*r2*r3 output (Fortran order), or NULL (ranks and Z only)
+ *   beta       : r1*r2*r3 output (Fortran order; doubles, or floats with the handle's
+ *                beta_fp32 option), or NULL (ranks and Z only)
  *   result     : int32[8]: r1, r2, r3, status (rhosvd_status of this problem:
  *                OK, ERR_NONFINITE, ERR_CAPACITY, or ERR_DEVICE when an
  *                eigensolver wait ran out), dropped terms, 3 reserved
@@ -180,7 +184,7 @@ typedef struct {
     double* Z1;
     double* Z2;
     double* Z3;
-    double* beta;
+    void* beta;
     int32_t* result;
 } rhosvd_problem;
 

@@ -111,7 +111,7 @@ rhosvd_status fail(rhosvd_ctx* h, rhosvd_status s, const std::string& msg) {
 rhosvd_status check_options(const rhosvd_options* o, std::string& msg) {
     if (!o) return RHOSVD_OK;
     if (o->precision < 0 || o->precision > 2) { msg = "unknown precision"; return RHOSVD_ERR_ARG; }
-    for (int i = 0; i < 5; ++i)
+    for (int i = 0; i < 4; ++i)
         if (o->reserved[i] != 0) { msg = "reserved option fields must be zero"; return RHOSVD_ERR_ARG; }
     return RHOSVD_OK;
 }
@@ -467,7 +467,7 @@ rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R, const double*
     return RHOSVD_OK;
 }
 
-rhosvd_status rhosvd_get(rhosvd_handle h, double* Z1, double* Z2, double* Z3, double* beta, double* sigma,
+rhosvd_status rhosvd_get(rhosvd_handle h, double* Z1, double* Z2, double* Z3, void* beta, double* sigma,
                          rhosvd_report* report) {
     if (!h) return RHOSVD_ERR_ARG;
     if (!h->have) return fail(h, RHOSVD_ERR_STATE, "no successful rhosvd_reduce on this handle");
@@ -485,6 +485,7 @@ rhosvd_status rhosvd_get(rhosvd_handle h, double* Z1, double* Z2, double* Z3, do
         ca.xip = h->xip;
         ca.beta = beta;
         ca.prec = h->vprec;
+        ca.beta_f32 = h->opt.beta_fp32 != 0;
         CK(h, launch_core(ca, st));
     }
     if (h->opt.profile && h->ev_ok) hipEventRecord(h->ev[8], st);
@@ -572,7 +573,8 @@ rhosvd_status rhosvd_reduce_batched(rhosvd_handle h, int32_t count, const rhosvd
     std::string msg;
     const int vs = batch_validate(problems, count, msg);
     if (vs != RHOSVD_OK) return fail(h, (rhosvd_status)vs, msg);
-    if (!batch_plan_matches(h->batch, problems, count, h->opt.precision)) {
+    const int prec_key = h->opt.precision | (h->opt.beta_fp32 ? 16 : 0);
+    if (!batch_plan_matches(h->batch, problems, count, prec_key)) {
         // earlier work on the stream may still use the old plan's memory
         CK(h, hipStreamSynchronize(h->stream));
         if (h->batch) {
@@ -580,7 +582,7 @@ rhosvd_status rhosvd_reduce_batched(rhosvd_handle h, int32_t count, const rhosvd
             h->batch = nullptr;
         }
         std::string err;
-        h->batch = batch_plan_create(problems, count, h->opt.precision, err);
+        h->batch = batch_plan_create(problems, count, prec_key, err);
         if (!h->batch) return fail(h, RHOSVD_ERR_ALLOC, err);
     }
     CK(h, batch_plan_run(h->batch, h->stream));

@@ -73,6 +73,7 @@ __global__ __launch_bounds__(256) void k_finish_b(const BProb* __restrict__ P) {
 struct BatchPlan {
     std::vector<rhosvd_problem> key;
     int prec = 0;
+    int prec_key = 0;
     std::vector<BProb> hp;
     // device memory
     char* ws = nullptr;
@@ -274,8 +275,10 @@ int batch_validate(const rhosvd_problem* probs, int count, std::string& msg) {
 
 BatchPlan* batch_plan_create(const rhosvd_problem* probs, int count, int prec, std::string& err) {
     BatchPlan* B = new BatchPlan();
+    // prec: the core precision, plus 16 when beta is written as float
     B->key.assign(probs, probs + count);
-    B->prec = prec;
+    B->prec = prec & 3;
+    B->prec_key = prec;
     B->hp.resize(count);
     for (int p = 0; p < count; ++p) {
         const rhosvd_problem& d = probs[p];
@@ -301,6 +304,7 @@ BatchPlan* batch_plan_create(const rhosvd_problem* probs, int count, int prec, s
         q.Zo[2] = d.Z3;
         q.beta = d.beta;
         q.cap_beta = d.cap_beta;
+        q.beta_f32 = (prec & 16) ? 1 : 0;
         q.result = d.result;
     }
     const size_t need = carve_batch(*B, nullptr);
@@ -353,7 +357,7 @@ BatchPlan* batch_plan_create(const rhosvd_problem* probs, int count, int prec, s
             return nullptr;
         }
     }
-    B->core_grid = core_b_max_grid(prec);
+    B->core_grid = core_b_max_grid(B->prec);
     // record the pass into a graph; on any failure the pass runs eagerly
     const char* env = getenv("RHOSVD_BATCH_GRAPH");
     if (!(env && env[0] == '0') && hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking) == hipSuccess) {
@@ -375,7 +379,7 @@ BatchPlan* batch_plan_create(const rhosvd_problem* probs, int count, int prec, s
 }
 
 bool batch_plan_matches(const BatchPlan* B, const rhosvd_problem* probs, int count, int prec) {
-    return B && B->prec == prec && same_key(B->key, probs, count);
+    return B && B->prec_key == prec && same_key(B->key, probs, count);
 }
 
 hipError_t batch_plan_run(BatchPlan* B, hipStream_t st) {

@@ -27,10 +27,15 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t per) {
     return (bid % NXCD) * per + bid / NXCD;
 }
 
+// beta entries are written as double, or as float when f32 (the mixed cores' option)
 template <typename T>
-__device__ __forceinline__ void store_beta(double* __restrict__ beta, int r1, int r2, int r3, int j1, int j2,
+__device__ __forceinline__ void store_beta(void* __restrict__ beta, int f32, int r1, int r2, int r3, int j1, int j2,
                                            int j3, T v) {
-    if (j1 < r1 && j2 < r2 && j3 < r3) beta[(int64_t)j1 + (int64_t)r1 * ((int64_t)j2 + (int64_t)r2 * j3)] = (double)v;
+    if (j1 < r1 && j2 < r2 && j3 < r3) {
+        const int64_t o = (int64_t)j1 + (int64_t)r1 * ((int64_t)j2 + (int64_t)r2 * j3);
+        if (f32) ((float*)beta)[o] = (float)v;
+        else ((double*)beta)[o] = (double)v;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -54,7 +59,7 @@ struct MF<float> {
 template <typename T>
 __device__ void core_tile_std(int r1, int r2, int r3, int ld1, int ld2, int ld3, int64_t Kp,
                               const T* __restrict__ V1, const T* __restrict__ V2, const T* __restrict__ V3,
-                              const double* __restrict__ xip, double* __restrict__ beta, int N2T, int N3T,
+                              const double* __restrict__ xip, void* __restrict__ beta, int f32, int N2T, int N3T,
                               int64_t tile) {
     constexpr int TM = 64, KC = 16;
     typedef typename MF<T>::acc_t acc_t;
@@ -123,7 +128,7 @@ __device__ void core_tile_std(int r1, int r2, int r3, int ld1, int ld2, int ld3,
         for (int g = 0; g < 4; ++g)
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                store_beta(beta, r1, r2, r3, m0 + 16 * f + MF<T>::row(lane, i), b2 + c_col(lane), b3 + 4 * w + g,
+                store_beta(beta, f32, r1, r2, r3, m0 + 16 * f + MF<T>::row(lane, i), b2 + c_col(lane), b3 + 4 * w + g,
                            acc[f][g][i]);
 }
 
@@ -131,11 +136,11 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_core_std(int r1, int r2, int r3, int ld1, int ld2, int ld3,
                                                   int64_t Kp, const T* __restrict__ V1,
                                                   const T* __restrict__ V2, const T* __restrict__ V3,
-                                                  const double* __restrict__ xip, double* __restrict__ beta,
+                                                  const double* __restrict__ xip, void* __restrict__ beta, int f32,
                                                   int MT, int N2T, int N3T, int64_t per) {
     const int64_t tile = xcd_tile(blockIdx.x, per);
     if (tile >= (int64_t)MT * N2T * N3T) return;
-    core_tile_std<T>(r1, r2, r3, ld1, ld2, ld3, Kp, V1, V2, V3, xip, beta, N2T, N3T, tile);
+    core_tile_std<T>(r1, r2, r3, ld1, ld2, ld3, Kp, V1, V2, V3, xip, beta, f32, N2T, N3T, tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -151,7 +156,7 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
 __device__ void core_tile_bf16x3(int r1, int r2, int r3, int ld1, int ld2, int ld3, int64_t Kp,
                                  const float* __restrict__ V1, const float* __restrict__ V2,
                                  const float* __restrict__ V3, const double* __restrict__ xip,
-                                 double* __restrict__ beta, int N2T, int N3T, int64_t tile) {
+                                 void* __restrict__ beta, int f32, int N2T, int N3T, int64_t tile) {
     __shared__ __attribute__((aligned(16))) __bf16 sAh[2][BTM * BLDA];
     __shared__ __attribute__((aligned(16))) __bf16 sAl[2][BTM * BLDA];
     __shared__ float s2[2][BKC][TN2];
@@ -243,18 +248,18 @@ __device__ void core_tile_bf16x3(int r1, int r2, int r3, int ld1, int ld2, int l
         for (int g = 0; g < 4; ++g)
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                store_beta(beta, r1, r2, r3, m0 + 16 * f + c_row32(lane, i), b2 + c_col(lane), b3 + 4 * w + g,
+                store_beta(beta, f32, r1, r2, r3, m0 + 16 * f + c_row32(lane, i), b2 + c_col(lane), b3 + 4 * w + g,
                            acc[f][g][i]);
 }
 
 __global__ __launch_bounds__(256) void k_core_bf16x3(int r1, int r2, int r3, int ld1, int ld2, int ld3,
                                                      int64_t Kp, const float* __restrict__ V1,
                                                      const float* __restrict__ V2, const float* __restrict__ V3,
-                                                     const double* __restrict__ xip, double* __restrict__ beta,
+                                                     const double* __restrict__ xip, void* __restrict__ beta, int f32,
                                                      int MT, int N2T, int N3T, int64_t per) {
     const int64_t tile = xcd_tile(blockIdx.x, per);
     if (tile >= (int64_t)MT * N2T * N3T) return;
-    core_tile_bf16x3(r1, r2, r3, ld1, ld2, ld3, Kp, V1, V2, V3, xip, beta, N2T, N3T, tile);
+    core_tile_bf16x3(r1, r2, r3, ld1, ld2, ld3, Kp, V1, V2, V3, xip, beta, f32, N2T, N3T, tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -303,13 +308,13 @@ __global__ __launch_bounds__(256) void k_core_persist_b(const BProb* __restrict_
         const int64_t local = tile - pre[lo];
         if (PREC == 0)
             core_tile_std<double>(r1, r2, r3, q.rcap_pad, q.rcap_pad, q.rcap_pad, q.R_pad, (const double*)q.V[0],
-                                  (const double*)q.V[1], (const double*)q.V[2], q.xip, q.beta, N2T, N3T, local);
+                                  (const double*)q.V[1], (const double*)q.V[2], q.xip, q.beta, q.beta_f32, N2T, N3T, local);
         else if (PREC == 1)
             core_tile_std<float>(r1, r2, r3, q.rcap_pad, q.rcap_pad, q.rcap_pad, q.R_pad, (const float*)q.V[0],
-                                 (const float*)q.V[1], (const float*)q.V[2], q.xip, q.beta, N2T, N3T, local);
+                                 (const float*)q.V[1], (const float*)q.V[2], q.xip, q.beta, q.beta_f32, N2T, N3T, local);
         else
             core_tile_bf16x3(r1, r2, r3, q.rcap_pad, q.rcap_pad, q.rcap_pad, q.R_pad, (const float*)q.V[0],
-                             (const float*)q.V[1], (const float*)q.V[2], q.xip, q.beta, N2T, N3T, local);
+                             (const float*)q.V[1], (const float*)q.V[2], q.xip, q.beta, q.beta_f32, N2T, N3T, local);
     }
 }
 
@@ -329,15 +334,15 @@ hipError_t launch_core(const CoreArgs& a, hipStream_t st) {
     if (a.prec == 0) {
         hipLaunchKernelGGL(k_core_std<double>, grid, dim3(256), 0, st, a.r[0], a.r[1], a.r[2], a.r_pad[0], a.r_pad[1],
                            a.r_pad[2], a.R_pad, (const double*)a.V[0], (const double*)a.V[1],
-                           (const double*)a.V[2], a.xip, a.beta, MT, N2T, N3T, per);
+                           (const double*)a.V[2], a.xip, a.beta, a.beta_f32, MT, N2T, N3T, per);
     } else if (a.prec == 1) {
         hipLaunchKernelGGL(k_core_std<float>, grid, dim3(256), 0, st, a.r[0], a.r[1], a.r[2], a.r_pad[0], a.r_pad[1],
                            a.r_pad[2], a.R_pad, (const float*)a.V[0], (const float*)a.V[1],
-                           (const float*)a.V[2], a.xip, a.beta, MT, N2T, N3T, per);
+                           (const float*)a.V[2], a.xip, a.beta, a.beta_f32, MT, N2T, N3T, per);
     } else {
         hipLaunchKernelGGL(k_core_bf16x3, grid, dim3(256), 0, st, a.r[0], a.r[1], a.r[2], a.r_pad[0], a.r_pad[1],
                            a.r_pad[2], a.R_pad, (const float*)a.V[0], (const float*)a.V[1],
-                           (const float*)a.V[2], a.xip, a.beta, MT, N2T, N3T, per);
+                           (const float*)a.V[2], a.xip, a.beta, a.beta_f32, MT, N2T, N3T, per);
     }
     return hipGetLastError();
 }

@@ -134,8 +134,9 @@ struct CoreArgs {
     int64_t R_pad;
     const void* V[3];
     const double* xip;
-    double* beta;
+    void* beta;       // double, or float when beta_f32
     int prec;
+    int beta_f32;
 };
 hipError_t launch_core(const CoreArgs& a, hipStream_t st);
 
@@ -167,8 +168,9 @@ struct BProb {
     double* Z[3];          // n_pad x rcap_pad
     void* V[3];            // rcap_pad x R_pad (FP64, or FP32 for the mixed cores)
     double* Zo[3];         // caller outputs, n x cap_rank (ld n), or null
-    double* beta;          // caller output or null
+    void* beta;            // caller output (double, or float when beta_f32) or null
     int64_t cap_beta;
+    int beta_f32;
     int* result;           // caller's int32[8]: r1, r2, r3, status
 };
 enum { BK_COLNORM = 0, BK_ANORM = 1, BK_GRAM = 2, BK_PROJECT = 3, BK_SIGN = 4 };
@@ -191,6 +193,7 @@ hipError_t launch_finish_b(const BProb* P, int np, hipStream_t st);
 // Batch plans (batch.hip): validation, layout + uploads + graph capture, replay.
 struct BatchPlan;
 int batch_validate(const rhosvd_problem* probs, int count, std::string& msg);   // rhosvd_status
+// prec: core precision (0..2), plus 16 when beta is written as float
 BatchPlan* batch_plan_create(const rhosvd_problem* probs, int count, int prec, std::string& err);
 bool batch_plan_matches(const BatchPlan* plan, const rhosvd_problem* probs, int count, int prec);
 hipError_t batch_plan_run(BatchPlan* plan, hipStream_t st);

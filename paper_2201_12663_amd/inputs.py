@@ -162,6 +162,36 @@ def batch_problem(seed: int, index: int, n: int, R: int, eps: float = 1e-5) -> C
     return CanonicalInput(U, full.xi[:R].copy(), eps, name=f"batch{index}-n{n}-R{R}")
 
 
+def batch_problem_params(seed: int, index: int, n: int, R: int, eps: float = 1e-5):
+    """The random draws of batch_problem (alpha, centres (R, 3), xi) without
+    sampling the side matrices: the same Philox stream, so the tensors built from
+    them on any device are the ones batch_problem returns."""
+    nc = (R + 31) // 32
+    g = rng(WL_BATCH, seed * 4096 + index)
+    centres_c = g.uniform(-6.0, 6.0, size=(nc, 3))
+    q = np.where(g.uniform(size=nc) < 0.5, -1.0, 1.0)
+    alpha_k, w_k = newton_gaussian_sum(32)
+    alpha = np.tile(alpha_k, nc)[:R]
+    centres = np.repeat(centres_c, 32, axis=0)[:R]
+    xi = (np.repeat(q, 32) * np.tile(w_k, nc))[:R]
+    return alpha, centres, xi
+
+
+def gaussian_side_matrices_torch(n: int, alpha: np.ndarray, centres: np.ndarray, b: float = 10.0,
+                                 device: str = "cuda") -> list:
+    """gaussian_side_matrices sampled with torch on `device`: three (n, R)
+    column-major float64 tensors (for inputs too large to build on the host)."""
+    import torch
+    x = torch.from_numpy(grid(n, b)).to(device)
+    a = torch.from_numpy(np.ascontiguousarray(alpha)).to(device)
+    out = []
+    for l in range(3):
+        c = torch.from_numpy(np.ascontiguousarray(centres[:, l])).to(device)
+        d = x[None, :] - c[:, None]                   # (R, n): row nu is column nu of U
+        out.append(torch.exp(-a[:, None] * d * d).t())
+    return out
+
+
 def exactly_low_rank(seed: int, n: int, R: int, ranks=(3, 4, 5), eps: float = 1e-8,
                      signed: bool = True) -> CanonicalInput:
     """U^(l) = Q_l C_l with Q_l (n x r_l) orthonormal and C_l (r_l x R) Gaussian, so

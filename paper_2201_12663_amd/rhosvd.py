@@ -29,7 +29,7 @@ EXPORTS = ["rhosvd_create", "rhosvd_destroy", "rhosvd_set_options", "rhosvd_redu
 
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("max_eig_sweeps", ctypes.c_int32),
-                ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("profile", ctypes.c_int32), ("beta_fp32", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 class Report(ctypes.Structure):
@@ -125,10 +125,12 @@ class Result:
 class Reducer:
     """One library handle bound to a stream."""
 
-    def __init__(self, precision="fp64", stream=None, max_eig_sweeps=0, profile=False):
+    def __init__(self, precision="fp64", stream=None, max_eig_sweeps=0, profile=False, beta_fp32=False):
         import torch
         self.lib = load()
         self.opt = Options()
+        self.opt.beta_fp32 = 1 if beta_fp32 else 0
+        self.beta_dtype = torch.float32 if beta_fp32 else torch.float64
         self.opt.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self.opt.max_eig_sweeps = int(max_eig_sweeps)
         self.opt.profile = 1 if profile else 0
@@ -187,11 +189,11 @@ class Reducer:
         b = None
         if beta:
             if beta_out is not None:
-                if beta_out.numel() < r1 * r2 * r3 or beta_out.dtype != torch.float64:
-                    raise ValueError("beta_out too small or not float64")
+                if beta_out.numel() < r1 * r2 * r3 or beta_out.dtype != self.beta_dtype:
+                    raise ValueError(f"beta_out too small or not {self.beta_dtype}")
                 flat = beta_out
             else:
-                flat = torch.empty(r1 * r2 * r3, dtype=torch.float64, device=dev)
+                flat = torch.empty(r1 * r2 * r3, dtype=self.beta_dtype, device=dev)
             b = flat[: r1 * r2 * r3]
         sig = torch.empty(r1 + r2 + r3, dtype=torch.float64, device=dev) if sigma else None
         rep = Report()
@@ -208,6 +210,8 @@ class Reducer:
 
     def core_only(self, beta_flat):
         """Enqueue only the core contraction into beta_flat (for timing loops)."""
+        if beta_flat.dtype != self.beta_dtype:
+            raise ValueError(f"beta_flat must be {self.beta_dtype}")
         self._check(self.lib.rhosvd_get(self.h, None, None, None, ctypes.c_void_p(beta_flat.data_ptr()),
                                         None, None))
 
@@ -239,7 +243,7 @@ class Reducer:
         problems: list of (U1, U2, U3, xi, eps) with column-major CUDA tensors.
         results:  (count, 8) int32 CUDA tensor (ranks, status, dropped).
         outputs:  None (ranks only), or a list of (Z1, Z2, Z3, beta_flat) per problem
-                  (Z_l: (n, cap) column-major float64, beta_flat: float64 or None).
+                  (Z_l: (n, cap) column-major float64, beta_flat: the handle's beta dtype, or None).
         cap_rank: per-problem rank caps when outputs is None (default min(n, R))."""
         import torch
         if not (results.is_cuda and results.dtype == torch.int32 and results.is_contiguous()
@@ -270,6 +274,8 @@ class Reducer:
                 if d.cap_rank < 1:
                     d.cap_rank = 1
                 if b is not None and b.numel() > 0:
+                    if b.dtype != self.beta_dtype:
+                        raise ValueError(f"beta outputs must be {self.beta_dtype}")
                     d.beta = b.data_ptr()
                     d.cap_beta = int(b.numel())
         return arr
@@ -297,7 +303,7 @@ class Reducer:
             r = [int(x) for x in ranks[i, :3]]
             cap = max(1, max(r))
             Zs = [colmajor_empty(n, cap) for _ in range(3)]
-            b = torch.empty(max(1, r[0] * r[1] * r[2]), dtype=torch.float64, device="cuda") if beta else None
+            b = torch.empty(max(1, r[0] * r[1] * r[2]), dtype=self.beta_dtype, device="cuda") if beta else None
             outs.append((Zs[0], Zs[1], Zs[2], b))
         res2 = torch.zeros((count, 8), dtype=torch.int32, device="cuda")
         desc = self.batch_descriptors(problems, res2, outputs=outs)

@@ -247,3 +247,27 @@ def test_batched_uneven_config_sample():
     torch.cuda.synchronize()
     red.close()
     single.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_beta_fp32_output_is_the_rounded_core(batch_inputs, prec):
+    """With the beta_fp32 option the core (accumulated in FP32) is stored as float:
+    exactly the double output rounded to float, on the single path and batched."""
+    import torch
+    from paper_2201_12663_amd import rhosvd
+    ci = batch_inputs[5]
+    p = to_dev(ci)
+    a = rhosvd.Reducer(precision=prec)
+    b = rhosvd.Reducer(precision=prec, beta_fp32=True)
+    a.reduce(*p)
+    b.reduce(*p)
+    ra, rb = a.get(Z=False, sigma=False), b.get(Z=False, sigma=False)
+    torch.cuda.synchronize()
+    assert rb.beta.dtype == torch.float32
+    assert torch.equal(rb.beta, ra.beta.float())
+    oa, _, _, _ = a.reduce_batched([p])
+    ob, _, _, _ = b.reduce_batched([p])
+    torch.cuda.synchronize()
+    assert torch.equal(ob[0]["beta"], oa[0]["beta"].float())
+    a.close()
+    b.close()
