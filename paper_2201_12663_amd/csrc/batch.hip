@@ -240,7 +240,7 @@ hipError_t enqueue_batch(const BatchPlan& B, hipStream_t st, bool coop) {
     }
     if ((e = launch_batched_dense(BK_SIGN, P, B.pre[4], np, B.nblk[4], 0, st)) != hipSuccess) return e;
     if ((e = launch_batched_dense(BK_PROJECT, P, B.pre[3], np, B.nblk[3], B.prec != 0, st)) != hipSuccess) return e;
-    if ((e = launch_core_b(P, np, B.prec, B.core_work, B.core_grid, st)) != hipSuccess) return e;
+    if ((e = launch_core_b(P, np, B.prec_key, B.core_work, B.core_grid, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_finish_b, dim3((unsigned)np, 3, 8), dim3(256), 0, st, P);
     return hipGetLastError();
 }
@@ -357,7 +357,7 @@ BatchPlan* batch_plan_create(const rhosvd_problem* probs, int count, int prec, s
             return nullptr;
         }
     }
-    B->core_grid = core_b_max_grid(B->prec);
+    B->core_grid = core_b_max_grid(B->prec_key);
     // record the pass into a graph; on any failure the pass runs eagerly
     const char* env = getenv("RHOSVD_BATCH_GRAPH");
     if (!(env && env[0] == '0') && hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking) == hipSuccess) {

@@ -27,15 +27,10 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t per) {
     return (bid % NXCD) * per + bid / NXCD;
 }
 
-// beta entries are written as double, or as float when f32 (the mixed cores' option)
-template <typename T>
-__device__ __forceinline__ void store_beta(void* __restrict__ beta, int f32, int r1, int r2, int r3, int j1, int j2,
-                                           int j3, T v) {
-    if (j1 < r1 && j2 < r2 && j3 < r3) {
-        const int64_t o = (int64_t)j1 + (int64_t)r1 * ((int64_t)j2 + (int64_t)r2 * j3);
-        if (f32) ((float*)beta)[o] = (float)v;
-        else ((double*)beta)[o] = (double)v;
-    }
+// beta entries are written as O: double, or float (the mixed cores' option)
+template <typename O, typename T>
+__device__ __forceinline__ void store_beta(O* __restrict__ beta, int r1, int r2, int r3, int j1, int j2, int j3, T v) {
+    if (j1 < r1 && j2 < r2 && j3 < r3) beta[(int64_t)j1 + (int64_t)r1 * ((int64_t)j2 + (int64_t)r2 * j3)] = (O)v;
 }
 
 // ---------------------------------------------------------------------------
@@ -56,10 +51,10 @@ struct MF<float> {
     static __device__ __forceinline__ int row(int lane, int i) { return c_row32(lane, i); }
 };
 
-template <typename T>
-__device__ void core_tile_std(int r1, int r2, int r3, int ld1, int ld2, int ld3, int64_t Kp,
+template <typename T, typename O>
+__device__ __forceinline__ void core_tile_std(int r1, int r2, int r3, int ld1, int ld2, int ld3, int64_t Kp,
                               const T* __restrict__ V1, const T* __restrict__ V2, const T* __restrict__ V3,
-                              const double* __restrict__ xip, void* __restrict__ beta, int f32, int N2T, int N3T,
+                              const double* __restrict__ xip, O* __restrict__ beta, int N2T, int N3T,
                               int64_t tile) {
     constexpr int TM = 64, KC = 16;
     typedef typename MF<T>::acc_t acc_t;
@@ -128,19 +123,19 @@ __device__ void core_tile_std(int r1, int r2, int r3, int ld1, int ld2, int ld3,
         for (int g = 0; g < 4; ++g)
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                store_beta(beta, f32, r1, r2, r3, m0 + 16 * f + MF<T>::row(lane, i), b2 + c_col(lane), b3 + 4 * w + g,
+                store_beta<O>(beta, r1, r2, r3, m0 + 16 * f + MF<T>::row(lane, i), b2 + c_col(lane), b3 + 4 * w + g,
                            acc[f][g][i]);
 }
 
-template <typename T>
+template <typename T, typename O>
 __global__ __launch_bounds__(256) void k_core_std(int r1, int r2, int r3, int ld1, int ld2, int ld3,
                                                   int64_t Kp, const T* __restrict__ V1,
                                                   const T* __restrict__ V2, const T* __restrict__ V3,
-                                                  const double* __restrict__ xip, void* __restrict__ beta, int f32,
+                                                  const double* __restrict__ xip, O* __restrict__ beta,
                                                   int MT, int N2T, int N3T, int64_t per) {
     const int64_t tile = xcd_tile(blockIdx.x, per);
     if (tile >= (int64_t)MT * N2T * N3T) return;
-    core_tile_std<T>(r1, r2, r3, ld1, ld2, ld3, Kp, V1, V2, V3, xip, beta, f32, N2T, N3T, tile);
+    core_tile_std<T, O>(r1, r2, r3, ld1, ld2, ld3, Kp, V1, V2, V3, xip, beta, N2T, N3T, tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -153,10 +148,11 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
     lo = (__bf16)(x - (float)hi);
 }
 
-__device__ void core_tile_bf16x3(int r1, int r2, int r3, int ld1, int ld2, int ld3, int64_t Kp,
+template <typename O>
+__device__ __forceinline__ void core_tile_bf16x3(int r1, int r2, int r3, int ld1, int ld2, int ld3, int64_t Kp,
                                  const float* __restrict__ V1, const float* __restrict__ V2,
                                  const float* __restrict__ V3, const double* __restrict__ xip,
-                                 void* __restrict__ beta, int f32, int N2T, int N3T, int64_t tile) {
+                                 O* __restrict__ beta, int N2T, int N3T, int64_t tile) {
     __shared__ __attribute__((aligned(16))) __bf16 sAh[2][BTM * BLDA];
     __shared__ __attribute__((aligned(16))) __bf16 sAl[2][BTM * BLDA];
     __shared__ float s2[2][BKC][TN2];
@@ -248,18 +244,19 @@ __device__ void core_tile_bf16x3(int r1, int r2, int r3, int ld1, int ld2, int l
         for (int g = 0; g < 4; ++g)
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                store_beta(beta, f32, r1, r2, r3, m0 + 16 * f + c_row32(lane, i), b2 + c_col(lane), b3 + 4 * w + g,
+                store_beta<O>(beta, r1, r2, r3, m0 + 16 * f + c_row32(lane, i), b2 + c_col(lane), b3 + 4 * w + g,
                            acc[f][g][i]);
 }
 
+template <typename O>
 __global__ __launch_bounds__(256) void k_core_bf16x3(int r1, int r2, int r3, int ld1, int ld2, int ld3,
                                                      int64_t Kp, const float* __restrict__ V1,
                                                      const float* __restrict__ V2, const float* __restrict__ V3,
-                                                     const double* __restrict__ xip, void* __restrict__ beta, int f32,
+                                                     const double* __restrict__ xip, O* __restrict__ beta,
                                                      int MT, int N2T, int N3T, int64_t per) {
     const int64_t tile = xcd_tile(blockIdx.x, per);
     if (tile >= (int64_t)MT * N2T * N3T) return;
-    core_tile_bf16x3(r1, r2, r3, ld1, ld2, ld3, Kp, V1, V2, V3, xip, beta, f32, N2T, N3T, tile);
+    core_tile_bf16x3<O>(r1, r2, r3, ld1, ld2, ld3, Kp, V1, V2, V3, xip, beta, N2T, N3T, tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -283,7 +280,7 @@ __global__ void k_core_plan_b(const BProb* __restrict__ P, int np, int tm, int64
     work[0] = 0;
 }
 
-template <int PREC>
+template <int PREC, typename O>
 __global__ __launch_bounds__(256) void k_core_persist_b(const BProb* __restrict__ P, int np,
                                                         int64_t* __restrict__ work) {
     __shared__ int64_t s_tile;
@@ -307,18 +304,36 @@ __global__ __launch_bounds__(256) void k_core_persist_b(const BProb* __restrict_
         const int N2T = (int)ceil_div(r2, TN2), N3T = (int)ceil_div(r3, TN3);
         const int64_t local = tile - pre[lo];
         if (PREC == 0)
-            core_tile_std<double>(r1, r2, r3, q.rcap_pad, q.rcap_pad, q.rcap_pad, q.R_pad, (const double*)q.V[0],
-                                  (const double*)q.V[1], (const double*)q.V[2], q.xip, q.beta, q.beta_f32, N2T, N3T, local);
+            core_tile_std<double, O>(r1, r2, r3, q.rcap_pad, q.rcap_pad, q.rcap_pad, q.R_pad, (const double*)q.V[0],
+                                  (const double*)q.V[1], (const double*)q.V[2], q.xip, (O*)q.beta, N2T, N3T, local);
         else if (PREC == 1)
-            core_tile_std<float>(r1, r2, r3, q.rcap_pad, q.rcap_pad, q.rcap_pad, q.R_pad, (const float*)q.V[0],
-                                 (const float*)q.V[1], (const float*)q.V[2], q.xip, q.beta, q.beta_f32, N2T, N3T, local);
+            core_tile_std<float, O>(r1, r2, r3, q.rcap_pad, q.rcap_pad, q.rcap_pad, q.R_pad, (const float*)q.V[0],
+                                 (const float*)q.V[1], (const float*)q.V[2], q.xip, (O*)q.beta, N2T, N3T, local);
         else
-            core_tile_bf16x3(r1, r2, r3, q.rcap_pad, q.rcap_pad, q.rcap_pad, q.R_pad, (const float*)q.V[0],
-                             (const float*)q.V[1], (const float*)q.V[2], q.xip, q.beta, q.beta_f32, N2T, N3T, local);
+            core_tile_bf16x3<O>(r1, r2, r3, q.rcap_pad, q.rcap_pad, q.rcap_pad, q.R_pad, (const float*)q.V[0],
+                             (const float*)q.V[1], (const float*)q.V[2], q.xip, (O*)q.beta, N2T, N3T, local);
     }
 }
 
 }  // namespace
+
+template <typename O>
+static void launch_core_t(const CoreArgs& a, dim3 grid, int MT, int N2T, int N3T, int64_t per, hipStream_t st) {
+    O* beta = (O*)a.beta;
+    if (a.prec == 0) {
+        hipLaunchKernelGGL((k_core_std<double, O>), grid, dim3(256), 0, st, a.r[0], a.r[1], a.r[2], a.r_pad[0],
+                           a.r_pad[1], a.r_pad[2], a.R_pad, (const double*)a.V[0], (const double*)a.V[1],
+                           (const double*)a.V[2], a.xip, beta, MT, N2T, N3T, per);
+    } else if (a.prec == 1) {
+        hipLaunchKernelGGL((k_core_std<float, O>), grid, dim3(256), 0, st, a.r[0], a.r[1], a.r[2], a.r_pad[0],
+                           a.r_pad[1], a.r_pad[2], a.R_pad, (const float*)a.V[0], (const float*)a.V[1],
+                           (const float*)a.V[2], a.xip, beta, MT, N2T, N3T, per);
+    } else {
+        hipLaunchKernelGGL((k_core_bf16x3<O>), grid, dim3(256), 0, st, a.r[0], a.r[1], a.r[2], a.r_pad[0],
+                           a.r_pad[1], a.r_pad[2], a.R_pad, (const float*)a.V[0], (const float*)a.V[1],
+                           (const float*)a.V[2], a.xip, beta, MT, N2T, N3T, per);
+    }
+}
 
 hipError_t launch_core(const CoreArgs& a, hipStream_t st) {
     if (a.r[0] < 1 || a.r[1] < 1 || a.r[2] < 1) return hipSuccess;
@@ -331,30 +346,25 @@ hipError_t launch_core(const CoreArgs& a, hipStream_t st) {
     const int64_t ntile = (int64_t)MT * N2T * N3T;
     const int64_t per = ceil_div(ntile, NXCD);
     dim3 grid((unsigned)(per * NXCD));
-    if (a.prec == 0) {
-        hipLaunchKernelGGL(k_core_std<double>, grid, dim3(256), 0, st, a.r[0], a.r[1], a.r[2], a.r_pad[0], a.r_pad[1],
-                           a.r_pad[2], a.R_pad, (const double*)a.V[0], (const double*)a.V[1],
-                           (const double*)a.V[2], a.xip, a.beta, a.beta_f32, MT, N2T, N3T, per);
-    } else if (a.prec == 1) {
-        hipLaunchKernelGGL(k_core_std<float>, grid, dim3(256), 0, st, a.r[0], a.r[1], a.r[2], a.r_pad[0], a.r_pad[1],
-                           a.r_pad[2], a.R_pad, (const float*)a.V[0], (const float*)a.V[1],
-                           (const float*)a.V[2], a.xip, a.beta, a.beta_f32, MT, N2T, N3T, per);
-    } else {
-        hipLaunchKernelGGL(k_core_bf16x3, grid, dim3(256), 0, st, a.r[0], a.r[1], a.r[2], a.r_pad[0], a.r_pad[1],
-                           a.r_pad[2], a.R_pad, (const float*)a.V[0], (const float*)a.V[1],
-                           (const float*)a.V[2], a.xip, a.beta, a.beta_f32, MT, N2T, N3T, per);
-    }
+    if (a.beta_f32) launch_core_t<float>(a, grid, MT, N2T, N3T, per, st);
+    else launch_core_t<double>(a, grid, MT, N2T, N3T, per, st);
     return hipGetLastError();
+}
+
+template <typename O>
+static void launch_persist_t(const BProb* P, int np, int prec, int64_t* work, int grid, hipStream_t st) {
+    if (prec == 0) hipLaunchKernelGGL((k_core_persist_b<0, O>), dim3((unsigned)grid), dim3(256), 0, st, P, np, work);
+    else if (prec == 1) hipLaunchKernelGGL((k_core_persist_b<1, O>), dim3((unsigned)grid), dim3(256), 0, st, P, np, work);
+    else hipLaunchKernelGGL((k_core_persist_b<2, O>), dim3((unsigned)grid), dim3(256), 0, st, P, np, work);
 }
 
 hipError_t launch_core_b(const BProb* P, int np, int prec, int64_t* work, int grid, hipStream_t st) {
     if (np < 1) return hipSuccess;
-    hipLaunchKernelGGL(k_core_plan_b, dim3(1), dim3(64), 0, st, P, np, prec == 2 ? BTM : 64, work);
+    hipLaunchKernelGGL(k_core_plan_b, dim3(1), dim3(64), 0, st, P, np, (prec & 3) == 2 ? BTM : 64, work);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (prec == 0) hipLaunchKernelGGL(k_core_persist_b<0>, dim3((unsigned)grid), dim3(256), 0, st, P, np, work);
-    else if (prec == 1) hipLaunchKernelGGL(k_core_persist_b<1>, dim3((unsigned)grid), dim3(256), 0, st, P, np, work);
-    else hipLaunchKernelGGL(k_core_persist_b<2>, dim3((unsigned)grid), dim3(256), 0, st, P, np, work);
+    if (prec & 16) launch_persist_t<float>(P, np, prec & 3, work, grid, st);
+    else launch_persist_t<double>(P, np, prec & 3, work, grid, st);
     return hipGetLastError();
 }
 
@@ -362,8 +372,13 @@ int core_b_max_grid(int prec) {
     int dev = 0, ncu = 0, occ = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 256;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 256;
-    const void* f = prec == 0 ? (const void*)k_core_persist_b<0>
-                              : (prec == 1 ? (const void*)k_core_persist_b<1> : (const void*)k_core_persist_b<2>);
+    const bool f32 = (prec & 16) != 0;
+    const void* f;
+    switch (prec & 3) {
+        case 0: f = f32 ? (const void*)k_core_persist_b<0, float> : (const void*)k_core_persist_b<0, double>; break;
+        case 1: f = f32 ? (const void*)k_core_persist_b<1, float> : (const void*)k_core_persist_b<1, double>; break;
+        default: f = f32 ? (const void*)k_core_persist_b<2, float> : (const void*)k_core_persist_b<2, double>; break;
+    }
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, 256, 0) != hipSuccess || occ < 1) occ = 1;
     return ncu * occ;
 }

@@ -8,7 +8,7 @@
 // xi'_nu = xi_nu * s1 * s2 * s3; a term with xi = 0 or a zero column is dropped
 // (xi' = 0, normalized columns zero).  Padded rows/terms are written as zero.
 // ===========================================================================
-__device__ void colnorm_term(int64_t n, int64_t R, int64_t n_pad, int64_t R_pad, const double* __restrict__ U0,
+__device__ __forceinline__ void colnorm_term(int64_t n, int64_t R, int64_t n_pad, int64_t R_pad, const double* __restrict__ U0,
                              const double* __restrict__ U1, const double* __restrict__ U2,
                              const double* __restrict__ xi, double* __restrict__ T0, double* __restrict__ T1,
                              double* __restrict__ T2, double* __restrict__ xip, int* __restrict__ flags, int64_t nu) {
@@ -153,7 +153,7 @@ __device__ __forceinline__ void zero_acc(d4_t acc[2][2]) {
 // mirrors the tile into the upper triangle.
 // grid: (tile pairs, splits, mode)
 // ===========================================================================
-__device__ void gram_tile(int64_t n_pad, int64_t R_pad, const double* __restrict__ T, double* __restrict__ G,
+__device__ __forceinline__ void gram_tile(int64_t n_pad, int64_t R_pad, const double* __restrict__ T, double* __restrict__ G,
                           double* __restrict__ part, int splits, int64_t t, int split, int mode) {
     __shared__ double sA[KC * LDS_STRIDE];
     __shared__ double sB[KC * LDS_STRIDE];
@@ -243,7 +243,7 @@ hipError_t launch_gram_nt(int64_t n_pad, int64_t R_pad, double* const Ut[3], dou
 // formed with FP64 MFMA, multiplied entrywise, weighted, and reduced to one
 // partial sum per tile (off-diagonal tiles count twice).
 // ===========================================================================
-__device__ void anorm_tile(int64_t n_pad, int64_t R_pad, const double* __restrict__ T0,
+__device__ __forceinline__ void anorm_tile(int64_t n_pad, int64_t R_pad, const double* __restrict__ T0,
                            const double* __restrict__ T1, const double* __restrict__ T2,
                            const double* __restrict__ xip, double* __restrict__ part, double* __restrict__ G0,
                            double* __restrict__ G1, double* __restrict__ G2, int64_t t) {
@@ -325,7 +325,7 @@ hipError_t launch_anorm_partials(int64_t n_pad, int64_t R_pad, double* const Ut[
 // Z: n_pad x r_pad (ld n_pad) -> A(j,i) = Z[i + j*n_pad] (K-contiguous);
 // U~: n_pad x R_pad -> B(i,nu) = U~[i + nu*n_pad] (K-contiguous).
 // ===========================================================================
-__device__ void project_tile(int64_t n_pad, int64_t R_pad, int64_t r_pad, const double* __restrict__ Z,
+__device__ __forceinline__ void project_tile(int64_t n_pad, int64_t R_pad, int64_t r_pad, const double* __restrict__ Z,
                              const double* __restrict__ T, double* __restrict__ out64, float* __restrict__ out32,
                              int64_t tm, int64_t tn) {
     __shared__ double sA[KC * LDS_STRIDE];

@@ -89,20 +89,22 @@ __device__ __forceinline__ double ll_val(uint64_t lo, uint64_t hi) {
     return __longlong_as_double((long long)((lo & 0xffffffffull) | (hi << 32)));
 }
 
-// Receive N values (entries idx[q] of the word array, q < N, skipped when idx < 0).
+// Receive N values: value q from the word pair at w[q] (skipped when w[q] is null).
+// All pending pairs are loaded together, so one round trip serves every value
+// that is already there.
 template <int N>
-__device__ __forceinline__ void ll_get(const uint64_t* base, const int (&idx)[N], double (&out)[N], uint32_t flag,
+__device__ __forceinline__ void ll_get(const uint64_t* const (&w)[N], double (&out)[N], uint32_t flag,
                                        int* abort_w) {
     bool ready[N];
 #pragma unroll
-    for (int q = 0; q < N; ++q) ready[q] = idx[q] < 0;
+    for (int q = 0; q < N; ++q) ready[q] = (w[q] == nullptr);
     for (int spin = 0;; ++spin) {
         uint64_t lo[N], hi[N];
 #pragma unroll
         for (int q = 0; q < N; ++q)
             if (!ready[q]) {
-                lo[q] = ll_ld(base + 2 * idx[q]);
-                hi[q] = ll_ld(base + 2 * idx[q] + 1);
+                lo[q] = ll_ld(w[q]);
+                hi[q] = ll_ld(w[q] + 1);
             }
         bool all = true;
 #pragma unroll
@@ -186,7 +188,7 @@ __global__ __launch_bounds__(256) void k_tridiag(TriArgs a) {
     __shared__ double red2[CMAX * 4];
     __shared__ double vjs[CMAX], wjs[CMAX], pjs[CMAX];
     __shared__ double parts[256];
-    __shared__ double cw_s, tau_s;
+    __shared__ double cw_s;
     int q0 = 0;
     while (q0 + 1 < a.nmat && (int)blockIdx.x >= a.mat[q0 + 1].blk0) ++q0;
     const TriMat& M = a.mat[q0];
@@ -205,29 +207,29 @@ __global__ __launch_bounds__(256) void k_tridiag(TriArgs a) {
     for (int k = 0; k + 2 < m; ++k) {
         const int par = k & 1;
         const uint32_t flag = (uint32_t)k + 1;
-        // receive v_k (this thread's rows) and tau_k
+        // receive v_k (this thread's rows) and tau_k in one poll
         double vr[RPT];
+        double tau;
         {
-            int idx[RPT];
+            const uint64_t* w[RPT + 1];
+            double val[RPT + 1];
 #pragma unroll
             for (int q = 0; q < RPT; ++q) {
                 const int i = k + 1 + t + 256 * q;
-                idx[q] = (i < m) ? i : -1;
-                vr[q] = 0.0;
+                w[q] = (i < m) ? xv(M, par) + 2 * i : nullptr;
+                val[q] = 0.0;
             }
-            ll_get<RPT>(xv(M, par), idx, vr, flag, a.abort_w);
+            w[RPT] = xtau(M, par);
+            ll_get<RPT + 1>(w, val, flag, a.abort_w);
 #pragma unroll
-            for (int q = 0; q < RPT; ++q)
-                if (idx[q] >= 0) vs[idx[q]] = vr[q];
-            if (t == 0) {
-                int ti[1] = {0};
-                double tv[1] = {0.0};
-                ll_get<1>(xtau(M, par), ti, tv, flag, a.abort_w);
-                tau_s = tv[0];
+            for (int q = 0; q < RPT; ++q) {
+                vr[q] = val[q];
+                const int i = k + 1 + t + 256 * q;
+                if (i < m) vs[i] = vr[q];
             }
+            tau = val[RPT];
         }
-        __syncthreads();   // vs and tau_s
-        const double tau = tau_s;
+        __syncthreads();   // vs
         const int cs = max(0, k + 1 - c0);   // first local column with j > k
         const int cn = k + 1 - c0;           // local index of column k+1
         {
@@ -263,23 +265,23 @@ __global__ __launch_bounds__(256) void k_tridiag(TriArgs a) {
                 const double sp = wave_sum(pv);
                 if (t == 0) ll_put(xpart(M, par) + 2 * gb, sp, flag);
             }
-            // receive p (this thread's rows) and the per-block partial sums
+            // receive p (this thread's rows) and one per-block partial sum in one poll
             double pr[RPT];
             {
-                int idx[RPT];
+                const uint64_t* w[RPT + 1];
+                double val[RPT + 1];
 #pragma unroll
                 for (int q = 0; q < RPT; ++q) {
                     const int i = k + 1 + t + 256 * q;
-                    idx[q] = (i < m) ? i : -1;
-                    pr[q] = 0.0;
+                    w[q] = (i < m) ? xp(M, par) + 2 * i : nullptr;
+                    val[q] = 0.0;
                 }
-                ll_get<RPT>(xp(M, par), idx, pr, flag, a.abort_w);
-                if (t < M.bpm) {
-                    int pi[1] = {t};
-                    double pvv[1] = {0.0};
-                    ll_get<1>(xpart(M, par), pi, pvv, flag, a.abort_w);
-                    parts[t] = pvv[0];
-                }
+                w[RPT] = (t < M.bpm) ? xpart(M, par) + 2 * t : nullptr;
+                val[RPT] = 0.0;
+                ll_get<RPT + 1>(w, val, flag, a.abort_w);
+#pragma unroll
+                for (int q = 0; q < RPT; ++q) pr[q] = val[q];
+                if (t < M.bpm) parts[t] = val[RPT];
             }
             __syncthreads();
             if (t == 0) {

@@ -25,7 +25,7 @@ __device__ double block_sum(double v, double* red) {
 }
 
 // one block per mode: sorted spectrum, tails, rank; mode 0 also writes the norms
-__device__ void truncate_mode(int mode, const double* __restrict__ lam, int m, const double* __restrict__ xip,
+__device__ __forceinline__ void truncate_mode(int mode, const double* __restrict__ lam, int m, const double* __restrict__ xip,
                               int64_t R_pad, const double* __restrict__ anorm_part, int64_t anorm_ntiles, double eps,
                               double* __restrict__ sigma, int* __restrict__ order, double* __restrict__ tails,
                               int* __restrict__ ranks, double* __restrict__ scal) {
