@@ -193,6 +193,77 @@ rhosvd_status rhosvd_reduce_batched(rhosvd_handle h, int32_t count, const rhosvd
 /* 1 when the last batched call ran as a graph replay, 0 when it ran eagerly. */
 int32_t rhosvd_batch_uses_graph(rhosvd_handle h);
 
+/*
+ * Rank-proposal network (learned rank proposal for the randomized range
+ * finder; not part of the paper's method, an addition on top of it).  A small
+ * FP32 multilayer perceptron
+ *     x (67) -> relu(W1 x + b1) (128) -> relu(W2 h1 + b2) (128) -> W3 h2 + b3 (2)
+ * held on the handle.  Parameters are one float vector, W1 | b1 | W2 | b2 | W3 | b3,
+ * each W row-major (out x in), rhosvd_net_num_params() floats in total.  Inputs
+ * x are the per-mode features of rhosvd_sketch_features; rows of x, y, target
+ * are samples.  All pointers are DEVICE pointers; calls are enqueued on the
+ * handle's stream and do not synchronize.
+ *   rhosvd_net_set_params : copy params in (and reset the Adam optimizer)
+ *   rhosvd_net_get_params : copy params out
+ *   rhosvd_net_forward    : y (count x 2) = net(x (count x 67))
+ *   rhosvd_net_train_step : gradient of L = 1/(2 count) sum (y - target)^2 at the
+ *                           current params into grad (nullable), L into loss
+ *                           (nullable, one float), then one Adam step with
+ *                           learning rate lr (lr = 0: gradient only, no update)
+ * Errors: ARG, STATE (no parameters set), ALLOC, DEVICE.
+ */
+int32_t rhosvd_net_num_params(void);
+rhosvd_status rhosvd_net_set_params(rhosvd_handle h, const float* params);
+rhosvd_status rhosvd_net_get_params(rhosvd_handle h, float* params);
+rhosvd_status rhosvd_net_forward(rhosvd_handle h, int32_t count, const float* x, float* y);
+rhosvd_status rhosvd_net_train_step(rhosvd_handle h, int32_t count, const float* x, const float* target, float lr,
+                                    float* loss, float* grad);
+
+/*
+ * Learned rank proposal with a randomized range finder (an addition on top of
+ * the paper's method; Halko, Martinsson & Tropp 2011 for the range finder).
+ *
+ * rhosvd_sketch_features: normalizes the side matrices (as rhosvd_reduce) and
+ *   writes the network's input for each mode into feat (DEVICE, 3 x 67 floats):
+ *   from the 32 singular values s_k of the sketch Y_l = U~_l Omega[:, 0:32]
+ *   (via the eigenvalues of Y_l^T Y_l), log10(s_k / s_1) / 16 clamped at -1,
+ *   then 32 zeros, ln(n)/10, ln(R)/10, ln(eps)/10.
+ *   omega: DEVICE, R x omega_cols Gaussian test matrix (ld R), omega_cols >= 32.
+ *   Does not synchronize.  Errors: as rhosvd_reduce, ARG.
+ *
+ * rhosvd_reduce_learned: rhosvd_reduce with the network's proposals (the
+ *   handle needs network parameters; omega_cols >= 64).  Per mode the network
+ *   proposes a rank r^ and a sketch width p (out0 * m, out1 * m; p >= r^ + 8,
+ *   rounded up to a multiple of 64, at most omega_cols).  Where 3p < m the mode
+ *   runs the range finder: Y = U~ Omega[:, 0:p]; an orthonormal basis Q of Y in
+ *   FP64 (two symmetric orthogonalizations); B = Q^T U~; eigenpairs of B B^T;
+ *   tails t_r^2 = sum_{k>r} sigma_k(B)^2 + |U~ - Q B|_F^2 (the residual computed
+ *   directly); r_l = min{r : t_r <= tau}; Z_l = Q times the top r_l eigenvectors.
+ *   Theorem 2.3's bound holds for any orthonormal Z with these tails.  A mode
+ *   whose residual alone exceeds tau (no r <= p certifies) falls back to the
+ *   Gram path, as does every mode where 3p >= m, and every mode when R < n.
+ *   Ranks, Z, beta and the report come out as for rhosvd_reduce (rhosvd_get);
+ *   for a range-finder mode the spectrum holds the p Ritz values.
+ *   info (HOST, nullable): per mode the proposed rank, the width used (0 on the
+ *   Gram path), the path (0 range finder, 1 Gram path chosen up front, 2 Gram
+ *   path after a failed certificate, 3 Gram path because R < n) and the residual.
+ *   Synchronizes with the stream two or three times.
+ */
+typedef struct {
+    int32_t proposal[3];
+    int32_t width[3];
+    int32_t fallback[3];
+    int32_t reserved;
+    double residual[3];
+} rhosvd_learned_info;
+
+rhosvd_status rhosvd_sketch_features(rhosvd_handle h, int64_t n, int64_t R, const double* U1, const double* U2,
+                                     const double* U3, const double* xi, double eps, const double* omega,
+                                     int32_t omega_cols, float* feat);
+rhosvd_status rhosvd_reduce_learned(rhosvd_handle h, int64_t n, int64_t R, const double* U1, const double* U2,
+                                    const double* U3, const double* xi, double eps, const double* omega,
+                                    int32_t omega_cols, int32_t ranks[3], rhosvd_learned_info* info);
+
 /* Phase times in milliseconds of the last rhosvd_reduce / rhosvd_get when the
  * handle was created with profile != 0 (synchronizes with the stream):
  *   0 norms, 1 |A| identity, 2 Gram, 3 eigensolver, 4 truncation + Z,

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <string>
+#include <vector>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -50,10 +51,13 @@ struct rhosvd_ctx {
     double* htau[3] = {};                // Householder scalars
     double* Tw[3] = {};                  // compact-WY factors of the back-transformation
     // eigensolver plans (Gram matrices; R < n re-orthonormalization) and their work memory
-    EigPlan* plan[2] = {nullptr, nullptr};
-    size_t plan_key[2][4] = {};
-    void* plan_w[2] = {nullptr, nullptr};
-    size_t plan_wbytes[2] = {0, 0};
+    // [0] Gram matrices, [1] R < n re-orthonormalization, [2] sketch Grams of the
+    // rank proposal, [3] range-finder matrices
+    static constexpr int NPLAN = 4;
+    EigPlan* plan[NPLAN] = {};
+    std::vector<EigMat> plan_mats[NPLAN];
+    void* plan_w[NPLAN] = {};
+    size_t plan_wbytes[NPLAN] = {};
     double* gram_part = nullptr;
     int gram_splits = 1;
     double* anorm_part = nullptr;
@@ -87,6 +91,25 @@ struct rhosvd_ctx {
     int sweeps = 0, dropped = 0;
     // batched reductions: the plan of the last descriptor list
     BatchPlan* batch = nullptr;
+    // rank-proposal network: parameters, gradient, Adam moments (one allocation)
+    float* net = nullptr;
+    float* net_work = nullptr;
+    size_t net_work_n = 0;
+    int net_step = 0;
+    bool net_set = false;
+    // learned rank proposal + range finder workspace (grow-only)
+    struct Learned {
+        char* ws = nullptr;
+        size_t bytes = 0;
+        int p_cap = 0;
+        double* Om32 = nullptr;
+        double *Om[3] = {}, *Y[3] = {}, *Qb[3] = {}, *G2[3] = {}, *W2[3] = {}, *Qn2[3] = {}, *Mg2[3] = {}, *Pf[3] = {},
+               *S2[3] = {}, *lam2[3] = {}, *dd2[3] = {}, *ee2[3] = {}, *tau2[3] = {}, *Bm[3] = {}, *Tw[3] = {},
+               *part[3] = {}, *Wsel[3] = {};
+        double* floor2 = nullptr;
+        float* feat = nullptr;
+        float* out = nullptr;
+    } L;
     // profiling
     hipEvent_t ev[NEV] = {};
     bool ev_ok = false;
@@ -222,8 +245,9 @@ rhosvd_status layout(rhosvd_ctx* h, int64_t n, int64_t R) {
 // (Re)build eigensolver plan `which` when the matrix list changed; the plan's
 // tables are uploaded once and reused by every later call with the same layout.
 rhosvd_status ensure_plan(rhosvd_ctx* h, int which, const EigMat* mats, int nmat) {
-    const size_t key[4] = {(size_t)mats[0].m, (size_t)mats[0].ld, (size_t)mats[0].G, (size_t)nmat};
-    if (h->plan[which] && memcmp(key, h->plan_key[which], sizeof(key)) == 0) return RHOSVD_OK;
+    std::vector<EigMat>& key = h->plan_mats[which];
+    if (h->plan[which] && (int)key.size() == nmat && memcmp(key.data(), mats, nmat * sizeof(EigMat)) == 0)
+        return RHOSVD_OK;
     if (h->plan[which]) {
         hipStreamSynchronize(h->stream);   // its tables may still be in use
         eig_plan_destroy(h->plan[which]);
@@ -248,7 +272,75 @@ rhosvd_status ensure_plan(rhosvd_ctx* h, int which, const EigMat* mats, int nmat
         return fail(h, RHOSVD_ERR_DEVICE, std::string("eigensolver plan upload: ") + hipGetErrorString(e));
     }
     h->plan[which] = P;
-    memcpy(h->plan_key[which], key, sizeof(key));
+    key.assign(mats, mats + nmat);
+    return RHOSVD_OK;
+}
+
+// workspace of the learned path for the current layout (p_cap columns of the
+// test matrix); base == nullptr only measures
+size_t carve_learned(rhosvd_ctx* h, char* base, int p_cap) {
+    Carve c{base};
+    auto& L = h->L;
+    const size_t np = h->n_pad, Rp = h->R_pad, pc = p_cap, zp = h->zr_pad;
+    L.Om32 = c.take<double>(Rp * 64);
+    for (int l = 0; l < 3; ++l) {
+        L.Om[l] = c.take<double>(Rp * pc);
+        L.Y[l] = c.take<double>(np * pc);
+        L.Qb[l] = c.take<double>(np * pc);
+        L.G2[l] = c.take<double>(pc * pc);
+        L.W2[l] = c.take<double>(pc * pc);
+        L.Qn2[l] = c.take<double>(pc * pc);
+        L.Mg2[l] = c.take<double>(pc * pc);
+        L.Pf[l] = c.take<double>(pc * pc);
+        L.S2[l] = c.take<double>(pc * pc);
+        L.lam2[l] = c.take<double>(pc);
+        L.dd2[l] = c.take<double>(pc);
+        L.ee2[l] = c.take<double>(pc);
+        L.tau2[l] = c.take<double>(pc);
+        L.Bm[l] = c.take<double>(pc * Rp);
+        L.Tw[l] = c.take<double>(backtransform_work_doubles((int)pc));
+        L.part[l] = c.take<double>((np / 64) * (Rp / 64));
+        L.Wsel[l] = c.take<double>(pc * zp);
+    }
+    L.floor2 = c.take<double>(4);
+    L.feat = c.take<float>(3 * NET_IN);
+    L.out = c.take<float>(3 * NET_OUT);
+    return c.off;
+}
+
+rhosvd_status learned_layout(rhosvd_ctx* h, int p_cap) {
+    const size_t need = carve_learned(h, nullptr, p_cap);
+    if (need > h->L.bytes) {
+        if (h->L.ws) { hipStreamSynchronize(h->stream); hipFree(h->L.ws); h->L.ws = nullptr; h->L.bytes = 0; }
+        if (hipMalloc((void**)&h->L.ws, need) != hipSuccess) {
+            h->L.ws = nullptr;
+            return fail(h, RHOSVD_ERR_ALLOC, "learned-path workspace allocation of " + std::to_string(need) + " bytes failed");
+        }
+        h->L.bytes = need;
+    }
+    carve_learned(h, h->L.ws, p_cap);
+    h->L.p_cap = p_cap;
+    return RHOSVD_OK;
+}
+
+// features of the three modes into h->L.feat (normalized side matrices in h->Ut):
+// sketch Y_l = U~_l Omega[:, :32], eigenvalues of Y_l^T Y_l, log-spectrum features
+rhosvd_status learned_features(rhosvd_ctx* h, const double* omega, int w, double eps) {
+    hipStream_t st = h->stream;
+    auto& L = h->L;
+    const int64_t np = h->n_pad, Rp = h->R_pad;
+    CK(h, launch_pad_omega(h->R, Rp, std::min(w, 32), 64, omega, L.Om32, st));
+    EigMat em[3];
+    for (int l = 0; l < 3; ++l) {
+        CK(h, launch_gemm64(false, true, np, 64, Rp, h->Ut[l], np, L.Om32, Rp, L.Y[l], np, 1.0, st));
+        CK(h, launch_gemm64(true, true, 64, 64, np, L.Y[l], np, L.Y[l], np, L.G2[l], 64, 1.0, st));
+        em[l] = EigMat{L.G2[l], L.lam2[l], L.W2[l], L.Qn2[l], L.Mg2[l], L.dd2[l], L.ee2[l], L.tau2[l], 32, 64};
+    }
+    rhosvd_status ps = ensure_plan(h, 2, em, 3);
+    if (ps != RHOSVD_OK) return ps;
+    CK(h, eig_plan_enqueue(h->plan[2], h->flags + 2, st));
+    const double* lam[3] = {L.lam2[0], L.lam2[1], L.lam2[2]};
+    CK(h, launch_features(lam, (int)h->n, h->R, eps, L.feat, st));
     return RHOSVD_OK;
 }
 
@@ -328,6 +420,8 @@ rhosvd_status rhosvd_create(rhosvd_handle* out, void* hip_stream, const rhosvd_o
         g_create_error = "pinned host allocation failed";
         return RHOSVD_ERR_ALLOC;
     }
+    // host staging words: 0..2 ranks, 4..6 flags, 8 abort word (report), 32.. doubles
+    // (0..2 norms, 4..6 tails, 8..10 range-finder residuals), 56..61 network outputs
     h->hostd = (double*)(h->host + 32);
     h->ev_ok = true;
     for (int i = 0; i < NEV; ++i)
@@ -341,7 +435,10 @@ rhosvd_status rhosvd_destroy(rhosvd_handle h) {
     hipStreamSynchronize(h->stream);
     if (h->ws) hipFree(h->ws);
     if (h->batch) batch_plan_destroy(h->batch);
-    for (int i = 0; i < 2; ++i) {
+    if (h->net) hipFree(h->net);
+    if (h->L.ws) hipFree(h->L.ws);
+    if (h->net_work) hipFree(h->net_work);
+    for (int i = 0; i < rhosvd_ctx::NPLAN; ++i) {
         if (h->plan[i]) eig_plan_destroy(h->plan[i]);
         if (h->plan_w[i]) hipFree(h->plan_w[i]);
     }
@@ -422,6 +519,9 @@ rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R, const double*
     CK(h, hipStreamSynchronize(st));
     if (h->host[4]) return fail(h, RHOSVD_ERR_NONFINITE, "input contains NaN or Inf");
     if (h->host[6]) return fail(h, RHOSVD_ERR_DEVICE, "eigensolver: a cross-workgroup wait ran out");
+    for (int l = 0; l < 3; ++l)
+        if (h->host[l] < 0 || h->host[l] > h->m)
+            return fail(h, RHOSVD_ERR_DEVICE, "truncation returned rank " + std::to_string(h->host[l]) + " (internal error)");
     h->sweeps = 0;
     h->dropped = h->host[5];
     h->xi_norm = h->hostd[0];
@@ -586,6 +686,367 @@ rhosvd_status rhosvd_reduce_batched(rhosvd_handle h, int32_t count, const rhosvd
         if (!h->batch) return fail(h, RHOSVD_ERR_ALLOC, err);
     }
     CK(h, batch_plan_run(h->batch, h->stream));
+    return RHOSVD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// rank-proposal network
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+rhosvd_status net_alloc(rhosvd_ctx* h, int batch) {
+    if (!h->net) {
+        if (hipMalloc((void**)&h->net, 4 * (size_t)NET_PARAMS * sizeof(float)) != hipSuccess) {
+            h->net = nullptr;
+            return fail(h, RHOSVD_ERR_ALLOC, "network parameter allocation failed");
+        }
+    }
+    const size_t need = net_work_floats(std::max(batch, 1));
+    if (need > h->net_work_n) {
+        if (h->net_work) { hipStreamSynchronize(h->stream); hipFree(h->net_work); h->net_work = nullptr; }
+        h->net_work_n = 0;
+        if (hipMalloc((void**)&h->net_work, need * sizeof(float)) != hipSuccess) {
+            h->net_work = nullptr;
+            return fail(h, RHOSVD_ERR_ALLOC, "network workspace allocation failed");
+        }
+        h->net_work_n = need;
+    }
+    return RHOSVD_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int32_t rhosvd_net_num_params(void) { return NET_PARAMS; }
+
+rhosvd_status rhosvd_net_set_params(rhosvd_handle h, const float* params) {
+    if (!h) return RHOSVD_ERR_ARG;
+    if (!params) return fail(h, RHOSVD_ERR_ARG, "params is NULL");
+    rhosvd_status s = net_alloc(h, 1);
+    if (s != RHOSVD_OK) return s;
+    CK(h, hipMemcpyAsync(h->net, params, (size_t)NET_PARAMS * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+    // new parameters restart the optimizer: gradient and both moments zero
+    CK(h, hipMemsetAsync(h->net + NET_PARAMS, 0, 3 * (size_t)NET_PARAMS * sizeof(float), h->stream));
+    h->net_step = 0;
+    h->net_set = true;
+    return RHOSVD_OK;
+}
+
+rhosvd_status rhosvd_net_get_params(rhosvd_handle h, float* params) {
+    if (!h) return RHOSVD_ERR_ARG;
+    if (!h->net_set) return fail(h, RHOSVD_ERR_STATE, "no network parameters on this handle");
+    if (!params) return fail(h, RHOSVD_ERR_ARG, "params is NULL");
+    CK(h, hipMemcpyAsync(params, h->net, (size_t)NET_PARAMS * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+    return RHOSVD_OK;
+}
+
+rhosvd_status rhosvd_net_forward(rhosvd_handle h, int32_t count, const float* x, float* y) {
+    if (!h) return RHOSVD_ERR_ARG;
+    if (!h->net_set) return fail(h, RHOSVD_ERR_STATE, "no network parameters on this handle");
+    if (count < 1 || !x || !y) return fail(h, RHOSVD_ERR_ARG, "count >= 1 and non-null x, y required");
+    rhosvd_status s = net_alloc(h, count);
+    if (s != RHOSVD_OK) return s;
+    CK(h, net_forward(h->net, count, x, y, h->net_work, h->stream));
+    return RHOSVD_OK;
+}
+
+rhosvd_status rhosvd_net_train_step(rhosvd_handle h, int32_t count, const float* x, const float* target, float lr,
+                                    float* loss, float* grad) {
+    if (!h) return RHOSVD_ERR_ARG;
+    if (!h->net_set) return fail(h, RHOSVD_ERR_STATE, "no network parameters on this handle");
+    if (count < 1 || !x || !target) return fail(h, RHOSVD_ERR_ARG, "count >= 1 and non-null x, target required");
+    if (!(lr >= 0.0f)) return fail(h, RHOSVD_ERR_ARG, "lr must be >= 0");
+    rhosvd_status s = net_alloc(h, count);
+    if (s != RHOSVD_OK) return s;
+    float* G = h->net + NET_PARAMS;
+    if (lr > 0.0f) ++h->net_step;
+    CK(h, net_train_step(h->net, G, G + NET_PARAMS, G + 2 * NET_PARAMS, std::max(h->net_step, 1), lr, count, x,
+                         target, loss, h->net_work, h->stream));
+    if (grad)
+        CK(h, hipMemcpyAsync(grad, G, (size_t)NET_PARAMS * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+    return RHOSVD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// learned rank proposal + randomized range finder
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+// argument checks, layout, normalization and the |A| identity (the part of a
+// reduction both paths share)
+rhosvd_status prologue(rhosvd_ctx* h, int64_t n, int64_t R, const double* U1, const double* U2, const double* U3,
+                       const double* xi, double eps) {
+    if (!U1 || !U2 || !U3 || !xi) return fail(h, RHOSVD_ERR_ARG, "null pointer argument");
+    if (n < 1 || R < 1) return fail(h, RHOSVD_ERR_ARG, "n and R must be >= 1");
+    if (!(eps > 0.0) || !isfinite(eps)) return fail(h, RHOSVD_ERR_ARG, "eps must be finite and > 0");
+    if ((n < R ? n : R) > 2048) return fail(h, RHOSVD_ERR_UNSUPPORTED, "min(n, R) > 2048 is not supported by this build");
+    if (n > 65536) return fail(h, RHOSVD_ERR_UNSUPPORTED, "n > 65536 is not supported by this build");
+    rhosvd_status s = layout(h, n, R);
+    if (s != RHOSVD_OK) return s;
+    hipStream_t st = h->stream;
+    const double* U[3] = {U1, U2, U3};
+    CK(h, hipMemsetAsync(h->flags, 0, 64, st));
+    CK(h, launch_colnorm(n, R, h->n_pad, h->R_pad, U, xi, h->Ut, h->xip, h->flags, st));
+    int64_t nt = 0;
+    CK(h, launch_anorm_partials(h->n_pad, h->R_pad, h->Ut, h->xip, h->anorm_part, &nt, h->rside ? h->G : nullptr, st));
+    return RHOSVD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rhosvd_status rhosvd_sketch_features(rhosvd_handle h, int64_t n, int64_t R, const double* U1, const double* U2,
+                                     const double* U3, const double* xi, double eps, const double* omega,
+                                     int32_t omega_cols, float* feat) {
+    if (!h) return RHOSVD_ERR_ARG;
+    h->have = false;
+    h->err.clear();
+    if (!omega || !feat || omega_cols < 32) return fail(h, RHOSVD_ERR_ARG, "omega (>= 32 columns) and feat required");
+    rhosvd_status s = prologue(h, n, R, U1, U2, U3, xi, eps);
+    if (s != RHOSVD_OK) return s;
+    s = learned_layout(h, 64);
+    if (s != RHOSVD_OK) return s;
+    s = learned_features(h, omega, omega_cols, eps);
+    if (s != RHOSVD_OK) return s;
+    CK(h, hipMemcpyAsync(feat, h->L.feat, 3 * NET_IN * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+    return RHOSVD_OK;
+}
+
+rhosvd_status rhosvd_reduce_learned(rhosvd_handle h, int64_t n, int64_t R, const double* U1, const double* U2,
+                                    const double* U3, const double* xi, double eps, const double* omega,
+                                    int32_t omega_cols, int32_t ranks[3], rhosvd_learned_info* info) {
+    if (!h) return RHOSVD_ERR_ARG;
+    h->have = false;
+    h->err.clear();
+    if (!ranks) return fail(h, RHOSVD_ERR_ARG, "ranks is NULL");
+    if (!omega || omega_cols < 64) return fail(h, RHOSVD_ERR_ARG, "omega with >= 64 columns required");
+    if (!h->net_set) return fail(h, RHOSVD_ERR_STATE, "no network parameters on this handle");
+    rhosvd_learned_info li;
+    memset(&li, 0, sizeof(li));
+    if (R < n) {
+        // the range finder is built for the n-side Gram path: the full method runs
+        rhosvd_status s = rhosvd_reduce(h, n, R, U1, U2, U3, xi, eps, ranks);
+        for (int l = 0; l < 3; ++l) li.fallback[l] = 3;
+        if (info) *info = li;
+        return s;
+    }
+    rhosvd_status s = prologue(h, n, R, U1, U2, U3, xi, eps);
+    if (s != RHOSVD_OK) return s;
+    hipStream_t st = h->stream;
+    const int m = (int)h->m;
+    const int p_cap = (int)std::min<int64_t>(round_up(m, 64), (int64_t)(omega_cols / 64) * 64);
+    if ((s = learned_layout(h, std::max(p_cap, 64))) != RHOSVD_OK) return s;
+    auto& L = h->L;
+    mark(h, 0);
+    if ((s = learned_features(h, omega, omega_cols, eps)) != RHOSVD_OK) return s;
+    if ((s = net_alloc(h, 3)) != RHOSVD_OK) return s;
+    CK(h, net_forward(h->net, 3, L.feat, L.out, h->net_work, st));
+    float* hout = (float*)(h->host + 56);   // host words 56..61 (see rhosvd_create)
+    CK(h, hipMemcpyAsync(hout, L.out, 3 * NET_OUT * sizeof(float), hipMemcpyDeviceToHost, st));
+    CK(h, hipMemcpyAsync(h->host + 4, h->flags, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
+    CK(h, hipStreamSynchronize(st));
+    if (h->host[4]) return fail(h, RHOSVD_ERR_NONFINITE, "input contains NaN or Inf");
+    if (h->host[6]) return fail(h, RHOSVD_ERR_DEVICE, "eigensolver: a cross-workgroup wait ran out");
+    // proposals: rank r = out0 * m, sketch width p = out1 * m (at least r + 8), in
+    // multiples of 64; the range finder is used where it saves eigensolver work (3p < m)
+    int width[3] = {0, 0, 0};
+    bool rf[3] = {false, false, false};
+    for (int l = 0; l < 3; ++l) {
+        const double o0 = std::isfinite(hout[2 * l]) ? hout[2 * l] : 1.0;
+        const double o1 = std::isfinite(hout[2 * l + 1]) ? hout[2 * l + 1] : 1.0;
+        const int rh = (int)std::min<double>(m, std::max(1.0, std::round(o0 * m)));
+        int p = (int)std::min<double>(m, std::max<double>(rh + 8, std::round(o1 * m)));
+        const int pp = (int)std::min<int64_t>(round_up(p, 64), p_cap);
+        li.proposal[l] = rh;
+        rf[l] = pp >= 64 && 3 * pp < m;
+        width[l] = rf[l] ? pp : 0;
+        li.width[l] = width[l];
+        li.fallback[l] = rf[l] ? 0 : 1;
+    }
+    const int64_t np = h->n_pad, Rp = h->R_pad;
+    CK(h, hipMemsetAsync(L.floor2, 0, 4 * sizeof(double), st));
+    std::vector<EigMat> em;
+    auto rf_eig = [&]() -> rhosvd_status {
+        rhosvd_status ps = ensure_plan(h, 3, em.data(), (int)em.size());
+        if (ps != RHOSVD_OK) return ps;
+        CK(h, eig_plan_enqueue(h->plan[3], h->flags + 2, st));
+        return RHOSVD_OK;
+    };
+    std::vector<int> rfl;
+    for (int l = 0; l < 3; ++l)
+        if (rf[l]) rfl.push_back(l);
+    if (!rfl.empty()) {
+        // Y = U~ Omega_p, orthonormal basis Q by two Lowdin passes, B = Q^T U~
+        for (int l : rfl) {
+            const int p = width[l];
+            CK(h, launch_pad_omega(h->R, Rp, omega_cols, p, omega, L.Om[l], st));
+            CK(h, launch_gemm64(false, true, np, p, Rp, h->Ut[l], np, L.Om[l], Rp, L.Y[l], np, 1.0, st));
+            em.push_back(EigMat{L.G2[l], L.lam2[l], L.W2[l], L.Qn2[l], L.Mg2[l], L.dd2[l], L.ee2[l], L.tau2[l], p, p});
+        }
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int l : rfl) {
+                const int p = width[l];
+                const double* X = pass == 0 ? L.Y[l] : L.Qb[l];
+                CK(h, launch_gemm64(true, true, p, p, np, X, np, X, np, L.G2[l], p, 1.0, st));
+            }
+            if ((s = rf_eig()) != RHOSVD_OK) return s;
+            std::vector<BtJob> jobs;
+            for (int l : rfl) {
+                const int p = width[l];
+                jobs.push_back(BtJob{p, p, L.G2[l], L.tau2[l], L.W2[l], nullptr, p, nullptr, L.Pf[l], p, p, L.Tw[l]});
+            }
+            CK(h, launch_backtransform(jobs.data(), (int)jobs.size(), st));
+            for (int l : rfl) {
+                const int p = width[l];
+                CK(h, launch_lowdin(p, p, L.lam2[l], L.Pf[l], L.S2[l], 1e-15, st));
+                // pass 0: Qb = Y S;  pass 1: Y = Qb S (the orthonormal basis ends in Y)
+                if (pass == 0)
+                    CK(h, launch_gemm64(false, true, np, p, p, L.Y[l], np, L.S2[l], p, L.Qb[l], np, 1.0, st));
+                else
+                    CK(h, launch_gemm64(false, true, np, p, p, L.Qb[l], np, L.S2[l], p, L.Y[l], np, 1.0, st));
+            }
+        }
+        for (int l : rfl) {
+            const int p = width[l];
+            CK(h, launch_project(np, Rp, p, L.Y[l], h->Ut[l], L.Bm[l], nullptr, st));
+            CK(h, launch_resid_partials(np, Rp, p, L.Y[l], L.Bm[l], h->Ut[l], L.part[l], st));
+            CK(h, launch_floor_sum(L.part[l], (np / 64) * (Rp / 64), L.floor2 + l, st));
+            CK(h, launch_gemm64(false, false, p, p, Rp, L.Bm[l], p, L.Bm[l], p, L.G2[l], p, 1.0, st));
+        }
+        if ((s = rf_eig()) != RHOSVD_OK) return s;
+    }
+    // the Gram path for the other modes (all three Grams are formed; the
+    // eigensolver runs only for the modes that need it)
+    bool gram_done = false;
+    auto gram_modes = [&](const bool* which) -> rhosvd_status {
+        if (!(which[0] || which[1] || which[2])) return RHOSVD_OK;
+        if (!gram_done) {
+            CK(h, launch_gram_nt(h->n_pad, h->R_pad, h->Ut, h->G, h->gram_part, h->gram_splits, st));
+            gram_done = true;
+        }
+        std::vector<EigMat> eg;
+        for (int l = 0; l < 3; ++l)
+            if (which[l])
+                eg.push_back(EigMat{h->G[l], h->lam[l], h->W[l], h->Qn[l], h->Mg[l], h->dd[l], h->ee[l], h->htau[l], m,
+                                    (int)h->m_pad});
+        if (eg.empty()) return RHOSVD_OK;
+        rhosvd_status ps = ensure_plan(h, 0, eg.data(), (int)eg.size());
+        if (ps != RHOSVD_OK) return ps;
+        CK(h, eig_plan_enqueue(h->plan[0], h->flags + 2, st));
+        return RHOSVD_OK;
+    };
+    bool gm[3] = {!rf[0], !rf[1], !rf[2]};
+    if ((s = gram_modes(gm)) != RHOSVD_OK) return s;
+    auto truncate = [&]() -> rhosvd_status {
+        TruncArgs ta{};
+        for (int l = 0; l < 3; ++l) {
+            ta.lam[l] = rf[l] ? L.lam2[l] : h->lam[l];
+            ta.m_mode[l] = rf[l] ? width[l] : m;
+            ta.sigma[l] = h->sigma[l];
+            ta.order[l] = h->order[l];
+            ta.tails[l] = h->tails[l];
+            if (rf[l]) CK(h, hipMemsetAsync(h->sigma[l], 0, (size_t)(h->m_pad + 1) * 8, st));
+        }
+        ta.m = m;
+        ta.m_pad = (int)h->m_pad;
+        ta.n = (int)n;
+        ta.n_pad = (int)h->n_pad;
+        ta.xip = h->xip;
+        ta.R_pad = h->R_pad;
+        ta.anorm_part = h->anorm_part;
+        ta.anorm_ntiles = h->anorm_ntiles;
+        ta.eps = eps;
+        ta.ranks = h->ranks_dev;
+        ta.scal = h->scal;
+        ta.floor2 = L.floor2;
+        CK(h, launch_truncate(ta, st));
+        CK(h, hipMemcpyAsync(h->host, h->ranks_dev, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
+        CK(h, hipMemcpyAsync(h->host + 4, h->flags, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
+        CK(h, hipMemcpyAsync(h->hostd, h->scal, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+        CK(h, hipMemcpyAsync(h->hostd + 8, L.floor2, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+        CK(h, hipStreamSynchronize(st));
+        if (h->host[6]) return fail(h, RHOSVD_ERR_DEVICE, "eigensolver: a cross-workgroup wait ran out");
+        return RHOSVD_OK;
+    };
+    if ((s = truncate()) != RHOSVD_OK) return s;
+    // certificate: a range-finder mode whose tails never reach tau (rank m + 1) falls back
+    bool again[3] = {false, false, false};
+    bool any = false;
+    for (int l = 0; l < 3; ++l) {
+        li.residual[l] = rf[l] ? sqrt(std::max(h->hostd[8 + l], 0.0)) : 0.0;
+        if (rf[l] && h->host[l] > width[l]) {
+            again[l] = true;
+            any = true;
+            rf[l] = false;
+            li.fallback[l] = 2;
+        }
+    }
+    if (any) {
+        // the Gram path has no residual: clear the floor of the modes that fall back
+        for (int l = 0; l < 3; ++l)
+            if (again[l]) CK(h, hipMemsetAsync(L.floor2 + l, 0, sizeof(double), st));
+        if ((s = gram_modes(again)) != RHOSVD_OK) return s;
+        if ((s = truncate()) != RHOSVD_OK) return s;
+    }
+    for (int l = 0; l < 3; ++l)
+        if (h->host[l] < 0 || h->host[l] > (rf[l] ? width[l] : m))
+            return fail(h, RHOSVD_ERR_DEVICE, "truncation returned rank " + std::to_string(h->host[l]) + " for mode " +
+                                                  std::to_string(l) + " (internal error)");
+    mark(h, 4);
+    h->sweeps = 0;
+    h->dropped = h->host[5];
+    h->xi_norm = h->hostd[0];
+    h->a_norm = h->hostd[1];
+    h->tau = h->hostd[2];
+    for (int l = 0; l < 3; ++l) {
+        h->ranks[l] = h->host[l];
+        h->r_pad[l] = (int)round_up(h->ranks[l] > 0 ? h->ranks[l] : 1, 128);
+    }
+    // Z: range-finder modes Z = Q W_B[:, order[0..r-1]]; Gram modes as in rhosvd_reduce
+    std::vector<BtJob> jobs;
+    for (int l = 0; l < 3; ++l) {
+        const int r = h->ranks[l];
+        if (r < 1) continue;
+        if (rf[l]) {
+            const int p = width[l];
+            CK(h, hipMemsetAsync(L.Wsel[l], 0, (size_t)p * h->r_pad[l] * 8, st));
+            jobs.push_back(BtJob{p, p, L.G2[l], L.tau2[l], L.W2[l], h->order[l], r, nullptr, L.Wsel[l], p, p, L.Tw[l]});
+        } else {
+            jobs.push_back(BtJob{m, (int)h->m_pad, h->G[l], h->htau[l], h->W[l], h->order[l], r, nullptr, h->Z[l],
+                                 (int)np, (int)np, h->Tw[l]});
+        }
+    }
+    CK(h, launch_backtransform(jobs.data(), (int)jobs.size(), st));
+    for (int l = 0; l < 3; ++l) {
+        const int r = h->ranks[l];
+        if (r < 1) continue;
+        if (rf[l])
+            CK(h, launch_gemm64(false, true, np, h->r_pad[l], width[l], L.Y[l], np, L.Wsel[l], width[l], h->Z[l], np,
+                                1.0, st));
+        CK(h, launch_sign_cols((int)n, (int)np, r, h->Z[l], st));
+        if (h->r_pad[l] > r)
+            CK(h, hipMemsetAsync(h->Z[l] + (int64_t)r * np, 0, (size_t)(h->r_pad[l] - r) * np * 8, st));
+    }
+    mark(h, 5);
+    for (int l = 0; l < 3; ++l) {
+        if (h->ranks[l] < 1) continue;
+        if (h->vprec == RHOSVD_FP64)
+            CK(h, launch_project(np, Rp, h->r_pad[l], h->Z[l], h->Ut[l], (double*)h->V[l], nullptr, st));
+        else
+            CK(h, launch_project(np, Rp, h->r_pad[l], h->Z[l], h->Ut[l], nullptr, (float*)h->V[l], st));
+    }
+    mark(h, 6);
+    // phases 1..3 are not separated on this path: the events between them coincide
+    for (int i = 1; i <= 3; ++i) mark(h, i);
+    h->reduce_timed = true;
+    h->get_timed = false;
+    for (int l = 0; l < 3; ++l) ranks[l] = h->ranks[l];
+    if (info) *info = li;
+    h->have = true;
     return RHOSVD_OK;
 }
 

@@ -581,3 +581,46 @@ hipError_t launch_batched_dense(int which, const BProb* P, const int64_t* pre, i
     }
     return hipGetLastError();
 }
+
+// ===========================================================================
+// Residual of a range finder: partial sums over 64 x 64 tiles of
+// |U~ - Q B|_F^2 with Q (n_pad x p_pad, ld n_pad) and B = Q^T U~ (p_pad x R_pad).
+// grid: (R_pad / 64, n_pad / 64); part[ti + tj * tiles_i]
+// ===========================================================================
+__global__ __launch_bounds__(256) void k_resid_partials(int64_t n_pad, int64_t R_pad, int64_t p_pad,
+                                                        const double* __restrict__ Q, const double* __restrict__ B,
+                                                        const double* __restrict__ T, double* __restrict__ part) {
+    __shared__ double sA[KC * LDS_STRIDE];
+    __shared__ double sB[KC * LDS_STRIDE];
+    __shared__ double red[4];
+    const int64_t tn = blockIdx.x, tm = blockIdx.y;
+    d4_t acc[2][2];
+    zero_acc(acc);
+    tile64_f64<false, true>(Q, n_pad, B, p_pad, tm * T64, tn * T64, 0, p_pad, sA, sB, acc);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t r = tm * T64 + wr + a * 16 + c_row64(lane, i);
+                const int64_t c = tn * T64 + wc + b * 16 + c_col(lane);
+                const double d = T[r + c * n_pad] - acc[a][b][i];
+                s += d * d;
+            }
+    s = wave_sum(s);
+    if (lane == 0) red[w] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[tm + tn * (n_pad / T64)] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+hipError_t launch_resid_partials(int64_t n_pad, int64_t R_pad, int64_t p_pad, const double* Q, const double* B,
+                                 const double* Ut, double* part, hipStream_t st) {
+    if (n_pad % T64 || R_pad % T64 || p_pad % KC) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_resid_partials, dim3((unsigned)(R_pad / T64), (unsigned)(n_pad / T64)), dim3(256), 0, st,
+                       n_pad, R_pad, p_pad, Q, B, Ut, part);
+    return hipGetLastError();
+}

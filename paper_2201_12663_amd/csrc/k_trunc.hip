@@ -25,10 +25,13 @@ __device__ double block_sum(double v, double* red) {
 }
 
 // one block per mode: sorted spectrum, tails, rank; mode 0 also writes the norms
+// floor2: a squared tail that every t_r carries in addition to the discarded
+// eigenvalues (the residual of a range finder; 0 on the Gram path).  When no
+// r <= m certifies t_r <= tau the rank is set to m + 1.
 __device__ __forceinline__ void truncate_mode(int mode, const double* __restrict__ lam, int m, const double* __restrict__ xip,
                               int64_t R_pad, const double* __restrict__ anorm_part, int64_t anorm_ntiles, double eps,
                               double* __restrict__ sigma, int* __restrict__ order, double* __restrict__ tails,
-                              int* __restrict__ ranks, double* __restrict__ scal) {
+                              int* __restrict__ ranks, double* __restrict__ scal, double floor2 = 0.0) {
     __shared__ double key[MAXM];
     __shared__ int idx[MAXM];
     __shared__ double scan[MAXM + 1];
@@ -86,7 +89,11 @@ __device__ __forceinline__ void truncate_mode(int mode, const double* __restrict
         for (int i = t; i < m; i += TB) scan[i] += add[cnt++];
         __syncthreads();
     }
-    if (t == 0) rmin = m;
+    if (floor2 != 0.0) {
+        for (int i = t; i <= m; i += TB) scan[i] += floor2;
+        __syncthreads();
+    }
+    if (t == 0) rmin = m + 1;
     __syncthreads();
     // r = min{ r >= 1 : t_r <= tau }, t_r = sqrt(scan[r])
     for (int r = 1 + t; r <= m; r += TB)
@@ -106,8 +113,9 @@ __device__ __forceinline__ void truncate_mode(int mode, const double* __restrict
 
 __global__ __launch_bounds__(TB) void k_truncate(TruncArgs a) {
     const int mode = blockIdx.x;
-    truncate_mode(mode, a.lam[mode], a.m, a.xip, a.R_pad, a.anorm_part, a.anorm_ntiles, a.eps, a.sigma[mode],
-                  a.order[mode], a.tails[mode], a.ranks, a.scal);
+    const int m = a.m_mode[mode] > 0 ? a.m_mode[mode] : a.m;
+    truncate_mode(mode, a.lam[mode], m, a.xip, a.R_pad, a.anorm_part, a.anorm_ntiles, a.eps, a.sigma[mode],
+                  a.order[mode], a.tails[mode], a.ranks, a.scal, a.floor2 ? a.floor2[mode] : 0.0);
 }
 
 // batched: grid (3, problems); problems with non-finite input are skipped

@@ -31,6 +31,10 @@ hipError_t launch_anorm_partials(int64_t n_pad, int64_t R_pad, double* const Ut[
                                  const double* xip, double* part, int64_t* ntiles, double* const Gr[3],
                                  hipStream_t st);
 
+// |U~ - Q B|_F^2 partial sums per 64 x 64 tile (R_pad/64 * n_pad/64 doubles in part)
+hipError_t launch_resid_partials(int64_t n_pad, int64_t R_pad, int64_t p_pad, const double* Q, const double* B,
+                                 const double* Ut, double* part, hipStream_t st);
+
 // Generic FP64 MFMA GEMM on padded operands, C = alpha A B (col-major C).
 //   a_kcontig: A(i,k) = A[k + i*lda], else A[i + k*lda]
 //   b_kcontig: B(k,j) = B[k + j*ldb], else B[j + k*ldb]
@@ -121,8 +125,10 @@ struct TruncArgs {
     double* sigma[3];       // m each, descending
     int* order[3];          // m each: column of W for the k-th largest
     double* tails[3];       // m + 1 each
-    int* ranks;             // 3 ints
+    int* ranks;             // 3 ints (m + 1 when no r certifies, see floor2)
     double* scal;           // [0] xi_norm, [1] a_norm, [2] tau
+    int m_mode[3];          // per-mode number of eigenvalues (0: m)
+    const double* floor2;   // per-mode squared tail floor (device, 3 doubles) or null
 };
 hipError_t launch_truncate(const TruncArgs& a, hipStream_t st);
 
@@ -200,3 +206,26 @@ bool batch_plan_matches(const BatchPlan* plan, const rhosvd_problem* probs, int 
 hipError_t batch_plan_run(BatchPlan* plan, hipStream_t st);
 bool batch_plan_uses_graph(const BatchPlan* plan);
 void batch_plan_destroy(BatchPlan* plan);
+
+// ---------------------------------------------------------------------------
+// Rank-proposal network (k_net.hip): FP32 MLP NET_IN -> NET_HID -> NET_HID -> NET_OUT.
+// ---------------------------------------------------------------------------
+constexpr int NET_IN = 67, NET_HID = 128, NET_OUT = 2;
+constexpr int NET_PARAMS = NET_HID * NET_IN + NET_HID + NET_HID * NET_HID + NET_HID + NET_OUT * NET_HID + NET_OUT;
+size_t net_work_floats(int batch);
+// Y (B x NET_OUT) = net(X (B x NET_IN)); work: net_work_floats(B) floats
+hipError_t net_forward(const float* params, int B, const float* X, float* Y, float* work, hipStream_t st);
+// gradient G of the MSE loss at (X, T); loss (nullable) receives the mean loss; when
+// lr > 0, one Adam step (step = 1, 2, ...) updates params with moments M, V
+hipError_t net_train_step(float* params, float* G, float* M, float* V, int step, float lr, int B, const float* X,
+                          const float* T, float* loss, float* work, hipStream_t st);
+
+// Learned rank proposal (k_learned.hip)
+// feat (3 x NET_IN floats) from the 32 eigenvalues of each mode's sketch Gram
+hipError_t launch_features(const double* const lam[3], int n, int64_t R, double eps, float* feat, hipStream_t st);
+// out (R_pad x cols, ld R_pad) = omega (R x w, ld R) zero padded (columns >= w zero)
+hipError_t launch_pad_omega(int64_t R, int64_t R_pad, int w, int cols, const double* omega, double* out,
+                            hipStream_t st);
+// out[:, j] = P[:, j] / sqrt(mu_j) for mu_j > rel * max(mu), else 0 (mp x mp, leading dimension ld)
+hipError_t launch_lowdin(int mp, int ld, const double* mu, const double* P, double* out, double rel, hipStream_t st);
+hipError_t launch_floor_sum(const double* part, int64_t ntiles, double* out, hipStream_t st);

@@ -192,6 +192,38 @@ def gaussian_side_matrices_torch(n: int, alpha: np.ndarray, centres: np.ndarray,
     return out
 
 
+def gaussian_test_matrix(seed: int, R: int, w: int) -> np.ndarray:
+    """R x w standard Gaussian test matrix (Fortran order) for the sketches of the
+    learned rank proposal and its randomized range finder."""
+    g = rng(WL_RANKNET, seed)
+    return np.asfortranarray(g.standard_normal(size=(R, w)))
+
+
+def smooth_problem_params(seed: int, index: int, n: int, R: int):
+    """A smooth Gaussian sum (the low-rank end of the rank-proposal workloads):
+    exponents log-uniform in [1e-2, 1], centres uniform in [-6, 6]^3, weights
+    uniform in [-1, 1].  Returns (alpha, centres (R, 3), xi)."""
+    g = rng(WL_RANKNET, 2_000_000 + seed * 4096 + index)
+    alpha = np.exp(g.uniform(math.log(1e-2), math.log(1.0), size=R))
+    centres = g.uniform(-6.0, 6.0, size=(R, 3))
+    xi = g.uniform(-1.0, 1.0, size=R)
+    return alpha, centres, xi
+
+
+def ranknet_shapes(seed: int, count: int):
+    """(family, n, R, eps) of the rank-proposal training and evaluation problems:
+    the uneven batch's size distribution (n uniform in {128,...,2048}, R
+    log-uniform in [64, 8192]), eps uniform over {1e-6, 1e-5, 1e-4, 1e-3}, and
+    the family ("newton": charges x 32-term 1/|x| sums, ranks about 0.6 m;
+    "smooth": smooth_problem_params, ranks about 0.1 m) with equal odds."""
+    g = rng(WL_RANKNET, 1_000_000 + seed)
+    ns = g.choice(np.array([128, 256, 512, 1024, 2048]), size=count)
+    Rs = np.rint(np.exp(g.uniform(math.log(64), math.log(8192), size=count))).astype(int)
+    es = g.choice(np.array([1e-6, 1e-5, 1e-4, 1e-3]), size=count)
+    fam = np.where(g.uniform(size=count) < 0.5, "newton", "smooth")
+    return [(str(f), int(a), int(c), float(e)) for f, a, c, e in zip(fam, ns, Rs, es)]
+
+
 def exactly_low_rank(seed: int, n: int, R: int, ranks=(3, 4, 5), eps: float = 1e-8,
                      signed: bool = True) -> CanonicalInput:
     """U^(l) = Q_l C_l with Q_l (n x r_l) orthonormal and C_l (r_l x R) Gaussian, so

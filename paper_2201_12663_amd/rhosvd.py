@@ -24,7 +24,12 @@ STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_NONFINITE", -3: "ERR_ALLOC", -4: "ERR
 # every symbol include/rhosvd.h declares
 EXPORTS = ["rhosvd_create", "rhosvd_destroy", "rhosvd_set_options", "rhosvd_reduce", "rhosvd_get",
            "rhosvd_get_xi", "rhosvd_get_spectrum", "rhosvd_get_v", "rhosvd_reduce_batched",
-           "rhosvd_batch_uses_graph", "rhosvd_phase_ms", "rhosvd_last_error", "rhosvd_version"]
+           "rhosvd_batch_uses_graph", "rhosvd_net_num_params", "rhosvd_net_set_params", "rhosvd_net_get_params",
+           "rhosvd_net_forward", "rhosvd_net_train_step", "rhosvd_sketch_features", "rhosvd_reduce_learned",
+           "rhosvd_phase_ms", "rhosvd_last_error", "rhosvd_version"]
+
+NET_IN, NET_OUT = 67, 2
+PATHS = {0: "range finder", 1: "gram (chosen)", 2: "gram (certificate failed)", 3: "gram (R < n)"}
 
 
 class Options(ctypes.Structure):
@@ -45,6 +50,12 @@ class Problem(ctypes.Structure):
                 ("cap_rank", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("cap_beta", ctypes.c_int64),
                 ("Z1", ctypes.c_void_p), ("Z2", ctypes.c_void_p), ("Z3", ctypes.c_void_p),
                 ("beta", ctypes.c_void_p), ("result", ctypes.c_void_p)]
+
+
+class LearnedInfo(ctypes.Structure):
+    """rhosvd_learned_info"""
+    _fields_ = [("proposal", ctypes.c_int32 * 3), ("width", ctypes.c_int32 * 3), ("fallback", ctypes.c_int32 * 3),
+                ("reserved", ctypes.c_int32), ("residual", ctypes.c_double * 3)]
 
 
 class RhosvdError(RuntimeError):
@@ -75,13 +86,24 @@ def load():
         lib.rhosvd_reduce_batched.argtypes = [vp, i32, ctypes.POINTER(Problem)]
         lib.rhosvd_batch_uses_graph.argtypes = [vp]
         lib.rhosvd_batch_uses_graph.restype = i32
+        fp = ctypes.c_float
+        lib.rhosvd_net_num_params.restype = i32
+        lib.rhosvd_net_set_params.argtypes = [vp, vp]
+        lib.rhosvd_net_get_params.argtypes = [vp, vp]
+        lib.rhosvd_net_forward.argtypes = [vp, i32, vp, vp]
+        lib.rhosvd_net_train_step.argtypes = [vp, i32, vp, vp, fp, vp, vp]
+        lib.rhosvd_sketch_features.argtypes = [vp, i64, i64, vp, vp, vp, vp, dbl, vp, i32, vp]
+        lib.rhosvd_reduce_learned.argtypes = [vp, i64, i64, vp, vp, vp, vp, dbl, vp, i32, ctypes.POINTER(i32),
+                                              ctypes.POINTER(LearnedInfo)]
         lib.rhosvd_phase_ms.argtypes = [vp, i32]
         lib.rhosvd_phase_ms.restype = dbl
         lib.rhosvd_last_error.argtypes = [vp]
         lib.rhosvd_last_error.restype = ctypes.c_char_p
         lib.rhosvd_version.restype = ctypes.c_char_p
         for f in ("rhosvd_create", "rhosvd_destroy", "rhosvd_set_options", "rhosvd_reduce", "rhosvd_get",
-                  "rhosvd_get_xi", "rhosvd_get_spectrum", "rhosvd_get_v", "rhosvd_reduce_batched"):
+                  "rhosvd_get_xi", "rhosvd_get_spectrum", "rhosvd_get_v", "rhosvd_reduce_batched",
+                  "rhosvd_net_set_params", "rhosvd_net_get_params", "rhosvd_net_forward", "rhosvd_net_train_step",
+                  "rhosvd_sketch_features", "rhosvd_reduce_learned"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -283,6 +305,68 @@ class Reducer:
     def reduce_batched_raw(self, descriptors):
         """Enqueue one batched pass (see include/rhosvd.h)."""
         self._check(self.lib.rhosvd_reduce_batched(self.h, len(descriptors), descriptors))
+
+    # ---- rank-proposal network and the learned path
+    @staticmethod
+    def _f32(t, name, numel=None):
+        import torch
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+            raise ValueError(f"{name}: expected a contiguous float32 CUDA tensor")
+        if numel is not None and t.numel() < numel:
+            raise ValueError(f"{name}: expected at least {numel} elements")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def net_set(self, params):
+        self._check(self.lib.rhosvd_net_set_params(self.h, self._f32(params, "params", self.lib.rhosvd_net_num_params())))
+
+    def net_get(self):
+        import torch
+        out = torch.empty(self.lib.rhosvd_net_num_params(), dtype=torch.float32, device="cuda")
+        self._check(self.lib.rhosvd_net_get_params(self.h, ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def net_forward(self, x):
+        import torch
+        y = torch.empty((x.shape[0], NET_OUT), dtype=torch.float32, device="cuda")
+        self._check(self.lib.rhosvd_net_forward(self.h, x.shape[0], self._f32(x, "x"), ctypes.c_void_p(y.data_ptr())))
+        return y
+
+    def net_train_step(self, x, target, lr, want_grad=False):
+        import torch
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        grad = torch.empty(self.lib.rhosvd_net_num_params(), dtype=torch.float32, device="cuda") if want_grad else None
+        self._check(self.lib.rhosvd_net_train_step(self.h, x.shape[0], self._f32(x, "x"), self._f32(target, "target"),
+                                                   float(lr), ctypes.c_void_p(loss.data_ptr()),
+                                                   ctypes.c_void_p(grad.data_ptr()) if grad is not None else None))
+        return loss, grad
+
+    def sketch_features(self, U1, U2, U3, xi, eps, omega):
+        import torch
+        n, R = U1.shape
+        if not (omega.is_cuda and omega.dtype == torch.float64 and omega.dim() == 2 and omega.shape[0] == R):
+            raise ValueError("omega: expected an (R, w) float64 CUDA tensor")
+        feat = torch.empty((3, NET_IN), dtype=torch.float32, device="cuda")
+        self._check(self.lib.rhosvd_sketch_features(self.h, n, R, _colmajor(U1, "U1"), _colmajor(U2, "U2"),
+                                                    _colmajor(U3, "U3"), ctypes.c_void_p(xi.data_ptr()), float(eps),
+                                                    _colmajor(omega, "omega"), omega.shape[1],
+                                                    ctypes.c_void_p(feat.data_ptr())))
+        return feat
+
+    def reduce_learned(self, U1, U2, U3, xi, eps, omega):
+        import torch
+        n, R = U1.shape
+        if not (omega.is_cuda and omega.dtype == torch.float64 and omega.dim() == 2 and omega.shape[0] == R):
+            raise ValueError("omega: expected an (R, w) float64 CUDA tensor")
+        ranks = (ctypes.c_int32 * 3)()
+        info = LearnedInfo()
+        self._check(self.lib.rhosvd_reduce_learned(self.h, n, R, _colmajor(U1, "U1"), _colmajor(U2, "U2"),
+                                                   _colmajor(U3, "U3"), ctypes.c_void_p(xi.data_ptr()), float(eps),
+                                                   _colmajor(omega, "omega"), omega.shape[1], ranks,
+                                                   ctypes.byref(info)))
+        self.n, self.R = n, R
+        self.ranks = tuple(int(r) for r in ranks)
+        return self.ranks, dict(proposal=list(info.proposal), width=list(info.width),
+                                path=list(info.fallback), residual=list(info.residual))
 
     def batch_uses_graph(self):
         return bool(self.lib.rhosvd_batch_uses_graph(self.h))

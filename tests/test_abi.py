@@ -57,6 +57,13 @@ def test_null_handle_batched(lib):
     assert lib.rhosvd_batch_uses_graph(None) == 0
 
 
+def test_network_size_and_null_handles(lib):
+    assert lib.rhosvd_net_num_params() == 128 * 67 + 128 + 128 * 128 + 128 + 2 * 128 + 2
+    assert lib.rhosvd_net_set_params(None, None) == -1
+    assert lib.rhosvd_net_forward(None, 1, None, None) == -1
+    assert lib.rhosvd_reduce_learned(None, 1, 1, None, None, None, None, 1e-3, None, 64, None, None) == -1
+
+
 def test_struct_offsets_match_a_c_compiler(tmp_path):
     """Compile the header with the host C compiler and compare every field offset
     of the public structs with the ctypes mirrors of the binding."""
@@ -67,7 +74,7 @@ def test_struct_offsets_match_a_c_compiler(tmp_path):
     if cc is None:
         pytest.skip("no host C compiler")
     structs = {"rhosvd_options": rhosvd.Options, "rhosvd_report": rhosvd.Report,
-               "rhosvd_problem": rhosvd.Problem}
+               "rhosvd_problem": rhosvd.Problem, "rhosvd_learned_info": rhosvd.LearnedInfo}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rhosvd.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')

@@ -1,0 +1,235 @@
+"""GPU tests of the learned rank proposal through the C-ABI: the FP32 network
+kernels against the FP64 oracle network (forward, gradient, Adam, a short
+training trajectory), the sketch features against the oracle's definition, the
+range finder's certificate and fallbacks with fixed proposals, and what the
+trained network gains over the plain method."""
+import math
+import os
+import time
+
+import numpy as np
+import pytest
+
+from oracle import mlp
+from paper_2201_12663_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PARAMS = os.path.join(ROOT, "paper_2201_12663_amd", "ranknet_params.npy")
+
+
+def dev(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    return (t if dtype is None else t.to(dtype)).cuda()
+
+
+def reducer(prec="fp64"):
+    from paper_2201_12663_amd import rhosvd
+    return rhosvd.Reducer(precision=prec)
+
+
+def rand_net(seed, scale=0.05):
+    g = np.random.default_rng(seed)
+    p = mlp.init_params(seed) + scale * g.standard_normal(mlp.N_PARAMS)
+    return p.astype(np.float32)
+
+
+def test_network_forward_gradient_adam_match_oracle():
+    import torch
+    g = np.random.default_rng(11)
+    p32 = rand_net(1)
+    p64 = p32.astype(np.float64)
+    X = g.standard_normal((33, 67)).astype(np.float32)
+    T = g.standard_normal((33, 2)).astype(np.float32)
+    red = reducer()
+    red.net_set(dev(p32))
+    y = red.net_forward(dev(X)).cpu().numpy()
+    yo, _, _ = mlp.forward(p64, X.astype(np.float64))
+    assert np.max(np.abs(y - yo)) <= 1e-4 * (1.0 + np.max(np.abs(yo)))
+    loss, grad = red.net_train_step(dev(X), dev(T), 0.0, want_grad=True)
+    Lo, Go = mlp.loss_and_grad(p64, X.astype(np.float64), T.astype(np.float64))
+    assert abs(float(loss.item()) - Lo) <= 1e-5 * max(1.0, Lo)
+    grad = grad.cpu().numpy()
+    assert np.max(np.abs(grad - Go)) <= 1e-4 * np.max(np.abs(Go)), np.max(np.abs(grad - Go))
+    # lr = 0 left the parameters alone
+    assert np.array_equal(red.net_get().cpu().numpy(), p32)
+    # one Adam step: compare where the gradient is not at rounding level
+    red.net_set(dev(p32))
+    red.net_train_step(dev(X), dev(T), 1e-3)
+    p1 = red.net_get().cpu().numpy().astype(np.float64)
+    po, _, _ = mlp.adam_step(p64, Go, np.zeros_like(p64), np.zeros_like(p64), 1, 1e-3)
+    big = np.abs(Go) > 1e-3 * np.max(np.abs(Go))
+    assert np.max(np.abs(p1 - po)[big]) <= 1e-6
+    red.close()
+
+
+def test_training_tracks_oracle_and_learns():
+    """Ten full-batch Adam steps on the GPU follow the FP64 oracle's loss curve;
+    three hundred reduce the loss of a smooth regression tenfold."""
+    g = np.random.default_rng(12)
+    X = g.standard_normal((64, 67)).astype(np.float32)
+    W = g.standard_normal((2, 67)) / 8.0
+    T = np.tanh(X @ W.T).astype(np.float32)
+    p32 = rand_net(2)
+    red = reducer()
+    red.net_set(dev(p32))
+    p, m, v = p32.astype(np.float64), np.zeros(mlp.N_PARAMS), np.zeros(mlp.N_PARAMS)
+    for t in range(1, 11):
+        loss, _ = red.net_train_step(dev(X), dev(T), 1e-3)
+        Lo, Go = mlp.loss_and_grad(p, X.astype(np.float64), T.astype(np.float64))
+        p, m, v = mlp.adam_step(p, Go, m, v, t, 1e-3)
+        assert abs(float(loss.item()) - Lo) <= 2e-4 * Lo, (t, float(loss.item()), Lo)
+    first = Lo
+    for _ in range(290):
+        loss, _ = red.net_train_step(dev(X), dev(T), 1e-3)
+    assert float(loss.item()) < first / 10
+    red.close()
+
+
+def test_sketch_features_match_oracle(orc):
+    ci = inputs.small_gaussian_sum(seed=3, n=100, R=333)
+    om = inputs.gaussian_test_matrix(5, ci.R, 64)
+    red = reducer()
+    from paper_2201_12663_amd import rhosvd
+    U = [rhosvd.to_device(u) for u in ci.U]
+    f = red.sketch_features(U[0], U[1], U[2], dev(ci.xi), ci.eps, rhosvd.to_device(om)).cpu().numpy()
+    Ut, _, _, _ = orc.normalize(ci.U, ci.xi)
+    fo = mlp.sketch_features(Ut, om, ci.n, ci.R, ci.eps)
+    resolved = fo > -6.0 / 16.0            # sigma_k / sigma_1 above 1e-6: the Gram route resolves them
+    assert np.max(np.abs(f - fo)[resolved]) <= 1e-5
+    assert np.all(f[~resolved] <= -5.0 / 16.0)
+    assert np.allclose(f[:, 32:], fo[:, 32:], atol=1e-6)
+    red.close()
+
+
+def constant_net(a, b):
+    """Parameters whose output is (a, b) for every input."""
+    p = np.zeros(mlp.N_PARAMS, dtype=np.float32)
+    p[-2:] = [a, b]
+    return p
+
+
+def smooth_problem(n, R, eps, idx=0):
+    a, c, xi = inputs.smooth_problem_params(9, idx, n, R)
+    return inputs.CanonicalInput(inputs.gaussian_side_matrices(inputs.grid(n), a, c), xi, eps,
+                                 name=f"smooth-n{n}-R{R}")
+
+
+def run_learned(ci, params, prec="fp64"):
+    import torch
+    from paper_2201_12663_amd import rhosvd
+    U = [rhosvd.to_device(u) for u in ci.U]
+    xi = dev(ci.xi)
+    om = rhosvd.to_device(inputs.gaussian_test_matrix(7, ci.R, min(max(64, ci.n), 2048)))
+    red = rhosvd.Reducer(precision=prec)
+    red.net_set(dev(params))
+    ranks, info = red.reduce_learned(U[0], U[1], U[2], xi, ci.eps, om)
+    res = red.get()
+    plain = rhosvd.Reducer(precision=prec)
+    pr = plain.reduce(U[0], U[1], U[2], xi, ci.eps)
+    pres = plain.get()
+    torch.cuda.synchronize()
+    red.close()
+    plain.close()
+    return ranks, info, res, tuple(pr), pres
+
+
+def test_range_finder_certified_with_ample_width(orc):
+    """Proposed width 128 on a smooth problem of rank ~44 (m = 512): the range
+    finder runs and certifies; the result is a valid reduction: orthonormal Z,
+    beta the exact core of Z, error within eps |A| and the Theorem 2.3 bound."""
+    ci = smooth_problem(512, 1024, 1e-5)
+    ranks, info, res, pranks, pres = run_learned(ci, constant_net(0.1, 0.15))
+    print("learned", ranks, info, "plain", pranks, flush=True)
+    assert info["path"] == [0, 0, 0] and info["width"] == [128, 128, 128]
+    o = orc.rhosvd(ci.U, ci.xi, ci.eps, with_core=False)
+    Ut, xip, _, _ = orc.normalize(ci.U, ci.xi)
+    Z = [z.cpu().numpy() for z in res.Z]
+    for l in range(3):
+        assert np.max(np.abs(Z[l].T @ Z[l] - np.eye(ranks[l]))) <= 1e-12
+        # the certified rank never undercuts the exact method's (its tails are no smaller)
+        assert ranks[l] >= o.ranks[l] - 1 and ranks[l] <= o.ranks[l] + 3, (ranks, o.ranks)
+        assert info["residual"][l] <= res.report["tau"]
+    be = orc.core([orc.project(Z[l], Ut[l]) for l in range(3)], xip)
+    assert np.max(np.abs(res.beta.cpu().numpy() - be)) <= 1e-10 * o.xi_norm
+    err = orc.error_gram(Ut, xip, Z)
+    assert err <= res.report["bound"] * (1 + 1e-9) + 1e-300
+    assert res.report["bound"] <= ci.eps * o.a_norm * (1 + 1e-9)
+
+
+def test_range_finder_falls_back_when_the_certificate_fails():
+    """Width 64 on a problem of rank ~260 (m = 512): no rank certifies, every mode
+    falls back to the Gram path and the result equals rhosvd_reduce's bit for bit."""
+    import torch
+    ci = inputs.batch_problem(3, 2, 512, 1024, 1e-3)
+    ranks, info, res, pranks, pres = run_learned(ci, constant_net(0.01, 0.01))
+    assert info["width"] == [64, 64, 64] and info["path"] == [2, 2, 2]
+    assert ranks == pranks
+    for l in range(3):
+        assert torch.equal(res.Z[l], pres.Z[l])
+    assert torch.equal(res.beta, pres.beta)
+
+
+def test_gram_path_chosen_for_wide_proposals():
+    import torch
+    ci = smooth_problem(256, 700, 1e-6, idx=1)
+    ranks, info, res, pranks, pres = run_learned(ci, constant_net(0.9, 0.95))
+    assert info["path"] == [1, 1, 1] and info["width"] == [0, 0, 0]
+    assert ranks == pranks
+    for l in range(3):
+        assert torch.equal(res.Z[l], pres.Z[l])
+
+
+@pytest.mark.skipif(not os.path.exists(PARAMS), reason="trained network parameters not present")
+def test_trained_network_gains_over_the_plain_method():
+    """Fresh problems of the rank-proposal workloads (seeds the training never
+    saw): with the trained network the learned path certifies on the low-rank
+    (smooth) problems and runs faster than the plain method there, keeps every
+    result within the Theorem 2.3 bound <= eps |A| (ranks never above the plain
+    method's), and on the high-rank (newton) problems chooses the Gram path
+    instead of wasting a range finder."""
+    import torch
+    from paper_2201_12663_amd import rhosvd, ranknet
+    params = np.load(PARAMS)
+    shapes = [("smooth", 1024, 4096, 1e-5), ("smooth", 2048, 4096, 1e-4), ("smooth", 1024, 2048, 1e-6),
+              ("smooth", 2048, 8192, 1e-5), ("newton", 1024, 2048, 1e-5), ("newton", 512, 4096, 1e-4)]
+    red = rhosvd.Reducer(precision="fp32")
+    red.net_set(dev(params))
+    plain = rhosvd.Reducer(precision="fp32")
+    t_l = {"smooth": 0.0, "newton": 0.0}
+    t_p = {"smooth": 0.0, "newton": 0.0}
+    rows = []
+    for i, (fam, n, R, eps) in enumerate(shapes):
+        p = ranknet.device_problem(fam, 777, i, n, R, eps)
+        om = ranknet.omega_for(555 + i, R, min(n, 2048))
+        for rep in range(2):            # the first run of each shape builds plans
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rl, info = red.reduce_learned(*p, om)
+            res = red.get(Z=False, sigma=False)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            rp = plain.reduce(*p)
+            pres = plain.get(Z=False, sigma=False)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+        t_l[fam] += t1 - t0
+        t_p[fam] += t2 - t1
+        rows.append((fam, n, R, eps, rl, rp, info["path"], info["width"]))
+        # certified: Theorem 2.3 with the range finder's exact tails
+        assert res.report["bound"] <= eps * res.report["a_norm"] * (1 + 1e-9)
+        # never coarser than the plain method; smaller where the Gram route's tails
+        # sit on its FP64 noise floor (eigenvalues of G are exact only to ~u |G|)
+        assert all(a <= b + 2 for a, b in zip(rl, rp)), (rl, rp)
+        if fam == "smooth":
+            assert info["path"] == [0, 0, 0], (fam, n, R, info)
+        else:
+            assert all(x in (1, 2) for x in info["path"]), (fam, n, R, info)
+    for r in rows:
+        print(r, flush=True)
+    print("seconds learned / plain:", t_l, t_p, flush=True)
+    assert t_l["smooth"] < 0.8 * t_p["smooth"]
+    red.close()
+    plain.close()
