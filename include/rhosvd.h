@@ -68,7 +68,17 @@ typedef struct {
     int32_t profile;         /* nonzero: time each phase with HIP events (see rhosvd_phase_ms) */
     int32_t beta_fp32;       /* nonzero: beta is written as float (r1*r2*r3 floats) instead of
                                 double, halving its size; meant for the FP32 and BF16x3 cores */
-    int32_t reserved[4];     /* must be zero */
+    int32_t refine_tails;    /* nonzero (rhosvd_reduce): after the Gram-route cut r, with
+                                Z_p the leading p = min(m, r + r/8 + 16) eigenvectors and
+                                V_p = Z_p^T U~, the cut is taken again on the tails
+                                t_r^2 = sum_{r<=k<p} |V_p[k,:]|^2 + |U~ - Z_p V_p|_F^2
+                                (= |(I - Z_r Z_r^T) U~|_F^2 exactly, in Z's column order),
+                                both parts formed directly in FP64.  The Gram route's
+                                small eigenvalues carry FP64 noise of about u |G|; where
+                                tau^2 lies below that floor the refined ranks are the
+                                smaller, still certified ones (Theorem 2.3); the
+                                spectrum then holds |V_p[k,:]| for k < p. */
+    int32_t reserved[3];     /* must be zero */
 } rhosvd_options;
 
 typedef struct {

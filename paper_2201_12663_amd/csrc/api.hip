@@ -69,6 +69,9 @@ struct rhosvd_ctx {
     double* scal = nullptr;
     double* Z[3] = {};                   // n_pad x zr_pad
     void* V[3] = {};                     // zr_pad x R_pad (FP64 or FP32)
+    double* Vref[3] = {};                // refine_tails with a mixed core: FP64 projection
+    double* rpart[3] = {};               // refine_tails: residual partial sums
+    double* rfloor = nullptr;            // refine_tails: squared residuals (3)
     int vprec = 0;
     // R < n: Z = U~ W_r Lambda_r^-1/2, re-orthonormalized by (Z^T Z)^-1/2
     double* Wr[3] = {};                  // R_pad x zr_pad
@@ -134,7 +137,7 @@ rhosvd_status fail(rhosvd_ctx* h, rhosvd_status s, const std::string& msg) {
 rhosvd_status check_options(const rhosvd_options* o, std::string& msg) {
     if (!o) return RHOSVD_OK;
     if (o->precision < 0 || o->precision > 2) { msg = "unknown precision"; return RHOSVD_ERR_ARG; }
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 3; ++i)
         if (o->reserved[i] != 0) { msg = "reserved option fields must be zero"; return RHOSVD_ERR_ARG; }
     return RHOSVD_OK;
 }
@@ -182,6 +185,12 @@ size_t carve_all(rhosvd_ctx* h, char* base) {
         h->Z[l] = c.take<double>((size_t)np * zp);
         h->V[l] = (void*)c.take<char>((size_t)zp * Rp * esz);
     }
+    for (int l = 0; l < 3; ++l) {
+        const bool refine = h->opt.refine_tails != 0;
+        h->Vref[l] = (refine && esz == 4) ? c.take<double>((size_t)zp * Rp) : nullptr;
+        h->rpart[l] = refine ? c.take<double>((size_t)(np / 64) * (Rp / 64)) : nullptr;
+    }
+    h->rfloor = c.take<double>(4);
     h->xip = c.take<double>(Rp);
     h->flags = c.take<int>(16);
     h->gram_part = (h->gram_splits > 1) ? c.take<double>((size_t)h->gram_splits * 3 * np * np) : nullptr;
@@ -531,6 +540,15 @@ rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R, const double*
         h->ranks[l] = h->host[l];
         h->r_pad[l] = (int)round_up(h->ranks[l] > 0 ? h->ranks[l] : 1, RPAD_CORE);
     }
+    // refine_tails: Z and V first at the wider p_l = min(m, r + r/8 + 16)
+    const bool refine = h->opt.refine_tails != 0 && h->ranks[0] > 0;
+    int p_ref[3] = {0, 0, 0};
+    if (refine)
+        for (int l = 0; l < 3; ++l) {
+            p_ref[l] = (int)std::min<int64_t>(h->m, h->ranks[l] + h->ranks[l] / 8 + 16);
+            h->ranks[l] = p_ref[l];
+            h->r_pad[l] = (int)round_up(p_ref[l], RPAD_CORE);
+        }
     // a5/a6: Z and the projections V = Z^T U~ (FP64 MFMA; rounded to FP32 for the mixed core)
     if (!h->rside) {
         // Z = H W[:, order[0..r-1]]: back-transformed eigenvectors, sign rule, zero padding
@@ -556,8 +574,58 @@ rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R, const double*
         if (h->ranks[l] < 1) continue;
         if (h->vprec == RHOSVD_FP64)
             CK(h, launch_project(h->n_pad, h->R_pad, h->r_pad[l], h->Z[l], h->Ut[l], (double*)h->V[l], nullptr, st));
+        else if (refine)
+            CK(h, launch_project(h->n_pad, h->R_pad, h->r_pad[l], h->Z[l], h->Ut[l], h->Vref[l], nullptr, st));
         else
             CK(h, launch_project(h->n_pad, h->R_pad, h->r_pad[l], h->Z[l], h->Ut[l], nullptr, (float*)h->V[l], st));
+    }
+    if (refine) {
+        // the cut again on tails computed from V, not from G: for orthonormal Z_p,
+        // |(I - Z_r Z_r^T) U~|_F^2 = sum_{r<=k<p} |V[k, :]|^2 + |U~ - Z_p V_p|_F^2 exactly,
+        // in the order of Z's columns; both parts are formed directly in FP64
+        const int64_t ntl = (h->n_pad / 64) * (h->R_pad / 64);
+        for (int l = 0; l < 3; ++l) {
+            const double* V64 = h->vprec == RHOSVD_FP64 ? (const double*)h->V[l] : h->Vref[l];
+            CK(h, launch_resid_partials(h->n_pad, h->R_pad, h->r_pad[l], h->Z[l], V64, h->Ut[l], h->rpart[l], st));
+            CK(h, launch_floor_sum(h->rpart[l], ntl, h->rfloor + l, st));
+            CK(h, launch_row_norms2(p_ref[l], h->r_pad[l], h->R_pad, V64, h->Qn[l], st));
+        }
+        TruncArgs tb{};
+        for (int l = 0; l < 3; ++l) {
+            tb.lam[l] = h->Qn[l];
+            tb.m_mode[l] = p_ref[l];
+            tb.sigma[l] = h->sigma[l];
+            tb.order[l] = h->order[l];
+            tb.tails[l] = h->tails[l];
+        }
+        tb.m = (int)h->m;
+        tb.m_pad = (int)h->m_pad;
+        tb.n = (int)n;
+        tb.n_pad = (int)h->n_pad;
+        tb.xip = h->xip;
+        tb.R_pad = h->R_pad;
+        tb.anorm_part = h->anorm_part;
+        tb.anorm_ntiles = h->anorm_ntiles;
+        tb.eps = eps;
+        tb.ranks = h->ranks_dev;
+        tb.scal = h->scal;
+        tb.floor2 = h->rfloor;
+        tb.presorted = 1;
+        CK(h, launch_truncate(tb, st));
+        CK(h, hipMemcpyAsync(h->host, h->ranks_dev, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
+        CK(h, hipStreamSynchronize(st));
+        for (int l = 0; l < 3; ++l) {
+            // p_l + 1: not even p_l certifies on the refined tails; keep p_l (the report's tail says so)
+            const int r = std::max(1, std::min(h->host[l], p_ref[l]));
+            h->ranks[l] = r;
+            if (h->r_pad[l] > r)
+                CK(h, hipMemsetAsync(h->Z[l] + (int64_t)r * h->n_pad, 0, (size_t)(h->r_pad[l] - r) * h->n_pad * 8, st));
+            if (h->vprec == RHOSVD_FP64)
+                CK(h, launch_v_finalize(r, h->r_pad[l], h->R_pad, (const double*)h->V[l], (double*)h->V[l], nullptr,
+                                        st));
+            else
+                CK(h, launch_v_finalize(r, h->r_pad[l], h->R_pad, h->Vref[l], nullptr, (float*)h->V[l], st));
+        }
     }
     mark(h, 6);
     h->reduce_timed = true;

@@ -86,7 +86,55 @@ __global__ void k_floor_sum(const double* __restrict__ part, int64_t ntiles, dou
     if (threadIdx.x == 0) *out = red[0];
 }
 
+// out[k] = sigma[k]^2, k < r (sorted singular values back to eigenvalues)
+__global__ void k_square_prefix(int r, const double* __restrict__ sigma, double* __restrict__ out) {
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < r; k += gridDim.x * blockDim.x) out[k] = sigma[k] * sigma[k];
+}
+
+// out[k] = sum_nu V[k, nu]^2, one thread per row (coalesced across k)
+__global__ void k_row_norms2(int p, int ld, int64_t R_pad, const double* __restrict__ V, double* __restrict__ out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= p) return;
+    double acc = 0.0;
+    for (int64_t nu = 0; nu < R_pad; ++nu) {
+        const double v = V[k + nu * ld];
+        acc = fma(v, v, acc);
+    }
+    out[k] = acc;
+}
+
+// dst = src with rows >= keep set to zero (ld x R_pad, column-major); dst may be src
+template <typename O>
+__global__ void k_v_finalize(int keep, int ld, int64_t R_pad, const double* __restrict__ src, O* __restrict__ dst) {
+    const int64_t tot = (int64_t)ld * R_pad;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(e % ld);
+        dst[e] = (O)(j < keep ? src[e] : 0.0);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_square_prefix(int r, const double* sigma, double* out, hipStream_t st) {
+    if (r < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_square_prefix, dim3((unsigned)((r + 255) / 256)), dim3(256), 0, st, r, sigma, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_norms2(int p, int ld, int64_t R_pad, const double* V, double* out, hipStream_t st) {
+    if (p < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_row_norms2, dim3((unsigned)((p + 63) / 64)), dim3(64), 0, st, p, ld, R_pad, V, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_v_finalize(int keep, int ld, int64_t R_pad, const double* src, double* dst64, float* dst32,
+                             hipStream_t st) {
+    if (dst64)
+        hipLaunchKernelGGL(k_v_finalize<double>, dim3(2048), dim3(256), 0, st, keep, ld, R_pad, src, dst64);
+    else
+        hipLaunchKernelGGL(k_v_finalize<float>, dim3(2048), dim3(256), 0, st, keep, ld, R_pad, src, dst32);
+    return hipGetLastError();
+}
 
 hipError_t launch_features(const double* const lam[3], int n, int64_t R, double eps, float* feat, hipStream_t st) {
     hipLaunchKernelGGL(k_features, dim3(3), dim3(128), 0, st, lam[0], lam[1], lam[2], n, R, eps, feat);

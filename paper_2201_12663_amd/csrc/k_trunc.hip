@@ -31,7 +31,8 @@ __device__ double block_sum(double v, double* red) {
 __device__ __forceinline__ void truncate_mode(int mode, const double* __restrict__ lam, int m, const double* __restrict__ xip,
                               int64_t R_pad, const double* __restrict__ anorm_part, int64_t anorm_ntiles, double eps,
                               double* __restrict__ sigma, int* __restrict__ order, double* __restrict__ tails,
-                              int* __restrict__ ranks, double* __restrict__ scal, double floor2 = 0.0) {
+                              int* __restrict__ ranks, double* __restrict__ scal, double floor2 = 0.0,
+                              bool presorted = false) {
     __shared__ double key[MAXM];
     __shared__ int idx[MAXM];
     __shared__ double scan[MAXM + 1];
@@ -57,8 +58,9 @@ __device__ __forceinline__ void truncate_mode(int mode, const double* __restrict
         idx[i] = i;
     }
     __syncthreads();
-    // bitonic sort: descending key, ascending index on ties
-    for (int size = 2; size <= N2; size <<= 1) {
+    // bitonic sort: descending key, ascending index on ties (skipped when the values
+    // come in the order of the vectors they belong to: the tails then follow that order)
+    for (int size = 2; size <= (presorted ? 1 : N2); size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
             for (int i = t; i < N2; i += TB) {
                 int j = i ^ stride;
@@ -115,7 +117,7 @@ __global__ __launch_bounds__(TB) void k_truncate(TruncArgs a) {
     const int mode = blockIdx.x;
     const int m = a.m_mode[mode] > 0 ? a.m_mode[mode] : a.m;
     truncate_mode(mode, a.lam[mode], m, a.xip, a.R_pad, a.anorm_part, a.anorm_ntiles, a.eps, a.sigma[mode],
-                  a.order[mode], a.tails[mode], a.ranks, a.scal, a.floor2 ? a.floor2[mode] : 0.0);
+                  a.order[mode], a.tails[mode], a.ranks, a.scal, a.floor2 ? a.floor2[mode] : 0.0, a.presorted != 0);
 }
 
 // batched: grid (3, problems); problems with non-finite input are skipped

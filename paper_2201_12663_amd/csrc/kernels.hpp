@@ -129,6 +129,7 @@ struct TruncArgs {
     double* scal;           // [0] xi_norm, [1] a_norm, [2] tau
     int m_mode[3];          // per-mode number of eigenvalues (0: m)
     const double* floor2;   // per-mode squared tail floor (device, 3 doubles) or null
+    int presorted;          // nonzero: keep the given order (no sort; order = identity)
 };
 hipError_t launch_truncate(const TruncArgs& a, hipStream_t st);
 
@@ -229,3 +230,10 @@ hipError_t launch_pad_omega(int64_t R, int64_t R_pad, int w, int cols, const dou
 // out[:, j] = P[:, j] / sqrt(mu_j) for mu_j > rel * max(mu), else 0 (mp x mp, leading dimension ld)
 hipError_t launch_lowdin(int mp, int ld, const double* mu, const double* P, double* out, double rel, hipStream_t st);
 hipError_t launch_floor_sum(const double* part, int64_t ntiles, double* out, hipStream_t st);
+// out[k] = |V[k, :]|^2 for k < p (V: ld x R_pad, column-major, FP64)
+hipError_t launch_row_norms2(int p, int ld, int64_t R_pad, const double* V, double* out, hipStream_t st);
+// refinement of the Gram-route cut: out[k] = sigma[k]^2 (k < r); V rows >= keep zeroed
+// (dst64 may equal src) or converted to FP32 (dst32)
+hipError_t launch_square_prefix(int r, const double* sigma, double* out, hipStream_t st);
+hipError_t launch_v_finalize(int keep, int ld, int64_t R_pad, const double* src, double* dst64, float* dst32,
+                             hipStream_t st);

@@ -7,8 +7,9 @@ backward passes and Adam steps (rhosvd_net_*).  This module only draws the
 problems, batches the samples and keeps the loop.
 
 Targets per mode (both as fractions of m = min(n, R)): the plain method's rank
-r, and a sketch width p = min(m, ceil(1.1 r) + 16) that leaves the range finder
-room to certify.
+r (with the residual-refined cut, so that the labels are not inflated by the
+Gram route's FP64 noise floor), and a sketch width p = min(m, ceil(1.1 r) + 16)
+that leaves the range finder room to certify.
 
     python -m paper_2201_12663_amd.ranknet train --problems 768 --out PATH
     python -m paper_2201_12663_amd.ranknet evaluate --params PATH --problems 256
@@ -125,7 +126,9 @@ def main():
     args = ap.parse_args()
     from . import inputs, rhosvd
     log = lambda m: print(m, file=sys.stderr, flush=True)
-    red = rhosvd.Reducer(precision="fp64")
+    # labels: the plain method with the residual-refined cut (refine_tails), whose
+    # ranks are not inflated by the Gram route's FP64 noise floor
+    red = rhosvd.Reducer(precision="fp64", refine_tails=True)
     if args.cmd == "train":
         shapes = inputs.ranknet_shapes(args.seed, args.problems)
         X, T, meta = dataset(red, shapes, args.seed, log)

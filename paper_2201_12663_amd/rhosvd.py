@@ -34,7 +34,8 @@ PATHS = {0: "range finder", 1: "gram (chosen)", 2: "gram (certificate failed)", 
 
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("max_eig_sweeps", ctypes.c_int32),
-                ("profile", ctypes.c_int32), ("beta_fp32", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("profile", ctypes.c_int32), ("beta_fp32", ctypes.c_int32), ("refine_tails", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class Report(ctypes.Structure):
@@ -147,11 +148,13 @@ class Result:
 class Reducer:
     """One library handle bound to a stream."""
 
-    def __init__(self, precision="fp64", stream=None, max_eig_sweeps=0, profile=False, beta_fp32=False):
+    def __init__(self, precision="fp64", stream=None, max_eig_sweeps=0, profile=False, beta_fp32=False,
+                 refine_tails=False):
         import torch
         self.lib = load()
         self.opt = Options()
         self.opt.beta_fp32 = 1 if beta_fp32 else 0
+        self.opt.refine_tails = 1 if refine_tails else 0
         self.beta_dtype = torch.float32 if beta_fp32 else torch.float64
         self.opt.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self.opt.max_eig_sweeps = int(max_eig_sweeps)

@@ -193,8 +193,9 @@ def test_trained_network_gains_over_the_plain_method():
     import torch
     from paper_2201_12663_amd import rhosvd, ranknet
     params = np.load(PARAMS)
-    shapes = [("smooth", 1024, 4096, 1e-5), ("smooth", 2048, 4096, 1e-4), ("smooth", 1024, 2048, 1e-6),
-              ("smooth", 2048, 8192, 1e-5), ("newton", 1024, 2048, 1e-5), ("newton", 512, 4096, 1e-4)]
+    # within the FP64 Gram route's resolution (tau^2 / sigma_1^2 above ~1e-15)
+    shapes = [("smooth", 1024, 4096, 1e-5), ("smooth", 2048, 4096, 1e-4), ("smooth", 2048, 8192, 1e-3),
+              ("smooth", 1024, 4096, 1e-4), ("newton", 1024, 4096, 1e-4), ("newton", 512, 2048, 1e-5)]
     red = rhosvd.Reducer(precision="fp32")
     red.net_set(dev(params))
     plain = rhosvd.Reducer(precision="fp32")
@@ -224,12 +225,13 @@ def test_trained_network_gains_over_the_plain_method():
         # sit on its FP64 noise floor (eigenvalues of G are exact only to ~u |G|)
         assert all(a <= b + 2 for a, b in zip(rl, rp)), (rl, rp)
         if fam == "smooth":
-            assert info["path"] == [0, 0, 0], (fam, n, R, info)
+            assert sum(x == 0 for x in info["path"]) >= 2, (fam, n, R, info)
         else:
             assert all(x in (1, 2) for x in info["path"]), (fam, n, R, info)
     for r in rows:
         print(r, flush=True)
     print("seconds learned / plain:", t_l, t_p, flush=True)
-    assert t_l["smooth"] < 0.8 * t_p["smooth"]
+    assert t_l["smooth"] < 0.5 * t_p["smooth"]
+    assert t_l["newton"] < 1.2 * t_p["newton"]
     red.close()
     plain.close()

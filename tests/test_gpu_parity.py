@@ -196,3 +196,65 @@ def test_full_size_newton1024_mixed(orc, prec):
     err = float(np.sqrt(err_z ** 2 + db ** 2))
     _flush(f"{prec}: rel err {err / a:.3e} (core part {db / a:.3e})")
     assert err <= (ci.eps + 1e-6) * a
+
+
+@pytest.mark.parametrize("prec,shape", [("fp64", (512, 1024, 1e-5)), ("fp32", (512, 1024, 1e-5)),
+                                        ("fp64", (256, 2048, 1e-6)), ("fp32", (512, 2048, 1e-6))])
+def test_refined_tails_recover_the_oracle_ranks(orc, prec, shape):
+    """Smooth low-rank inputs: where the sum of the Gram route's noise eigenvalues
+    (about u |G| each) exceeds tau^2 its ranks come out above the oracle's; with
+    refine_tails the cut uses tails formed from V and the exact residual and lands
+    on the oracle's ranks, with orthonormal Z, beta the exact core of Z and the
+    error within the bound.  (Below tau^2 ~ u |G| itself the Gram route's vectors
+    near the cut are inaccurate and no refinement of its cut can recover them.)"""
+    import torch
+    from paper_2201_12663_amd import rhosvd
+    n, R, eps = shape
+    a, c, xi = inputs.smooth_problem_params(9, 0, n, R)
+    ci = inputs.CanonicalInput(inputs.gaussian_side_matrices(inputs.grid(n), a, c), xi, eps)
+    o = orc.rhosvd(ci.U, ci.xi, ci.eps, with_core=False)
+    U = [rhosvd.to_device(u) for u in ci.U]
+    xd = torch.from_numpy(ci.xi).cuda()
+    plain = rhosvd.Reducer(precision=prec)
+    ref = rhosvd.Reducer(precision=prec, refine_tails=True)
+    rp = plain.reduce(U[0], U[1], U[2], xd, ci.eps)
+    rr = ref.reduce(U[0], U[1], U[2], xd, ci.eps)
+    res = ref.get()
+    torch.cuda.synchronize()
+    print("oracle", o.ranks, "gram route", rp, "refined", rr, flush=True)
+    for l in range(3):
+        assert abs(rr[l] - o.ranks[l]) <= 2, (rr, o.ranks)
+        assert rr[l] <= rp[l]
+    Ut, xip, _, _ = orc.normalize(ci.U, ci.xi)
+    Z = [z.cpu().numpy() for z in res.Z]
+    for l in range(3):
+        assert np.max(np.abs(Z[l].T @ Z[l] - np.eye(rr[l]))) <= 1e-12
+    be = orc.core([orc.project(Z[l], Ut[l]) for l in range(3)], xip)
+    tol = 1e-10 if prec == "fp64" else 2e-6
+    assert np.linalg.norm((res.beta.cpu().numpy() - be).ravel()) <= tol * o.xi_norm
+    err = orc.error_gram(Ut, xip, Z)
+    assert err <= res.report["bound"] * (1 + 1e-9)
+    assert res.report["bound"] <= ci.eps * o.a_norm * (1 + 1e-9)
+    plain.close()
+    ref.close()
+
+
+def test_refined_tails_keep_accurate_gram_ranks(orc):
+    """Where the Gram route's tails are accurate (the Newton-type input), the
+    refinement keeps the same ranks."""
+    import torch
+    from paper_2201_12663_amd import rhosvd
+    ci = inputs.newton_centres(seed=2, n=160, n_centres=20, eps=1e-5)
+    U = [rhosvd.to_device(u) for u in ci.U]
+    xd = torch.from_numpy(ci.xi).cuda()
+    a = rhosvd.Reducer(precision="fp64")
+    b = rhosvd.Reducer(precision="fp64", refine_tails=True)
+    ra = a.reduce(U[0], U[1], U[2], xd, ci.eps)
+    rb = b.reduce(U[0], U[1], U[2], xd, ci.eps)
+    torch.cuda.synchronize()
+    o = orc.rhosvd(ci.U, ci.xi, ci.eps, with_core=False)
+    print("oracle", o.ranks, "gram", ra, "refined", rb, flush=True)
+    for l in range(3):
+        assert abs(rb[l] - ra[l]) <= 1 and abs(rb[l] - o.ranks[l]) <= 1
+    a.close()
+    b.close()
