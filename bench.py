@@ -14,7 +14,9 @@ eps + 1e-6 of |A| in this run: the truncation part is bounded by Theorem 2.3 (th
 library's report), the core part is measured against the FP64 path's core, and
 the two are orthogonal.
 
-The line also carries "batched": the uneven batch (256 problems, n uniform in
+The line also carries "learned": fresh problems of the rank-proposal workloads
+through the learned path (trained network, certified range finder, fallback)
+against the plain method; and "batched": the uneven batch (256 problems, n uniform in
 {128,...,2048}, R log-uniform in [64, 8192], each the first R terms of ceil(R/32)
 charges x 32 Gaussian terms, eps = 1e-5) as one graph-recorded batched pass
 (FP32-MFMA cores, FP64 eigensolver), timed over replays, next to the plain FP64
@@ -42,6 +44,23 @@ WORKLOAD = ("newton-n1024-R4096: 128 random +-1 charges in [-6,6]^3 x 32-term Ga
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "core_bf16x3_newton1024_traffic.json")
+
+
+def core_traffic(kernel_source):
+    """HBM bytes per launch of the BF16x3 core from the committed counter summary
+    (rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size),
+    or None when there is none or the kernel source changed since it was taken."""
+    import hashlib
+    import json as _json
+    try:
+        d = _json.load(open(TRAFFIC_SUMMARY))
+        sha = hashlib.sha256(open(kernel_source, "rb").read()).hexdigest()
+        return d["bytes_per_launch"] if d.get("source_sha256") == sha else None
+    except (OSError, ValueError, KeyError):
+        return None
 
 
 def time_path(red, U, xi, eps, beta_buf, steps, warmup):
@@ -172,6 +191,57 @@ def bench_batched(args):
     return result
 
 
+def bench_learned(args):
+    """Fresh problems of the rank-proposal workloads (evaluation seeds, disjoint
+    from training): the learned path (trained network, range finder, certificate,
+    fallback) against the plain method, FP32 cores, one after the other."""
+    import numpy as np
+    import torch
+    from paper_2201_12663_amd import inputs, ranknet, rhosvd
+    if not os.path.exists(ranknet.DEFAULT_PARAMS):
+        return {"skipped": "no trained network parameters"}
+    shapes = inputs.ranknet_shapes(10_000 + 7, args.learned_count)
+    red = rhosvd.Reducer(precision="fp32")
+    red.net_set(torch.from_numpy(np.load(ranknet.DEFAULT_PARAMS)).cuda())
+    plain = rhosvd.Reducer(precision="fp32")
+    t_l = t_p = 0.0
+    modes_rf = modes = certified = 0
+    fam_t = {}
+    for i, (fam, n, R, eps) in enumerate(shapes):
+        p = ranknet.device_problem(fam, 10_007, i, n, R, eps)
+        om = ranknet.omega_for(900_000 + i, R, min(n, 2048))
+        for rep in range(2):      # the first pass builds the eigensolver plans for the sizes
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rl, info = red.reduce_learned(*p, om)
+            res = red.get(Z=False, sigma=False)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            plain.reduce(*p)
+            plain.get(Z=False, sigma=False)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+        t_l += t1 - t0
+        t_p += t2 - t1
+        ft = fam_t.setdefault(fam, [0.0, 0.0])
+        ft[0] += t1 - t0
+        ft[1] += t2 - t1
+        modes += 3
+        modes_rf += sum(x == 0 for x in info["path"])
+        certified += res.report["bound"] <= eps * res.report["a_norm"] * (1 + 1e-9)
+        del p, om
+    red.close()
+    plain.close()
+    out = dict(workload=("%d fresh rank-proposal problems (n in {128..2048}, R log-uniform [64, 8192], "
+                         "eps in {1e-6..1e-3}, newton/smooth families)" % len(shapes)),
+               range_finder_modes=modes_rf, modes=modes, within_bound=certified,
+               s_learned=round(t_l, 3), s_plain=round(t_p, 3), speedup=round(t_p / t_l, 3),
+               by_family={k: dict(s_learned=round(v[0], 3), s_plain=round(v[1], 3), speedup=round(v[1] / v[0], 3))
+                          for k, v in fam_t.items()})
+    log(f"learned: {modes_rf}/{modes} modes on the range finder, speedup {out['speedup']} ({out['by_family']})")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -185,15 +255,25 @@ def main():
     ap.add_argument("--batch-warmup", type=int, default=1)
     ap.add_argument("--batch-precision", default="fp32")
     ap.add_argument("--no-batch-fp64-baseline", dest="batch_fp64_baseline", action="store_false")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--learned-count", type=int, default=32)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="copy this many MiB once (a plain copy kernel of known size for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build's path runs on a single MI355X "
-              "(multi-GPU sharding is a design note, not an implemented path).", file=sys.stderr)
+        print("bench.py measures one GPU only: the reduction runs on a single MI355X and sharding "
+              "across GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
     from paper_2201_12663_amd import inputs, rhosvd
 
+    if args.calib_copy_mib > 0:
+        src = torch.ones(args.calib_copy_mib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     log("generating inputs")
     ci = inputs.newton_centres(0)
     U = [rhosvd.to_device(u) for u in ci.U]
@@ -261,12 +341,16 @@ def main():
         "speedup_vs_plain_fp64": (rb["reductions_per_s"] / results["fp64"]["reductions_per_s"]
                                   if "fp64" in results else None),
         "roofline": {"bound": "mfma", "kernel": f"k_core ({best})", "achieved": round(achieved, 3),
-                     "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                     "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                     "traffic": core_traffic(os.path.join(ROOT, "paper_2201_12663_amd", "csrc", "k_core.hip"))
+                     if best == "bf16x3" else None,
                      "flops_per_launch": 2.0 * rb["ranks"][0] * rb["ranks"][1] * rb["ranks"][2] * ci.R
                      * (3 if best == "bf16x3" else 1)},
     }
     if not args.no_batch:
         line["batched"] = bench_batched(args)
+    if not args.no_learned:
+        line["learned"] = bench_learned(args)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample)")
         line["cpu_baseline"] = cpu_baseline(ci)

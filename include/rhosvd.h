@@ -48,7 +48,7 @@ typedef enum {
     RHOSVD_ERR_DEVICE = -4,     /* a HIP runtime call failed */
     RHOSVD_ERR_NOCONV = -5,     /* the eigensolver hit its sweep cap */
     RHOSVD_ERR_STATE = -6,      /* rhosvd_get/inspection without a successful rhosvd_reduce */
-    RHOSVD_ERR_UNSUPPORTED = -7, /* size or option outside what this build supports */
+    RHOSVD_ERR_UNSUPPORTED = -7, /* size or option outside what the library supports */
     RHOSVD_ERR_CAPACITY = -8     /* batched: a rank exceeds cap_rank, or r1 r2 r3 exceeds cap_beta */
 } rhosvd_status;
 

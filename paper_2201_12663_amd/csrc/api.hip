@@ -476,8 +476,8 @@ rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R, const double*
     if (!U1 || !U2 || !U3 || !xi || !ranks) return fail(h, RHOSVD_ERR_ARG, "null pointer argument");
     if (n < 1 || R < 1) return fail(h, RHOSVD_ERR_ARG, "n and R must be >= 1");
     if (!(eps > 0.0) || !isfinite(eps)) return fail(h, RHOSVD_ERR_ARG, "eps must be finite and > 0");
-    if ((n < R ? n : R) > 2048) return fail(h, RHOSVD_ERR_UNSUPPORTED, "min(n, R) > 2048 is not supported by this build");
-    if (n > 65536) return fail(h, RHOSVD_ERR_UNSUPPORTED, "n > 65536 is not supported by this build");
+    if ((n < R ? n : R) > 2048) return fail(h, RHOSVD_ERR_UNSUPPORTED, "min(n, R) > 2048 is not supported by this library");
+    if (n > 65536) return fail(h, RHOSVD_ERR_UNSUPPORTED, "n > 65536 is not supported by this library");
     rhosvd_status s = layout(h, n, R);
     if (s != RHOSVD_OK) return s;
     hipStream_t st = h->stream;
@@ -850,8 +850,8 @@ rhosvd_status prologue(rhosvd_ctx* h, int64_t n, int64_t R, const double* U1, co
     if (!U1 || !U2 || !U3 || !xi) return fail(h, RHOSVD_ERR_ARG, "null pointer argument");
     if (n < 1 || R < 1) return fail(h, RHOSVD_ERR_ARG, "n and R must be >= 1");
     if (!(eps > 0.0) || !isfinite(eps)) return fail(h, RHOSVD_ERR_ARG, "eps must be finite and > 0");
-    if ((n < R ? n : R) > 2048) return fail(h, RHOSVD_ERR_UNSUPPORTED, "min(n, R) > 2048 is not supported by this build");
-    if (n > 65536) return fail(h, RHOSVD_ERR_UNSUPPORTED, "n > 65536 is not supported by this build");
+    if ((n < R ? n : R) > 2048) return fail(h, RHOSVD_ERR_UNSUPPORTED, "min(n, R) > 2048 is not supported by this library");
+    if (n > 65536) return fail(h, RHOSVD_ERR_UNSUPPORTED, "n > 65536 is not supported by this library");
     rhosvd_status s = layout(h, n, R);
     if (s != RHOSVD_OK) return s;
     hipStream_t st = h->stream;
