@@ -205,7 +205,7 @@ def bench_learned(args):
     red.net_set(torch.from_numpy(np.load(ranknet.DEFAULT_PARAMS)).cuda())
     plain = rhosvd.Reducer(precision="fp32")
     t_l = t_p = 0.0
-    modes_rf = modes = certified = 0
+    modes_rf = modes = certified = eligible = 0
     fam_t = {}
     for i, (fam, n, R, eps) in enumerate(shapes):
         p = ranknet.device_problem(fam, 10_007, i, n, R, eps)
@@ -227,6 +227,7 @@ def bench_learned(args):
         ft[0] += t1 - t0
         ft[1] += t2 - t1
         modes += 3
+        eligible += 3 if min(n, R) >= 192 and R >= n else 0
         modes_rf += sum(x == 0 for x in info["path"])
         certified += res.report["bound"] <= eps * res.report["a_norm"] * (1 + 1e-9)
         del p, om
@@ -234,7 +235,7 @@ def bench_learned(args):
     plain.close()
     out = dict(workload=("%d fresh rank-proposal problems (n in {128..2048}, R log-uniform [64, 8192], "
                          "eps in {1e-6..1e-3}, newton/smooth families)" % len(shapes)),
-               range_finder_modes=modes_rf, modes=modes, within_bound=certified,
+               range_finder_modes=modes_rf, modes=modes, eligible_modes=eligible, within_bound=certified,
                s_learned=round(t_l, 3), s_plain=round(t_p, 3), speedup=round(t_p / t_l, 3),
                by_family={k: dict(s_learned=round(v[0], 3), s_plain=round(v[1], 3), speedup=round(v[1] / v[0], 3))
                           for k, v in fam_t.items()})
@@ -256,7 +257,7 @@ def main():
     ap.add_argument("--batch-precision", default="fp32")
     ap.add_argument("--no-batch-fp64-baseline", dest="batch_fp64_baseline", action="store_false")
     ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--learned-count", type=int, default=32)
+    ap.add_argument("--learned-count", type=int, default=64)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="copy this many MiB once (a plain copy kernel of known size for counter calibration)")
     args = ap.parse_args()

@@ -251,7 +251,8 @@ rhosvd_status rhosvd_net_train_step(rhosvd_handle h, int32_t count, const float*
  *   directly); r_l = min{r : t_r <= tau}; Z_l = Q times the top r_l eigenvectors.
  *   Theorem 2.3's bound holds for any orthonormal Z with these tails.  A mode
  *   whose residual alone exceeds tau (no r <= p certifies) falls back to the
- *   Gram path, as does every mode where 3p >= m, and every mode when R < n.
+ *   Gram path, as does every mode where 3p >= m (always when m < 192: the
+ *   network is then not consulted), and every mode when R < n.
  *   Ranks, Z, beta and the report come out as for rhosvd_reduce (rhosvd_get);
  *   for a range-finder mode the spectrum holds the p Ritz values.
  *   info (HOST, nullable): per mode the proposed rank, the width used (0 on the

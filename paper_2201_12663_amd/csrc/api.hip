@@ -895,10 +895,11 @@ rhosvd_status rhosvd_reduce_learned(rhosvd_handle h, int64_t n, int64_t R, const
     if (!h->net_set) return fail(h, RHOSVD_ERR_STATE, "no network parameters on this handle");
     rhosvd_learned_info li;
     memset(&li, 0, sizeof(li));
-    if (R < n) {
-        // the range finder is built for the n-side Gram path: the full method runs
+    if (R < n || std::min(n, R) < 192) {
+        // the range finder is built for the n-side Gram path, and below m = 192 no
+        // width (a multiple of 64) satisfies 3p < m: the full method runs
         rhosvd_status s = rhosvd_reduce(h, n, R, U1, U2, U3, xi, eps, ranks);
-        for (int l = 0; l < 3; ++l) li.fallback[l] = 3;
+        for (int l = 0; l < 3; ++l) li.fallback[l] = R < n ? 3 : 1;
         if (info) *info = li;
         return s;
     }
