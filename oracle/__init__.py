@@ -147,6 +147,21 @@ def anorm_gram(Ut: list, xip: np.ndarray) -> float:
     return math.sqrt(max(val, 0.0))
 
 
+def anorm_hadamard(factors) -> float:
+    """|A|_F of the pointwise (Hadamard) product A = B o C of two canonical
+    tensors (Section 4.3, Lemma 4.3), by definition: B and C are formed slab by slab on the
+    grid, B[:, :, k] = U_a0 diag(x_a * U_a2[k, :]) U_a1^T, and the squares of
+    B o C summed.  factors = ((U_a, x_a), (U_b, x_b)) with U_* three n x R_* arrays."""
+    (Ua, xa), (Ub, xb) = factors
+    n = Ua[0].shape[0]
+    s = 0.0
+    for k in range(n):
+        Bk = (Ua[0] * (xa * Ua[2][k])) @ Ua[1].T
+        Ck = (Ub[0] * (xb * Ub[2][k])) @ Ub[1].T
+        s += float(np.sum((Bk * Ck) ** 2))
+    return float(np.sqrt(s))
+
+
 def anorm(Ut: list, xip: np.ndarray, brute_max_n: int = 64) -> float:
     n = Ut[0].shape[0]
     if n <= brute_max_n:

@@ -141,7 +141,8 @@ def hadamard_product(seed: int = 0, n: int = 512, R_each: int = 300, b: float = 
         P = (Ua[l][:, :, None] * Ub[l][:, None, :]).reshape(n, R_each * R_each)
         U.append(np.asfortranarray(P))
     xi = (xa[:, None] * xb[None, :]).reshape(-1)
-    return CanonicalInput(U, xi, eps, name=f"hadamard-n{n}-R{R_each * R_each}")
+    return CanonicalInput(U, xi, eps, name=f"hadamard-n{n}-R{R_each * R_each}",
+                          meta=dict(factors=((Ua, xa), (Ub, xb))))
 
 
 def batch_shapes(seed: int = 0, count: int = 256):
