@@ -162,6 +162,18 @@ def anorm_hadamard(factors) -> float:
     return float(np.sqrt(s))
 
 
+def hadamard_full(factors) -> np.ndarray:
+    """The pointwise product A = B o C of two canonical tensors materialized on
+    the n^3 grid (Section 4.3): slab k is B[:, :, k] * C[:, :, k], each slab of
+    a canonical tensor formed as U_0 diag(x * U_2[k, :]) U_1^T."""
+    (Ua, xa), (Ub, xb) = factors
+    n = Ua[0].shape[0]
+    A = np.empty((n, n, n), order="F")
+    for k in range(n):
+        A[:, :, k] = ((Ua[0] * (xa * Ua[2][k])) @ Ua[1].T) * ((Ub[0] * (xb * Ub[2][k])) @ Ub[1].T)
+    return A
+
+
 def anorm(Ut: list, xip: np.ndarray, brute_max_n: int = 64) -> float:
     n = Ut[0].shape[0]
     if n <= brute_max_n:
@@ -246,6 +258,12 @@ def reconstruct(beta: np.ndarray, Z: list) -> np.ndarray:
 # ---------------------------------------------------------------------------
 def error_brute(Ut: list, xip: np.ndarray, beta: np.ndarray, Z: list) -> float:
     return float(np.linalg.norm((full_tensor(Ut, xip) - reconstruct(beta, Z)).ravel()))
+
+
+def error_dense(A: np.ndarray, beta: np.ndarray, Z: list) -> float:
+    """|A - beta x_1 Z1 x_2 Z2 x_3 Z3|_F against a materialized A (any n the
+    memory allows; A - A_r formed entry by entry)."""
+    return float(np.linalg.norm((A - reconstruct(beta, Z)).ravel()))
 
 
 def error_gram(Ut: list, xip: np.ndarray, Z: list) -> float:

@@ -50,6 +50,25 @@ def test_anorm_gram_matches_brute(orc):
     assert abs(orc.anorm_gram(Ut, xip) - a) <= 1e-12 * a
 
 
+def test_hadamard_product_helpers_match_the_canonical_product(orc):
+    """A = B o C formed slab by slab equals, entry by entry, the canonical tensor
+    of R_a * R_b product terms built by the generator (brute force); its norm and
+    a truncated reduction's dense error agree with the Gram-identity forms."""
+    from paper_2201_12663_amd import inputs
+    ci = inputs.hadamard_product(5, n=14, R_each=5, eps=1e-3)
+    Ut, xip, _, _ = orc.normalize(ci.U, ci.xi)
+    ref = orc.full_tensor(Ut, xip)
+    A = orc.hadamard_full(ci.meta["factors"])
+    assert np.max(np.abs(A - ref)) <= 1e-13 * np.max(np.abs(ref))
+    a = float(np.linalg.norm(ref.ravel()))
+    assert abs(orc.anorm_hadamard(ci.meta["factors"]) - a) <= 1e-12 * a
+    res = orc.rhosvd(ci.U, ci.xi, ci.eps)
+    assert min(res.ranks) < 14
+    e = orc.error_dense(A, res.beta, res.Z)
+    assert abs(e - orc.error_gram(Ut, xip, res.Z)) <= 1e-6 * e + 1e-12 * a
+    assert e <= res.bound <= ci.eps * a * (1 + 1e-12)
+
+
 # ----------------------------------------------------------------------------
 # planted mistakes: each must make at least one pin fail
 # ----------------------------------------------------------------------------
