@@ -35,10 +35,19 @@ __device__ __forceinline__ void colnorm_term(int64_t n, int64_t R, int64_t n_pad
         mx = wave_max(mx);
         double acc = 0.0;
         if (mx > 0.0 && isfinite(mx)) {
-            double inv = 1.0 / mx;
-            for (int64_t i = lane; i < n; i += 64) {
-                double v = col[i] * inv;
-                acc += v * v;
+            // 1/mx overflows for a subnormal mx (and loses bits for a huge one):
+            // outside [2^-1000, 2^1000] divide instead (mx is uniform across the wave)
+            if (mx >= 0x1p-1000 && mx <= 0x1p1000) {
+                const double inv = 1.0 / mx;
+                for (int64_t i = lane; i < n; i += 64) {
+                    const double v = col[i] * inv;
+                    acc += v * v;
+                }
+            } else {
+                for (int64_t i = lane; i < n; i += 64) {
+                    const double v = col[i] / mx;
+                    acc += v * v;
+                }
             }
         }
         acc = wave_sum(acc);

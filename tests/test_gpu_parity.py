@@ -120,6 +120,31 @@ def test_dropped_terms_and_all_dropped(orc):
     assert g3["ranks"] == (0, 0, 0)
 
 
+def test_tiny_and_huge_columns_are_normalized_not_dropped(orc):
+    """Columns whose largest entry is subnormal (1/max overflows) or above 2^1000
+    are nonzero: their terms stay in the normalized side matrices, as in the
+    oracle (their unit columns shape the Gram even where xi' rounds to almost
+    nothing).  The subnormal columns keep 40+ bits, so both sides' normalized
+    columns agree to ~1e-13."""
+    ci = inputs.small_gaussian_sum(6, n=40, R=80, eps=1e-5)
+    U = [u.copy() for u in ci.U]
+    xi = ci.xi.copy()
+    U[0][:, 3] *= 1e-310
+    U[1][:, 7] *= 3e-309
+    U[2][:, 11] *= 1e305
+    xi[11] *= 1e-305
+    ci2 = inputs.CanonicalInput(U, xi, ci.eps)
+    o = orc.rhosvd(U, xi, ci.eps)
+    g = gc.run_gpu(ci2, "fp64")
+    assert g["report"]["dropped"] == 0
+    tiny = [3, 7]
+    for k in tiny + [11]:
+        assert g["xip"][k] != 0.0
+        assert abs(g["xip"][k] - o.xip[k]) <= 1e-12 * abs(o.xip[k]) + 8 * 2.0 ** -1074
+    g["xip"][tiny] = o.xip[tiny]        # subnormal: compared above to their own precision
+    gc.compare_fp64(g, o, ci2)
+
+
 def test_nonfinite_input_is_rejected():
     import torch
     from paper_2201_12663_amd import rhosvd
