@@ -136,6 +136,16 @@ def full_tensor(Ut: list, xip: np.ndarray) -> np.ndarray:
     return A
 
 
+def full_tensor_slabs(Ut: list, xip: np.ndarray) -> np.ndarray:
+    """The same A, one k-slab at a time: A[:, :, k] = U~1 diag(xi' * U~3[k, :]) U~2^T
+    (Fortran order; any n the memory allows)."""
+    n = Ut[0].shape[0]
+    A = np.empty((n, n, n), order="F")
+    for k in range(n):
+        A[:, :, k] = (Ut[0] * (xip * Ut[2][k])) @ Ut[1].T
+    return A
+
+
 def anorm_gram(Ut: list, xip: np.ndarray) -> float:
     """|A|_F^2 = sum_{nu,mu} xi'_nu xi'_mu prod_l <u~_nu^(l), u~_mu^(l)>
     = xi'^T (G1 o G2 o G3) xi', with G_l = U~^(l)T U~^(l) (R x R): the inner
@@ -249,8 +259,13 @@ def core(V: list, xip: np.ndarray) -> np.ndarray:
 
 
 def reconstruct(beta: np.ndarray, Z: list) -> np.ndarray:
-    """A_r = beta x_1 Z1 x_2 Z2 x_3 Z3 (materialized; small n only)."""
-    return np.einsum("abc,ia,jb,kc->ijk", beta, Z[0], Z[1], Z[2], optimize=True)
+    """A_r = beta x_1 Z1 x_2 Z2 x_3 Z3 (materialized, n^3 entries), one mode
+    product at a time: c with Z3, then a with Z1, then b with Z2.  Returned as
+    an (i, j, k) view of a (k, j, i) array (Fortran order, like hadamard_full)."""
+    T = np.tensordot(Z[2], beta, axes=([1], [2]))          # (k, a, b)
+    T = np.tensordot(T, Z[1], axes=([2], [1]))             # (k, a, j)
+    T = np.tensordot(T, Z[0], axes=([1], [1]))             # (k, j, i)
+    return T.transpose(2, 1, 0)
 
 
 # ---------------------------------------------------------------------------
@@ -263,7 +278,7 @@ def error_brute(Ut: list, xip: np.ndarray, beta: np.ndarray, Z: list) -> float:
 def error_dense(A: np.ndarray, beta: np.ndarray, Z: list) -> float:
     """|A - beta x_1 Z1 x_2 Z2 x_3 Z3|_F against a materialized A (any n the
     memory allows; A - A_r formed entry by entry)."""
-    return float(np.linalg.norm((A - reconstruct(beta, Z)).ravel()))
+    return float(np.linalg.norm((A - reconstruct(beta, Z)).ravel(order="K")))
 
 
 def error_gram(Ut: list, xip: np.ndarray, Z: list) -> float:

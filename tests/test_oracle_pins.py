@@ -60,6 +60,7 @@ def test_hadamard_product_helpers_match_the_canonical_product(orc):
     ref = orc.full_tensor(Ut, xip)
     A = orc.hadamard_full(ci.meta["factors"])
     assert np.max(np.abs(A - ref)) <= 1e-13 * np.max(np.abs(ref))
+    assert np.max(np.abs(orc.full_tensor_slabs(Ut, xip) - ref)) <= 1e-13 * np.max(np.abs(ref))
     a = float(np.linalg.norm(ref.ravel()))
     assert abs(orc.anorm_hadamard(ci.meta["factors"]) - a) <= 1e-12 * a
     res = orc.rhosvd(ci.U, ci.xi, ci.eps)
