@@ -67,7 +67,9 @@ typedef struct {
     int32_t max_eig_sweeps;  /* unused (the eigensolver is not iterative); any value */
     int32_t profile;         /* nonzero: time each phase with HIP events (see rhosvd_phase_ms) */
     int32_t beta_fp32;       /* nonzero: beta is written as float (r1*r2*r3 floats) instead of
-                                double, halving its size; meant for the FP32 and BF16x3 cores */
+                                double, halving its size; meant for the FP32 and BF16x3 cores.
+                                When R (padded to 64) exceeds 8192 these cores add their
+                                partial sums over each 8192 terms into beta, in float here */
     int32_t refine_tails;    /* nonzero (rhosvd_reduce): after the Gram-route cut r, with
                                 Z_p the leading p = min(m, r + r/8 + 16) eigenvectors and
                                 V_p = Z_p^T U~, the cut is taken again on the tails

@@ -74,6 +74,7 @@ struct BatchPlan {
     std::vector<rhosvd_problem> key;
     int prec = 0;
     int prec_key = 0;
+    int core_key = 0;                    // prec_key, + 32 when some R_pad exceeds core_flush_span()
     std::vector<BProb> hp;
     // device memory
     char* ws = nullptr;
@@ -240,7 +241,7 @@ hipError_t enqueue_batch(const BatchPlan& B, hipStream_t st, bool coop) {
     }
     if ((e = launch_batched_dense(BK_SIGN, P, B.pre[4], np, B.nblk[4], 0, st)) != hipSuccess) return e;
     if ((e = launch_batched_dense(BK_PROJECT, P, B.pre[3], np, B.nblk[3], B.prec != 0, st)) != hipSuccess) return e;
-    if ((e = launch_core_b(P, np, B.prec_key, B.core_work, B.core_grid, st)) != hipSuccess) return e;
+    if ((e = launch_core_b(P, np, B.core_key, B.core_work, B.core_grid, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_finish_b, dim3((unsigned)np, 3, 8), dim3(256), 0, st, P);
     return hipGetLastError();
 }
@@ -357,7 +358,10 @@ BatchPlan* batch_plan_create(const rhosvd_problem* probs, int count, int prec, s
             return nullptr;
         }
     }
-    B->core_grid = core_b_max_grid(B->prec_key);
+    int64_t rmax = 0;
+    for (const BProb& q : B->hp) rmax = std::max<int64_t>(rmax, q.R_pad);
+    B->core_key = B->prec_key | (rmax > core_flush_span() ? 32 : 0);
+    B->core_grid = core_b_max_grid(B->core_key);
     // record the pass into a graph; on any failure the pass runs eagerly
     const char* env = getenv("RHOSVD_BATCH_GRAPH");
     if (!(env && env[0] == '0') && hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking) == hipSuccess) {

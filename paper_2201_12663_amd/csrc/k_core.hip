@@ -13,7 +13,8 @@
 //
 // Variants: FP64 (v_mfma_f64_16x16x4, TM=64), FP32 (v_mfma_f32_16x16x4, TM=64)
 // and BF16x3 (v_mfma_f32_16x16x32_bf16, TM=128): a = a_hi + a_lo, b = b_hi + b_lo
-// in bf16, a*b ~ a_hi b_hi + a_hi b_lo + a_lo b_hi, FP32 accumulation.
+// in bf16, a*b ~ a_hi b_hi + a_hi b_lo + a_lo b_hi, FP32 accumulation restarted
+// every KFLUSH values of nu (partial sums added in beta's precision).
 #include <hip/hip_runtime.h>
 #include "common.hpp"
 #include "kernels.hpp"
@@ -31,6 +32,45 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t per) {
 template <typename O, typename T>
 __device__ __forceinline__ void store_beta(O* __restrict__ beta, int r1, int r2, int r3, int j1, int j2, int j3, T v) {
     if (j1 < r1 && j2 < r2 && j3 < r3) beta[(int64_t)j1 + (int64_t)r1 * ((int64_t)j2 + (int64_t)r2 * j3)] = (O)v;
+}
+
+// The FP32-accumulating cores hand their accumulators to beta every KFLUSH
+// values of nu: the first hand-over stores, later ones add in FP64 (FP32 for a
+// float beta) and the accumulators restart from zero.  A workgroup owns its
+// tile, and every lane reads back only what it wrote itself, so no
+// synchronization is needed.  Rounding of a sequential FP32 sum grows with the
+// running total; restarting every KFLUSH terms bounds that growth (R = 90000:
+// about 10x smaller error).  The hand-over variants run only when R_pad > KFLUSH;
+// shorter contractions keep the single final store.
+constexpr int64_t KFLUSH = 8192;
+
+// NF x 4 accumulator fragments of a 16 x 16 FP32 MFMA (rows 4 (lane / 16) + i,
+// column lane % 16) into beta: store (first) or add, then reset to zero.  One
+// base pointer per j3 column and constant offsets 16 f + i keep the addressing
+// out of the registers.
+template <int NF, typename O>
+__device__ __forceinline__ void hand_over(O* __restrict__ beta, int r1, int r2, int r3, int m0, int b2, int b3,
+                                          int lane, int w, f4_t (&acc)[NF][4], bool first) {
+    const int rb = m0 + 4 * (lane >> 4);
+    const int rows = r1 - rb;                       // rows rb + o exist for o < rows
+    const int j2 = b2 + c_col(lane);
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const int j3 = b3 + 4 * w + g;
+        if (j2 < r2 && j3 < r3) {
+            O* p = beta + rb + (int64_t)r1 * ((int64_t)j2 + (int64_t)r2 * j3);
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (16 * f + i < rows) {
+                        O& x = p[16 * f + i];
+                        x = first ? (O)acc[f][g][i] : (O)((double)x + (double)acc[f][g][i]);
+                    }
+        }
+#pragma unroll
+        for (int f = 0; f < NF; ++f) acc[f][g] = f4_t{0.f, 0.f, 0.f, 0.f};
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -51,7 +91,7 @@ struct MF<float> {
     static __device__ __forceinline__ int row(int lane, int i) { return c_row32(lane, i); }
 };
 
-template <typename T, typename O>
+template <typename T, typename O, bool FLUSH>
 __device__ __forceinline__ void core_tile_std(int r1, int r2, int r3, int ld1, int ld2, int ld3, int64_t Kp,
                               const T* __restrict__ V1, const T* __restrict__ V2, const T* __restrict__ V3,
                               const double* __restrict__ xip, O* __restrict__ beta, int N2T, int N3T,
@@ -93,6 +133,10 @@ __device__ __forceinline__ void core_tile_std(int r1, int r2, int r3, int ld1, i
 #pragma unroll
         for (int g = 0; g < 4; ++g) acc[f][g] = acc_t{0, 0, 0, 0};
 
+    constexpr bool f32 = sizeof(T) == 4 && FLUSH;
+    constexpr int64_t FL = KFLUSH / KC;   // chunks between hand-overs (FP32 only)
+    bool first = true;
+
     const int64_t nchunk = Kp / KC;
     gload(0);
     lstore(0);
@@ -114,8 +158,18 @@ __device__ __forceinline__ void core_tile_std(int r1, int r2, int r3, int ld1, i
 #pragma unroll
                 for (int g = 0; g < 4; ++g) acc[f][g] = MF<T>::mma(a[f], b[g], acc[f][g]);
         }
+        if constexpr (f32) {
+            if ((c + 1) % FL == 0 && c + 1 < nchunk) {
+                hand_over<4, O>(beta, r1, r2, r3, m0, b2, b3, lane, w, acc, first);
+                first = false;
+            }
+        }
         if (c + 1 < nchunk) lstore(buf ^ 1);
         __syncthreads();
+    }
+    if constexpr (f32) {
+        hand_over<4, O>(beta, r1, r2, r3, m0, b2, b3, lane, w, acc, first);
+        return;
     }
 #pragma unroll
     for (int f = 0; f < 4; ++f)
@@ -127,7 +181,7 @@ __device__ __forceinline__ void core_tile_std(int r1, int r2, int r3, int ld1, i
                            acc[f][g][i]);
 }
 
-template <typename T, typename O>
+template <typename T, typename O, bool FLUSH>
 __global__ __launch_bounds__(256) void k_core_std(int r1, int r2, int r3, int ld1, int ld2, int ld3,
                                                   int64_t Kp, const T* __restrict__ V1,
                                                   const T* __restrict__ V2, const T* __restrict__ V3,
@@ -135,7 +189,7 @@ __global__ __launch_bounds__(256) void k_core_std(int r1, int r2, int r3, int ld
                                                   int MT, int N2T, int N3T, int64_t per) {
     const int64_t tile = xcd_tile(blockIdx.x, per);
     if (tile >= (int64_t)MT * N2T * N3T) return;
-    core_tile_std<T, O>(r1, r2, r3, ld1, ld2, ld3, Kp, V1, V2, V3, xip, beta, N2T, N3T, tile);
+    core_tile_std<T, O, FLUSH>(r1, r2, r3, ld1, ld2, ld3, Kp, V1, V2, V3, xip, beta, N2T, N3T, tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -148,7 +202,7 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
     lo = (__bf16)(x - (float)hi);
 }
 
-template <typename O>
+template <typename O, bool FLUSH>
 __device__ __forceinline__ void core_tile_bf16x3(int r1, int r2, int r3, int ld1, int ld2, int ld3, int64_t Kp,
                                  const float* __restrict__ V1, const float* __restrict__ V2,
                                  const float* __restrict__ V3, const double* __restrict__ xip,
@@ -200,6 +254,9 @@ __device__ __forceinline__ void core_tile_bf16x3(int r1, int r2, int r3, int ld1
 #pragma unroll
         for (int g = 0; g < 4; ++g) acc[f][g] = f4_t{0.f, 0.f, 0.f, 0.f};
 
+    constexpr int64_t FL = KFLUSH / BKC;   // chunks between hand-overs
+    bool first = true;
+
     const int64_t nchunk = Kp / BKC;
     gload(0);
     lstore(0);
@@ -235,8 +292,18 @@ __device__ __forceinline__ void core_tile_bf16x3(int r1, int r2, int r3, int ld1
                 acc[f][g] = mfma_bf16(al, bh[g], acc[f][g]);
             }
         }
+        if constexpr (FLUSH) {
+            if ((c + 1) % FL == 0 && c + 1 < nchunk) {
+                hand_over<8, O>(beta, r1, r2, r3, m0, b2, b3, lane, w, acc, first);
+                first = false;
+            }
+        }
         if (c + 1 < nchunk) lstore(buf ^ 1);
         __syncthreads();
+    }
+    if constexpr (FLUSH) {
+        hand_over<8, O>(beta, r1, r2, r3, m0, b2, b3, lane, w, acc, first);
+        return;
     }
 #pragma unroll
     for (int f = 0; f < 8; ++f)
@@ -248,7 +315,7 @@ __device__ __forceinline__ void core_tile_bf16x3(int r1, int r2, int r3, int ld1
                            acc[f][g][i]);
 }
 
-template <typename O>
+template <typename O, bool FLUSH>
 __global__ __launch_bounds__(256) void k_core_bf16x3(int r1, int r2, int r3, int ld1, int ld2, int ld3,
                                                      int64_t Kp, const float* __restrict__ V1,
                                                      const float* __restrict__ V2, const float* __restrict__ V3,
@@ -256,7 +323,7 @@ __global__ __launch_bounds__(256) void k_core_bf16x3(int r1, int r2, int r3, int
                                                      int MT, int N2T, int N3T, int64_t per) {
     const int64_t tile = xcd_tile(blockIdx.x, per);
     if (tile >= (int64_t)MT * N2T * N3T) return;
-    core_tile_bf16x3<O>(r1, r2, r3, ld1, ld2, ld3, Kp, V1, V2, V3, xip, beta, N2T, N3T, tile);
+    core_tile_bf16x3<O, FLUSH>(r1, r2, r3, ld1, ld2, ld3, Kp, V1, V2, V3, xip, beta, N2T, N3T, tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -280,7 +347,7 @@ __global__ void k_core_plan_b(const BProb* __restrict__ P, int np, int tm, int64
     work[0] = 0;
 }
 
-template <int PREC, typename O>
+template <int PREC, typename O, bool FLUSH>
 __global__ __launch_bounds__(256) void k_core_persist_b(const BProb* __restrict__ P, int np,
                                                         int64_t* __restrict__ work) {
     __shared__ int64_t s_tile;
@@ -304,32 +371,32 @@ __global__ __launch_bounds__(256) void k_core_persist_b(const BProb* __restrict_
         const int N2T = (int)ceil_div(r2, TN2), N3T = (int)ceil_div(r3, TN3);
         const int64_t local = tile - pre[lo];
         if (PREC == 0)
-            core_tile_std<double, O>(r1, r2, r3, q.rcap_pad, q.rcap_pad, q.rcap_pad, q.R_pad, (const double*)q.V[0],
+            core_tile_std<double, O, false>(r1, r2, r3, q.rcap_pad, q.rcap_pad, q.rcap_pad, q.R_pad, (const double*)q.V[0],
                                   (const double*)q.V[1], (const double*)q.V[2], q.xip, (O*)q.beta, N2T, N3T, local);
         else if (PREC == 1)
-            core_tile_std<float, O>(r1, r2, r3, q.rcap_pad, q.rcap_pad, q.rcap_pad, q.R_pad, (const float*)q.V[0],
+            core_tile_std<float, O, FLUSH>(r1, r2, r3, q.rcap_pad, q.rcap_pad, q.rcap_pad, q.R_pad, (const float*)q.V[0],
                                  (const float*)q.V[1], (const float*)q.V[2], q.xip, (O*)q.beta, N2T, N3T, local);
         else
-            core_tile_bf16x3<O>(r1, r2, r3, q.rcap_pad, q.rcap_pad, q.rcap_pad, q.R_pad, (const float*)q.V[0],
+            core_tile_bf16x3<O, FLUSH>(r1, r2, r3, q.rcap_pad, q.rcap_pad, q.rcap_pad, q.R_pad, (const float*)q.V[0],
                              (const float*)q.V[1], (const float*)q.V[2], q.xip, (O*)q.beta, N2T, N3T, local);
     }
 }
 
 }  // namespace
 
-template <typename O>
+template <typename O, bool FLUSH>
 static void launch_core_t(const CoreArgs& a, dim3 grid, int MT, int N2T, int N3T, int64_t per, hipStream_t st) {
     O* beta = (O*)a.beta;
     if (a.prec == 0) {
-        hipLaunchKernelGGL((k_core_std<double, O>), grid, dim3(256), 0, st, a.r[0], a.r[1], a.r[2], a.r_pad[0],
+        hipLaunchKernelGGL((k_core_std<double, O, false>), grid, dim3(256), 0, st, a.r[0], a.r[1], a.r[2], a.r_pad[0],
                            a.r_pad[1], a.r_pad[2], a.R_pad, (const double*)a.V[0], (const double*)a.V[1],
                            (const double*)a.V[2], a.xip, beta, MT, N2T, N3T, per);
     } else if (a.prec == 1) {
-        hipLaunchKernelGGL((k_core_std<float, O>), grid, dim3(256), 0, st, a.r[0], a.r[1], a.r[2], a.r_pad[0],
+        hipLaunchKernelGGL((k_core_std<float, O, FLUSH>), grid, dim3(256), 0, st, a.r[0], a.r[1], a.r[2], a.r_pad[0],
                            a.r_pad[1], a.r_pad[2], a.R_pad, (const float*)a.V[0], (const float*)a.V[1],
                            (const float*)a.V[2], a.xip, beta, MT, N2T, N3T, per);
     } else {
-        hipLaunchKernelGGL((k_core_bf16x3<O>), grid, dim3(256), 0, st, a.r[0], a.r[1], a.r[2], a.r_pad[0],
+        hipLaunchKernelGGL((k_core_bf16x3<O, FLUSH>), grid, dim3(256), 0, st, a.r[0], a.r[1], a.r[2], a.r_pad[0],
                            a.r_pad[1], a.r_pad[2], a.R_pad, (const float*)a.V[0], (const float*)a.V[1],
                            (const float*)a.V[2], a.xip, beta, MT, N2T, N3T, per);
     }
@@ -346,39 +413,60 @@ hipError_t launch_core(const CoreArgs& a, hipStream_t st) {
     const int64_t ntile = (int64_t)MT * N2T * N3T;
     const int64_t per = ceil_div(ntile, NXCD);
     dim3 grid((unsigned)(per * NXCD));
-    if (a.beta_f32) launch_core_t<float>(a, grid, MT, N2T, N3T, per, st);
-    else launch_core_t<double>(a, grid, MT, N2T, N3T, per, st);
+    const bool flush = a.R_pad > KFLUSH;   // the hand-over variants only where they act
+    if (a.beta_f32) {
+        if (flush) launch_core_t<float, true>(a, grid, MT, N2T, N3T, per, st);
+        else launch_core_t<float, false>(a, grid, MT, N2T, N3T, per, st);
+    } else {
+        if (flush) launch_core_t<double, true>(a, grid, MT, N2T, N3T, per, st);
+        else launch_core_t<double, false>(a, grid, MT, N2T, N3T, per, st);
+    }
     return hipGetLastError();
 }
 
-template <typename O>
+template <typename O, bool FLUSH>
 static void launch_persist_t(const BProb* P, int np, int prec, int64_t* work, int grid, hipStream_t st) {
-    if (prec == 0) hipLaunchKernelGGL((k_core_persist_b<0, O>), dim3((unsigned)grid), dim3(256), 0, st, P, np, work);
-    else if (prec == 1) hipLaunchKernelGGL((k_core_persist_b<1, O>), dim3((unsigned)grid), dim3(256), 0, st, P, np, work);
-    else hipLaunchKernelGGL((k_core_persist_b<2, O>), dim3((unsigned)grid), dim3(256), 0, st, P, np, work);
+    const dim3 g((unsigned)grid), b(256);
+    if (prec == 0) hipLaunchKernelGGL((k_core_persist_b<0, O, false>), g, b, 0, st, P, np, work);
+    else if (prec == 1) hipLaunchKernelGGL((k_core_persist_b<1, O, FLUSH>), g, b, 0, st, P, np, work);
+    else hipLaunchKernelGGL((k_core_persist_b<2, O, FLUSH>), g, b, 0, st, P, np, work);
 }
 
+// prec: 0 FP64, 1 FP32, 2 BF16x3; +16 float beta; +32 some problem has R_pad > KFLUSH
 hipError_t launch_core_b(const BProb* P, int np, int prec, int64_t* work, int grid, hipStream_t st) {
     if (np < 1) return hipSuccess;
     hipLaunchKernelGGL(k_core_plan_b, dim3(1), dim3(64), 0, st, P, np, (prec & 3) == 2 ? BTM : 64, work);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (prec & 16) launch_persist_t<float>(P, np, prec & 3, work, grid, st);
-    else launch_persist_t<double>(P, np, prec & 3, work, grid, st);
+    const bool f32 = (prec & 16) != 0, flush = (prec & 32) != 0;
+    if (f32) {
+        if (flush) launch_persist_t<float, true>(P, np, prec & 3, work, grid, st);
+        else launch_persist_t<float, false>(P, np, prec & 3, work, grid, st);
+    } else {
+        if (flush) launch_persist_t<double, true>(P, np, prec & 3, work, grid, st);
+        else launch_persist_t<double, false>(P, np, prec & 3, work, grid, st);
+    }
     return hipGetLastError();
+}
+
+int64_t core_flush_span() { return KFLUSH; }
+
+template <typename O, bool FLUSH>
+static const void* persist_fn(int prec) {
+    switch (prec) {
+        case 0: return (const void*)k_core_persist_b<0, O, false>;
+        case 1: return (const void*)k_core_persist_b<1, O, FLUSH>;
+        default: return (const void*)k_core_persist_b<2, O, FLUSH>;
+    }
 }
 
 int core_b_max_grid(int prec) {
     int dev = 0, ncu = 0, occ = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 256;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 256;
-    const bool f32 = (prec & 16) != 0;
-    const void* f;
-    switch (prec & 3) {
-        case 0: f = f32 ? (const void*)k_core_persist_b<0, float> : (const void*)k_core_persist_b<0, double>; break;
-        case 1: f = f32 ? (const void*)k_core_persist_b<1, float> : (const void*)k_core_persist_b<1, double>; break;
-        default: f = f32 ? (const void*)k_core_persist_b<2, float> : (const void*)k_core_persist_b<2, double>; break;
-    }
+    const bool f32 = (prec & 16) != 0, flush = (prec & 32) != 0;
+    const void* f = f32 ? (flush ? persist_fn<float, true>(prec & 3) : persist_fn<float, false>(prec & 3))
+                        : (flush ? persist_fn<double, true>(prec & 3) : persist_fn<double, false>(prec & 3));
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, 256, 0) != hipSuccess || occ < 1) occ = 1;
     return ncu * occ;
 }

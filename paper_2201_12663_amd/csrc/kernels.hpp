@@ -191,10 +191,13 @@ hipError_t launch_truncate_b(const BProb* P, int np, hipStream_t st);
 // Khatri-Rao cores of every problem with status 0 and a beta output, as one
 // persistent launch: a device-side plan counts each problem's tiles from its
 // ranks, workgroups take tiles from a shared counter.  work: np + 4 int64.
-// prec: core precision (0..2), plus 16 when beta is written as float.
+// prec: core precision (0..2), plus 16 when beta is written as float, plus 32
+// when some problem's R_pad exceeds core_flush_span() (the FP32-accumulating
+// cores then hand their partial sums to beta periodically).
 hipError_t launch_core_b(const BProb* P, int np, int prec, int64_t* work, int grid, hipStream_t st);
 // workgroups of the persistent core that fit on the device at once (prec as above)
 int core_b_max_grid(int prec);
+int64_t core_flush_span();
 // copy Z to the caller's buffers and write the result words (ranks, status)
 hipError_t launch_finish_b(const BProb* P, int np, hipStream_t st);
 

@@ -207,6 +207,51 @@ def test_batched_mixed_precision(orc, batch_inputs, prec):
     rm.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_long_contraction_hands_over_partial_sums(orc, batch_inputs, prec):
+    """R = 20000 (R_pad above 8192): the FP32-accumulating cores hand their
+    partial sums to beta every 8192 terms, on the single path and in a batch
+    that also holds a short problem (whose core then runs in the same kernel
+    variant with a single final store).  Every beta is within the core's
+    precision of the exact core of its own Z; with FP32 cores the total error is
+    within (eps + 1e-6) |A| against the materialized tensor."""
+    import torch
+    from paper_2201_12663_amd import rhosvd
+    long_ci = inputs.small_gaussian_sum(seed=21, n=96, R=20000, eps=1e-6)
+    cis = [long_ci, batch_inputs[2]]
+    probs = [to_dev(ci) for ci in cis]
+    red = rhosvd.Reducer(precision=prec)
+    out, _, _, _ = red.reduce_batched(probs)
+    single = rhosvd.Reducer(precision=prec)
+    # |beta - beta_exact| against |A|: FP32 accumulation of up to 8192 terms
+    # (2048 sequential MFMA steps) per hand-over, u32 sqrt(2048) ~ 3e-6 of the
+    # running sums for positive terms; BF16x3 adds its split error (~2^-17)
+    tol = 3e-6 if prec == "fp32" else 1e-5
+    for k, (ci, p, o) in enumerate(zip(cis, probs, out)):
+        assert o["status"] == 0
+        r = single.reduce(*p)
+        res = single.get(sigma=False)
+        torch.cuda.synchronize()
+        assert tuple(r) == o["ranks"], ci.name
+        Ut, xip, _, _ = orc.normalize(ci.U, ci.xi)
+        A = orc.full_tensor_slabs(Ut, xip)
+        a_norm = float(np.linalg.norm(A.ravel(order="K")))
+        for Zt, bt, where in ((o["Z"], o["beta"], "batched"), (res.Z, res.beta, "single")):
+            Z = [z.cpu().numpy() for z in Zt]
+            beta = bt.cpu().numpy()
+            be = orc.core([orc.project(Z[l], Ut[l]) for l in range(3)], xip)
+            db = float(np.linalg.norm((beta - be).ravel()))
+            err = orc.error_dense(A, beta, Z)
+            print(f"{prec} {ci.name} {where}: ranks {o['ranks']} core error {db / a_norm:.3e} |A|, "
+                  f"total error {err / a_norm:.3e} |A|", flush=True)
+            assert db <= tol * a_norm, (ci.name, where, db / a_norm)
+            if prec == "fp32":
+                assert err <= (ci.eps + 1e-6) * a_norm
+        del A
+    red.close()
+    single.close()
+
+
 def test_batched_uneven_config_sample():
     """Problems of the uneven batch at their real sizes (n up to 2048, R up to
     8192, one R < n): ranks equal the single path's, Z is orthonormal, its
