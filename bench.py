@@ -191,6 +191,48 @@ def bench_batched(args):
     return result
 
 
+def bench_precision_study(args):
+    """FP64 vs FP32 vs BF16x3 cores (FP64 Gram, eigensolver and truncation) on the
+    Hadamard product of two 300-term Gaussian sums, n = 512, R = 90000, at
+    eps = 1e-4 and 1e-6: time per reduction, ranks, the core's distance from the
+    FP64 core, and the certified total (Theorem 2.3 bound and core error, which
+    are orthogonal)."""
+    import numpy as np
+    import torch
+    from paper_2201_12663_amd import inputs, rhosvd
+    log("precision study: Hadamard product n=512, R=90000")
+    ci = inputs.hadamard_product(0)
+    U = [rhosvd.to_device(u) for u in ci.U]
+    xi = torch.from_numpy(np.ascontiguousarray(ci.xi)).cuda()
+    cases = []
+    for eps in (1e-4, 1e-6):
+        b64 = None
+        for prec in ("fp64", "fp32", "bf16x3"):
+            red = rhosvd.Reducer(precision=prec, profile=True)
+            ranks = red.reduce(U[0], U[1], U[2], xi, eps)
+            r1, r2, r3 = ranks
+            beta = torch.empty(r1 * r2 * r3, dtype=torch.float64, device="cuda")
+            ms, core_ms, avg = time_path(red, U, xi, eps, beta, args.precision_steps, 1)
+            rep = red.get(beta=False, Z=False, sigma=False).report
+            row = dict(eps=eps, precision=prec, ranks=list(ranks), ms=round(ms, 3), core_ms=round(core_ms, 3),
+                       core_tflops=round(2.0 * r1 * r2 * r3 * ci.R / (core_ms * 1e-3) / 1e12, 2),
+                       phase_ms={k: round(v, 3) for k, v in avg.items()},
+                       bound_rel=rep["bound"] / rep["a_norm"])
+            if prec == "fp64":
+                b64 = beta
+            elif b64 is not None and b64.numel() == beta.numel():
+                row["core_err_rel"] = float(torch.linalg.vector_norm(beta - b64).item()) / rep["a_norm"]
+                row["err_bound_rel"] = math.hypot(row["bound_rel"], row["core_err_rel"])
+                row["within_eps_plus_1e-6"] = row["err_bound_rel"] <= eps + 1e-6
+            log(f"  eps={eps} {prec}: {row}")
+            cases.append(row)
+            red.close()
+            del beta
+        del b64
+    return dict(workload="hadamard-n512-R90000 (pointwise product of two 300-term Gaussian sums)",
+                steps=args.precision_steps, cases=cases)
+
+
 def bench_learned(args):
     """Fresh problems of the rank-proposal workloads (evaluation seeds, disjoint
     from training): the learned path (trained network, range finder, certificate,
@@ -257,6 +299,8 @@ def main():
     ap.add_argument("--batch-precision", default="fp32")
     ap.add_argument("--no-batch-fp64-baseline", dest="batch_fp64_baseline", action="store_false")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-precision-study", action="store_true")
+    ap.add_argument("--precision-steps", type=int, default=2)
     ap.add_argument("--learned-count", type=int, default=64)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="copy this many MiB once (a plain copy kernel of known size for counter calibration)")
@@ -352,6 +396,8 @@ def main():
         line["batched"] = bench_batched(args)
     if not args.no_learned:
         line["learned"] = bench_learned(args)
+    if not args.no_precision_study:
+        line["precision_study"] = bench_precision_study(args)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample)")
         line["cpu_baseline"] = cpu_baseline(ci)

@@ -1,0 +1,141 @@
+"""Precision study on the rank-multiplying Hadamard product (Section 4.3): two
+300-term Gaussian sums multiplied pointwise on a 512^3 grid, R = 90000, at
+eps = 1e-4 and 1e-6, through the C-ABI.
+
+The FP64 path is compared with stored oracle values (tests/golden/
+hadamard512_seed0.json, written by make_golden.py): |A|, |xi'|, the side-matrix
+spectra, ranks where the cut's margin allows, sampled core entries, and the
+exact error of the GPU's own result against the product formed on the grid.
+The FP32 and BF16x3 cores (FP64 Gram, eigensolver and truncation) keep the
+FP64 ranks; the FP32 core keeps the total error within (eps + 1e-6) |A| at
+both eps, BF16x3 at eps = 1e-4 (at 1e-6 its split error, ~2e-6 |A|, is the
+floor).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2201_12663_amd import inputs
+import gpu_cases as gc
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLD = os.path.join(HERE, "golden", "hadamard512_seed0.json")
+EPS = (1e-4, 1e-6)
+
+
+class _State:
+    ci = None
+    dev = None
+    A = None
+    gold = None
+    runs = {}
+
+
+S = _State()
+
+
+def _flush(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def had(orc):
+    import torch
+    from paper_2201_12663_amd import rhosvd
+    if S.ci is None:
+        _flush("hadamard n=512 R=90000: generating input and the product on the grid")
+        S.gold = json.load(open(GOLD))
+        S.ci = inputs.hadamard_product(0)
+        S.dev = ([rhosvd.to_device(u) for u in S.ci.U], torch.from_numpy(S.ci.xi).cuda())
+        S.A = orc.hadamard_full(S.ci.meta["factors"])
+    yield S
+
+
+def run(prec, eps):
+    key = (prec, eps)
+    if key not in S.runs:
+        import torch
+        from paper_2201_12663_amd import rhosvd
+        _flush(f"hadamard reduce {prec} eps={eps}")
+        U, xi = S.dev
+        red = rhosvd.Reducer(precision=prec)
+        ranks = red.reduce(U[0], U[1], U[2], xi, eps)
+        res = red.get()
+        spec = [red.spectrum(l) for l in range(3)]
+        torch.cuda.synchronize()
+        S.runs[key] = dict(ranks=tuple(ranks), Z=[z.cpu().numpy() for z in res.Z],
+                           beta=res.beta.double().cpu().numpy(), report=res.report,
+                           spectra=[s.cpu().numpy() for s in spec])
+        red.close()
+    return S.runs[key]
+
+
+@pytest.mark.parametrize("eps", EPS)
+def test_hadamard_fp64_vs_oracle(orc, had, eps):
+    gold = had.gold
+    case = gold["cases"][EPS.index(eps)]
+    ci = had.ci
+    g = run("fp64", eps)
+    rep = g["report"]
+    assert abs(rep["a_norm"] - gold["a_norm"]) <= 1e-12 * gold["a_norm"]
+    assert abs(rep["xi_norm"] - gold["xi_norm"]) <= 1e-13 * gold["xi_norm"]
+    zero_col = np.any(np.stack([np.max(np.abs(u), axis=0) for u in ci.U]) == 0.0, axis=0)
+    assert rep["dropped"] == int(np.sum(zero_col | (ci.xi == 0.0)))
+    assert abs(rep["tau"] - case["tau"]) <= 1e-12 * case["tau"]
+    margins = []
+    for l in range(3):
+        so = np.array(gold["sigma"][l])
+        s1 = so[0]
+        d2 = np.abs(g["spectra"][l] ** 2 - so ** 2)
+        assert np.all(d2 <= gc.eig_tol(ci.n, ci.R) * s1 ** 2), (l, d2.max() / s1 ** 2)
+        tails = np.sqrt(np.concatenate([np.cumsum((so ** 2)[::-1])[::-1], [0.0]]))
+        ok = gc.cut_margin_ok(tails, case["ranks"][l], case["tau"], s1)
+        margins.append(ok)
+        if ok:
+            assert g["ranks"][l] == case["ranks"][l], (l, g["ranks"], case["ranks"])
+        Z = g["Z"][l]
+        assert np.max(np.abs(Z.T @ Z - np.eye(Z.shape[1]))) <= 1e-12
+    if eps == 1e-4:
+        # the cut lies far above the FP64 Gram route's resolution here
+        assert all(margins)
+        for j1, j2, j3, v in case["beta_samples"]:
+            assert abs(g["beta"][j1, j2, j3] - v) <= 1e-9 * gold["xi_norm"], (j1, j2, j3)
+    err = orc.error_dense(had.A, g["beta"], g["Z"])
+    _flush(f"fp64 eps={eps}: ranks {g['ranks']} (oracle {case['ranks']}) rel err {err / gold['a_norm']:.3e}"
+           f" (oracle {case['error'] / gold['a_norm']:.3e}) bound {rep['bound'] / gold['a_norm']:.3e}")
+    assert err <= rep["bound"] * (1 + 1e-9)
+    assert rep["bound"] <= eps * gold["a_norm"] * (1 + 1e-9)
+    if tuple(g["ranks"]) == tuple(case["ranks"]):
+        assert abs(err - case["error"]) <= 1e-4 * case["error"]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("eps", EPS)
+def test_hadamard_mixed_cores(orc, had, prec, eps):
+    """FP64 Gram, eigensolver and truncation: the ranks and Z are the FP64
+    path's.  FP32 core: accumulation restarted every 8192 terms keeps its error
+    near u32 sqrt(2048) of the running sums (bound 2e-6 |A|), so the total error
+    stays within (eps + 1e-6) |A| at both eps.  BF16x3 core: each operand is
+    hi + lo in bf16 (representation error ~2^-18 per operand, lo*lo dropped), an
+    error that does not average out over a sum of positive terms, so its core
+    error is bounded by 2^-17 |A|: within (eps + 1e-6) |A| at eps = 1e-4, and
+    eps + 2^-17 at 1e-6 (the split's floor)."""
+    a = had.gold["a_norm"]
+    g64 = run("fp64", eps)
+    g = run(prec, eps)
+    assert g["ranks"] == g64["ranks"]
+    for l in range(3):
+        assert np.array_equal(g["Z"][l], g64["Z"][l])
+    db = float(np.linalg.norm((g["beta"] - g64["beta"]).ravel()))
+    err = orc.error_dense(had.A, g["beta"], g["Z"])
+    _flush(f"{prec} eps={eps}: rel err {err / a:.3e}, core vs FP64 {db / a:.3e}")
+    if prec == "fp32":
+        assert db <= 2e-6 * a
+        assert err <= (eps + 1e-6) * a
+    else:
+        assert db <= 2.0 ** -17 * a
+        assert err <= (eps + (1e-6 if eps >= 1e-4 else 2.0 ** -17)) * a
