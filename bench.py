@@ -160,7 +160,7 @@ def bench_batched(args):
                   "charges x 32-term Gaussian sums for 1/|x|, eps=1e-5" % len(probs)),
         precision=args.batch_precision, problems=len(probs), steps=args.batch_steps,
         ms_per_batch=round(ms, 3), reductions_per_s=round(len(probs) / (ms * 1e-3), 3),
-        graph=red.batch_uses_graph(), all_ok=all(s == 0 for s in status),
+        graph=red.batch_uses_graph(), core_tile=red.last_core_tile(), all_ok=all(s == 0 for s in status),
         core_flops=core_flops, core_tflops_whole_pass=round(core_flops / (ms * 1e-3) / 1e12, 2),
         beta_gb=round(beta_gb, 2), max_rank=max(max(r) for r in ranks))
     log(f"batch: {ms:.1f} ms per batch -> {result['reductions_per_s']} reductions/s")
@@ -215,6 +215,7 @@ def bench_precision_study(args):
             ms, core_ms, avg = time_path(red, U, xi, eps, beta, args.precision_steps, 1)
             rep = red.get(beta=False, Z=False, sigma=False).report
             row = dict(eps=eps, precision=prec, ranks=list(ranks), ms=round(ms, 3), core_ms=round(core_ms, 3),
+                       core_tile=red.last_core_tile(),
                        core_tflops=round(2.0 * r1 * r2 * r3 * ci.R / (core_ms * 1e-3) / 1e12, 2),
                        phase_ms={k: round(v, 3) for k, v in avg.items()},
                        bound_rel=rep["bound"] / rep["a_norm"])
@@ -342,7 +343,7 @@ def main():
                              core_mfma_tflops=mfma_ops / (core_ms * 1e-3) / 1e12,
                              phase_ms={k: round(v, 4) for k, v in avg.items()},
                              eig_sweeps=rep["eig_sweeps"], a_norm=rep["a_norm"],
-                             bound_rel=rep["bound"] / rep["a_norm"])
+                             bound_rel=rep["bound"] / rep["a_norm"], core_tile=red.last_core_tile())
         betas[prec] = beta
         log(f"  {prec}: {ms:.2f} ms/step, core {core_ms:.2f} ms "
             f"({results[prec]['core_tflops']:.1f} TFLOP/s), phases {results[prec]['phase_ms']}")

@@ -80,7 +80,17 @@ typedef struct {
                                 tau^2 lies below that floor the refined ranks are the
                                 smaller, still certified ones (Theorem 2.3); the
                                 spectrum then holds |V_p[k,:]| for k < p. */
-    int32_t reserved[3];     /* must be zero */
+    int32_t core_tile;       /* rows of j1 per workgroup tile of the FP32 / BF16x3 core: 64 or
+                                128; 0 (default): chosen by the library's autotuner, which
+                                times both on the first core of each shape class (precision,
+                                beta type, r1 in steps of 32, r2*r3 and R in quarter octaves)
+                                on the caller's stream and keeps the faster.  That first
+                                rhosvd_get synchronizes the stream (and its beta is written
+                                up to four times, the last by the winner); batched: the
+                                first rhosvd_reduce_batched of a plan does the same with
+                                the persistent core before recording its graph.  The FP64
+                                core has one tile (64).  See rhosvd_last_core_tile. */
+    int32_t reserved[2];     /* must be zero */
 } rhosvd_options;
 
 typedef struct {
@@ -204,6 +214,10 @@ rhosvd_status rhosvd_reduce_batched(rhosvd_handle h, int32_t count, const rhosvd
 
 /* 1 when the last batched call ran as a graph replay, 0 when it ran eagerly. */
 int32_t rhosvd_batch_uses_graph(rhosvd_handle h);
+
+/* Tile height (rows of j1) used by the last core launch on this handle
+ * (rhosvd_get or rhosvd_reduce_batched): 64 or 128, 0 before any core. */
+int32_t rhosvd_last_core_tile(rhosvd_handle h);
 
 /*
  * Rank-proposal network (learned rank proposal for the randomized range

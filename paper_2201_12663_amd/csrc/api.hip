@@ -30,6 +30,8 @@ struct rhosvd_ctx {
     hipStream_t stream = nullptr;
     rhosvd_options opt{};
     std::string err;
+    CoreTuner* tuner = nullptr;          // core tile per shape class (tune.hip)
+    int last_tile = 0;                   // tile of the last core launch
     // workspace (grow-only)
     char* ws = nullptr;
     size_t ws_bytes = 0;
@@ -137,8 +139,12 @@ rhosvd_status fail(rhosvd_ctx* h, rhosvd_status s, const std::string& msg) {
 rhosvd_status check_options(const rhosvd_options* o, std::string& msg) {
     if (!o) return RHOSVD_OK;
     if (o->precision < 0 || o->precision > 2) { msg = "unknown precision"; return RHOSVD_ERR_ARG; }
-    for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < 2; ++i)
         if (o->reserved[i] != 0) { msg = "reserved option fields must be zero"; return RHOSVD_ERR_ARG; }
+    if (o->core_tile != 0 && !core_tile_valid(o->precision, o->core_tile)) {
+        msg = "core_tile must be 0 (tuned), 64, or 128 (128 only for the FP32 and BF16x3 cores)";
+        return RHOSVD_ERR_ARG;
+    }
     return RHOSVD_OK;
 }
 
@@ -424,6 +430,7 @@ rhosvd_status rhosvd_create(rhosvd_handle* out, void* hip_stream, const rhosvd_o
     rhosvd_ctx* h = new rhosvd_ctx();
     h->stream = (hipStream_t)hip_stream;
     apply_options(h, opt);
+    h->tuner = core_tuner_create();
     if (hipHostMalloc((void**)&h->host, 256, hipHostMallocDefault) != hipSuccess) {
         delete h;
         g_create_error = "pinned host allocation failed";
@@ -454,6 +461,7 @@ rhosvd_status rhosvd_destroy(rhosvd_handle h) {
     if (h->host) hipHostFree(h->host);
     for (int i = 0; i < NEV; ++i)
         if (h->ev[i]) hipEventDestroy(h->ev[i]);
+    core_tuner_destroy(h->tuner);
     delete h;
     return RHOSVD_OK;
 }
@@ -654,7 +662,13 @@ rhosvd_status rhosvd_get(rhosvd_handle h, double* Z1, double* Z2, double* Z3, vo
         ca.beta = beta;
         ca.prec = h->vprec;
         ca.beta_f32 = h->opt.beta_fp32 != 0;
-        CK(h, launch_core(ca, st));
+        if (h->opt.core_tile) {
+            ca.tile = h->opt.core_tile;
+            CK(h, launch_core(ca, st));
+            h->last_tile = ca.tile;
+        } else {
+            CK(h, launch_core_tuned(h->tuner, ca, st, &h->last_tile));
+        }
     }
     if (h->opt.profile && h->ev_ok) hipEventRecord(h->ev[8], st);
     h->get_timed = true;
@@ -741,7 +755,7 @@ rhosvd_status rhosvd_reduce_batched(rhosvd_handle h, int32_t count, const rhosvd
     std::string msg;
     const int vs = batch_validate(problems, count, msg);
     if (vs != RHOSVD_OK) return fail(h, (rhosvd_status)vs, msg);
-    const int prec_key = h->opt.precision | (h->opt.beta_fp32 ? 16 : 0);
+    const int prec_key = h->opt.precision | (h->opt.beta_fp32 ? 16 : 0) | (h->opt.core_tile << 8);
     if (!batch_plan_matches(h->batch, problems, count, prec_key)) {
         // earlier work on the stream may still use the old plan's memory
         CK(h, hipStreamSynchronize(h->stream));
@@ -754,6 +768,7 @@ rhosvd_status rhosvd_reduce_batched(rhosvd_handle h, int32_t count, const rhosvd
         if (!h->batch) return fail(h, RHOSVD_ERR_ALLOC, err);
     }
     CK(h, batch_plan_run(h->batch, h->stream));
+    h->last_tile = batch_plan_core_tile(h->batch);
     return RHOSVD_OK;
 }
 
@@ -1120,6 +1135,8 @@ rhosvd_status rhosvd_reduce_learned(rhosvd_handle h, int64_t n, int64_t R, const
 }
 
 int32_t rhosvd_batch_uses_graph(rhosvd_handle h) { return (h && batch_plan_uses_graph(h->batch)) ? 1 : 0; }
+
+int32_t rhosvd_last_core_tile(rhosvd_handle h) { return h ? h->last_tile : 0; }
 
 double rhosvd_phase_ms(rhosvd_handle h, int32_t phase) {
     if (!h || !h->opt.profile || !h->ev_ok || phase < 0 || phase >= NPHASE) return -1.0;

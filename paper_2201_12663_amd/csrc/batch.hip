@@ -74,7 +74,9 @@ struct BatchPlan {
     std::vector<rhosvd_problem> key;
     int prec = 0;
     int prec_key = 0;
-    int core_key = 0;                    // prec_key, + 32 when some R_pad exceeds core_flush_span()
+    int core_key = 0;                    // prec_key & 63, + 32 when some R_pad exceeds core_flush_span()
+    int core_tile = 0;                   // rows per core tile: fixed by the caller, or chosen on the first run
+    bool tune_pending = false;           // the first run times the tile candidates
     std::vector<BProb> hp;
     // device memory
     char* ws = nullptr;
@@ -193,7 +195,8 @@ size_t carve_batch(BatchPlan& B, char* base) {
     return c.off;
 }
 
-hipError_t enqueue_batch(const BatchPlan& B, hipStream_t st, bool coop) {
+// everything up to and including the projection
+static hipError_t enqueue_batch_pre(const BatchPlan& B, hipStream_t st, bool coop) {
     hipError_t e;
     const int np = (int)B.hp.size();
     const BProb* P = B.dP;
@@ -240,10 +243,44 @@ hipError_t enqueue_batch(const BatchPlan& B, hipStream_t st, bool coop) {
         }
     }
     if ((e = launch_batched_dense(BK_SIGN, P, B.pre[4], np, B.nblk[4], 0, st)) != hipSuccess) return e;
-    if ((e = launch_batched_dense(BK_PROJECT, P, B.pre[3], np, B.nblk[3], B.prec != 0, st)) != hipSuccess) return e;
-    if ((e = launch_core_b(P, np, B.core_key, B.core_work, B.core_grid, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_finish_b, dim3((unsigned)np, 3, 8), dim3(256), 0, st, P);
+    return launch_batched_dense(BK_PROJECT, P, B.pre[3], np, B.nblk[3], B.prec != 0, st);
+}
+
+static hipError_t enqueue_finish(const BatchPlan& B, hipStream_t st) {
+    hipLaunchKernelGGL(k_finish_b, dim3((unsigned)B.hp.size(), 3, 8), dim3(256), 0, st, B.dP);
     return hipGetLastError();
+}
+
+hipError_t enqueue_batch(const BatchPlan& B, hipStream_t st, bool coop) {
+    hipError_t e;
+    if ((e = enqueue_batch_pre(B, st, coop)) != hipSuccess) return e;
+    if ((e = launch_core_b(B.dP, (int)B.hp.size(), B.core_key, B.core_tile, B.core_work, B.core_grid, st)) !=
+        hipSuccess)
+        return e;
+    return enqueue_finish(B, st);
+}
+
+// record the pass into a graph; on any failure the pass runs eagerly
+static void capture_batch(BatchPlan* B) {
+    const char* env = getenv("RHOSVD_BATCH_GRAPH");
+    if (env && env[0] == '0') return;
+    if (!B->cap && hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking) != hipSuccess) {
+        B->cap = nullptr;
+        return;
+    }
+    bool ok = hipStreamBeginCapture(B->cap, hipStreamCaptureModeRelaxed) == hipSuccess;
+    hipError_t ee = ok ? enqueue_batch(*B, B->cap, false) : hipErrorUnknown;
+    hipGraph_t g = nullptr;
+    hipError_t ec = ok ? hipStreamEndCapture(B->cap, &g) : hipErrorUnknown;
+    if (ok && ee == hipSuccess && ec == hipSuccess && g &&
+        hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0) == hipSuccess) {
+        B->graph = g;
+        B->use_graph = true;
+    } else {
+        if (g) hipGraphDestroy(g);
+        B->exec = nullptr;
+        hipGetLastError();
+    }
 }
 
 bool same_key(const std::vector<rhosvd_problem>& k, const rhosvd_problem* probs, int count) {
@@ -276,7 +313,8 @@ int batch_validate(const rhosvd_problem* probs, int count, std::string& msg) {
 
 BatchPlan* batch_plan_create(const rhosvd_problem* probs, int count, int prec, std::string& err) {
     BatchPlan* B = new BatchPlan();
-    // prec: the core precision, plus 16 when beta is written as float
+    // prec: the core precision, plus 16 when beta is written as float, plus the
+    // caller's fixed core tile times 256 (0: tuned on the first run)
     B->key.assign(probs, probs + count);
     B->prec = prec & 3;
     B->prec_key = prec;
@@ -360,24 +398,16 @@ BatchPlan* batch_plan_create(const rhosvd_problem* probs, int count, int prec, s
     }
     int64_t rmax = 0;
     for (const BProb& q : B->hp) rmax = std::max<int64_t>(rmax, q.R_pad);
-    B->core_key = B->prec_key | (rmax > core_flush_span() ? 32 : 0);
-    B->core_grid = core_b_max_grid(B->core_key);
-    // record the pass into a graph; on any failure the pass runs eagerly
-    const char* env = getenv("RHOSVD_BATCH_GRAPH");
-    if (!(env && env[0] == '0') && hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking) == hipSuccess) {
-        bool ok = hipStreamBeginCapture(B->cap, hipStreamCaptureModeRelaxed) == hipSuccess;
-        hipError_t ee = ok ? enqueue_batch(*B, B->cap, false) : hipErrorUnknown;
-        hipGraph_t g = nullptr;
-        hipError_t ec = ok ? hipStreamEndCapture(B->cap, &g) : hipErrorUnknown;
-        if (ok && ee == hipSuccess && ec == hipSuccess && g &&
-            hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0) == hipSuccess) {
-            B->graph = g;
-            B->use_graph = true;
-        } else {
-            if (g) hipGraphDestroy(g);
-            B->exec = nullptr;
-            hipGetLastError();
-        }
+    B->core_key = (B->prec_key & 63) | (rmax > core_flush_span() ? 32 : 0);
+    const int fixed = B->prec_key >> 8;
+    bool any_beta = false;
+    for (const BProb& q : B->hp) any_beta = any_beta || q.beta != nullptr;
+    if (fixed || B->prec == 0 || !any_beta) {
+        B->core_tile = fixed ? fixed : core_tile_default(B->prec);
+        B->core_grid = core_b_max_grid(B->core_key, B->core_tile);
+        capture_batch(B);
+    } else {
+        B->tune_pending = true;   // the first run times the candidates, then records the graph
     }
     return B;
 }
@@ -387,9 +417,35 @@ bool batch_plan_matches(const BatchPlan* B, const rhosvd_problem* probs, int cou
 }
 
 hipError_t batch_plan_run(BatchPlan* B, hipStream_t st) {
+    if (B->tune_pending) {
+        // first run: the pass up to the projection, then the persistent core with
+        // each tile candidate (timed), then the rest; later runs use the winner
+        hipError_t e;
+        if ((e = enqueue_batch_pre(*B, st, true)) != hipSuccess) return e;
+        const int np = (int)B->hp.size();
+        int best = 0;
+        const int tiles[2] = {64, 128};
+        e = time_candidates(
+            tiles, 2,
+            [&](int tile) {
+                return launch_core_b(B->dP, np, B->core_key, tile, B->core_work, core_b_max_grid(B->core_key, tile),
+                                     st);
+            },
+            st, &best);
+        if (e != hipSuccess) return e;
+        if ((e = enqueue_finish(*B, st)) != hipSuccess) return e;
+        B->core_tile = best;
+        B->core_grid = core_b_max_grid(B->core_key, best);
+        B->tune_pending = false;
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+        capture_batch(B);
+        return hipSuccess;
+    }
     if (B->use_graph) return hipGraphLaunch(B->exec, st);
     return enqueue_batch(*B, st, true);
 }
+
+int batch_plan_core_tile(const BatchPlan* B) { return B ? B->core_tile : 0; }
 
 bool batch_plan_uses_graph(const BatchPlan* B) { return B && B->use_graph; }
 

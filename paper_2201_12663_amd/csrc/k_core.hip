@@ -91,12 +91,13 @@ struct MF<float> {
     static __device__ __forceinline__ int row(int lane, int i) { return c_row32(lane, i); }
 };
 
-template <typename T, typename O, bool FLUSH>
+template <typename T, typename O, bool FLUSH, int NF>
 __device__ __forceinline__ void core_tile_std(int r1, int r2, int r3, int ld1, int ld2, int ld3, int64_t Kp,
                               const T* __restrict__ V1, const T* __restrict__ V2, const T* __restrict__ V3,
                               const double* __restrict__ xip, O* __restrict__ beta, int N2T, int N3T,
                               int64_t tile) {
-    constexpr int TM = 64, KC = 16;
+    constexpr int TM = 16 * NF, KC = 16;
+    constexpr int PA = TM * KC / 256, AS = 256 / TM;   // A entries per thread, their k stride
     typedef typename MF<T>::acc_t acc_t;
     __shared__ T sA[2][KC][TM];
     __shared__ T s2[2][KC][TN2];
@@ -107,14 +108,14 @@ __device__ __forceinline__ void core_tile_std(int r1, int r2, int r3, int ld1, i
     const int m0 = mt * TM, b2 = n2t * TN2, b3 = n3t * TN3;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
 
-    // staging maps: A 64 x 16 (4 per thread), V2/V3 16 x 16 (1 each)
-    const int ai = t & 63, ak = t >> 6;
+    // staging maps: A TM x 16 (PA per thread), V2/V3 16 x 16 (1 each)
+    const int ai = t % TM, ak = t / TM;
     const int vi = t & 15, vk = t >> 4;
-    T ra[4], rv2, rv3;
+    T ra[PA], rv2, rv3;
     auto gload = [&](int64_t k0) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int64_t k = k0 + ak + 4 * q;
+        for (int q = 0; q < PA; ++q) {
+            const int64_t k = k0 + ak + AS * q;
             ra[q] = V1[(int64_t)(m0 + ai) + k * ld1] * (T)xip[k];
         }
         rv2 = V2[(int64_t)(b2 + vi) + (k0 + vk) * ld2];
@@ -122,14 +123,14 @@ __device__ __forceinline__ void core_tile_std(int r1, int r2, int r3, int ld1, i
     };
     auto lstore = [&](int buf) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) sA[buf][ak + 4 * q][ai] = ra[q];
+        for (int q = 0; q < PA; ++q) sA[buf][ak + AS * q][ai] = ra[q];
         s2[buf][vk][vi] = rv2;
         s3[buf][vk][vi] = rv3;
     };
 
-    acc_t acc[4][4];
+    acc_t acc[NF][4];
 #pragma unroll
-    for (int f = 0; f < 4; ++f)
+    for (int f = 0; f < NF; ++f)
 #pragma unroll
         for (int g = 0; g < 4; ++g) acc[f][g] = acc_t{0, 0, 0, 0};
 
@@ -147,20 +148,20 @@ __device__ __forceinline__ void core_tile_std(int r1, int r2, int r3, int ld1, i
 #pragma unroll
         for (int kk = 0; kk < KC / 4; ++kk) {
             const int k = 4 * kk + (lane >> 4);
-            T a[4], b[4];
+            T a[NF], b[4];
 #pragma unroll
-            for (int f = 0; f < 4; ++f) a[f] = sA[buf][k][16 * f + (lane & 15)];
+            for (int f = 0; f < NF; ++f) a[f] = sA[buf][k][16 * f + (lane & 15)];
             const T v2 = s2[buf][k][lane & 15];
 #pragma unroll
             for (int g = 0; g < 4; ++g) b[g] = v2 * s3[buf][k][4 * w + g];
 #pragma unroll
-            for (int f = 0; f < 4; ++f)
+            for (int f = 0; f < NF; ++f)
 #pragma unroll
                 for (int g = 0; g < 4; ++g) acc[f][g] = MF<T>::mma(a[f], b[g], acc[f][g]);
         }
         if constexpr (f32) {
             if ((c + 1) % FL == 0 && c + 1 < nchunk) {
-                hand_over<4, O>(beta, r1, r2, r3, m0, b2, b3, lane, w, acc, first);
+                hand_over<NF, O>(beta, r1, r2, r3, m0, b2, b3, lane, w, acc, first);
                 first = false;
             }
         }
@@ -168,11 +169,11 @@ __device__ __forceinline__ void core_tile_std(int r1, int r2, int r3, int ld1, i
         __syncthreads();
     }
     if constexpr (f32) {
-        hand_over<4, O>(beta, r1, r2, r3, m0, b2, b3, lane, w, acc, first);
+        hand_over<NF, O>(beta, r1, r2, r3, m0, b2, b3, lane, w, acc, first);
         return;
     }
 #pragma unroll
-    for (int f = 0; f < 4; ++f)
+    for (int f = 0; f < NF; ++f)
 #pragma unroll
         for (int g = 0; g < 4; ++g)
 #pragma unroll
@@ -181,7 +182,7 @@ __device__ __forceinline__ void core_tile_std(int r1, int r2, int r3, int ld1, i
                            acc[f][g][i]);
 }
 
-template <typename T, typename O, bool FLUSH>
+template <typename T, typename O, bool FLUSH, int NF>
 __global__ __launch_bounds__(256) void k_core_std(int r1, int r2, int r3, int ld1, int ld2, int ld3,
                                                   int64_t Kp, const T* __restrict__ V1,
                                                   const T* __restrict__ V2, const T* __restrict__ V3,
@@ -189,42 +190,44 @@ __global__ __launch_bounds__(256) void k_core_std(int r1, int r2, int r3, int ld
                                                   int MT, int N2T, int N3T, int64_t per) {
     const int64_t tile = xcd_tile(blockIdx.x, per);
     if (tile >= (int64_t)MT * N2T * N3T) return;
-    core_tile_std<T, O, FLUSH>(r1, r2, r3, ld1, ld2, ld3, Kp, V1, V2, V3, xip, beta, N2T, N3T, tile);
+    core_tile_std<T, O, FLUSH, NF>(r1, r2, r3, ld1, ld2, ld3, Kp, V1, V2, V3, xip, beta, N2T, N3T, tile);
 }
 
 // ---------------------------------------------------------------------------
 // BF16x3 variant, TM = 128, KC = 32.  V_l are FP32.
 // ---------------------------------------------------------------------------
-constexpr int BTM = 128, BKC = 32, BLDA = BKC + 8;   // bf16 elements per LDS row of A
+constexpr int BKC = 32, BLDA = BKC + 8;   // bf16 elements per LDS row of A
 
 __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
     hi = (__bf16)x;
     lo = (__bf16)(x - (float)hi);
 }
 
-template <typename O, bool FLUSH>
+template <typename O, bool FLUSH, int NF>
 __device__ __forceinline__ void core_tile_bf16x3(int r1, int r2, int r3, int ld1, int ld2, int ld3, int64_t Kp,
                                  const float* __restrict__ V1, const float* __restrict__ V2,
                                  const float* __restrict__ V3, const double* __restrict__ xip,
                                  O* __restrict__ beta, int N2T, int N3T, int64_t tile) {
-    __shared__ __attribute__((aligned(16))) __bf16 sAh[2][BTM * BLDA];
-    __shared__ __attribute__((aligned(16))) __bf16 sAl[2][BTM * BLDA];
+    constexpr int TM = 16 * NF;
+    constexpr int PA = TM * BKC / 256, AS = 256 / TM;   // A entries per thread, their k stride
+    __shared__ __attribute__((aligned(16))) __bf16 sAh[2][TM * BLDA];
+    __shared__ __attribute__((aligned(16))) __bf16 sAl[2][TM * BLDA];
     __shared__ float s2[2][BKC][TN2];
     __shared__ float s3[2][BKC][TN3];
     const int NT = N2T * N3T;
     const int mt = (int)(tile / NT), nt = (int)(tile % NT);
     const int n3t = nt / N2T, n2t = nt % N2T;
-    const int m0 = mt * BTM, b2 = n2t * TN2, b3 = n3t * TN3;
+    const int m0 = mt * TM, b2 = n2t * TN2, b3 = n3t * TN3;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
 
-    // staging: A 128 x 32 (16 per thread), V2/V3 32 x 16 (2 each)
-    const int ai = t & 127, ak = t >> 7;           // k = ak + 2q
+    // staging: A TM x 32 (PA per thread), V2/V3 32 x 16 (2 each)
+    const int ai = t % TM, ak = t / TM;            // k = ak + AS q
     const int vi = t & 15, vk = t >> 4;            // k = vk, vk + 16
-    float ra[16], rv2[2], rv3[2];
+    float ra[PA], rv2[2], rv3[2];
     auto gload = [&](int64_t k0) {
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int64_t k = k0 + ak + 2 * q;
+        for (int q = 0; q < PA; ++q) {
+            const int64_t k = k0 + ak + AS * q;
             ra[q] = V1[(int64_t)(m0 + ai) + k * ld1] * (float)xip[k];
         }
 #pragma unroll
@@ -235,11 +238,11 @@ __device__ __forceinline__ void core_tile_bf16x3(int r1, int r2, int r3, int ld1
     };
     auto lstore = [&](int buf) {
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
+        for (int q = 0; q < PA; ++q) {
             __bf16 h, l;
             split_bf16(ra[q], h, l);
-            sAh[buf][ai * BLDA + ak + 2 * q] = h;
-            sAl[buf][ai * BLDA + ak + 2 * q] = l;
+            sAh[buf][ai * BLDA + ak + AS * q] = h;
+            sAl[buf][ai * BLDA + ak + AS * q] = l;
         }
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
@@ -248,9 +251,9 @@ __device__ __forceinline__ void core_tile_bf16x3(int r1, int r2, int r3, int ld1
         }
     };
 
-    f4_t acc[8][4];
+    f4_t acc[NF][4];
 #pragma unroll
-    for (int f = 0; f < 8; ++f)
+    for (int f = 0; f < NF; ++f)
 #pragma unroll
         for (int g = 0; g < 4; ++g) acc[f][g] = f4_t{0.f, 0.f, 0.f, 0.f};
 
@@ -281,7 +284,7 @@ __device__ __forceinline__ void core_tile_bf16x3(int r1, int r2, int r3, int ld1
             }
         }
 #pragma unroll
-        for (int f = 0; f < 8; ++f) {
+        for (int f = 0; f < NF; ++f) {
             const int row = 16 * f + (lane & 15);
             const bf8_t ah = *reinterpret_cast<const bf8_t*>(&sAh[buf][row * BLDA + kg]);
             const bf8_t al = *reinterpret_cast<const bf8_t*>(&sAl[buf][row * BLDA + kg]);
@@ -294,7 +297,7 @@ __device__ __forceinline__ void core_tile_bf16x3(int r1, int r2, int r3, int ld1
         }
         if constexpr (FLUSH) {
             if ((c + 1) % FL == 0 && c + 1 < nchunk) {
-                hand_over<8, O>(beta, r1, r2, r3, m0, b2, b3, lane, w, acc, first);
+                hand_over<NF, O>(beta, r1, r2, r3, m0, b2, b3, lane, w, acc, first);
                 first = false;
             }
         }
@@ -302,11 +305,11 @@ __device__ __forceinline__ void core_tile_bf16x3(int r1, int r2, int r3, int ld1
         __syncthreads();
     }
     if constexpr (FLUSH) {
-        hand_over<8, O>(beta, r1, r2, r3, m0, b2, b3, lane, w, acc, first);
+        hand_over<NF, O>(beta, r1, r2, r3, m0, b2, b3, lane, w, acc, first);
         return;
     }
 #pragma unroll
-    for (int f = 0; f < 8; ++f)
+    for (int f = 0; f < NF; ++f)
 #pragma unroll
         for (int g = 0; g < 4; ++g)
 #pragma unroll
@@ -315,7 +318,7 @@ __device__ __forceinline__ void core_tile_bf16x3(int r1, int r2, int r3, int ld1
                            acc[f][g][i]);
 }
 
-template <typename O, bool FLUSH>
+template <typename O, bool FLUSH, int NF>
 __global__ __launch_bounds__(256) void k_core_bf16x3(int r1, int r2, int r3, int ld1, int ld2, int ld3,
                                                      int64_t Kp, const float* __restrict__ V1,
                                                      const float* __restrict__ V2, const float* __restrict__ V3,
@@ -323,7 +326,7 @@ __global__ __launch_bounds__(256) void k_core_bf16x3(int r1, int r2, int r3, int
                                                      int MT, int N2T, int N3T, int64_t per) {
     const int64_t tile = xcd_tile(blockIdx.x, per);
     if (tile >= (int64_t)MT * N2T * N3T) return;
-    core_tile_bf16x3<O, FLUSH>(r1, r2, r3, ld1, ld2, ld3, Kp, V1, V2, V3, xip, beta, N2T, N3T, tile);
+    core_tile_bf16x3<O, FLUSH, NF>(r1, r2, r3, ld1, ld2, ld3, Kp, V1, V2, V3, xip, beta, N2T, N3T, tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -347,7 +350,7 @@ __global__ void k_core_plan_b(const BProb* __restrict__ P, int np, int tm, int64
     work[0] = 0;
 }
 
-template <int PREC, typename O, bool FLUSH>
+template <int PREC, typename O, bool FLUSH, int NF>
 __global__ __launch_bounds__(256) void k_core_persist_b(const BProb* __restrict__ P, int np,
                                                         int64_t* __restrict__ work) {
     __shared__ int64_t s_tile;
@@ -371,40 +374,54 @@ __global__ __launch_bounds__(256) void k_core_persist_b(const BProb* __restrict_
         const int N2T = (int)ceil_div(r2, TN2), N3T = (int)ceil_div(r3, TN3);
         const int64_t local = tile - pre[lo];
         if (PREC == 0)
-            core_tile_std<double, O, false>(r1, r2, r3, q.rcap_pad, q.rcap_pad, q.rcap_pad, q.R_pad, (const double*)q.V[0],
+            core_tile_std<double, O, false, 4>(r1, r2, r3, q.rcap_pad, q.rcap_pad, q.rcap_pad, q.R_pad, (const double*)q.V[0],
                                   (const double*)q.V[1], (const double*)q.V[2], q.xip, (O*)q.beta, N2T, N3T, local);
         else if (PREC == 1)
-            core_tile_std<float, O, FLUSH>(r1, r2, r3, q.rcap_pad, q.rcap_pad, q.rcap_pad, q.R_pad, (const float*)q.V[0],
+            core_tile_std<float, O, FLUSH, NF>(r1, r2, r3, q.rcap_pad, q.rcap_pad, q.rcap_pad, q.R_pad, (const float*)q.V[0],
                                  (const float*)q.V[1], (const float*)q.V[2], q.xip, (O*)q.beta, N2T, N3T, local);
         else
-            core_tile_bf16x3<O, FLUSH>(r1, r2, r3, q.rcap_pad, q.rcap_pad, q.rcap_pad, q.R_pad, (const float*)q.V[0],
+            core_tile_bf16x3<O, FLUSH, NF>(r1, r2, r3, q.rcap_pad, q.rcap_pad, q.rcap_pad, q.R_pad, (const float*)q.V[0],
                              (const float*)q.V[1], (const float*)q.V[2], q.xip, (O*)q.beta, N2T, N3T, local);
     }
 }
 
 }  // namespace
 
-template <typename O, bool FLUSH>
+template <typename O, bool FLUSH, int NF>
 static void launch_core_t(const CoreArgs& a, dim3 grid, int MT, int N2T, int N3T, int64_t per, hipStream_t st) {
     O* beta = (O*)a.beta;
     if (a.prec == 0) {
-        hipLaunchKernelGGL((k_core_std<double, O, false>), grid, dim3(256), 0, st, a.r[0], a.r[1], a.r[2], a.r_pad[0],
-                           a.r_pad[1], a.r_pad[2], a.R_pad, (const double*)a.V[0], (const double*)a.V[1],
-                           (const double*)a.V[2], a.xip, beta, MT, N2T, N3T, per);
+        hipLaunchKernelGGL((k_core_std<double, O, false, 4>), grid, dim3(256), 0, st, a.r[0], a.r[1], a.r[2],
+                           a.r_pad[0], a.r_pad[1], a.r_pad[2], a.R_pad, (const double*)a.V[0],
+                           (const double*)a.V[1], (const double*)a.V[2], a.xip, beta, MT, N2T, N3T, per);
     } else if (a.prec == 1) {
-        hipLaunchKernelGGL((k_core_std<float, O, FLUSH>), grid, dim3(256), 0, st, a.r[0], a.r[1], a.r[2], a.r_pad[0],
-                           a.r_pad[1], a.r_pad[2], a.R_pad, (const float*)a.V[0], (const float*)a.V[1],
-                           (const float*)a.V[2], a.xip, beta, MT, N2T, N3T, per);
+        hipLaunchKernelGGL((k_core_std<float, O, FLUSH, NF>), grid, dim3(256), 0, st, a.r[0], a.r[1], a.r[2],
+                           a.r_pad[0], a.r_pad[1], a.r_pad[2], a.R_pad, (const float*)a.V[0],
+                           (const float*)a.V[1], (const float*)a.V[2], a.xip, beta, MT, N2T, N3T, per);
     } else {
-        hipLaunchKernelGGL((k_core_bf16x3<O, FLUSH>), grid, dim3(256), 0, st, a.r[0], a.r[1], a.r[2], a.r_pad[0],
-                           a.r_pad[1], a.r_pad[2], a.R_pad, (const float*)a.V[0], (const float*)a.V[1],
-                           (const float*)a.V[2], a.xip, beta, MT, N2T, N3T, per);
+        hipLaunchKernelGGL((k_core_bf16x3<O, FLUSH, NF>), grid, dim3(256), 0, st, a.r[0], a.r[1], a.r[2],
+                           a.r_pad[0], a.r_pad[1], a.r_pad[2], a.R_pad, (const float*)a.V[0],
+                           (const float*)a.V[1], (const float*)a.V[2], a.xip, beta, MT, N2T, N3T, per);
     }
+}
+
+template <typename O, bool FLUSH>
+static void launch_core_nf(const CoreArgs& a, int nf, dim3 grid, int MT, int N2T, int N3T, int64_t per,
+                           hipStream_t st) {
+    if (nf == 8) launch_core_t<O, FLUSH, 8>(a, grid, MT, N2T, N3T, per, st);
+    else launch_core_t<O, FLUSH, 4>(a, grid, MT, N2T, N3T, per, st);
+}
+
+int core_tile_default(int prec) { return (prec & 3) == 2 ? 128 : 64; }
+
+bool core_tile_valid(int prec, int tile) {
+    return (prec & 3) == 0 ? tile == 64 : (tile == 64 || tile == 128);
 }
 
 hipError_t launch_core(const CoreArgs& a, hipStream_t st) {
     if (a.r[0] < 1 || a.r[1] < 1 || a.r[2] < 1) return hipSuccess;
-    const int TMv = (a.prec == 2) ? BTM : 64;
+    const int TMv = a.tile ? a.tile : core_tile_default(a.prec);
+    if (!core_tile_valid(a.prec, TMv)) return hipErrorInvalidValue;
     const int KCv = (a.prec == 2) ? BKC : 16;
     if (a.R_pad % KCv != 0) return hipErrorInvalidValue;
     const int MT = (int)ceil_div(a.r[0], TMv), N2T = (int)ceil_div(a.r[1], TN2), N3T = (int)ceil_div(a.r[2], TN3);
@@ -414,59 +431,75 @@ hipError_t launch_core(const CoreArgs& a, hipStream_t st) {
     const int64_t per = ceil_div(ntile, NXCD);
     dim3 grid((unsigned)(per * NXCD));
     const bool flush = a.R_pad > KFLUSH;   // the hand-over variants only where they act
+    const int nf = TMv / 16;
     if (a.beta_f32) {
-        if (flush) launch_core_t<float, true>(a, grid, MT, N2T, N3T, per, st);
-        else launch_core_t<float, false>(a, grid, MT, N2T, N3T, per, st);
+        if (flush) launch_core_nf<float, true>(a, nf, grid, MT, N2T, N3T, per, st);
+        else launch_core_nf<float, false>(a, nf, grid, MT, N2T, N3T, per, st);
     } else {
-        if (flush) launch_core_t<double, true>(a, grid, MT, N2T, N3T, per, st);
-        else launch_core_t<double, false>(a, grid, MT, N2T, N3T, per, st);
+        if (flush) launch_core_nf<double, true>(a, nf, grid, MT, N2T, N3T, per, st);
+        else launch_core_nf<double, false>(a, nf, grid, MT, N2T, N3T, per, st);
     }
     return hipGetLastError();
 }
 
-template <typename O, bool FLUSH>
+template <typename O, bool FLUSH, int NF>
 static void launch_persist_t(const BProb* P, int np, int prec, int64_t* work, int grid, hipStream_t st) {
     const dim3 g((unsigned)grid), b(256);
-    if (prec == 0) hipLaunchKernelGGL((k_core_persist_b<0, O, false>), g, b, 0, st, P, np, work);
-    else if (prec == 1) hipLaunchKernelGGL((k_core_persist_b<1, O, FLUSH>), g, b, 0, st, P, np, work);
-    else hipLaunchKernelGGL((k_core_persist_b<2, O, FLUSH>), g, b, 0, st, P, np, work);
+    if (prec == 0) hipLaunchKernelGGL((k_core_persist_b<0, O, false, 4>), g, b, 0, st, P, np, work);
+    else if (prec == 1) hipLaunchKernelGGL((k_core_persist_b<1, O, FLUSH, NF>), g, b, 0, st, P, np, work);
+    else hipLaunchKernelGGL((k_core_persist_b<2, O, FLUSH, NF>), g, b, 0, st, P, np, work);
+}
+
+template <typename O, bool FLUSH>
+static void launch_persist_nf(const BProb* P, int np, int prec, int nf, int64_t* work, int grid, hipStream_t st) {
+    if (nf == 8) launch_persist_t<O, FLUSH, 8>(P, np, prec, work, grid, st);
+    else launch_persist_t<O, FLUSH, 4>(P, np, prec, work, grid, st);
 }
 
 // prec: 0 FP64, 1 FP32, 2 BF16x3; +16 float beta; +32 some problem has R_pad > KFLUSH
-hipError_t launch_core_b(const BProb* P, int np, int prec, int64_t* work, int grid, hipStream_t st) {
+hipError_t launch_core_b(const BProb* P, int np, int prec, int tile, int64_t* work, int grid, hipStream_t st) {
     if (np < 1) return hipSuccess;
-    hipLaunchKernelGGL(k_core_plan_b, dim3(1), dim3(64), 0, st, P, np, (prec & 3) == 2 ? BTM : 64, work);
+    const int TMv = tile ? tile : core_tile_default(prec);
+    if (!core_tile_valid(prec, TMv)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_core_plan_b, dim3(1), dim3(64), 0, st, P, np, TMv, work);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const bool f32 = (prec & 16) != 0, flush = (prec & 32) != 0;
+    const int nf = TMv / 16;
     if (f32) {
-        if (flush) launch_persist_t<float, true>(P, np, prec & 3, work, grid, st);
-        else launch_persist_t<float, false>(P, np, prec & 3, work, grid, st);
+        if (flush) launch_persist_nf<float, true>(P, np, prec & 3, nf, work, grid, st);
+        else launch_persist_nf<float, false>(P, np, prec & 3, nf, work, grid, st);
     } else {
-        if (flush) launch_persist_t<double, true>(P, np, prec & 3, work, grid, st);
-        else launch_persist_t<double, false>(P, np, prec & 3, work, grid, st);
+        if (flush) launch_persist_nf<double, true>(P, np, prec & 3, nf, work, grid, st);
+        else launch_persist_nf<double, false>(P, np, prec & 3, nf, work, grid, st);
     }
     return hipGetLastError();
 }
 
 int64_t core_flush_span() { return KFLUSH; }
 
-template <typename O, bool FLUSH>
+template <typename O, bool FLUSH, int NF>
 static const void* persist_fn(int prec) {
     switch (prec) {
-        case 0: return (const void*)k_core_persist_b<0, O, false>;
-        case 1: return (const void*)k_core_persist_b<1, O, FLUSH>;
-        default: return (const void*)k_core_persist_b<2, O, FLUSH>;
+        case 0: return (const void*)k_core_persist_b<0, O, false, 4>;
+        case 1: return (const void*)k_core_persist_b<1, O, FLUSH, NF>;
+        default: return (const void*)k_core_persist_b<2, O, FLUSH, NF>;
     }
 }
 
-int core_b_max_grid(int prec) {
+template <int NF>
+static const void* persist_fn_nf(int prec) {
+    const bool f32 = (prec & 16) != 0, flush = (prec & 32) != 0;
+    return f32 ? (flush ? persist_fn<float, true, NF>(prec & 3) : persist_fn<float, false, NF>(prec & 3))
+               : (flush ? persist_fn<double, true, NF>(prec & 3) : persist_fn<double, false, NF>(prec & 3));
+}
+
+int core_b_max_grid(int prec, int tile) {
     int dev = 0, ncu = 0, occ = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 256;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 256;
-    const bool f32 = (prec & 16) != 0, flush = (prec & 32) != 0;
-    const void* f = f32 ? (flush ? persist_fn<float, true>(prec & 3) : persist_fn<float, false>(prec & 3))
-                        : (flush ? persist_fn<double, true>(prec & 3) : persist_fn<double, false>(prec & 3));
+    const int TMv = tile ? tile : core_tile_default(prec);
+    const void* f = TMv == 128 ? persist_fn_nf<8>(prec) : persist_fn_nf<4>(prec);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, 256, 0) != hipSuccess || occ < 1) occ = 1;
     return ncu * occ;
 }

@@ -1,6 +1,8 @@
 // Host-side launchers of the gfx950 kernels (internal to the library).
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include <functional>
 #include <stdint.h>
 
 #include <string>
@@ -144,8 +146,23 @@ struct CoreArgs {
     void* beta;       // double, or float when beta_f32
     int prec;
     int beta_f32;
+    int tile;         // rows of j1 per workgroup tile: 64 or 128 (FP32, BF16x3), 64 (FP64); 0: default
 };
 hipError_t launch_core(const CoreArgs& a, hipStream_t st);
+int core_tile_default(int prec);
+bool core_tile_valid(int prec, int tile);
+
+// Autotuner of the core tile (tune.hip).  launch_core_tuned launches with the
+// cached tile of the shape class, or times the candidates first (synchronizing
+// the stream; the output then holds the winner's result); *used: tile launched.
+struct CoreTuner;
+CoreTuner* core_tuner_create();
+void core_tuner_destroy(CoreTuner* T);
+hipError_t launch_core_tuned(CoreTuner* T, CoreArgs a, hipStream_t st, int* used);
+// times launch(tile) for each candidate (two alternating rounds, fastest launch
+// of each), leaves the winner's result in place, synchronizes st
+hipError_t time_candidates(const int* tiles, int ncand, const std::function<hipError_t(int)>& launch,
+                           hipStream_t st, int* best);
 
 // ---------------------------------------------------------------------------
 // Batched reductions: one descriptor per problem in device memory.  Sizes are
@@ -194,9 +211,9 @@ hipError_t launch_truncate_b(const BProb* P, int np, hipStream_t st);
 // prec: core precision (0..2), plus 16 when beta is written as float, plus 32
 // when some problem's R_pad exceeds core_flush_span() (the FP32-accumulating
 // cores then hand their partial sums to beta periodically).
-hipError_t launch_core_b(const BProb* P, int np, int prec, int64_t* work, int grid, hipStream_t st);
-// workgroups of the persistent core that fit on the device at once (prec as above)
-int core_b_max_grid(int prec);
+hipError_t launch_core_b(const BProb* P, int np, int prec, int tile, int64_t* work, int grid, hipStream_t st);
+// workgroups of the persistent core that fit on the device at once (prec, tile as above)
+int core_b_max_grid(int prec, int tile);
 int64_t core_flush_span();
 // copy Z to the caller's buffers and write the result words (ranks, status)
 hipError_t launch_finish_b(const BProb* P, int np, hipStream_t st);
@@ -209,6 +226,8 @@ BatchPlan* batch_plan_create(const rhosvd_problem* probs, int count, int prec, s
 bool batch_plan_matches(const BatchPlan* plan, const rhosvd_problem* probs, int count, int prec);
 hipError_t batch_plan_run(BatchPlan* plan, hipStream_t st);
 bool batch_plan_uses_graph(const BatchPlan* plan);
+// rows per core tile of the plan's batched core (0 until the first run has chosen)
+int batch_plan_core_tile(const BatchPlan* plan);
 void batch_plan_destroy(BatchPlan* plan);
 
 // ---------------------------------------------------------------------------

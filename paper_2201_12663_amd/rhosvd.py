@@ -24,7 +24,7 @@ STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_NONFINITE", -3: "ERR_ALLOC", -4: "ERR
 # every symbol include/rhosvd.h declares
 EXPORTS = ["rhosvd_create", "rhosvd_destroy", "rhosvd_set_options", "rhosvd_reduce", "rhosvd_get",
            "rhosvd_get_xi", "rhosvd_get_spectrum", "rhosvd_get_v", "rhosvd_reduce_batched",
-           "rhosvd_batch_uses_graph", "rhosvd_net_num_params", "rhosvd_net_set_params", "rhosvd_net_get_params",
+           "rhosvd_batch_uses_graph", "rhosvd_last_core_tile", "rhosvd_net_num_params", "rhosvd_net_set_params", "rhosvd_net_get_params",
            "rhosvd_net_forward", "rhosvd_net_train_step", "rhosvd_sketch_features", "rhosvd_reduce_learned",
            "rhosvd_phase_ms", "rhosvd_last_error", "rhosvd_version"]
 
@@ -35,7 +35,7 @@ PATHS = {0: "range finder", 1: "gram (chosen)", 2: "gram (certificate failed)", 
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("max_eig_sweeps", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("beta_fp32", ctypes.c_int32), ("refine_tails", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("core_tile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class Report(ctypes.Structure):
@@ -87,6 +87,8 @@ def load():
         lib.rhosvd_reduce_batched.argtypes = [vp, i32, ctypes.POINTER(Problem)]
         lib.rhosvd_batch_uses_graph.argtypes = [vp]
         lib.rhosvd_batch_uses_graph.restype = i32
+        lib.rhosvd_last_core_tile.argtypes = [vp]
+        lib.rhosvd_last_core_tile.restype = i32
         fp = ctypes.c_float
         lib.rhosvd_net_num_params.restype = i32
         lib.rhosvd_net_set_params.argtypes = [vp, vp]
@@ -149,10 +151,11 @@ class Reducer:
     """One library handle bound to a stream."""
 
     def __init__(self, precision="fp64", stream=None, max_eig_sweeps=0, profile=False, beta_fp32=False,
-                 refine_tails=False):
+                 refine_tails=False, core_tile=0):
         import torch
         self.lib = load()
         self.opt = Options()
+        self.opt.core_tile = int(core_tile)
         self.opt.beta_fp32 = 1 if beta_fp32 else 0
         self.opt.refine_tails = 1 if refine_tails else 0
         self.beta_dtype = torch.float32 if beta_fp32 else torch.float64
@@ -373,6 +376,10 @@ class Reducer:
 
     def batch_uses_graph(self):
         return bool(self.lib.rhosvd_batch_uses_graph(self.h))
+
+    def last_core_tile(self):
+        """Rows per workgroup tile of the last core launch (64 or 128; 0 before any)."""
+        return int(self.lib.rhosvd_last_core_tile(self.h))
 
     def reduce_batched(self, problems, beta=True):
         """Batched reductions with outputs sized exactly: a ranks-only pass, then

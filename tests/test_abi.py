@@ -55,6 +55,7 @@ def test_struct_layouts_match_header():
 def test_null_handle_batched(lib):
     assert lib.rhosvd_reduce_batched(None, 1, None) == -1
     assert lib.rhosvd_batch_uses_graph(None) == 0
+    assert lib.rhosvd_last_core_tile(None) == 0
 
 
 def test_network_size_and_null_handles(lib):
