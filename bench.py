@@ -49,16 +49,18 @@ def log(msg):
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "core_bf16x3_newton1024_traffic.json")
 
 
-def core_traffic(kernel_source):
+def core_traffic(kernel_source, tile):
     """HBM bytes per launch of the BF16x3 core from the committed counter summary
     (rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size),
-    or None when there is none or the kernel source changed since it was taken."""
+    or None when there is none, the kernel source changed since it was taken, or
+    the summary is for another tile variant than the one launched."""
     import hashlib
     import json as _json
     try:
         d = _json.load(open(TRAFFIC_SUMMARY))
         sha = hashlib.sha256(open(kernel_source, "rb").read()).hexdigest()
-        return d["bytes_per_launch"] if d.get("source_sha256") == sha else None
+        ok = d.get("source_sha256") == sha and d.get("tile") == tile
+        return d["bytes_per_launch"] if ok else None
     except (OSError, ValueError, KeyError):
         return None
 
@@ -386,10 +388,10 @@ def main():
         "paths": results,
         "speedup_vs_plain_fp64": (rb["reductions_per_s"] / results["fp64"]["reductions_per_s"]
                                   if "fp64" in results else None),
-        "roofline": {"bound": "mfma", "kernel": f"k_core ({best})", "achieved": round(achieved, 3),
-                     "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                     "traffic": core_traffic(os.path.join(ROOT, "paper_2201_12663_amd", "csrc", "k_core.hip"))
-                     if best == "bf16x3" else None,
+        "roofline": {"bound": "mfma", "kernel": f"k_core ({best}, {rb['core_tile']}-row tile)",
+                     "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                     "traffic": core_traffic(os.path.join(ROOT, "paper_2201_12663_amd", "csrc", "k_core.hip"),
+                                             rb["core_tile"]) if best == "bf16x3" else None,
                      "flops_per_launch": 2.0 * rb["ranks"][0] * rb["ranks"][1] * rb["ranks"][2] * ci.R
                      * (3 if best == "bf16x3" else 1)},
     }
