@@ -175,39 +175,75 @@ __device__ void form_reflector(const double* x, int k, const TriMat& M, double* 
     }
 }
 
-constexpr int RPT = MAXN / 256;   // rows per thread
+// Sums of 32 values across the wave at once: five halving butterfly steps
+// (each lane keeps half of its values and adds its partner's copy of that
+// half) and a last pairwise add.  Lane l ends with the wave total of value
+// l >> 1.  32 shuffles instead of 32 separate 6-step reductions.
+__device__ __forceinline__ double wave_sum32(const double (&a)[32], int lane) {
+    double b16[16], b8[8], b4[4], b2[2];
+    {
+        const bool h = lane & 32;
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            b16[j] = (h ? a[j + 16] : a[j]) + __shfl_xor(h ? a[j] : a[j + 16], 32, WAVE);
+    }
+    {
+        const bool h = lane & 16;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) b8[j] = (h ? b16[j + 8] : b16[j]) + __shfl_xor(h ? b16[j] : b16[j + 8], 16, WAVE);
+    }
+    {
+        const bool h = lane & 8;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b4[j] = (h ? b8[j + 4] : b8[j]) + __shfl_xor(h ? b8[j] : b8[j + 4], 8, WAVE);
+    }
+    {
+        const bool h = lane & 4;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b2[j] = (h ? b4[j + 2] : b4[j]) + __shfl_xor(h ? b4[j] : b4[j + 2], 4, WAVE);
+    }
+    const bool h = lane & 2;
+    const double b1 = (h ? b2[1] : b2[0]) + __shfl_xor(h ? b2[0] : b2[1], 2, WAVE);
+    return b1 + __shfl_xor(b1, 1, WAVE);
+}
 
 // One-sided Householder tridiagonalization H^T G H = T, column-distributed:
 // step k broadcasts v_k, every block forms p_j = tau (G v)_j for its columns,
 // the p_j and the per-block sums of p_j v_j are all-gathered, and each block
 // applies G <- G - v w^T - w v^T with w = p - (tau/2)(p.v) v to its columns.
 // The owner of column k+1 updates it first and forms reflector k+1.
+// Thread t holds rows t + 256 q, q < RPT, of every vector and LDS column; each
+// column is stored with RPT * 256 rows (rows >= m are zero), and v_k and w_k
+// are zero on rows <= k, so the row loops need no bounds: an update or dot
+// product over all RPT * 256 rows touches only the live part.
+template <int RPT>
 __global__ __launch_bounds__(256) void k_tridiag(TriArgs a) {
-    extern __shared__ double slab[];   // cpb columns x m_round, then v (m_round)
+    constexpr int S = RPT * 256;       // stored rows per column
+    extern __shared__ double slab[];   // cpb columns x S, then v (S)
     __shared__ double red[4];
     __shared__ double red2[CMAX * 4];
     __shared__ double vjs[CMAX], wjs[CMAX], pjs[CMAX];
     __shared__ double parts[256];
     __shared__ double cw_s;
+    static_assert(CMAX == 32, "one butterfly reduction covers the 32 column slots");
     int q0 = 0;
     while (q0 + 1 < a.nmat && (int)blockIdx.x >= a.mat[q0 + 1].blk0) ++q0;
     const TriMat& M = a.mat[q0];
     const int gb = blockIdx.x - M.blk0;
     if (gb >= M.bpm) return;
     const int m = M.m, ld = M.ld, cpb = M.cpb;
-    const int mr = (m + 63) & ~63;
-    double* vs = slab + (size_t)cpb * mr;
+    double* vs = slab + (size_t)cpb * S;
     const int c0 = gb * cpb;
     const int nc = max(0, min(cpb, m - c0));
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63;
     for (int c = 0; c < nc; ++c)
-        for (int i = t; i < m; i += 256) slab[c * mr + i] = M.G[i + (int64_t)(c0 + c) * ld];
+        for (int i = t; i < S; i += 256) slab[c * S + i] = (i < m) ? M.G[i + (int64_t)(c0 + c) * ld] : 0.0;
     __syncthreads();
     if (m > 2 && c0 == 0 && nc > 0) form_reflector(slab, 0, M, red);
     for (int k = 0; k + 2 < m; ++k) {
         const int par = k & 1;
         const uint32_t flag = (uint32_t)k + 1;
-        // receive v_k (this thread's rows) and tau_k in one poll
+        // receive v_k (this thread's rows > k) and tau_k in one poll
         double vr[RPT];
         double tau;
         {
@@ -215,8 +251,8 @@ __global__ __launch_bounds__(256) void k_tridiag(TriArgs a) {
             double val[RPT + 1];
 #pragma unroll
             for (int q = 0; q < RPT; ++q) {
-                const int i = k + 1 + t + 256 * q;
-                w[q] = (i < m) ? xv(M, par) + 2 * i : nullptr;
+                const int i = t + 256 * q;
+                w[q] = (i > k && i < m) ? xv(M, par) + 2 * i : nullptr;
                 val[q] = 0.0;
             }
             w[RPT] = xtau(M, par);
@@ -224,8 +260,7 @@ __global__ __launch_bounds__(256) void k_tridiag(TriArgs a) {
 #pragma unroll
             for (int q = 0; q < RPT; ++q) {
                 vr[q] = val[q];
-                const int i = k + 1 + t + 256 * q;
-                if (i < m) vs[i] = vr[q];
+                vs[t + 256 * q] = vr[q];
             }
             tau = val[RPT];
         }
@@ -237,22 +272,15 @@ __global__ __launch_bounds__(256) void k_tridiag(TriArgs a) {
             // tau = 0: the all-gather of p orders the reuse of the step buffers)
             double acc[CMAX];
 #pragma unroll
-            for (int c = 0; c < CMAX; ++c) acc[c] = 0.0;
+            for (int c = 0; c < CMAX; ++c) {
+                acc[c] = 0.0;
+                if (c >= cs && c < nc) {
 #pragma unroll
-            for (int q = 0; q < RPT; ++q) {
-                const int i = k + 1 + t + 256 * q;
-                if (i < m) {
-#pragma unroll
-                    for (int c = 0; c < CMAX; ++c)
-                        if (c >= cs && c < nc) acc[c] += slab[c * mr + i] * vr[q];
+                    for (int q = 0; q < RPT; ++q) acc[c] += slab[c * S + t + 256 * q] * vr[q];
                 }
             }
-#pragma unroll
-            for (int c = 0; c < CMAX; ++c)
-                if (c >= cs && c < nc) {
-                    const double sw = wave_sum(acc[c]);
-                    if ((t & 63) == 0) red2[c * 4 + (t >> 6)] = sw;
-                }
+            const double sw = wave_sum32(acc, lane);   // lane l: column l >> 1
+            if ((lane & 1) == 0) red2[(lane >> 1) * 4 + (t >> 6)] = sw;
             __syncthreads();
             if (t < 64) {
                 double pv = 0.0;
@@ -265,15 +293,15 @@ __global__ __launch_bounds__(256) void k_tridiag(TriArgs a) {
                 const double sp = wave_sum(pv);
                 if (t == 0) ll_put(xpart(M, par) + 2 * gb, sp, flag);
             }
-            // receive p (this thread's rows) and one per-block partial sum in one poll
+            // receive p (this thread's rows > k) and one per-block partial sum in one poll
             double pr[RPT];
             {
                 const uint64_t* w[RPT + 1];
                 double val[RPT + 1];
 #pragma unroll
                 for (int q = 0; q < RPT; ++q) {
-                    const int i = k + 1 + t + 256 * q;
-                    w[q] = (i < m) ? xp(M, par) + 2 * i : nullptr;
+                    const int i = t + 256 * q;
+                    w[q] = (i > k && i < m) ? xp(M, par) + 2 * i : nullptr;
                     val[q] = 0.0;
                 }
                 w[RPT] = (t < M.bpm) ? xpart(M, par) + 2 * t : nullptr;
@@ -296,29 +324,24 @@ __global__ __launch_bounds__(256) void k_tridiag(TriArgs a) {
                 wjs[t] = pjs[t] - cw * vs[c0 + t];
             }
             __syncthreads();
+            double wr[RPT];
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) wr[q] = pr[q] - cw * vr[q];
             int cfirst = cs;
             if (cn >= 0 && cn < nc) {
 #pragma unroll
-                for (int q = 0; q < RPT; ++q) {
-                    const int i = k + 1 + t + 256 * q;
-                    if (i < m) slab[cn * mr + i] -= vr[q] * wjs[cn] + (pr[q] - cw * vr[q]) * vjs[cn];
-                }
+                for (int q = 0; q < RPT; ++q) slab[cn * S + t + 256 * q] -= vr[q] * wjs[cn] + wr[q] * vjs[cn];
                 __syncthreads();
-                if (k + 3 < m) form_reflector(slab + cn * mr, k + 1, M, red);
+                if (k + 3 < m) form_reflector(slab + cn * S, k + 1, M, red);
                 cfirst = cn + 1;
             }
-            if (cfirst < nc) {
 #pragma unroll
-                for (int q = 0; q < RPT; ++q) {
-                    const int i = k + 1 + t + 256 * q;
-                    if (i < m) {
-                        const double vi = vr[q], wi = pr[q] - cw * vr[q];
+            for (int c = 0; c < CMAX; ++c)
+                if (c >= cfirst && c < nc) {
+                    const double wc = wjs[c], vc = vjs[c];
 #pragma unroll
-                        for (int c = 0; c < CMAX; ++c)
-                            if (c >= cfirst && c < nc) slab[c * mr + i] -= vi * wjs[c] + wi * vjs[c];
-                    }
+                    for (int q = 0; q < RPT; ++q) slab[c * S + t + 256 * q] -= vr[q] * wc + wr[q] * vc;
                 }
-            }
         }
         __syncthreads();
     }
@@ -326,10 +349,26 @@ __global__ __launch_bounds__(256) void k_tridiag(TriArgs a) {
     for (int c = 0; c < nc; ++c) {
         const int j = c0 + c;
         if (t == 0) {
-            if (j == m - 2 || (m == 1 && j == 0)) M.d[j] = slab[c * mr + j];
-            if (j == m - 1) M.d[j] = slab[c * mr + j];
-            if (j == m - 2) M.e[j] = slab[c * mr + j + 1];
+            if (j == m - 2 || (m == 1 && j == 0)) M.d[j] = slab[c * S + j];
+            if (j == m - 1) M.d[j] = slab[c * S + j];
+            if (j == m - 2) M.e[j] = slab[c * S + j + 1];
         }
+    }
+}
+
+// rows per thread of the launch: the smallest power of two with 256 RPT >= m
+static int tri_rpt(int m) {
+    int r = 1;
+    while (256 * r < m) r *= 2;
+    return r;
+}
+
+static const void* tri_kernel(int rpt) {
+    switch (rpt) {
+        case 1: return (const void*)k_tridiag<1>;
+        case 2: return (const void*)k_tridiag<2>;
+        case 4: return (const void*)k_tridiag<4>;
+        default: return (const void*)k_tridiag<8>;
     }
 }
 
@@ -994,6 +1033,7 @@ struct EigPlan {
     struct TriLaunch {
         std::vector<int> mats;   // indices into mats
         int cpb;                 // columns per workgroup (set by the largest m of the launch)
+        int rpt;                 // rows per thread (set by the largest m of the launch)
         size_t shbytes;
         int nblocks;
         TriArgs args;
@@ -1015,7 +1055,7 @@ struct EigPlan {
 };
 
 static int tri_cpb(int m, int maxsh) {
-    const int mr = (m + 63) & ~63;
+    const int mr = 256 * tri_rpt(m);   // stored rows per column
     int cpb = (int)((maxsh - 8192 - mr * 8) / ((size_t)mr * 8));
     return std::max(1, std::min(cpb, CMAX));
 }
@@ -1043,14 +1083,16 @@ EigPlan* eig_plan_create(const EigMat* mats, int nmat, size_t* work_bytes) {
     for (size_t q = 0; q < ord.size();) {
         EigPlan::TriLaunch L;
         const int m0 = mats[ord[q]].m;
-        const int mr = (m0 + 63) & ~63;
+        L.rpt = tri_rpt(m0);
+        const int mr = 256 * L.rpt;
         const int cpb0 = tri_cpb(m0, maxsh);
         L.cpb = cpb0;
         L.shbytes = (size_t)(cpb0 + 1) * mr * 8;
-        if (hipFuncSetAttribute((const void*)k_tridiag, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.shbytes) !=
+        const void* kf = tri_kernel(L.rpt);
+        if (hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.shbytes) !=
             hipSuccess) { delete P; return nullptr; }
         int occ = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_tridiag, 256, L.shbytes) != hipSuccess ||
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kf, 256, L.shbytes) != hipSuccess ||
             occ < 1) { delete P; return nullptr; }
         const int cap = occ * ncu;
         int blocks = 0;
@@ -1153,16 +1195,20 @@ hipError_t eig_plan_enqueue(const EigPlan* P, int* abort_w, hipStream_t st, bool
     for (const auto& L : P->tri) {
         TriArgs ta = L.args;
         ta.abort_w = abort_w;
-        if ((e = hipFuncSetAttribute((const void*)k_tridiag, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)L.shbytes)) != hipSuccess)
+        const void* kf = tri_kernel(L.rpt);
+        if ((e = hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.shbytes)) != hipSuccess)
             return e;
         if (cooperative) {
             void* args[] = {&ta};
-            if ((e = hipLaunchCooperativeKernel((const void*)k_tridiag, dim3(L.nblocks), dim3(256), args, L.shbytes,
-                                                st)) != hipSuccess)
+            if ((e = hipLaunchCooperativeKernel(kf, dim3(L.nblocks), dim3(256), args, L.shbytes, st)) != hipSuccess)
                 return e;
         } else {
-            hipLaunchKernelGGL(k_tridiag, dim3(L.nblocks), dim3(256), L.shbytes, st, ta);
+            switch (L.rpt) {
+                case 1: hipLaunchKernelGGL(k_tridiag<1>, dim3(L.nblocks), dim3(256), L.shbytes, st, ta); break;
+                case 2: hipLaunchKernelGGL(k_tridiag<2>, dim3(L.nblocks), dim3(256), L.shbytes, st, ta); break;
+                case 4: hipLaunchKernelGGL(k_tridiag<4>, dim3(L.nblocks), dim3(256), L.shbytes, st, ta); break;
+                default: hipLaunchKernelGGL(k_tridiag<8>, dim3(L.nblocks), dim3(256), L.shbytes, st, ta); break;
+            }
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
     }
