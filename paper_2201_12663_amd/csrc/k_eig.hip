@@ -207,6 +207,52 @@ __device__ __forceinline__ double wave_sum32(const double (&a)[32], int lane) {
     return b1 + __shfl_xor(b1, 1, WAVE);
 }
 
+// The owner of column k+1 at step k: applies the step's update to that column
+// (fixed row map, rows t + 256 q), accumulating the squares below row k+2 in
+// the same pass, then forms reflector k+1 from it and sends v_{k+1}, tau_{k+1}.
+template <int RPT>
+__device__ __forceinline__ void owner_step(double* col, int k, const TriMat& M, double* red, const double (&vr)[RPT],
+                                           const double (&wr)[RPT], double wc, double vc) {
+    const int t = threadIdx.x, m = M.m, j = k + 1;
+    double x[RPT], s = 0.0;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int i = t + 256 * q;
+        x[q] = col[i] - (vr[q] * wc + wr[q] * vc);
+        col[i] = x[q];
+        if (i > j + 1 && i < m) s += x[q] * x[q];
+    }
+    s = block_sum256(s, red);   // its barriers make col[j], col[j+1] visible
+    if (j + 2 >= m) return;      // no reflector follows (last 2 x 2 block)
+    const double alpha = col[j + 1];
+    double tau, beta, scal;
+    if (s == 0.0) {
+        tau = 0.0; beta = alpha; scal = 0.0;
+    } else {
+        const double nrm = sqrt(alpha * alpha + s);
+        beta = alpha >= 0.0 ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        scal = 1.0 / (alpha - beta);
+    }
+    const uint32_t flag = (uint32_t)j + 1;
+    uint64_t* vx = xv(M, j & 1);
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int i = t + 256 * q;
+        if (i > j && i < m) {
+            const double v = (i == j + 1) ? 1.0 : x[q] * scal;
+            ll_put(vx + 2 * i, v, flag);
+            M.G[i + (int64_t)j * M.ld] = v;
+        }
+    }
+    if (t == 0) {
+        ll_put(xtau(M, j & 1), tau, flag);
+        M.tau[j] = tau;
+        M.e[j] = beta;
+        M.d[j] = col[j];
+    }
+}
+
 // One-sided Householder tridiagonalization H^T G H = T, column-distributed:
 // step k broadcasts v_k, every block forms p_j = tau (G v)_j for its columns,
 // the p_j and the per-block sums of p_j v_j are all-gathered, and each block
@@ -219,20 +265,17 @@ __device__ __forceinline__ double wave_sum32(const double (&a)[32], int lane) {
 template <int RPT>
 __global__ __launch_bounds__(256) void k_tridiag(TriArgs a) {
     constexpr int S = RPT * 256;       // stored rows per column
-    extern __shared__ double slab[];   // cpb columns x S, then v (S)
+    extern __shared__ double slab[];   // cpb (< CMAX) columns x S
     __shared__ double red[4];
     __shared__ double red2[CMAX * 4];
     __shared__ double vjs[CMAX], wjs[CMAX], pjs[CMAX];
-    __shared__ double parts[256];
-    __shared__ double cw_s;
-    static_assert(CMAX == 32, "one butterfly reduction covers the 32 column slots");
+    static_assert(CMAX == 32, "one butterfly reduction covers 31 columns and the partial p.v");
     int q0 = 0;
     while (q0 + 1 < a.nmat && (int)blockIdx.x >= a.mat[q0 + 1].blk0) ++q0;
     const TriMat& M = a.mat[q0];
     const int gb = blockIdx.x - M.blk0;
     if (gb >= M.bpm) return;
     const int m = M.m, ld = M.ld, cpb = M.cpb;
-    double* vs = slab + (size_t)cpb * S;
     const int c0 = gb * cpb;
     const int nc = max(0, min(cpb, m - c0));
     const int t = threadIdx.x, lane = t & 63;
@@ -259,42 +302,44 @@ __global__ __launch_bounds__(256) void k_tridiag(TriArgs a) {
             ll_get<RPT + 1>(w, val, flag, a.abort_w);
 #pragma unroll
             for (int q = 0; q < RPT; ++q) {
+                const int i = t + 256 * q;
                 vr[q] = val[q];
-                vs[t + 256 * q] = vr[q];
+                if (i >= c0 && i < c0 + nc) vjs[i - c0] = vr[q];
             }
             tau = val[RPT];
         }
-        __syncthreads();   // vs
+        __syncthreads();   // vjs
         const int cs = max(0, k + 1 - c0);   // first local column with j > k
         const int cn = k + 1 - c0;           // local index of column k+1
         {
             // p_j = tau sum_i G[i,j] v_i for own columns j > k (exchanged even when
             // tau = 0: the all-gather of p orders the reuse of the step buffers)
+            // slot CMAX-1 carries this thread's part of sum_j (G v)_j v_j
             double acc[CMAX];
+            acc[CMAX - 1] = 0.0;
 #pragma unroll
-            for (int c = 0; c < CMAX; ++c) {
+            for (int c = 0; c < CMAX - 1; ++c) {
                 acc[c] = 0.0;
                 if (c >= cs && c < nc) {
 #pragma unroll
                     for (int q = 0; q < RPT; ++q) acc[c] += slab[c * S + t + 256 * q] * vr[q];
+                    acc[CMAX - 1] += acc[c] * vjs[c];
                 }
             }
-            const double sw = wave_sum32(acc, lane);   // lane l: column l >> 1
+            const double sw = wave_sum32(acc, lane);   // lane l: slot l >> 1
             if ((lane & 1) == 0) red2[(lane >> 1) * 4 + (t >> 6)] = sw;
             __syncthreads();
-            if (t < 64) {
-                double pv = 0.0;
-                if (t >= cs && t < nc) {
-                    const double pj = tau * ((red2[t * 4] + red2[t * 4 + 1]) + (red2[t * 4 + 2] + red2[t * 4 + 3]));
-                    ll_put(xp(M, par) + 2 * (c0 + t), pj, flag);
-                    pjs[t] = pj;
-                    pv = pj * vs[c0 + t];
-                }
-                const double sp = wave_sum(pv);
-                if (t == 0) ll_put(xpart(M, par) + 2 * gb, sp, flag);
+            if (t < nc && t >= cs) {
+                const double pj = tau * ((red2[t * 4] + red2[t * 4 + 1]) + (red2[t * 4 + 2] + red2[t * 4 + 3]));
+                ll_put(xp(M, par) + 2 * (c0 + t), pj, flag);
+                pjs[t] = pj;
+            }
+            if (t == 0) {
+                constexpr int P = (CMAX - 1) * 4;
+                ll_put(xpart(M, par) + 2 * gb, tau * ((red2[P] + red2[P + 1]) + (red2[P + 2] + red2[P + 3])), flag);
             }
             // receive p (this thread's rows > k) and one per-block partial sum in one poll
-            double pr[RPT];
+            double pr[RPT], partial = 0.0;
             {
                 const uint64_t* w[RPT + 1];
                 double val[RPT + 1];
@@ -309,30 +354,18 @@ __global__ __launch_bounds__(256) void k_tridiag(TriArgs a) {
                 ll_get<RPT + 1>(w, val, flag, a.abort_w);
 #pragma unroll
                 for (int q = 0; q < RPT; ++q) pr[q] = val[q];
-                if (t < M.bpm) parts[t] = val[RPT];
+                partial = val[RPT];
             }
-            __syncthreads();
-            if (t == 0) {
-                double s = 0.0;
-                for (int q = 0; q < M.bpm; ++q) s += parts[q];
-                cw_s = 0.5 * tau * s;
-            }
-            __syncthreads();
-            const double cw = cw_s;
-            if (t >= cs && t < nc) {
-                vjs[t] = vs[c0 + t];
-                wjs[t] = pjs[t] - cw * vs[c0 + t];
-            }
+            // the same sum, in the same order, in every workgroup of the matrix
+            const double cw = 0.5 * tau * block_sum256(partial, red);
+            if (t >= cs && t < nc) wjs[t] = pjs[t] - cw * vjs[t];
             __syncthreads();
             double wr[RPT];
 #pragma unroll
             for (int q = 0; q < RPT; ++q) wr[q] = pr[q] - cw * vr[q];
             int cfirst = cs;
             if (cn >= 0 && cn < nc) {
-#pragma unroll
-                for (int q = 0; q < RPT; ++q) slab[cn * S + t + 256 * q] -= vr[q] * wjs[cn] + wr[q] * vjs[cn];
-                __syncthreads();
-                if (k + 3 < m) form_reflector(slab + cn * S, k + 1, M, red);
+                owner_step<RPT>(slab + cn * S, k, M, red, vr, wr, wjs[cn], vjs[cn]);
                 cfirst = cn + 1;
             }
 #pragma unroll
@@ -1056,8 +1089,8 @@ struct EigPlan {
 
 static int tri_cpb(int m, int maxsh) {
     const int mr = 256 * tri_rpt(m);   // stored rows per column
-    int cpb = (int)((maxsh - 8192 - mr * 8) / ((size_t)mr * 8));
-    return std::max(1, std::min(cpb, CMAX));
+    int cpb = (int)((maxsh - 8192) / ((size_t)mr * 8));
+    return std::max(1, std::min(cpb, CMAX - 1));
 }
 
 EigPlan* eig_plan_create(const EigMat* mats, int nmat, size_t* work_bytes) {
@@ -1087,7 +1120,7 @@ EigPlan* eig_plan_create(const EigMat* mats, int nmat, size_t* work_bytes) {
         const int mr = 256 * L.rpt;
         const int cpb0 = tri_cpb(m0, maxsh);
         L.cpb = cpb0;
-        L.shbytes = (size_t)(cpb0 + 1) * mr * 8;
+        L.shbytes = (size_t)cpb0 * mr * 8;
         const void* kf = tri_kernel(L.rpt);
         if (hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.shbytes) !=
             hipSuccess) { delete P; return nullptr; }
