@@ -299,7 +299,7 @@ def main():
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--batch-warmup", type=int, default=1)
-    ap.add_argument("--batch-precision", default="fp32")
+    ap.add_argument("--batch-precision", default="bf16x3")
     ap.add_argument("--no-batch-fp64-baseline", dest="batch_fp64_baseline", action="store_false")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-precision-study", action="store_true")
