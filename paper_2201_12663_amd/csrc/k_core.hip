@@ -99,7 +99,8 @@ __device__ __forceinline__ void core_tile_std(int r1, int r2, int r3, int ld1, i
     constexpr int TM = 16 * NF, KC = 16;
     constexpr int PA = TM * KC / 256, AS = 256 / TM;   // A entries per thread, their k stride
     typedef typename MF<T>::acc_t acc_t;
-    __shared__ T sA[2][KC][TM];
+    // rows of sA padded by 64 bytes: the two k rows a half-wave reads fall 16 banks apart
+    __shared__ T sA[2][KC][TM + 64 / sizeof(T)];
     __shared__ T s2[2][KC][TN2];
     __shared__ T s3[2][KC][TN3];
     const int NT = N2T * N3T;
@@ -209,25 +210,30 @@ __device__ __forceinline__ void core_tile_bf16x3(int r1, int r2, int r3, int ld1
                                  const float* __restrict__ V3, const double* __restrict__ xip,
                                  O* __restrict__ beta, int N2T, int N3T, int64_t tile) {
     constexpr int TM = 16 * NF;
-    constexpr int PA = TM * BKC / 256, AS = 256 / TM;   // A entries per thread, their k stride
+    constexpr int PA = TM * BKC / 256;   // A entries per thread: PA consecutive k of one row
+    static_assert(PA % 8 == 0, "A is staged in 16-byte groups of 8 bf16");
+    // rows of s2/s3 are padded to 18 floats: the k rows that one half-wave reads
+    // (8 apart) then fall 16 banks apart
+    constexpr int VLD = TN2 + 2;
     __shared__ __attribute__((aligned(16))) __bf16 sAh[2][TM * BLDA];
     __shared__ __attribute__((aligned(16))) __bf16 sAl[2][TM * BLDA];
-    __shared__ float s2[2][BKC][TN2];
-    __shared__ float s3[2][BKC][TN3];
+    __shared__ float s2[2][BKC][VLD];
+    __shared__ float s3[2][BKC][VLD];
     const int NT = N2T * N3T;
     const int mt = (int)(tile / NT), nt = (int)(tile % NT);
     const int n3t = nt / N2T, n2t = nt % N2T;
     const int m0 = mt * TM, b2 = n2t * TN2, b3 = n3t * TN3;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
 
-    // staging: A TM x 32 (PA per thread), V2/V3 32 x 16 (2 each)
-    const int ai = t % TM, ak = t / TM;            // k = ak + AS q
+    // staging: A TM x 32 (row ai, k = ak .. ak + PA - 1 per thread, written to LDS
+    // as 16-byte groups), V2/V3 32 x 16 (2 each)
+    const int ai = t % TM, ak = (t / TM) * PA;
     const int vi = t & 15, vk = t >> 4;            // k = vk, vk + 16
     float ra[PA], rv2[2], rv3[2];
     auto gload = [&](int64_t k0) {
 #pragma unroll
         for (int q = 0; q < PA; ++q) {
-            const int64_t k = k0 + ak + AS * q;
+            const int64_t k = k0 + ak + q;
             ra[q] = V1[(int64_t)(m0 + ai) + k * ld1] * (float)xip[k];
         }
 #pragma unroll
@@ -238,11 +244,17 @@ __device__ __forceinline__ void core_tile_bf16x3(int r1, int r2, int r3, int ld1
     };
     auto lstore = [&](int buf) {
 #pragma unroll
-        for (int q = 0; q < PA; ++q) {
-            __bf16 h, l;
-            split_bf16(ra[q], h, l);
-            sAh[buf][ai * BLDA + ak + AS * q] = h;
-            sAl[buf][ai * BLDA + ak + AS * q] = l;
+        for (int g8 = 0; g8 < PA / 8; ++g8) {
+            bf8_t h8, l8;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                __bf16 h, l;
+                split_bf16(ra[8 * g8 + e], h, l);
+                h8[e] = h;
+                l8[e] = l;
+            }
+            *reinterpret_cast<bf8_t*>(&sAh[buf][ai * BLDA + ak + 8 * g8]) = h8;
+            *reinterpret_cast<bf8_t*>(&sAl[buf][ai * BLDA + ak + 8 * g8]) = l8;
         }
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
