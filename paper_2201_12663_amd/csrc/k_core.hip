@@ -199,10 +199,19 @@ __global__ __launch_bounds__(256) void k_core_std(int r1, int r2, int r3, int ld
 // ---------------------------------------------------------------------------
 constexpr int BKC = 32, BLDA = BKC + 8;   // bf16 elements per LDS row of A
 
-__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
-    hi = (__bf16)x;
-    lo = (__bf16)(x - (float)hi);
+typedef float f2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 b2_t __attribute__((ext_vector_type(2)));
+union bf8_pairs {
+    bf8_t v;
+    b2_t p[4];
+};
+
+// two values at once: hi = bf16(x), lo = bf16(x - hi) (packed conversions)
+__device__ __forceinline__ void split2(f2_t x, b2_t& hi, b2_t& lo) {
+    hi = __builtin_convertvector(x, b2_t);
+    lo = __builtin_convertvector(x - __builtin_convertvector(hi, f2_t), b2_t);
 }
+
 
 template <typename O, bool FLUSH, int NF>
 __device__ __forceinline__ void core_tile_bf16x3(int r1, int r2, int r3, int ld1, int ld2, int ld3, int64_t Kp,
@@ -215,10 +224,12 @@ __device__ __forceinline__ void core_tile_bf16x3(int r1, int r2, int r3, int ld1
     // rows of s2/s3 are padded to 18 floats: the k rows that one half-wave reads
     // (8 apart) then fall 16 banks apart
     constexpr int VLD = TN2 + 2;
+    // s3 rows: 20 floats, so that a wave reads its 4 j3 values of a k row as one 16-byte load
+    constexpr int VLD3 = TN3 + 4;
     __shared__ __attribute__((aligned(16))) __bf16 sAh[2][TM * BLDA];
     __shared__ __attribute__((aligned(16))) __bf16 sAl[2][TM * BLDA];
     __shared__ float s2[2][BKC][VLD];
-    __shared__ float s3[2][BKC][VLD];
+    __shared__ __attribute__((aligned(16))) float s3[2][BKC][VLD3];
     const int NT = N2T * N3T;
     const int mt = (int)(tile / NT), nt = (int)(tile % NT);
     const int n3t = nt / N2T, n2t = nt % N2T;
@@ -245,16 +256,12 @@ __device__ __forceinline__ void core_tile_bf16x3(int r1, int r2, int r3, int ld1
     auto lstore = [&](int buf) {
 #pragma unroll
         for (int g8 = 0; g8 < PA / 8; ++g8) {
-            bf8_t h8, l8;
+            bf8_pairs h8, l8;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                __bf16 h, l;
-                split_bf16(ra[8 * g8 + e], h, l);
-                h8[e] = h;
-                l8[e] = l;
-            }
-            *reinterpret_cast<bf8_t*>(&sAh[buf][ai * BLDA + ak + 8 * g8]) = h8;
-            *reinterpret_cast<bf8_t*>(&sAl[buf][ai * BLDA + ak + 8 * g8]) = l8;
+            for (int e = 0; e < 4; ++e)
+                split2(f2_t{ra[8 * g8 + 2 * e], ra[8 * g8 + 2 * e + 1]}, h8.p[e], l8.p[e]);
+            *reinterpret_cast<bf8_t*>(&sAh[buf][ai * BLDA + ak + 8 * g8]) = h8.v;
+            *reinterpret_cast<bf8_t*>(&sAl[buf][ai * BLDA + ak + 8 * g8]) = l8.v;
         }
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
@@ -281,19 +288,19 @@ __device__ __forceinline__ void core_tile_bf16x3(int r1, int r2, int r3, int ld1
         const int buf = (int)(c & 1);
         if (c + 1 < nchunk) gload((c + 1) * BKC);
         // B fragments: 8 k values of column (j2 = lane%16, j3 = 4w+g), split hi/lo
-        bf8_t bh[4], bl[4];
+        bf8_pairs bh[4], bl[4];
         float v2[8];
+        f4_t v3[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) v2[e] = s2[buf][kg + e][lane & 15];
+        for (int e = 0; e < 8; ++e) {
+            v2[e] = s2[buf][kg + e][lane & 15];
+            v3[e] = *reinterpret_cast<const f4_t*>(&s3[buf][kg + e][4 * w]);
+        }
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                __bf16 h, l;
-                split_bf16(v2[e] * s3[buf][kg + e][4 * w + g], h, l);
-                bh[g][e] = h;
-                bl[g][e] = l;
-            }
+            for (int e = 0; e < 4; ++e)
+                split2(f2_t{v2[2 * e] * v3[2 * e][g], v2[2 * e + 1] * v3[2 * e + 1][g]}, bh[g].p[e], bl[g].p[e]);
         }
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
@@ -302,9 +309,9 @@ __device__ __forceinline__ void core_tile_bf16x3(int r1, int r2, int r3, int ld1
             const bf8_t al = *reinterpret_cast<const bf8_t*>(&sAl[buf][row * BLDA + kg]);
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
-                acc[f][g] = mfma_bf16(ah, bh[g], acc[f][g]);
-                acc[f][g] = mfma_bf16(ah, bl[g], acc[f][g]);
-                acc[f][g] = mfma_bf16(al, bh[g], acc[f][g]);
+                acc[f][g] = mfma_bf16(ah, bh[g].v, acc[f][g]);
+                acc[f][g] = mfma_bf16(ah, bl[g].v, acc[f][g]);
+                acc[f][g] = mfma_bf16(al, bh[g].v, acc[f][g]);
             }
         }
         if constexpr (FLUSH) {
