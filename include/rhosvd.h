@@ -70,7 +70,8 @@ typedef struct {
                                 double, halving its size; meant for the FP32 and BF16x3 cores.
                                 When R (padded to 64) exceeds 8192 these cores add their
                                 partial sums over each 8192 terms into beta, in float here */
-    int32_t refine_tails;    /* nonzero (rhosvd_reduce): after the Gram-route cut r, with
+    int32_t refine_tails;    /* 0, 1 or 2 (rhosvd_reduce; other values: RHOSVD_ERR_ARG).
+                                1: after the Gram-route cut r, with
                                 Z_p the leading p = min(m, r + r/8 + 16) eigenvectors and
                                 V_p = Z_p^T U~, the cut is taken again on the tails
                                 t_r^2 = sum_{r<=k<p} |V_p[k,:]|^2 + |U~ - Z_p V_p|_F^2
@@ -79,7 +80,19 @@ typedef struct {
                                 small eigenvalues carry FP64 noise of about u |G|; where
                                 tau^2 lies below that floor the refined ranks are the
                                 smaller, still certified ones (Theorem 2.3); the
-                                spectrum then holds |V_p[k,:]| for k < p. */
+                                spectrum then holds |V_p[k,:]| for k < p.
+                                2 (n <= R; when R < n it acts as 1): a deflated second
+                                Gram pass.  With Z_k the leading k eigenvectors of the
+                                first pass whose singular values are >= 2^-13 sigma_1
+                                (k < r), U'' = (I - Z_k Z_k^T)^2 U~ is formed in FP64 and
+                                its Gram eigendecomposed again; its spectrum resolves
+                                values down to about u^(1/2) sigma_(k+1) instead of
+                                u^(1/2) sigma_1.  The cut is taken on that spectrum with
+                                the same tau, r = k + r'; Z = [Z_k, Z'] with Z' the leading
+                                r' deflated eigenvectors projected once more against Z_k;
+                                the spectrum reported is sigma_1..k of the first pass
+                                followed by the deflated one, the tails those of U''.
+                                Costs one more Gram, eigensolve and two projections. */
     int32_t core_tile;       /* rows of j1 per workgroup tile of the FP32 / BF16x3 core: 64 or
                                 128; 0 (default): chosen by the library's autotuner, which
                                 times both on the first core of each shape class (precision,

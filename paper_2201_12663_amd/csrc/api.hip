@@ -72,6 +72,10 @@ struct rhosvd_ctx {
     double* Z[3] = {};                   // n_pad x zr_pad
     void* V[3] = {};                     // zr_pad x R_pad (FP64 or FP32)
     double* Vref[3] = {};                // refine_tails with a mixed core: FP64 projection
+    double* Ud[3] = {};                  // refine_tails = 2: deflated side matrices (n_pad x R_pad)
+    double* Zs[3] = {};                  //   second-pass vectors before re-orthogonalization (n_pad x zr_pad)
+    double* Cz[3] = {};                  //   Z_k^T Z' (zr_pad x zr_pad)
+    double* dscr = nullptr;              //   first-pass spectrum, second-pass spectrum and tails
     double* rpart[3] = {};               // refine_tails: residual partial sums
     double* rfloor = nullptr;            // refine_tails: squared residuals (3)
     int vprec = 0;
@@ -141,6 +145,7 @@ rhosvd_status check_options(const rhosvd_options* o, std::string& msg) {
     if (o->precision < 0 || o->precision > 2) { msg = "unknown precision"; return RHOSVD_ERR_ARG; }
     for (int i = 0; i < 2; ++i)
         if (o->reserved[i] != 0) { msg = "reserved option fields must be zero"; return RHOSVD_ERR_ARG; }
+    if (o->refine_tails < 0 || o->refine_tails > 2) { msg = "refine_tails must be 0, 1 or 2"; return RHOSVD_ERR_ARG; }
     if (o->core_tile != 0 && !core_tile_valid(o->precision, o->core_tile)) {
         msg = "core_tile must be 0 (tuned), 64, or 128 (128 only for the FP32 and BF16x3 cores)";
         return RHOSVD_ERR_ARG;
@@ -193,9 +198,14 @@ size_t carve_all(rhosvd_ctx* h, char* base) {
     }
     for (int l = 0; l < 3; ++l) {
         const bool refine = h->opt.refine_tails != 0;
+        const bool deflate = h->opt.refine_tails == 2 && !h->rside;
         h->Vref[l] = (refine && esz == 4) ? c.take<double>((size_t)zp * Rp) : nullptr;
         h->rpart[l] = refine ? c.take<double>((size_t)(np / 64) * (Rp / 64)) : nullptr;
+        h->Ud[l] = deflate ? c.take<double>((size_t)np * Rp) : nullptr;
+        h->Zs[l] = deflate ? c.take<double>((size_t)np * zp) : nullptr;
+        h->Cz[l] = deflate ? c.take<double>((size_t)zp * zp) : nullptr;
     }
+    h->dscr = (h->opt.refine_tails == 2 && !h->rside) ? c.take<double>((size_t)9 * (h->m_pad + 64)) : nullptr;
     h->rfloor = c.take<double>(4);
     h->xip = c.take<double>(Rp);
     h->flags = c.take<int>(16);
@@ -406,6 +416,101 @@ rhosvd_status form_z_rside(rhosvd_ctx* h) {
     return RHOSVD_OK;
 }
 
+// refine_tails = 2 (n <= R): a second, deflated Gram pass.  The leading k_l
+// eigenvectors of the first pass (sigma >= 2^-13 sigma_1, where the FP64 Gram
+// route is accurate) form Z_k; the side matrix is deflated twice,
+// U'' = (I - Z_k Z_k^T)^2 U~, so that its Gram has norm ~sigma_{k+1}^2 and
+// resolves singular values down to ~u^(1/2) sigma_{k+1} instead of ~u^(1/2)
+// sigma_1.  The cut is taken on the deflated spectrum with the same tau (the
+// tails of U~ beyond Z_k are those of U''); Z = [Z_k, Z'] with Z' the leading
+// deflated eigenvectors, projected once more against Z_k.
+rhosvd_status deflate_pass(rhosvd_ctx* h, double eps) {
+    hipStream_t st = h->stream;
+    const int64_t np = h->n_pad, Rp = h->R_pad, mp = h->m_pad, zp = h->zr_pad;
+    const int m = (int)h->m;
+    std::vector<double> sg((size_t)3 * m);
+    for (int l = 0; l < 3; ++l)
+        CK(h, hipMemcpyAsync(sg.data() + (size_t)l * m, h->sigma[l], (size_t)m * 8, hipMemcpyDeviceToHost, st));
+    CK(h, hipStreamSynchronize(st));
+    int k[3];
+    double *sig1[3], *sig2[3], *tl2[3];
+    for (int l = 0; l < 3; ++l) {
+        const double s1 = sg[(size_t)l * m];
+        int kk = 0;
+        while (kk < m && sg[(size_t)l * m + kk] >= s1 * 0x1p-13) ++kk;
+        k[l] = std::max(0, std::min(kk, h->ranks[l] - 1));
+        sig1[l] = h->dscr + (size_t)l * 3 * (mp + 64);
+        sig2[l] = sig1[l] + (mp + 64);
+        tl2[l] = sig2[l] + (mp + 64);
+        CK(h, hipMemcpyAsync(sig1[l], h->sigma[l], (size_t)m * 8, hipMemcpyDeviceToDevice, st));
+    }
+    // Z_k from the first pass (its Householder vectors are still in G)
+    BtJob jobs[3];
+    for (int l = 0; l < 3; ++l) {
+        CK(h, hipMemsetAsync(h->Z[l], 0, (size_t)np * zp * 8, st));
+        jobs[l] = BtJob{m, (int)mp, h->G[l], h->htau[l], h->W[l], h->order[l], k[l], nullptr, h->Z[l], (int)np,
+                        (int)np, h->Tw[l]};
+    }
+    CK(h, launch_backtransform(jobs, 3, st));
+    int kp[3];
+    for (int l = 0; l < 3; ++l) {
+        kp[l] = (int)round_up(std::max(k[l], 1), 64);
+        double* V64 = h->vprec == RHOSVD_FP64 ? (double*)h->V[l] : h->Vref[l];
+        CK(h, launch_project(np, Rp, kp[l], h->Z[l], h->Ut[l], V64, nullptr, st));
+        CK(h, launch_residual(np, Rp, kp[l], h->Z[l], V64, h->Ut[l], h->Ud[l], st));
+        CK(h, launch_project(np, Rp, kp[l], h->Z[l], h->Ud[l], V64, nullptr, st));
+        CK(h, launch_residual(np, Rp, kp[l], h->Z[l], V64, h->Ud[l], h->Ud[l], st));
+    }
+    // the deflated Grams through the same eigensolver plan (same buffers)
+    CK(h, launch_gram_nt(np, Rp, h->Ud, h->G, h->gram_part, h->gram_splits, st));
+    CK(h, eig_plan_enqueue(h->plan[0], h->flags + 2, st));
+    TruncArgs ta{};
+    for (int l = 0; l < 3; ++l) {
+        ta.lam[l] = h->lam[l];
+        ta.sigma[l] = h->sigma[l];
+        ta.order[l] = h->order[l];
+        ta.tails[l] = h->tails[l];
+    }
+    ta.m = m;
+    ta.m_pad = (int)mp;
+    ta.n = (int)h->n;
+    ta.n_pad = (int)np;
+    ta.xip = h->xip;
+    ta.R_pad = Rp;
+    ta.anorm_part = h->anorm_part;
+    ta.anorm_ntiles = h->anorm_ntiles;
+    ta.eps = eps;
+    ta.ranks = h->ranks_dev;
+    ta.scal = h->scal;
+    CK(h, launch_truncate(ta, st));
+    CK(h, hipMemcpyAsync(h->host, h->ranks_dev, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
+    CK(h, hipMemcpyAsync(h->host + 6, h->flags + 2, sizeof(int), hipMemcpyDeviceToHost, st));
+    CK(h, hipStreamSynchronize(st));
+    if (h->host[6]) return fail(h, RHOSVD_ERR_DEVICE, "eigensolver: a cross-workgroup wait ran out");
+    for (int l = 0; l < 3; ++l) {
+        const int r2 = std::max(1, std::min(h->host[l], m - k[l]));
+        // combined spectrum and tails
+        CK(h, hipMemcpyAsync(sig2[l], h->sigma[l], (size_t)m * 8, hipMemcpyDeviceToDevice, st));
+        CK(h, hipMemcpyAsync(tl2[l], h->tails[l], (size_t)(m + 1) * 8, hipMemcpyDeviceToDevice, st));
+        CK(h, launch_combine_spectrum(k[l], m, sig1[l], sig2[l], tl2[l], h->sigma[l], h->tails[l], st));
+        // Z' = the leading r2 deflated eigenvectors, projected against Z_k once more
+        CK(h, hipMemsetAsync(h->Zs[l], 0, (size_t)np * zp * 8, st));
+        BtJob jb{m, (int)mp, h->G[l], h->htau[l], h->W[l], h->order[l], r2, nullptr, h->Zs[l], (int)np, (int)np,
+                 h->Tw[l]};
+        CK(h, launch_backtransform(&jb, 1, st));
+        CK(h, launch_project(np, zp, kp[l], h->Z[l], h->Zs[l], h->Cz[l], nullptr, st));
+        CK(h, launch_residual(np, zp, kp[l], h->Z[l], h->Cz[l], h->Zs[l], h->Zs[l], st));
+        CK(h, hipMemcpyAsync(h->Z[l] + (int64_t)k[l] * np, h->Zs[l], (size_t)r2 * np * 8, hipMemcpyDeviceToDevice,
+                             st));
+        const int r = k[l] + r2;
+        CK(h, launch_sign_cols((int)h->n, (int)np, r, h->Z[l], st));
+        h->ranks[l] = r;
+        h->r_pad[l] = (int)round_up(r, RPAD_CORE);
+        if (zp > r) CK(h, hipMemsetAsync(h->Z[l] + (int64_t)r * np, 0, (size_t)(zp - r) * np * 8, st));
+    }
+    return RHOSVD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -548,8 +653,15 @@ rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R, const double*
         h->ranks[l] = h->host[l];
         h->r_pad[l] = (int)round_up(h->ranks[l] > 0 ? h->ranks[l] : 1, RPAD_CORE);
     }
-    // refine_tails: Z and V first at the wider p_l = min(m, r + r/8 + 16)
-    const bool refine = h->opt.refine_tails != 0 && h->ranks[0] > 0;
+    // refine_tails = 2: the deflated second pass forms Z itself
+    bool z_done = false;
+    if (h->opt.refine_tails == 2 && !h->rside && h->ranks[0] > 0) {
+        rhosvd_status ds = deflate_pass(h, eps);
+        if (ds != RHOSVD_OK) return ds;
+        z_done = true;
+    }
+    // refine_tails = 1: Z and V first at the wider p_l = min(m, r + r/8 + 16)
+    const bool refine = (h->opt.refine_tails == 1 || (h->opt.refine_tails == 2 && h->rside)) && h->ranks[0] > 0;
     int p_ref[3] = {0, 0, 0};
     if (refine)
         for (int l = 0; l < 3; ++l) {
@@ -558,7 +670,8 @@ rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R, const double*
             h->r_pad[l] = (int)round_up(p_ref[l], RPAD_CORE);
         }
     // a5/a6: Z and the projections V = Z^T U~ (FP64 MFMA; rounded to FP32 for the mixed core)
-    if (!h->rside) {
+    if (z_done) {
+    } else if (!h->rside) {
         // Z = H W[:, order[0..r-1]]: back-transformed eigenvectors, sign rule, zero padding
         BtJob jobs[3];
         for (int l = 0; l < 3; ++l)

@@ -626,6 +626,39 @@ __global__ __launch_bounds__(256) void k_resid_partials(int64_t n_pad, int64_t R
     if (threadIdx.x == 0) part[tm + tn * (n_pad / T64)] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// out = T - Q B (n_pad x N_pad, ld n_pad): Q n_pad x p_pad (ld n_pad), B p_pad x
+// N_pad (ld p_pad).  Each block reads and writes only its own 64 x 64 tile of T
+// and out, so out may be T.
+__global__ __launch_bounds__(256) void k_residual(int64_t n_pad, int64_t p_pad, const double* __restrict__ Q,
+                                                  const double* __restrict__ B, const double* T, double* out) {
+    __shared__ double sA[KC * LDS_STRIDE];
+    __shared__ double sB[KC * LDS_STRIDE];
+    const int64_t tn = blockIdx.x, tm = blockIdx.y;
+    d4_t acc[2][2];
+    zero_acc(acc);
+    tile64_f64<false, true>(Q, n_pad, B, p_pad, tm * T64, tn * T64, 0, p_pad, sA, sB, acc);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t r = tm * T64 + wr + a * 16 + c_row64(lane, i);
+                const int64_t c = tn * T64 + wc + b * 16 + c_col(lane);
+                out[r + c * n_pad] = T[r + c * n_pad] - acc[a][b][i];
+            }
+}
+
+hipError_t launch_residual(int64_t n_pad, int64_t N_pad, int64_t p_pad, const double* Q, const double* B,
+                           const double* T, double* out, hipStream_t st) {
+    if (n_pad % T64 || N_pad % T64 || p_pad % KC) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_residual, dim3((unsigned)(N_pad / T64), (unsigned)(n_pad / T64)), dim3(256), 0, st, n_pad,
+                       p_pad, Q, B, T, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_resid_partials(int64_t n_pad, int64_t R_pad, int64_t p_pad, const double* Q, const double* B,
                                  const double* Ut, double* part, hipStream_t st) {
     if (n_pad % T64 || R_pad % T64 || p_pad % KC) return hipErrorInvalidValue;

@@ -164,3 +164,29 @@ hipError_t launch_truncate_b(const BProb* P, int np, hipStream_t st) {
     hipLaunchKernelGGL(k_status_b, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, P, np);
     return hipGetLastError();
 }
+
+namespace {
+// Spectrum and tails of a deflated reduction: the first k singular values from
+// the first pass (sig1), then those of the deflated side matrix (sig2, tails2
+// over its own index).  tails[i] for i >= k is tails2[i - k]; below k the first
+// pass values are added: tails[i]^2 = sum_{i <= j < k} sig1[j]^2 + tails2[0]^2.
+__global__ void k_combine_spectrum(int k, int m, const double* __restrict__ sig1, const double* __restrict__ sig2,
+                                   const double* __restrict__ tails2, double* __restrict__ sigma,
+                                   double* __restrict__ tails) {
+    for (int i = threadIdx.x; i < m; i += blockDim.x) sigma[i] = i < k ? sig1[i] : sig2[i - k];
+    for (int i = k + threadIdx.x; i <= m; i += blockDim.x) tails[i] = tails2[i - k];
+    if (threadIdx.x == 0) {
+        double s = tails2[0] * tails2[0];
+        for (int i = k - 1; i >= 0; --i) {
+            s += sig1[i] * sig1[i];
+            tails[i] = sqrt(s);
+        }
+    }
+}
+}  // namespace
+
+hipError_t launch_combine_spectrum(int k, int m, const double* sig1, const double* sig2, const double* tails2,
+                                   double* sigma, double* tails, hipStream_t st) {
+    hipLaunchKernelGGL(k_combine_spectrum, dim3(1), dim3(256), 0, st, k, m, sig1, sig2, tails2, sigma, tails);
+    return hipGetLastError();
+}

@@ -40,6 +40,13 @@ hipError_t launch_resid_partials(int64_t n_pad, int64_t R_pad, int64_t p_pad, co
 // Generic FP64 MFMA GEMM on padded operands, C = alpha A B (col-major C).
 //   a_kcontig: A(i,k) = A[k + i*lda], else A[i + k*lda]
 //   b_kcontig: B(k,j) = B[k + j*ldb], else B[j + k*ldb]
+// out = T - Q B (n_pad x N_pad, ld n_pad; Q n_pad x p_pad ld n_pad; B p_pad x N_pad
+// ld p_pad); out may be T
+hipError_t launch_residual(int64_t n_pad, int64_t N_pad, int64_t p_pad, const double* Q, const double* B,
+                           const double* T, double* out, hipStream_t st);
+// deflated spectrum: sigma = [sig1[0..k), sig2[0..m-k)], tails from tails2 plus sig1
+hipError_t launch_combine_spectrum(int k, int m, const double* sig1, const double* sig2, const double* tails2,
+                                   double* sigma, double* tails, hipStream_t st);
 hipError_t launch_gemm64(bool a_kcontig, bool b_kcontig, int64_t M, int64_t N, int64_t K, const double* A,
                          int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc, double alpha,
                          hipStream_t st);

@@ -157,7 +157,7 @@ class Reducer:
         self.opt = Options()
         self.opt.core_tile = int(core_tile)
         self.opt.beta_fp32 = 1 if beta_fp32 else 0
-        self.opt.refine_tails = 1 if refine_tails else 0
+        self.opt.refine_tails = int(refine_tails) if refine_tails in (0, 1, 2) else -1
         self.beta_dtype = torch.float32 if beta_fp32 else torch.float64
         self.opt.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self.opt.max_eig_sweeps = int(max_eig_sweeps)

@@ -55,14 +55,14 @@ def had(orc):
     yield S
 
 
-def run(prec, eps):
-    key = (prec, eps)
+def run(prec, eps, refine=0):
+    key = (prec, eps, refine)
     if key not in S.runs:
         import torch
         from paper_2201_12663_amd import rhosvd
-        _flush(f"hadamard reduce {prec} eps={eps}")
+        _flush(f"hadamard reduce {prec} eps={eps} refine_tails={refine}")
         U, xi = S.dev
-        red = rhosvd.Reducer(precision=prec)
+        red = rhosvd.Reducer(precision=prec, refine_tails=refine)
         ranks = red.reduce(U[0], U[1], U[2], xi, eps)
         res = red.get()
         spec = [red.spectrum(l) for l in range(3)]
@@ -139,3 +139,51 @@ def test_hadamard_mixed_cores(orc, had, prec, eps):
     else:
         assert db <= 2.0 ** -17 * a
         assert err <= (eps + (1e-6 if eps >= 1e-4 else 2.0 ** -17)) * a
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("eps", EPS)
+def test_hadamard_deflated_second_pass(orc, had, eps, prec):
+    """refine_tails = 2: Z_k (singular values >= 2^-13 sigma_1) from the first
+    pass, the side matrix deflated twice and its Gram eigendecomposed again.  The
+    second pass's noise is ~u sigma_(k+1)^2 instead of ~u sigma_1^2, so at
+    eps = 1e-6, where the plain Gram route's cut is lost in its noise, the ranks
+    are the oracle's wherever the margin measured against sigma_(k+1) allows; Z
+    is orthonormal, the error is the certified one and close to the oracle's."""
+    gold = had.gold
+    case = gold["cases"][EPS.index(eps)]
+    ci = had.ci
+    g = run(prec, eps, refine=2)
+    rep = g["report"]
+    for l in range(3):
+        so = np.array(gold["sigma"][l])
+        s1 = so[0]
+        k = min(int(np.sum(so >= s1 * 2.0 ** -13)), case["ranks"][l] - 1)
+        sp = g["spectra"][l]
+        # sigma_1..k are the first pass's, the rest the deflated pass's
+        d2 = np.abs(sp[:k] ** 2 - so[:k] ** 2)
+        assert np.all(d2 <= gc.eig_tol(ci.n, ci.R) * s1 ** 2), (l, d2.max() / s1 ** 2)
+        tails = np.sqrt(np.concatenate([np.cumsum((so ** 2)[::-1])[::-1], [0.0]]))
+        ok = gc.cut_margin_ok(tails, case["ranks"][l], case["tau"], so[k])
+        _flush(f"mode {l}: k={k}, rank {g['ranks'][l]} (oracle {case['ranks'][l]}), margin ok {ok}")
+        if ok:
+            assert g["ranks"][l] == case["ranks"][l], (l, g["ranks"], case["ranks"])
+        else:
+            assert g["ranks"][l] >= case["ranks"][l] - 2
+        Z = g["Z"][l]
+        assert Z.shape[1] == g["ranks"][l]
+        assert np.max(np.abs(Z.T @ Z - np.eye(Z.shape[1]))) <= 1e-12
+    err = orc.error_dense(had.A, g["beta"], g["Z"])
+    _flush(f"{prec} deflated eps={eps}: ranks {g['ranks']} (oracle {case['ranks']}) rel err "
+           f"{err / gold['a_norm']:.3e} (oracle {case['error'] / gold['a_norm']:.3e}) "
+           f"bound {rep['bound'] / gold['a_norm']:.3e}")
+    core = 0.0 if prec == "fp64" else 2e-6 * gold["a_norm"]
+    assert err <= rep["bound"] * (1 + 1e-9) + core
+    assert rep["bound"] <= eps * gold["a_norm"] * (1 + 1e-9)
+    if prec == "fp64" and tuple(g["ranks"]) == tuple(case["ranks"]):
+        assert abs(err - case["error"]) <= 1e-3 * case["error"]
+    if prec == "fp32":
+        g64 = run("fp64", eps, refine=2)
+        assert g["ranks"] == g64["ranks"]
+        for l in range(3):
+            assert np.array_equal(g["Z"][l], g64["Z"][l])

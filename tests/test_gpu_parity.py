@@ -223,15 +223,17 @@ def test_full_size_newton1024_mixed(orc, prec):
     assert err <= (ci.eps + 1e-6) * a
 
 
+@pytest.mark.parametrize("refine", [1, 2])
 @pytest.mark.parametrize("prec,shape", [("fp64", (512, 1024, 1e-5)), ("fp32", (512, 1024, 1e-5)),
                                         ("fp64", (256, 2048, 1e-6)), ("fp32", (512, 2048, 1e-6))])
-def test_refined_tails_recover_the_oracle_ranks(orc, prec, shape):
+def test_refined_tails_recover_the_oracle_ranks(orc, prec, shape, refine):
     """Smooth low-rank inputs: where the sum of the Gram route's noise eigenvalues
     (about u |G| each) exceeds tau^2 its ranks come out above the oracle's; with
     refine_tails the cut uses tails formed from V and the exact residual and lands
     on the oracle's ranks, with orthonormal Z, beta the exact core of Z and the
     error within the bound.  (Below tau^2 ~ u |G| itself the Gram route's vectors
-    near the cut are inaccurate and no refinement of its cut can recover them.)"""
+    near the cut are inaccurate and no refinement of its cut can recover them;
+    refine_tails = 2, the deflated second pass, is meant for that case.)"""
     import torch
     from paper_2201_12663_amd import rhosvd
     n, R, eps = shape
@@ -241,12 +243,12 @@ def test_refined_tails_recover_the_oracle_ranks(orc, prec, shape):
     U = [rhosvd.to_device(u) for u in ci.U]
     xd = torch.from_numpy(ci.xi).cuda()
     plain = rhosvd.Reducer(precision=prec)
-    ref = rhosvd.Reducer(precision=prec, refine_tails=True)
+    ref = rhosvd.Reducer(precision=prec, refine_tails=refine)
     rp = plain.reduce(U[0], U[1], U[2], xd, ci.eps)
     rr = ref.reduce(U[0], U[1], U[2], xd, ci.eps)
     res = ref.get()
     torch.cuda.synchronize()
-    print("oracle", o.ranks, "gram route", rp, "refined", rr, flush=True)
+    print("oracle", o.ranks, "gram route", rp, f"refined ({refine})", rr, flush=True)
     for l in range(3):
         assert abs(rr[l] - o.ranks[l]) <= 2, (rr, o.ranks)
         assert rr[l] <= rp[l]
@@ -283,3 +285,52 @@ def test_refined_tails_keep_accurate_gram_ranks(orc):
         assert abs(rb[l] - ra[l]) <= 1 and abs(rb[l] - o.ranks[l]) <= 1
     a.close()
     b.close()
+
+
+def test_deflated_pass_on_rank_one_and_on_the_r_side(orc):
+    """refine_tails = 2 edge cases: a rank-1 tensor (k = 0, nothing deflated, the
+    second pass repeats the first: same ranks and Z), and R < n, where the option
+    acts as refine_tails = 1."""
+    import torch
+    from paper_2201_12663_amd import rhosvd
+    rng = np.random.default_rng(41)
+    n, R = 96, 150
+    u = [rng.standard_normal(n) for _ in range(3)]
+    U = [np.ascontiguousarray(np.outer(v, rng.uniform(0.5, 2.0, R))) for v in u]
+    xi = rng.uniform(0.1, 1.0, R)
+    ci = inputs.CanonicalInput([np.asfortranarray(m) for m in U], xi, 1e-3)
+    outs = {}
+    for refine in (0, 2):
+        red = rhosvd.Reducer(precision="fp64", refine_tails=refine)
+        Ud = [rhosvd.to_device(m) for m in ci.U]
+        r = red.reduce(Ud[0], Ud[1], Ud[2], torch.from_numpy(xi).cuda(), ci.eps)
+        res = red.get()
+        torch.cuda.synchronize()
+        outs[refine] = (tuple(r), [z.cpu().numpy() for z in res.Z], res.report)
+        red.close()
+    assert outs[0][0] == outs[2][0] == (1, 1, 1)
+    for l in range(3):
+        assert np.array_equal(outs[0][1][l], outs[2][1][l])
+    o = orc.rhosvd(ci.U, ci.xi, ci.eps, with_core=False)
+    assert tuple(o.ranks) == (1, 1, 1)
+    # R < n
+    ci = inputs.small_gaussian_sum(seed=42, n=300, R=120, eps=1e-6)
+    got = {}
+    for refine in (1, 2):
+        red = rhosvd.Reducer(precision="fp64", refine_tails=refine)
+        Ud = [rhosvd.to_device(m) for m in ci.U]
+        r = red.reduce(Ud[0], Ud[1], Ud[2], torch.from_numpy(ci.xi).cuda(), ci.eps)
+        res = red.get()
+        torch.cuda.synchronize()
+        got[refine] = (tuple(r), [z.cpu().numpy() for z in res.Z], res.beta.cpu().numpy())
+        red.close()
+    assert got[1][0] == got[2][0]
+    for l in range(3):
+        assert np.array_equal(got[1][1][l], got[2][1][l])
+    assert np.array_equal(got[1][2], got[2][2])
+
+
+def test_refine_tails_values_are_checked():
+    from paper_2201_12663_amd import rhosvd
+    with pytest.raises(rhosvd.RhosvdError):
+        rhosvd.Reducer(precision="fp64", refine_tails=3)
