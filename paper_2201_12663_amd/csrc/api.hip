@@ -72,6 +72,7 @@ struct rhosvd_ctx {
     double* Z[3] = {};                   // n_pad x zr_pad
     void* V[3] = {};                     // zr_pad x R_pad (FP64 or FP32)
     double* Vref[3] = {};                // refine_tails with a mixed core: FP64 projection
+    void* Asplit = nullptr;              // BF16x3 core: hi/lo bf16 planes of V1 diag(xi') (zr_pad x R_pad each)
     double* Ud[3] = {};                  // refine_tails = 2: deflated side matrices (n_pad x R_pad)
     double* Zs[3] = {};                  //   second-pass vectors before re-orthogonalization (n_pad x zr_pad)
     double* Cz[3] = {};                  //   Z_k^T Z' (zr_pad x zr_pad)
@@ -205,6 +206,7 @@ size_t carve_all(rhosvd_ctx* h, char* base) {
         h->Zs[l] = deflate ? c.take<double>((size_t)np * zp) : nullptr;
         h->Cz[l] = deflate ? c.take<double>((size_t)zp * zp) : nullptr;
     }
+    h->Asplit = h->opt.precision == RHOSVD_BF16X3 ? (void*)c.take<char>((size_t)zp * Rp * 4) : nullptr;
     h->dscr = (h->opt.refine_tails == 2 && !h->rside) ? c.take<double>((size_t)9 * (h->m_pad + 64)) : nullptr;
     h->rfloor = c.take<double>(4);
     h->xip = c.take<double>(Rp);
@@ -775,6 +777,10 @@ rhosvd_status rhosvd_get(rhosvd_handle h, double* Z1, double* Z2, double* Z3, vo
         ca.beta = beta;
         ca.prec = h->vprec;
         ca.beta_f32 = h->opt.beta_fp32 != 0;
+        if (h->vprec == RHOSVD_BF16X3) {
+            CK(h, launch_split_a(h->r_pad[0], h->R_pad, h->r_pad[0], (const float*)h->V[0], h->xip, h->Asplit, st));
+            ca.Asplit = h->Asplit;
+        }
         if (h->opt.core_tile) {
             ca.tile = h->opt.core_tile;
             CK(h, launch_core(ca, st));

@@ -82,8 +82,8 @@ struct BatchPlan {
     char* ws = nullptr;
     size_t ws_bytes = 0;
     BProb* dP = nullptr;
-    int64_t* pre[5] = {};
-    int64_t nblk[5] = {};
+    int64_t* pre[6] = {};
+    int64_t nblk[6] = {};
     int64_t* core_work = nullptr;
     int* abort_w = nullptr;
     int core_grid = 256;
@@ -124,7 +124,7 @@ size_t carve_batch(BatchPlan& B, char* base) {
     Carve c{base};
     const int np = (int)B.hp.size();
     B.dP = c.take<BProb>(np);
-    for (int k = 0; k < 5; ++k) B.pre[k] = c.take<int64_t>(np + 1);
+    for (int k = 0; k < 6; ++k) B.pre[k] = c.take<int64_t>(np + 1);
     B.core_work = c.take<int64_t>(np + 4);
     B.abort_w = c.take<int>(16);
     const int esz = B.prec == RHOSVD_FP64 ? 8 : 4;
@@ -146,6 +146,7 @@ size_t carve_batch(BatchPlan& B, char* base) {
         q.anorm_ntiles = rt * (rt + 1) / 2;
         q.anorm_part = c.take<double>(q.anorm_ntiles);
         q.abort_w = B.abort_w;
+        q.Asplit = B.prec == RHOSVD_BF16X3 ? (void*)c.take<char>(zp * Rp * 4) : nullptr;
         BatchPlan::RSide r{};
         r.p = p;
         if (q.rside) {
@@ -243,7 +244,8 @@ static hipError_t enqueue_batch_pre(const BatchPlan& B, hipStream_t st, bool coo
         }
     }
     if ((e = launch_batched_dense(BK_SIGN, P, B.pre[4], np, B.nblk[4], 0, st)) != hipSuccess) return e;
-    return launch_batched_dense(BK_PROJECT, P, B.pre[3], np, B.nblk[3], B.prec != 0, st);
+    if ((e = launch_batched_dense(BK_PROJECT, P, B.pre[3], np, B.nblk[3], B.prec != 0, st)) != hipSuccess) return e;
+    return B.prec == RHOSVD_BF16X3 ? launch_split_b(P, B.pre[5], np, B.nblk[5], st) : hipSuccess;
 }
 
 static hipError_t enqueue_finish(const BatchPlan& B, hipStream_t st) {
@@ -356,17 +358,18 @@ BatchPlan* batch_plan_create(const rhosvd_problem* probs, int count, int prec, s
     B->ws_bytes = need;
     carve_batch(*B, B->ws);
     // flattened grids
-    std::vector<int64_t> pre(5 * (count + 1), 0);
+    std::vector<int64_t> pre(6 * (count + 1), 0);
     for (int p = 0; p < count; ++p) {
         const BProb& q = B->hp[p];
         const int64_t rt = q.R_pad / 64, nt = q.n_pad / 64;
-        const int64_t cnt[5] = {ceil_div(q.R_pad, 4), rt * (rt + 1) / 2, q.rside ? 0 : 3 * nt * (nt + 1) / 2,
-                                3 * (int64_t)(q.rcap_pad / 64) * rt, 3 * (int64_t)(q.rcap_pad / 4)};
-        for (int k = 0; k < 5; ++k) pre[k * (count + 1) + p + 1] = pre[k * (count + 1) + p] + cnt[k];
+        const int64_t cnt[6] = {ceil_div(q.R_pad, 4), rt * (rt + 1) / 2, q.rside ? 0 : 3 * nt * (nt + 1) / 2,
+                                3 * (int64_t)(q.rcap_pad / 64) * rt, 3 * (int64_t)(q.rcap_pad / 4),
+                                (int64_t)(q.rcap_pad / 64) * rt};
+        for (int k = 0; k < 6; ++k) pre[k * (count + 1) + p + 1] = pre[k * (count + 1) + p] + cnt[k];
     }
-    for (int k = 0; k < 5; ++k) B->nblk[k] = pre[k * (count + 1) + count];
+    for (int k = 0; k < 6; ++k) B->nblk[k] = pre[k * (count + 1) + count];
     hipError_t e = hipMemcpy(B->dP, B->hp.data(), count * sizeof(BProb), hipMemcpyHostToDevice);
-    for (int k = 0; k < 5 && e == hipSuccess; ++k)
+    for (int k = 0; k < 6 && e == hipSuccess; ++k)
         e = hipMemcpy(B->pre[k], pre.data() + k * (count + 1), (count + 1) * sizeof(int64_t), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         err = std::string("batch table upload: ") + hipGetErrorString(e);

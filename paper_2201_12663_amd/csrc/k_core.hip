@@ -14,7 +14,9 @@
 // Variants: FP64 (v_mfma_f64_16x16x4, TM=64), FP32 (v_mfma_f32_16x16x4, TM=64)
 // and BF16x3 (v_mfma_f32_16x16x32_bf16, TM=128): a = a_hi + a_lo, b = b_hi + b_lo
 // in bf16, a*b ~ a_hi b_hi + a_hi b_lo + a_lo b_hi, FP32 accumulation restarted
-// every KFLUSH values of nu (partial sums added in beta's precision).
+// every KFLUSH values of nu (partial sums added in beta's precision).  The BF16x3
+// core reads V1 diag(xi') already split (launch_split_a: hi and lo planes, nu
+// contiguous), so its vector ALUs only form and split the Khatri-Rao operand.
 #include <hip/hip_runtime.h>
 #include "common.hpp"
 #include "kernels.hpp"
@@ -214,13 +216,12 @@ __device__ __forceinline__ void split2(f2_t x, b2_t& hi, b2_t& lo) {
 
 
 template <typename O, bool FLUSH, int NF>
-__device__ __forceinline__ void core_tile_bf16x3(int r1, int r2, int r3, int ld1, int ld2, int ld3, int64_t Kp,
-                                 const float* __restrict__ V1, const float* __restrict__ V2,
-                                 const float* __restrict__ V3, const double* __restrict__ xip,
+__device__ __forceinline__ void core_tile_bf16x3(int r1, int r2, int r3, int ld2, int ld3, int64_t Kp,
+                                 const __bf16* __restrict__ Ah, const __bf16* __restrict__ Al,
+                                 const float* __restrict__ V2, const float* __restrict__ V3,
                                  O* __restrict__ beta, int N2T, int N3T, int64_t tile) {
     constexpr int TM = 16 * NF;
-    constexpr int PA = TM * BKC / 256;   // A entries per thread: PA consecutive k of one row
-    static_assert(PA % 8 == 0, "A is staged in 16-byte groups of 8 bf16");
+    constexpr int GA = TM / 64;          // 16-byte groups (8 k of one row) per thread and plane
     // rows of s2/s3 are padded to 18 floats: the k rows that one half-wave reads
     // (8 apart) then fall 16 banks apart
     constexpr int VLD = TN2 + 2;
@@ -236,16 +237,18 @@ __device__ __forceinline__ void core_tile_bf16x3(int r1, int r2, int r3, int ld1
     const int m0 = mt * TM, b2 = n2t * TN2, b3 = n3t * TN3;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
 
-    // staging: A TM x 32 (row ai, k = ak .. ak + PA - 1 per thread, written to LDS
-    // as 16-byte groups), V2/V3 32 x 16 (2 each)
-    const int ai = t % TM, ak = (t / TM) * PA;
+    // staging: A TM x 32 from the hi/lo planes (rows ai + 64 g, k = ak .. ak + 7 as
+    // one 16-byte load per plane), V2/V3 32 x 16 (2 each)
+    const int ai = t >> 2, ak = (t & 3) * 8;
     const int vi = t & 15, vk = t >> 4;            // k = vk, vk + 16
-    float ra[PA], rv2[2], rv3[2];
+    bf8_t rah[GA], ral[GA];
+    float rv2[2], rv3[2];
     auto gload = [&](int64_t k0) {
 #pragma unroll
-        for (int q = 0; q < PA; ++q) {
-            const int64_t k = k0 + ak + q;
-            ra[q] = V1[(int64_t)(m0 + ai) + k * ld1] * (float)xip[k];
+        for (int g = 0; g < GA; ++g) {
+            const int64_t off = (int64_t)(m0 + ai + 64 * g) * Kp + k0 + ak;
+            rah[g] = *reinterpret_cast<const bf8_t*>(Ah + off);
+            ral[g] = *reinterpret_cast<const bf8_t*>(Al + off);
         }
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
@@ -255,13 +258,9 @@ __device__ __forceinline__ void core_tile_bf16x3(int r1, int r2, int r3, int ld1
     };
     auto lstore = [&](int buf) {
 #pragma unroll
-        for (int g8 = 0; g8 < PA / 8; ++g8) {
-            bf8_pairs h8, l8;
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                split2(f2_t{ra[8 * g8 + 2 * e], ra[8 * g8 + 2 * e + 1]}, h8.p[e], l8.p[e]);
-            *reinterpret_cast<bf8_t*>(&sAh[buf][ai * BLDA + ak + 8 * g8]) = h8.v;
-            *reinterpret_cast<bf8_t*>(&sAl[buf][ai * BLDA + ak + 8 * g8]) = l8.v;
+        for (int g = 0; g < GA; ++g) {
+            *reinterpret_cast<bf8_t*>(&sAh[buf][(ai + 64 * g) * BLDA + ak]) = rah[g];
+            *reinterpret_cast<bf8_t*>(&sAl[buf][(ai + 64 * g) * BLDA + ak]) = ral[g];
         }
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
@@ -338,14 +337,70 @@ __device__ __forceinline__ void core_tile_bf16x3(int r1, int r2, int r3, int ld1
 }
 
 template <typename O, bool FLUSH, int NF>
-__global__ __launch_bounds__(256) void k_core_bf16x3(int r1, int r2, int r3, int ld1, int ld2, int ld3,
-                                                     int64_t Kp, const float* __restrict__ V1,
+__global__ __launch_bounds__(256) void k_core_bf16x3(int r1, int r2, int r3, int ld2, int ld3, int64_t Kp,
+                                                     const __bf16* __restrict__ Ah, const __bf16* __restrict__ Al,
                                                      const float* __restrict__ V2, const float* __restrict__ V3,
-                                                     const double* __restrict__ xip, O* __restrict__ beta,
-                                                     int MT, int N2T, int N3T, int64_t per) {
+                                                     O* __restrict__ beta, int MT, int N2T, int N3T, int64_t per) {
     const int64_t tile = xcd_tile(blockIdx.x, per);
     if (tile >= (int64_t)MT * N2T * N3T) return;
-    core_tile_bf16x3<O, FLUSH, NF>(r1, r2, r3, ld1, ld2, ld3, Kp, V1, V2, V3, xip, beta, N2T, N3T, tile);
+    core_tile_bf16x3<O, FLUSH, NF>(r1, r2, r3, ld2, ld3, Kp, Ah, Al, V2, V3, beta, N2T, N3T, tile);
+}
+
+// ---------------------------------------------------------------------------
+// The BF16x3 core's A operand: x = V1[j1, nu] * xi'_nu (FP32, as the FP32 core
+// forms it), split into hi = bf16(x) and lo = bf16(x - hi), stored as two planes
+// with nu contiguous: plane[j1 * Kp + nu].  One 64 x 64 tile per workgroup,
+// transposed through LDS.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void split_tile(const float* __restrict__ V1, int64_t ld, const double* __restrict__ xip,
+                                           int64_t Kp, __bf16* __restrict__ Ah, __bf16* __restrict__ Al, int64_t tm,
+                                           int64_t tn) {
+    __shared__ float s[64][65];
+    const int t = threadIdx.x;
+    const int64_t r0 = tm * 64, k0 = tn * 64;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int kk = (t >> 6) + 4 * q, rr = t & 63;
+        s[kk][rr] = V1[(r0 + rr) + (k0 + kk) * ld] * (float)xip[k0 + kk];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+        const int idx = t + 256 * g;
+        const int rr = idx >> 3, kq = (idx & 7) * 8;
+        bf8_pairs h8, l8;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) split2(f2_t{s[kq + 2 * e][rr], s[kq + 2 * e + 1][rr]}, h8.p[e], l8.p[e]);
+        const int64_t off = (r0 + rr) * Kp + k0 + kq;
+        *reinterpret_cast<bf8_t*>(Ah + off) = h8.v;
+        *reinterpret_cast<bf8_t*>(Al + off) = l8.v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_split_a(const float* __restrict__ V1, int64_t ld,
+                                                 const double* __restrict__ xip, int64_t Kp,
+                                                 __bf16* __restrict__ Ah, __bf16* __restrict__ Al) {
+    split_tile(V1, ld, xip, Kp, Ah, Al, blockIdx.y, blockIdx.x);
+}
+
+// batched: problem p's blocks cover rcap_pad / 64 x R_pad / 64 tiles of mode 1;
+// tiles beyond the rank (rounded to the 128-row core tile) are skipped
+__global__ __launch_bounds__(256) void k_split_b(const BProb* __restrict__ P, const int64_t* __restrict__ pre, int np) {
+    int lo = 0, hi = np;   // largest p with pre[p] <= blockIdx.x
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pre[mid] <= (int64_t)blockIdx.x) lo = mid;
+        else hi = mid;
+    }
+    const BProb& q = P[lo];
+    const int64_t TN = q.R_pad / 64;
+    const int64_t local = (int64_t)blockIdx.x - pre[lo];
+    const int64_t tm = local / TN, tn = local % TN;
+    const int r = min(q.ranks[0], q.rcap);
+    if (q.ranks[3] != 0 || r < 1 || tm * 64 >= round_up(r, 128)) return;
+    const __bf16* base = (const __bf16*)q.Asplit;
+    split_tile((const float*)q.V[0], q.rcap_pad, q.xip, q.R_pad, (__bf16*)base,
+               (__bf16*)base + (int64_t)q.rcap_pad * q.R_pad, tm, tn);
 }
 
 // ---------------------------------------------------------------------------
@@ -399,8 +454,9 @@ __global__ __launch_bounds__(256) void k_core_persist_b(const BProb* __restrict_
             core_tile_std<float, O, FLUSH, NF>(r1, r2, r3, q.rcap_pad, q.rcap_pad, q.rcap_pad, q.R_pad, (const float*)q.V[0],
                                  (const float*)q.V[1], (const float*)q.V[2], q.xip, (O*)q.beta, N2T, N3T, local);
         else
-            core_tile_bf16x3<O, FLUSH, NF>(r1, r2, r3, q.rcap_pad, q.rcap_pad, q.rcap_pad, q.R_pad, (const float*)q.V[0],
-                             (const float*)q.V[1], (const float*)q.V[2], q.xip, (O*)q.beta, N2T, N3T, local);
+            core_tile_bf16x3<O, FLUSH, NF>(r1, r2, r3, q.rcap_pad, q.rcap_pad, q.R_pad, (const __bf16*)q.Asplit,
+                             (const __bf16*)q.Asplit + (int64_t)q.rcap_pad * q.R_pad, (const float*)q.V[1],
+                             (const float*)q.V[2], (O*)q.beta, N2T, N3T, local);
     }
 }
 
@@ -418,9 +474,10 @@ static void launch_core_t(const CoreArgs& a, dim3 grid, int MT, int N2T, int N3T
                            a.r_pad[0], a.r_pad[1], a.r_pad[2], a.R_pad, (const float*)a.V[0],
                            (const float*)a.V[1], (const float*)a.V[2], a.xip, beta, MT, N2T, N3T, per);
     } else {
+        const __bf16* Ah = (const __bf16*)a.Asplit;
         hipLaunchKernelGGL((k_core_bf16x3<O, FLUSH, NF>), grid, dim3(256), 0, st, a.r[0], a.r[1], a.r[2],
-                           a.r_pad[0], a.r_pad[1], a.r_pad[2], a.R_pad, (const float*)a.V[0],
-                           (const float*)a.V[1], (const float*)a.V[2], a.xip, beta, MT, N2T, N3T, per);
+                           a.r_pad[1], a.r_pad[2], a.R_pad, Ah, Ah + (int64_t)a.r_pad[0] * a.R_pad,
+                           (const float*)a.V[1], (const float*)a.V[2], beta, MT, N2T, N3T, per);
     }
 }
 
@@ -443,6 +500,7 @@ hipError_t launch_core(const CoreArgs& a, hipStream_t st) {
     if (!core_tile_valid(a.prec, TMv)) return hipErrorInvalidValue;
     const int KCv = (a.prec == 2) ? BKC : 16;
     if (a.R_pad % KCv != 0) return hipErrorInvalidValue;
+    if (a.prec == 2 && !a.Asplit) return hipErrorInvalidValue;
     const int MT = (int)ceil_div(a.r[0], TMv), N2T = (int)ceil_div(a.r[1], TN2), N3T = (int)ceil_div(a.r[2], TN3);
     // the kernels read whole tiles: padded rows must exist (and be zero)
     if (a.r_pad[0] < MT * TMv || a.r_pad[1] < N2T * TN2 || a.r_pad[2] < N3T * TN3) return hipErrorInvalidValue;
@@ -496,6 +554,21 @@ hipError_t launch_core_b(const BProb* P, int np, int prec, int tile, int64_t* wo
 }
 
 int64_t core_flush_span() { return KFLUSH; }
+
+hipError_t launch_split_a(int64_t rows_pad, int64_t R_pad, int64_t ld, const float* V1, const double* xip,
+                          void* planes, hipStream_t st) {
+    if (rows_pad % 64 || R_pad % 64 || ld < rows_pad) return hipErrorInvalidValue;
+    __bf16* Ah = (__bf16*)planes;
+    hipLaunchKernelGGL(k_split_a, dim3((unsigned)(R_pad / 64), (unsigned)(rows_pad / 64)), dim3(256), 0, st, V1, ld,
+                       xip, R_pad, Ah, Ah + rows_pad * R_pad);
+    return hipGetLastError();
+}
+
+hipError_t launch_split_b(const BProb* P, const int64_t* pre, int np, int64_t nblocks, hipStream_t st) {
+    if (nblocks < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_split_b, dim3((unsigned)nblocks), dim3(256), 0, st, P, pre, np);
+    return hipGetLastError();
+}
 
 template <typename O, bool FLUSH, int NF>
 static const void* persist_fn(int prec) {

@@ -154,8 +154,14 @@ struct CoreArgs {
     int prec;
     int beta_f32;
     int tile;         // rows of j1 per workgroup tile: 64 or 128 (FP32, BF16x3), 64 (FP64); 0: default
+    const void* Asplit;   // BF16x3: V1 diag(xi') as bf16 hi and lo planes (launch_split_a), r_pad[0] x R_pad each
 };
 hipError_t launch_core(const CoreArgs& a, hipStream_t st);
+// A operand of the BF16x3 core: x = V1[j1, nu] * xi'_nu (FP32), hi = bf16(x), lo =
+// bf16(x - hi), as two planes of rows_pad x R_pad bf16 with nu contiguous
+// (plane[j1 * R_pad + nu]; lo plane right after hi).  V1: FP32, ld >= rows_pad.
+hipError_t launch_split_a(int64_t rows_pad, int64_t R_pad, int64_t ld, const float* V1, const double* xip,
+                          void* planes, hipStream_t st);
 int core_tile_default(int prec);
 bool core_tile_valid(int prec, int tile);
 
@@ -198,13 +204,16 @@ struct BProb {
     int* ranks;            // [0..2] ranks, [3] status
     double* Z[3];          // n_pad x rcap_pad
     void* V[3];            // rcap_pad x R_pad (FP64, or FP32 for the mixed cores)
+    void* Asplit;          // BF16x3: hi and lo planes of V1 diag(xi') (rcap_pad x R_pad bf16 each)
     double* Zo[3];         // caller outputs, n x cap_rank (ld n), or null
     void* beta;            // caller output (double, or float when beta_f32) or null
     int64_t cap_beta;
     int beta_f32;
     int* result;           // caller's int32[8]: r1, r2, r3, status
 };
-enum { BK_COLNORM = 0, BK_ANORM = 1, BK_GRAM = 2, BK_PROJECT = 3, BK_SIGN = 4 };
+enum { BK_COLNORM = 0, BK_ANORM = 1, BK_GRAM = 2, BK_PROJECT = 3, BK_SIGN = 4, BK_SPLIT = 5 };
+// the BF16x3 A planes of every problem (blocks: rcap_pad / 64 x R_pad / 64 each)
+hipError_t launch_split_b(const BProb* P, const int64_t* pre, int np, int64_t nblocks, hipStream_t st);
 // Flattened launch of one batched dense phase: pre (device, np + 1 entries) holds
 // each problem's first block, nblocks = pre[np].  f32: V in FP32 (projection).
 hipError_t launch_batched_dense(int which, const BProb* P, const int64_t* pre, int np, int64_t nblocks, int f32,
