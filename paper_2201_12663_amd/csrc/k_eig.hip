@@ -547,11 +547,16 @@ __global__ __launch_bounds__(256) void k_dc_leaves(DCArgs a) {
     }
 }
 
-// phase A (one workgroup per node): z, sort, deflation
+// phase A (one workgroup per node): z, sort, deflation.  The deflation scan is
+// sequential (each rotation changes the next comparison); it runs on LDS copies
+// of D and z, which are written out afterwards by all threads.
 __global__ __launch_bounds__(256) void k_dc_prep(DCArgs a) {
     __shared__ double key[MAXN];
     __shared__ int idx[MAXN];
+    __shared__ double zs[MAXN];
+    __shared__ int keep_s[MAXN];
     __shared__ double red[4];
+    __shared__ int s_k;
     const int node = blockIdx.x;
     const Node nd = a.nodes[node];
     const int n1 = nd.mid - nd.lo, n = nd.hi - nd.lo;
@@ -595,11 +600,10 @@ __global__ __launch_bounds__(256) void k_dc_prep(DCArgs a) {
     double mx = 0.0;
     for (int s = t; s < n; s += 256) {
         const int i = idx[s];
-        D[s] = key[s];
         perm[s] = i;
         // column lo+i: last row of child 1 (row mid-1) or first row of child 2 (row mid)
         const int row = (i < n1) ? nd.mid - 1 : nd.mid;
-        z[s] = rs2 * Q[row + (int64_t)(nd.lo + i) * ld];
+        zs[s] = rs2 * Q[row + (int64_t)(nd.lo + i) * ld];
         mx = fmax(mx, fabs(key[s]));
     }
     mx = wave_max(mx);
@@ -608,24 +612,22 @@ __global__ __launch_bounds__(256) void k_dc_prep(DCArgs a) {
     if (t == 0) {
         mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
         const double tol = 8.0 * U64 * fmax(mx, rho);
-        double* dd = ns_dd(a, node);
-        double* zk = ns_zk(a, node);
         double* rc = ns_rc(a, node);
-        int* keep = ns_keep(a, node);
         int* rp = ns_rp(a, node);
+        double* Dl = key;
         int k = 0, nrot = 0, prev = -1;
         for (int i = 0; i < n; ++i) {
-            if (fabs(rho * z[i]) <= tol) continue;   // deflated: eigenpair (D_i, e_i)
+            if (fabs(rho * zs[i]) <= tol) continue;   // deflated: eigenpair (D_i, e_i)
             if (prev < 0) { prev = i; continue; }
-            const double tt = hypot(z[prev], z[i]);
-            const double c = z[i] / tt, s = -z[prev] / tt;
-            if (fabs((D[i] - D[prev]) * c * s) <= tol) {
+            const double tt = hypot(zs[prev], zs[i]);
+            const double c = zs[i] / tt, s = -zs[prev] / tt;
+            if (fabs((Dl[i] - Dl[prev]) * c * s) <= tol) {
                 // close poles: rotate so that z[prev] = 0 and deflate prev
-                const double dp = D[prev], di = D[i];
-                D[prev] = dp * c * c + di * s * s;
-                D[i] = dp * s * s + di * c * c;
-                z[i] = tt;
-                z[prev] = 0.0;
+                const double dp = Dl[prev], di = Dl[i];
+                Dl[prev] = dp * c * c + di * s * s;
+                Dl[i] = dp * s * s + di * c * c;
+                zs[i] = tt;
+                zs[prev] = 0.0;
                 rp[2 * nrot] = prev;
                 rp[2 * nrot + 1] = i;
                 rc[2 * nrot] = c;
@@ -633,54 +635,74 @@ __global__ __launch_bounds__(256) void k_dc_prep(DCArgs a) {
                 ++nrot;
                 prev = i;
             } else {
-                keep[k++] = prev;
+                keep_s[k++] = prev;
                 prev = i;
             }
         }
-        if (prev >= 0) keep[k++] = prev;
-        for (int q = 0; q < k; ++q) {
-            dd[q] = D[keep[q]];
-            zk[q] = z[keep[q]];
-        }
+        if (prev >= 0) keep_s[k++] = prev;
+        s_k = k;
         NodeScratch* h = ns_head(a, node);
         h->rho = rho;
         h->sgn = sgn;
         h->k = k;
         h->nrot = nrot;
     }
+    __syncthreads();
+    const int k = s_k;
+    double* dd = ns_dd(a, node);
+    double* zk = ns_zk(a, node);
+    for (int s = t; s < n; s += 256) {
+        D[s] = key[s];
+        z[s] = zs[s];
+    }
+    int* keep = ns_keep(a, node);
+    for (int q = t; q < k; q += 256) {
+        keep[q] = keep_s[q];
+        dd[q] = key[keep_s[q]];
+        zk[q] = zs[keep_s[q]];
+    }
 }
 
-// phase B: secular roots; one wave per root, nodes x roots flattened in y
+// phase B: secular roots; one wave per root, nodes x roots flattened in y.  The
+// workgroup's four waves share one LDS copy of the poles and of z^2.
 __global__ __launch_bounds__(256) void k_dc_roots(DCArgs a) {
+    __shared__ double s_dd[MAXN];
+    __shared__ double s_z2[MAXN];
     const int node = blockIdx.y;
     const NodeScratch* h = ns_head(a, node);
     const int k = h->k;
+    if ((int)blockIdx.x * 4 >= k) return;   // uniform across the workgroup
+    const double* dd = ns_dd(a, node);
+    const double* zk = ns_zk(a, node);
+    for (int i = threadIdx.x; i < k; i += 256) {
+        s_dd[i] = dd[i];
+        s_z2[i] = zk[i] * zk[i];
+    }
+    __syncthreads();
     const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (j >= k) return;
-    const double* dd = ns_dd(a, node);
-    const double* zk = ns_zk(a, node);
     const double rho = h->rho;
     double zz2 = 0.0;
-    for (int i = lane; i < k; i += 64) zz2 += zk[i] * zk[i];
+    for (int i = lane; i < k; i += 64) zz2 += s_z2[i];
     zz2 = wave_sum(zz2);
-    const double lo_pole = dd[j];
-    const double hi_pole = (j + 1 < k) ? dd[j + 1] : dd[j] + rho * zz2;
+    const double lo_pole = s_dd[j];
+    const double hi_pole = (j + 1 < k) ? s_dd[j + 1] : s_dd[j] + rho * zz2;
     int o = j;
     if (j + 1 < k) {
         const double mid = 0.5 * (hi_pole - lo_pole);
         double f = 0.0;
-        for (int i = lane; i < k; i += 64) f += zk[i] * zk[i] / ((dd[i] - lo_pole) - mid);
+        for (int i = lane; i < k; i += 64) f += s_z2[i] / ((s_dd[i] - lo_pole) - mid);
         f = 1.0 + rho * wave_sum(f);
         o = (f > 0.0) ? j : j + 1;
     }
-    const double dorg = dd[o];
+    const double dorg = s_dd[o];
     double lo = lo_pole - dorg, hi = hi_pole - dorg;
     for (int it = 0; it < 200; ++it) {
         const double tm = 0.5 * (lo + hi);
         if (tm == lo || tm == hi) break;
         double f = 0.0;
-        for (int i = lane; i < k; i += 64) f += zk[i] * zk[i] / ((dd[i] - dorg) - tm);
+        for (int i = lane; i < k; i += 64) f += s_z2[i] / ((s_dd[i] - dorg) - tm);
         f = 1.0 + rho * wave_sum(f);
         if (f > 0.0) hi = tm;
         else lo = tm;
