@@ -969,23 +969,38 @@ __global__ __launch_bounds__(256) void k_apply_wy(BtJobs J) {
     const int nblk = m >= 3 ? (m - 2 + NB - 1) / NB : 0;
     for (int b = nblk - 1; b >= 0; --b) {
         const int k0 = NB * b, kc = min(NB, (m - 2) - k0);
-        // pass 1: wave w -> tile jt = w & 1 of Wm, rows interleaved by halves h = w >> 1
+        // pass 1: wave w -> tile jt = w & 1 of Wm, rows interleaved by halves h = w >> 1;
+        // the reflector values of the next 64 rows are loaded before this step's
+        // MFMAs, which alternate between two accumulators
         {
             const int jt = w & 1, h = w >> 1;
-            d4_t acc = {0.0, 0.0, 0.0, 0.0};
-            for (int row0 = k0 + 1 + 4 * h; row0 < m; row0 += 64) {
+            d4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+            double an[8];
+            const int rfirst = k0 + 1 + 4 * h;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) an[u] = vb(Hv, ld, m, k0, 16 * jt + (lane & 15), kc, rfirst + 8 * u + (lane >> 4));
+            for (int row0 = rfirst; row0 < m; row0 += 64) {
                 double av[8], bv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) av[u] = an[u];
+                if (row0 + 64 < m) {
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        an[u] = vb(Hv, ld, m, k0, 16 * jt + (lane & 15), kc, row0 + 64 + 8 * u + (lane >> 4));
+                }
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     const int row = row0 + 8 * u + (lane >> 4);
-                    av[u] = vb(Hv, ld, m, k0, 16 * jt + (lane & 15), kc, row);
                     bv[u] = (row < m && (XL || (lane & 15) < nc)) ? X(row, lane & 15) : 0.0;
                 }
 #pragma unroll
-                for (int u = 0; u < 8; ++u) acc = mfma_f64(av[u], bv[u], acc);
+                for (int u = 0; u < 8; u += 2) {
+                    acc0 = mfma_f64(av[u], bv[u], acc0);
+                    acc1 = mfma_f64(av[u + 1], bv[u + 1], acc1);
+                }
             }
 #pragma unroll
-            for (int q = 0; q < 4; ++q) P[h][16 * jt + c_row64(lane, q)][c_col(lane)] = acc[q];
+            for (int q = 0; q < 4; ++q) P[h][16 * jt + c_row64(lane, q)][c_col(lane)] = acc0[q] + acc1[q];
         }
         __syncthreads();
         // W2 = T_b Wm (T_b upper triangular, column-major)
@@ -1020,13 +1035,16 @@ __global__ __launch_bounds__(256) void k_apply_wy(BtJobs J) {
                     for (int st = 0; st < NB / 4; ++st)
                         an[st] = vb(Hv, ld, m, k0, 4 * st + (lane >> 4), kc, rb + 64 + (lane & 15));
                 }
-                d4_t acc = {0.0, 0.0, 0.0, 0.0};
+                d4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int st = 0; st < NB / 4; ++st) acc = mfma_f64(av[st], W2[4 * st + (lane >> 4)][lane & 15], acc);
+                for (int st = 0; st < NB / 4; st += 2) {
+                    acc0 = mfma_f64(av[st], W2[4 * st + (lane >> 4)][lane & 15], acc0);
+                    acc1 = mfma_f64(av[st + 1], W2[4 * (st + 1) + (lane >> 4)][lane & 15], acc1);
+                }
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int row = rb + c_row64(lane, q);
-                    if (row < m && (XL || c_col(lane) < nc)) X(row, c_col(lane)) -= acc[q];
+                    if (row < m && (XL || c_col(lane) < nc)) X(row, c_col(lane)) -= acc0[q] + acc1[q];
                 }
             }
         }
