@@ -252,6 +252,7 @@ hipError_t launch_gram_nt(int64_t n_pad, int64_t R_pad, double* const Ut[3], dou
 // formed with FP64 MFMA, multiplied entrywise, weighted, and reduced to one
 // partial sum per tile (off-diagonal tiles count twice).
 // ===========================================================================
+template <bool STORE_G>
 __device__ __forceinline__ void anorm_tile(int64_t n_pad, int64_t R_pad, const double* __restrict__ T0,
                            const double* __restrict__ T1, const double* __restrict__ T2,
                            const double* __restrict__ xip, double* __restrict__ part, double* __restrict__ G0,
@@ -266,13 +267,14 @@ __device__ __forceinline__ void anorm_tile(int64_t n_pad, int64_t R_pad, const d
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
     d4_t prod[2][2];
-    const double* Ts[3] = {T0, T1, T2};
+#pragma unroll 1
     for (int l = 0; l < 3; ++l) {
+        const double* Tl = l == 0 ? T0 : (l == 1 ? T1 : T2);
         d4_t acc[2][2];
         zero_acc(acc);
-        tile64_f64<true, true>(Ts[l], n_pad, Ts[l], n_pad, ti * T64, tj * T64, 0, n_pad, sA, sB, acc);
+        tile64_f64<true, true>(Tl, n_pad, Tl, n_pad, ti * T64, tj * T64, 0, n_pad, sA, sB, acc);
         double* Gl = l == 0 ? G0 : (l == 1 ? G1 : G2);
-        if (Gl) {   // R < n: this tile of U~^T U~ is the mode's Gram on the R side
+        if (STORE_G && Gl) {   // R < n: this tile of U~^T U~ is the mode's Gram on the R side
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -311,12 +313,13 @@ __device__ __forceinline__ void anorm_tile(int64_t n_pad, int64_t R_pad, const d
     }
 }
 
+template <bool STORE_G>
 __global__ __launch_bounds__(256) void k_anorm(int64_t n_pad, int64_t R_pad, const double* __restrict__ T0,
                                                const double* __restrict__ T1, const double* __restrict__ T2,
                                                const double* __restrict__ xip, double* __restrict__ part,
                                                double* __restrict__ G0, double* __restrict__ G1,
                                                double* __restrict__ G2) {
-    anorm_tile(n_pad, R_pad, T0, T1, T2, xip, part, G0, G1, G2, blockIdx.x);
+    anorm_tile<STORE_G>(n_pad, R_pad, T0, T1, T2, xip, part, G0, G1, G2, blockIdx.x);
 }
 
 hipError_t launch_anorm_partials(int64_t n_pad, int64_t R_pad, double* const Ut[3],
@@ -324,8 +327,12 @@ hipError_t launch_anorm_partials(int64_t n_pad, int64_t R_pad, double* const Ut[
                                  hipStream_t st) {
     const int64_t nt = R_pad / T64;
     *ntiles = nt * (nt + 1) / 2;
-    hipLaunchKernelGGL(k_anorm, dim3((unsigned)*ntiles), dim3(256), 0, st, n_pad, R_pad, Ut[0], Ut[1],
-                       Ut[2], xip, part, Gr ? Gr[0] : nullptr, Gr ? Gr[1] : nullptr, Gr ? Gr[2] : nullptr);
+    if (Gr)
+        hipLaunchKernelGGL(k_anorm<true>, dim3((unsigned)*ntiles), dim3(256), 0, st, n_pad, R_pad, Ut[0], Ut[1],
+                           Ut[2], xip, part, Gr[0], Gr[1], Gr[2]);
+    else
+        hipLaunchKernelGGL(k_anorm<false>, dim3((unsigned)*ntiles), dim3(256), 0, st, n_pad, R_pad, Ut[0], Ut[1],
+                           Ut[2], xip, part, nullptr, nullptr, nullptr);
     return hipGetLastError();
 }
 
@@ -513,11 +520,15 @@ __global__ __launch_bounds__(256) void k_colnorm_b(const BProb* __restrict__ P, 
                  nu);
 }
 
+// RSIDE: the instance for problems with R < n (which also store the R-side
+// Grams); each instance skips the other kind of problem
+template <bool RSIDE>
 __global__ __launch_bounds__(256) void k_anorm_b(const BProb* __restrict__ P, const int64_t* __restrict__ pre, int np) {
     const int p = find_problem(pre, np, blockIdx.x);
     const BProb& q = P[p];
-    anorm_tile(q.n_pad, q.R_pad, q.Ut[0], q.Ut[1], q.Ut[2], q.xip, q.anorm_part, q.rside ? q.G[0] : nullptr,
-               q.rside ? q.G[1] : nullptr, q.rside ? q.G[2] : nullptr, blockIdx.x - pre[p]);
+    if ((q.rside != 0) != RSIDE) return;
+    anorm_tile<RSIDE>(q.n_pad, q.R_pad, q.Ut[0], q.Ut[1], q.Ut[2], q.xip, q.anorm_part, q.G[0], q.G[1], q.G[2],
+                      blockIdx.x - pre[p]);
 }
 
 __global__ __launch_bounds__(256) void k_gram_b(const BProb* __restrict__ P, const int64_t* __restrict__ pre, int np) {
@@ -582,7 +593,11 @@ hipError_t launch_batched_dense(int which, const BProb* P, const int64_t* pre, i
     const dim3 grid((unsigned)nblocks), blk(256);
     switch (which) {
         case BK_COLNORM: hipLaunchKernelGGL(k_colnorm_b, grid, blk, 0, st, P, pre, np); break;
-        case BK_ANORM: hipLaunchKernelGGL(k_anorm_b, grid, blk, 0, st, P, pre, np); break;
+        case BK_ANORM:
+            hipLaunchKernelGGL(k_anorm_b<false>, grid, blk, 0, st, P, pre, np);
+            if (hipGetLastError() != hipSuccess) break;
+            hipLaunchKernelGGL(k_anorm_b<true>, grid, blk, 0, st, P, pre, np);
+            break;
         case BK_GRAM: hipLaunchKernelGGL(k_gram_b, grid, blk, 0, st, P, pre, np); break;
         case BK_PROJECT: hipLaunchKernelGGL(k_project_b, grid, blk, 0, st, P, pre, np, f32); break;
         case BK_SIGN: hipLaunchKernelGGL(k_sign_b, grid, blk, 0, st, P, pre, np); break;
