@@ -102,26 +102,32 @@ constexpr int T64 = 64;
 constexpr int KC = 16;
 constexpr int LDS_STRIDE = T64 + 4;   // doubles per k-row in LDS
 
+// thread t's four entries of a 64 x 16 chunk: (i, k) = (t % 64, t / 64 + 4q) for an
+// M-contiguous operand, (t / 4, 4 (t % 4) + q) for a K-contiguous one
 template <bool AK>
-__device__ __forceinline__ void stage64(const double* __restrict__ A, int64_t lda, int64_t m0,
-                                        int64_t k0, double* __restrict__ s) {
+__device__ __forceinline__ void gload64(const double* __restrict__ A, int64_t lda, int64_t m0, int64_t k0,
+                                        double (&r)[4]) {
     const int t = threadIdx.x;
-    if (!AK) {   // A(i,k) = A[i + k*lda]: 16 rows of 64 contiguous entries
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            int k = (t >> 6) + 4 * q, i = t & 63;
-            s[k * LDS_STRIDE + i] = A[(m0 + i) + (k0 + k) * lda];
-        }
-    } else {     // A(i,k) = A[k + i*lda]: 64 rows of 16 contiguous entries
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            int i = t >> 2, k = ((t & 3) << 2) + q;
-            s[k * LDS_STRIDE + i] = A[(k0 + k) + (m0 + i) * lda];
-        }
+    for (int q = 0; q < 4; ++q) {
+        if (!AK) r[q] = A[(m0 + (t & 63)) + (k0 + (t >> 6) + 4 * q) * lda];
+        else r[q] = A[(k0 + ((t & 3) << 2) + q) + (m0 + (t >> 2)) * lda];
     }
 }
 
-// acc[a][b] += A[m0 + wave rows][k-chunk] * B[k-chunk][n0 + wave cols]
+template <bool AK>
+__device__ __forceinline__ void sstore64(const double (&r)[4], double* __restrict__ s) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (!AK) s[((t >> 6) + 4 * q) * LDS_STRIDE + (t & 63)] = r[q];
+        else s[(((t & 3) << 2) + q) * LDS_STRIDE + (t >> 2)] = r[q];
+    }
+}
+
+// acc[a][b] += A[m0 + wave rows][k0 .. k1) * B[k0 .. k1)[n0 + wave cols].  sA and sB
+// hold two chunk buffers each (2 * KC * LDS_STRIDE doubles): the next chunk's global
+// loads are in flight during the current chunk's MFMAs, one barrier per chunk.
 template <bool AK, bool BK>
 __device__ __forceinline__ void tile64_f64(const double* __restrict__ A, int64_t lda,
                                            const double* __restrict__ B, int64_t ldb,
@@ -129,23 +135,40 @@ __device__ __forceinline__ void tile64_f64(const double* __restrict__ A, int64_t
                                            double* sA, double* sB, d4_t acc[2][2]) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+    if (k0 >= k1) return;
+    double ra[4], rb[4];
+    gload64<AK>(A, lda, m0, k0, ra);
+    gload64<BK>(B, ldb, n0, k0, rb);
+    sstore64<AK>(ra, sA);
+    sstore64<BK>(rb, sB);
+    __syncthreads();
+    int buf = 0;
     for (int64_t kb = k0; kb < k1; kb += KC) {
-        stage64<AK>(A, lda, m0, kb, sA);
-        stage64<BK>(B, ldb, n0, kb, sB);
-        __syncthreads();
+        const bool more = kb + KC < k1;
+        if (more) {
+            gload64<AK>(A, lda, m0, kb + KC, ra);
+            gload64<BK>(B, ldb, n0, kb + KC, rb);
+        }
+        const double* cA = sA + buf * KC * LDS_STRIDE;
+        const double* cB = sB + buf * KC * LDS_STRIDE;
 #pragma unroll
         for (int kk = 0; kk < KC / 4; ++kk) {
             const int k = kk * 4 + (lane >> 4);
-            double a0 = sA[k * LDS_STRIDE + wr + (lane & 15)];
-            double a1 = sA[k * LDS_STRIDE + wr + 16 + (lane & 15)];
-            double b0 = sB[k * LDS_STRIDE + wc + (lane & 15)];
-            double b1 = sB[k * LDS_STRIDE + wc + 16 + (lane & 15)];
+            double a0 = cA[k * LDS_STRIDE + wr + (lane & 15)];
+            double a1 = cA[k * LDS_STRIDE + wr + 16 + (lane & 15)];
+            double b0 = cB[k * LDS_STRIDE + wc + (lane & 15)];
+            double b1 = cB[k * LDS_STRIDE + wc + 16 + (lane & 15)];
             acc[0][0] = mfma_f64(a0, b0, acc[0][0]);
             acc[0][1] = mfma_f64(a0, b1, acc[0][1]);
             acc[1][0] = mfma_f64(a1, b0, acc[1][0]);
             acc[1][1] = mfma_f64(a1, b1, acc[1][1]);
         }
+        if (more) {
+            sstore64<AK>(ra, sA + (buf ^ 1) * KC * LDS_STRIDE);
+            sstore64<BK>(rb, sB + (buf ^ 1) * KC * LDS_STRIDE);
+        }
         __syncthreads();
+        buf ^= 1;
     }
 }
 
@@ -164,8 +187,8 @@ __device__ __forceinline__ void zero_acc(d4_t acc[2][2]) {
 // ===========================================================================
 __device__ __forceinline__ void gram_tile(int64_t n_pad, int64_t R_pad, const double* __restrict__ T, double* __restrict__ G,
                           double* __restrict__ part, int splits, int64_t t, int split, int mode) {
-    __shared__ double sA[KC * LDS_STRIDE];
-    __shared__ double sB[KC * LDS_STRIDE];
+    __shared__ double sA[2 * KC * LDS_STRIDE];
+    __shared__ double sB[2 * KC * LDS_STRIDE];
     // lower-triangle tile (ti >= tj) from the linear index
     int64_t ti = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
     while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
@@ -257,8 +280,8 @@ __device__ __forceinline__ void anorm_tile(int64_t n_pad, int64_t R_pad, const d
                            const double* __restrict__ T1, const double* __restrict__ T2,
                            const double* __restrict__ xip, double* __restrict__ part, double* __restrict__ G0,
                            double* __restrict__ G1, double* __restrict__ G2, int64_t t) {
-    __shared__ double sA[KC * LDS_STRIDE];
-    __shared__ double sB[KC * LDS_STRIDE];
+    __shared__ double sA[2 * KC * LDS_STRIDE];
+    __shared__ double sB[2 * KC * LDS_STRIDE];
     __shared__ double red[4];
     int64_t ti = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
     while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
@@ -344,8 +367,8 @@ hipError_t launch_anorm_partials(int64_t n_pad, int64_t R_pad, double* const Ut[
 __device__ __forceinline__ void project_tile(int64_t n_pad, int64_t R_pad, int64_t r_pad, const double* __restrict__ Z,
                              const double* __restrict__ T, double* __restrict__ out64, float* __restrict__ out32,
                              int64_t tm, int64_t tn) {
-    __shared__ double sA[KC * LDS_STRIDE];
-    __shared__ double sB[KC * LDS_STRIDE];
+    __shared__ double sA[2 * KC * LDS_STRIDE];
+    __shared__ double sB[2 * KC * LDS_STRIDE];
     d4_t acc[2][2];
     zero_acc(acc);
     tile64_f64<true, true>(Z, n_pad, T, n_pad, tm * T64, tn * T64, 0, n_pad, sA, sB, acc);
@@ -386,8 +409,8 @@ template <bool AK, bool BK>
 __global__ __launch_bounds__(256) void k_gemm64(int64_t K, const double* __restrict__ A, int64_t lda,
                                                 const double* __restrict__ B, int64_t ldb, double* __restrict__ C,
                                                 int64_t ldc, double alpha) {
-    __shared__ double sA[KC * LDS_STRIDE];
-    __shared__ double sB[KC * LDS_STRIDE];
+    __shared__ double sA[2 * KC * LDS_STRIDE];
+    __shared__ double sB[2 * KC * LDS_STRIDE];
     const int64_t tm = blockIdx.y, tn = blockIdx.x;
     d4_t acc[2][2];
     zero_acc(acc);
@@ -614,8 +637,8 @@ hipError_t launch_batched_dense(int which, const BProb* P, const int64_t* pre, i
 __global__ __launch_bounds__(256) void k_resid_partials(int64_t n_pad, int64_t R_pad, int64_t p_pad,
                                                         const double* __restrict__ Q, const double* __restrict__ B,
                                                         const double* __restrict__ T, double* __restrict__ part) {
-    __shared__ double sA[KC * LDS_STRIDE];
-    __shared__ double sB[KC * LDS_STRIDE];
+    __shared__ double sA[2 * KC * LDS_STRIDE];
+    __shared__ double sB[2 * KC * LDS_STRIDE];
     __shared__ double red[4];
     const int64_t tn = blockIdx.x, tm = blockIdx.y;
     d4_t acc[2][2];
@@ -646,8 +669,8 @@ __global__ __launch_bounds__(256) void k_resid_partials(int64_t n_pad, int64_t R
 // and out, so out may be T.
 __global__ __launch_bounds__(256) void k_residual(int64_t n_pad, int64_t p_pad, const double* __restrict__ Q,
                                                   const double* __restrict__ B, const double* T, double* out) {
-    __shared__ double sA[KC * LDS_STRIDE];
-    __shared__ double sB[KC * LDS_STRIDE];
+    __shared__ double sA[2 * KC * LDS_STRIDE];
+    __shared__ double sB[2 * KC * LDS_STRIDE];
     const int64_t tn = blockIdx.x, tm = blockIdx.y;
     d4_t acc[2][2];
     zero_acc(acc);
