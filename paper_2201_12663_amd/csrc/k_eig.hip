@@ -548,15 +548,20 @@ __global__ __launch_bounds__(256) void k_dc_leaves(DCArgs a) {
 }
 
 // phase A (one workgroup per node): z, sort, deflation.  The deflation scan is
-// sequential (each rotation changes the next comparison); it runs on LDS copies
-// of D and z, which are written out afterwards by all threads.
+// sequential where a close-pole rotation occurs (a rotation changes the next
+// comparison).  All threads first test every consecutive pair of undeflated
+// entries with the unrotated values: when no pair calls for a rotation the
+// scan's result is the compacted list of undeflated entries, formed in
+// parallel; otherwise one thread runs the scan.  Both work on LDS copies of D
+// and z, written out afterwards by all threads.
 __global__ __launch_bounds__(256) void k_dc_prep(DCArgs a) {
     __shared__ double key[MAXN];
     __shared__ int idx[MAXN];
     __shared__ double zs[MAXN];
     __shared__ int keep_s[MAXN];
     __shared__ double red[4];
-    __shared__ int s_k;
+    __shared__ int s_k, s_rot;
+    __shared__ int cnt_s[256];
     const int node = blockIdx.x;
     const Node nd = a.nodes[node];
     const int n1 = nd.mid - nd.lo, n = nd.hi - nd.lo;
@@ -609,9 +614,46 @@ __global__ __launch_bounds__(256) void k_dc_prep(DCArgs a) {
     mx = wave_max(mx);
     if ((t & 63) == 0) red[t >> 6] = mx;
     __syncthreads();
+    mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    const double tol = 8.0 * U64 * fmax(mx, rho);
+    // undeflated entries of this thread's range, compacted in order
+    const int per = (n + 255) / 256, b0 = min(n, t * per), b1 = min(n, b0 + per);
+    int c = 0;
+    for (int i = b0; i < b1; ++i) c += fabs(rho * zs[i]) > tol;
+    cnt_s[t] = c;
+    if (t == 0) s_rot = 0;
+    __syncthreads();
     if (t == 0) {
-        mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-        const double tol = 8.0 * U64 * fmax(mx, rho);
+        int acc = 0;
+        for (int q = 0; q < 256; ++q) {
+            const int v = cnt_s[q];
+            cnt_s[q] = acc;
+            acc += v;
+        }
+        s_k = acc;
+    }
+    __syncthreads();
+    {
+        int o = cnt_s[t];
+        for (int i = b0; i < b1; ++i)
+            if (fabs(rho * zs[i]) > tol) keep_s[o++] = i;
+    }
+    __syncthreads();
+    for (int q = t + 1; q < s_k; q += 256) {
+        const int pv = keep_s[q - 1], i = keep_s[q];
+        const double tt = hypot(zs[pv], zs[i]);
+        const double cc = zs[i] / tt, ss = -zs[pv] / tt;
+        if (fabs((key[i] - key[pv]) * cc * ss) <= tol) s_rot = 1;
+    }
+    __syncthreads();
+    if (t == 0 && !s_rot) {
+        NodeScratch* h = ns_head(a, node);
+        h->rho = rho;
+        h->sgn = sgn;
+        h->k = s_k;
+        h->nrot = 0;
+    }
+    if (t == 0 && s_rot) {
         double* rc = ns_rc(a, node);
         int* rp = ns_rp(a, node);
         double* Dl = key;
