@@ -334,3 +334,44 @@ def test_refine_tails_values_are_checked():
     from paper_2201_12663_amd import rhosvd
     with pytest.raises(rhosvd.RhosvdError):
         rhosvd.Reducer(precision="fp64", refine_tails=3)
+
+
+@pytest.mark.parametrize("n,R", [(1, 4), (2, 5), (3, 2), (2, 2), (5, 3), (65, 1), (65, 129)])
+def test_tiny_and_ragged_sizes(orc, n, R):
+    """The smallest shapes (one- to five-row side matrices, R = 1 .. 5: Gram
+    matrices of size 1 to 5, eigensolver without a tridiagonalization step) and
+    shapes one past a 64-row tile, against the oracle."""
+    rng = np.random.default_rng(1000 + 7 * n + R)
+    U = [np.asfortranarray(rng.standard_normal((n, R))) for _ in range(3)]
+    xi = rng.uniform(0.5, 1.5, R)
+    ci = inputs.CanonicalInput(U, xi, 1e-8)
+    _flush(f"tiny case n={n} R={R}")
+    o = orc.rhosvd(ci.U, ci.xi, ci.eps)
+    g = gc.run_gpu(ci, "fp64")
+    gc.compare_fp64(g, o, ci)
+    err = gc.recon_error(orc, ci, g["Z"], g["beta"])
+    assert err <= ci.eps * o.a_norm * (1 + 1e-9) + 1e-12 * o.a_norm
+
+
+def test_argument_and_size_limits():
+    """Empty inputs, eps <= 0 or not finite, and sizes beyond the library's
+    limits (min(n, R) > 2048, n > 65536) are errors, raised before any kernel runs;
+    an all-zero input reduces to ranks (0, 0, 0)."""
+    import torch
+    from paper_2201_12663_amd import rhosvd
+    red = rhosvd.Reducer(precision="fp64")
+
+    def call(n, R, eps=1e-6):
+        U = [torch.zeros((R, n), dtype=torch.float64, device="cuda").t() for _ in range(3)]
+        xi = torch.zeros(R, dtype=torch.float64, device="cuda")
+        return red.reduce(U[0], U[1], U[2], xi, eps)
+
+    for args in [(0, 5), (5, 0), (4, 4, 0.0), (4, 4, -1.0), (4, 4, float("nan")), (4, 4, float("inf"))]:
+        with pytest.raises((rhosvd.RhosvdError, ValueError)):
+            call(*args)
+    for args in [(2049, 2049), (65537, 1)]:
+        with pytest.raises(rhosvd.RhosvdError) as ei:
+            call(*args)
+        assert ei.value.status == -7
+    assert call(4, 4) == (0, 0, 0)
+    red.close()
