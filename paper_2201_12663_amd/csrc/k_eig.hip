@@ -982,10 +982,12 @@ __global__ __launch_bounds__(256) void k_larft(BtJobs J) {
 //   Wm = V_b^T X (MFMA, 2 tiles x 2 halves of the rows), W2 = T_b Wm, X -= V_b W2 (MFMA).
 // XL: the slab lives in LDS as X[i * 16 + c]; otherwise it is updated in place in out.
 // grid: (slabs of the largest job, jobs); slabs at or beyond the job's rank exit.
+// BT_WAVES waves per workgroup (two per SIMD: the steps are latency-bound).
+constexpr int BT_WAVES = 8, BT_THREADS = 64 * BT_WAVES, BT_H = BT_WAVES / 2;
 template <bool XL>
-__global__ __launch_bounds__(256) void k_apply_wy(BtJobs J) {
+__global__ __launch_bounds__(BT_THREADS) void k_apply_wy(BtJobs J) {
     extern __shared__ double Xs[];              // mr x 16 when XL
-    __shared__ double P[2][NB][17];
+    __shared__ double P[BT_H][NB][17];
     __shared__ double W2[NB][17];
     constexpr int CW = 16;
     const BtJob& jb = J.job[blockIdx.y];
@@ -1001,7 +1003,7 @@ __global__ __launch_bounds__(256) void k_apply_wy(BtJobs J) {
     auto X = [&](int i, int c) -> double& { return XL ? Xs[i * CW + c] : Xo[i + (int64_t)c * ldo]; };
     // load the slab (columns beyond nc and rows beyond m are zero)
     const int rows_ld = XL ? mr : m;
-    for (int e = t; e < rows_ld * CW; e += 256) {
+    for (int e = t; e < rows_ld * CW; e += BT_THREADS) {
         const int c = e % CW, i = e / CW;
         double v = 0.0;
         if (c < nc && i < m) v = jb.Q[i + (int64_t)(jb.order ? jb.order[c0 + c] : c0 + c) * ld];
@@ -1011,28 +1013,29 @@ __global__ __launch_bounds__(256) void k_apply_wy(BtJobs J) {
     const int nblk = m >= 3 ? (m - 2 + NB - 1) / NB : 0;
     for (int b = nblk - 1; b >= 0; --b) {
         const int k0 = NB * b, kc = min(NB, (m - 2) - k0);
-        // pass 1: wave w -> tile jt = w & 1 of Wm, rows interleaved by halves h = w >> 1;
-        // the reflector values of the next 64 rows are loaded before this step's
-        // MFMAs, which alternate between two accumulators
+        // pass 1: wave w -> tile jt = w & 1 of Wm and the groups of 4 rows h, h + BT_H,
+        // h + 2 BT_H, .. (h = w / 2); the reflector values of the next 8 groups are
+        // loaded before this step's MFMAs, which alternate between two accumulators
         {
+            constexpr int RS = 4 * BT_H, RSTEP = 8 * RS;   // row stride between MFMAs, per step
             const int jt = w & 1, h = w >> 1;
             d4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
             double an[8];
             const int rfirst = k0 + 1 + 4 * h;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) an[u] = vb(Hv, ld, m, k0, 16 * jt + (lane & 15), kc, rfirst + 8 * u + (lane >> 4));
-            for (int row0 = rfirst; row0 < m; row0 += 64) {
+            for (int u = 0; u < 8; ++u) an[u] = vb(Hv, ld, m, k0, 16 * jt + (lane & 15), kc, rfirst + RS * u + (lane >> 4));
+            for (int row0 = rfirst; row0 < m; row0 += RSTEP) {
                 double av[8], bv[8];
 #pragma unroll
                 for (int u = 0; u < 8; ++u) av[u] = an[u];
-                if (row0 + 64 < m) {
+                if (row0 + RSTEP < m) {
 #pragma unroll
                     for (int u = 0; u < 8; ++u)
-                        an[u] = vb(Hv, ld, m, k0, 16 * jt + (lane & 15), kc, row0 + 64 + 8 * u + (lane >> 4));
+                        an[u] = vb(Hv, ld, m, k0, 16 * jt + (lane & 15), kc, row0 + RSTEP + RS * u + (lane >> 4));
                 }
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
-                    const int row = row0 + 8 * u + (lane >> 4);
+                    const int row = row0 + RS * u + (lane >> 4);
                     bv[u] = (row < m && (XL || (lane & 15) < nc)) ? X(row, lane & 15) : 0.0;
                 }
 #pragma unroll
@@ -1048,10 +1051,15 @@ __global__ __launch_bounds__(256) void k_apply_wy(BtJobs J) {
         // W2 = T_b Wm (T_b upper triangular, column-major)
         {
             const double* T = jb.Tw + (int64_t)b * NB * NB;
-            for (int e = t; e < NB * CW; e += 256) {
+            for (int e = t; e < NB * CW; e += BT_THREADS) {
                 const int j = e % NB, c = e / NB;
                 double s = 0.0;
-                for (int q = j; q < kc; ++q) s += T[j + q * NB] * (P[0][q][c] + P[1][q][c]);
+                for (int q = j; q < kc; ++q) {
+                    double pq = 0.0;
+#pragma unroll
+                    for (int hh = 0; hh < BT_H; ++hh) pq += P[hh][q][c];
+                    s += T[j + q * NB] * pq;
+                }
                 W2[j][c] = s;
             }
         }
@@ -1067,15 +1075,15 @@ __global__ __launch_bounds__(256) void k_apply_wy(BtJobs J) {
                 for (int st = 0; st < NB / 4; ++st)
                     an[st] = vb(Hv, ld, m, k0, 4 * st + (lane >> 4), kc, i0 + 16 * w + (lane & 15));
             }
-            for (int tl = w; tl < ntile; tl += 4) {
+            for (int tl = w; tl < ntile; tl += BT_WAVES) {
                 const int rb = i0 + 16 * tl;
                 double av[NB / 4];
 #pragma unroll
                 for (int st = 0; st < NB / 4; ++st) av[st] = an[st];
-                if (tl + 4 < ntile) {
+                if (tl + BT_WAVES < ntile) {
 #pragma unroll
                     for (int st = 0; st < NB / 4; ++st)
-                        an[st] = vb(Hv, ld, m, k0, 4 * st + (lane >> 4), kc, rb + 64 + (lane & 15));
+                        an[st] = vb(Hv, ld, m, k0, 4 * st + (lane >> 4), kc, rb + 16 * BT_WAVES + (lane & 15));
                 }
                 d4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -1093,12 +1101,12 @@ __global__ __launch_bounds__(256) void k_apply_wy(BtJobs J) {
         __syncthreads();
     }
     if (XL) {
-        for (int e = t; e < nrows * CW; e += 256) {
+        for (int e = t; e < nrows * CW; e += BT_THREADS) {
             const int i = e % nrows, c = e / nrows;
             if (c < nc) Xo[i + (int64_t)c * ldo] = (i < m) ? Xs[i * CW + c] : 0.0;
         }
     } else {
-        for (int e = t; e < nrows * CW; e += 256) {
+        for (int e = t; e < nrows * CW; e += BT_THREADS) {
             const int i = e % nrows, c = e / nrows;
             if (c < nc && i >= m) Xo[i + (int64_t)c * ldo] = 0.0;
         }
@@ -1393,9 +1401,9 @@ hipError_t launch_backtransform(const BtJob* jobs, int njobs, hipStream_t st) {
             if ((e = hipFuncSetAttribute((const void*)k_apply_wy<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                          (int)sh)) != hipSuccess)
                 return e;
-            hipLaunchKernelGGL((k_apply_wy<true>), grid, dim3(256), sh, st, J);
+            hipLaunchKernelGGL((k_apply_wy<true>), grid, dim3(BT_THREADS), sh, st, J);
         } else {
-            hipLaunchKernelGGL((k_apply_wy<false>), grid, dim3(256), 0, st, J);
+            hipLaunchKernelGGL((k_apply_wy<false>), grid, dim3(BT_THREADS), 0, st, J);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
