@@ -738,19 +738,46 @@ __global__ __launch_bounds__(256) void k_dc_roots(DCArgs a) {
         f = 1.0 + rho * wave_sum(f);
         o = (f > 0.0) ? j : j + 1;
     }
+    // f(t) = 1 + rho sum z_i^2 / ((d_i - d_o) - t) increases between the poles.
+    // Bisection until the bracket is 2^-20 of its first width, then Newton steps
+    // kept inside the bracket (which every evaluation narrows; a step leaving it is
+    // replaced by the midpoint) until a step falls below two ulps of t or no double
+    // is left inside the bracket.
     const double dorg = s_dd[o];
     double lo = lo_pole - dorg, hi = hi_pole - dorg;
+    const double w0 = hi - lo;
     for (int it = 0; it < 200; ++it) {
         const double tm = 0.5 * (lo + hi);
-        if (tm == lo || tm == hi) break;
+        if (tm == lo || tm == hi || hi - lo <= w0 * 0x1p-20) break;
         double f = 0.0;
         for (int i = lane; i < k; i += 64) f += s_z2[i] / ((s_dd[i] - dorg) - tm);
         f = 1.0 + rho * wave_sum(f);
         if (f > 0.0) hi = tm;
         else lo = tm;
     }
+    double tm = 0.5 * (lo + hi);
+    for (int it = 0; it < 64; ++it) {
+        if (tm == lo || tm == hi) break;
+        double f = 0.0, fp = 0.0;
+        for (int i = lane; i < k; i += 64) {
+            const double inv = 1.0 / ((s_dd[i] - dorg) - tm);
+            const double q = s_z2[i] * inv;
+            f += q;
+            fp += q * inv;
+        }
+        f = 1.0 + rho * wave_sum(f);
+        fp = rho * wave_sum(fp);
+        if (f == 0.0) break;
+        if (f > 0.0) hi = tm;
+        else lo = tm;
+        double nt = tm - f / fp;
+        if (!(nt > lo && nt < hi)) nt = 0.5 * (lo + hi);
+        const bool small = fabs(nt - tm) <= 2.0 * U64 * fabs(nt);
+        tm = nt;
+        if (small) break;
+    }
     if (lane == 0) {
-        ns_tau(a, node)[j] = 0.5 * (lo + hi);
+        ns_tau(a, node)[j] = tm;
         ns_org(a, node)[j] = o;
     }
 }
