@@ -284,6 +284,9 @@ __global__ __launch_bounds__(256) void k_tridiag(TriArgs a) {
     __syncthreads();
     if (m > 2 && c0 == 0 && nc > 0) form_reflector(slab, 0, M, red);
     for (int k = 0; k + 2 < m; ++k) {
+        // every own column is final (none > k): leave; the others skip this
+        // workgroup's partial sums from here on (they would be zero)
+        if (c0 + nc <= k + 1) break;
         const int par = k & 1;
         const uint32_t flag = (uint32_t)k + 1;
         // receive v_k (this thread's rows > k) and tau_k in one poll
@@ -349,7 +352,8 @@ __global__ __launch_bounds__(256) void k_tridiag(TriArgs a) {
                     w[q] = (i > k && i < m) ? xp(M, par) + 2 * i : nullptr;
                     val[q] = 0.0;
                 }
-                w[RPT] = (t < M.bpm) ? xpart(M, par) + 2 * t : nullptr;
+                const bool live = t < M.bpm && t * cpb + min(cpb, m - t * cpb) > k + 1;
+                w[RPT] = live ? xpart(M, par) + 2 * t : nullptr;
                 val[RPT] = 0.0;
                 ll_get<RPT + 1>(w, val, flag, a.abort_w);
 #pragma unroll
