@@ -307,6 +307,20 @@ def theorem23_bound(xi_norm: float, tail_at_rank: list) -> float:
     return xi_norm * float(sum(tail_at_rank))
 
 
+def certificate(Ut: list, xip: np.ndarray, Z: list) -> float:
+    """The bound reached inside the proof of Theorem 2.3 (Section 2.1) before its
+    final Cauchy-Schwarz step:
+        |A - A_r| <= sum_l sum_nu |xi'_nu| |(I - Z_l Z_l^T) u~_nu^(l)|,
+    each residual column formed directly (not from 1 - |Z^T u~|^2).  It is at
+    most |xi'| sum_l t_{l, r_l} and, like that bound, holds for any orthonormal
+    Z_l (the proof uses only |u~_nu| = 1 and |Z_l Z_l^T u~_nu| <= 1)."""
+    c = 0.0
+    for l in range(D):
+        Dl = Ut[l] - Z[l] @ (Z[l].T @ Ut[l])
+        c += float(np.abs(xip) @ np.sqrt(np.sum(Dl * Dl, axis=0)))
+    return c
+
+
 # ---------------------------------------------------------------------------
 # the whole reduction
 # ---------------------------------------------------------------------------

@@ -16,6 +16,9 @@ Pins:
   projection_identity  V V^T = diag(sigma_1^2..sigma_r^2)   (Z0^T U = D0 V0^T)
   pythagoras           |beta|^2 + err^2 = |A|^2 (A_r is an orthogonal projection)
   theorem23            err <= |xi'| sum_l t_{l,r_l} on signed random inputs
+  certificate          the bound inside the proof of Theorem 2.3: a closed form
+                       when every term lies in a known plane, and err <= c <= b
+                       on signed random inputs
   corollary24          (A) one orthonormal side matrix: |A| = |xi'|;
                        (B) non-negative data: |xi'| <= |A|
   degenerate           R = 1 and identical columns give rank (1,1,1), beta = +-xi'
@@ -160,6 +163,36 @@ def theorem23(orc):
         assert err <= eps * res.a_norm + slack
 
 
+def certificate(orc):
+    # closed form: per mode, every normalized term lies in the plane of two
+    # orthonormal vectors e1, e2, u~_nu = cos(a) e1 + sin(a) e2, and Z = [e1]; then
+    # |(I - Z Z^T) u~_nu| = |sin(a)| and c = sum_l sum_nu |xi'_nu| |sin(a_{l,nu})|
+    g = inputs.rng(inputs.WL_RANDOM, 111)
+    n, R = 9, 13
+    ang = g.uniform(-np.pi, np.pi, size=(3, R))
+    xi = g.uniform(0.5, 2.0, R) * np.where(g.uniform(size=R) < 0.5, -1.0, 1.0)
+    U, Z = [], []
+    for l in range(3):
+        E = _orth(g, n, 2)
+        U.append(E[:, :1] * np.cos(ang[l]) + E[:, 1:] * np.sin(ang[l]))
+        Z.append(E[:, :1])
+    Ut, xip, _, _ = orc.normalize(U, xi)
+    want = float(np.sum(np.abs(xi) * np.abs(np.sin(ang)).sum(axis=0)))
+    got = orc.certificate(Ut, xip, Z)
+    assert abs(got - want) <= 1e-13 * want, (got, want)
+    # err <= c <= b on signed random inputs, at the oracle's own cut
+    for seed, eps in [(0, 1e-2), (1, 1e-3), (2, 3e-2)]:
+        ci = inputs.small_gaussian_sum(60 + seed, n=14, R=33, eps=eps)
+        xs = ci.xi * np.where(g.uniform(size=33) < 0.5, -1.0, 1.0)
+        res = orc.rhosvd(ci.U, xs, eps)
+        Ut, xip, _, _ = orc.normalize(ci.U, xs)
+        err = float(np.linalg.norm((orc.full_tensor(Ut, xip) - orc.reconstruct(res.beta, res.Z)).ravel()))
+        c = orc.certificate(Ut, xip, res.Z)
+        slack = 1e-12 * res.a_norm
+        assert err <= c + slack, (err, c)
+        assert c <= res.bound + slack, (c, res.bound)
+
+
 def corollary24(orc):
     g = inputs.rng(inputs.WL_RANDOM, 104)
     n, R = 14, 9
@@ -210,5 +243,5 @@ def invariances(orc):
 
 
 ALL = [svd_known_spectrum, svd_vs_lapack, lowrank_exact, brute_force_error,
-       hosvd_special_case, projection_identity, pythagoras, theorem23, corollary24,
+       hosvd_special_case, projection_identity, pythagoras, theorem23, certificate, corollary24,
        degenerate, invariances]

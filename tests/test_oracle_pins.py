@@ -134,3 +134,25 @@ def test_planted_unsorted_vectors(orc, monkeypatch):
 def test_planted_transposed_projection(orc, monkeypatch):
     monkeypatch.setattr(orc, "project", lambda Z, Ut: (Ut.T @ Z).T[:, ::-1])
     assert _fails(orc, [pins.projection_identity, pins.lowrank_exact])
+
+
+def test_planted_squared_residuals_in_certificate(orc, monkeypatch):
+    def bad_cert(Ut, xip, Z):
+        c = 0.0
+        for l in range(3):
+            Dl = Ut[l] - Z[l] @ (Z[l].T @ Ut[l])
+            c += float(np.abs(xip) @ np.sum(Dl * Dl, axis=0))     # squared norms
+        return c
+    monkeypatch.setattr(orc, "certificate", bad_cert)
+    assert _fails(orc, [pins.certificate])
+
+
+def test_planted_signed_weights_in_certificate(orc, monkeypatch):
+    def bad_cert(Ut, xip, Z):
+        c = 0.0
+        for l in range(3):
+            Dl = Ut[l] - Z[l] @ (Z[l].T @ Ut[l])
+            c += float(xip @ np.sqrt(np.sum(Dl * Dl, axis=0)))     # xi' without |.|
+        return c
+    monkeypatch.setattr(orc, "certificate", bad_cert)
+    assert _fails(orc, [pins.certificate])
