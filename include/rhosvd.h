@@ -103,7 +103,13 @@ typedef struct {
                                 first rhosvd_reduce_batched of a plan does the same with
                                 the persistent core before recording its graph.  The FP64
                                 core has one tile (64).  See rhosvd_last_core_tile. */
-    int32_t reserved[2];     /* must be zero */
+    int32_t certificate;     /* nonzero: rhosvd_get with a report also forms the certificate
+                                inside the proof of Theorem 2.3,
+                                c = sum_l sum_nu |xi'_nu| |(I - Z_l Z_l^T) u~_nu^(l)| <= bound,
+                                each residual column formed directly in FP64 (from an FP64
+                                projection in every precision: one more n x r x R product per
+                                mode on the mixed paths).  Not formed by rhosvd_reduce_batched. */
+    int32_t reserved[1];     /* must be zero */
 } rhosvd_options;
 
 typedef struct {
@@ -116,6 +122,9 @@ typedef struct {
     int32_t m;           /* min(n, R): number of singular values per mode */
     int32_t eig_sweeps;  /* eigensolver sweeps used */
     int32_t dropped;     /* terms dropped because xi = 0 or a column is zero */
+    double certificate;  /* with the certificate option: sum_l sum_nu |xi'_nu| |(I - Z_l Z_l^T)
+                            u~_nu^(l)| (proof of Theorem 2.3), |A - A_r| <= certificate <= bound;
+                            -1 when not formed */
 } rhosvd_report;
 
 typedef struct rhosvd_ctx* rhosvd_handle;

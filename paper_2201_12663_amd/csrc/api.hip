@@ -73,6 +73,9 @@ struct rhosvd_ctx {
     void* V[3] = {};                     // zr_pad x R_pad (FP64 or FP32)
     double* Vref[3] = {};                // refine_tails with a mixed core: FP64 projection
     void* Asplit = nullptr;              // BF16x3 core: hi/lo bf16 planes of V1 diag(xi') (zr_pad x R_pad each)
+    double* Vc = nullptr;                // certificate on a mixed path: FP64 projection (zr_pad x R_pad)
+    double* cpart = nullptr;             // certificate: column sums of squares (n_pad / 64 x R_pad)
+    double* cout = nullptr;              // certificate: per-block partials of the three modes, then the sum
     double* Ud[3] = {};                  // refine_tails = 2: deflated side matrices (n_pad x R_pad)
     double* Zs[3] = {};                  //   second-pass vectors before re-orthogonalization (n_pad x zr_pad)
     double* Cz[3] = {};                  //   Z_k^T Z' (zr_pad x zr_pad)
@@ -144,8 +147,7 @@ rhosvd_status fail(rhosvd_ctx* h, rhosvd_status s, const std::string& msg) {
 rhosvd_status check_options(const rhosvd_options* o, std::string& msg) {
     if (!o) return RHOSVD_OK;
     if (o->precision < 0 || o->precision > 2) { msg = "unknown precision"; return RHOSVD_ERR_ARG; }
-    for (int i = 0; i < 2; ++i)
-        if (o->reserved[i] != 0) { msg = "reserved option fields must be zero"; return RHOSVD_ERR_ARG; }
+    if (o->reserved[0] != 0) { msg = "reserved option fields must be zero"; return RHOSVD_ERR_ARG; }
     if (o->refine_tails < 0 || o->refine_tails > 2) { msg = "refine_tails must be 0, 1 or 2"; return RHOSVD_ERR_ARG; }
     if (o->core_tile != 0 && !core_tile_valid(o->precision, o->core_tile)) {
         msg = "core_tile must be 0 (tuned), 64, or 128 (128 only for the FP32 and BF16x3 cores)";
@@ -207,6 +209,10 @@ size_t carve_all(rhosvd_ctx* h, char* base) {
         h->Cz[l] = deflate ? c.take<double>((size_t)zp * zp) : nullptr;
     }
     h->Asplit = h->opt.precision == RHOSVD_BF16X3 ? (void*)c.take<char>((size_t)zp * Rp * 4) : nullptr;
+    const bool cert = h->opt.certificate != 0;
+    h->Vc = (cert && esz == 4) ? c.take<double>((size_t)zp * Rp) : nullptr;
+    h->cpart = cert ? c.take<double>((size_t)(np / 64) * Rp) : nullptr;
+    h->cout = cert ? c.take<double>((size_t)3 * cert_blocks(Rp) + 8) : nullptr;
     h->dscr = (h->opt.refine_tails == 2 && !h->rside) ? c.take<double>((size_t)9 * (h->m_pad + 64)) : nullptr;
     h->rfloor = c.take<double>(4);
     h->xip = c.take<double>(Rp);
@@ -802,6 +808,21 @@ rhosvd_status rhosvd_get(rhosvd_handle h, double* Z1, double* Z2, double* Z3, vo
             CK(h, hipMemcpyAsync(sigma + off, h->sigma[l], (size_t)r * 8, hipMemcpyDeviceToDevice, st));
         off += r;
     }
+    const bool cert = report && h->opt.certificate && any;
+    if (cert) {
+        const int64_t nb = cert_blocks(h->R_pad);
+        for (int l = 0; l < 3; ++l) {
+            const double* V64 = (const double*)h->V[l];
+            if (h->vprec != RHOSVD_FP64) {
+                CK(h, launch_project(h->n_pad, h->R_pad, h->r_pad[l], h->Z[l], h->Ut[l], h->Vc, nullptr, st));
+                V64 = h->Vc;
+            }
+            CK(h, launch_cert_mode(h->n_pad, h->R_pad, h->r_pad[l], h->Z[l], V64, h->Ut[l], h->xip, h->cpart,
+                                   h->cout + l * nb, st));
+        }
+        CK(h, launch_floor_sum(h->cout, 3 * nb, h->cout + 3 * nb, st));
+        CK(h, hipMemcpyAsync(h->hostd + 8, h->cout + 3 * nb, 8, hipMemcpyDeviceToHost, st));
+    }
     if (report) {
         // tails at the ranks need one small read; only done when a report is requested
         double tl[3] = {0, 0, 0};
@@ -824,6 +845,7 @@ rhosvd_status rhosvd_get(rhosvd_handle h, double* Z1, double* Z2, double* Z3, vo
         report->m = (int)h->m;
         report->eig_sweeps = h->sweeps;
         report->dropped = h->dropped;
+        report->certificate = cert ? h->hostd[8] : -1.0;
     }
     return RHOSVD_OK;
 }

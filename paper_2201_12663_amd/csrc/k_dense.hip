@@ -704,3 +704,79 @@ hipError_t launch_resid_partials(int64_t n_pad, int64_t R_pad, int64_t p_pad, co
                        n_pad, R_pad, p_pad, Q, B, Ut, part);
     return hipGetLastError();
 }
+
+// ===========================================================================
+// The certificate inside the proof of Theorem 2.3:
+//   c_l = sum_nu |xi'_nu| |U~[:, nu] - Z V[:, nu]|   (V = Z^T U~ in FP64),
+// every residual column formed directly.  k_colresid2: per 64 x 64 tile the sum of
+// squares of each column's 64 residual entries -> part[tm * R_pad + col];
+// k_cert_cols: per column the fixed-order sum over the row tiles, its root times
+// |xi'|, one partial per 256 columns -> out[blockIdx.x].
+// ===========================================================================
+__global__ __launch_bounds__(256) void k_colresid2(int64_t n_pad, int64_t R_pad, int64_t p_pad,
+                                                   const double* __restrict__ Q, const double* __restrict__ B,
+                                                   const double* __restrict__ T, double* __restrict__ part) {
+    __shared__ double sA[2 * KC * LDS_STRIDE];
+    __shared__ double sB[2 * KC * LDS_STRIDE];
+    __shared__ double cs[2][T64];
+    const int64_t tn = blockIdx.x, tm = blockIdx.y;
+    d4_t acc[2][2];
+    zero_acc(acc);
+    tile64_f64<false, true>(Q, n_pad, B, p_pad, tm * T64, tn * T64, 0, p_pad, sA, sB, acc);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+    double sq[2] = {0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t r = tm * T64 + wr + a * 16 + c_row64(lane, i);
+                const int64_t c = tn * T64 + wc + b * 16 + c_col(lane);
+                const double d = T[r + c * n_pad] - acc[a][b][i];
+                sq[b] += d * d;
+            }
+    // lanes l, l ^ 16, l ^ 32, l ^ 48 hold the same column
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        sq[b] += __shfl_xor(sq[b], 16);
+        sq[b] += __shfl_xor(sq[b], 32);
+    }
+    if (lane < 16) {
+        cs[w >> 1][wc + lane] = sq[0];
+        cs[w >> 1][wc + 16 + lane] = sq[1];
+    }
+    __syncthreads();
+    if (threadIdx.x < T64) part[tm * R_pad + tn * T64 + threadIdx.x] = cs[0][threadIdx.x] + cs[1][threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void k_cert_cols(const double* __restrict__ part, int64_t ntm, int64_t R_pad,
+                                                   const double* __restrict__ xip, double* __restrict__ out) {
+    __shared__ double red[4];
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double v = 0.0;
+    if (c < R_pad) {
+        double s = 0.0;
+        for (int64_t rt = 0; rt < ntm; ++rt) s += part[rt * R_pad + c];
+        v = fabs(xip[c]) * sqrt(s);
+    }
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+int64_t cert_blocks(int64_t R_pad) { return (R_pad + 255) / 256; }
+
+hipError_t launch_cert_mode(int64_t n_pad, int64_t R_pad, int64_t p_pad, const double* Z, const double* V64,
+                            const double* Ut, const double* xip, double* part, double* out, hipStream_t st) {
+    if (n_pad % T64 || R_pad % T64 || p_pad % KC) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_colresid2, dim3((unsigned)(R_pad / T64), (unsigned)(n_pad / T64)), dim3(256), 0, st, n_pad,
+                       R_pad, p_pad, Z, V64, Ut, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cert_cols, dim3((unsigned)cert_blocks(R_pad)), dim3(256), 0, st, part, n_pad / T64, R_pad,
+                       xip, out);
+    return hipGetLastError();
+}

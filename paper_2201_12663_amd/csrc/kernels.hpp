@@ -42,6 +42,12 @@ hipError_t launch_resid_partials(int64_t n_pad, int64_t R_pad, int64_t p_pad, co
 //   b_kcontig: B(k,j) = B[k + j*ldb], else B[j + k*ldb]
 // out = T - Q B (n_pad x N_pad, ld n_pad; Q n_pad x p_pad ld n_pad; B p_pad x N_pad
 // ld p_pad); out may be T
+// The certificate inside the proof of Theorem 2.3 for one mode: per 256 columns,
+// sum_nu |xi'_nu| |U~[:, nu] - Z V[:, nu]| -> out[0 .. cert_blocks(R_pad)) (Z: n_pad x
+// p_pad, V: p_pad x R_pad FP64 = Z^T U~).  part: n_pad / 64 x R_pad doubles of scratch.
+int64_t cert_blocks(int64_t R_pad);
+hipError_t launch_cert_mode(int64_t n_pad, int64_t R_pad, int64_t p_pad, const double* Z, const double* V64,
+                            const double* Ut, const double* xip, double* part, double* out, hipStream_t st);
 hipError_t launch_residual(int64_t n_pad, int64_t N_pad, int64_t p_pad, const double* Q, const double* B,
                            const double* T, double* out, hipStream_t st);
 // deflated spectrum: sigma = [sig1[0..k), sig2[0..m-k)], tails from tails2 plus sig1

@@ -35,13 +35,14 @@ PATHS = {0: "range finder", 1: "gram (chosen)", 2: "gram (certificate failed)", 
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("max_eig_sweeps", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("beta_fp32", ctypes.c_int32), ("refine_tails", ctypes.c_int32),
-                ("core_tile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("core_tile", ctypes.c_int32), ("certificate", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
 
 class Report(ctypes.Structure):
     _fields_ = [("xi_norm", ctypes.c_double), ("a_norm", ctypes.c_double), ("tau", ctypes.c_double),
                 ("bound", ctypes.c_double), ("tail", ctypes.c_double * 3), ("ranks", ctypes.c_int32 * 3),
-                ("m", ctypes.c_int32), ("eig_sweeps", ctypes.c_int32), ("dropped", ctypes.c_int32)]
+                ("m", ctypes.c_int32), ("eig_sweeps", ctypes.c_int32), ("dropped", ctypes.c_int32),
+                ("certificate", ctypes.c_double)]
 
 
 class Problem(ctypes.Structure):
@@ -151,11 +152,12 @@ class Reducer:
     """One library handle bound to a stream."""
 
     def __init__(self, precision="fp64", stream=None, max_eig_sweeps=0, profile=False, beta_fp32=False,
-                 refine_tails=False, core_tile=0):
+                 refine_tails=False, core_tile=0, certificate=False):
         import torch
         self.lib = load()
         self.opt = Options()
         self.opt.core_tile = int(core_tile)
+        self.opt.certificate = 1 if certificate else 0
         self.opt.beta_fp32 = 1 if beta_fp32 else 0
         self.opt.refine_tails = int(refine_tails) if refine_tails in (0, 1, 2) else -1
         self.beta_dtype = torch.float32 if beta_fp32 else torch.float64
@@ -230,7 +232,7 @@ class Reducer:
                                         ctypes.byref(rep)))
         report = dict(xi_norm=rep.xi_norm, a_norm=rep.a_norm, tau=rep.tau, bound=rep.bound,
                       tail=list(rep.tail), ranks=list(rep.ranks), m=rep.m, eig_sweeps=rep.eig_sweeps,
-                      dropped=rep.dropped)
+                      dropped=rep.dropped, certificate=rep.certificate)
         beta_t = None
         if b is not None:
             beta_t = b.view(r3, r2, r1).permute(2, 1, 0) if b.numel() > 0 else b.view(r1, r2, r3)

@@ -48,8 +48,8 @@ def test_version_and_null_handle_errors(lib):
 def test_struct_layouts_match_header():
     from paper_2201_12663_amd import rhosvd
     assert ctypes.sizeof(rhosvd.Options) == 32
-    # 4 doubles + 3 doubles + 3 int32 + 3 int32 = 56 + 24 = 80
-    assert ctypes.sizeof(rhosvd.Report) == 80
+    # 4 doubles + 3 doubles + 3 int32 + 3 int32 + 1 double = 56 + 24 + 8 = 88
+    assert ctypes.sizeof(rhosvd.Report) == 88
 
 
 def test_null_handle_batched(lib):

@@ -375,3 +375,40 @@ def test_argument_and_size_limits():
         assert ei.value.status == -7
     assert call(4, 4) == (0, 0, 0)
     red.close()
+
+
+CERT_CASES = [("newton n160 R640", lambda: inputs.newton_centres(2, n=160, n_centres=20, eps=1e-5)),
+              ("gauss n200 R90 (R<n)", lambda: inputs.small_gaussian_sum(11, n=200, R=90, eps=1e-5)),
+              ("gauss n100 R333", lambda: inputs.small_gaussian_sum(1, n=100, R=333, eps=1e-3))]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("name,make", CERT_CASES, ids=[c[0] for c in CERT_CASES])
+def test_certificate(orc, name, make, prec):
+    """The certificate from the proof of Theorem 2.3 (certificate option): equal to
+    the oracle's certificate of the GPU's own Z, the same in every precision (it
+    uses an FP64 projection), and err <= c <= bound."""
+    import torch
+    from paper_2201_12663_amd import rhosvd
+    ci = make()
+    U = [rhosvd.to_device(u) for u in ci.U]
+    xi = torch.from_numpy(np.ascontiguousarray(ci.xi)).cuda()
+    red = rhosvd.Reducer(precision=prec, certificate=True)
+    red.reduce(U[0], U[1], U[2], xi, ci.eps)
+    res = red.get()
+    torch.cuda.synchronize()
+    Z = [z.cpu().numpy() for z in res.Z]
+    red.close()
+    c = res.report["certificate"]
+    Ut, xip, _, _ = orc.normalize(ci.U, ci.xi)
+    co = orc.certificate(Ut, xip, Z)
+    _flush(f"{name} {prec}: certificate {c:.6e} (oracle {co:.6e}), bound {res.report['bound']:.6e}")
+    assert abs(c - co) <= 1e-8 * co + 1e-13 * float(np.sum(np.abs(xip)))
+    assert c <= res.report["bound"] * (1 + 1e-9)
+    if prec == "fp64":
+        err = orc.error_gram(Ut, xip, Z)
+        assert err <= c * (1 + 1e-9) + 1e-12 * res.report["a_norm"]
+    plain = rhosvd.Reducer(precision=prec)
+    plain.reduce(U[0], U[1], U[2], xi, ci.eps)
+    assert plain.get(beta=False, Z=False, sigma=False).report["certificate"] == -1.0
+    plain.close()
