@@ -19,7 +19,7 @@ through the learned path (trained network, certified range finder, fallback)
 against the plain method; and "batched": the uneven batch (256 problems, n uniform in
 {128,...,2048}, R log-uniform in [64, 8192], each the first R terms of ceil(R/32)
 charges x 32 Gaussian terms, eps = 1e-5) as one graph-recorded batched pass
-(FP32-MFMA cores, FP64 eigensolver), timed over replays, next to the plain FP64
+(BF16x3 cores by default, FP64 eigensolver), timed over replays, next to the plain FP64
 single-problem path over the same problems.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-batch]
