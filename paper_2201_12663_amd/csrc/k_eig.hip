@@ -1009,18 +1009,19 @@ __global__ __launch_bounds__(256) void k_larft(BtJobs J) {
     for (int e = t; e < NB * NB; e += 256) jb.Tw[(int64_t)b * NB * NB + e] = T[e % NB][e / NB];
 }
 
-// X <- H X for a slab of 16 columns of X (one workgroup), blocks applied last first:
+// X <- H X for a slab of CW columns of X (one workgroup), blocks applied last first:
 //   Wm = V_b^T X (MFMA, 2 tiles x 2 halves of the rows), W2 = T_b Wm, X -= V_b W2 (MFMA).
-// XL: the slab lives in LDS as X[i * 16 + c]; otherwise it is updated in place in out.
+// XL: the slab lives in LDS as X[i * CW + c]; otherwise it is updated in place in out.
+// CW = 16, or 8 where 16 columns of m rows do not fit in LDS (the MFMA lanes of
+// columns 8 .. 15 then carry zeros and their results are not stored).
 // grid: (slabs of the largest job, jobs); slabs at or beyond the job's rank exit.
 // BT_WAVES waves per workgroup (two per SIMD: the steps are latency-bound).
 constexpr int BT_WAVES = 8, BT_THREADS = 64 * BT_WAVES, BT_H = BT_WAVES / 2;
-template <bool XL>
+template <bool XL, int CW>
 __global__ __launch_bounds__(BT_THREADS) void k_apply_wy(BtJobs J) {
     extern __shared__ double Xs[];              // mr x 16 when XL
     __shared__ double P[BT_H][NB][17];
     __shared__ double W2[NB][17];
-    constexpr int CW = 16;
     const BtJob& jb = J.job[blockIdx.y];
     const int m = jb.m, ld = jb.ld, ldo = jb.ldo, nrows = jb.nrows;
     const int r = jb.r_dev ? min(*jb.r_dev, jb.r) : jb.r;
@@ -1040,6 +1041,7 @@ __global__ __launch_bounds__(BT_THREADS) void k_apply_wy(BtJobs J) {
         if (c < nc && i < m) v = jb.Q[i + (int64_t)(jb.order ? jb.order[c0 + c] : c0 + c) * ld];
         if (XL || c < nc) X(i, c) = v;
     }
+    for (int e = t; e < NB * 17; e += BT_THREADS) (&W2[0][0])[e] = 0.0;   // columns >= CW stay zero
     __syncthreads();
     const int nblk = m >= 3 ? (m - 2 + NB - 1) / NB : 0;
     for (int b = nblk - 1; b >= 0; --b) {
@@ -1067,7 +1069,7 @@ __global__ __launch_bounds__(BT_THREADS) void k_apply_wy(BtJobs J) {
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     const int row = row0 + RS * u + (lane >> 4);
-                    bv[u] = (row < m && (XL || (lane & 15) < nc)) ? X(row, lane & 15) : 0.0;
+                    bv[u] = (row < m && (lane & 15) < (XL ? CW : nc)) ? X(row, lane & 15) : 0.0;
                 }
 #pragma unroll
                 for (int u = 0; u < 8; u += 2) {
@@ -1125,7 +1127,7 @@ __global__ __launch_bounds__(BT_THREADS) void k_apply_wy(BtJobs J) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int row = rb + c_row64(lane, q);
-                    if (row < m && (XL || c_col(lane) < nc)) X(row, c_col(lane)) -= acc0[q] + acc1[q];
+                    if (row < m && c_col(lane) < (XL ? CW : nc)) X(row, c_col(lane)) -= acc0[q] + acc1[q];
                 }
             }
         }
@@ -1426,15 +1428,22 @@ hipError_t launch_backtransform(const BtJob* jobs, int njobs, hipStream_t st) {
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         const int mr = (mmax + 63) & ~63;
-        const size_t sh = (size_t)16 * mr * sizeof(double);
-        const dim3 grid((unsigned)((rmax + 15) / 16), (unsigned)cnt);
-        if (sh <= 128 * 1024) {
-            if ((e = hipFuncSetAttribute((const void*)k_apply_wy<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         (int)sh)) != hipSuccess)
+        const size_t sh16 = (size_t)16 * mr * sizeof(double), sh8 = sh16 / 2;
+        if (sh16 <= 128 * 1024) {
+            if ((e = hipFuncSetAttribute((const void*)k_apply_wy<true, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)sh16)) != hipSuccess)
                 return e;
-            hipLaunchKernelGGL((k_apply_wy<true>), grid, dim3(BT_THREADS), sh, st, J);
+            hipLaunchKernelGGL((k_apply_wy<true, 16>), dim3((unsigned)((rmax + 15) / 16), (unsigned)cnt),
+                               dim3(BT_THREADS), sh16, st, J);
+        } else if (sh8 <= 128 * 1024) {
+            if ((e = hipFuncSetAttribute((const void*)k_apply_wy<true, 8>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)sh8)) != hipSuccess)
+                return e;
+            hipLaunchKernelGGL((k_apply_wy<true, 8>), dim3((unsigned)((rmax + 7) / 8), (unsigned)cnt),
+                               dim3(BT_THREADS), sh8, st, J);
         } else {
-            hipLaunchKernelGGL((k_apply_wy<false>), grid, dim3(BT_THREADS), 0, st, J);
+            hipLaunchKernelGGL((k_apply_wy<false, 16>), dim3((unsigned)((rmax + 15) / 16), (unsigned)cnt),
+                               dim3(BT_THREADS), 0, st, J);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
