@@ -412,3 +412,29 @@ def test_certificate(orc, name, make, prec):
     plain.reduce(U[0], U[1], U[2], xi, ci.eps)
     assert plain.get(beta=False, Z=False, sigma=False).report["certificate"] == -1.0
     plain.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_certificate_after_deflated_pass(orc, prec):
+    """The certificate also covers the Z of the deflated second pass (A9: any
+    orthonormal Z), and stays below that path's bound."""
+    import torch
+    from paper_2201_12663_amd import rhosvd
+    n, R, eps = 256, 2048, 1e-6
+    a, c, xi = inputs.smooth_problem_params(9, 0, n, R)
+    ci = inputs.CanonicalInput(inputs.gaussian_side_matrices(inputs.grid(n), a, c), xi, eps)
+    U = [rhosvd.to_device(u) for u in ci.U]
+    xd = torch.from_numpy(ci.xi).cuda()
+    red = rhosvd.Reducer(precision=prec, refine_tails=2, certificate=True)
+    red.reduce(U[0], U[1], U[2], xd, eps)
+    res = red.get()
+    torch.cuda.synchronize()
+    Z = [z.cpu().numpy() for z in res.Z]
+    red.close()
+    Ut, xip, _, _ = orc.normalize(ci.U, ci.xi)
+    co = orc.certificate(Ut, xip, Z)
+    cg = res.report["certificate"]
+    _flush(f"deflated {prec}: ranks {res.ranks} certificate {cg:.6e} (oracle {co:.6e}) bound {res.report['bound']:.6e}")
+    assert abs(cg - co) <= 1e-8 * co + 1e-13 * float(np.sum(np.abs(xip)))
+    assert cg <= res.report["bound"] * (1 + 1e-9)
+    assert orc.error_gram(Ut, xip, Z) <= cg * (1 + 1e-9) + 1e-12 * res.report["a_norm"]
