@@ -336,8 +336,13 @@ __device__ __forceinline__ void core_tile_bf16x3(int r1, int r2, int r3, int ld2
                            acc[f][g][i]);
 }
 
+// Two waves per SIMD at least: the 128-row tile then fits 256 registers (its
+// accumulators are 128 of them) with a few spills outside the K loop, instead
+// of 260 registers at one wave per SIMD; the 64-row tile drops to 165
+// registers.  The 128-row tile forms each Khatri-Rao fragment once for twice
+// the MFMAs, which is what the kernel's time follows.
 template <typename O, bool FLUSH, int NF>
-__global__ __launch_bounds__(256) void k_core_bf16x3(int r1, int r2, int r3, int ld2, int ld3, int64_t Kp,
+__global__ __launch_bounds__(256, 2) void k_core_bf16x3(int r1, int r2, int r3, int ld2, int ld3, int64_t Kp,
                                                      const __bf16* __restrict__ Ah, const __bf16* __restrict__ Al,
                                                      const float* __restrict__ V2, const float* __restrict__ V3,
                                                      O* __restrict__ beta, int MT, int N2T, int N3T, int64_t per) {
@@ -424,8 +429,9 @@ __global__ void k_core_plan_b(const BProb* __restrict__ P, int np, int tm, int64
     work[0] = 0;
 }
 
+// the BF16x3 instances at two waves per SIMD, as k_core_bf16x3
 template <int PREC, typename O, bool FLUSH, int NF>
-__global__ __launch_bounds__(256) void k_core_persist_b(const BProb* __restrict__ P, int np,
+__global__ __launch_bounds__(256, PREC == 2 ? 2 : 1) void k_core_persist_b(const BProb* __restrict__ P, int np,
                                                         int64_t* __restrict__ work) {
     __shared__ int64_t s_tile;
     const int64_t total = work[1];
