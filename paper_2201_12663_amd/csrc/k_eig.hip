@@ -393,18 +393,21 @@ __global__ __launch_bounds__(256) void k_tridiag(TriArgs a) {
     }
 }
 
-// rows per thread of the launch: the smallest power of two with 256 RPT >= m
-static int tri_rpt(int m) {
-    int r = 1;
-    while (256 * r < m) r *= 2;
-    return r;
-}
+// rows per thread of the launch: the smallest RPT with 256 RPT >= m (1..8).
+// Every RPT has its own instance, so a column of m rows occupies 256 RPT rows of
+// LDS and no more (m = 1100: 1280 rows, 14 columns per workgroup, where the next
+// power of two would store 2048 rows and fit 9)
+static int tri_rpt(int m) { return std::max(1, (m + 255) / 256); }
 
 static const void* tri_kernel(int rpt) {
     switch (rpt) {
         case 1: return (const void*)k_tridiag<1>;
         case 2: return (const void*)k_tridiag<2>;
+        case 3: return (const void*)k_tridiag<3>;
         case 4: return (const void*)k_tridiag<4>;
+        case 5: return (const void*)k_tridiag<5>;
+        case 6: return (const void*)k_tridiag<6>;
+        case 7: return (const void*)k_tridiag<7>;
         default: return (const void*)k_tridiag<8>;
     }
 }
@@ -1378,7 +1381,11 @@ hipError_t eig_plan_enqueue(const EigPlan* P, int* abort_w, hipStream_t st, bool
             switch (L.rpt) {
                 case 1: hipLaunchKernelGGL(k_tridiag<1>, dim3(L.nblocks), dim3(256), L.shbytes, st, ta); break;
                 case 2: hipLaunchKernelGGL(k_tridiag<2>, dim3(L.nblocks), dim3(256), L.shbytes, st, ta); break;
+                case 3: hipLaunchKernelGGL(k_tridiag<3>, dim3(L.nblocks), dim3(256), L.shbytes, st, ta); break;
                 case 4: hipLaunchKernelGGL(k_tridiag<4>, dim3(L.nblocks), dim3(256), L.shbytes, st, ta); break;
+                case 5: hipLaunchKernelGGL(k_tridiag<5>, dim3(L.nblocks), dim3(256), L.shbytes, st, ta); break;
+                case 6: hipLaunchKernelGGL(k_tridiag<6>, dim3(L.nblocks), dim3(256), L.shbytes, st, ta); break;
+                case 7: hipLaunchKernelGGL(k_tridiag<7>, dim3(L.nblocks), dim3(256), L.shbytes, st, ta); break;
                 default: hipLaunchKernelGGL(k_tridiag<8>, dim3(L.nblocks), dim3(256), L.shbytes, st, ta); break;
             }
             if ((e = hipGetLastError()) != hipSuccess) return e;
