@@ -65,7 +65,7 @@ struct TriArgs {
     int* abort_w;       // set to 1 when an exchange wait ran out
 };
 
-__host__ __device__ constexpr size_t tri_xwords(int m) { return (size_t)8 * ((m + 63) & ~63) + 4 * 256 + 8; }
+__host__ __device__ constexpr size_t tri_xwords(int m) { return (size_t)8 * ((m + 63) & ~63) + 8; }
 
 // Cross-workgroup exchange of the tridiagonalization.  A double travels as two
 // 64-bit words {32 data bits, 32 flag bits}, each written by one agent-scope
@@ -130,16 +130,14 @@ __device__ __forceinline__ void ll_get(const uint64_t* const (&w)[N], double (&o
     }
 }
 
-// word offsets inside a matrix's exchange area
+// word offsets inside a matrix's exchange area (a word pair per value; v and p
+// by row, per step parity)
 __device__ __forceinline__ uint64_t* xv(const TriMat& M, int par) { return M.x + (size_t)par * 2 * ((M.m + 63) & ~63); }
 __device__ __forceinline__ uint64_t* xp(const TriMat& M, int par) {
-    return M.x + (size_t)4 * ((M.m + 63) & ~63) + (size_t)par * 2 * ((M.m + 63) & ~63);
-}
-__device__ __forceinline__ uint64_t* xpart(const TriMat& M, int par) {
-    return M.x + (size_t)8 * ((M.m + 63) & ~63) + (size_t)par * 2 * 256;
+    return M.x + (size_t)(2 + par) * 2 * ((M.m + 63) & ~63);
 }
 __device__ __forceinline__ uint64_t* xtau(const TriMat& M, int par) {
-    return M.x + (size_t)8 * ((M.m + 63) & ~63) + 4 * 256 + 2 * par;
+    return M.x + (size_t)8 * ((M.m + 63) & ~63) + 2 * par;
 }
 
 // reflector k from the (current) column k held in LDS: v (rows k+1..m-1,
@@ -269,7 +267,7 @@ __global__ __launch_bounds__(256) void k_tridiag(TriArgs a) {
     __shared__ double red[4];
     __shared__ double red2[CMAX * 4];
     __shared__ double vjs[CMAX], wjs[CMAX], pjs[CMAX];
-    static_assert(CMAX == 32, "one butterfly reduction covers 31 columns and the partial p.v");
+    static_assert(CMAX == 32, "one butterfly reduction covers the (at most 31) columns");
     int q0 = 0;
     while (q0 + 1 < a.nmat && (int)blockIdx.x >= a.mat[q0 + 1].blk0) ++q0;
     const TriMat& M = a.mat[q0];
@@ -284,8 +282,7 @@ __global__ __launch_bounds__(256) void k_tridiag(TriArgs a) {
     __syncthreads();
     if (m > 2 && c0 == 0 && nc > 0) form_reflector(slab, 0, M, red);
     for (int k = 0; k + 2 < m; ++k) {
-        // every own column is final (none > k): leave; the others skip this
-        // workgroup's partial sums from here on (they would be zero)
+        // every own column is final (none > k): leave
         if (c0 + nc <= k + 1) break;
         const int par = k & 1;
         const uint32_t flag = (uint32_t)k + 1;
@@ -317,7 +314,6 @@ __global__ __launch_bounds__(256) void k_tridiag(TriArgs a) {
         {
             // p_j = tau sum_i G[i,j] v_i for own columns j > k (exchanged even when
             // tau = 0: the all-gather of p orders the reuse of the step buffers)
-            // slot CMAX-1 carries this thread's part of sum_j (G v)_j v_j
             double acc[CMAX];
             acc[CMAX - 1] = 0.0;
 #pragma unroll
@@ -326,7 +322,6 @@ __global__ __launch_bounds__(256) void k_tridiag(TriArgs a) {
                 if (c >= cs && c < nc) {
 #pragma unroll
                     for (int q = 0; q < RPT; ++q) acc[c] += slab[c * S + t + 256 * q] * vr[q];
-                    acc[CMAX - 1] += acc[c] * vjs[c];
                 }
             }
             const double sw = wave_sum32(acc, lane);   // lane l: slot l >> 1
@@ -337,30 +332,27 @@ __global__ __launch_bounds__(256) void k_tridiag(TriArgs a) {
                 ll_put(xp(M, par) + 2 * (c0 + t), pj, flag);
                 pjs[t] = pj;
             }
-            if (t == 0) {
-                constexpr int P = (CMAX - 1) * 4;
-                ll_put(xpart(M, par) + 2 * gb, tau * ((red2[P] + red2[P + 1]) + (red2[P + 2] + red2[P + 3])), flag);
-            }
-            // receive p (this thread's rows > k) and one per-block partial sum in one poll
+            // receive p (this thread's rows > k)
             double pr[RPT], partial = 0.0;
             {
-                const uint64_t* w[RPT + 1];
-                double val[RPT + 1];
+                const uint64_t* w[RPT];
+                double val[RPT];
 #pragma unroll
                 for (int q = 0; q < RPT; ++q) {
                     const int i = t + 256 * q;
                     w[q] = (i > k && i < m) ? xp(M, par) + 2 * i : nullptr;
                     val[q] = 0.0;
                 }
-                const bool live = t < M.bpm && t * cpb + min(cpb, m - t * cpb) > k + 1;
-                w[RPT] = live ? xpart(M, par) + 2 * t : nullptr;
-                val[RPT] = 0.0;
-                ll_get<RPT + 1>(w, val, flag, a.abort_w);
+                ll_get<RPT>(w, val, flag, a.abort_w);
 #pragma unroll
-                for (int q = 0; q < RPT; ++q) pr[q] = val[q];
-                partial = val[RPT];
+                for (int q = 0; q < RPT; ++q) {
+                    pr[q] = val[q];
+                    partial += pr[q] * vr[q];
+                }
             }
-            // the same sum, in the same order, in every workgroup of the matrix
+            // p.v over all rows, by the same threads in the same order in every
+            // workgroup of the matrix, so the sum does not depend on how the
+            // columns are split among workgroups (and needs no exchange of its own)
             const double cw = 0.5 * tau * block_sum256(partial, red);
             if (t >= cs && t < nc) wjs[t] = pjs[t] - cw * vjs[t];
             __syncthreads();
