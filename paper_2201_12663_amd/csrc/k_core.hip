@@ -185,8 +185,11 @@ __device__ __forceinline__ void core_tile_std(int r1, int r2, int r3, int ld1, i
                            acc[f][g][i]);
 }
 
+// Two waves per SIMD at least: the FP32 instances with the hand-over of long
+// contractions then fit without spills (436 -> 256 registers at 128 rows,
+// 212 -> 126 at 64), and the 128-row tile without it drops from 268 to 192.
 template <typename T, typename O, bool FLUSH, int NF>
-__global__ __launch_bounds__(256) void k_core_std(int r1, int r2, int r3, int ld1, int ld2, int ld3,
+__global__ __launch_bounds__(256, 2) void k_core_std(int r1, int r2, int r3, int ld1, int ld2, int ld3,
                                                   int64_t Kp, const T* __restrict__ V1,
                                                   const T* __restrict__ V2, const T* __restrict__ V3,
                                                   const double* __restrict__ xip, O* __restrict__ beta,
