@@ -24,6 +24,16 @@ Pins:
   degenerate           R = 1 and identical columns give rank (1,1,1), beta = +-xi'
   invariances          term permutation, column rescaling with compensated xi,
                        orthogonal row transform of one mode
+  truncation_rule      ranks of hand-built inputs whose |A|, |xi'| and side-matrix
+                       spectra are known in closed form (Corollary 2.4(A): one
+                       orthonormal side matrix gives |A| = |xi'|; all terms equal
+                       in two modes gives |A| = |sum of the third mode's vectors|),
+                       with eps placed so that tau = eps |A| / (d |xi'|) and each
+                       plausible variant of it (d dropped, d squared, |A|/|xi'|
+                       ignored, raw xi instead of xi') give different ranks
+  sign_rule            the reading's sign convention on hand-built vectors
+                       (largest-magnitude entry positive, ties to the lowest
+                       index) and on a singular vector known in closed form
 """
 from __future__ import annotations
 
@@ -242,6 +252,90 @@ def invariances(orc):
     assert _proj_dist(res.Z[0], Q @ base.Z[0]) < 1e-8
 
 
+def _plane(E, ang):
+    """Unit vectors cos(a) e1 + sin(a) e2 in the plane of the orthonormal pair E."""
+    return E[:, :1] * np.cos(ang) + E[:, 1:] * np.sin(ang)
+
+
+def truncation_rule(orc):
+    """Ranks fixed by closed forms.  A side matrix whose unit columns are
+    cos(a_nu) e1 + sin(a_nu) e2 with the angles +a and -a equally often has
+    U~ U~^T = R cos^2(a) e1 e1^T + R sin^2(a) e2 e2^T, so sigma = (sqrt(R) cos a,
+    sqrt(R) |sin a|, 0, ...) and its first tail is t_1 = sqrt(R) |sin a|
+    (Theorem 2.3's sum over the discarded singular values)."""
+    g = inputs.rng(inputs.WL_RANDOM, 120)
+    eps = 1e-3
+    # case 1 (Corollary 2.4(A)): U^(1) has orthonormal columns, so |A| = |xi'| and
+    # tau = eps / 3.  Mode 2: t_1 = 0.6 tau (rank 1; 2 if tau had d^2),
+    # mode 3: t_1 = 1.5 tau (rank 2; 1 if tau lacked d).  Columns are scaled and xi
+    # compensated, so xi' = (1, -0.5, 0.7, 1.3) while the raw xi is not.
+    n, R = 8, 4
+    Q = _orth(g, n, n)
+    c = g.uniform(0.5, 2.0, size=(3, R))
+    sg = np.array([1.0, 1.0, -1.0, -1.0])
+    a2 = math.asin(0.6 * (eps / 3) / 2.0)          # t_1 = 2 sin(a2)
+    a3 = math.asin(1.5 * (eps / 3) / 2.0)
+    E2, E3 = _orth(g, n, 2), _orth(g, n, 2)
+    U = [Q[:, :R] * c[0], _plane(E2, a2 * sg) * c[1], _plane(E3, a3 * sg) * c[2]]
+    xip = np.array([1.0, -0.5, 0.7, 1.3])
+    res = orc.rhosvd(U, xip / np.prod(c, axis=0), eps)
+    assert abs(res.a_norm - np.linalg.norm(xip)) <= 1e-13 * res.a_norm     # |A| = |xi'|
+    assert abs(res.tau - eps / 3) <= 1e-14 * eps, (res.tau, eps / 3)
+    assert tuple(res.ranks) == (4, 1, 2), res.ranks
+    # case 2: modes 1 and 2 hold one unit vector e for every term and xi' = 1, so
+    # A = e (x) e (x) sum_nu u3_nu and |A| = R cos(a) while |xi'| = sqrt(R).  With
+    # R = 16, tan(a) = 0.8 eps / 3: t_1 = 4 sin a <= tau = (4/3) eps cos a, rank 1;
+    # with tau = eps / 3, eps |A| / (9 |xi'|) or the raw |xi| (= 32 |xi'| / 4) it is 2.
+    R = 16
+    e = _orth(g, n, 1)
+    E = _orth(g, n, 2)
+    a = math.atan(0.8 * eps / 3)
+    sg = np.where(np.arange(R) % 2 == 0, 1.0, -1.0)
+    c = np.full((3, R), 0.5)
+    U = [np.repeat(e, R, axis=1) * c[0], np.repeat(e, R, axis=1) * c[1], _plane(E, a * sg) * c[2]]
+    res = orc.rhosvd(U, 1.0 / np.prod(c, axis=0), eps)
+    assert abs(res.a_norm - R * math.cos(a)) <= 1e-13 * R
+    assert abs(res.xi_norm - 4.0) <= 1e-14
+    assert tuple(res.ranks) == (1, 1, 1), res.ranks
+    # the guarantee the rule is chosen for: |A - A_r| <= eps |A| (brute force)
+    Ut, xp, _, _ = orc.normalize(U, 1.0 / np.prod(c, axis=0))
+    err = float(np.linalg.norm((orc.full_tensor(Ut, xp) - orc.reconstruct(res.beta, res.Z)).ravel()))
+    assert err <= eps * res.a_norm
+    # the same input with eps lowered below the cut's closed-form threshold
+    # (tan a = 1.25 eps' / 3 > eps' / 3) keeps the second direction
+    res = orc.rhosvd(U, 1.0 / np.prod(c, axis=0), eps * 0.64)
+    assert tuple(res.ranks) == (1, 1, 2), res.ranks
+
+
+def sign_rule(orc):
+    """Each kept singular vector has its largest-magnitude entry positive, the
+    lowest index winning a tie."""
+    Z = np.array([[0.6, -0.8, 0.5, -0.5],
+                  [-0.8, 0.6, -0.5, 0.5],
+                  [0.0, 0.0, 0.5, 0.5],
+                  [0.0, 0.0, -0.5, 0.5]])
+    want = np.array([[-0.6, 0.8, 0.5, 0.5],
+                     [0.8, -0.6, -0.5, -0.5],
+                     [0.0, 0.0, 0.5, -0.5],
+                     [0.0, 0.0, -0.5, -0.5]])
+    assert np.array_equal(orc.sign_normalize(Z), want)
+    # end to end: the leading left singular vector of a plane side matrix is
+    # +-e1 (sigma_1 = sqrt(R) cos a >> sigma_2); e1 is built with its
+    # largest-magnitude entry negative, so the rule returns -e1
+    g = inputs.rng(inputs.WL_RANDOM, 121)
+    n, R = 6, 10
+    e1 = np.array([0.1, -0.9, 0.3, 0.2, -0.1, 0.15])
+    e1 /= np.linalg.norm(e1)
+    e2 = g.standard_normal(n)
+    e2 -= (e2 @ e1) * e1
+    e2 /= np.linalg.norm(e2)
+    E = np.stack([e1, e2], axis=1)
+    ang = 0.3 * np.where(np.arange(R) % 2 == 0, 1.0, -1.0)
+    U = [_plane(E, ang), g.standard_normal((n, R)), g.standard_normal((n, R))]
+    res = orc.rhosvd(U, g.uniform(0.5, 1.5, R), eps=1e-6)
+    assert np.max(np.abs(res.Z[0][:, 0] + e1)) < 1e-12, res.Z[0][:, 0]
+
+
 ALL = [svd_known_spectrum, svd_vs_lapack, lowrank_exact, brute_force_error,
        hosvd_special_case, projection_identity, pythagoras, theorem23, certificate, corollary24,
-       degenerate, invariances]
+       degenerate, invariances, truncation_rule, sign_rule]

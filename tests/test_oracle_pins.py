@@ -156,3 +156,55 @@ def test_planted_signed_weights_in_certificate(orc, monkeypatch):
         return c
     monkeypatch.setattr(orc, "certificate", bad_cert)
     assert _fails(orc, [pins.certificate])
+
+
+def test_planted_threshold_without_d(orc, monkeypatch):
+    monkeypatch.setattr(orc, "truncation_threshold", lambda eps, a, x: eps * a / x if x else 0.0)
+    assert _fails(orc, [pins.truncation_rule])
+
+
+def test_planted_threshold_with_d_squared(orc, monkeypatch):
+    monkeypatch.setattr(orc, "truncation_threshold", lambda eps, a, x: eps * a / (9 * x) if x else 0.0)
+    assert _fails(orc, [pins.truncation_rule])
+
+
+def test_planted_threshold_ignoring_norm_ratio(orc, monkeypatch):
+    monkeypatch.setattr(orc, "truncation_threshold", lambda eps, a, x: eps / 3 if x else 0.0)
+    assert _fails(orc, [pins.truncation_rule])
+
+
+def test_planted_threshold_on_raw_xi(orc, monkeypatch):
+    """|xi| of the raw weights instead of xi' (the norms not folded in)."""
+    real = orc.rhosvd
+
+    def bad_rhosvd(U, xi, eps, **kw):
+        raw = float(np.linalg.norm(xi))
+        monkeypatch.setattr(orc, "truncation_threshold", lambda e, a, x: e * a / (3 * raw) if x else 0.0)
+        return real(U, xi, eps, **kw)
+    monkeypatch.setattr(orc, "rhosvd", bad_rhosvd)
+    assert _fails(orc, [pins.truncation_rule])
+
+
+def test_planted_flipped_sign_rule(orc, monkeypatch):
+    def bad_sign(Z):
+        Z = Z.copy()
+        for k in range(Z.shape[1]):
+            i = int(np.argmax(np.abs(Z[:, k])))
+            if Z[i, k] > 0:                       # largest entry made negative
+                Z[:, k] = -Z[:, k]
+        return Z
+    monkeypatch.setattr(orc, "sign_normalize", bad_sign)
+    assert _fails(orc, [pins.sign_rule])
+
+
+def test_planted_sign_tie_to_highest_index(orc, monkeypatch):
+    def bad_sign(Z):
+        Z = Z.copy()
+        for k in range(Z.shape[1]):
+            a = np.abs(Z[:, k])
+            i = len(a) - 1 - int(np.argmax(a[::-1]))    # last index of the maximum
+            if Z[i, k] < 0:
+                Z[:, k] = -Z[:, k]
+        return Z
+    monkeypatch.setattr(orc, "sign_normalize", bad_sign)
+    assert _fails(orc, [pins.sign_rule])
