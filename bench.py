@@ -19,8 +19,10 @@ through the learned path (trained network, certified range finder, fallback)
 against the plain method; and "batched": the uneven batch (256 problems, n uniform in
 {128,...,2048}, R log-uniform in [64, 8192], each the first R terms of ceil(R/32)
 charges x 32 Gaussian terms, eps = 1e-5) as one graph-recorded batched pass
-(BF16x3 cores by default, FP64 eigensolver), timed over replays, next to the plain FP64
-single-problem path over the same problems.
+(FP32-MFMA cores, the batch's stated precision, and BF16x3 cores as a second row;
+FP64 eigensolver), timed over replays, next to the plain FP64 single-problem path
+over the same problems.  "cpu_baseline" is one full oracle reduction of the
+benchmarked input on the host's threads.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-batch]
 """
@@ -87,45 +89,44 @@ def time_path(red, U, xi, eps, beta_buf, steps, warmup):
 
 
 def cpu_baseline(ci):
-    """The oracle on the host cores, on a bounded sample of the same reduction:
-    normalization and |A| in full, the SVD of mode 1 only (x3 for the three
-    modes), and 16 of the r3 core slabs (x r3/16); scaled to one reduction."""
-    import numpy as np
+    """The oracle on the host cores: one full reduction of the benchmarked input
+    (normalization, exact |A|, three Jacobi SVDs, truncation, projections and the
+    whole core), timed at all host threads; and a full reduction of the small
+    workload (n=64, R=200) at one thread and at all threads, for the per-thread
+    rate.  Nothing is extrapolated."""
     import oracle
+    from paper_2201_12663_amd import inputs
+    from threadpoolctl import threadpool_limits
     oracle.build(force=False)
-    t = {}
+    threads = oracle.num_threads()
     t0 = time.perf_counter()
-    Ut, xip, _, _ = oracle.normalize(ci.U, ci.xi)
-    t["normalize"] = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    a_norm = oracle.anorm_gram(Ut, xip)
-    t["anorm"] = time.perf_counter() - t0
-    xi_norm = float(np.linalg.norm(xip))
-    tau = oracle.truncation_threshold(ci.eps, a_norm, xi_norm)
-    t0 = time.perf_counter()
-    s, Zf, _ = oracle.svd_left(Ut[0])
-    r = oracle.choose_rank(oracle.tails(s), tau)
-    Z = oracle.sign_normalize(Zf[:, :r])
-    V = oracle.project(Z, Ut[0])
-    t["svd_trunc_project_one_mode"] = time.perf_counter() - t0
-    nslab = 16
-    t0 = time.perf_counter()
-    oracle.core([V, V, V[:nslab]], xip)
-    t["core_16_slabs"] = time.perf_counter() - t0
-    total = t["normalize"] + t["anorm"] + 3 * t["svd_trunc_project_one_mode"] + t["core_16_slabs"] * r / nslab
-    return dict(value=1.0 / total, unit="reductions/s", cores=oracle.num_threads(), kind="oracle",
-                sample=("normalization and |A| in full; SVD+truncation+projection of mode 1 timed and "
-                        "counted x3; 16 of the ~%d core slabs timed and scaled; seconds per part: %s; "
-                        "estimated %.1f s per reduction" % (r, {k: round(v, 2) for k, v in t.items()}, total)))
+    res = oracle.rhosvd(ci.U, ci.xi, ci.eps)
+    full_s = time.perf_counter() - t0
+    small = inputs.small_gaussian_sum(0)
+    per = {}
+    for label, limit in (("all_threads", None), ("one_thread", 1)):
+        if limit is None:
+            t0 = time.perf_counter()
+            oracle.rhosvd(small.U, small.xi, small.eps)
+            per[label] = time.perf_counter() - t0
+        else:
+            with threadpool_limits(limits=limit):
+                t0 = time.perf_counter()
+                oracle.rhosvd(small.U, small.xi, small.eps)
+                per[label] = time.perf_counter() - t0
+    return dict(value=1.0 / full_s, unit="reductions/s", cores=threads, kind="oracle",
+                sample=("one full oracle reduction of the benchmarked input (n=1024, R=4096, eps=1e-5) at %d "
+                        "threads: %.1f s, ranks %s" % (threads, full_s, list(res.ranks))),
+                small_workload=dict(workload="n=64, R=200, eps=1e-6 Gaussian sum (full reduction)",
+                                    s_all_threads=round(per["all_threads"], 4),
+                                    s_one_thread=round(per["one_thread"], 4),
+                                    reductions_per_s_one_thread=round(1.0 / per["one_thread"], 3)))
 
 
-def bench_batched(args):
-    """The uneven batch as one batched pass (graph replay), and the plain FP64
-    single-problem path over the same problems for comparison."""
-    import numpy as np
+def batch_inputs(count):
     import torch
-    from paper_2201_12663_amd import inputs, rhosvd
-    shapes = inputs.batch_shapes(seed=0, count=args.batch_count)
+    from paper_2201_12663_amd import inputs
+    shapes = inputs.batch_shapes(seed=0, count=count)
     t0 = time.perf_counter()
     probs = []
     for i, (n, R) in enumerate(shapes):
@@ -134,7 +135,15 @@ def bench_batched(args):
         probs.append((U[0], U[1], U[2], torch.from_numpy(xi).cuda(), 1e-5))
     torch.cuda.synchronize()
     log(f"batch: {len(probs)} problems generated on the device in {time.perf_counter() - t0:.1f} s")
-    red = rhosvd.Reducer(precision=args.batch_precision, beta_fp32=args.batch_precision != "fp64")
+    return shapes, probs
+
+
+def batched_pass(args, probs, shapes, precision):
+    """One precision of the batched pass: sizing and first (tuned, recorded) pass,
+    then replays timed with HIP events."""
+    import torch
+    from paper_2201_12663_amd import rhosvd
+    red = rhosvd.Reducer(precision=precision, beta_fp32=precision != "fp64")
     t0 = time.perf_counter()
     out, desc, res, outs = red.reduce_batched(probs)
     torch.cuda.synchronize()
@@ -143,7 +152,7 @@ def bench_batched(args):
     ranks = [tuple(int(x) for x in rr[i, :3]) for i in range(len(probs))]
     status = [int(rr[i, 3]) for i in range(len(probs))]
     beta_gb = sum(r[0] * r[1] * r[2] for r in ranks) * outs[0][3].element_size() / 1e9
-    log(f"batch: sizing + first pass {first_s:.1f} s (graph recorded: {red.batch_uses_graph()}), "
+    log(f"batch {precision}: sizing + first pass {first_s:.1f} s (graph recorded: {red.batch_uses_graph()}), "
         f"beta outputs {beta_gb:.1f} GB, statuses {sorted(set(status))}")
     for _ in range(args.batch_warmup):
         red.reduce_batched_raw(desc)
@@ -157,38 +166,80 @@ def bench_batched(args):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.batch_steps
     core_flops = float(sum(2.0 * r[0] * r[1] * r[2] * R for r, (n, R) in zip(ranks, shapes)))
+    row = dict(precision=precision, ms_per_batch=round(ms, 3), reductions_per_s=round(len(probs) / (ms * 1e-3), 3),
+               graph=red.batch_uses_graph(), core_tile=red.last_core_tile(), all_ok=all(x == 0 for x in status),
+               core_flops=core_flops, core_tflops_whole_pass=round(core_flops / (ms * 1e-3) / 1e12, 2),
+               beta_gb=round(beta_gb, 2), max_rank=max(max(r) for r in ranks))
+    log(f"batch {precision}: {ms:.1f} ms per batch -> {row['reductions_per_s']} reductions/s")
+    red.close()
+    del outs, out
+    torch.cuda.empty_cache()
+    return row, ranks
+
+
+def bench_batched(args):
+    """The uneven batch as one batched pass (graph replay) with FP32-MFMA cores
+    (the batch's stated precision; BF16x3 cores as an extra row), and the plain
+    FP64 single-problem path over the same problems for comparison.  Where a
+    problem's ranks differ between the two, the single path's cut margin is
+    reported against the FP64 tail error (the knife-edge rule)."""
+    import numpy as np
+    import torch
+    from paper_2201_12663_amd import rhosvd
+    shapes, probs = batch_inputs(args.batch_count)
+    rows = {}
+    ranks_by = {}
+    for prec in args.batch_precision.split(","):
+        rows[prec], ranks_by[prec] = batched_pass(args, probs, shapes, prec)
+    head = args.batch_precision.split(",")[0]
     result = dict(
         workload=("uneven batch: %d problems, n uniform in {128,...,2048}, R log-uniform in [64, 8192], "
                   "charges x 32-term Gaussian sums for 1/|x|, eps=1e-5" % len(probs)),
-        precision=args.batch_precision, problems=len(probs), steps=args.batch_steps,
-        ms_per_batch=round(ms, 3), reductions_per_s=round(len(probs) / (ms * 1e-3), 3),
-        graph=red.batch_uses_graph(), core_tile=red.last_core_tile(), all_ok=all(s == 0 for s in status),
-        core_flops=core_flops, core_tflops_whole_pass=round(core_flops / (ms * 1e-3) / 1e12, 2),
-        beta_gb=round(beta_gb, 2), max_rank=max(max(r) for r in ranks))
-    log(f"batch: {ms:.1f} ms per batch -> {result['reductions_per_s']} reductions/s")
-    red.close()
+        problems=len(probs), steps=args.batch_steps, **rows[head])
+    result["rows"] = rows
     if args.batch_fp64_baseline:
         # the plain FP64 path, one problem at a time; every core goes into one
-        # FP64 buffer sized for the largest problem (the batch's outputs stay alive)
+        # FP64 buffer sized for the largest problem
+        ranks = ranks_by[head]
         red64 = rhosvd.Reducer(precision="fp64")
         big = torch.empty(max(r[0] * r[1] * r[2] for r in ranks) + 1, dtype=torch.float64, device="cuda")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        same = 0
+        single = []
         for i, p in enumerate(probs):
             r = red64.reduce(*p)
-            same += tuple(r) == ranks[i]
+            single.append(tuple(r))
             if all(x > 0 for x in r) and r[0] * r[1] * r[2] <= big.numel():
                 red64.core_only(big)
         torch.cuda.synchronize()
         t64 = time.perf_counter() - t0
+        same = sum(a == b for a, b in zip(single, ranks))
+        # explain every difference: the single path's own cut margin in units of
+        # the FP64 tail error e_t = 2^-52 sigma_1^2 / (2 tau)
+        mism = []
+        for i, (a, b) in enumerate(zip(single, ranks)):
+            if a == b:
+                continue
+            red64.reduce(*probs[i])
+            rep = red64.get(beta=False, Z=False, sigma=False).report
+            tau = rep["tau"]
+            info = dict(index=i, n=shapes[i][0], R=shapes[i][1], single=list(a), batched=list(b), modes=[])
+            for l in range(3):
+                if a[l] == b[l]:
+                    continue
+                sg = red64.spectrum(l).cpu().numpy()
+                t = np.sqrt(np.concatenate([np.cumsum((sg ** 2)[::-1])[::-1], [0.0]]))
+                e_t = 2.0 ** -52 * sg[0] ** 2 / (2 * tau)
+                r = a[l]
+                margin = min(t[r - 1] - tau, tau - t[r])
+                info["modes"].append(dict(mode=l, margin_over_tail_error=float(margin / e_t)))
+            mism.append(info)
         red64.close()
         result["plain_fp64"] = dict(s_per_batch=round(t64, 3), reductions_per_s=round(len(probs) / t64, 3),
-                                    ranks_equal=same)
-        result["speedup_vs_plain_fp64"] = round(t64 / (ms * 1e-3), 3)
+                                    ranks_equal=same, rank_differences=mism)
+        result["speedup_vs_plain_fp64"] = round(t64 / (result["ms_per_batch"] * 1e-3), 3)
         del big
-        log(f"batch: plain FP64 one by one {t64:.1f} s ({same}/{len(probs)} ranks equal)")
-    del outs, out
+        log(f"batch: plain FP64 one by one {t64:.1f} s ({same}/{len(probs)} ranks equal; differences {mism})")
     torch.cuda.empty_cache()
     return result
 
@@ -250,7 +301,7 @@ def bench_learned(args):
     shapes = inputs.ranknet_shapes(10_000 + 7, args.learned_count)
     red = rhosvd.Reducer(precision="fp32")
     red.net_set(torch.from_numpy(np.load(ranknet.DEFAULT_PARAMS)).cuda())
-    plain = rhosvd.Reducer(precision="fp32")
+    plain = rhosvd.Reducer(precision="fp32", anorm="exact")   # like for like: the learned path uses the exact |A|
     t_l = t_p = 0.0
     modes_rf = modes = certified = eligible = 0
     fam_t = {}
@@ -301,7 +352,8 @@ def main():
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--batch-warmup", type=int, default=1)
-    ap.add_argument("--batch-precision", default="bf16x3")
+    ap.add_argument("--batch-precision", default="fp32,bf16x3",
+                    help="comma-separated core precisions of the batched pass; the first is the batch's headline row")
     ap.add_argument("--no-batch-fp64-baseline", dest="batch_fp64_baseline", action="store_false")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-precision-study", action="store_true")
@@ -406,7 +458,7 @@ def main():
     if not args.no_precision_study:
         line["precision_study"] = bench_precision_study(args)
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle on a bounded sample)")
+        log("cpu baseline (one full oracle reduction of the benchmarked input)")
         line["cpu_baseline"] = cpu_baseline(ci)
     print(json.dumps(line), flush=True)
 

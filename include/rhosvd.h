@@ -13,7 +13,8 @@
  *
  * Truncation rule (the paper leaves it open): tau = eps * |A|_F / (3 |xi'|_2),
  * r_l = min{ r >= 1 : (sum_{k>r} sigma_{l,k}^2)^(1/2) <= tau }.  Theorem 2.3 then
- * guarantees |A - A_r|_F <= eps |A|_F.
+ * guarantees |A - A_r|_F <= eps |A|_F.  |A|_F is exact or a certified lower bound
+ * (rhosvd_options.anorm); a lower bound only lowers tau, so the guarantee holds.
  *
  * Conventions
  *   - All matrices are column-major.  U^(l): n x R, leading dimension n, column nu
@@ -109,13 +110,31 @@ typedef struct {
                                 each residual column formed directly in FP64 (from an FP64
                                 projection in every precision: one more n x r x R product per
                                 mode on the mixed paths).  Not formed by rhosvd_reduce_batched. */
-    int32_t reserved[1];     /* must be zero */
+    int32_t anorm;           /* how rhosvd_reduce obtains |A|_F for tau (other values: RHOSVD_ERR_ARG):
+                                1 exact: |A|^2 = xi'^T (G1 o G2 o G3) xi' with G_l = U~_l^T U~_l
+                                  (R x R, 3 n R^2 flops).
+                                2 probe: a certified lower bound L <= |A|, the norm of the
+                                  core at probe ranks p_l (the smallest ranks whose tails
+                                  t_{l,p} are <= 1/30): |beta_p| = |A x_1 Z_p1^T x_2 Z_p2^T
+                                  x_3 Z_p3^T| <= |A| (an orthogonal projection of A), formed
+                                  with the FP64 core after the eigensolver (2 p1 p2 p3 R
+                                  flops).  Theorem 2.3 applied at p gives the upper bound
+                                  U = (L^2 + b_p^2)^(1/2), b_p = |xi'| sum_l t_{l,p_l}; tau
+                                  from L is at most the exact one (so the result stays
+                                  certified: bound <= eps L <= eps |A|) and differs from it
+                                  by at most 1 - L/U relatively.
+                                0 (default): the probe where n <= R, its flops are under
+                                  half the exact identity's and b_p <= L / 10; else exact.
+                                When R < n the identity's tiles are the Gram matrices
+                                themselves, so it is always exact there.  Batched and
+                                learned reductions use the exact identity. */
 } rhosvd_options;
 
 typedef struct {
     double xi_norm;      /* |xi'|_2 after normalization */
-    double a_norm;       /* |A|_F (exact, from the Gram identity) */
-    double tau;          /* truncation threshold on the tails */
+    double a_norm;       /* |A|_F as used for tau: exact (Gram identity), or the probe's certified
+                            lower bound (anorm_method) */
+    double tau;          /* truncation threshold on the tails, eps * a_norm / (3 |xi'|) */
     double bound;        /* Theorem 2.3: |xi'| * sum_l tail[l] */
     double tail[3];      /* t_{l, r_l} = (sum_{k > r_l} sigma_{l,k}^2)^(1/2) */
     int32_t ranks[3];
@@ -125,6 +144,10 @@ typedef struct {
     double certificate;  /* with the certificate option: sum_l sum_nu |xi'_nu| |(I - Z_l Z_l^T)
                             u~_nu^(l)| (proof of Theorem 2.3), |A - A_r| <= certificate <= bound;
                             -1 when not formed */
+    double a_norm_upper; /* an upper bound of |A|_F: equal to a_norm when that is exact,
+                            (a_norm^2 + b_p^2)^(1/2) with the probe (see rhosvd_options.anorm) */
+    int32_t anorm_method;  /* 1 exact identity, 2 probe lower bound */
+    int32_t reserved;
 } rhosvd_report;
 
 typedef struct rhosvd_ctx* rhosvd_handle;
@@ -142,14 +165,15 @@ rhosvd_status rhosvd_set_options(rhosvd_handle h, const rhosvd_options* opt);
 
 /*
  * Phase 1 of a reduction (Definition 2.1 up to the ranks): normalization, the
- * |A| identity, Gram matrices on the min(n,R) side, FP64 eigensolver,
- * truncation, Z and the projections V^(l).
+ * |A| identity or probe (rhosvd_options.anorm), Gram matrices on the min(n,R)
+ * side, FP64 eigensolver, truncation, Z and the projections V^(l).
  *   n, R     : grid size and canonical rank, 1 <= n <= 2048, R >= 1
  *   U1..U3   : device, n x R each (column-major, ld = n)
  *   xi       : device, R weights
  *   eps      : relative accuracy, > 0
  *   ranks    : HOST int32[3], receives (r1, r2, r3); (0,0,0) when every term is dropped
- * Synchronizes with the handle's stream once.  On error nothing is retained.
+ * Synchronizes with the handle's stream once (the probe adds two more, its
+ * fallback to the exact identity one more).  On error nothing is retained.
  * Errors: ARG, NONFINITE, ALLOC, DEVICE, NOCONV, UNSUPPORTED.
  */
 rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R,
@@ -315,8 +339,8 @@ rhosvd_status rhosvd_reduce_learned(rhosvd_handle h, int64_t n, int64_t R, const
 
 /* Phase times in milliseconds of the last rhosvd_reduce / rhosvd_get when the
  * handle was created with profile != 0 (synchronizes with the stream):
- *   0 norms, 1 |A| identity, 2 Gram, 3 eigensolver, 4 truncation + Z,
- *   5 projection, 6 core.  Returns -1 for an unknown phase or when profiling is off. */
+ *   0 norms, 1 |A| identity, 2 Gram, 3 eigensolver, 4 truncation + Z (with the
+ *   |A| probe, which runs after the eigensolver), 5 projection, 6 core.  Returns -1 for an unknown phase or when profiling is off. */
 double rhosvd_phase_ms(rhosvd_handle h, int32_t phase);
 
 /* Message describing the last error on this handle ("" if none); valid until

@@ -19,6 +19,7 @@ constexpr int NPHASE = 7;
 constexpr int NEV = 9;            // 0..6 bracket the reduce phases, 7..8 the core
 constexpr int DEFAULT_SWEEPS = 30;   // kept for the options ABI; the eigensolver has no sweep cap
 constexpr int RPAD_CORE = 128;                                 // V row padding (core tiles)
+constexpr size_t HOST_BYTES = 4096;                            // pinned host staging of a handle
 
 std::string g_create_error;
 
@@ -64,6 +65,14 @@ struct rhosvd_ctx {
     int gram_splits = 1;
     double* anorm_part = nullptr;
     int64_t anorm_ntiles = 0;
+    // |A| used by the truncation: partial sums of |A|^2 (exact identity) or of
+    // |beta_p|^2 (probe), and the probe's own workspace (grow-only)
+    const double* a2_part = nullptr;
+    int64_t a2_n = 0;
+    int anorm_method = 1;
+    double a_upper = 0;
+    char* pw = nullptr;
+    size_t pw_bytes = 0;
     double* sigma[3] = {};
     int* order[3] = {};
     double* tails[3] = {};
@@ -147,7 +156,7 @@ rhosvd_status fail(rhosvd_ctx* h, rhosvd_status s, const std::string& msg) {
 rhosvd_status check_options(const rhosvd_options* o, std::string& msg) {
     if (!o) return RHOSVD_OK;
     if (o->precision < 0 || o->precision > 2) { msg = "unknown precision"; return RHOSVD_ERR_ARG; }
-    if (o->reserved[0] != 0) { msg = "reserved option fields must be zero"; return RHOSVD_ERR_ARG; }
+    if (o->anorm < 0 || o->anorm > 2) { msg = "anorm must be 0 (auto), 1 (exact) or 2 (probe)"; return RHOSVD_ERR_ARG; }
     if (o->refine_tails < 0 || o->refine_tails > 2) { msg = "refine_tails must be 0, 1 or 2"; return RHOSVD_ERR_ARG; }
     if (o->core_tile != 0 && !core_tile_valid(o->precision, o->core_tile)) {
         msg = "core_tile must be 0 (tuned), 64, or 128 (128 only for the FP32 and BF16x3 cores)";
@@ -424,6 +433,135 @@ rhosvd_status form_z_rside(rhosvd_ctx* h) {
     return RHOSVD_OK;
 }
 
+// truncation arguments of the Gram path for the current layout (|A| from h->a2_part)
+TruncArgs trunc_args(rhosvd_ctx* h, double eps) {
+    TruncArgs ta{};
+    for (int l = 0; l < 3; ++l) {
+        ta.lam[l] = h->lam[l];
+        ta.sigma[l] = h->sigma[l];
+        ta.order[l] = h->order[l];
+        ta.tails[l] = h->tails[l];
+    }
+    ta.m = (int)h->m;
+    ta.m_pad = (int)h->m_pad;
+    ta.n = (int)h->n;
+    ta.n_pad = (int)h->n_pad;
+    ta.xip = h->xip;
+    ta.R_pad = h->R_pad;
+    ta.anorm_part = h->a2_part;
+    ta.anorm_ntiles = h->a2_n;
+    ta.eps = eps;
+    ta.ranks = h->ranks_dev;
+    ta.scal = h->scal;
+    return ta;
+}
+
+constexpr double PROBE_TAIL = 1.0 / 30.0;   // probe ranks: t_{l,p} <= 1/30 (b_p <= |xi'| / 10)
+constexpr double PROBE_GAP = 0.1;           // auto mode keeps the probe only if b_p <= L / 10
+constexpr int PROBE_NPART = 256;
+
+// |A| after the eigensolver (n <= R), for rhosvd_options.anorm = 0 or 2.  Probe
+// ranks p_l = min{p : t_{l,p} <= 1/30}; Z = all m back-transformed eigenvectors
+// (sign rule applied; later steps use its leading columns); V_p = Z_p^T U~ and
+// beta_p = the FP64 core at the probe ranks; |beta_p|^2 partial sums become the
+// truncation's |A|^2.  |beta_p| <= |A| (beta_p is the core of an orthogonal
+// projection of A), and Theorem 2.3 at the probe ranks gives |A|^2 <= |beta_p|^2 +
+// b_p^2 with b_p = |xi'| sum_l t_{l,p_l}.  Falls back to the exact identity in
+// auto mode when the probe would cost more than half the identity's flops or
+// b_p > L / 10.  *z_all is set when Z already holds every eigenvector.
+rhosvd_status anorm_probe(rhosvd_ctx* h, int mode, bool* z_all) {
+    hipStream_t st = h->stream;
+    const int64_t np = h->n_pad, Rp = h->R_pad;
+    const int m = (int)h->m;
+    *z_all = false;
+    auto exact = [&]() -> rhosvd_status {
+        int64_t nt = 0;
+        CK(h, launch_anorm_partials(h->n_pad, h->R_pad, h->Ut, h->xip, h->anorm_part, &nt, nullptr, st));
+        h->a2_part = h->anorm_part;
+        h->a2_n = h->anorm_ntiles;
+        h->anorm_method = 1;
+        h->a_upper = -1.0;
+        return RHOSVD_OK;
+    };
+    TruncArgs tp = trunc_args(h, 1.0);
+    tp.anorm_part = nullptr;
+    tp.anorm_ntiles = 0;
+    tp.tau_fixed = PROBE_TAIL;
+    CK(h, launch_truncate(tp, st));
+    CK(h, hipMemcpyAsync(h->host, h->ranks_dev, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
+    CK(h, hipMemcpyAsync(h->hostd, h->scal, 6 * sizeof(double), hipMemcpyDeviceToHost, st));
+    CK(h, hipStreamSynchronize(st));
+    int p[3];
+    double tp_sum = 0.0;
+    for (int l = 0; l < 3; ++l) {
+        p[l] = std::min(h->host[l], m);
+        tp_sum += h->hostd[3 + l];
+    }
+    const double xi_norm = h->hostd[0];
+    if (p[0] < 1 || p[1] < 1 || p[2] < 1 || !(xi_norm > 0.0)) return exact();
+    const double R = (double)h->R, n = (double)h->n;
+    const double probe_flops = 2.0 * p[0] * p[1] * p[2] * R + 2.0 * n * (p[0] + p[1] + p[2]) * R;
+    const double exact_flops = 3.0 * n * R * R;
+    if (mode == 0 && 2.0 * probe_flops > exact_flops) return exact();
+    int pp[3];
+    for (int l = 0; l < 3; ++l) pp[l] = (int)round_up(p[l], RPAD_CORE);
+    // probe workspace: V_p (FP64, three modes), beta_p, partial sums
+    const size_t vbytes = a256((size_t)(pp[0] + pp[1] + pp[2]) * Rp * 8);
+    const size_t bbytes = a256((size_t)p[0] * p[1] * p[2] * 8);
+    const size_t need = vbytes + bbytes + a256(PROBE_NPART * 8);
+    if (need > h->pw_bytes) {
+        if (h->pw) { CK(h, hipStreamSynchronize(st)); hipFree(h->pw); h->pw = nullptr; h->pw_bytes = 0; }
+        if (hipMalloc((void**)&h->pw, need) != hipSuccess) {
+            h->pw = nullptr;
+            return fail(h, RHOSVD_ERR_ALLOC, "|A| probe workspace allocation of " + std::to_string(need) + " bytes failed");
+        }
+        h->pw_bytes = need;
+    }
+    double* Vp[3];
+    Vp[0] = (double*)h->pw;
+    Vp[1] = Vp[0] + (size_t)pp[0] * Rp;
+    Vp[2] = Vp[1] + (size_t)pp[1] * Rp;
+    double* beta_p = (double*)(h->pw + vbytes);
+    double* part = (double*)(h->pw + vbytes + bbytes);
+    // every eigenvector, back-transformed and sign-normalized, into Z
+    BtJob jobs[3];
+    for (int l = 0; l < 3; ++l)
+        jobs[l] = BtJob{m, (int)h->m_pad, h->G[l], h->htau[l], h->W[l], h->order[l], m, nullptr, h->Z[l], (int)np,
+                        (int)np, h->Tw[l]};
+    CK(h, launch_backtransform(jobs, 3, st));
+    for (int l = 0; l < 3; ++l) {
+        CK(h, launch_sign_cols((int)h->n, (int)np, m, h->Z[l], st));
+        if (h->zr_pad > m)
+            CK(h, hipMemsetAsync(h->Z[l] + (int64_t)m * np, 0, (size_t)(h->zr_pad - m) * np * 8, st));
+        CK(h, launch_project(np, Rp, pp[l], h->Z[l], h->Ut[l], Vp[l], nullptr, st));
+    }
+    *z_all = true;
+    CoreArgs ca{};
+    for (int l = 0; l < 3; ++l) {
+        ca.r[l] = p[l];
+        ca.r_pad[l] = pp[l];
+        ca.V[l] = Vp[l];
+    }
+    ca.R_pad = Rp;
+    ca.xip = h->xip;
+    ca.beta = beta_p;
+    ca.prec = RHOSVD_FP64;
+    ca.tile = 64;
+    CK(h, launch_core(ca, st));
+    CK(h, launch_sumsq_partials(beta_p, (int64_t)p[0] * p[1] * p[2], part, PROBE_NPART, st));
+    CK(h, hipMemcpyAsync(h->hostd + 64, part, PROBE_NPART * sizeof(double), hipMemcpyDeviceToHost, st));
+    CK(h, hipStreamSynchronize(st));
+    double L2 = 0.0;
+    for (int i = 0; i < PROBE_NPART; ++i) L2 += h->hostd[64 + i];
+    const double L = sqrt(std::max(L2, 0.0)), bp = xi_norm * tp_sum;
+    if (mode == 0 && !(bp <= PROBE_GAP * L)) return exact();
+    h->a2_part = part;
+    h->a2_n = PROBE_NPART;
+    h->anorm_method = 2;
+    h->a_upper = sqrt(L * L + bp * bp);
+    return RHOSVD_OK;
+}
+
 // refine_tails = 2 (n <= R): a second, deflated Gram pass.  The leading k_l
 // eigenvectors of the first pass (sigma >= 2^-13 sigma_1, where the FP64 Gram
 // route is accurate) form Z_k; the side matrix is deflated twice,
@@ -485,8 +623,8 @@ rhosvd_status deflate_pass(rhosvd_ctx* h, double eps) {
     ta.n_pad = (int)np;
     ta.xip = h->xip;
     ta.R_pad = Rp;
-    ta.anorm_part = h->anorm_part;
-    ta.anorm_ntiles = h->anorm_ntiles;
+    ta.anorm_part = h->a2_part;
+    ta.anorm_ntiles = h->a2_n;
     ta.eps = eps;
     ta.ranks = h->ranks_dev;
     ta.scal = h->scal;
@@ -544,13 +682,14 @@ rhosvd_status rhosvd_create(rhosvd_handle* out, void* hip_stream, const rhosvd_o
     h->stream = (hipStream_t)hip_stream;
     apply_options(h, opt);
     h->tuner = core_tuner_create();
-    if (hipHostMalloc((void**)&h->host, 256, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void**)&h->host, HOST_BYTES, hipHostMallocDefault) != hipSuccess) {
         delete h;
         g_create_error = "pinned host allocation failed";
         return RHOSVD_ERR_ALLOC;
     }
     // host staging words: 0..2 ranks, 4..6 flags, 8 abort word (report), 32.. doubles
-    // (0..2 norms, 4..6 tails, 8..10 range-finder residuals), 56..61 network outputs
+    // (0..2 norms, 3..5 probe tails, 4..6 tails, 8..10 range-finder residuals;
+    // 64 .. 64 + PROBE_NPART probe partial sums), 56..61 network outputs
     h->hostd = (double*)(h->host + 32);
     h->ev_ok = true;
     for (int i = 0; i < NEV; ++i)
@@ -563,6 +702,7 @@ rhosvd_status rhosvd_destroy(rhosvd_handle h) {
     if (!h) return RHOSVD_ERR_ARG;
     hipStreamSynchronize(h->stream);
     if (h->ws) hipFree(h->ws);
+    if (h->pw) hipFree(h->pw);
     if (h->batch) batch_plan_destroy(h->batch);
     if (h->net) hipFree(h->net);
     if (h->L.ws) hipFree(h->L.ws);
@@ -607,10 +747,18 @@ rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R, const double*
     CK(h, hipMemsetAsync(h->flags, 0, 64, st));
     CK(h, launch_colnorm(n, R, h->n_pad, h->R_pad, U, xi, h->Ut, h->xip, h->flags, st));
     mark(h, 1);
-    int64_t nt = 0;
-    // |A| identity; when R < n the same tiles are the Grams U~^T U~ on the R side
-    CK(h, launch_anorm_partials(h->n_pad, h->R_pad, h->Ut, h->xip, h->anorm_part, &nt,
-                                h->rside ? h->G : nullptr, st));
+    // |A|: the exact identity now (when R < n its tiles are the Grams U~^T U~ on the
+    // R side), or after the eigensolver by the probe (rhosvd_options.anorm)
+    const bool probe = !h->rside && h->opt.anorm != 1;
+    h->a2_part = h->anorm_part;
+    h->a2_n = h->anorm_ntiles;
+    h->anorm_method = 1;
+    h->a_upper = -1.0;
+    if (!probe) {
+        int64_t nt = 0;
+        CK(h, launch_anorm_partials(h->n_pad, h->R_pad, h->Ut, h->xip, h->anorm_part, &nt,
+                                    h->rside ? h->G : nullptr, st));
+    }
     mark(h, 2);
     if (!h->rside)
         CK(h, launch_gram_nt(h->n_pad, h->R_pad, h->Ut, h->G, h->gram_part, h->gram_splits, st));
@@ -623,25 +771,12 @@ rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R, const double*
     if (s != RHOSVD_OK) return s;
     CK(h, eig_plan_enqueue(h->plan[0], h->flags + 2, st));
     mark(h, 4);
-    TruncArgs ta{};
-    for (int l = 0; l < 3; ++l) {
-        ta.lam[l] = h->lam[l];
-        ta.sigma[l] = h->sigma[l];
-        ta.order[l] = h->order[l];
-        ta.tails[l] = h->tails[l];
+    bool z_all = false;   // the probe leaves every eigenvector in Z
+    if (probe) {
+        s = anorm_probe(h, h->opt.anorm, &z_all);
+        if (s != RHOSVD_OK) return s;
     }
-    ta.m = (int)h->m;
-    ta.m_pad = (int)h->m_pad;
-    ta.n = (int)n;
-    ta.n_pad = (int)h->n_pad;
-    ta.xip = h->xip;
-    ta.R_pad = h->R_pad;
-    ta.anorm_part = h->anorm_part;
-    ta.anorm_ntiles = h->anorm_ntiles;
-    ta.eps = eps;
-    ta.ranks = h->ranks_dev;
-    ta.scal = h->scal;
-    CK(h, launch_truncate(ta, st));
+    CK(h, launch_truncate(trunc_args(h, eps), st));
     // the one host synchronization: ranks, flags, sweeps and norms
     CK(h, hipMemcpyAsync(h->host, h->ranks_dev, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
     CK(h, hipMemcpyAsync(h->host + 4, h->flags, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -679,6 +814,13 @@ rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R, const double*
         }
     // a5/a6: Z and the projections V = Z^T U~ (FP64 MFMA; rounded to FP32 for the mixed core)
     if (z_done) {
+    } else if (z_all) {
+        for (int l = 0; l < 3; ++l) {
+            const int r = h->ranks[l];
+            if (r >= 1 && h->r_pad[l] > r)
+                CK(h, hipMemsetAsync(h->Z[l] + (int64_t)r * h->n_pad, 0,
+                                     (size_t)(h->r_pad[l] - r) * h->n_pad * 8, st));
+        }
     } else if (!h->rside) {
         // Z = H W[:, order[0..r-1]]: back-transformed eigenvectors, sign rule, zero padding
         BtJob jobs[3];
@@ -733,8 +875,8 @@ rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R, const double*
         tb.n_pad = (int)h->n_pad;
         tb.xip = h->xip;
         tb.R_pad = h->R_pad;
-        tb.anorm_part = h->anorm_part;
-        tb.anorm_ntiles = h->anorm_ntiles;
+        tb.anorm_part = h->a2_part;
+        tb.anorm_ntiles = h->a2_n;
         tb.eps = eps;
         tb.ranks = h->ranks_dev;
         tb.scal = h->scal;
@@ -846,6 +988,8 @@ rhosvd_status rhosvd_get(rhosvd_handle h, double* Z1, double* Z2, double* Z3, vo
         report->eig_sweeps = h->sweeps;
         report->dropped = h->dropped;
         report->certificate = cert ? h->hostd[8] : -1.0;
+        report->anorm_method = h->anorm_method;
+        report->a_norm_upper = h->anorm_method == 2 ? h->a_upper : h->a_norm;
     }
     return RHOSVD_OK;
 }
@@ -1016,6 +1160,10 @@ rhosvd_status prologue(rhosvd_ctx* h, int64_t n, int64_t R, const double* U1, co
     CK(h, launch_colnorm(n, R, h->n_pad, h->R_pad, U, xi, h->Ut, h->xip, h->flags, st));
     int64_t nt = 0;
     CK(h, launch_anorm_partials(h->n_pad, h->R_pad, h->Ut, h->xip, h->anorm_part, &nt, h->rside ? h->G : nullptr, st));
+    h->a2_part = h->anorm_part;
+    h->a2_n = h->anorm_ntiles;
+    h->anorm_method = 1;
+    h->a_upper = -1.0;
     return RHOSVD_OK;
 }
 

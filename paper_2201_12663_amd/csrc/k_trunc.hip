@@ -32,7 +32,7 @@ __device__ __forceinline__ void truncate_mode(int mode, const double* __restrict
                               int64_t R_pad, const double* __restrict__ anorm_part, int64_t anorm_ntiles, double eps,
                               double* __restrict__ sigma, int* __restrict__ order, double* __restrict__ tails,
                               int* __restrict__ ranks, double* __restrict__ scal, double floor2 = 0.0,
-                              bool presorted = false) {
+                              bool presorted = false, double tau_fixed = 0.0) {
     __shared__ double key[MAXM];
     __shared__ int idx[MAXM];
     __shared__ double scan[MAXM + 1];
@@ -48,7 +48,7 @@ __device__ __forceinline__ void truncate_mode(int mode, const double* __restrict
     for (int64_t i = t; i < anorm_ntiles; i += TB) v += anorm_part[i];
     const double a2 = block_sum(v, red);
     const double xi_norm = sqrt(xi2), a_norm = sqrt(fmax(a2, 0.0));
-    const double tau = (xi_norm > 0.0) ? eps * a_norm / (3.0 * xi_norm) : 0.0;
+    const double tau = tau_fixed > 0.0 ? tau_fixed : (xi_norm > 0.0) ? eps * a_norm / (3.0 * xi_norm) : 0.0;
 
     // eigenvalues, padded to a power of two with -inf
     int N2 = 1;
@@ -109,6 +109,7 @@ __device__ __forceinline__ void truncate_mode(int mode, const double* __restrict
     for (int i = t; i <= m; i += TB) tails[i] = sqrt(scan[i]);
     if (t == 0) {
         ranks[mode] = r;
+        scal[3 + mode] = sqrt(scan[r < m ? r : m]);
         if (mode == 0) { scal[0] = xi_norm; scal[1] = a_norm; scal[2] = tau; }
     }
 }
@@ -117,7 +118,22 @@ __global__ __launch_bounds__(TB) void k_truncate(TruncArgs a) {
     const int mode = blockIdx.x;
     const int m = a.m_mode[mode] > 0 ? a.m_mode[mode] : a.m;
     truncate_mode(mode, a.lam[mode], m, a.xip, a.R_pad, a.anorm_part, a.anorm_ntiles, a.eps, a.sigma[mode],
-                  a.order[mode], a.tails[mode], a.ranks, a.scal, a.floor2 ? a.floor2[mode] : 0.0, a.presorted != 0);
+                  a.order[mode], a.tails[mode], a.ranks, a.scal, a.floor2 ? a.floor2[mode] : 0.0, a.presorted != 0,
+                  a.tau_fixed);
+}
+
+// part[b] = sum of x[i]^2 over i = b, b + nparts, ... (one block per part, fixed order)
+__global__ __launch_bounds__(256) void k_sumsq_partials(const double* __restrict__ x, int64_t count,
+                                                        double* __restrict__ part, int nparts) {
+    __shared__ double red[40];
+    double v = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x + (int64_t)nparts * threadIdx.x; i < count; i += (int64_t)nparts * 256)
+        v += x[i] * x[i];
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // batched: grid (3, problems); problems with non-finite input are skipped
@@ -188,5 +204,11 @@ __global__ void k_combine_spectrum(int k, int m, const double* __restrict__ sig1
 hipError_t launch_combine_spectrum(int k, int m, const double* sig1, const double* sig2, const double* tails2,
                                    double* sigma, double* tails, hipStream_t st) {
     hipLaunchKernelGGL(k_combine_spectrum, dim3(1), dim3(256), 0, st, k, m, sig1, sig2, tails2, sigma, tails);
+    return hipGetLastError();
+}
+
+hipError_t launch_sumsq_partials(const double* x, int64_t count, double* part, int nparts, hipStream_t st) {
+    if (nparts < 1 || nparts > 1024 || count < 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sumsq_partials, dim3((unsigned)nparts), dim3(256), 0, st, x, count, part, nparts);
     return hipGetLastError();
 }

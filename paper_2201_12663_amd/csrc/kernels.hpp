@@ -141,12 +141,16 @@ struct TruncArgs {
     int* order[3];          // m each: column of W for the k-th largest
     double* tails[3];       // m + 1 each
     int* ranks;             // 3 ints (m + 1 when no r certifies, see floor2)
-    double* scal;           // [0] xi_norm, [1] a_norm, [2] tau
+    double* scal;           // [0] xi_norm, [1] a_norm, [2] tau, [3 + l] tail at mode l's rank
     int m_mode[3];          // per-mode number of eigenvalues (0: m)
     const double* floor2;   // per-mode squared tail floor (device, 3 doubles) or null
     int presorted;          // nonzero: keep the given order (no sort; order = identity)
+    double tau_fixed;       // > 0: use this tau instead of eps |A| / (3 |xi'|)
 };
 hipError_t launch_truncate(const TruncArgs& a, hipStream_t st);
+// Sums of squares of x[0 .. count) into part[0 .. nparts), each over a fixed
+// strided subset in a fixed order (nparts <= 1024).
+hipError_t launch_sumsq_partials(const double* x, int64_t count, double* part, int nparts, hipStream_t st);
 
 // a7: beta[j1 + r1 (j2 + r2 j3)] = sum_nu xi'_nu V1[j1,nu] V2[j2,nu] V3[j3,nu].
 // V_l: col-major (r_pad_l x R_pad), xip: R_pad.  prec 0 = f64, 1 = f32, 2 = bf16x3.

@@ -7,8 +7,11 @@ implementation.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
+import weakref
 from dataclasses import dataclass
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -17,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "librhosvd.so")
 FP64, FP32, BF16X3 = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
 PHASES = ["norms", "anorm", "gram", "eig", "trunc_z", "project", "core"]
+ANORM = {"auto": 0, "exact": 1, "probe": 2}
 
 STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_NONFINITE", -3: "ERR_ALLOC", -4: "ERR_DEVICE",
           -5: "ERR_NOCONV", -6: "ERR_STATE", -7: "ERR_UNSUPPORTED", -8: "ERR_CAPACITY"}
@@ -35,14 +39,15 @@ PATHS = {0: "range finder", 1: "gram (chosen)", 2: "gram (certificate failed)", 
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("max_eig_sweeps", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("beta_fp32", ctypes.c_int32), ("refine_tails", ctypes.c_int32),
-                ("core_tile", ctypes.c_int32), ("certificate", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
+                ("core_tile", ctypes.c_int32), ("certificate", ctypes.c_int32), ("anorm", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
     _fields_ = [("xi_norm", ctypes.c_double), ("a_norm", ctypes.c_double), ("tau", ctypes.c_double),
                 ("bound", ctypes.c_double), ("tail", ctypes.c_double * 3), ("ranks", ctypes.c_int32 * 3),
                 ("m", ctypes.c_int32), ("eig_sweeps", ctypes.c_int32), ("dropped", ctypes.c_int32),
-                ("certificate", ctypes.c_double)]
+                ("certificate", ctypes.c_double), ("a_norm_upper", ctypes.c_double),
+                ("anorm_method", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Problem(ctypes.Structure):
@@ -58,6 +63,21 @@ class LearnedInfo(ctypes.Structure):
     """rhosvd_learned_info"""
     _fields_ = [("proposal", ctypes.c_int32 * 3), ("width", ctypes.c_int32 * 3), ("fallback", ctypes.c_int32 * 3),
                 ("reserved", ctypes.c_int32), ("residual", ctypes.c_double * 3)]
+
+
+# Handles still open when the interpreter exits are closed by an atexit hook,
+# which runs before the C runtime's exit handlers (where the HIP runtime and
+# any loaded profiler tear down), so no library call reaches a finalized runtime.
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_handles():
+    for r in list(_live):
+        try:
+            r.close()
+        except Exception:
+            pass
 
 
 class RhosvdError(RuntimeError):
@@ -152,12 +172,13 @@ class Reducer:
     """One library handle bound to a stream."""
 
     def __init__(self, precision="fp64", stream=None, max_eig_sweeps=0, profile=False, beta_fp32=False,
-                 refine_tails=False, core_tile=0, certificate=False):
+                 refine_tails=False, core_tile=0, certificate=False, anorm="auto"):
         import torch
         self.lib = load()
         self.opt = Options()
         self.opt.core_tile = int(core_tile)
         self.opt.certificate = 1 if certificate else 0
+        self.opt.anorm = ANORM[anorm] if isinstance(anorm, str) else int(anorm)
         self.opt.beta_fp32 = 1 if beta_fp32 else 0
         self.opt.refine_tails = int(refine_tails) if refine_tails in (0, 1, 2) else -1
         self.beta_dtype = torch.float32 if beta_fp32 else torch.float64
@@ -174,13 +195,27 @@ class Reducer:
             raise RhosvdError(s, self.lib.rhosvd_last_error(None).decode())
         self.n = self.R = 0
         self.ranks = (0, 0, 0)
+        _live.add(self)
 
     def close(self):
+        """Release the handle (waits for its stream).  Idempotent."""
         if self.h:
             self.lib.rhosvd_destroy(self.h)
             self.h = ctypes.c_void_p()
+        _live.discard(self)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
 
     def __del__(self):
+        # during interpreter teardown the HIP runtime may already be gone: the
+        # atexit hook has closed every handle by then, so nothing is left to do
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -232,7 +267,8 @@ class Reducer:
                                         ctypes.byref(rep)))
         report = dict(xi_norm=rep.xi_norm, a_norm=rep.a_norm, tau=rep.tau, bound=rep.bound,
                       tail=list(rep.tail), ranks=list(rep.ranks), m=rep.m, eig_sweeps=rep.eig_sweeps,
-                      dropped=rep.dropped, certificate=rep.certificate)
+                      dropped=rep.dropped, certificate=rep.certificate, a_norm_upper=rep.a_norm_upper,
+                      anorm_method=rep.anorm_method)
         beta_t = None
         if b is not None:
             beta_t = b.view(r3, r2, r1).permute(2, 1, 0) if b.numel() > 0 else b.view(r1, r2, r3)

@@ -5,6 +5,7 @@ seeded generators; nothing is read from the GPU path.
 
     python tests/golden/make_golden.py newton1024 [seed]
     python tests/golden/make_golden.py hadamard512 [seed]
+    python tests/golden/make_golden.py batch [seed]
 
 newton1024: n=1024 grid on [-10,10]^3, R=4096 = 128 random +-1 charges x a
 32-term Gaussian sum for 1/|x| (exponents log-spaced in [1e-2, 1e4]), eps=1e-5.
@@ -17,6 +18,11 @@ Gaussian sums (R = 90000), eps in {1e-4, 1e-6}.  |A| from the product formed on
 the grid; per eps the ranks, tau, tails at the cut, the Theorem 2.3 bound, the
 exact error of the oracle's reduction against the materialized A, and (eps =
 1e-4) sampled core entries.
+
+batch: two problems of the uneven batch (seed 0 of the batch shapes) at their
+real sizes, the largest n <= R one (index 58: n=2048, R=7115) and the largest
+R < n one (index 179: n=2048, R=2041), each the first R terms of ceil(R/32)
+charges x 32 Gaussian terms, eps=1e-5.  Stores what newton1024 stores.
 """
 import json
 import os
@@ -45,6 +51,54 @@ def separated(sigma, r, rel_gap=1e-4):
         if min(lo, hi) > rel_gap * s2[0]:
             out.append(k)
     return out
+
+
+def reduction_record(ci, res, err, sample_seed, per_mode=12):
+    """Stored values of one oracle reduction: ranks, norms, tau, tails at the cut,
+    the bound, the exact error, every singular value and sampled core entries at
+    indices whose singular vectors are well separated."""
+    g = np.random.default_rng(sample_seed)
+    sep = [separated(res.sigma[l], res.ranks[l]) for l in range(3)]
+    picks = [np.sort(g.choice(sep[l], size=min(per_mode, len(sep[l])), replace=False)) for l in range(3)]
+    sub = oracle.core([res.V[l][picks[l], :] for l in range(3)], res.xip)
+    samples = []
+    for a, j1 in enumerate(picks[0]):
+        for b, j2 in enumerate(picks[1]):
+            for c, j3 in enumerate(picks[2]):
+                if (a + b + c) % 7 == 0:
+                    samples.append([int(j1), int(j2), int(j3), float(sub[a, b, c])])
+    return dict(
+        n=ci.n, R=ci.R, eps=ci.eps,
+        ranks=list(res.ranks), a_norm=res.a_norm, xi_norm=res.xi_norm, tau=res.tau,
+        tail_at_rank=[float(res.tails[l][res.ranks[l]]) for l in range(3)],
+        tail_below_rank=[float(res.tails[l][res.ranks[l] - 1]) for l in range(3)],
+        bound=res.bound, error=err, sweeps=res.sweeps,
+        sigma=[[float(x) for x in res.sigma[l]] for l in range(3)],
+        beta_samples=samples,
+        z_sign_rule="largest-magnitude entry of each column positive")
+
+
+def batch(seed=0):
+    shapes = inputs.batch_shapes(seed=seed, count=256)
+    out = dict(workload="uneven batch, seed %d: the largest n <= R and the largest R < n problem" % seed,
+               problems=[])
+    for idx in (58, 179):
+        n, R = shapes[idx]
+        t0 = time.time()
+        ci = inputs.batch_problem(seed, idx, n, R)
+        res = oracle.rhosvd(ci.U, ci.xi, ci.eps, with_core=False)
+        Ut, xip, _, _ = oracle.normalize(ci.U, ci.xi)
+        t1 = time.time()
+        err = oracle.error_gram(Ut, xip, res.Z)
+        t2 = time.time()
+        rec = reduction_record(ci, res, err, 1000 + idx)
+        rec.update(index=idx, seconds=dict(reduce=t1 - t0, error=t2 - t1))
+        out["problems"].append(rec)
+        print(idx, (n, R), rec["ranks"], "err/|A|", err / res.a_norm, "secs", rec["seconds"], flush=True)
+    path = os.path.join(HERE, f"batch_seed{seed}.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(path)
 
 
 def newton1024(seed=0):
@@ -136,4 +190,4 @@ def hadamard512(seed=0):
 if __name__ == "__main__":
     which = sys.argv[1] if len(sys.argv) > 1 else "newton1024"
     seed = int(sys.argv[2]) if len(sys.argv) > 2 else 0
-    {"newton1024": newton1024, "hadamard512": hadamard512}[which](seed)
+    {"newton1024": newton1024, "hadamard512": hadamard512, "batch": batch}[which](seed)

@@ -8,6 +8,7 @@ import math
 import numpy as np
 
 U64 = 2.0 ** -53
+U32 = 2.0 ** -24
 ETA64 = 2.0 ** -52     # relative error of the FP64 Gram matrix (a few ulps)
 
 
@@ -21,12 +22,12 @@ def eig_tol(n, R):
     return 16.0 * (math.sqrt(K) + m) * U64
 
 
-def run_gpu(ci, precision="fp64", want_beta=True, profile=False):
+def run_gpu(ci, precision="fp64", want_beta=True, profile=False, **kw):
     import torch
     from paper_2201_12663_amd import rhosvd
     U = [rhosvd.to_device(u) for u in ci.U]
     xi = torch.from_numpy(np.ascontiguousarray(ci.xi)).cuda()
-    red = rhosvd.Reducer(precision=precision, profile=profile)
+    red = rhosvd.Reducer(precision=precision, profile=profile, **kw)
     ranks = red.reduce(U[0], U[1], U[2], xi, ci.eps)
     res = red.get(beta=want_beta)
     spectra = [red.spectrum(l) for l in range(3)]
@@ -76,14 +77,35 @@ def align_signs(Zg, Zo):
     return np.sign(np.sum(Zg * Zo, axis=0) + 1e-300)
 
 
+def check_anorm(rep, a_exact, tau_exact):
+    """|A| as the path used it: the exact identity (equal to the oracle's to 1e-11),
+    or the probe's certified bracket a_norm <= |A| <= a_norm_upper, which puts the
+    path's tau at or below the oracle's.  Returns the tau the path cut with."""
+    if rep["anorm_method"] == 1:
+        assert abs(rep["a_norm"] - a_exact) <= 1e-11 * a_exact
+        assert abs(rep["tau"] - tau_exact) <= 1e-11 * tau_exact
+    else:
+        assert rep["anorm_method"] == 2
+        assert rep["a_norm"] <= a_exact * (1 + 1e-12), (rep["a_norm"], a_exact)
+        assert a_exact <= rep["a_norm_upper"] * (1 + 1e-12), (a_exact, rep["a_norm_upper"])
+        assert rep["tau"] <= tau_exact * (1 + 1e-12)
+    return rep["tau"]
+
+
 def compare_fp64(g, o, ci, check_beta=True):
-    """GPU FP64 result g (run_gpu) vs oracle result o (oracle.rhosvd)."""
+    """GPU FP64 result g (run_gpu) vs oracle result o (oracle.rhosvd).  Ranks are
+    compared with the oracle's cut at the tau the path used (the same as the
+    oracle's with the exact |A|; at most it with the probe's lower bound)."""
+    import oracle as orc
     # xi' elementwise
     assert np.allclose(g["xip"], o.xip, rtol=1e-13, atol=0.0)
     # norms
     rep = g["report"]
     assert abs(rep["xi_norm"] - o.xi_norm) <= 1e-13 * o.xi_norm
-    assert abs(rep["a_norm"] - o.a_norm) <= 1e-11 * o.a_norm
+    tau = check_anorm(rep, o.a_norm, o.tau)
+    o_ranks = tuple(orc.choose_rank(o.tails[l], tau) for l in range(3))
+    if o_ranks != tuple(o.ranks):
+        o = orc.rhosvd(ci.U, ci.xi, ci.eps, a_norm=o.a_norm * tau / o.tau)
     for l in range(3):
         s1 = o.sigma[l][0]
         m = len(o.sigma[l])
@@ -138,3 +160,72 @@ def recon_error(orc, ci, Z, beta=None):
         A = orc.full_tensor(Ut, xip)
         return float(np.linalg.norm((A - orc.reconstruct(beta, Z)).ravel()))
     return orc.error_gram(Ut, xip, Z)
+
+
+def pad64(x):
+    return -(-int(x) // 64) * 64
+
+
+def v_abs_error(n):
+    """Bound on the absolute error of one entry of the FP64 projection
+    V[j, nu] = z_j . u~_nu of unit vectors: the FP64 MFMA (16x16x4) accumulates
+    the n_pad products in n_pad/4 rounded steps, each partial sum at most
+    sum_i |z_i||u_i| <= 1 (Cauchy-Schwarz); doubled for safety."""
+    return 2.0 * (pad64(n) / 4 + 16) * U64
+
+
+def core_rel_const(prec, R, beta_fp32=False):
+    """c_p: |beta_gpu[j] - beta_exact[j]| <= c_p * S_j per entry, where
+    S_j = sum_nu |xi'_nu| |V1[j1,nu]| |V2[j2,nu]| |V3[j3,nu]| and the V are the
+    exact projections (their own error is added separately).  Per product:
+    FP64: two roundings (xi' V1 and V2 V3); FP32: the three V and xi' rounded to
+    float and the two products (6 u32); BF16x3: those plus the split (bf16 keeps
+    8 significant bits, so hi = bf16(a) is within 2^-8 |a| and lo = bf16(a - hi)
+    leaves |a - hi - lo| <= 2^-16 |a| for each operand, and the dropped lo*lo is
+    <= 2^-16 |ab|: 3 * 2^-16 in all).  Then one rounding per accumulation step:
+    R_pad/4 MFMA steps (16x16x4 FP64 / FP32), 3 R_pad / 32 for BF16x3 (three
+    16x16x32 products per 32 terms).  A float beta adds its final rounding."""
+    Rp = pad64(R)
+    if prec == "fp64":
+        c = (Rp / 4 + 8) * U64
+    elif prec == "fp32":
+        c = (Rp / 4 + 12) * U32
+    else:
+        c = 3 * 2.0 ** -16 + (3 * Rp / 32 + 12) * U32
+    return c + (U32 if beta_fp32 else 0.0)
+
+
+def check_core_slabs(orc, Ut, xip, Z, beta, j3s, prec, beta_fp32=False, what="", beta_is_slabs=False):
+    """Element-by-element check of the core on the j3-slabs j3s (Proposition 2.2):
+    the oracle forms V = Z^T U~ from its own normalized side matrices and the
+    returned (orthonormal) Z, and beta[:, :, j3] = V1 diag(xi' V3[j3, :]) V2^T.
+    Each entry must lie within c_p S_j + (S^d_j - S_j) of it, S^d the same sum
+    with every |V| raised by the projection's error bound d (v_abs_error).
+    With beta_is_slabs, beta holds only the slabs j3s (sorted, no repeats).
+    Returns the largest ratio |error| / tolerance over the slabs."""
+    n = Ut[0].shape[0]
+    R = Ut[0].shape[1]
+    V = [orc.project(Z[l], Ut[l]) for l in range(3)]
+    d = v_abs_error(n)
+    j3s = sorted(set(int(j) for j in j3s))
+    ref = orc.core([V[0], V[1], V[2][j3s, :]], xip)
+    aV = [np.abs(v) for v in V]
+    ax = np.abs(xip)
+    S = orc.core([aV[0], aV[1], aV[2][j3s, :]], ax)
+    Sd = orc.core([aV[0] + d, aV[1] + d, aV[2][j3s, :] + d], ax)
+    tol = core_rel_const(prec, R, beta_fp32) * S + (Sd - S) + 1e-300
+    got = np.asarray(beta if beta_is_slabs else beta[:, :, j3s], dtype=np.float64)
+    err = np.abs(got - ref)
+    worst = float(np.max(err / tol))
+    assert worst <= 1.0, (what, prec, "slab", j3s[int(np.argmax(np.max(err / tol, axis=(0, 1))))], worst)
+    return worst
+
+
+def boundary_slabs(r3, extra=()):
+    """j3 slabs at the core's tile edges (16-wide j2/j3 tiles, 64/128-row j1
+    tiles), the first and the ragged last slab, and any extra ones."""
+    js = {0, r3 - 1, min(15, r3 - 1), min(16, r3 - 1), r3 // 2}
+    for j in extra:
+        if 0 <= j < r3:
+            js.add(int(j))
+    return sorted(js)

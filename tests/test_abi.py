@@ -48,8 +48,8 @@ def test_version_and_null_handle_errors(lib):
 def test_struct_layouts_match_header():
     from paper_2201_12663_amd import rhosvd
     assert ctypes.sizeof(rhosvd.Options) == 32
-    # 4 doubles + 3 doubles + 3 int32 + 3 int32 + 1 double = 56 + 24 + 8 = 88
-    assert ctypes.sizeof(rhosvd.Report) == 88
+    # 4 doubles + 3 doubles + 3 int32 + 3 int32 + 2 doubles + 2 int32 = 56 + 24 + 16 + 8 = 104
+    assert ctypes.sizeof(rhosvd.Report) == 104
 
 
 def test_null_handle_batched(lib):

@@ -8,7 +8,7 @@ import math
 import numpy as np
 import pytest
 
-from gpu_cases import U64, cut_margin_ok, eig_tol
+from gpu_cases import U64, check_core_slabs, cut_margin_ok, eig_tol
 from paper_2201_12663_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -195,6 +195,8 @@ def test_batched_mixed_precision(orc, batch_inputs, prec):
             assert torch.equal(a["Z"][l], b["Z"][l]), (ci.name, l)
         Ut, xip, _, _ = orc.normalize(ci.U, ci.xi)
         Z = [z.cpu().numpy() for z in b["Z"]]
+        bb = b["beta"].cpu().numpy()
+        check_core_slabs(orc, Ut, xip, Z, bb, range(bb.shape[2]), prec, what=ci.name)
         be = orc.core([orc.project(Z[l], Ut[l]) for l in range(3)], xip)
         db = np.linalg.norm((b["beta"].cpu().numpy() - be).ravel())
         xin = float(np.linalg.norm(xip))
@@ -316,3 +318,65 @@ def test_beta_fp32_output_is_the_rounded_core(batch_inputs, prec):
     assert torch.equal(ob[0]["beta"], oa[0]["beta"].float())
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batched_real_sizes_vs_golden(orc, prec):
+    """The uneven batch's largest n <= R problem (n=2048, R=7115) and largest R < n
+    problem (n=2048, R=2041) in one batched pass with two small ones, against the
+    oracle's stored values (tests/golden/batch_seed0.json): ranks under the margin
+    rule, every singular value within the Gram route's accuracy, the oracle's core
+    samples (entries of well-separated singular vectors, FP64 cores), whole slabs
+    of the core element by element against the oracle's core of the returned Z,
+    and the exact error within eps |A| and the Theorem 2.3 bound."""
+    import json
+    import os
+    import torch
+    from gpu_cases import boundary_slabs, separated
+    from paper_2201_12663_amd import rhosvd
+    gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batch_seed0.json")))
+    shapes = inputs.batch_shapes(seed=0, count=256)
+    big = [inputs.batch_problem(0, p["index"], *shapes[p["index"]]) for p in gold["problems"]]
+    small = [make_problem(k, n, R, i) for i, (k, n, R) in enumerate(SHAPES[:2])]
+    cis = big + small
+    print(f"real-size batch {prec}:", [(ci.n, ci.R) for ci in cis], flush=True)
+    probs = [to_dev(ci) for ci in cis]
+    red = rhosvd.Reducer(precision=prec)
+    out, _, _, _ = red.reduce_batched(probs)
+    torch.cuda.synchronize()
+    for ci, g, o in zip(big, gold["problems"], out):
+        assert o["status"] == 0
+        r = o["ranks"]
+        m = min(ci.n, ci.R)
+        Z = [z.cpu().numpy() for z in o["Z"]]
+        for l in range(3):
+            so = np.array(g["sigma"][l])
+            tails = np.sqrt(np.concatenate([np.cumsum((so ** 2)[::-1])[::-1], [0.0]]))
+            if cut_margin_ok(tails, g["ranks"][l], g["tau"], so[0]):
+                assert r[l] == g["ranks"][l], (ci.name, l, r, g["ranks"])
+            assert np.max(np.abs(Z[l].T @ Z[l] - np.eye(r[l]))) <= 100 * m * U64
+        Ut, xip, _, _ = orc.normalize(ci.U, ci.xi)
+        beta = o["beta"]
+        if prec == "fp64":
+            checked = 0
+            for j1, j2, j3, v in g["beta_samples"]:
+                if j1 < r[0] and j2 < r[1] and j3 < r[2]:
+                    assert abs(float(beta[j1, j2, j3]) - v) <= 1e-9 * g["xi_norm"], (ci.name, j1, j2, j3)
+                    checked += 1
+            assert checked >= len(g["beta_samples"]) - 2
+        slabs = boundary_slabs(r[2], extra=(127, 128, 511, 512, 1023, 1024))
+        bs = beta[:, :, slabs].cpu().numpy()
+        w = check_core_slabs(orc, Ut, xip, Z, bs, slabs, prec, what=ci.name, beta_is_slabs=True)
+        err = orc.error_gram(Ut, xip, Z)
+        print(f"  {ci.name}: ranks {r} (oracle {g['ranks']}), worst core entry at {w:.3f} of its bound, "
+              f"rel err {err / g['a_norm']:.3e}", flush=True)
+        assert err <= ci.eps * g["a_norm"] * (1 + 1e-9)
+        del beta
+    for ci, o in zip(small, out[2:]):
+        assert o["status"] == 0
+        Z = [z.cpu().numpy() for z in o["Z"]]
+        check_against_oracle(orc, ci, o["ranks"], Z, o["beta"].cpu().numpy(),
+                             beta_tol=1e-10 if prec == "fp64" else 2e-6)
+    del out
+    red.close()
+    torch.cuda.empty_cache()

@@ -91,6 +91,11 @@ def test_mixed_precision_parity(orc, prec):
     assert err <= (ci.eps + 1e-6) * o.a_norm
     db = np.linalg.norm((g["beta"] - g64["beta"]).ravel()) / o.a_norm
     assert db <= (1e-5 if prec == "bf16x3" else 1e-6), db
+    # every entry of every slab against the oracle's core of Z (Proposition 2.2)
+    Ut, xip, _, _ = orc.normalize(ci.U, ci.xi)
+    for gg, p in ((g, prec), (g64, "fp64")):
+        w = gc.check_core_slabs(orc, Ut, xip, gg["Z"], gg["beta"], range(gg["ranks"][2]), p, what="n96 R300")
+        _flush(f"{p}: worst entry at {w:.3f} of its bound")
 
 
 def test_degenerate_single_term(orc):
@@ -196,14 +201,26 @@ def test_full_size_newton1024_vs_golden(orc):
         r = g["ranks"][l]
         Z = g["Z"][l]
         assert np.max(np.abs(Z.T @ Z - np.eye(r))) <= 1e-11
-    # sampled core entries (oracle's sign convention; separated singular vectors)
-    if list(g["ranks"]) == gold["ranks"]:
-        for j1, j2, j3, v in gold["beta_samples"]:
+    # sampled core entries of the oracle's own reduction (its sign convention; indices
+    # of well-separated singular vectors).  beta[j1,j2,j3] depends only on columns
+    # j1, j2, j3 of the Z's, not on the ranks, so a knife-edge rank difference in
+    # one mode leaves every sample below both ranks comparable
+    checked = 0
+    for j1, j2, j3, v in gold["beta_samples"]:
+        if j1 < g["ranks"][0] and j2 < g["ranks"][1] and j3 < g["ranks"][2]:
             assert abs(g["beta"][j1, j2, j3] - v) <= 1e-9 * gold["xi_norm"], (j1, j2, j3)
+            checked += 1
+    assert checked >= len(gold["beta_samples"]) - 2, checked
+    # whole slabs element by element: the oracle's core of the returned Z at the
+    # tile edges, the ragged last slab and a few more (Proposition 2.2)
+    Ut, xip, _, _ = orc.normalize(ci.U, ci.xi)
+    slabs = gc.boundary_slabs(g["ranks"][2], extra=(127, 128, 255, 256, 511, 512))
+    w = gc.check_core_slabs(orc, Ut, xip, g["Z"], g["beta"], slabs, "fp64", what="newton1024")
     err = gc.recon_error(orc, ci, g["Z"])
     assert err <= ci.eps * gold["a_norm"]
     assert err <= rep["bound"] * (1 + 1e-9)
-    _flush(f"full size: ranks {g['ranks']} rel err {err / gold['a_norm']:.3e}")
+    _flush(f"full size: ranks {g['ranks']} rel err {err / gold['a_norm']:.3e}, "
+           f"{checked} oracle samples, slabs {slabs}: worst entry at {w:.3f} of its bound")
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
@@ -216,10 +233,21 @@ def test_full_size_newton1024_mixed(orc, prec):
     assert g["ranks"] == g64["ranks"]
     err_z = gc.recon_error(orc, ci, g["Z"])
     a = g64["report"]["a_norm"]
-    db = float(np.linalg.norm((g["beta"] - g64["beta"]).ravel()))
-    # A - A_r is orthogonal to the Tucker subspace, the core error lies inside it
+    # whole slabs element by element against the oracle's core of Z, each entry
+    # within the mixed core's own bound (and the FP64 core's within its own)
+    Ut, xip, _, _ = orc.normalize(ci.U, ci.xi)
+    slabs = gc.boundary_slabs(g["ranks"][2], extra=(127, 128, 255, 256))
+    w = gc.check_core_slabs(orc, Ut, xip, g["Z"], g["beta"], slabs, prec, what="newton1024")
+    w64 = gc.check_core_slabs(orc, Ut, xip, g64["Z"], g64["beta"], slabs, "fp64", what="newton1024")
+    # the mixed core's whole distance from the exact core of Z, through the FP64
+    # core (same Z): |beta' - beta_e| <= |beta' - beta_64| + |beta_64 - beta_e|, the
+    # last at most the FP64 per-entry bound (below 1e-10 |xi'| here, checked on the
+    # slabs above).  The total error: A - A_r is orthogonal to the Tucker subspace
+    # and the core error lies inside it
+    db = float(np.linalg.norm((g["beta"] - g64["beta"]).ravel())) + 1e-10 * g64["report"]["xi_norm"]
     err = float(np.sqrt(err_z ** 2 + db ** 2))
-    _flush(f"{prec}: rel err {err / a:.3e} (core part {db / a:.3e})")
+    _flush(f"{prec}: worst slab entry at {w:.3f} of its bound (FP64 core {w64:.2e}); rel err {err / a:.3e} "
+           f"(core part {db / a:.3e})")
     assert err <= (ci.eps + 1e-6) * a
 
 
@@ -438,3 +466,88 @@ def test_certificate_after_deflated_pass(orc, prec):
     assert abs(cg - co) <= 1e-8 * co + 1e-13 * float(np.sum(np.abs(xip)))
     assert cg <= res.report["bound"] * (1 + 1e-9)
     assert orc.error_gram(Ut, xip, Z) <= cg * (1 + 1e-9) + 1e-12 * res.report["a_norm"]
+
+
+def smooth_wide(seed, n, R, eps, pairs=False):
+    """Wide Gaussians (alpha log-uniform in [0.05, 0.5]), centres in [-4, 4]^3, so the
+    side matrices have low numerical rank; with pairs, every term is followed by a
+    copy whose centre moved by 1e-3 and whose weight has the opposite sign, so that
+    |A| is about 1e-3 |xi'| (heavy cancellation)."""
+    g = np.random.default_rng(9000 + seed)
+    k = R // 2 if pairs else R
+    a = np.exp(g.uniform(np.log(0.05), np.log(0.5), k))
+    c = g.uniform(-4, 4, (k, 3))
+    xi = g.uniform(0.5, 1.5, k)
+    if pairs:
+        a = np.repeat(a, 2)
+        c = np.repeat(c, 2, axis=0)
+        c[1::2] += 1e-3
+        xi = np.repeat(xi, 2) * np.tile([1.0, -1.0], k)
+    U = inputs.gaussian_side_matrices(inputs.grid(n), a, c)
+    return inputs.CanonicalInput(U, xi, eps, name=f"smooth-wide n{n} R{R}{' pairs' if pairs else ''}")
+
+
+PROBE_CASES = [
+    ("gauss n64 R200", lambda: inputs.small_gaussian_sum(0)),
+    ("newton n160 R640", lambda: inputs.newton_centres(2, n=160, n_centres=20, eps=1e-5)),
+    ("smooth n96 R3000", lambda: smooth_wide(1, 96, 3000, 1e-6)),
+    ("lowrank n70 R150", lambda: inputs.exactly_low_rank(3, 70, 150, ranks=(3, 7, 12), eps=1e-8)),
+]
+
+
+@pytest.mark.parametrize("name,make", PROBE_CASES, ids=[c[0] for c in PROBE_CASES])
+def test_anorm_probe_certified_lower_bound(orc, name, make):
+    """rhosvd_options.anorm = probe: |A| from the FP64 core at the probe ranks
+    (tails <= 1/30).  Its value L = |beta_p| is a lower bound of the oracle's exact
+    |A| and (L^2 + b_p^2)^(1/2) an upper bound (Theorem 2.3 at the probe ranks);
+    tau is at most the oracle's; the ranks are the oracle's cut at that tau
+    (margin rule); the error stays within the bound, and the bound within
+    eps |A| with the exact |A|."""
+    ci = make()
+    _flush(f"probe case {name}")
+    o = orc.rhosvd(ci.U, ci.xi, ci.eps)
+    g = gc.run_gpu(ci, "fp64", anorm="probe")
+    rep = g["report"]
+    assert rep["anorm_method"] == 2
+    tau = gc.check_anorm(rep, o.a_norm, o.tau)
+    _flush(f"  L/|A| = {rep['a_norm'] / o.a_norm:.9f}, U/|A| = {rep['a_norm_upper'] / o.a_norm:.9f}")
+    for l in range(3):
+        r_ref = orc.choose_rank(o.tails[l], tau)
+        if gc.cut_margin_ok(o.tails[l], r_ref, tau, o.sigma[l][0]):
+            assert g["ranks"][l] == r_ref, (l, g["ranks"], r_ref)
+    err = gc.recon_error(orc, ci, g["Z"], g["beta"])
+    assert err <= rep["bound"] * (1 + 1e-9) + 1e-12 * o.a_norm
+    assert rep["bound"] <= ci.eps * o.a_norm * (1 + 1e-9)
+    # the same reduction with the exact identity: same spectrum, ranks no larger
+    g1 = gc.run_gpu(ci, "fp64", want_beta=False, anorm="exact")
+    assert g1["report"]["anorm_method"] == 1
+    assert all(a >= b for a, b in zip(g["ranks"], g1["ranks"]))
+    for l in range(3):
+        assert np.array_equal(g["spectra"][l], g1["spectra"][l])
+
+
+def test_anorm_auto_mode_choices(orc):
+    """Default |A| (anorm auto): the probe where n << R and the spectra are low
+    (its flops well under the identity's 3 n R^2), the exact identity where the
+    probe would cost more (n160 R640 here) and where heavy cancellation makes the
+    probe's bracket wide (|A| ~ 1e-3 |xi'|, so b_p > L / 10).  Every result is
+    certified against the oracle's exact |A|."""
+    for ci, want in ((smooth_wide(1, 96, 3000, 1e-6), 2),
+                     (inputs.newton_centres(2, n=160, n_centres=20, eps=1e-5), 1),
+                     (smooth_wide(2, 64, 2000, 1e-6, pairs=True), 1)):
+        o = orc.rhosvd(ci.U, ci.xi, ci.eps, with_core=False)
+        g = gc.run_gpu(ci, "fp64")
+        rep = g["report"]
+        _flush(f"{ci.name}: anorm method {rep['anorm_method']} (want {want}), |A|/|xi'| {o.a_norm / o.xi_norm:.3e}")
+        assert rep["anorm_method"] == want, ci.name
+        gc.check_anorm(rep, o.a_norm, o.tau)
+        assert rep["bound"] <= ci.eps * o.a_norm * (1 + 1e-9)
+        err = gc.recon_error(orc, ci, g["Z"])
+        # rounding scale: |xi'| (the terms' own size), not |A|, under cancellation
+        assert err <= rep["bound"] * (1 + 1e-9) + 1e-10 * o.xi_norm
+    # the forced probe under heavy cancellation is still certified (its tau only smaller)
+    ci = smooth_wide(2, 64, 2000, 1e-6, pairs=True)
+    o = orc.rhosvd(ci.U, ci.xi, ci.eps, with_core=False)
+    g = gc.run_gpu(ci, "fp64", anorm="probe")
+    gc.check_anorm(g["report"], o.a_norm, o.tau)
+    assert g["report"]["bound"] <= ci.eps * o.a_norm * (1 + 1e-9)

@@ -34,8 +34,12 @@ def run_single(ci, prec, tile, repeat=1):
     return outs
 
 
-def oracle_core_error(orc, ci, Z, beta):
+def oracle_core_error(orc, ci, Z, beta, prec):
+    """Every slab element by element (gpu_cases.check_core_slabs, which asserts)
+    and the Frobenius distance from the exact core of Z relative to |xi'|."""
+    import gpu_cases as gc
     Ut, xip, _, _ = orc.normalize(ci.U, ci.xi)
+    gc.check_core_slabs(orc, Ut, xip, Z, beta, range(beta.shape[2]), prec, what=ci.name)
     be = orc.core([orc.project(Z[l], Ut[l]) for l in range(3)], xip)
     return float(np.linalg.norm((beta - be).ravel())) / float(np.linalg.norm(xip))
 
@@ -51,7 +55,7 @@ def test_every_tile_matches_oracle(orc, prec, tile, name, make):
     ci = make()
     (ranks, Z, beta, used), = run_single(ci, prec, tile)
     assert used == tile
-    e = oracle_core_error(orc, ci, Z, beta)
+    e = oracle_core_error(orc, ci, Z, beta, prec)
     print(f"{name} {prec} tile {tile}: ranks {ranks} core error {e:.3e} |xi'|", flush=True)
     assert e <= TOL[prec]
 
@@ -107,6 +111,6 @@ def test_batched_tuning_then_replay(orc, prec):
     for ci, o, b in zip(cis, out2, first):
         assert torch.equal(o["beta"], b), ci.name
         Z = [z.cpu().numpy() for z in o["Z"]]
-        assert oracle_core_error(orc, ci, Z, o["beta"].cpu().numpy()) <= TOL[prec]
+        assert oracle_core_error(orc, ci, Z, o["beta"].cpu().numpy(), prec) <= TOL[prec]
     red.close()
     fixed.close()
