@@ -128,6 +128,20 @@ typedef struct {
                                 When R < n the identity's tiles are the Gram matrices
                                 themselves, so it is always exact there.  Batched and
                                 learned reductions use the exact identity. */
+    int32_t als_sweeps;      /* 0..4: sweeps of the canonical-to-Tucker ALS iteration started from
+                                the RHOSVD factors (Section 2.1 after Definition 2.1, eq.
+                                eqn:can_A_Tuck_als), run by rhosvd_reduce after Z at fixed
+                                ranks.  For mode l (others a, b, modes taken 1, 2, 3 in turn,
+                                each with the others' latest factors) Z_l becomes the r_l
+                                leading left singular vectors of the contracted unfolding
+                                M_l = U~_l diag(xi') (V_b (.) V_a)^T, computed as the leading
+                                eigenvectors of M_l M_l^T = U~_l diag(xi') (V_a^T V_a o
+                                V_b^T V_b) diag(xi') U~_l^T in FP64.  Each update maximizes
+                                |beta| given the others, so |A - A_r| only decreases and the
+                                Theorem 2.3 bound of the RHOSVD factors (the report's) still
+                                holds.  n <= R <= 16384 (the R x R FP64 products);
+                                otherwise RHOSVD_ERR_UNSUPPORTED.  Not used by batched or
+                                learned reductions. */
 } rhosvd_options;
 
 typedef struct {
@@ -336,6 +350,53 @@ rhosvd_status rhosvd_sketch_features(rhosvd_handle h, int64_t n, int64_t R, cons
 rhosvd_status rhosvd_reduce_learned(rhosvd_handle h, int64_t n, int64_t R, const double* U1, const double* U2,
                                     const double* U3, const double* xi, double eps, const double* omega,
                                     int32_t omega_cols, int32_t ranks[3], rhosvd_learned_info* info);
+
+/*
+ * Tucker-to-canonical transform (T2C) of a 3rd-order core (Section 2.3,
+ * Remark 2.6, eqs. T2C_slice, T2C_SVD, beta_R).  The core is written as the sum
+ * of its third-mode slices, beta = sum_m B_m (x) e_m with B_m = beta[:, :, m]
+ * (r1 x r2); each slice's SVD keeps its p_m singular values above the threshold
+ *     thr = eps / (r3 sqrt(min(r1, r2)))     (eps / r^(3/2) for an r x r x r core)
+ * and the kept terms of all slices give the canonical tensor
+ *     beta_(R) = sum_m sum_{k <= p_m} sigma_k^(m) u_k^(m) (x) v_k^(m) (x) e_m,
+ * of rank R = p_1 + ... + p_r3 <= r3 min(r1, r2), with
+ *     |beta - beta_(R)|_F <= sum_m (sum_{k > p_m} sigma_k^(m)^2)^(1/2) <= eps.
+ * eps is absolute (as in the remark); a relative accuracy is eps_rel |beta|_F.
+ * With orthonormal Tucker factors Z^(l) the same holds for the full tensors:
+ * lifting the factors, A_(R) = sum sigma (Z1 u) (x) (Z2 v) (x) z3_m, leaves
+ * |A_r - A_(R)| = |beta - beta_(R)|.
+ *
+ * Each slice is decomposed by a one-sided Jacobi SVD in one workgroup's LDS:
+ * min(r1, r2) <= 256 and r1 * r2 * 8 bytes <= 152 KiB (a 139 x 139 core, or
+ * 64 x 304 ...); larger cores give RHOSVD_ERR_UNSUPPORTED.
+ *
+ * rhosvd_t2c: phase 1, the slice SVDs and the counts.
+ *   r1, r2, r3 : core dimensions (>= 1)
+ *   beta       : DEVICE, r1*r2*r3 doubles, Fortran order (index j1 + r1 (j2 + r2 j3)),
+ *                for example rhosvd_get's FP64 output; read again by rhosvd_t2c_get,
+ *                so it must stay valid and unchanged until then
+ *   eps        : absolute accuracy, > 0
+ *   R          : HOST, receives the canonical rank R
+ *   bound      : HOST, nullable, receives sum_m (sum_{k > p_m} sigma_k^2)^(1/2)
+ * Synchronizes with the handle's stream once.  Errors: ARG, UNSUPPORTED,
+ * NOCONV (a slice's Jacobi sweeps did not converge), ALLOC, DEVICE.
+ *
+ * rhosvd_t2c_get: phase 2, the R terms of the last rhosvd_t2c on this handle.
+ *   weights : DEVICE, R doubles (sigma_k^(m), slices in order, descending within one)
+ *   F1, F2  : DEVICE, r1 x R and r2 x R (column-major, ld r1 / r2): unit u_k, v_k
+ *   slice   : DEVICE, R int32: m of each term (its third factor is e_m)
+ *   n, Z1, Z2, Z3, C1, C2, C3 : optional lifting (all non-NULL and n >= 1, or
+ *             all NULL): Z_l DEVICE n x r_l (ld n, orthonormal columns), C_l DEVICE
+ *             n x R (ld n) receive Z1 F1, Z2 F2 and the columns Z3[:, slice]
+ *   sigma   : DEVICE, nullable, r3 * min(r1, r2) doubles: every slice's singular
+ *             values, slice by slice, descending
+ * Enqueued on the handle's stream; does not synchronize.  Errors: STATE, ARG, DEVICE.
+ */
+rhosvd_status rhosvd_t2c(rhosvd_handle h, int32_t r1, int32_t r2, int32_t r3, const double* beta, double eps,
+                         int64_t* R, double* bound);
+rhosvd_status rhosvd_t2c_get(rhosvd_handle h, double* weights, double* F1, double* F2, int32_t* slice,
+                             double* sigma, int64_t n, const double* Z1, const double* Z2, const double* Z3,
+                             double* C1, double* C2, double* C3);
 
 /* Phase times in milliseconds of the last rhosvd_reduce / rhosvd_get when the
  * handle was created with profile != 0 (synchronizes with the stream):

@@ -56,7 +56,7 @@ struct rhosvd_ctx {
     // eigensolver plans (Gram matrices; R < n re-orthonormalization) and their work memory
     // [0] Gram matrices, [1] R < n re-orthonormalization, [2] sketch Grams of the
     // rank proposal, [3] range-finder matrices
-    static constexpr int NPLAN = 4;
+    static constexpr int NPLAN = 5;     // [4]: the ALS Gram matrix (one n x n matrix)
     EigPlan* plan[NPLAN] = {};
     std::vector<EigMat> plan_mats[NPLAN];
     void* plan_w[NPLAN] = {};
@@ -90,6 +90,10 @@ struct rhosvd_ctx {
     double* Cz[3] = {};                  //   Z_k^T Z' (zr_pad x zr_pad)
     double* dscr = nullptr;              //   first-pass spectrum, second-pass spectrum and tails
     double* rpart[3] = {};               // refine_tails: residual partial sums
+    double* Ha = nullptr;                // ALS: V_a^T V_a, then P (R_pad x R_pad)
+    double* Hb = nullptr;                // ALS: V_b^T V_b (R_pad x R_pad)
+    double* Tals = nullptr;              // ALS: U~_l P (n_pad x R_pad)
+    double* V64a[3] = {};                // ALS on a mixed path: FP64 projections (zr_pad x R_pad)
     double* rfloor = nullptr;            // refine_tails: squared residuals (3)
     int vprec = 0;
     // R < n: Z = U~ W_r Lambda_r^-1/2, re-orthonormalized by (Z^T Z)^-1/2
@@ -132,6 +136,21 @@ struct rhosvd_ctx {
         float* feat = nullptr;
         float* out = nullptr;
     } L;
+    // Tucker-to-canonical transform: state of the last rhosvd_t2c (grow-only workspace)
+    struct T2C {
+        char* ws = nullptr;
+        size_t bytes = 0;
+        char* lw = nullptr;              // lifting scratch: padded Z, F and C
+        size_t lbytes = 0;
+        int r1 = 0, r2 = 0, r3 = 0;
+        const double* beta = nullptr;
+        int64_t R = 0;
+        bool have = false;
+        double *W = nullptr, *sig = nullptr, *tails = nullptr;
+        int* p = nullptr;
+        int64_t* off = nullptr;
+        int* flags = nullptr;
+    } T;
     // profiling
     hipEvent_t ev[NEV] = {};
     bool ev_ok = false;
@@ -157,6 +176,7 @@ rhosvd_status check_options(const rhosvd_options* o, std::string& msg) {
     if (!o) return RHOSVD_OK;
     if (o->precision < 0 || o->precision > 2) { msg = "unknown precision"; return RHOSVD_ERR_ARG; }
     if (o->anorm < 0 || o->anorm > 2) { msg = "anorm must be 0 (auto), 1 (exact) or 2 (probe)"; return RHOSVD_ERR_ARG; }
+    if (o->als_sweeps < 0 || o->als_sweeps > 4) { msg = "als_sweeps must be 0..4"; return RHOSVD_ERR_ARG; }
     if (o->refine_tails < 0 || o->refine_tails > 2) { msg = "refine_tails must be 0, 1 or 2"; return RHOSVD_ERR_ARG; }
     if (o->core_tile != 0 && !core_tile_valid(o->precision, o->core_tile)) {
         msg = "core_tile must be 0 (tuned), 64, or 128 (128 only for the FP32 and BF16x3 cores)";
@@ -217,6 +237,11 @@ size_t carve_all(rhosvd_ctx* h, char* base) {
         h->Zs[l] = deflate ? c.take<double>((size_t)np * zp) : nullptr;
         h->Cz[l] = deflate ? c.take<double>((size_t)zp * zp) : nullptr;
     }
+    const bool als = h->opt.als_sweeps > 0 && !h->rside;
+    h->Ha = als ? c.take<double>((size_t)Rp * Rp) : nullptr;
+    h->Hb = als ? c.take<double>((size_t)Rp * Rp) : nullptr;
+    h->Tals = als ? c.take<double>((size_t)np * Rp) : nullptr;
+    for (int l = 0; l < 3; ++l) h->V64a[l] = (als && esz == 4) ? c.take<double>((size_t)zp * Rp) : nullptr;
     h->Asplit = h->opt.precision == RHOSVD_BF16X3 ? (void*)c.take<char>((size_t)zp * Rp * 4) : nullptr;
     const bool cert = h->opt.certificate != 0;
     h->Vc = (cert && esz == 4) ? c.take<double>((size_t)zp * Rp) : nullptr;
@@ -562,6 +587,53 @@ rhosvd_status anorm_probe(rhosvd_ctx* h, int mode, bool* z_all) {
     return RHOSVD_OK;
 }
 
+// ALS sweeps at fixed ranks (rhosvd_options.als_sweeps; n <= R).  For mode l with
+// the others a, b: P = diag(xi') (V_a^T V_a o V_b^T V_b) diag(xi'), G = U~_l P U~_l^T
+// (= M_l M_l^T for the contracted unfolding M_l = U~_l diag(xi') (V_b (.) V_a)^T),
+// Z_l = its r_l leading eigenvectors (same eigensolver, sign rule), V_l = Z_l^T U~_l.
+// Modes are updated in the order 0, 1, 2, each with the others' latest V.  Uses the
+// mode-0 eigensolver buffers for every mode; leaves V in the path's precision.
+rhosvd_status als_refine(rhosvd_ctx* h) {
+    hipStream_t st = h->stream;
+    const int64_t np = h->n_pad, Rp = h->R_pad, mp = h->m_pad;
+    const int m = (int)h->m;
+    const bool f64 = h->vprec == RHOSVD_FP64;
+    double* V64[3];
+    for (int l = 0; l < 3; ++l) {
+        V64[l] = f64 ? (double*)h->V[l] : h->V64a[l];
+        if (!f64) CK(h, launch_project(np, Rp, h->r_pad[l], h->Z[l], h->Ut[l], V64[l], nullptr, st));
+    }
+    EigMat em{h->G[0], h->lam[0], h->W[0], h->Qn[0], h->Mg[0], h->dd[0], h->ee[0], h->htau[0], m, (int)mp};
+    rhosvd_status s = ensure_plan(h, 4, &em, 1);
+    if (s != RHOSVD_OK) return s;
+    for (int sweep = 0; sweep < h->opt.als_sweeps; ++sweep) {
+        for (int l = 0; l < 3; ++l) {
+            const int a = l == 0 ? 1 : 0, b = l == 2 ? 1 : 2;
+            CK(h, launch_gemm64(true, true, Rp, Rp, h->r_pad[a], V64[a], h->r_pad[a], V64[a], h->r_pad[a], h->Ha, Rp,
+                                1.0, st));
+            CK(h, launch_gemm64(true, true, Rp, Rp, h->r_pad[b], V64[b], h->r_pad[b], V64[b], h->r_pad[b], h->Hb, Rp,
+                                1.0, st));
+            CK(h, launch_als_hadamard(Rp, h->Ha, h->Hb, h->xip, st));
+            CK(h, launch_gemm64(false, true, np, Rp, Rp, h->Ut[l], np, h->Ha, Rp, h->Tals, np, 1.0, st));
+            CK(h, launch_gemm64(false, false, np, np, Rp, h->Tals, np, h->Ut[l], np, h->G[0], mp, 1.0, st));
+            CK(h, eig_plan_enqueue(h->plan[4], h->flags + 2, st));
+            CK(h, launch_order_desc(h->lam[0], m, h->order[0], st));
+            const int r = h->ranks[l];
+            BtJob jb{m, (int)mp, h->G[0], h->htau[0], h->W[0], h->order[0], r, nullptr, h->Z[l], (int)np, (int)np,
+                     h->Tw[0]};
+            CK(h, launch_backtransform(&jb, 1, st));
+            CK(h, launch_sign_cols((int)h->n, (int)np, r, h->Z[l], st));
+            if (h->r_pad[l] > r)
+                CK(h, hipMemsetAsync(h->Z[l] + (int64_t)r * np, 0, (size_t)(h->r_pad[l] - r) * np * 8, st));
+            CK(h, launch_project(np, Rp, h->r_pad[l], h->Z[l], h->Ut[l], V64[l], nullptr, st));
+        }
+    }
+    if (!f64)
+        for (int l = 0; l < 3; ++l)
+            CK(h, launch_project(np, Rp, h->r_pad[l], h->Z[l], h->Ut[l], nullptr, (float*)h->V[l], st));
+    return RHOSVD_OK;
+}
+
 // refine_tails = 2 (n <= R): a second, deflated Gram pass.  The leading k_l
 // eigenvectors of the first pass (sigma >= 2^-13 sigma_1, where the FP64 Gram
 // route is accurate) form Z_k; the side matrix is deflated twice,
@@ -706,6 +778,8 @@ rhosvd_status rhosvd_destroy(rhosvd_handle h) {
     if (h->batch) batch_plan_destroy(h->batch);
     if (h->net) hipFree(h->net);
     if (h->L.ws) hipFree(h->L.ws);
+    if (h->T.ws) hipFree(h->T.ws);
+    if (h->T.lw) hipFree(h->T.lw);
     if (h->net_work) hipFree(h->net_work);
     for (int i = 0; i < rhosvd_ctx::NPLAN; ++i) {
         if (h->plan[i]) eig_plan_destroy(h->plan[i]);
@@ -739,6 +813,8 @@ rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R, const double*
     if (!(eps > 0.0) || !isfinite(eps)) return fail(h, RHOSVD_ERR_ARG, "eps must be finite and > 0");
     if ((n < R ? n : R) > 2048) return fail(h, RHOSVD_ERR_UNSUPPORTED, "min(n, R) > 2048 is not supported by this library");
     if (n > 65536) return fail(h, RHOSVD_ERR_UNSUPPORTED, "n > 65536 is not supported by this library");
+    if (h->opt.als_sweeps > 0 && (R < n || R > 16384))
+        return fail(h, RHOSVD_ERR_UNSUPPORTED, "ALS sweeps need n <= R <= 16384");
     rhosvd_status s = layout(h, n, R);
     if (s != RHOSVD_OK) return s;
     hipStream_t st = h->stream;
@@ -897,6 +973,13 @@ rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R, const double*
             else
                 CK(h, launch_v_finalize(r, h->r_pad[l], h->R_pad, h->Vref[l], nullptr, (float*)h->V[l], st));
         }
+    }
+    if (h->opt.als_sweeps > 0 && h->ranks[0] > 0 && h->ranks[1] > 0 && h->ranks[2] > 0) {
+        rhosvd_status as = als_refine(h);
+        if (as != RHOSVD_OK) return as;
+        CK(h, hipMemcpyAsync(h->host + 6, h->flags + 2, sizeof(int), hipMemcpyDeviceToHost, st));
+        CK(h, hipStreamSynchronize(st));
+        if (h->host[6]) return fail(h, RHOSVD_ERR_DEVICE, "eigensolver: a cross-workgroup wait ran out");
     }
     mark(h, 6);
     h->reduce_timed = true;
@@ -1420,6 +1503,125 @@ rhosvd_status rhosvd_reduce_learned(rhosvd_handle h, int64_t n, int64_t R, const
     for (int l = 0; l < 3; ++l) ranks[l] = h->ranks[l];
     if (info) *info = li;
     h->have = true;
+    return RHOSVD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Tucker-to-canonical transform (Remark 2.6)
+// ---------------------------------------------------------------------------
+rhosvd_status rhosvd_t2c(rhosvd_handle h, int32_t r1, int32_t r2, int32_t r3, const double* beta, double eps,
+                         int64_t* R, double* bound) {
+    if (!h) return RHOSVD_ERR_ARG;
+    h->err.clear();
+    auto& T = h->T;
+    T.have = false;
+    if (!beta || !R) return fail(h, RHOSVD_ERR_ARG, "beta and R are required");
+    if (r1 < 1 || r2 < 1 || r3 < 1) return fail(h, RHOSVD_ERR_ARG, "core dimensions must be >= 1");
+    if (!(eps > 0.0) || !isfinite(eps)) return fail(h, RHOSVD_ERR_ARG, "eps must be finite and > 0");
+    if (std::min(r1, r2) > T2C_MAXC || t2c_lds_bytes(r1, r2) > T2C_MAX_LDS)
+        return fail(h, RHOSVD_ERR_UNSUPPORTED, "core slices too large for the one-workgroup Jacobi SVD "
+                                               "(min(r1, r2) <= 256 and r1 r2 <= 19456)");
+    hipStream_t st = h->stream;
+    const int L = std::max(r1, r2), c = std::min(r1, r2);
+    Carve cv{nullptr};
+    auto carve = [&](Carve& k) {
+        T.W = k.take<double>((size_t)r3 * L * c);
+        T.sig = k.take<double>((size_t)r3 * c);
+        T.tails = k.take<double>(r3);
+        T.p = k.take<int>(r3);
+        T.off = k.take<int64_t>((size_t)r3 + 1);
+        T.flags = k.take<int>(4);
+    };
+    carve(cv);
+    if (cv.off > T.bytes) {
+        if (T.ws) { CK(h, hipStreamSynchronize(st)); hipFree(T.ws); T.ws = nullptr; T.bytes = 0; }
+        if (hipMalloc((void**)&T.ws, cv.off) != hipSuccess) {
+            T.ws = nullptr;
+            return fail(h, RHOSVD_ERR_ALLOC, "T2C workspace allocation of " + std::to_string(cv.off) + " bytes failed");
+        }
+        T.bytes = cv.off;
+    }
+    Carve ck{T.ws};
+    carve(ck);
+    const double thr = eps / ((double)r3 * sqrt((double)c));
+    CK(h, hipMemsetAsync(T.flags, 0, 4 * sizeof(int), st));
+    CK(h, launch_t2c_jacobi(beta, r1, r2, r3, thr, 60, T.W, T.sig, T.p, T.tails, T.flags, st));
+    std::vector<int> p(r3);
+    std::vector<double> tl(r3);
+    int flag = 0;
+    CK(h, hipMemcpyAsync(p.data(), T.p, (size_t)r3 * sizeof(int), hipMemcpyDeviceToHost, st));
+    CK(h, hipMemcpyAsync(tl.data(), T.tails, (size_t)r3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    CK(h, hipMemcpyAsync(&flag, T.flags, sizeof(int), hipMemcpyDeviceToHost, st));
+    CK(h, hipStreamSynchronize(st));
+    if (flag) return fail(h, RHOSVD_ERR_NOCONV, "T2C: a slice's Jacobi sweeps did not converge");
+    std::vector<int64_t> off((size_t)r3 + 1, 0);
+    double b = 0.0;
+    for (int m = 0; m < r3; ++m) {
+        if (p[m] < 0 || p[m] > c) return fail(h, RHOSVD_ERR_DEVICE, "T2C: invalid slice rank (internal error)");
+        off[m + 1] = off[m] + p[m];
+        b += tl[m];
+    }
+    CK(h, hipMemcpy(T.off, off.data(), off.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    T.r1 = r1;
+    T.r2 = r2;
+    T.r3 = r3;
+    T.beta = beta;
+    T.R = off[r3];
+    T.have = true;
+    *R = T.R;
+    if (bound) *bound = b;
+    return RHOSVD_OK;
+}
+
+rhosvd_status rhosvd_t2c_get(rhosvd_handle h, double* weights, double* F1, double* F2, int32_t* slice,
+                             double* sigma, int64_t n, const double* Z1, const double* Z2, const double* Z3,
+                             double* C1, double* C2, double* C3) {
+    if (!h) return RHOSVD_ERR_ARG;
+    auto& T = h->T;
+    if (!T.have) return fail(h, RHOSVD_ERR_STATE, "no successful rhosvd_t2c on this handle");
+    const bool lift_any = Z1 || Z2 || Z3 || C1 || C2 || C3;
+    const bool lift = lift_any && n >= 1 && Z1 && Z2 && Z3 && C1 && C2 && C3;
+    if (lift_any && !lift) return fail(h, RHOSVD_ERR_ARG, "lifting needs n >= 1 and all of Z1..Z3, C1..C3");
+    if (T.R > 0 && (!weights || !F1 || !F2 || !slice))
+        return fail(h, RHOSVD_ERR_ARG, "weights, F1, F2 and slice are required");
+    hipStream_t st = h->stream;
+    const int c = std::min(T.r1, T.r2);
+    if (sigma) CK(h, hipMemcpyAsync(sigma, T.sig, (size_t)T.r3 * c * 8, hipMemcpyDeviceToDevice, st));
+    if (T.R < 1) return RHOSVD_OK;
+    CK(h, launch_t2c_terms(T.beta, T.r1, T.r2, T.r3, T.W, T.sig, T.off, T.R, weights, F1, T.r1, F2, T.r2, slice, st));
+    if (!lift) return RHOSVD_OK;
+    // C_l = Z_l F_l through the FP64 MFMA GEMM on zero-padded copies
+    const int64_t np = round_up(n, 64), Rp = round_up(T.R, 64);
+    const int64_t kp = round_up(std::max(T.r1, T.r2), 64);
+    const size_t need = a256((size_t)np * kp * 8) + a256((size_t)kp * Rp * 8) + a256((size_t)np * Rp * 8);
+    if (need > T.lbytes) {
+        if (T.lw) { CK(h, hipStreamSynchronize(st)); hipFree(T.lw); T.lw = nullptr; T.lbytes = 0; }
+        if (hipMalloc((void**)&T.lw, need) != hipSuccess) {
+            T.lw = nullptr;
+            return fail(h, RHOSVD_ERR_ALLOC, "T2C lifting workspace allocation of " + std::to_string(need) +
+                                                 " bytes failed");
+        }
+        T.lbytes = need;
+    }
+    double* Zp = (double*)T.lw;
+    double* Fp = (double*)(T.lw + a256((size_t)np * kp * 8));
+    double* Cp = (double*)(T.lw + a256((size_t)np * kp * 8) + a256((size_t)kp * Rp * 8));
+    const double* Zs[2] = {Z1, Z2};
+    const double* Fs[2] = {F1, F2};
+    double* Cs[2] = {C1, C2};
+    const int rs[2] = {T.r1, T.r2};
+    for (int l = 0; l < 2; ++l) {
+        CK(h, hipMemsetAsync(Zp, 0, (size_t)np * kp * 8, st));
+        CK(h, hipMemsetAsync(Fp, 0, (size_t)kp * Rp * 8, st));
+        CK(h, hipMemcpy2DAsync(Zp, (size_t)np * 8, Zs[l], (size_t)n * 8, (size_t)n * 8, (size_t)rs[l],
+                               hipMemcpyDeviceToDevice, st));
+        CK(h, hipMemcpy2DAsync(Fp, (size_t)kp * 8, Fs[l], (size_t)rs[l] * 8, (size_t)rs[l] * 8, (size_t)T.R,
+                               hipMemcpyDeviceToDevice, st));
+        CK(h, launch_gemm64(false, true, np, Rp, kp, Zp, np, Fp, kp, Cp, np, 1.0, st));
+        CK(h, hipMemcpy2DAsync(Cs[l], (size_t)n * 8, Cp, (size_t)np * 8, (size_t)n * 8, (size_t)T.R,
+                               hipMemcpyDeviceToDevice, st));
+    }
+    CK(h, launch_t2c_gather_cols((int)n, T.R, Z3, n, slice, C3, n, st));
     return RHOSVD_OK;
 }
 

@@ -285,3 +285,29 @@ hipError_t launch_row_norms2(int p, int ld, int64_t R_pad, const double* V, doub
 hipError_t launch_square_prefix(int r, const double* sigma, double* out, hipStream_t st);
 hipError_t launch_v_finalize(int keep, int ld, int64_t R_pad, const double* src, double* dst64, float* dst32,
                              hipStream_t st);
+
+// Tucker-to-canonical transform (k_t2c.hip).  Slices B_m = beta[:, :, m] of an
+// r1 x r2 x r3 FP64 core (Fortran order); min(r1, r2) <= T2C_MAXC and r1 r2
+// doubles within T2C_MAX_LDS bytes (the slice lives in one workgroup's LDS).
+constexpr int T2C_MAXC = 256;
+constexpr size_t T2C_MAX_LDS = 152 * 1024;
+size_t t2c_lds_bytes(int r1, int r2);
+// one-sided Jacobi SVD of every slice: Wout (r3 x L x c: unit singular vectors on
+// the side of length L = max(r1, r2), by descending sigma), sig_out (r3 x c,
+// descending), p_out (r3: sigma > thr), tail_out (r3: dropped tail norms);
+// flags |= 1 when a slice did not converge within max_sweeps
+hipError_t launch_t2c_jacobi(const double* beta, int r1, int r2, int r3, double thr, int max_sweeps, double* Wout,
+                             double* sig_out, int* p_out, double* tail_out, int* flags, hipStream_t st);
+// the R kept terms (off: r3 + 1 prefix offsets of p): weights, u_k into F1 (ld1),
+// v_k into F2 (ld2), slice index of each term
+hipError_t launch_t2c_terms(const double* beta, int r1, int r2, int r3, const double* Wj, const double* sig,
+                            const int64_t* off, int64_t R, double* weights, double* F1, int64_t ld1, double* F2,
+                            int64_t ld2, int* slice_of, hipStream_t st);
+// C[:, t] = Z[:, slice_of[t]]
+hipError_t launch_t2c_gather_cols(int n, int64_t R, const double* Z, int64_t ldz, const int* slice_of, double* C,
+                                  int64_t ldc, hipStream_t st);
+
+// ALS refinement (k_als.hip): Ha <- diag(xi') (Ha o Hb) diag(xi') on R_pad x R_pad,
+// and the descending order of m eigenvalues
+hipError_t launch_als_hadamard(int64_t R_pad, double* Ha, const double* Hb, const double* xip, hipStream_t st);
+hipError_t launch_order_desc(const double* lam, int m, int* order, hipStream_t st);

@@ -34,6 +34,7 @@ WL_BATCH = 3            # 256 uneven (n, R) problems
 WL_RANKNET = 4          # rank-proposal training / evaluation draws
 WL_LOWRANK = 10         # exactly-low-rank test inputs
 WL_RANDOM = 11          # dense random test inputs
+WL_CORE = 13            # synthetic Tucker cores (Tucker-to-canonical tests)
 
 
 def rng(workload: int, seed: int) -> np.random.Generator:
@@ -245,3 +246,23 @@ def random_dense(seed: int, n: int, R: int, eps: float = 1e-3) -> CanonicalInput
     U = [np.asfortranarray(g.standard_normal((n, R))) for _ in range(3)]
     xi = g.standard_normal(R)
     return CanonicalInput(U, xi, eps, name=f"random-n{n}-R{R}")
+
+
+def core_with_slice_spectra(seed: int, r1: int, r2: int, r3: int, spectra) -> np.ndarray:
+    """An r1 x r2 x r3 core (Fortran order) whose third-mode slice m is
+    Q_m diag(spectra[m]) P_m^T with random orthonormal Q_m (r1 x k), P_m (r2 x k),
+    k = min(r1, r2): the slices' singular values are spectra[m] exactly (up to
+    rounding)."""
+    g = rng(WL_CORE, seed)
+    k = min(r1, r2)
+    beta = np.zeros((r1, r2, r3), order="F")
+    for m in range(r3):
+        Q, _ = np.linalg.qr(g.standard_normal((r1, k)))
+        P, _ = np.linalg.qr(g.standard_normal((r2, k)))
+        beta[:, :, m] = (Q * np.asarray(spectra[m])[None, :]) @ P.T
+    return beta
+
+
+def random_core(seed: int, r1: int, r2: int, r3: int) -> np.ndarray:
+    """Gaussian random core (Fortran order)."""
+    return np.asfortranarray(rng(WL_CORE, 100_000 + seed).standard_normal((r1, r2, r3)))

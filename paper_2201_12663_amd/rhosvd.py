@@ -30,7 +30,7 @@ EXPORTS = ["rhosvd_create", "rhosvd_destroy", "rhosvd_set_options", "rhosvd_redu
            "rhosvd_get_xi", "rhosvd_get_spectrum", "rhosvd_get_v", "rhosvd_reduce_batched",
            "rhosvd_batch_uses_graph", "rhosvd_last_core_tile", "rhosvd_net_num_params", "rhosvd_net_set_params", "rhosvd_net_get_params",
            "rhosvd_net_forward", "rhosvd_net_train_step", "rhosvd_sketch_features", "rhosvd_reduce_learned",
-           "rhosvd_phase_ms", "rhosvd_last_error", "rhosvd_version"]
+           "rhosvd_phase_ms", "rhosvd_last_error", "rhosvd_version", "rhosvd_t2c", "rhosvd_t2c_get"]
 
 NET_IN, NET_OUT = 67, 2
 PATHS = {0: "range finder", 1: "gram (chosen)", 2: "gram (certificate failed)", 3: "gram (R < n)"}
@@ -39,7 +39,8 @@ PATHS = {0: "range finder", 1: "gram (chosen)", 2: "gram (certificate failed)", 
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("max_eig_sweeps", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("beta_fp32", ctypes.c_int32), ("refine_tails", ctypes.c_int32),
-                ("core_tile", ctypes.c_int32), ("certificate", ctypes.c_int32), ("anorm", ctypes.c_int32)]
+                ("core_tile", ctypes.c_int32), ("certificate", ctypes.c_int32), ("anorm", ctypes.c_int32),
+                ("als_sweeps", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -119,6 +120,8 @@ def load():
         lib.rhosvd_sketch_features.argtypes = [vp, i64, i64, vp, vp, vp, vp, dbl, vp, i32, vp]
         lib.rhosvd_reduce_learned.argtypes = [vp, i64, i64, vp, vp, vp, vp, dbl, vp, i32, ctypes.POINTER(i32),
                                               ctypes.POINTER(LearnedInfo)]
+        lib.rhosvd_t2c.argtypes = [vp, i32, i32, i32, vp, dbl, ctypes.POINTER(i64), ctypes.POINTER(dbl)]
+        lib.rhosvd_t2c_get.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp]
         lib.rhosvd_phase_ms.argtypes = [vp, i32]
         lib.rhosvd_phase_ms.restype = dbl
         lib.rhosvd_last_error.argtypes = [vp]
@@ -127,7 +130,7 @@ def load():
         for f in ("rhosvd_create", "rhosvd_destroy", "rhosvd_set_options", "rhosvd_reduce", "rhosvd_get",
                   "rhosvd_get_xi", "rhosvd_get_spectrum", "rhosvd_get_v", "rhosvd_reduce_batched",
                   "rhosvd_net_set_params", "rhosvd_net_get_params", "rhosvd_net_forward", "rhosvd_net_train_step",
-                  "rhosvd_sketch_features", "rhosvd_reduce_learned"):
+                  "rhosvd_sketch_features", "rhosvd_reduce_learned", "rhosvd_t2c", "rhosvd_t2c_get"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -172,13 +175,14 @@ class Reducer:
     """One library handle bound to a stream."""
 
     def __init__(self, precision="fp64", stream=None, max_eig_sweeps=0, profile=False, beta_fp32=False,
-                 refine_tails=False, core_tile=0, certificate=False, anorm="auto"):
+                 refine_tails=False, core_tile=0, certificate=False, anorm="auto", als_sweeps=0):
         import torch
         self.lib = load()
         self.opt = Options()
         self.opt.core_tile = int(core_tile)
         self.opt.certificate = 1 if certificate else 0
         self.opt.anorm = ANORM[anorm] if isinstance(anorm, str) else int(anorm)
+        self.opt.als_sweeps = int(als_sweeps)
         self.opt.beta_fp32 = 1 if beta_fp32 else 0
         self.opt.refine_tails = int(refine_tails) if refine_tails in (0, 1, 2) else -1
         self.beta_dtype = torch.float32 if beta_fp32 else torch.float64
@@ -411,6 +415,47 @@ class Reducer:
         self.ranks = tuple(int(r) for r in ranks)
         return self.ranks, dict(proposal=list(info.proposal), width=list(info.width),
                                 path=list(info.fallback), residual=list(info.residual))
+
+    # ---- Tucker-to-canonical transform (Remark 2.6)
+    def t2c(self, beta, eps, Z=None):
+        """Canonical form of a core: beta (r1, r2, r3) float64 CUDA tensor in
+        Fortran order (as Result.beta), eps the absolute accuracy.  Returns a dict:
+        weights (R,), F1 (r1, R), F2 (r2, R) column-major, slice (R,) int32, sigma
+        (r3, min(r1, r2)), bound, and with Z = [Z1, Z2, Z3] the lifted factors
+        C1, C2, C3 (n, R)."""
+        import torch
+        if not (beta.is_cuda and beta.dtype == torch.float64 and beta.dim() == 3):
+            raise ValueError("beta: expected a 3-D float64 CUDA tensor")
+        r1, r2, r3 = beta.shape
+        if beta.numel() and beta.stride() != (1, r1, r1 * r2):
+            raise ValueError("beta: expected Fortran order (strides (1, r1, r1 r2))")
+        R = ctypes.c_int64()
+        bound = ctypes.c_double()
+        self._check(self.lib.rhosvd_t2c(self.h, r1, r2, r3, ctypes.c_void_p(beta.data_ptr()), float(eps),
+                                        ctypes.byref(R), ctypes.byref(bound)))
+        R = int(R.value)
+        w = torch.empty(R, dtype=torch.float64, device="cuda")
+        F1, F2 = colmajor_empty(r1, R), colmajor_empty(r2, R)
+        sl = torch.empty(R, dtype=torch.int32, device="cuda")
+        sig = torch.empty((r3, min(r1, r2)), dtype=torch.float64, device="cuda")
+        ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p()
+        out = dict(R=R, bound=bound.value, weights=w, F1=F1, F2=F2, slice=sl, sigma=sig)
+        n = 0
+        Zp = [ctypes.c_void_p()] * 3
+        Cp = [ctypes.c_void_p()] * 3
+        if Z is not None:
+            n = Z[0].shape[0]
+            Cs = [colmajor_empty(n, R) for _ in range(3)]
+            Zp = [_colmajor(z, f"Z{l + 1}") for l, z in enumerate(Z)]
+            Cp = [ptr(c) for c in Cs]
+            out.update(C1=Cs[0], C2=Cs[1], C3=Cs[2])
+            if R == 0:
+                n = 0
+                Zp = [ctypes.c_void_p()] * 3
+                Cp = [ctypes.c_void_p()] * 3
+        self._check(self.lib.rhosvd_t2c_get(self.h, ptr(w), ptr(F1), ptr(F2), ptr(sl), ptr(sig), n,
+                                            Zp[0], Zp[1], Zp[2], Cp[0], Cp[1], Cp[2]))
+        return out
 
     def batch_uses_graph(self):
         return bool(self.lib.rhosvd_batch_uses_graph(self.h))

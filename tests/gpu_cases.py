@@ -60,6 +60,26 @@ def cut_margin_ok(tails, rank, tau, sigma1, eta=ETA64):
     return min(lo, hi) > 10.0 * e_t
 
 
+def tails_of(sigma):
+    """t_r = (sum_{k >= r} sigma_k^2)^(1/2), r = 0..m, summed smallest first."""
+    s2 = np.asarray(sigma, dtype=np.float64) ** 2
+    return np.sqrt(np.concatenate([np.cumsum(s2[::-1])[::-1], [0.0]]))
+
+
+def cut_margin_ok_measured(t_path, t_orc, rank, tau, factor=10.0):
+    """Rank-parity rule with the path's tail error measured instead of modelled:
+    the path's tails t_path (from its own spectrum) differ from the oracle's by
+    d = max |t_path - t_orc| at r - 1 and r; ranks must agree when the oracle's
+    cut margin exceeds factor * d.  (For Gram matrices of order ~2000 the
+    eigensolver's own backward error, tens of u |G|, exceeds the 2^-52 |G| of
+    the modelled rule.)"""
+    if tau <= 0 or rank < 1:
+        return False
+    d = max(abs(t_path[rank - 1] - t_orc[rank - 1]), abs(t_path[rank] - t_orc[rank]))
+    margin = min(t_orc[rank - 1] - tau, tau - t_orc[rank])
+    return margin > factor * d
+
+
 def separated(sigma, r, rel_gap=1e-4):
     s2 = sigma ** 2
     out = []
