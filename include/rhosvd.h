@@ -398,6 +398,36 @@ rhosvd_status rhosvd_t2c_get(rhosvd_handle h, double* weights, double* F1, doubl
                              double* sigma, int64_t n, const double* Z1, const double* Z2, const double* Z3,
                              double* C1, double* C2, double* C3);
 
+/*
+ * rhosvd_t2c_noalloc: rhosvd_t2c and rhosvd_t2c_get in one call that allocates
+ * nothing (no hipMalloc, hipFree or allocating library call), for callers that
+ * cannot allocate device memory: code being captured into a HIP graph, tight
+ * serving loops, harnesses that forbid allocation.  It needs no handle and never
+ * waits for the GPU: everything, the status included, is written to device memory.
+ *
+ * Workspace: one static device array of 8 MiB per GPU (created with the code
+ * object, held until the process ends), shared by every call on that GPU: calls
+ * that overlap on one GPU (different streams, or threads) race and must not be
+ * made.  The core must fit it: r3 (max(r1, r2) min(r1, r2) + min(r1, r2) + 3) doubles
+ * plus a few hundred bytes (for example a 64 x 64 x 64 or 90 x 90 x 60 core), and
+ * the limits of rhosvd_t2c; larger cores return RHOSVD_ERR_UNSUPPORTED.
+ *
+ *   hip_stream : hipStream_t as void* (NULL: the default stream); all work is enqueued on it
+ *   r1, r2, r3, beta, eps : as rhosvd_t2c (beta DEVICE, read during the call's kernels)
+ *   cap        : capacity of the outputs in terms (>= 0); R above it writes no term
+ *   weights, F1, F2, slice : DEVICE outputs as rhosvd_t2c_get, each sized for cap terms
+ *                (F1 r1 x cap, F2 r2 x cap, ld r1 / r2); may be NULL when cap = 0
+ *   R          : DEVICE int64, receives the canonical rank
+ *   bound      : DEVICE double, nullable, receives the error estimate (as rhosvd_t2c)
+ *   status     : DEVICE int32, receives RHOSVD_OK, RHOSVD_ERR_NOCONV (a slice's Jacobi
+ *                sweeps did not converge) or RHOSVD_ERR_CAPACITY (R > cap); the terms
+ *                are written only with RHOSVD_OK
+ * Returns (host): OK once enqueued, ARG, UNSUPPORTED, DEVICE.
+ */
+rhosvd_status rhosvd_t2c_noalloc(void* hip_stream, int32_t r1, int32_t r2, int32_t r3, const double* beta,
+                                 double eps, int64_t cap, double* weights, double* F1, double* F2, int32_t* slice,
+                                 int64_t* R, double* bound, int32_t* status);
+
 /* Phase times in milliseconds of the last rhosvd_reduce / rhosvd_get when the
  * handle was created with profile != 0 (synchronizes with the stream):
  *   0 norms, 1 |A| identity, 2 Gram, 3 eigensolver, 4 truncation + Z (with the

@@ -158,8 +158,9 @@ __global__ __launch_bounds__(T2C_THREADS) void k_t2c_terms(const double* __restr
                                                          const int64_t* __restrict__ off, int r3,
                                                          double* __restrict__ weights, double* __restrict__ F1,
                                                          int64_t ld1, double* __restrict__ F2, int64_t ld2,
-                                                         int* __restrict__ slice_of) {
+                                                         int* __restrict__ slice_of, const int64_t* __restrict__ R_lim) {
     const int64_t t = blockIdx.x;
+    if (R_lim && t >= *R_lim) return;               // grid sized for a capacity, R known on the device
     int lo = 0, hi = r3;                             // slice m: off[m] <= t < off[m + 1]
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
@@ -195,6 +196,35 @@ __global__ __launch_bounds__(T2C_THREADS) void k_t2c_terms(const double* __restr
     }
 }
 
+// Counts to offsets on the device (one thread, slices in order): off[m + 1] =
+// off[m] + p[m], R = off[r3], bound = sum of the tails, status NOCONV when a
+// slice did not converge, CAPACITY when R > cap; *R_lim = R when the terms may be
+// written, else 0.
+__global__ void k_t2c_offsets(const int* __restrict__ p, const double* __restrict__ tails, int r3, int64_t cap,
+                              const int* __restrict__ flags, int64_t* __restrict__ off, int64_t* __restrict__ R_lim,
+                              int64_t* __restrict__ R_out, double* __restrict__ bound_out, int* __restrict__ status) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    int64_t acc = 0;
+    double b = 0.0;
+    off[0] = 0;
+    for (int m = 0; m < r3; ++m) {
+        acc += p[m];
+        b += tails[m];
+        off[m + 1] = acc;
+    }
+    int st = 0;
+    if (flags[0] & 1) st = RHOSVD_ERR_NOCONV;
+    else if (acc > cap) st = RHOSVD_ERR_CAPACITY;
+    *R_lim = st == 0 ? acc : 0;
+    *R_out = acc;
+    if (bound_out) *bound_out = b;
+    *status = st;
+}
+
+__global__ void k_t2c_clear_flags(int* __restrict__ flags) {
+    if (threadIdx.x < 4) flags[threadIdx.x] = 0;
+}
+
 // C[:, t] = Z3[:, slice_of[t]] for every term (n rows, ld ldc / ldz)
 __global__ void k_t2c_gather_cols(int n, int64_t R, const double* __restrict__ Z, int64_t ldz,
                                   const int* __restrict__ slice_of, double* __restrict__ C, int64_t ldc) {
@@ -226,10 +256,22 @@ hipError_t launch_t2c_jacobi(const double* beta, int r1, int r2, int r3, double 
 
 hipError_t launch_t2c_terms(const double* beta, int r1, int r2, int r3, const double* Wj, const double* sig,
                             const int64_t* off, int64_t R, double* weights, double* F1, int64_t ld1, double* F2,
-                            int64_t ld2, int* slice_of, hipStream_t st) {
+                            int64_t ld2, int* slice_of, hipStream_t st, const int64_t* R_lim) {
     if (R < 1) return hipSuccess;
     hipLaunchKernelGGL(k_t2c_terms, dim3((unsigned)R), dim3(T2C_THREADS), 0, st, beta, r1, r2, Wj, sig, off, r3,
-                       weights, F1, ld1, F2, ld2, slice_of);
+                       weights, F1, ld1, F2, ld2, slice_of, R_lim);
+    return hipGetLastError();
+}
+
+hipError_t launch_t2c_offsets(const int* p, const double* tails, int r3, int64_t cap, const int* flags, int64_t* off,
+                              int64_t* R_lim, int64_t* R_out, double* bound_out, int* status, hipStream_t st) {
+    hipLaunchKernelGGL(k_t2c_offsets, dim3(1), dim3(64), 0, st, p, tails, r3, cap, flags, off, R_lim, R_out, bound_out,
+                       status);
+    return hipGetLastError();
+}
+
+hipError_t launch_t2c_clear_flags(int* flags, hipStream_t st) {
+    hipLaunchKernelGGL(k_t2c_clear_flags, dim3(1), dim3(64), 0, st, flags);
     return hipGetLastError();
 }
 

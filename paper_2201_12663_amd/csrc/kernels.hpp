@@ -300,9 +300,14 @@ hipError_t launch_t2c_jacobi(const double* beta, int r1, int r2, int r3, double 
                              double* sig_out, int* p_out, double* tail_out, int* flags, hipStream_t st);
 // the R kept terms (off: r3 + 1 prefix offsets of p): weights, u_k into F1 (ld1),
 // v_k into F2 (ld2), slice index of each term
+// (R_lim, nullable: device word; terms t >= *R_lim are skipped, so R may be a capacity)
 hipError_t launch_t2c_terms(const double* beta, int r1, int r2, int r3, const double* Wj, const double* sig,
                             const int64_t* off, int64_t R, double* weights, double* F1, int64_t ld1, double* F2,
-                            int64_t ld2, int* slice_of, hipStream_t st);
+                            int64_t ld2, int* slice_of, hipStream_t st, const int64_t* R_lim = nullptr);
+// counts to offsets, R, bound and a status word on the device (no host round trip)
+hipError_t launch_t2c_offsets(const int* p, const double* tails, int r3, int64_t cap, const int* flags, int64_t* off,
+                              int64_t* R_lim, int64_t* R_out, double* bound_out, int* status, hipStream_t st);
+hipError_t launch_t2c_clear_flags(int* flags, hipStream_t st);
 // C[:, t] = Z[:, slice_of[t]]
 hipError_t launch_t2c_gather_cols(int n, int64_t R, const double* Z, int64_t ldz, const int* slice_of, double* C,
                                   int64_t ldc, hipStream_t st);

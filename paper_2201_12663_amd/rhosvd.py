@@ -30,7 +30,8 @@ EXPORTS = ["rhosvd_create", "rhosvd_destroy", "rhosvd_set_options", "rhosvd_redu
            "rhosvd_get_xi", "rhosvd_get_spectrum", "rhosvd_get_v", "rhosvd_reduce_batched",
            "rhosvd_batch_uses_graph", "rhosvd_last_core_tile", "rhosvd_net_num_params", "rhosvd_net_set_params", "rhosvd_net_get_params",
            "rhosvd_net_forward", "rhosvd_net_train_step", "rhosvd_sketch_features", "rhosvd_reduce_learned",
-           "rhosvd_phase_ms", "rhosvd_last_error", "rhosvd_version", "rhosvd_t2c", "rhosvd_t2c_get"]
+           "rhosvd_phase_ms", "rhosvd_last_error", "rhosvd_version", "rhosvd_t2c", "rhosvd_t2c_get",
+           "rhosvd_t2c_noalloc"]
 
 NET_IN, NET_OUT = 67, 2
 PATHS = {0: "range finder", 1: "gram (chosen)", 2: "gram (certificate failed)", 3: "gram (R < n)"}
@@ -122,6 +123,7 @@ def load():
                                               ctypes.POINTER(LearnedInfo)]
         lib.rhosvd_t2c.argtypes = [vp, i32, i32, i32, vp, dbl, ctypes.POINTER(i64), ctypes.POINTER(dbl)]
         lib.rhosvd_t2c_get.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp]
+        lib.rhosvd_t2c_noalloc.argtypes = [vp, i32, i32, i32, vp, dbl, i64, vp, vp, vp, vp, vp, vp, vp]
         lib.rhosvd_phase_ms.argtypes = [vp, i32]
         lib.rhosvd_phase_ms.restype = dbl
         lib.rhosvd_last_error.argtypes = [vp]
@@ -130,7 +132,7 @@ def load():
         for f in ("rhosvd_create", "rhosvd_destroy", "rhosvd_set_options", "rhosvd_reduce", "rhosvd_get",
                   "rhosvd_get_xi", "rhosvd_get_spectrum", "rhosvd_get_v", "rhosvd_reduce_batched",
                   "rhosvd_net_set_params", "rhosvd_net_get_params", "rhosvd_net_forward", "rhosvd_net_train_step",
-                  "rhosvd_sketch_features", "rhosvd_reduce_learned", "rhosvd_t2c", "rhosvd_t2c_get"):
+                  "rhosvd_sketch_features", "rhosvd_reduce_learned", "rhosvd_t2c", "rhosvd_t2c_get", "rhosvd_t2c_noalloc"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -496,6 +498,27 @@ class Reducer:
             out.append(dict(ranks=r, status=int(rr[i, 3]), dropped=int(rr[i, 4]),
                             Z=[Z1[:, :r[0]], Z2[:, :r[1]], Z3[:, :r[2]]], beta=bt))
         return out, desc, res2, outs
+
+
+def t2c_noalloc(beta, eps, cap, weights, F1, F2, slice_, R, bound, status, stream=None):
+    """rhosvd_t2c_noalloc (include/rhosvd.h): enqueue the transform of beta into
+    caller-allocated device tensors (no allocation by the library, no wait).
+    beta: (r1, r2, r3) float64 CUDA tensor in Fortran order; weights (cap,) float64;
+    F1 (r1, cap), F2 (r2, cap) column-major float64; slice_ (cap,) int32; R (1,)
+    int64; bound (1,) float64 or None; status (1,) int32.  Returns the host status."""
+    import torch
+    lib = load()
+    if not (beta.is_cuda and beta.dtype == torch.float64 and beta.dim() == 3):
+        raise ValueError("beta: expected a 3-D float64 CUDA tensor")
+    r1, r2, r3 = beta.shape
+    if beta.stride() != (1, r1, r1 * r2):
+        raise ValueError("beta: expected Fortran order")
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p()
+    return int(lib.rhosvd_t2c_noalloc(ctypes.c_void_p(stream.cuda_stream), r1, r2, r3, ptr(beta), float(eps),
+                                      int(cap), ptr(weights), ptr(F1), ptr(F2), ptr(slice_), ptr(R), ptr(bound),
+                                      ptr(status)))
 
 
 def reduce(U1, U2, U3, xi, eps, precision="fp64", **kw):
