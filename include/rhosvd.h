@@ -26,7 +26,8 @@
  *     synchronizes with that stream once (to return the ranks on the host);
  *     rhosvd_get does not synchronize.
  *   - A handle owns its device workspace (grown on demand, reused across
- *     calls, released by rhosvd_destroy).  A handle is not thread-safe and must
+ *     calls, released by rhosvd_destroy), drawn from the caller's allocator
+ *     (rhosvd_create_with_allocator) or hipMalloc.  A handle is not thread-safe and must
  *     not be used by two calls at once.
  *   - Functions never throw; they return a status.  rhosvd_last_error gives a
  *     human-readable message for the last failing call on a handle.
@@ -71,7 +72,18 @@ typedef struct {
                                 double, halving its size; meant for the FP32 and BF16x3 cores.
                                 When R (padded to 64) exceeds 8192 these cores add their
                                 partial sums over each 8192 terms into beta, in float here */
-    int32_t refine_tails;    /* 0, 1 or 2 (rhosvd_reduce; other values: RHOSVD_ERR_ARG).
+    int32_t refine_tails;    /* 0 (auto), 1, 2 or 3 (off) (rhosvd_reduce; other values:
+                                RHOSVD_ERR_ARG).
+                                0 (default): when the Gram-route cut of some mode lies
+                                in the FP64 noise band of its Gram matrix, lambda_r <=
+                                64 u lambda_1 (u = 2^-53: there the discarded and even
+                                the last kept eigenvalues carry noise of about u |G|),
+                                2 if tau^2 itself lies in that band (n <= R), else 1;
+                                none otherwise.  The report's refine_used says which.
+                                With 1, where even the wider p does not certify on the
+                                refined tails, p grows (2p + 64, at most m) and the
+                                refined cut is taken again.
+                                3: the plain Gram-route cut.
                                 1: after the Gram-route cut r, with
                                 Z_p the leading p = min(m, r + r/8 + 16) eigenvectors and
                                 V_p = Z_p^T U~, the cut is taken again on the tails
@@ -161,15 +173,37 @@ typedef struct {
     double a_norm_upper; /* an upper bound of |A|_F: equal to a_norm when that is exact,
                             (a_norm^2 + b_p^2)^(1/2) with the probe (see rhosvd_options.anorm) */
     int32_t anorm_method;  /* 1 exact identity, 2 probe lower bound */
-    int32_t reserved;
+    int32_t refine_used;   /* the refinement rhosvd_reduce ran: 0 none, 1 refined tails, 2 deflated pass */
 } rhosvd_report;
 
 typedef struct rhosvd_ctx* rhosvd_handle;
+
+/* A caller's device-memory allocator (for example a framework's caching
+ * allocator).  alloc returns device memory of at least `bytes` bytes, aligned to
+ * 256 bytes and usable on the handle's stream, or NULL; free releases a pointer
+ * alloc returned.  Both are called from the thread that calls the library, only
+ * inside library calls (create, reduce, get, the batched, learned, network and
+ * transform calls, set_options, destroy), and a pointer is freed only after the
+ * handle's stream has finished the work that used it. */
+typedef struct {
+    void* (*alloc)(size_t bytes, void* ctx);
+    void (*free)(void* ptr, void* ctx);
+    void* ctx;
+} rhosvd_allocator;
 
 /* Create a handle bound to a HIP stream (hipStream_t passed as void*; NULL is
  * the default stream).  opt may be NULL (FP64, default sweep cap).
  * Errors: RHOSVD_ERR_ARG (out == NULL, bad option), RHOSVD_ERR_DEVICE. */
 rhosvd_status rhosvd_create(rhosvd_handle* out, void* hip_stream, const rhosvd_options* opt);
+
+/* rhosvd_create with the handle's device memory drawn from `allocator` (copied;
+ * NULL: hipMalloc / hipFree): the reduction workspace, the eigensolver plans'
+ * work memory, batch plans, the learned path's and the network's memory, the |A|
+ * probe's and the Tucker-to-canonical transform's workspace.  (The handle's 4 KiB
+ * of pinned host staging is separate.)  Errors: as rhosvd_create, ARG when the
+ * allocator lacks alloc or free. */
+rhosvd_status rhosvd_create_with_allocator(rhosvd_handle* out, void* hip_stream, const rhosvd_allocator* allocator,
+                                           const rhosvd_options* opt);
 
 /* Release the handle and its workspace (waits for the handle's stream). */
 rhosvd_status rhosvd_destroy(rhosvd_handle h);
@@ -239,12 +273,19 @@ rhosvd_status rhosvd_get_v(rhosvd_handle h, int32_t l, double* V);
  *   n, R       : 1 <= n, R; min(n, R) <= 2048
  *   U1..U3, xi : inputs as for rhosvd_reduce
  *   eps        : > 0
- *   cap_rank   : >= 1, the columns available in each Z output; ranks above it
+ *   cap_rank   : >= 1, the columns available in each Z output (rows of each V); ranks above it
  *                give RHOSVD_ERR_CAPACITY for that problem (Z, beta not written)
  *   cap_beta   : entries available in beta (>= 1 when beta is set)
  *   Z1..Z3     : n x cap_rank outputs (ld n, first r_l columns written), or all NULL
  *   beta       : r1*r2*r3 output (Fortran order; doubles, or floats with the handle's
  *                beta_fp32 option), or NULL (ranks and Z only)
+ *   V1..V3     : r_l x R outputs V^(l) = Z^(l)T U~^(l) (ld cap_rank, FP64, converted from FP32
+ *                on the mixed paths): with xi' (the normalized weights) they are the
+ *                factors of the mixed Tucker-canonical format of Proposition 2.2, whose core
+ *                is the rank-R canonical tensor sum_nu xi'_nu V1[:,nu] (x) V2[:,nu] (x) V3[:,nu]
+ *                (R (r1 + r2 + r3) numbers instead of r1 r2 r3), or all NULL.  Set with
+ *                beta NULL to skip the Khatri-Rao core altogether.  xi' is not an output of
+ *                the batch; it is xi times the three column norms of each term.
  *   result     : int32[8]: r1, r2, r3, status (rhosvd_status of this problem:
  *                OK, ERR_NONFINITE, ERR_CAPACITY, or ERR_DEVICE when an
  *                eigensolver wait ran out), dropped terms, 3 reserved
@@ -268,6 +309,9 @@ typedef struct {
     double* Z3;
     void* beta;
     int32_t* result;
+    double* V1;
+    double* V2;
+    double* V3;
 } rhosvd_problem;
 
 rhosvd_status rhosvd_reduce_batched(rhosvd_handle h, int32_t count, const rhosvd_problem* problems);

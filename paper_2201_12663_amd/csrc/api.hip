@@ -8,10 +8,11 @@
 #include <string>
 #include <vector>
 
+#include "capacity.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
 
-#define RHOSVD_VERSION "0.1.0"
+#define RHOSVD_VERSION "0.2.0"
 
 namespace {
 
@@ -20,6 +21,12 @@ constexpr int NEV = 9;            // 0..6 bracket the reduce phases, 7..8 the co
 constexpr int DEFAULT_SWEEPS = 30;   // kept for the options ABI; the eigensolver has no sweep cap
 constexpr int RPAD_CORE = 128;                                 // V row padding (core tiles)
 constexpr size_t HOST_BYTES = 4096;                            // pinned host staging of a handle
+constexpr int REFINE_AUTO = 0, REFINE_OFF = 3;                 // rhosvd_options.refine_tails
+// auto refinement: a mode whose last kept eigenvalue of the Gram matrix lies
+// within NOISE_BAND u sigma_1^2 of zero has its cut inside the FP64 Gram route's
+// noise band (eigenvalues of G are exact only to about u |G|)
+constexpr double NOISE_BAND = 64.0;
+constexpr double U64H = 1.1102230246251565e-16;                // 2^-53
 
 std::string g_create_error;
 
@@ -29,6 +36,7 @@ size_t a256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 struct rhosvd_ctx {
     hipStream_t stream = nullptr;
+    DevAlloc alloc;                      // device memory: the caller's allocator, or hipMalloc
     rhosvd_options opt{};
     std::string err;
     CoreTuner* tuner = nullptr;          // core tile per shape class (tune.hip)
@@ -70,6 +78,7 @@ struct rhosvd_ctx {
     const double* a2_part = nullptr;
     int64_t a2_n = 0;
     int anorm_method = 1;
+    int refine_used = 0;                 // refinement the last reduction used (0 none, 1, 2)
     double a_upper = 0;
     char* pw = nullptr;
     size_t pw_bytes = 0;
@@ -177,7 +186,7 @@ rhosvd_status check_options(const rhosvd_options* o, std::string& msg) {
     if (o->precision < 0 || o->precision > 2) { msg = "unknown precision"; return RHOSVD_ERR_ARG; }
     if (o->anorm < 0 || o->anorm > 2) { msg = "anorm must be 0 (auto), 1 (exact) or 2 (probe)"; return RHOSVD_ERR_ARG; }
     if (o->als_sweeps < 0 || o->als_sweeps > 4) { msg = "als_sweeps must be 0..4"; return RHOSVD_ERR_ARG; }
-    if (o->refine_tails < 0 || o->refine_tails > 2) { msg = "refine_tails must be 0, 1 or 2"; return RHOSVD_ERR_ARG; }
+    if (o->refine_tails < 0 || o->refine_tails > 3) { msg = "refine_tails must be 0 (auto), 1, 2 or 3 (off)"; return RHOSVD_ERR_ARG; }
     if (o->core_tile != 0 && !core_tile_valid(o->precision, o->core_tile)) {
         msg = "core_tile must be 0 (tuned), 64, or 128 (128 only for the FP32 and BF16x3 cores)";
         return RHOSVD_ERR_ARG;
@@ -229,8 +238,8 @@ size_t carve_all(rhosvd_ctx* h, char* base) {
         h->V[l] = (void*)c.take<char>((size_t)zp * Rp * esz);
     }
     for (int l = 0; l < 3; ++l) {
-        const bool refine = h->opt.refine_tails != 0;
-        const bool deflate = h->opt.refine_tails == 2 && !h->rside;
+        const bool refine = h->opt.refine_tails != REFINE_OFF;   // auto may refine
+        const bool deflate = (h->opt.refine_tails == 2 || h->opt.refine_tails == REFINE_AUTO) && !h->rside;
         h->Vref[l] = (refine && esz == 4) ? c.take<double>((size_t)zp * Rp) : nullptr;
         h->rpart[l] = refine ? c.take<double>((size_t)(np / 64) * (Rp / 64)) : nullptr;
         h->Ud[l] = deflate ? c.take<double>((size_t)np * Rp) : nullptr;
@@ -247,14 +256,15 @@ size_t carve_all(rhosvd_ctx* h, char* base) {
     h->Vc = (cert && esz == 4) ? c.take<double>((size_t)zp * Rp) : nullptr;
     h->cpart = cert ? c.take<double>((size_t)(np / 64) * Rp) : nullptr;
     h->cout = cert ? c.take<double>((size_t)3 * cert_blocks(Rp) + 8) : nullptr;
-    h->dscr = (h->opt.refine_tails == 2 && !h->rside) ? c.take<double>((size_t)9 * (h->m_pad + 64)) : nullptr;
+    h->dscr = ((h->opt.refine_tails == 2 || h->opt.refine_tails == REFINE_AUTO) && !h->rside)
+                  ? c.take<double>((size_t)9 * (h->m_pad + 64)) : nullptr;
     h->rfloor = c.take<double>(4);
     h->xip = c.take<double>(Rp);
     h->flags = c.take<int>(16);
     h->gram_part = (h->gram_splits > 1) ? c.take<double>((size_t)h->gram_splits * 3 * np * np) : nullptr;
     h->anorm_part = c.take<double>(h->anorm_ntiles);
     h->ranks_dev = c.take<int>(16);
-    h->scal = c.take<double>(8);
+    h->scal = c.take<double>(16);
     if (h->rside) {
         for (int l = 0; l < 3; ++l) {
             h->Wr[l] = c.take<double>((size_t)Rp * zp);
@@ -296,10 +306,8 @@ rhosvd_status layout(rhosvd_ctx* h, int64_t n, int64_t R) {
     h->anorm_ntiles = rt * (rt + 1) / 2;
     const size_t need = carve_all(h, nullptr);
     if (need > h->ws_bytes) {
-        if (h->ws) { hipStreamSynchronize(h->stream); hipFree(h->ws); h->ws = nullptr; h->ws_bytes = 0; }
-        hipError_t e = hipMalloc((void**)&h->ws, need);
-        if (e != hipSuccess) {
-            h->ws = nullptr;
+        if (h->ws) { hipStreamSynchronize(h->stream); h->alloc.put(h->ws); h->ws = nullptr; h->ws_bytes = 0; }
+        if (!(h->ws = (char*)h->alloc.get(need))) {
             return fail(h, RHOSVD_ERR_ALLOC, "workspace allocation of " + std::to_string(need) + " bytes failed");
         }
         h->ws_bytes = need;
@@ -324,10 +332,9 @@ rhosvd_status ensure_plan(rhosvd_ctx* h, int which, const EigMat* mats, int nmat
     EigPlan* P = eig_plan_create(mats, nmat, &need);
     if (!P) return fail(h, RHOSVD_ERR_UNSUPPORTED, "eigensolver plan: matrix sizes not supported on this device");
     if (need > h->plan_wbytes[which]) {
-        if (h->plan_w[which]) { hipStreamSynchronize(h->stream); hipFree(h->plan_w[which]); h->plan_w[which] = nullptr; }
+        if (h->plan_w[which]) { hipStreamSynchronize(h->stream); h->alloc.put(h->plan_w[which]); h->plan_w[which] = nullptr; }
         h->plan_wbytes[which] = 0;
-        if (hipMalloc(&h->plan_w[which], need) != hipSuccess) {
-            h->plan_w[which] = nullptr;
+        if (!(h->plan_w[which] = h->alloc.get(need))) {
             eig_plan_destroy(P);
             return fail(h, RHOSVD_ERR_ALLOC, "eigensolver work allocation failed");
         }
@@ -378,9 +385,8 @@ size_t carve_learned(rhosvd_ctx* h, char* base, int p_cap) {
 rhosvd_status learned_layout(rhosvd_ctx* h, int p_cap) {
     const size_t need = carve_learned(h, nullptr, p_cap);
     if (need > h->L.bytes) {
-        if (h->L.ws) { hipStreamSynchronize(h->stream); hipFree(h->L.ws); h->L.ws = nullptr; h->L.bytes = 0; }
-        if (hipMalloc((void**)&h->L.ws, need) != hipSuccess) {
-            h->L.ws = nullptr;
+        if (h->L.ws) { hipStreamSynchronize(h->stream); h->alloc.put(h->L.ws); h->L.ws = nullptr; h->L.bytes = 0; }
+        if (!(h->L.ws = (char*)h->alloc.get(need))) {
             return fail(h, RHOSVD_ERR_ALLOC, "learned-path workspace allocation of " + std::to_string(need) + " bytes failed");
         }
         h->L.bytes = need;
@@ -535,9 +541,8 @@ rhosvd_status anorm_probe(rhosvd_ctx* h, int mode, bool* z_all) {
     const size_t bbytes = a256((size_t)p[0] * p[1] * p[2] * 8);
     const size_t need = vbytes + bbytes + a256(PROBE_NPART * 8);
     if (need > h->pw_bytes) {
-        if (h->pw) { CK(h, hipStreamSynchronize(st)); hipFree(h->pw); h->pw = nullptr; h->pw_bytes = 0; }
-        if (hipMalloc((void**)&h->pw, need) != hipSuccess) {
-            h->pw = nullptr;
+        if (h->pw) { CK(h, hipStreamSynchronize(st)); h->alloc.put(h->pw); h->pw = nullptr; h->pw_bytes = 0; }
+        if (!(h->pw = (char*)h->alloc.get(need))) {
             return fail(h, RHOSVD_ERR_ALLOC, "|A| probe workspace allocation of " + std::to_string(need) + " bytes failed");
         }
         h->pw_bytes = need;
@@ -740,7 +745,16 @@ const char* rhosvd_last_error(rhosvd_handle h) {
 }
 
 rhosvd_status rhosvd_create(rhosvd_handle* out, void* hip_stream, const rhosvd_options* opt) {
+    return rhosvd_create_with_allocator(out, hip_stream, nullptr, opt);
+}
+
+rhosvd_status rhosvd_create_with_allocator(rhosvd_handle* out, void* hip_stream, const rhosvd_allocator* allocator,
+                                           const rhosvd_options* opt) {
     if (!out) { g_create_error = "out is NULL"; return RHOSVD_ERR_ARG; }
+    if (allocator && (!allocator->alloc || !allocator->free)) {
+        g_create_error = "allocator needs both alloc and free";
+        return RHOSVD_ERR_ARG;
+    }
     *out = nullptr;
     std::string msg;
     rhosvd_status s = check_options(opt, msg);
@@ -752,6 +766,7 @@ rhosvd_status rhosvd_create(rhosvd_handle* out, void* hip_stream, const rhosvd_o
     }
     rhosvd_ctx* h = new rhosvd_ctx();
     h->stream = (hipStream_t)hip_stream;
+    if (allocator) h->alloc.a = *allocator;
     apply_options(h, opt);
     h->tuner = core_tuner_create();
     if (hipHostMalloc((void**)&h->host, HOST_BYTES, hipHostMallocDefault) != hipSuccess) {
@@ -773,17 +788,17 @@ rhosvd_status rhosvd_create(rhosvd_handle* out, void* hip_stream, const rhosvd_o
 rhosvd_status rhosvd_destroy(rhosvd_handle h) {
     if (!h) return RHOSVD_ERR_ARG;
     hipStreamSynchronize(h->stream);
-    if (h->ws) hipFree(h->ws);
-    if (h->pw) hipFree(h->pw);
+    h->alloc.put(h->ws);
+    h->alloc.put(h->pw);
     if (h->batch) batch_plan_destroy(h->batch);
-    if (h->net) hipFree(h->net);
-    if (h->L.ws) hipFree(h->L.ws);
-    if (h->T.ws) hipFree(h->T.ws);
-    if (h->T.lw) hipFree(h->T.lw);
-    if (h->net_work) hipFree(h->net_work);
+    h->alloc.put(h->net);
+    h->alloc.put(h->L.ws);
+    h->alloc.put(h->T.ws);
+    h->alloc.put(h->T.lw);
+    h->alloc.put(h->net_work);
     for (int i = 0; i < rhosvd_ctx::NPLAN; ++i) {
         if (h->plan[i]) eig_plan_destroy(h->plan[i]);
-        if (h->plan_w[i]) hipFree(h->plan_w[i]);
+        h->alloc.put(h->plan_w[i]);
     }
     if (h->host) hipHostFree(h->host);
     for (int i = 0; i < NEV; ++i)
@@ -856,13 +871,29 @@ rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R, const double*
     // the one host synchronization: ranks, flags, sweeps and norms
     CK(h, hipMemcpyAsync(h->host, h->ranks_dev, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
     CK(h, hipMemcpyAsync(h->host + 4, h->flags, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
-    CK(h, hipMemcpyAsync(h->hostd, h->scal, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    CK(h, hipMemcpyAsync(h->hostd, h->scal, 12 * sizeof(double), hipMemcpyDeviceToHost, st));
     CK(h, hipStreamSynchronize(st));
     if (h->host[4]) return fail(h, RHOSVD_ERR_NONFINITE, "input contains NaN or Inf");
     if (h->host[6]) return fail(h, RHOSVD_ERR_DEVICE, "eigensolver: a cross-workgroup wait ran out");
     for (int l = 0; l < 3; ++l)
         if (h->host[l] < 0 || h->host[l] > h->m)
             return fail(h, RHOSVD_ERR_DEVICE, "truncation returned rank " + std::to_string(h->host[l]) + " (internal error)");
+    // refine_tails = 0 (auto): refined tails (mode 1) when some mode's cut lies in the
+    // Gram route's noise band, lambda_r <= NOISE_BAND u lambda_1; else none
+    // (the deflated pass, mode 2, when tau^2 itself lies in that band: the first pass's
+    // vectors near such a cut are inaccurate, and only the deflated Gram resolves it)
+    int refine_mode = h->opt.refine_tails;
+    if (refine_mode == REFINE_AUTO) {
+        const double tau2 = h->hostd[2] * h->hostd[2];
+        int want = 0;
+        for (int l = 0; l < 3; ++l) {
+            const double band = NOISE_BAND * U64H * h->hostd[6 + l];
+            if (h->host[l] >= 1 && h->hostd[9 + l] <= band)
+                want = std::max(want, tau2 <= band && !h->rside ? 2 : 1);
+        }
+        refine_mode = want ? want : REFINE_OFF;
+    }
+    h->refine_used = refine_mode == REFINE_OFF ? 0 : refine_mode;
     h->sweeps = 0;
     h->dropped = h->host[5];
     h->xi_norm = h->hostd[0];
@@ -874,59 +905,64 @@ rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R, const double*
     }
     // refine_tails = 2: the deflated second pass forms Z itself
     bool z_done = false;
-    if (h->opt.refine_tails == 2 && !h->rside && h->ranks[0] > 0) {
+    if (refine_mode == 2 && !h->rside && h->ranks[0] > 0) {
         rhosvd_status ds = deflate_pass(h, eps);
         if (ds != RHOSVD_OK) return ds;
         z_done = true;
     }
-    // refine_tails = 1: Z and V first at the wider p_l = min(m, r + r/8 + 16)
-    const bool refine = (h->opt.refine_tails == 1 || (h->opt.refine_tails == 2 && h->rside)) && h->ranks[0] > 0;
+    // refine_tails = 1: Z and V first at the wider p_l = min(m, r + r/8 + 16); where
+    // even p_l does not certify on the refined tails, p_l grows (2 p_l + 64, at most m)
+    // and the pass repeats, so the refined cut always ends certified
+    const bool refine = (refine_mode == 1 || (refine_mode == 2 && h->rside)) && h->ranks[0] > 0;
     int p_ref[3] = {0, 0, 0};
     if (refine)
-        for (int l = 0; l < 3; ++l) {
-            p_ref[l] = (int)std::min<int64_t>(h->m, h->ranks[l] + h->ranks[l] / 8 + 16);
-            h->ranks[l] = p_ref[l];
-            h->r_pad[l] = (int)round_up(p_ref[l], RPAD_CORE);
+        for (int l = 0; l < 3; ++l) p_ref[l] = (int)std::min<int64_t>(h->m, h->ranks[l] + h->ranks[l] / 8 + 16);
+    for (int pass = 0;; ++pass) {
+        if (refine)
+            for (int l = 0; l < 3; ++l) {
+                h->ranks[l] = p_ref[l];
+                h->r_pad[l] = (int)round_up(p_ref[l], RPAD_CORE);
+            }
+        // a5/a6: Z and the projections V = Z^T U~ (FP64 MFMA; rounded to FP32 for the mixed core)
+        if (z_done) {
+        } else if (z_all && pass == 0) {
+            for (int l = 0; l < 3; ++l) {
+                const int r = h->ranks[l];
+                if (r >= 1 && h->r_pad[l] > r)
+                    CK(h, hipMemsetAsync(h->Z[l] + (int64_t)r * h->n_pad, 0,
+                                         (size_t)(h->r_pad[l] - r) * h->n_pad * 8, st));
+            }
+        } else if (!h->rside) {
+            // Z = H W[:, order[0..r-1]]: back-transformed eigenvectors, sign rule, zero padding
+            BtJob jobs[3];
+            for (int l = 0; l < 3; ++l)
+                jobs[l] = BtJob{(int)h->m, (int)h->m_pad, h->G[l], h->htau[l], h->W[l], h->order[l], h->ranks[l],
+                                nullptr, h->Z[l], (int)h->n_pad, (int)h->n_pad, h->Tw[l]};
+            CK(h, launch_backtransform(jobs, 3, st));
+            for (int l = 0; l < 3; ++l) {
+                const int r = h->ranks[l];
+                if (r < 1) continue;
+                CK(h, launch_sign_cols((int)n, (int)h->n_pad, r, h->Z[l], st));
+                if (h->r_pad[l] > r)
+                    CK(h, hipMemsetAsync(h->Z[l] + (int64_t)r * h->n_pad, 0,
+                                         (size_t)(h->r_pad[l] - r) * h->n_pad * 8, st));
+            }
+        } else if (h->ranks[0] > 0) {
+            rhosvd_status zs = form_z_rside(h);
+            if (zs != RHOSVD_OK) return zs;
         }
-    // a5/a6: Z and the projections V = Z^T U~ (FP64 MFMA; rounded to FP32 for the mixed core)
-    if (z_done) {
-    } else if (z_all) {
+        if (pass == 0) mark(h, 5);
         for (int l = 0; l < 3; ++l) {
-            const int r = h->ranks[l];
-            if (r >= 1 && h->r_pad[l] > r)
-                CK(h, hipMemsetAsync(h->Z[l] + (int64_t)r * h->n_pad, 0,
-                                     (size_t)(h->r_pad[l] - r) * h->n_pad * 8, st));
+            if (h->ranks[l] < 1) continue;
+            if (h->vprec == RHOSVD_FP64)
+                CK(h, launch_project(h->n_pad, h->R_pad, h->r_pad[l], h->Z[l], h->Ut[l], (double*)h->V[l], nullptr,
+                                     st));
+            else if (refine)
+                CK(h, launch_project(h->n_pad, h->R_pad, h->r_pad[l], h->Z[l], h->Ut[l], h->Vref[l], nullptr, st));
+            else
+                CK(h, launch_project(h->n_pad, h->R_pad, h->r_pad[l], h->Z[l], h->Ut[l], nullptr, (float*)h->V[l], st));
         }
-    } else if (!h->rside) {
-        // Z = H W[:, order[0..r-1]]: back-transformed eigenvectors, sign rule, zero padding
-        BtJob jobs[3];
-        for (int l = 0; l < 3; ++l)
-            jobs[l] = BtJob{(int)h->m, (int)h->m_pad, h->G[l], h->htau[l], h->W[l], h->order[l], h->ranks[l], nullptr,
-                            h->Z[l], (int)h->n_pad, (int)h->n_pad, h->Tw[l]};
-        CK(h, launch_backtransform(jobs, 3, st));
-        for (int l = 0; l < 3; ++l) {
-            const int r = h->ranks[l];
-            if (r < 1) continue;
-            CK(h, launch_sign_cols((int)n, (int)h->n_pad, r, h->Z[l], st));
-            if (h->r_pad[l] > r)
-                CK(h, hipMemsetAsync(h->Z[l] + (int64_t)r * h->n_pad, 0,
-                                     (size_t)(h->r_pad[l] - r) * h->n_pad * 8, st));
-        }
-    } else if (h->ranks[0] > 0) {
-        rhosvd_status zs = form_z_rside(h);
-        if (zs != RHOSVD_OK) return zs;
-    }
-    mark(h, 5);
-    for (int l = 0; l < 3; ++l) {
-        if (h->ranks[l] < 1) continue;
-        if (h->vprec == RHOSVD_FP64)
-            CK(h, launch_project(h->n_pad, h->R_pad, h->r_pad[l], h->Z[l], h->Ut[l], (double*)h->V[l], nullptr, st));
-        else if (refine)
-            CK(h, launch_project(h->n_pad, h->R_pad, h->r_pad[l], h->Z[l], h->Ut[l], h->Vref[l], nullptr, st));
-        else
-            CK(h, launch_project(h->n_pad, h->R_pad, h->r_pad[l], h->Z[l], h->Ut[l], nullptr, (float*)h->V[l], st));
-    }
-    if (refine) {
+        if (!refine) break;
         // the cut again on tails computed from V, not from G: for orthonormal Z_p,
         // |(I - Z_r Z_r^T) U~|_F^2 = sum_{r<=k<p} |V[k, :]|^2 + |U~ - Z_p V_p|_F^2 exactly,
         // in the order of Z's columns; both parts are formed directly in FP64
@@ -937,32 +973,26 @@ rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R, const double*
             CK(h, launch_floor_sum(h->rpart[l], ntl, h->rfloor + l, st));
             CK(h, launch_row_norms2(p_ref[l], h->r_pad[l], h->R_pad, V64, h->Qn[l], st));
         }
-        TruncArgs tb{};
+        TruncArgs tb = trunc_args(h, eps);
         for (int l = 0; l < 3; ++l) {
             tb.lam[l] = h->Qn[l];
             tb.m_mode[l] = p_ref[l];
-            tb.sigma[l] = h->sigma[l];
-            tb.order[l] = h->order[l];
-            tb.tails[l] = h->tails[l];
         }
-        tb.m = (int)h->m;
-        tb.m_pad = (int)h->m_pad;
-        tb.n = (int)n;
-        tb.n_pad = (int)h->n_pad;
-        tb.xip = h->xip;
-        tb.R_pad = h->R_pad;
-        tb.anorm_part = h->a2_part;
-        tb.anorm_ntiles = h->a2_n;
-        tb.eps = eps;
-        tb.ranks = h->ranks_dev;
-        tb.scal = h->scal;
         tb.floor2 = h->rfloor;
         tb.presorted = 1;
         CK(h, launch_truncate(tb, st));
         CK(h, hipMemcpyAsync(h->host, h->ranks_dev, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
         CK(h, hipStreamSynchronize(st));
+        bool again = false;
+        for (int l = 0; l < 3; ++l)
+            if (h->host[l] > p_ref[l] && p_ref[l] < h->m) {
+                p_ref[l] = (int)std::min<int64_t>(h->m, 2 * (int64_t)p_ref[l] + 64);
+                again = true;
+            }
+        if (again) continue;
         for (int l = 0; l < 3; ++l) {
-            // p_l + 1: not even p_l certifies on the refined tails; keep p_l (the report's tail says so)
+            // p_l + 1 with p_l = m: not even the full basis certifies (tau below the
+            // residual's rounding); keep m (the report's tail says so)
             const int r = std::max(1, std::min(h->host[l], p_ref[l]));
             h->ranks[l] = r;
             if (h->r_pad[l] > r)
@@ -973,6 +1003,7 @@ rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R, const double*
             else
                 CK(h, launch_v_finalize(r, h->r_pad[l], h->R_pad, h->Vref[l], nullptr, (float*)h->V[l], st));
         }
+        break;
     }
     if (h->opt.als_sweeps > 0 && h->ranks[0] > 0 && h->ranks[1] > 0 && h->ranks[2] > 0) {
         rhosvd_status as = als_refine(h);
@@ -1072,6 +1103,7 @@ rhosvd_status rhosvd_get(rhosvd_handle h, double* Z1, double* Z2, double* Z3, vo
         report->dropped = h->dropped;
         report->certificate = cert ? h->hostd[8] : -1.0;
         report->anorm_method = h->anorm_method;
+        report->refine_used = h->refine_used;
         report->a_norm_upper = h->anorm_method == 2 ? h->a_upper : h->a_norm;
     }
     return RHOSVD_OK;
@@ -1132,7 +1164,7 @@ rhosvd_status rhosvd_reduce_batched(rhosvd_handle h, int32_t count, const rhosvd
             h->batch = nullptr;
         }
         std::string err;
-        h->batch = batch_plan_create(problems, count, prec_key, err);
+        h->batch = batch_plan_create(problems, count, prec_key, err, h->alloc);
         if (!h->batch) return fail(h, RHOSVD_ERR_ALLOC, err);
     }
     CK(h, batch_plan_run(h->batch, h->stream));
@@ -1148,17 +1180,15 @@ rhosvd_status rhosvd_reduce_batched(rhosvd_handle h, int32_t count, const rhosvd
 namespace {
 rhosvd_status net_alloc(rhosvd_ctx* h, int batch) {
     if (!h->net) {
-        if (hipMalloc((void**)&h->net, 4 * (size_t)NET_PARAMS * sizeof(float)) != hipSuccess) {
-            h->net = nullptr;
+        if (!(h->net = (float*)h->alloc.get(4 * (size_t)NET_PARAMS * sizeof(float)))) {
             return fail(h, RHOSVD_ERR_ALLOC, "network parameter allocation failed");
         }
     }
     const size_t need = net_work_floats(std::max(batch, 1));
     if (need > h->net_work_n) {
-        if (h->net_work) { hipStreamSynchronize(h->stream); hipFree(h->net_work); h->net_work = nullptr; }
+        if (h->net_work) { hipStreamSynchronize(h->stream); h->alloc.put(h->net_work); h->net_work = nullptr; }
         h->net_work_n = 0;
-        if (hipMalloc((void**)&h->net_work, need * sizeof(float)) != hipSuccess) {
-            h->net_work = nullptr;
+        if (!(h->net_work = (float*)h->alloc.get(need * sizeof(float)))) {
             return fail(h, RHOSVD_ERR_ALLOC, "network workspace allocation failed");
         }
         h->net_work_n = need;
@@ -1461,6 +1491,11 @@ rhosvd_status rhosvd_reduce_learned(rhosvd_handle h, int64_t n, int64_t R, const
     for (int l = 0; l < 3; ++l) {
         h->ranks[l] = h->host[l];
         h->r_pad[l] = (int)round_up(h->ranks[l] > 0 ? h->ranks[l] : 1, 128);
+        const int bad = learned_mode_fits(m, (int)h->zr_pad, L.p_cap, rf[l], width[l], h->ranks[l], h->r_pad[l]);
+        if (bad)
+            return fail(h, RHOSVD_ERR_DEVICE, "learned path: rank " + std::to_string(h->ranks[l]) + " of mode " +
+                                                  std::to_string(l) + " exceeds its buffers (check " +
+                                                  std::to_string(bad) + ", internal error)");
     }
     // Z: range-finder modes Z = Q W_B[:, order[0..r-1]]; Gram modes as in rhosvd_reduce
     std::vector<BtJob> jobs;
@@ -1534,9 +1569,8 @@ rhosvd_status rhosvd_t2c(rhosvd_handle h, int32_t r1, int32_t r2, int32_t r3, co
     };
     carve(cv);
     if (cv.off > T.bytes) {
-        if (T.ws) { CK(h, hipStreamSynchronize(st)); hipFree(T.ws); T.ws = nullptr; T.bytes = 0; }
-        if (hipMalloc((void**)&T.ws, cv.off) != hipSuccess) {
-            T.ws = nullptr;
+        if (T.ws) { CK(h, hipStreamSynchronize(st)); h->alloc.put(T.ws); T.ws = nullptr; T.bytes = 0; }
+        if (!(T.ws = (char*)h->alloc.get(cv.off))) {
             return fail(h, RHOSVD_ERR_ALLOC, "T2C workspace allocation of " + std::to_string(cv.off) + " bytes failed");
         }
         T.bytes = cv.off;
@@ -1595,9 +1629,8 @@ rhosvd_status rhosvd_t2c_get(rhosvd_handle h, double* weights, double* F1, doubl
     const int64_t kp = round_up(std::max(T.r1, T.r2), 64);
     const size_t need = a256((size_t)np * kp * 8) + a256((size_t)kp * Rp * 8) + a256((size_t)np * Rp * 8);
     if (need > T.lbytes) {
-        if (T.lw) { CK(h, hipStreamSynchronize(st)); hipFree(T.lw); T.lw = nullptr; T.lbytes = 0; }
-        if (hipMalloc((void**)&T.lw, need) != hipSuccess) {
-            T.lw = nullptr;
+        if (T.lw) { CK(h, hipStreamSynchronize(st)); h->alloc.put(T.lw); T.lw = nullptr; T.lbytes = 0; }
+        if (!(T.lw = (char*)h->alloc.get(need))) {
             return fail(h, RHOSVD_ERR_ALLOC, "T2C lifting workspace allocation of " + std::to_string(need) +
                                                  " bytes failed");
         }

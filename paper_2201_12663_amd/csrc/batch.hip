@@ -59,13 +59,26 @@ __global__ __launch_bounds__(256) void k_finish_b(const BProb* __restrict__ P) {
         else if (threadIdx.x == 4) v = q.flags[1];
         q.result[threadIdx.x] = v;
     }
-    if (st != 0 || !q.Zo[l]) return;
+    if (st != 0) return;
     const int r = q.ranks[l];
-    for (int c = blockIdx.z; c < r; c += gridDim.z) {
-        const double* src = q.Z[l] + (int64_t)c * q.n_pad;
-        double* dst = q.Zo[l] + (int64_t)c * q.n;
-        for (int i = threadIdx.x; i < q.n; i += 256) dst[i] = src[i];
-    }
+    if (q.Zo[l])
+        for (int c = blockIdx.z; c < r; c += gridDim.z) {
+            const double* src = q.Z[l] + (int64_t)c * q.n_pad;
+            double* dst = q.Zo[l] + (int64_t)c * q.n;
+            for (int i = threadIdx.x; i < q.n; i += 256) dst[i] = src[i];
+        }
+    // V^(l) = Z^(l)T U~^(l), the factors of the mixed Tucker-canonical format
+    if (q.Vo[l])
+        for (int nu = blockIdx.z; nu < q.R; nu += gridDim.z) {
+            double* dst = q.Vo[l] + (int64_t)nu * q.cap_rank;
+            if (q.v_f32) {
+                const float* src = (const float*)q.V[l] + (int64_t)nu * q.rcap_pad;
+                for (int j = threadIdx.x; j < r; j += 256) dst[j] = (double)src[j];
+            } else {
+                const double* src = (const double*)q.V[l] + (int64_t)nu * q.rcap_pad;
+                for (int j = threadIdx.x; j < r; j += 256) dst[j] = src[j];
+            }
+        }
 }
 
 }  // namespace
@@ -102,15 +115,16 @@ struct BatchPlan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool use_graph = false;
+    DevAlloc alloc;                      // the handle's allocator
 
     ~BatchPlan() {
         if (exec) hipGraphExecDestroy(exec);
         if (graph) hipGraphDestroy(graph);
         for (int i = 0; i < 2; ++i) {
             if (eplan[i]) eig_plan_destroy(eplan[i]);
-            if (ework[i]) hipFree(ework[i]);
+            alloc.put(ework[i]);
         }
-        if (ws) hipFree(ws);
+        alloc.put(ws);
         if (cap) hipStreamDestroy(cap);
     }
 };
@@ -141,7 +155,7 @@ size_t carve_batch(BatchPlan& B, char* base) {
         q.xip = c.take<double>(Rp);
         q.flags = c.take<int>(8);
         q.ranks = c.take<int>(8);
-        q.scal = c.take<double>(8);
+        q.scal = c.take<double>(16);
         const int64_t rt = Rp / 64;
         q.anorm_ntiles = rt * (rt + 1) / 2;
         q.anorm_part = c.take<double>(q.anorm_ntiles);
@@ -303,6 +317,8 @@ int batch_validate(const rhosvd_problem* probs, int count, std::string& msg) {
         if (q.cap_rank < 1) { msg = at + "cap_rank must be >= 1"; return RHOSVD_ERR_ARG; }
         const int nz = (q.Z1 != nullptr) + (q.Z2 != nullptr) + (q.Z3 != nullptr);
         if (nz != 0 && nz != 3) { msg = at + "Z1, Z2, Z3 must be all set or all NULL"; return RHOSVD_ERR_ARG; }
+        const int nv = (q.V1 != nullptr) + (q.V2 != nullptr) + (q.V3 != nullptr);
+        if (nv != 0 && nv != 3) { msg = at + "V1, V2, V3 must be all set or all NULL"; return RHOSVD_ERR_ARG; }
         if (q.beta && q.cap_beta < 1) { msg = at + "cap_beta must be >= 1 when beta is set"; return RHOSVD_ERR_ARG; }
         if (q.reserved0 != 0) { msg = at + "reserved0 must be zero"; return RHOSVD_ERR_ARG; }
         if (std::min(q.n, q.R) > 2048 || q.n > 65536 || q.R > ((int64_t)1 << 24)) {
@@ -313,8 +329,10 @@ int batch_validate(const rhosvd_problem* probs, int count, std::string& msg) {
     return RHOSVD_OK;
 }
 
-BatchPlan* batch_plan_create(const rhosvd_problem* probs, int count, int prec, std::string& err) {
+BatchPlan* batch_plan_create(const rhosvd_problem* probs, int count, int prec, std::string& err,
+                             const DevAlloc& alloc) {
     BatchPlan* B = new BatchPlan();
+    B->alloc = alloc;
     // prec: the core precision, plus 16 when beta is written as float, plus the
     // caller's fixed core tile times 256 (0: tuned on the first run)
     B->key.assign(probs, probs + count);
@@ -343,14 +361,17 @@ BatchPlan* batch_plan_create(const rhosvd_problem* probs, int count, int prec, s
         q.Zo[0] = d.Z1;
         q.Zo[1] = d.Z2;
         q.Zo[2] = d.Z3;
+        q.Vo[0] = d.V1;
+        q.Vo[1] = d.V2;
+        q.Vo[2] = d.V3;
+        q.v_f32 = (prec & 3) != 0 ? 1 : 0;
         q.beta = d.beta;
         q.cap_beta = d.cap_beta;
         q.beta_f32 = (prec & 16) ? 1 : 0;
         q.result = d.result;
     }
     const size_t need = carve_batch(*B, nullptr);
-    if (hipMalloc((void**)&B->ws, need) != hipSuccess) {
-        B->ws = nullptr;
+    if (!(B->ws = (char*)B->alloc.get(need))) {
         err = "batch workspace allocation of " + std::to_string(need) + " bytes failed";
         delete B;
         return nullptr;
@@ -386,8 +407,7 @@ BatchPlan* batch_plan_create(const rhosvd_problem* probs, int count, int prec, s
             delete B;
             return nullptr;
         }
-        if (hipMalloc(&B->ework[i], wb) != hipSuccess) {
-            B->ework[i] = nullptr;
+        if (!(B->ework[i] = B->alloc.get(wb))) {
             err = "eigensolver work allocation failed";
             delete B;
             return nullptr;

@@ -110,6 +110,8 @@ __device__ __forceinline__ void truncate_mode(int mode, const double* __restrict
     if (t == 0) {
         ranks[mode] = r;
         scal[3 + mode] = sqrt(scan[r < m ? r : m]);
+        scal[6 + mode] = fmax(key[0], 0.0);                        // lambda_1
+        scal[9 + mode] = r >= 1 && r <= m ? fmax(key[r - 1], 0.0) : 0.0;   // lambda_r
         if (mode == 0) { scal[0] = xi_norm; scal[1] = a_norm; scal[2] = tau; }
     }
 }
@@ -158,7 +160,8 @@ __global__ void k_status_b(const BProb* __restrict__ P, int np) {
     else if (*q.abort_w != 0) st = -4;             // eigensolver wait ran out
     else {
         const int64_t r1 = q.ranks[0], r2 = q.ranks[1], r3 = q.ranks[2];
-        const bool zcap = (q.Zo[0] || q.Zo[1] || q.Zo[2]) && (r1 > q.cap_rank || r2 > q.cap_rank || r3 > q.cap_rank);
+        const bool zcap = (q.Zo[0] || q.Zo[1] || q.Zo[2] || q.Vo[0] || q.Vo[1] || q.Vo[2]) &&
+                          (r1 > q.cap_rank || r2 > q.cap_rank || r3 > q.cap_rank);
         const bool rcap = r1 > q.rcap || r2 > q.rcap || r3 > q.rcap;
         const bool bcap = q.beta && r1 * r2 * r3 > q.cap_beta;
         if (zcap || rcap || bcap) st = -8;          // capacity

@@ -9,6 +9,23 @@
 
 #include "../../include/rhosvd.h"
 
+// Device memory of a handle and its batch plans: the caller's allocator
+// (rhosvd_create_with_allocator), or hipMalloc / hipFree when it has none.
+struct DevAlloc {
+    rhosvd_allocator a{};
+    void* get(size_t bytes) const {
+        if (bytes == 0) bytes = 256;
+        if (a.alloc) return a.alloc(bytes, a.ctx);
+        void* p = nullptr;
+        return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
+    }
+    void put(void* p) const {
+        if (!p) return;
+        if (a.free) a.free(p, a.ctx);
+        else hipFree(p);
+    }
+};
+
 // Padding granularities shared by the workspace layout and the kernels.
 constexpr int PAD_N = 64;    // rows of U~, Z and the Gram side (n, m)
 constexpr int PAD_R = 64;    // canonical terms (columns of U~, K of the core)
@@ -141,7 +158,8 @@ struct TruncArgs {
     int* order[3];          // m each: column of W for the k-th largest
     double* tails[3];       // m + 1 each
     int* ranks;             // 3 ints (m + 1 when no r certifies, see floor2)
-    double* scal;           // [0] xi_norm, [1] a_norm, [2] tau, [3 + l] tail at mode l's rank
+    double* scal;           // 16 doubles: [0] xi_norm, [1] a_norm, [2] tau, [3 + l] tail at mode l's
+                            // rank, [6 + l] largest eigenvalue, [9 + l] eigenvalue at the rank
     int m_mode[3];          // per-mode number of eigenvalues (0: m)
     const double* floor2;   // per-mode squared tail floor (device, 3 doubles) or null
     int presorted;          // nonzero: keep the given order (no sort; order = identity)
@@ -216,6 +234,8 @@ struct BProb {
     void* V[3];            // rcap_pad x R_pad (FP64, or FP32 for the mixed cores)
     void* Asplit;          // BF16x3: hi and lo planes of V1 diag(xi') (rcap_pad x R_pad bf16 each)
     double* Zo[3];         // caller outputs, n x cap_rank (ld n), or null
+    double* Vo[3];         // caller outputs V^(l), r_l x R (ld cap_rank, FP64), or null
+    int v_f32;             // V is held in FP32 (mixed cores)
     void* beta;            // caller output (double, or float when beta_f32) or null
     int64_t cap_beta;
     int beta_f32;
@@ -248,7 +268,8 @@ hipError_t launch_finish_b(const BProb* P, int np, hipStream_t st);
 struct BatchPlan;
 int batch_validate(const rhosvd_problem* probs, int count, std::string& msg);   // rhosvd_status
 // prec: core precision (0..2), plus 16 when beta is written as float
-BatchPlan* batch_plan_create(const rhosvd_problem* probs, int count, int prec, std::string& err);
+BatchPlan* batch_plan_create(const rhosvd_problem* probs, int count, int prec, std::string& err,
+                             const DevAlloc& alloc);
 bool batch_plan_matches(const BatchPlan* plan, const rhosvd_problem* probs, int count, int prec);
 hipError_t batch_plan_run(BatchPlan* plan, hipStream_t st);
 bool batch_plan_uses_graph(const BatchPlan* plan);

@@ -35,6 +35,7 @@ WL_RANKNET = 4          # rank-proposal training / evaluation draws
 WL_LOWRANK = 10         # exactly-low-rank test inputs
 WL_RANDOM = 11          # dense random test inputs
 WL_CORE = 13            # synthetic Tucker cores (Tucker-to-canonical tests)
+WL_RS = 14              # range-separated workloads (multi-Slater amplitudes)
 
 
 def rng(workload: int, seed: int) -> np.random.Generator:
@@ -266,3 +267,145 @@ def core_with_slice_spectra(seed: int, r1: int, r2: int, r3: int, spectra) -> np
 def random_core(seed: int, r1: int, r2: int, r3: int) -> np.ndarray:
     """Gaussian random core (Fortran order)."""
     return np.asfortranarray(rng(WL_CORE, 100_000 + seed).standard_normal((r1, r2, r3)))
+
+
+# ---------------------------------------------------------------------------
+# range-separated (RS) workloads of Section 4: sinc-quadrature Gaussian sums for
+# radial functions, split into long-range (t_k <= 1) and short-range terms
+# (eq. eqn:RS_repres), the Hadamard cube of the Newton kernel (the 1/|x|^3 example
+# of Section 5) and sums of Slater functions on lattices (Section 4.5)
+# ---------------------------------------------------------------------------
+def collocation_grid(n: int, b: float = 10.0) -> np.ndarray:
+    """n equispaced points on [-b, b] including both ends (and the origin for odd
+    n): the collocation discretization of Section 4.1 for continuous or singular
+    radial functions."""
+    return np.linspace(-b, b, n)
+
+
+def _sinc_rule(M: int, h: float, logweight):
+    """Trapezoid rule in s over nodes s_k = k h, k = -M..M, of int f(s) ds with
+    f = exp(logweight(s)) times a Gaussian factor: returns (s_k, log w_k)."""
+    s = h * np.arange(-M, M + 1, dtype=np.float64)
+    return s, math.log(h) + logweight(s)
+
+
+def newton_sinc_terms(R: int = 19, n: int = 257, b: float = 10.0):
+    """R-term (R = 2M + 1) Gaussian sum for 1/z, 1/z ~ sum_k w_k exp(-t_k^2 z^2):
+    the Laplace-Gauss identity 1/z = (2/sqrt(pi)) int_0^inf exp(-z^2 t^2) dt
+    (eq. eqn:Laplace_Newton) with t = e^s and the trapezoid rule at s_k = k h,
+    k = -M..M (eq. eqn:sinc_Newt): t_k = e^{s_k}, w_k = (2/sqrt(pi)) h e^{s_k}.
+    The step h is the one (on a fine scan) with the smallest relative error on
+    z in [grid step, 2 b sqrt(3)], the range the grid's differences span.
+    Long-range terms are those with t_k <= 1 (k <= 0): M + 1 of them."""
+    assert R % 2 == 1
+    M = (R - 1) // 2
+    z = np.geomspace(2.0 * b / (n - 1), 2.0 * b * math.sqrt(3.0), 400)
+    best = None
+    for h in np.linspace(0.05, 2.5, 491):
+        s, lw = _sinc_rule(M, h, lambda s: math.log(2.0 / math.sqrt(math.pi)) + s)
+        t2 = np.exp(2.0 * s)
+        approx = np.exp(lw)[None, :] * np.exp(-z[:, None] ** 2 * t2[None, :])
+        err = float(np.max(np.abs(approx.sum(axis=1) * z - 1.0)))
+        if best is None or err < best[0]:
+            best = (err, h)
+    s, lw = _sinc_rule(M, best[1], lambda s: math.log(2.0 / math.sqrt(math.pi)) + s)
+    return np.exp(s), np.exp(lw), dict(h=best[1], rel_err=best[0])
+
+
+def newton_kernel(n: int = 257, R: int = 19, b: float = 10.0, long_range: bool = False):
+    """Side matrices and weights of the collocated Newton kernel P_R (eq.
+    eqn:sinc_general): columns exp(-t_k^2 x_i^2) on the collocation grid, weights
+    w_k; with long_range only the terms t_k <= 1 (P_{R_l} of eq. eqn:RS_repres)."""
+    t, w, info = newton_sinc_terms(R, n, b)
+    keep = t <= 1.0 if long_range else np.ones_like(t, dtype=bool)
+    x = collocation_grid(n, b)
+    V = np.exp(-(x[:, None] ** 2) * (t[keep] ** 2)[None, :])
+    return V, w[keep], info
+
+
+def newton_cubed(n: int = 257, R: int = 19, b: float = 10.0, long_range: bool = False,
+                 eps: float = 1e-5) -> CanonicalInput:
+    """P (.) P (.) P, the discretized 1/|x|^3 of Section 5 (the Newton kernel's
+    Gaussian sum cubed pointwise, Lemma 4.3 for its long-range part): columns
+    p_a (.) p_b (.) p_c in each mode for all (a, b, c), weights w_a w_b w_c, so
+    R' = R^3 (6859 for R = 19; 1000 for the long-range part, R_l = 10)."""
+    V, w, info = newton_kernel(n, R, b, long_range)
+    K = V.shape[1]
+    col = (V[:, :, None, None] * V[:, None, :, None] * V[:, None, None, :]).reshape(n, K ** 3)
+    xi = (w[:, None, None] * w[None, :, None] * w[None, None, :]).reshape(-1)
+    U = [np.asfortranarray(col) for _ in range(3)]
+    name = f"newton-cubed{'-long' if long_range else ''}-n{n}-R{K ** 3}"
+    return CanonicalInput(U, xi, eps, name=name, meta=dict(terms=K, sinc=info, b=b))
+
+
+def slater_sinc_terms(lam: float = 0.5, R: int = 8, R_l: int = 3, n: int = 384, b: float = 10.0):
+    """R-term Gaussian sum for the Slater function exp(-lam |x|) = G(rho),
+    rho = |x|^2, from its Laplace transform G(rho) = int_0^inf Ghat(tau)
+    exp(-rho tau) dtau with Ghat(tau) = sqrt(alpha/pi) tau^{-3/2} exp(-alpha/tau),
+    alpha = lam^2 / 4 (eq. Slater_Laplace_tr): tau = e^s, trapezoid nodes
+    s_k = (k - R_l + 1) h, k = 0..R-1, so that exactly R_l terms have tau_k <= 1
+    (the long-range part).  Weights w_k = h sqrt(alpha/pi) e^{-s_k/2}
+    exp(-alpha e^{-s_k}).  h minimizes the max error on rho in
+    [grid step^2, 12 b^2] (a scan)."""
+    alpha = lam * lam / 4.0
+    rho = np.geomspace((2.0 * b / (n - 1)) ** 2, 12.0 * b * b, 400)
+    exact = np.exp(-lam * np.sqrt(rho))
+
+    def rule(h):
+        s = h * (np.arange(R, dtype=np.float64) - (R_l - 1))
+        lw = math.log(h) + 0.5 * math.log(alpha / math.pi) - 0.5 * s - alpha * np.exp(-s)
+        return np.exp(s), np.exp(lw)
+
+    best = None
+    for h in np.linspace(0.05, 3.0, 591):
+        tau, w = rule(h)
+        err = float(np.max(np.abs((w[None, :] * np.exp(-rho[:, None] * tau[None, :])).sum(axis=1) - exact)))
+        if best is None or err < best[0]:
+            best = (err, h)
+    tau, w = rule(best[1])
+    return tau, w, dict(h=best[1], max_err=best[0])
+
+
+def lattice_nodes(L, spacing: float = 1.0) -> np.ndarray:
+    """Nodes of an L1 x L2 x L3 lattice with the given spacing, centred at the origin."""
+    axes = [spacing * (np.arange(Lk, dtype=np.float64) - (Lk - 1) / 2.0) for Lk in L]
+    X, Y, Zc = np.meshgrid(*axes, indexing="ij")
+    return np.stack([X.ravel(order="F"), Y.ravel(order="F"), Zc.ravel(order="F")], axis=1)
+
+
+def slater_amplitude_function(nodes: np.ndarray, c1: float = 6.0, c2: float = 0.1) -> np.ndarray:
+    """F(x,y,z) = c1 cos(x + 2y + 4z) exp(-c2 sqrt(x^2 + 2y^2 + 4z^2)) (eq. eq:func2)."""
+    x, y, z = nodes[:, 0], nodes[:, 1], nodes[:, 2]
+    return c1 * np.cos(x + 2 * y + 4 * z) * np.exp(-c2 * np.sqrt(x * x + 2 * y * y + 4 * z * z))
+
+
+def multi_slater(L=(4, 4, 4), n: int = 384, lam: float = 0.5, R: int = 8, R_l: int = 3, b: float = 10.0,
+                 spacing: float = 1.0, amplitudes: str = "random", seed: int = 0, long_range: bool = True,
+                 eps: float = 1e-3) -> CanonicalInput:
+    """Long-range part of a sum of Slater functions c_j exp(-lam |x - x_j|) over
+    the nodes x_j of an L1 x L2 x L3 lattice (Section 4.5, eq.
+    eqn:Slater_interp_multi): each Slater function is the Gaussian sum of
+    slater_sinc_terms, and its long-range terms (tau_k <= 1; all terms when
+    long_range is False) are shifted to the node, so the canonical rank is
+    N R_l.  Amplitudes: uniform in [-5, 5] ("random", Table 4.1) or
+    slater_amplitude_function at the nodes ("function", Table 4.2).
+    Collocation grid on [-b, b]."""
+    tau, w, info = slater_sinc_terms(lam, R, R_l, n, b)
+    keep = tau <= 1.0 if long_range else np.ones_like(tau, dtype=bool)
+    tau, w = tau[keep], w[keep]
+    nodes = lattice_nodes(L, spacing)
+    N = nodes.shape[0]
+    if amplitudes == "random":
+        c = rng(WL_RS, seed).uniform(-5.0, 5.0, size=N)
+    else:
+        c = slater_amplitude_function(nodes)
+    x = collocation_grid(n, b)
+    K = len(tau)
+    U = []
+    for l in range(3):
+        d = x[:, None] - nodes[None, :, l]                     # n x N
+        U.append(np.asfortranarray(np.exp(-(d[:, :, None] ** 2) * tau[None, None, :]).reshape(n, N * K)))
+    xi = (c[:, None] * w[None, :]).reshape(-1)
+    tag = "x".join(str(v) for v in L)
+    return CanonicalInput(U, xi, eps, name=f"multi-slater-{amplitudes}-{tag}-n{n}-R{N * K}",
+                          meta=dict(nodes=nodes, c=c, tau=tau, w=w, sinc=info, b=b, terms=K))

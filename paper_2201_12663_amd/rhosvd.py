@@ -21,12 +21,13 @@ FP64, FP32, BF16X3 = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
 PHASES = ["norms", "anorm", "gram", "eig", "trunc_z", "project", "core"]
 ANORM = {"auto": 0, "exact": 1, "probe": 2}
+REFINE = {"auto": 0, "refine": 1, "deflate": 2, "off": 3}
 
 STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_NONFINITE", -3: "ERR_ALLOC", -4: "ERR_DEVICE",
           -5: "ERR_NOCONV", -6: "ERR_STATE", -7: "ERR_UNSUPPORTED", -8: "ERR_CAPACITY"}
 
 # every symbol include/rhosvd.h declares
-EXPORTS = ["rhosvd_create", "rhosvd_destroy", "rhosvd_set_options", "rhosvd_reduce", "rhosvd_get",
+EXPORTS = ["rhosvd_create", "rhosvd_create_with_allocator", "rhosvd_destroy", "rhosvd_set_options", "rhosvd_reduce", "rhosvd_get",
            "rhosvd_get_xi", "rhosvd_get_spectrum", "rhosvd_get_v", "rhosvd_reduce_batched",
            "rhosvd_batch_uses_graph", "rhosvd_last_core_tile", "rhosvd_net_num_params", "rhosvd_net_set_params", "rhosvd_net_get_params",
            "rhosvd_net_forward", "rhosvd_net_train_step", "rhosvd_sketch_features", "rhosvd_reduce_learned",
@@ -35,6 +36,15 @@ EXPORTS = ["rhosvd_create", "rhosvd_destroy", "rhosvd_set_options", "rhosvd_redu
 
 NET_IN, NET_OUT = 67, 2
 PATHS = {0: "range finder", 1: "gram (chosen)", 2: "gram (certificate failed)", 3: "gram (R < n)"}
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    """rhosvd_allocator"""
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", ctypes.c_void_p)]
 
 
 class Options(ctypes.Structure):
@@ -49,7 +59,7 @@ class Report(ctypes.Structure):
                 ("bound", ctypes.c_double), ("tail", ctypes.c_double * 3), ("ranks", ctypes.c_int32 * 3),
                 ("m", ctypes.c_int32), ("eig_sweeps", ctypes.c_int32), ("dropped", ctypes.c_int32),
                 ("certificate", ctypes.c_double), ("a_norm_upper", ctypes.c_double),
-                ("anorm_method", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("anorm_method", ctypes.c_int32), ("refine_used", ctypes.c_int32)]
 
 
 class Problem(ctypes.Structure):
@@ -58,7 +68,8 @@ class Problem(ctypes.Structure):
                 ("U3", ctypes.c_void_p), ("xi", ctypes.c_void_p), ("eps", ctypes.c_double),
                 ("cap_rank", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("cap_beta", ctypes.c_int64),
                 ("Z1", ctypes.c_void_p), ("Z2", ctypes.c_void_p), ("Z3", ctypes.c_void_p),
-                ("beta", ctypes.c_void_p), ("result", ctypes.c_void_p)]
+                ("beta", ctypes.c_void_p), ("result", ctypes.c_void_p),
+                ("V1", ctypes.c_void_p), ("V2", ctypes.c_void_p), ("V3", ctypes.c_void_p)]
 
 
 class LearnedInfo(ctypes.Structure):
@@ -100,6 +111,8 @@ def load():
         lib = ctypes.CDLL(LIB_PATH)
         vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
         lib.rhosvd_create.argtypes = [ctypes.POINTER(vp), vp, ctypes.POINTER(Options)]
+        lib.rhosvd_create_with_allocator.argtypes = [ctypes.POINTER(vp), vp, ctypes.POINTER(Allocator),
+                                                     ctypes.POINTER(Options)]
         lib.rhosvd_destroy.argtypes = [vp]
         lib.rhosvd_set_options.argtypes = [vp, ctypes.POINTER(Options)]
         lib.rhosvd_reduce.argtypes = [vp, i64, i64, vp, vp, vp, vp, dbl, ctypes.POINTER(i32)]
@@ -129,7 +142,7 @@ def load():
         lib.rhosvd_last_error.argtypes = [vp]
         lib.rhosvd_last_error.restype = ctypes.c_char_p
         lib.rhosvd_version.restype = ctypes.c_char_p
-        for f in ("rhosvd_create", "rhosvd_destroy", "rhosvd_set_options", "rhosvd_reduce", "rhosvd_get",
+        for f in ("rhosvd_create", "rhosvd_create_with_allocator", "rhosvd_destroy", "rhosvd_set_options", "rhosvd_reduce", "rhosvd_get",
                   "rhosvd_get_xi", "rhosvd_get_spectrum", "rhosvd_get_v", "rhosvd_reduce_batched",
                   "rhosvd_net_set_params", "rhosvd_net_get_params", "rhosvd_net_forward", "rhosvd_net_train_step",
                   "rhosvd_sketch_features", "rhosvd_reduce_learned", "rhosvd_t2c", "rhosvd_t2c_get", "rhosvd_t2c_noalloc"):
@@ -177,7 +190,11 @@ class Reducer:
     """One library handle bound to a stream."""
 
     def __init__(self, precision="fp64", stream=None, max_eig_sweeps=0, profile=False, beta_fp32=False,
-                 refine_tails=False, core_tile=0, certificate=False, anorm="auto", als_sweeps=0):
+                 refine_tails="auto", core_tile=0, certificate=False, anorm="auto", als_sweeps=0,
+                 torch_allocator=True):
+        """torch_allocator: the handle's device workspace comes from PyTorch's
+        caching allocator (rhosvd_create_with_allocator), so it is counted by
+        torch.cuda.memory_allocated and shares torch's pool; False: hipMalloc."""
         import torch
         self.lib = load()
         self.opt = Options()
@@ -186,7 +203,8 @@ class Reducer:
         self.opt.anorm = ANORM[anorm] if isinstance(anorm, str) else int(anorm)
         self.opt.als_sweeps = int(als_sweeps)
         self.opt.beta_fp32 = 1 if beta_fp32 else 0
-        self.opt.refine_tails = int(refine_tails) if refine_tails in (0, 1, 2) else -1
+        self.opt.refine_tails = REFINE.get(refine_tails, -1) if isinstance(refine_tails, str) else \
+            (int(refine_tails) if refine_tails in (0, 1, 2, 3) else -1)
         self.beta_dtype = torch.float32 if beta_fp32 else torch.float64
         self.opt.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self.opt.max_eig_sweeps = int(max_eig_sweeps)
@@ -195,8 +213,25 @@ class Reducer:
             stream = torch.cuda.current_stream()
         self.stream = stream
         self.h = ctypes.c_void_p()
-        s = self.lib.rhosvd_create(ctypes.byref(self.h), ctypes.c_void_p(stream.cuda_stream),
-                                   ctypes.byref(self.opt))
+        self._allocator = None
+        if torch_allocator:
+            dev = torch.cuda.current_device()
+
+            def _alloc(size, ctx):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(size), dev, stream)
+                except Exception:      # out of memory: the library reports RHOSVD_ERR_ALLOC
+                    return None
+
+            def _free(ptr, ctx):
+                torch.cuda.caching_allocator_delete(ptr)
+
+            self._allocator = Allocator(ALLOC_FN(_alloc), FREE_FN(_free), None)
+            s = self.lib.rhosvd_create_with_allocator(ctypes.byref(self.h), ctypes.c_void_p(stream.cuda_stream),
+                                                      ctypes.byref(self._allocator), ctypes.byref(self.opt))
+        else:
+            s = self.lib.rhosvd_create(ctypes.byref(self.h), ctypes.c_void_p(stream.cuda_stream),
+                                       ctypes.byref(self.opt))
         if s != 0:
             raise RhosvdError(s, self.lib.rhosvd_last_error(None).decode())
         self.n = self.R = 0
@@ -274,7 +309,7 @@ class Reducer:
         report = dict(xi_norm=rep.xi_norm, a_norm=rep.a_norm, tau=rep.tau, bound=rep.bound,
                       tail=list(rep.tail), ranks=list(rep.ranks), m=rep.m, eig_sweeps=rep.eig_sweeps,
                       dropped=rep.dropped, certificate=rep.certificate, a_norm_upper=rep.a_norm_upper,
-                      anorm_method=rep.anorm_method)
+                      anorm_method=rep.anorm_method, refine_used=rep.refine_used)
         beta_t = None
         if b is not None:
             beta_t = b.view(r3, r2, r1).permute(2, 1, 0) if b.numel() > 0 else b.view(r1, r2, r3)
@@ -309,14 +344,16 @@ class Reducer:
         return {name: float(self.lib.rhosvd_phase_ms(self.h, i)) for i, name in enumerate(PHASES)}
 
     # ---- batched reductions
-    def batch_descriptors(self, problems, results, outputs=None, cap_rank=None):
+    def batch_descriptors(self, problems, results, outputs=None, cap_rank=None, v_outputs=None):
         """Descriptor array for rhosvd_reduce_batched.
 
         problems: list of (U1, U2, U3, xi, eps) with column-major CUDA tensors.
         results:  (count, 8) int32 CUDA tensor (ranks, status, dropped).
         outputs:  None (ranks only), or a list of (Z1, Z2, Z3, beta_flat) per problem
                   (Z_l: (n, cap) column-major float64, beta_flat: the handle's beta dtype, or None).
-        cap_rank: per-problem rank caps when outputs is None (default min(n, R))."""
+        cap_rank: per-problem rank caps when outputs is None (default min(n, R)).
+        v_outputs: None, or per problem (V1, V2, V3) column-major float64 tensors of
+                  shape (cap_rank, R) (the mixed Tucker-canonical factors), or None."""
         import torch
         if not (results.is_cuda and results.dtype == torch.int32 and results.is_contiguous()
                 and tuple(results.shape) == (len(problems), 8)):
@@ -350,6 +387,13 @@ class Reducer:
                         raise ValueError(f"beta outputs must be {self.beta_dtype}")
                     d.beta = b.data_ptr()
                     d.cap_beta = int(b.numel())
+            if v_outputs is not None and v_outputs[i] is not None:
+                Vs = v_outputs[i]
+                for V in Vs:
+                    if tuple(V.shape) != (d.cap_rank, R):
+                        raise ValueError("V outputs must be (cap_rank, R)")
+                d.V1, d.V2, d.V3 = (_colmajor(Vs[0], "V1").value, _colmajor(Vs[1], "V2").value,
+                                    _colmajor(Vs[2], "V3").value)
         return arr
 
     def reduce_batched_raw(self, descriptors):

@@ -74,7 +74,7 @@ def test_struct_offsets_match_a_c_compiler(tmp_path):
     cc = shutil.which("gcc") or shutil.which("cc")
     if cc is None:
         pytest.skip("no host C compiler")
-    structs = {"rhosvd_options": rhosvd.Options, "rhosvd_report": rhosvd.Report,
+    structs = {"rhosvd_options": rhosvd.Options, "rhosvd_report": rhosvd.Report, "rhosvd_allocator": rhosvd.Allocator,
                "rhosvd_problem": rhosvd.Problem, "rhosvd_learned_info": rhosvd.LearnedInfo}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rhosvd.h"', "int main(void) {"]
     for cname, py in structs.items():

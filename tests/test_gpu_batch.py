@@ -93,7 +93,7 @@ def test_batched_equals_single_path_ranks(batch_inputs):
     probs = [to_dev(ci) for ci in cis]
     red = rhosvd.Reducer(precision="fp64")
     out, _, _, _ = red.reduce_batched(probs, beta=False)
-    single = rhosvd.Reducer(precision="fp64")
+    single = rhosvd.Reducer(precision="fp64", anorm="exact", refine_tails="off")
     for ci, p, o in zip(cis, probs, out):
         r = single.reduce(*p)
         assert tuple(r) == o["ranks"], (ci.name, r, o["ranks"])
@@ -224,7 +224,7 @@ def test_long_contraction_hands_over_partial_sums(orc, batch_inputs, prec):
     probs = [to_dev(ci) for ci in cis]
     red = rhosvd.Reducer(precision=prec)
     out, _, _, _ = red.reduce_batched(probs)
-    single = rhosvd.Reducer(precision=prec)
+    single = rhosvd.Reducer(precision=prec, anorm="exact", refine_tails="off")
     # |beta - beta_exact| against |A|: FP32 accumulation of up to 8192 terms
     # (2048 sequential MFMA steps) per hand-over, u32 sqrt(2048) ~ 3e-6 of the
     # running sums for positive terms; BF16x3 adds its split error (~2^-17)
@@ -270,7 +270,7 @@ def test_batched_uneven_config_sample():
     probs = [to_dev(ci) for ci in cis]
     red = rhosvd.Reducer(precision="fp32")
     out, _, _, _ = red.reduce_batched(probs)
-    single = rhosvd.Reducer(precision="fp32")
+    single = rhosvd.Reducer(precision="fp32", anorm="exact", refine_tails="off")
     for ci, p, o in zip(cis, probs, out):
         assert o["status"] == 0
         r = single.reduce(*p)
@@ -347,7 +347,7 @@ def test_batched_real_sizes_vs_golden(orc, prec):
     # the single path on the same problems gives the spectrum the batched pass cut
     # (the two form the same Gram matrices and tridiagonalize them identically, up
     # to the Gram's summation order): its tails measure the path's tail error
-    single = rhosvd.Reducer(precision=prec, anorm="exact")
+    single = rhosvd.Reducer(precision=prec, anorm="exact", refine_tails="off")
     for ci, g, o in zip(big, gold["problems"], out):
         assert o["status"] == 0
         r = o["ranks"]

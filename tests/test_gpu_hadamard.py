@@ -91,6 +91,9 @@ def test_hadamard_fp64_vs_oracle(orc, had, eps, anorm):
     zero_col = np.any(np.stack([np.max(np.abs(u), axis=0) for u in ci.U]) == 0.0, axis=0)
     assert rep["dropped"] == int(np.sum(zero_col | (ci.xi == 0.0)))
     assert rep["anorm_method"] == (1 if anorm == "exact" else 2)
+    # the default refinement: at eps = 1e-6 tau^2 / sigma_1^2 ~ 6.5e-17 lies in the
+    # Gram route's noise band, so the deflated second pass runs; at 1e-4 no refinement
+    assert rep["refine_used"] == (2 if eps == 1e-6 else 0), rep["refine_used"]
     tau = gc.check_anorm(rep, gold["a_norm"], case["tau"])
     _flush(f"anorm {anorm}: |A| in [{rep['a_norm'] / gold['a_norm']:.8f}, {rep['a_norm_upper'] / gold['a_norm']:.8f}]"
            f" |A|, tau {tau / case['tau']:.8f} of the oracle's")
@@ -119,7 +122,8 @@ def test_hadamard_fp64_vs_oracle(orc, had, eps, anorm):
     assert err <= rep["bound"] * (1 + 1e-9)
     assert rep["bound"] <= eps * gold["a_norm"] * (1 + 1e-9)
     if tuple(g["ranks"]) == tuple(case["ranks"]):
-        assert abs(err - case["error"]) <= 1e-4 * case["error"]
+        # the deflated pass's vectors near the cut agree with the oracle's less closely
+        assert abs(err - case["error"]) <= (1e-3 if rep["refine_used"] == 2 else 1e-4) * case["error"]
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])

@@ -127,8 +127,9 @@ def run_learned(ci, params, prec="fp64"):
     red.net_set(dev(params))
     ranks, info = red.reduce_learned(U[0], U[1], U[2], xi, ci.eps, om)
     res = red.get()
-    # the learned path forms |A| by the exact identity; so does this plain reduction
-    plain = rhosvd.Reducer(precision=prec, anorm="exact")
+    # the learned path forms |A| by the exact identity and takes the Gram route's
+    # plain cut on its fallbacks; so does this plain reduction
+    plain = rhosvd.Reducer(precision=prec, anorm="exact", refine_tails="off")
     pr = plain.reduce(U[0], U[1], U[2], xi, ci.eps)
     pres = plain.get()
     torch.cuda.synchronize()
@@ -201,7 +202,7 @@ def test_trained_network_gains_over_the_plain_method():
     red.net_set(dev(params))
     # like for like: the learned path forms |A| by the exact identity, and so does
     # the plain reduction it is compared with
-    plain = rhosvd.Reducer(precision="fp32", anorm="exact")
+    plain = rhosvd.Reducer(precision="fp32", anorm="exact", refine_tails="off")
     t_l = {"smooth": 0.0, "newton": 0.0}
     t_p = {"smooth": 0.0, "newton": 0.0}
     rows = []
