@@ -12,7 +12,10 @@ FP64 norms/Gram/eigensolver/truncation/Z/projection, FP32-MFMA or BF16x3 core).
 `value` is the fastest mixed path whose reconstruction error is certified within
 eps + 1e-6 of |A| in this run: the truncation part is bounded by Theorem 2.3 (the
 library's report), the core part is measured against the FP64 path's core, and
-the two are orthogonal.
+the two are orthogonal.  The rate has two reductions in flight (two handles on two
+streams, so that the eigensolver phase of one overlaps the core of the other),
+when those reproduce the sequential run's ranks and core bit for bit; the
+one-at-a-time rate and latency of every path are in "paths".
 
 The line also carries "learned": fresh problems of the rank-proposal workloads
 through the learned path (trained network, certified range finder, fallback)
@@ -86,6 +89,40 @@ def time_path(red, U, xi, eps, beta_buf, steps, warmup):
     dt = time.perf_counter() - t0
     avg = {k: sum(p[k] for p in phases) / len(phases) for k in phases[0]}
     return dt / steps * 1e3, sum(core_ms) / len(core_ms), avg
+
+
+def time_pipelined(prec, U, xi, eps, ranks, steps, warmup, beta_ref):
+    """Two reductions in flight: two handles, each on its own stream, alternate
+    whole reductions (reduce + core), so that the first phase of one reduction
+    (norms, Grams, eigensolver: narrow launches) overlaps the core of the one
+    before it (the wide MFMA launch).  Each step is still one whole reduction of
+    the same input; the clock brackets all of them.  Returns (ms per reduction,
+    largest |beta - beta_ref| over the timed reductions, ranks seen)."""
+    import torch
+    from paper_2201_12663_amd import rhosvd
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    reds = [rhosvd.Reducer(precision=prec, stream=s) for s in streams]
+    r1, r2, r3 = ranks
+    bufs = [torch.empty(r1 * r2 * r3, dtype=torch.float64, device="cuda") for _ in range(2)]
+    seen = set()
+    for i in range(2 * max(warmup, 1)):
+        red = reds[i % 2]
+        seen.add(tuple(red.reduce(U[0], U[1], U[2], xi, eps)))
+        red.core_only(bufs[i % 2])
+    torch.cuda.synchronize()
+    diffs = []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        red = reds[i % 2]
+        seen.add(tuple(red.reduce(U[0], U[1], U[2], xi, eps)))   # waits for its own stream only
+        red.core_only(bufs[i % 2])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for b in bufs:
+        diffs.append(float((b - beta_ref).abs().max().item()))
+    for red in reds:
+        red.close()
+    return dt / steps * 1e3, max(diffs), sorted(seen)
 
 
 def cpu_baseline(ci):
@@ -455,6 +492,11 @@ def main():
                              certificate_rel=rep["certificate"] / rep["a_norm"], core_tile=red.last_core_tile(),
                              refine_used=rep["refine_used"], anorm_method=rep["anorm_method"])
         betas[prec] = beta
+        # the same path with two reductions in flight on two streams
+        pms, pdiff, pseen = time_pipelined(prec, U, xi, ci.eps, ranks, 2 * args.steps, args.warmup, beta)
+        results[prec].update(pipelined_ms_per_reduction=pms, pipelined_reductions_per_s=1e3 / pms,
+                             pipelined_max_abs_diff=pdiff, pipelined_ranks=[list(r) for r in pseen])
+        log(f"  {prec}: pipelined {pms:.2f} ms/reduction, |beta - sequential beta|_max = {pdiff:.3g}, ranks {pseen}")
         log(f"  {prec}: {ms:.2f} ms/step, core {core_ms:.2f} ms "
             f"({results[prec]['core_tflops']:.1f} TFLOP/s), phases {results[prec]['phase_ms']}")
         red.close()
@@ -476,26 +518,35 @@ def main():
     mixed = [p for p in results if p != "fp64" and bound_ok(p)]
     best = max(mixed, key=lambda p: results[p]["reductions_per_s"]) if mixed else next(iter(results))
     rb = results[best]
+    # the headline rate has two reductions in flight when they reproduce the
+    # sequential run's ranks and core exactly; else the sequential rate
+    piped = rb.get("pipelined_max_abs_diff") == 0.0 and rb.get("pipelined_ranks") == [rb["ranks"]]
+    rate = rb["pipelined_reductions_per_s"] if piped else rb["reductions_per_s"]
+    rate_key = "pipelined_reductions_per_s" if piped else "reductions_per_s"
     peak = PEAK_TFLOPS[best]
     achieved = rb["core_mfma_tflops"]
     line = {
         "metric": METRIC,
-        "value": round(rb["reductions_per_s"], 4),
+        "value": round(rate, 4),
         "unit": "reductions/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(rb["ms_per_step"], 4),
+        "ms_per_step": round(1e3 / rate, 4),
+        "latency_ms": round(rb["ms_per_step"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[best],
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "n": 1024, "R": 4096, "eps": 1e-5, "precision": best,
-                   "ranks": rb["ranks"], "parallelism": "single-gpu"},
+                   "ranks": rb["ranks"], "parallelism": "single-gpu",
+                   "in_flight": 2 if piped else 1},
         "paths": results,
-        "speedup_vs_plain_fp64": (rb["reductions_per_s"] / results["fp64"]["reductions_per_s"]
-                                  if "fp64" in results else None),
+        "speedup_vs_plain_fp64": (rate / results["fp64"][rate_key]
+                                  if "fp64" in results and rate_key in results["fp64"] else None),
+        "speedup_vs_plain_fp64_sequential": (rb["reductions_per_s"] / results["fp64"]["reductions_per_s"]
+                                             if "fp64" in results else None),
         "roofline": {"bound": "mfma", "kernel": f"k_core ({best}, {rb['core_tile']}-row tile)",
                      "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                      "traffic": core_traffic(os.path.join(ROOT, "paper_2201_12663_amd", "csrc", "k_core.hip"),

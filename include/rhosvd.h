@@ -78,8 +78,14 @@ typedef struct {
                                 in the FP64 noise band of its Gram matrix, lambda_r <=
                                 64 u lambda_1 (u = 2^-53: there the discarded and even
                                 the last kept eigenvalues carry noise of about u |G|),
-                                2 if tau^2 itself lies in that band (n <= R), else 1;
-                                none otherwise.  The report's refine_used says which.
+                                2 if tau^2 itself lies in that band, else 1; none
+                                otherwise.  The report's refine_used says which.
+                                When R < n (Gram on the R side, Z = U~ W Sigma^-1, whose
+                                columns at the Gram's rounding level are not
+                                orthonormal) a refinement re-runs the whole reduction
+                                on the n x n Gram with the exact |A| (n <= 2048; beyond
+                                that the plain cut stays), at the cost of that larger
+                                eigensolve.
                                 With 1, where even the wider p does not certify on the
                                 refined tails, p grows (2p + 64, at most m) and the
                                 refined cut is taken again.
@@ -94,7 +100,7 @@ typedef struct {
                                 tau^2 lies below that floor the refined ranks are the
                                 smaller, still certified ones (Theorem 2.3); the
                                 spectrum then holds |V_p[k,:]| for k < p.
-                                2 (n <= R; when R < n it acts as 1): a deflated second
+                                2: a deflated second
                                 Gram pass.  With Z_k the leading k eigenvectors of the
                                 first pass whose singular values are >= 2^-13 sigma_1
                                 (k < r), U'' = (I - Z_k Z_k^T)^2 U~ is formed in FP64 and
@@ -173,7 +179,8 @@ typedef struct {
     double a_norm_upper; /* an upper bound of |A|_F: equal to a_norm when that is exact,
                             (a_norm^2 + b_p^2)^(1/2) with the probe (see rhosvd_options.anorm) */
     int32_t anorm_method;  /* 1 exact identity, 2 probe lower bound */
-    int32_t refine_used;   /* the refinement rhosvd_reduce ran: 0 none, 1 refined tails, 2 deflated pass */
+    int32_t refine_used;   /* the refinement rhosvd_reduce ran: 0 none, 1 refined tails, 2 deflated
+                              pass; plus 4 when R < n and it ran on the n x n Gram */
 } rhosvd_report;
 
 typedef struct rhosvd_ctx* rhosvd_handle;

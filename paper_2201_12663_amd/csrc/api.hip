@@ -49,6 +49,7 @@ struct rhosvd_ctx {
     // layout of the last reduction
     int64_t n = 0, R = 0, n_pad = 0, R_pad = 0, m = 0, m_pad = 0, zr_pad = 0;
     bool rside = false;                  // R < n: Gram on the R side
+    bool force_nside = false;            // R < n re-run on the n x n Gram (refinement)
     double* Ut[3] = {};                  // normalized side matrices (n_pad x R_pad)
     double* xip = nullptr;               // xi' (R_pad)
     int* flags = nullptr;
@@ -290,8 +291,8 @@ rhosvd_status layout(rhosvd_ctx* h, int64_t n, int64_t R) {
     h->R = R;
     h->n_pad = round_up(n, PAD_N);
     h->R_pad = round_up(R, PAD_R);
-    h->m = n < R ? n : R;
-    h->rside = R < n;
+    h->rside = R < n && !h->force_nside;
+    h->m = h->rside ? R : n;                     // the Gram's size
     h->m_pad = h->rside ? h->R_pad : h->n_pad;   // Gram on the min(n, R) side
     h->zr_pad = round_up(h->m, RPAD_CORE);       // max padded rank
     const int64_t mp = h->m_pad, Rp = h->R_pad;
@@ -893,6 +894,24 @@ rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R, const double*
         }
         refine_mode = want ? want : REFINE_OFF;
     }
+    if (refine_mode != REFINE_OFF && h->rside) {
+        // The R-side route forms Z = U~ W Sigma^-1: its columns whose sigma^2 lies at
+        // the Gram's rounding level lose orthonormality, and the refined tails (which
+        // need orthonormal Z_p) would be wrong there.  The reduction runs again on the
+        // n x n Gram, whose eigenvectors are orthonormal to working precision, with the
+        // same refinement choice; beyond the eigensolver's size the plain cut stays.
+        if (n <= 2048) {
+            const rhosvd_options keep = h->opt;
+            h->force_nside = true;
+            h->opt.anorm = 1;
+            rhosvd_status rs = rhosvd_reduce(h, n, R, U1, U2, U3, xi, eps, ranks);
+            h->opt = keep;
+            h->force_nside = false;
+            if (rs == RHOSVD_OK) h->refine_used |= 4;
+            return rs;
+        }
+        refine_mode = REFINE_OFF;
+    }
     h->refine_used = refine_mode == REFINE_OFF ? 0 : refine_mode;
     h->sweeps = 0;
     h->dropped = h->host[5];
@@ -913,7 +932,7 @@ rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R, const double*
     // refine_tails = 1: Z and V first at the wider p_l = min(m, r + r/8 + 16); where
     // even p_l does not certify on the refined tails, p_l grows (2 p_l + 64, at most m)
     // and the pass repeats, so the refined cut always ends certified
-    const bool refine = (refine_mode == 1 || (refine_mode == 2 && h->rside)) && h->ranks[0] > 0;
+    const bool refine = refine_mode == 1 && h->ranks[0] > 0;
     int p_ref[3] = {0, 0, 0};
     if (refine)
         for (int l = 0; l < 3; ++l) p_ref[l] = (int)std::min<int64_t>(h->m, h->ranks[l] + h->ranks[l] / 8 + 16);
@@ -1082,13 +1101,13 @@ rhosvd_status rhosvd_get(rhosvd_handle h, double* Z1, double* Z2, double* Z3, vo
     if (report) {
         // tails at the ranks need one small read; only done when a report is requested
         double tl[3] = {0, 0, 0};
+        // (a mode cut to rank 0 discards its whole tail, tails[0])
         for (int l = 0; l < 3; ++l)
-            if (h->ranks[l] > 0)
-                CK(h, hipMemcpyAsync(h->hostd + 4 + l, h->tails[l] + h->ranks[l], 8, hipMemcpyDeviceToHost, st));
+            CK(h, hipMemcpyAsync(h->hostd + 4 + l, h->tails[l] + h->ranks[l], 8, hipMemcpyDeviceToHost, st));
         CK(h, hipMemcpyAsync(h->host + 8, h->flags + 2, sizeof(int), hipMemcpyDeviceToHost, st));
         CK(h, hipStreamSynchronize(st));
         if (h->host[8]) return fail(h, RHOSVD_ERR_DEVICE, "eigensolver: a cross-workgroup wait ran out");
-        for (int l = 0; l < 3; ++l) tl[l] = h->ranks[l] > 0 ? h->hostd[4 + l] : 0.0;
+        for (int l = 0; l < 3; ++l) tl[l] = h->hostd[4 + l];
         memset(report, 0, sizeof(*report));
         report->xi_norm = h->xi_norm;
         report->a_norm = h->a_norm;
@@ -1098,7 +1117,7 @@ rhosvd_status rhosvd_get(rhosvd_handle h, double* Z1, double* Z2, double* Z3, vo
             report->ranks[l] = h->ranks[l];
         }
         report->bound = h->xi_norm * (tl[0] + tl[1] + tl[2]);
-        report->m = (int)h->m;
+        report->m = (int)std::min(h->n, h->R);
         report->eig_sweeps = h->sweeps;
         report->dropped = h->dropped;
         report->certificate = cert ? h->hostd[8] : -1.0;
@@ -1121,7 +1140,9 @@ rhosvd_status rhosvd_get_spectrum(rhosvd_handle h, int32_t l, double* sigma_all)
     if (!h) return RHOSVD_ERR_ARG;
     if (!h->have) return fail(h, RHOSVD_ERR_STATE, "no successful rhosvd_reduce on this handle");
     if (l < 0 || l > 2 || !sigma_all) return fail(h, RHOSVD_ERR_ARG, "mode must be 0..2, pointer non-null");
-    CK(h, hipMemcpyAsync(sigma_all, h->sigma[l], (size_t)h->m * 8, hipMemcpyDeviceToDevice, h->stream));
+    // min(n, R) values (the n-side re-run of R < n has n, the rest rounding noise)
+    CK(h, hipMemcpyAsync(sigma_all, h->sigma[l], (size_t)std::min(h->n, h->R) * 8, hipMemcpyDeviceToDevice,
+                         h->stream));
     return RHOSVD_OK;
 }
 

@@ -252,10 +252,11 @@ class Reducer:
         self.close()
         return False
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # during interpreter teardown the HIP runtime may already be gone: the
         # atexit hook has closed every handle by then, so nothing is left to do
-        if sys.is_finalizing():
+        # (module globals may already be None then, hence the bound default)
+        if _finalizing() or not self.h:
             return
         try:
             self.close()

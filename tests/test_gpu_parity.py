@@ -253,7 +253,10 @@ def test_full_size_newton1024_mixed(orc, prec):
 
 @pytest.mark.parametrize("refine", [1, 2, "auto"])
 @pytest.mark.parametrize("prec,shape", [("fp64", (512, 1024, 1e-5)), ("fp32", (512, 1024, 1e-5)),
-                                        ("fp64", (256, 2048, 1e-6)), ("fp32", (512, 2048, 1e-6))])
+                                        ("fp64", (256, 2048, 1e-6)), ("fp32", (512, 2048, 1e-6)),
+                                        # R < n: the R-side Gram, re-run on the n side to refine
+                                        ("fp64", (512, 382, 1e-6, 10_007, 44)),
+                                        ("fp32", (1024, 455, 1e-6, 10_007, 125))])
 def test_refined_tails_recover_the_oracle_ranks(orc, prec, shape, refine):
     """Smooth low-rank inputs: where the sum of the Gram route's noise eigenvalues
     (about u |G| each) exceeds tau^2 its ranks come out above the oracle's; with
@@ -261,11 +264,14 @@ def test_refined_tails_recover_the_oracle_ranks(orc, prec, shape, refine):
     on the oracle's ranks, with orthonormal Z, beta the exact core of Z and the
     error within the bound.  (Below tau^2 ~ u |G| itself the Gram route's vectors
     near the cut are inaccurate and no refinement of its cut can recover them;
-    refine_tails = 2, the deflated second pass, is meant for that case.)"""
+    refine_tails = 2, the deflated second pass, is meant for that case.)  With
+    R < n the refinement runs on the n x n Gram (refine_used + 4)."""
     import torch
     from paper_2201_12663_amd import rhosvd
-    n, R, eps = shape
-    a, c, xi = inputs.smooth_problem_params(9, 0, n, R)
+    n, R, eps = shape[:3]
+    seed, index = shape[3:] if len(shape) > 3 else (9, 0)
+    _flush(f"refined tails {prec} n={n} R={R} eps={eps} refine={refine}")
+    a, c, xi = inputs.smooth_problem_params(seed, index, n, R)
     ci = inputs.CanonicalInput(inputs.gaussian_side_matrices(inputs.grid(n), a, c), xi, eps)
     o = orc.rhosvd(ci.U, ci.xi, ci.eps, with_core=False)
     U = [rhosvd.to_device(u) for u in ci.U]
@@ -283,9 +289,11 @@ def test_refined_tails_recover_the_oracle_ranks(orc, prec, shape, refine):
         # pass when tau^2 is in the band too; elsewhere it keeps the plain cut
         used = res.report["refine_used"]
         if any(rp[l] > o.ranks[l] + 2 for l in range(3)):
-            assert used in (1, 2)
+            assert used & 3 in (1, 2)
         if used == 0:
             assert tuple(rr) == tuple(rp)
+    if R < n and refine != "auto":
+        assert res.report["refine_used"] == refine + 4
     for l in range(3):
         assert abs(rr[l] - o.ranks[l]) <= 2, (rr, o.ranks)
         assert rr[l] <= rp[l]
@@ -327,7 +335,7 @@ def test_refined_tails_keep_accurate_gram_ranks(orc):
 def test_deflated_pass_on_rank_one_and_on_the_r_side(orc):
     """refine_tails = 2 edge cases: a rank-1 tensor (k = 0, nothing deflated, the
     second pass repeats the first: same ranks and Z), and R < n, where the option
-    acts as refine_tails = 1."""
+    re-runs on the n x n Gram with either choice."""
     import torch
     from paper_2201_12663_amd import rhosvd
     rng = np.random.default_rng(41)
@@ -359,12 +367,18 @@ def test_deflated_pass_on_rank_one_and_on_the_r_side(orc):
         r = red.reduce(Ud[0], Ud[1], Ud[2], torch.from_numpy(ci.xi).cuda(), ci.eps)
         res = red.get()
         torch.cuda.synchronize()
-        got[refine] = (tuple(r), [z.cpu().numpy() for z in res.Z], res.beta.cpu().numpy())
+        got[refine] = (tuple(r), [z.cpu().numpy() for z in res.Z], res.beta.cpu().numpy(), res.report)
         red.close()
-    assert got[1][0] == got[2][0]
-    for l in range(3):
-        assert np.array_equal(got[1][1][l], got[2][1][l])
-    assert np.array_equal(got[1][2], got[2][2])
+    o = orc.rhosvd(ci.U, ci.xi, ci.eps, with_core=False)
+    Ut, xip, _, _ = orc.normalize(ci.U, ci.xi)
+    for refine in (1, 2):
+        r, Z, beta, rep = got[refine]
+        assert rep["refine_used"] == refine + 4 and rep["m"] == 120
+        assert all(abs(r[l] - o.ranks[l]) <= 2 for l in range(3)), (r, o.ranks)
+        for l in range(3):
+            assert np.max(np.abs(Z[l].T @ Z[l] - np.eye(r[l]))) <= 1e-12
+        assert orc.error_gram(Ut, xip, Z) <= rep["bound"] * (1 + 1e-9)
+        assert rep["bound"] <= ci.eps * o.a_norm * (1 + 1e-9)
 
 
 def test_refine_tails_values_are_checked():
