@@ -1,12 +1,12 @@
 // a3: FP64 symmetric eigensolver for the Gram matrices.
 //
 //   1. Householder tridiagonalization G = H T H^T (H = H_0 ... H_{m-3}),
-//      one cooperative kernel: the columns of each matrix live in the LDS of
-//      a group of workgroups (a fixed slab per workgroup); per column, the owner
-//      forms the reflector, every workgroup computes its part of p = tau G v,
-//      then applies the rank-2 update G -= v w^T + w v^T to its own slab.  Per
-//      column, v is broadcast and p all-gathered through flag-tagged words;
-//      nothing else travels through memory.
+//      one cooperative kernel: the columns of each matrix live in the
+//      registers of a group of workgroups (at most 16 columns per workgroup);
+//      per column, the owner forms the reflector, every workgroup computes its
+//      part of p = tau G v, then applies the rank-2 update G -= v w^T + w v^T
+//      to its own columns.  Per column, v is broadcast and p all-gathered
+//      through flag-tagged words; nothing else travels through memory.
 //   2. Divide and conquer on T (Cuppen): T is split recursively into blocks of
 //      at most 32 (the coupling b = e_mid is removed as T = diag(T1, T2) +
 //      b u u^T); leaves are diagonalized by a parallel Jacobi in one
@@ -33,7 +33,7 @@ namespace {
 constexpr double U64 = 1.1102230246251565e-16;
 constexpr int LEAF = 32;
 constexpr int MAXN = 2048;
-constexpr int CMAX = 32;   // columns per workgroup in the tridiagonalization
+constexpr int TCOL = 16;   // columns per workgroup in the tridiagonalization (in registers)
 
 __device__ double block_sum256(double v, double* red) {
     v = wave_sum(v);
@@ -140,89 +140,67 @@ __device__ __forceinline__ uint64_t* xtau(const TriMat& M, int par) {
     return M.x + (size_t)8 * ((M.m + 63) & ~63) + 2 * par;
 }
 
-// reflector k from the (current) column k held in LDS: v (rows k+1..m-1,
-// v[k+1] = 1) and tau are sent for step k; G[:, k], tau, e_k = beta and d_k are
-// stored for the later kernels.
-__device__ void form_reflector(const double* x, int k, const TriMat& M, double* red) {
-    const int t = threadIdx.x, m = M.m;
-    double s = 0.0;
-    for (int i = k + 2 + t; i < m; i += 256) s += x[i] * x[i];
-    s = block_sum256(s, red);
-    const double alpha = x[k + 1];
-    double tau, beta, scal;
-    if (s == 0.0) {
-        tau = 0.0; beta = alpha; scal = 0.0;
-    } else {
-        const double nrm = sqrt(alpha * alpha + s);
-        beta = alpha >= 0.0 ? -nrm : nrm;
-        tau = (beta - alpha) / beta;
-        scal = 1.0 / (alpha - beta);
-    }
-    const uint32_t flag = (uint32_t)k + 1;
-    uint64_t* vx = xv(M, k & 1);
-    for (int i = k + 1 + t; i < m; i += 256) {
-        const double v = (i == k + 1) ? 1.0 : x[i] * scal;
-        ll_put(vx + 2 * i, v, flag);
-        M.G[i + (int64_t)k * M.ld] = v;
-    }
-    if (t == 0) {
-        ll_put(xtau(M, k & 1), tau, flag);
-        M.tau[k] = tau;
-        M.e[k] = beta;
-        M.d[k] = x[k];
-    }
+// Block sum over NT threads (4 or 8 waves), added in a fixed order, so that every
+// workgroup that sums the same values gets the same result.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    constexpr int NW = NT / 64;
+    static_assert(NW == 4 || NW == 8, "4 or 8 waves");
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double s = (red[0] + red[1]) + (red[2] + red[3]);
+    if constexpr (NW == 8) s += (red[4] + red[5]) + (red[6] + red[7]);
+    __syncthreads();
+    return s;
 }
 
-// Sums of 32 values across the wave at once: five halving butterfly steps
+// Sums of 16 values across the wave at once: four halving butterfly steps
 // (each lane keeps half of its values and adds its partner's copy of that
-// half) and a last pairwise add.  Lane l ends with the wave total of value
-// l >> 1.  32 shuffles instead of 32 separate 6-step reductions.
-__device__ __forceinline__ double wave_sum32(const double (&a)[32], int lane) {
-    double b16[16], b8[8], b4[4], b2[2];
+// half) and two last pairwise adds.  Lane l ends with the wave total of value
+// l >> 2.  18 shuffles instead of 16 separate 6-step reductions.
+__device__ __forceinline__ double wave_sum16(const double (&a)[16], int lane) {
+    double b8[8], b4[4], b2[2];
     {
         const bool h = lane & 32;
 #pragma unroll
-        for (int j = 0; j < 16; ++j)
-            b16[j] = (h ? a[j + 16] : a[j]) + __shfl_xor(h ? a[j] : a[j + 16], 32, WAVE);
+        for (int j = 0; j < 8; ++j) b8[j] = (h ? a[j + 8] : a[j]) + __shfl_xor(h ? a[j] : a[j + 8], 32, WAVE);
     }
     {
         const bool h = lane & 16;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) b8[j] = (h ? b16[j + 8] : b16[j]) + __shfl_xor(h ? b16[j] : b16[j + 8], 16, WAVE);
+        for (int j = 0; j < 4; ++j) b4[j] = (h ? b8[j + 4] : b8[j]) + __shfl_xor(h ? b8[j] : b8[j + 4], 16, WAVE);
     }
     {
         const bool h = lane & 8;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) b4[j] = (h ? b8[j + 4] : b8[j]) + __shfl_xor(h ? b8[j] : b8[j + 4], 8, WAVE);
+        for (int j = 0; j < 2; ++j) b2[j] = (h ? b4[j + 2] : b4[j]) + __shfl_xor(h ? b4[j] : b4[j + 2], 8, WAVE);
     }
-    {
-        const bool h = lane & 4;
-#pragma unroll
-        for (int j = 0; j < 2; ++j) b2[j] = (h ? b4[j + 2] : b4[j]) + __shfl_xor(h ? b4[j] : b4[j + 2], 4, WAVE);
-    }
-    const bool h = lane & 2;
-    const double b1 = (h ? b2[1] : b2[0]) + __shfl_xor(h ? b2[0] : b2[1], 2, WAVE);
+    const bool h = lane & 4;
+    double b1 = (h ? b2[1] : b2[0]) + __shfl_xor(h ? b2[0] : b2[1], 4, WAVE);
+    b1 += __shfl_xor(b1, 2, WAVE);
     return b1 + __shfl_xor(b1, 1, WAVE);
 }
 
-// The owner of column k+1 at step k: applies the step's update to that column
-// (fixed row map, rows t + 256 q), accumulating the squares below row k+2 in
-// the same pass, then forms reflector k+1 from it and sends v_{k+1}, tau_{k+1}.
-template <int RPT>
-__device__ __forceinline__ void owner_step(double* col, int k, const TriMat& M, double* red, const double (&vr)[RPT],
-                                           const double (&wr)[RPT], double wc, double vc) {
-    const int t = threadIdx.x, m = M.m, j = k + 1;
-    double x[RPT], s = 0.0;
+// Reflector j from column j (this thread's rows t + NT q in x, already updated
+// by every step before j): v (rows j+1..m-1, v[j+1] = 1) and tau are sent for
+// step j; G[:, j] below the diagonal, tau_j, e_j = beta and d_j are stored for
+// the later kernels.  bc: one shared word for the broadcast of x[j+1].
+template <int RPT, int NT>
+__device__ __forceinline__ void send_reflector(const double (&x)[RPT], int j, const TriMat& M, double* red,
+                                               double* bc) {
+    const int t = threadIdx.x, m = M.m;
+    double s = 0.0;
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-        const int i = t + 256 * q;
-        x[q] = col[i] - (vr[q] * wc + wr[q] * vc);
-        col[i] = x[q];
+        const int i = t + NT * q;
         if (i > j + 1 && i < m) s += x[q] * x[q];
+        if (i == j + 1) bc[0] = x[q];
+        if (i == j) M.d[j] = x[q];
     }
-    s = block_sum256(s, red);   // its barriers make col[j], col[j+1] visible
-    if (j + 2 >= m) return;      // no reflector follows (last 2 x 2 block)
-    const double alpha = col[j + 1];
+    s = block_sum<NT>(s, red);   // its barriers publish bc[0]
+    const double alpha = bc[0];
     double tau, beta, scal;
     if (s == 0.0) {
         tau = 0.0; beta = alpha; scal = 0.0;
@@ -236,7 +214,7 @@ __device__ __forceinline__ void owner_step(double* col, int k, const TriMat& M, 
     uint64_t* vx = xv(M, j & 1);
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-        const int i = t + 256 * q;
+        const int i = t + NT * q;
         if (i > j && i < m) {
             const double v = (i == j + 1) ? 1.0 : x[q] * scal;
             ll_put(vx + 2 * i, v, flag);
@@ -247,7 +225,6 @@ __device__ __forceinline__ void owner_step(double* col, int k, const TriMat& M, 
         ll_put(xtau(M, j & 1), tau, flag);
         M.tau[j] = tau;
         M.e[j] = beta;
-        M.d[j] = col[j];
     }
 }
 
@@ -255,19 +232,20 @@ __device__ __forceinline__ void owner_step(double* col, int k, const TriMat& M, 
 // step k broadcasts v_k, every block forms p_j = tau (G v)_j for its columns,
 // the p_j and the per-block sums of p_j v_j are all-gathered, and each block
 // applies G <- G - v w^T - w v^T with w = p - (tau/2)(p.v) v to its columns.
-// The owner of column k+1 updates it first and forms reflector k+1.
-// Thread t holds rows t + 256 q, q < RPT, of every vector and LDS column; each
-// column is stored with RPT * 256 rows (rows >= m are zero), and v_k and w_k
-// are zero on rows <= k, so the row loops need no bounds: an update or dot
-// product over all RPT * 256 rows touches only the live part.
-template <int RPT>
-__global__ __launch_bounds__(256) void k_tridiag(TriArgs a) {
-    constexpr int S = RPT * 256;       // stored rows per column
-    extern __shared__ double slab[];   // cpb (< CMAX) columns x S
-    __shared__ double red[4];
-    __shared__ double red2[CMAX * 4];
-    __shared__ double vjs[CMAX], wjs[CMAX], pjs[CMAX];
-    static_assert(CMAX == 32, "one butterfly reduction covers the (at most 31) columns");
+// The owner of column k+1 then forms reflector k+1 from it and sends it.
+// Each block keeps its (at most TCOL) columns in registers: thread t holds rows
+// t + NT q, q < RPT, of every column and vector, so neither the dot products
+// nor the updates touch memory; rows >= m are zero, v_k and w_k are zero on
+// rows <= k, and a column that is not live takes a zero update, so the loops
+// run over every register column without bounds or branches.
+template <int RPT, int NT>
+__global__ __launch_bounds__(NT) void k_tridiag(TriArgs a) {
+    constexpr int NW = NT / 64;
+    __shared__ double red[NW];
+    __shared__ double red2[TCOL * NW];
+    __shared__ double vjs[TCOL], wjs[TCOL], pjs[TCOL];
+    __shared__ double bc[1];
+    static_assert(TCOL == 16, "one butterfly reduction covers the columns");
     int q0 = 0;
     while (q0 + 1 < a.nmat && (int)blockIdx.x >= a.mat[q0 + 1].blk0) ++q0;
     const TriMat& M = a.mat[q0];
@@ -277,10 +255,15 @@ __global__ __launch_bounds__(256) void k_tridiag(TriArgs a) {
     const int c0 = gb * cpb;
     const int nc = max(0, min(cpb, m - c0));
     const int t = threadIdx.x, lane = t & 63;
-    for (int c = 0; c < nc; ++c)
-        for (int i = t; i < S; i += 256) slab[c * S + i] = (i < m) ? M.G[i + (int64_t)(c0 + c) * ld] : 0.0;
-    __syncthreads();
-    if (m > 2 && c0 == 0 && nc > 0) form_reflector(slab, 0, M, red);
+    double C[TCOL][RPT];
+#pragma unroll
+    for (int c = 0; c < TCOL; ++c)
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int i = t + NT * q;
+            C[c][q] = (c < nc && i < m) ? M.G[i + (int64_t)(c0 + c) * ld] : 0.0;
+        }
+    if (m > 2 && c0 == 0 && nc > 0) send_reflector<RPT, NT>(C[0], 0, M, red, bc);
     for (int k = 0; k + 2 < m; ++k) {
         // every own column is final (none > k): leave
         if (c0 + nc <= k + 1) break;
@@ -294,7 +277,7 @@ __global__ __launch_bounds__(256) void k_tridiag(TriArgs a) {
             double val[RPT + 1];
 #pragma unroll
             for (int q = 0; q < RPT; ++q) {
-                const int i = t + 256 * q;
+                const int i = t + NT * q;
                 w[q] = (i > k && i < m) ? xv(M, par) + 2 * i : nullptr;
                 val[q] = 0.0;
             }
@@ -302,106 +285,115 @@ __global__ __launch_bounds__(256) void k_tridiag(TriArgs a) {
             ll_get<RPT + 1>(w, val, flag, a.abort_w);
 #pragma unroll
             for (int q = 0; q < RPT; ++q) {
-                const int i = t + 256 * q;
+                const int i = t + NT * q;
                 vr[q] = val[q];
                 if (i >= c0 && i < c0 + nc) vjs[i - c0] = vr[q];
             }
             tau = val[RPT];
         }
-        __syncthreads();   // vjs
         const int cs = max(0, k + 1 - c0);   // first local column with j > k
         const int cn = k + 1 - c0;           // local index of column k+1
-        {
-            // p_j = tau sum_i G[i,j] v_i for own columns j > k (exchanged even when
-            // tau = 0: the all-gather of p orders the reuse of the step buffers)
-            double acc[CMAX];
-            acc[CMAX - 1] = 0.0;
+        // p_j = tau sum_i G[i,j] v_i for own columns j > k (exchanged even when
+        // tau = 0: the all-gather of p orders the reuse of the step buffers)
+        double acc[TCOL];
 #pragma unroll
-            for (int c = 0; c < CMAX - 1; ++c) {
-                acc[c] = 0.0;
-                if (c >= cs && c < nc) {
+        for (int c = 0; c < TCOL; ++c) {
+            acc[c] = 0.0;
 #pragma unroll
-                    for (int q = 0; q < RPT; ++q) acc[c] += slab[c * S + t + 256 * q] * vr[q];
-                }
-            }
-            const double sw = wave_sum32(acc, lane);   // lane l: slot l >> 1
-            if ((lane & 1) == 0) red2[(lane >> 1) * 4 + (t >> 6)] = sw;
-            __syncthreads();
-            if (t < nc && t >= cs) {
-                const double pj = tau * ((red2[t * 4] + red2[t * 4 + 1]) + (red2[t * 4 + 2] + red2[t * 4 + 3]));
-                ll_put(xp(M, par) + 2 * (c0 + t), pj, flag);
-                pjs[t] = pj;
-            }
-            // receive p (this thread's rows > k)
-            double pr[RPT], partial = 0.0;
-            {
-                const uint64_t* w[RPT];
-                double val[RPT];
-#pragma unroll
-                for (int q = 0; q < RPT; ++q) {
-                    const int i = t + 256 * q;
-                    w[q] = (i > k && i < m) ? xp(M, par) + 2 * i : nullptr;
-                    val[q] = 0.0;
-                }
-                ll_get<RPT>(w, val, flag, a.abort_w);
-#pragma unroll
-                for (int q = 0; q < RPT; ++q) {
-                    pr[q] = val[q];
-                    partial += pr[q] * vr[q];
-                }
-            }
-            // p.v over all rows, by the same threads in the same order in every
-            // workgroup of the matrix, so the sum does not depend on how the
-            // columns are split among workgroups (and needs no exchange of its own)
-            const double cw = 0.5 * tau * block_sum256(partial, red);
-            if (t >= cs && t < nc) wjs[t] = pjs[t] - cw * vjs[t];
-            __syncthreads();
-            double wr[RPT];
-#pragma unroll
-            for (int q = 0; q < RPT; ++q) wr[q] = pr[q] - cw * vr[q];
-            int cfirst = cs;
-            if (cn >= 0 && cn < nc) {
-                owner_step<RPT>(slab + cn * S, k, M, red, vr, wr, wjs[cn], vjs[cn]);
-                cfirst = cn + 1;
-            }
-#pragma unroll
-            for (int c = 0; c < CMAX; ++c)
-                if (c >= cfirst && c < nc) {
-                    const double wc = wjs[c], vc = vjs[c];
-#pragma unroll
-                    for (int q = 0; q < RPT; ++q) slab[c * S + t + 256 * q] -= vr[q] * wc + wr[q] * vc;
-                }
+            for (int q = 0; q < RPT; ++q) acc[c] += C[c][q] * vr[q];
         }
+        const double sw = wave_sum16(acc, lane);   // lane l: column l >> 2
+        if ((lane & 3) == 0) red2[(lane >> 2) * NW + (t >> 6)] = sw;
+        __syncthreads();   // red2, vjs
+        if (t < nc && t >= cs) {
+            double sp = (red2[t * NW] + red2[t * NW + 1]) + (red2[t * NW + 2] + red2[t * NW + 3]);
+            if constexpr (NW == 8)
+                sp += (red2[t * NW + 4] + red2[t * NW + 5]) + (red2[t * NW + 6] + red2[t * NW + 7]);
+            const double pj = tau * sp;
+            ll_put(xp(M, par) + 2 * (c0 + t), pj, flag);
+            pjs[t] = pj;
+        }
+        // receive p (this thread's rows > k)
+        double pr[RPT], partial = 0.0;
+        {
+            const uint64_t* w[RPT];
+            double val[RPT];
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int i = t + NT * q;
+                w[q] = (i > k && i < m) ? xp(M, par) + 2 * i : nullptr;
+                val[q] = 0.0;
+            }
+            ll_get<RPT>(w, val, flag, a.abort_w);
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                pr[q] = val[q];
+                partial += pr[q] * vr[q];
+            }
+        }
+        // p.v over all rows, by the same threads in the same order in every
+        // workgroup of the matrix, so the sum does not depend on how the
+        // columns are split among workgroups (and needs no exchange of its own)
+        const double cw = 0.5 * tau * block_sum<NT>(partial, red);
+        if (t >= cs && t < nc) wjs[t] = pjs[t] - cw * vjs[t];
         __syncthreads();
+        double wr[RPT];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) wr[q] = pr[q] - cw * vr[q];
+        // the owner's column k+1 first, then its reflector goes out; then the rest
+        if (cn >= 0 && cn < nc) {
+            const double wc = wjs[cn], vc = vjs[cn];
+            double x[RPT] = {};
+#pragma unroll
+            for (int c = 0; c < TCOL; ++c)
+                if (c == cn) {
+#pragma unroll
+                    for (int q = 0; q < RPT; ++q) {
+                        C[c][q] -= vr[q] * wc + wr[q] * vc;
+                        x[q] = C[c][q];
+                    }
+                }
+            if (k + 3 < m) send_reflector<RPT, NT>(x, k + 1, M, red, bc);
+        }
+#pragma unroll
+        for (int c = 0; c < TCOL; ++c) {
+            const bool live = c > cn && c >= cs && c < nc;
+            const double wc = live ? wjs[c] : 0.0, vc = live ? vjs[c] : 0.0;
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) C[c][q] -= vr[q] * wc + wr[q] * vc;
+        }
+        __syncthreads();   // vjs, wjs, pjs are rewritten next step
     }
-    // the last 2 x 2 block
-    for (int c = 0; c < nc; ++c) {
+    // the last 2 x 2 block (and T itself when m <= 2), from the registers
+#pragma unroll
+    for (int c = 0; c < TCOL; ++c) {
         const int j = c0 + c;
-        if (t == 0) {
-            if (j == m - 2 || (m == 1 && j == 0)) M.d[j] = slab[c * S + j];
-            if (j == m - 1) M.d[j] = slab[c * S + j];
-            if (j == m - 2) M.e[j] = slab[c * S + j + 1];
+        if (c < nc && j >= m - 2) {
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int i = t + NT * q;
+                if (i == j) M.d[j] = C[c][q];
+                if (j == m - 2 && i == j + 1) M.e[j] = C[c][q];
+            }
         }
     }
 }
 
-// rows per thread of the launch: the smallest RPT with 256 RPT >= m (1..8).
-// Every RPT has its own instance, so a column of m rows occupies 256 RPT rows of
-// LDS and no more (m = 1100: 1280 rows, 14 columns per workgroup, where the next
-// power of two would store 2048 rows and fit 9)
-static int tri_rpt(int m) { return std::max(1, (m + 255) / 256); }
+// rows per thread and threads per workgroup: 256 threads up to m = 1024, 512
+// beyond, and the smallest RPT with NT RPT >= m (1..4)
+static int tri_nt(int m) { return m <= 1024 ? 256 : 512; }
+static int tri_rpt(int m) { return std::max(1, (m + tri_nt(m) - 1) / tri_nt(m)); }
 
-static const void* tri_kernel(int rpt) {
-    switch (rpt) {
-        case 1: return (const void*)k_tridiag<1>;
-        case 2: return (const void*)k_tridiag<2>;
-        case 3: return (const void*)k_tridiag<3>;
-        case 4: return (const void*)k_tridiag<4>;
-        case 5: return (const void*)k_tridiag<5>;
-        case 6: return (const void*)k_tridiag<6>;
-        case 7: return (const void*)k_tridiag<7>;
-        default: return (const void*)k_tridiag<8>;
+static const void* tri_kernel(int rpt, int nt) {
+    if (nt == 256) {
+        switch (rpt) {
+            case 1: return (const void*)k_tridiag<1, 256>;
+            case 2: return (const void*)k_tridiag<2, 256>;
+            case 3: return (const void*)k_tridiag<3, 256>;
+            default: return (const void*)k_tridiag<4, 256>;
+        }
     }
+    return rpt <= 3 ? (const void*)k_tridiag<3, 512> : (const void*)k_tridiag<4, 512>;
 }
 
 __global__ void k_zero_words(uint64_t* p, size_t n) {
@@ -1183,9 +1175,8 @@ struct EigPlan {
     // tridiagonalization
     struct TriLaunch {
         std::vector<int> mats;   // indices into mats
-        int cpb;                 // columns per workgroup (set by the largest m of the launch)
-        int rpt;                 // rows per thread (set by the largest m of the launch)
-        size_t shbytes;
+        int cpb;                 // columns per workgroup (at most TCOL)
+        int rpt, nt;             // rows per thread, threads per workgroup (set by the largest m of the launch)
         int nblocks;
         TriArgs args;
     };
@@ -1205,24 +1196,17 @@ struct EigPlan {
     char* work = nullptr;
 };
 
-static int tri_cpb(int m, int maxsh) {
-    const int mr = 256 * tri_rpt(m);   // stored rows per column
-    int cpb = (int)((maxsh - 8192) / ((size_t)mr * 8));
-    return std::max(1, std::min(cpb, CMAX - 1));
-}
-
 EigPlan* eig_plan_create(const EigMat* mats, int nmat, size_t* work_bytes) {
     if (nmat < 1) return nullptr;
     for (int i = 0; i < nmat; ++i)
         if (mats[i].m < 1 || mats[i].m > MAXN || mats[i].ld < mats[i].m) return nullptr;
-    int dev = 0, ncu = 0, maxsh = 0;
+    int dev = 0, ncu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return nullptr;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return nullptr;
-    if (hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return nullptr;
     EigPlan* P = new EigPlan();
     P->mats.assign(mats, mats + nmat);
     // ---- tridiagonalization: largest matrices first, packed while every block of
-    // a launch can be resident at once (occupancy of the launch's LDS size)
+    // a launch can be resident at once (occupancy of the kernel's registers)
     std::vector<int> ord(nmat);
     for (int i = 0; i < nmat; ++i) ord[i] = i;
     std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return mats[x].m > mats[y].m; });
@@ -1235,16 +1219,15 @@ EigPlan* eig_plan_create(const EigMat* mats, int nmat, size_t* work_bytes) {
         EigPlan::TriLaunch L;
         const int m0 = mats[ord[q]].m;
         L.rpt = tri_rpt(m0);
-        const int mr = 256 * L.rpt;
-        const int cpb0 = tri_cpb(m0, maxsh);
+        L.nt = tri_nt(m0);
+        const int cpb0 = TCOL;
         L.cpb = cpb0;
-        L.shbytes = (size_t)cpb0 * mr * 8;
-        const void* kf = tri_kernel(L.rpt);
-        if (hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.shbytes) !=
-            hipSuccess) { delete P; return nullptr; }
+        const void* kf = tri_kernel(L.rpt, L.nt);
         int occ = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kf, 256, L.shbytes) != hipSuccess ||
-            occ < 1) { delete P; return nullptr; }
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kf, L.nt, 0) != hipSuccess || occ < 1) {
+            delete P;
+            return nullptr;
+        }
         const int cap = occ * ncu;
         int blocks = 0;
         while (q < ord.size() && (int)L.mats.size() < TRI_MAXMAT) {
@@ -1258,9 +1241,9 @@ EigPlan* eig_plan_create(const EigMat* mats, int nmat, size_t* work_bytes) {
             ++q;
         }
         // fewer columns per workgroup while every workgroup of the launch still
-        // has a CU of its own: each column step then reads and updates fewer
-        // columns per CU (three m = 1024 matrices: 19 -> 13 columns, 162 -> 237
-        // workgroups); two workgroups sharing a CU would serialize their steps
+        // has a CU of its own: each column step then updates fewer columns per
+        // CU (three m = 1024 matrices: 16 -> 13 columns, 192 -> 237 workgroups);
+        // two workgroups sharing a CU would serialize their steps
         for (int c = cpb0 - 1; c >= 1; --c) {
             int nb = 0, most = 0;
             for (int i : L.mats) {
@@ -1272,7 +1255,6 @@ EigPlan* eig_plan_create(const EigMat* mats, int nmat, size_t* work_bytes) {
             L.cpb = c;
             blocks = nb;
         }
-        L.shbytes = (size_t)L.cpb * mr * 8;
         L.nblocks = blocks;
         P->tri.push_back(L);
     }
@@ -1362,26 +1344,13 @@ hipError_t eig_plan_enqueue(const EigPlan* P, int* abort_w, hipStream_t st, bool
     for (const auto& L : P->tri) {
         TriArgs ta = L.args;
         ta.abort_w = abort_w;
-        const void* kf = tri_kernel(L.rpt);
-        if ((e = hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.shbytes)) != hipSuccess)
-            return e;
-        if (cooperative) {
-            void* args[] = {&ta};
-            if ((e = hipLaunchCooperativeKernel(kf, dim3(L.nblocks), dim3(256), args, L.shbytes, st)) != hipSuccess)
-                return e;
-        } else {
-            switch (L.rpt) {
-                case 1: hipLaunchKernelGGL(k_tridiag<1>, dim3(L.nblocks), dim3(256), L.shbytes, st, ta); break;
-                case 2: hipLaunchKernelGGL(k_tridiag<2>, dim3(L.nblocks), dim3(256), L.shbytes, st, ta); break;
-                case 3: hipLaunchKernelGGL(k_tridiag<3>, dim3(L.nblocks), dim3(256), L.shbytes, st, ta); break;
-                case 4: hipLaunchKernelGGL(k_tridiag<4>, dim3(L.nblocks), dim3(256), L.shbytes, st, ta); break;
-                case 5: hipLaunchKernelGGL(k_tridiag<5>, dim3(L.nblocks), dim3(256), L.shbytes, st, ta); break;
-                case 6: hipLaunchKernelGGL(k_tridiag<6>, dim3(L.nblocks), dim3(256), L.shbytes, st, ta); break;
-                case 7: hipLaunchKernelGGL(k_tridiag<7>, dim3(L.nblocks), dim3(256), L.shbytes, st, ta); break;
-                default: hipLaunchKernelGGL(k_tridiag<8>, dim3(L.nblocks), dim3(256), L.shbytes, st, ta); break;
-            }
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-        }
+        const void* kf = tri_kernel(L.rpt, L.nt);
+        void* args[] = {&ta};
+        if (cooperative)
+            e = hipLaunchCooperativeKernel(kf, dim3(L.nblocks), dim3(L.nt), args, 0, st);
+        else
+            e = hipLaunchKernel(kf, dim3(L.nblocks), dim3(L.nt), args, 0, st);
+        if (e != hipSuccess) return e;
     }
     // 2. divide and conquer
     const EigMat* dmats = (const EigMat*)(P->work + P->off_mats);
