@@ -62,7 +62,11 @@ def test_als_error_decreases_and_mixed_cores(orc):
     """n=256, R=1024, eps=1e-3: the exact error of the ALS factors is at most the
     RHOSVD's (and within the RHOSVD's Theorem 2.3 bound, which the report keeps);
     the FP32 path's refined factors equal the FP64 path's bit for bit (the
-    iteration runs in FP64 on both), its core within its own bound."""
+    iteration runs in FP64 on both), its core within its own bound.  After the
+    first sweep (here 39x below the RHOSVD's error) the iteration has converged
+    below what its FP64 Gram route resolves: the subspaces move within the
+    eigenvalue noise of the contracted Grams, about 64 sqrt(m) u |A|^2, so the
+    second sweep's error is bounded by that noise, not by the first's."""
     ci = inputs.batch_problem(5, 3, 256, 1024, eps=1e-3)
     g0 = gc.run_gpu(ci, "fp64", want_beta=False, anorm="exact")
     g1 = run(ci, 1)
@@ -72,7 +76,9 @@ def test_als_error_decreases_and_mixed_cores(orc):
     a = orc.anorm_gram(Ut, xip)
     e0, e1, e2 = (orc.error_gram(Ut, xip, g["Z"]) for g in (g0, g1, g2))
     flush(f"errors / |A|: RHOSVD {e0 / a:.4e}, ALS 1 sweep {e1 / a:.4e}, 2 sweeps {e2 / a:.4e}")
-    assert e1 <= e0 * (1 + 1e-9) and e2 <= e1 * (1 + 1e-9)
+    assert e1 <= e0 * (1 + 1e-9)
+    noise = 64.0 * np.sqrt(min(ci.n, ci.R)) * 2.0 ** -53 * a * a
+    assert e2 ** 2 <= e1 ** 2 * (1 + 1e-9) + noise, (e1, e2, noise)
     assert e2 <= g2["report"]["bound"] * (1 + 1e-9)
     for l in range(3):
         assert np.array_equal(g2f["Z"][l], g2["Z"][l])

@@ -554,7 +554,8 @@ def test_anorm_auto_mode_choices(orc):
     (its flops well under the identity's 3 n R^2), the exact identity where the
     probe would cost more (n160 R640 here) and where heavy cancellation makes the
     probe's bracket wide (|A| ~ 1e-3 |xi'|, so b_p > L / 10).  Every result is
-    certified against the oracle's exact |A|."""
+    certified against the oracle's exact |A|; two wide cases (R = 60000, beyond
+    the oracle's reach) against the library's own exact identity."""
     for ci, want in ((smooth_wide(1, 96, 3000, 1e-6), 2),
                      (inputs.newton_centres(2, n=160, n_centres=20, eps=1e-5), 1),
                      (smooth_wide(2, 64, 2000, 1e-6, pairs=True), 1)):
@@ -568,6 +569,14 @@ def test_anorm_auto_mode_choices(orc):
         err = gc.recon_error(orc, ci, g["Z"])
         # rounding scale: |xi'| (the terms' own size), not |A|, under cancellation
         assert err <= rep["bound"] * (1 + 1e-9) + 1e-10 * o.xi_norm
+    for ci, want in ((smooth_wide(3, 64, 60000, 1e-6), 2), (smooth_wide(4, 64, 60000, 1e-6, pairs=True), 1)):
+        g = gc.run_gpu(ci, "fp64", want_beta=False)
+        ge = gc.run_gpu(ci, "fp64", want_beta=False, anorm="exact")
+        rep, rex = g["report"], ge["report"]
+        _flush(f"{ci.name}: anorm method {rep['anorm_method']} (want {want}), |A|/|xi'| {rex['a_norm'] / rex['xi_norm']:.3e}")
+        assert rep["anorm_method"] == want, ci.name
+        gc.check_anorm(rep, rex["a_norm"], rex["tau"])
+        assert rep["bound"] <= ci.eps * rex["a_norm"] * (1 + 1e-9)
     # the forced probe under heavy cancellation is still certified (its tau only smaller)
     ci = smooth_wide(2, 64, 2000, 1e-6, pairs=True)
     o = orc.rhosvd(ci.U, ci.xi, ci.eps, with_core=False)
