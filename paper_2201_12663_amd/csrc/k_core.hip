@@ -6,8 +6,9 @@
 // registers as V2[j2,nu]*V3[j3,nu].
 //
 // Workgroup tile: TM rows of j1 x 256 columns = 16 (j2) x 16 (j3); 4 waves, wave
-// w owns columns j3 in [4w, 4w+4).  K chunks are double-buffered in LDS with the
-// next chunk's global loads in flight during the current chunk's MFMAs.
+// w owns columns j3 in [4w, 4w+4).  FP64/FP32: K chunks double-buffered in LDS
+// with the next chunk's global loads in flight during the current chunk's MFMAs;
+// BF16x3: a ring of three chunks filled by direct global-to-LDS loads.
 // Tiles are assigned XCD-contiguously: block b runs on XCD b % 8, and each XCD
 // gets one contiguous range of tiles, ordered so neighbouring tiles share V1 rows.
 //
@@ -200,9 +201,9 @@ __global__ __launch_bounds__(256, 2) void k_core_std(int r1, int r2, int r3, int
 }
 
 // ---------------------------------------------------------------------------
-// BF16x3 variant, TM = 128, KC = 32.  V_l are FP32.
+// BF16x3 variant, TM = 64 or 128, KC = 32.  V_l are FP32.
 // ---------------------------------------------------------------------------
-constexpr int BKC = 32, BLDA = BKC + 8;   // bf16 elements per LDS row of A
+constexpr int BKC = 32;   // K chunk
 
 typedef float f2_t __attribute__((ext_vector_type(2)));
 typedef __bf16 b2_t __attribute__((ext_vector_type(2)));
@@ -218,57 +219,65 @@ __device__ __forceinline__ void split2(f2_t x, b2_t& hi, b2_t& lo) {
 }
 
 
+// The BF16x3 tile with its operands streamed straight from global memory into
+// LDS (global_load_lds: lane L of a wave writes its 16 bytes at the
+// instruction's LDS base + 16 L, so no registers hold them on the way) through
+// a ring of three K-chunk stages: chunk c+2 is in flight while chunk c is
+// multiplied.  Layouts (bytes within a stage), chosen so that the reads of a
+// K-chunk meet no bank conflicts:
+//   A plane (hi, lo): row r at 64 r, its 8-k group q (16 B) at slot q ^ ((r >> 2) & 3);
+//   V2, V3: k row at 64 s(k), s(k) = 4 (k & 7) + (k >> 3), so that the four k
+//   rows a wave reads together (k, k+8, k+16, k+24) form one 256-byte block.
+template <int NF>
+struct DmaStage {
+    static constexpr int TM = 16 * NF;
+    static constexpr int A_BYTES = TM * 64;              // one plane of one chunk
+    static constexpr int V_BYTES = BKC * TN2 * 4;        // V2 or V3 of one chunk (2 KB)
+    static constexpr int BYTES = 2 * A_BYTES + 2 * V_BYTES;
+    static constexpr int LOADS = TM / 32 + 1;            // global_load_lds per wave per chunk
+};
+
+typedef __attribute__((address_space(3))) void* lds_void_ptr;
+
 template <typename O, bool FLUSH, int NF>
-__device__ __forceinline__ void core_tile_bf16x3(int r1, int r2, int r3, int ld2, int ld3, int64_t Kp,
-                                 const __bf16* __restrict__ Ah, const __bf16* __restrict__ Al,
-                                 const float* __restrict__ V2, const float* __restrict__ V3,
-                                 O* __restrict__ beta, int N2T, int N3T, int64_t tile) {
-    constexpr int TM = 16 * NF;
-    constexpr int GA = TM / 64;          // 16-byte groups (8 k of one row) per thread and plane
-    // rows of s2/s3 are padded to 18 floats: the k rows that one half-wave reads
-    // (8 apart) then fall 16 banks apart
-    constexpr int VLD = TN2 + 2;
-    // s3 rows: 20 floats, so that a wave reads its 4 j3 values of a k row as one 16-byte load
-    constexpr int VLD3 = TN3 + 4;
-    __shared__ __attribute__((aligned(16))) __bf16 sAh[2][TM * BLDA];
-    __shared__ __attribute__((aligned(16))) __bf16 sAl[2][TM * BLDA];
-    __shared__ float s2[2][BKC][VLD];
-    __shared__ __attribute__((aligned(16))) float s3[2][BKC][VLD3];
+__device__ __forceinline__ void core_tile_bf16x3_dma(int r1, int r2, int r3, int ld2, int ld3, int64_t Kp,
+                                                     const __bf16* __restrict__ Ah, const __bf16* __restrict__ Al,
+                                                     const float* __restrict__ V2, const float* __restrict__ V3,
+                                                     O* __restrict__ beta, int N2T, int N3T, int64_t tile) {
+    typedef DmaStage<NF> S;
+    constexpr int TM = S::TM, NS = 3;
+    __shared__ __attribute__((aligned(1024))) char ring[NS * S::BYTES];
     const int NT = N2T * N3T;
     const int mt = (int)(tile / NT), nt = (int)(tile % NT);
     const int n3t = nt / N2T, n2t = nt % N2T;
     const int m0 = mt * TM, b2 = n2t * TN2, b3 = n3t * TN3;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t nchunk = Kp / BKC;
 
-    // staging: A TM x 32 from the hi/lo planes (rows ai + 64 g, k = ak .. ak + 7 as
-    // one 16-byte load per plane), V2/V3 32 x 16 (2 each)
-    const int ai = t >> 2, ak = (t & 3) * 8;
-    const int vi = t & 15, vk = t >> 4;            // k = vk, vk + 16
-    bf8_t rah[GA], ral[GA];
-    float rv2[2], rv3[2];
-    auto gload = [&](int64_t k0) {
+    // issue this wave's loads of chunk c into stage c % NS
+    auto issue = [&](int64_t c) {
+        char* st = ring + (int)(c % NS) * S::BYTES;
+        const int64_t k0 = c * BKC;
+        // A: 16-row blocks (1 KB each) of both planes; wave w takes blocks w, w + 4, ...
 #pragma unroll
-        for (int g = 0; g < GA; ++g) {
-            const int64_t off = (int64_t)(m0 + ai + 64 * g) * Kp + k0 + ak;
-            rah[g] = *reinterpret_cast<const bf8_t*>(Ah + off);
-            ral[g] = *reinterpret_cast<const bf8_t*>(Al + off);
+        for (int i = 0; i < TM / 32; ++i) {
+            const int blk = w + 4 * i;                    // 0 .. 2 TM / 16 - 1 over both planes
+            const int plane = blk / (TM / 16), rb = (blk % (TM / 16)) * 16;
+            const int r = rb + (lane >> 2);
+            const int q = (lane & 3) ^ ((r >> 2) & 3);
+            const __bf16* src = (plane ? Al : Ah) + (int64_t)(m0 + r) * Kp + k0 + 8 * q;
+            __builtin_amdgcn_global_load_lds((const void*)src, (lds_void_ptr)(st + plane * S::A_BYTES + rb * 64), 16,
+                                             0, 0);
         }
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            rv2[q] = V2[(int64_t)(b2 + vi) + (k0 + vk + 16 * q) * ld2];
-            rv3[q] = V3[(int64_t)(b3 + vi) + (k0 + vk + 16 * q) * ld3];
-        }
-    };
-    auto lstore = [&](int buf) {
-#pragma unroll
-        for (int g = 0; g < GA; ++g) {
-            *reinterpret_cast<bf8_t*>(&sAh[buf][(ai + 64 * g) * BLDA + ak]) = rah[g];
-            *reinterpret_cast<bf8_t*>(&sAl[buf][(ai + 64 * g) * BLDA + ak]) = ral[g];
-        }
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            s2[buf][vk + 16 * q][vi] = rv2[q];
-            s3[buf][vk + 16 * q][vi] = rv3[q];
+        // V2 (waves 0, 1) and V3 (waves 2, 3): 16 k rows per instruction
+        {
+            const int half = w & 1;
+            const int s = 16 * half + (lane >> 2);
+            const int k = 8 * (s & 3) + (s >> 2);
+            const float* src = (w < 2) ? V2 + (int64_t)(b2 + 4 * (lane & 3)) + (k0 + k) * ld2
+                                       : V3 + (int64_t)(b3 + 4 * (lane & 3)) + (k0 + k) * ld3;
+            char* dst = st + 2 * S::A_BYTES + (w < 2 ? 0 : S::V_BYTES) + half * 1024;
+            __builtin_amdgcn_global_load_lds((const void*)src, (lds_void_ptr)dst, 16, 0, 0);
         }
     };
 
@@ -277,26 +286,36 @@ __device__ __forceinline__ void core_tile_bf16x3(int r1, int r2, int r3, int ld2
     for (int f = 0; f < NF; ++f)
 #pragma unroll
         for (int g = 0; g < 4; ++g) acc[f][g] = f4_t{0.f, 0.f, 0.f, 0.f};
-
-    constexpr int64_t FL = KFLUSH / BKC;   // chunks between hand-overs
+    constexpr int64_t FL = KFLUSH / BKC;
     bool first = true;
 
-    const int64_t nchunk = Kp / BKC;
-    gload(0);
-    lstore(0);
-    __syncthreads();
-    const int kg = 8 * (lane >> 4);   // this lane's 8 k indices
+    issue(0);
+    if (nchunk > 1) issue(1);
+    const int kq = lane >> 4, kg = 8 * kq;
     for (int64_t c = 0; c < nchunk; ++c) {
-        const int buf = (int)(c & 1);
-        if (c + 1 < nchunk) gload((c + 1) * BKC);
+        // chunk c has landed (this wave's loads; chunk c+1's may still fly), every
+        // wave's own LDS reads are done, then all waves meet: chunk c is visible
+        // to all and the stage of chunk c-1 is free
+        if (c + 1 < nchunk) {
+            static_assert(S::LOADS == 3 || S::LOADS == 5, "vmcnt of one chunk");
+            if constexpr (S::LOADS == 5) asm volatile("s_waitcnt vmcnt(5) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+            else asm volatile("s_waitcnt vmcnt(3) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+        } else {
+            asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+        }
+        if (c + 2 < nchunk) issue(c + 2);
+        const char* st = ring + (int)(c % NS) * S::BYTES;
+        const float* s2 = (const float*)(st + 2 * S::A_BYTES);
+        const float* s3 = (const float*)(st + 2 * S::A_BYTES + S::V_BYTES);
         // B fragments: 8 k values of column (j2 = lane%16, j3 = 4w+g), split hi/lo
         bf8_pairs bh[4], bl[4];
         float v2[8];
         f4_t v3[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            v2[e] = s2[buf][kg + e][lane & 15];
-            v3[e] = *reinterpret_cast<const f4_t*>(&s3[buf][kg + e][4 * w]);
+            const int srow = 4 * e + kq;                  // s(kg + e)
+            v2[e] = s2[srow * 16 + (lane & 15)];
+            v3[e] = *reinterpret_cast<const f4_t*>(&s3[srow * 16 + 4 * w]);
         }
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
@@ -307,8 +326,9 @@ __device__ __forceinline__ void core_tile_bf16x3(int r1, int r2, int r3, int ld2
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             const int row = 16 * f + (lane & 15);
-            const bf8_t ah = *reinterpret_cast<const bf8_t*>(&sAh[buf][row * BLDA + kg]);
-            const bf8_t al = *reinterpret_cast<const bf8_t*>(&sAl[buf][row * BLDA + kg]);
+            const int off = row * 64 + 16 * (kq ^ ((row >> 2) & 3));
+            const bf8_t ah = *reinterpret_cast<const bf8_t*>(st + off);
+            const bf8_t al = *reinterpret_cast<const bf8_t*>(st + S::A_BYTES + off);
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
                 acc[f][g] = mfma_bf16(ah, bh[g].v, acc[f][g]);
@@ -322,9 +342,10 @@ __device__ __forceinline__ void core_tile_bf16x3(int r1, int r2, int r3, int ld2
                 first = false;
             }
         }
-        if (c + 1 < nchunk) lstore(buf ^ 1);
-        __syncthreads();
     }
+    // the ring is reused by the next tile of a persistent workgroup: every wave is
+    // done reading it
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
     if constexpr (FLUSH) {
         hand_over<NF, O>(beta, r1, r2, r3, m0, b2, b3, lane, w, acc, first);
         return;
@@ -339,11 +360,13 @@ __device__ __forceinline__ void core_tile_bf16x3(int r1, int r2, int r3, int ld2
                            acc[f][g][i]);
 }
 
-// Two waves per SIMD at least: the 128-row tile then fits 256 registers (its
-// accumulators are 128 of them) with a few spills outside the K loop, instead
-// of 260 registers at one wave per SIMD; the 64-row tile drops to 165
-// registers.  The 128-row tile forms each Khatri-Rao fragment once for twice
-// the MFMAs, which is what the kernel's time follows.
+// Two waves per SIMD: the 128-row tile fits 234 registers (its accumulators are
+// 128 of them; the operands travel to LDS without registers), the 64-row tile
+// 158.  The 128-row tile forms each Khatri-Rao fragment once for twice the
+// MFMAs.  (A 256-row tile at one wave per SIMD, with its accumulators in AGPRs
+// and the next chunk's fragments formed during the current chunk's MFMAs, was
+// measured at 9.9 ms against 6.6 ms at the 1024 x 4096 workload: one wave per
+// SIMD leaves the matrix cores idle on every dependency.)
 template <typename O, bool FLUSH, int NF>
 __global__ __launch_bounds__(256, 2) void k_core_bf16x3(int r1, int r2, int r3, int ld2, int ld3, int64_t Kp,
                                                      const __bf16* __restrict__ Ah, const __bf16* __restrict__ Al,
@@ -351,8 +374,9 @@ __global__ __launch_bounds__(256, 2) void k_core_bf16x3(int r1, int r2, int r3, 
                                                      O* __restrict__ beta, int MT, int N2T, int N3T, int64_t per) {
     const int64_t tile = xcd_tile(blockIdx.x, per);
     if (tile >= (int64_t)MT * N2T * N3T) return;
-    core_tile_bf16x3<O, FLUSH, NF>(r1, r2, r3, ld2, ld3, Kp, Ah, Al, V2, V3, beta, N2T, N3T, tile);
+    core_tile_bf16x3_dma<O, FLUSH, NF>(r1, r2, r3, ld2, ld3, Kp, Ah, Al, V2, V3, beta, N2T, N3T, tile);
 }
+
 
 // ---------------------------------------------------------------------------
 // The BF16x3 core's A operand: x = V1[j1, nu] * xi'_nu (FP32, as the FP32 core
@@ -463,7 +487,7 @@ __global__ __launch_bounds__(256, PREC == 2 ? 2 : 1) void k_core_persist_b(const
             core_tile_std<float, O, FLUSH, NF>(r1, r2, r3, q.rcap_pad, q.rcap_pad, q.rcap_pad, q.R_pad, (const float*)q.V[0],
                                  (const float*)q.V[1], (const float*)q.V[2], q.xip, (O*)q.beta, N2T, N3T, local);
         else
-            core_tile_bf16x3<O, FLUSH, NF>(r1, r2, r3, q.rcap_pad, q.rcap_pad, q.R_pad, (const __bf16*)q.Asplit,
+            core_tile_bf16x3_dma<O, FLUSH, NF>(r1, r2, r3, q.rcap_pad, q.rcap_pad, q.R_pad, (const __bf16*)q.Asplit,
                              (const __bf16*)q.Asplit + (int64_t)q.rcap_pad * q.R_pad, (const float*)q.V[1],
                              (const float*)q.V[2], (O*)q.beta, N2T, N3T, local);
     }
