@@ -363,10 +363,12 @@ __device__ __forceinline__ void core_tile_bf16x3_dma(int r1, int r2, int r3, int
 // Two waves per SIMD: the 128-row tile fits 234 registers (its accumulators are
 // 128 of them; the operands travel to LDS without registers), the 64-row tile
 // 158.  The 128-row tile forms each Khatri-Rao fragment once for twice the
-// MFMAs.  (A 256-row tile at one wave per SIMD, with its accumulators in AGPRs
-// and the next chunk's fragments formed during the current chunk's MFMAs, was
-// measured at 9.9 ms against 6.6 ms at the 1024 x 4096 workload: one wave per
-// SIMD leaves the matrix cores idle on every dependency.)
+// MFMAs.  Measured at the 1024 x 4096 workload and not kept: a 256-row tile at
+// one wave per SIMD, accumulators in AGPRs, the next chunk's fragments formed
+// during the current chunk's MFMAs (9.9 ms against 6.6: one wave per SIMD leaves
+// the matrix cores idle on every dependency); a 256-row tile of 8 waves, each
+// with 2 j3 columns and all 16 row fragments, half the Khatri-Rao work per MFMA
+// for twice the A-fragment reads, one workgroup per CU (7.1 ms).
 template <typename O, bool FLUSH, int NF>
 __global__ __launch_bounds__(256, 2) void k_core_bf16x3(int r1, int r2, int r3, int ld2, int ld3, int64_t Kp,
                                                      const __bf16* __restrict__ Ah, const __bf16* __restrict__ Al,
