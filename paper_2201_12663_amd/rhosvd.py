@@ -520,6 +520,7 @@ class Reducer:
         count = len(problems)
         res = torch.zeros((count, 8), dtype=torch.int32, device="cuda")
         self.reduce_batched_raw(self.batch_descriptors(problems, res))
+        self.stream.synchronize()   # the pass runs on the handle's stream, the copy on the current one
         ranks = res.cpu().numpy()
         outs = []
         for i, (U1, _, _, _, _) in enumerate(problems):
@@ -532,6 +533,7 @@ class Reducer:
         res2 = torch.zeros((count, 8), dtype=torch.int32, device="cuda")
         desc = self.batch_descriptors(problems, res2, outputs=outs)
         self.reduce_batched_raw(desc)
+        self.stream.synchronize()
         rr = res2.cpu().numpy()
         out = []
         for i in range(count):
