@@ -10,7 +10,8 @@
 // with the next chunk's global loads in flight during the current chunk's MFMAs;
 // BF16x3: a ring of three chunks filled by direct global-to-LDS loads.
 // Tiles are assigned XCD-contiguously: block b runs on XCD b % 8, and each XCD
-// gets one contiguous range of tiles, ordered so neighbouring tiles share V1 rows.
+// gets one contiguous range of tiles, ordered so neighbouring tiles share V1 rows
+// and, in groups of 8 x 8 (j2, j3) tiles, their V2 and V3 slices.
 //
 // Variants: FP64 (v_mfma_f64_16x16x4, TM=64), FP32 (v_mfma_f32_16x16x4, TM=64)
 // and BF16x3 (v_mfma_f32_16x16x32_bf16, TM=128): a = a_hi + a_lo, b = b_hi + b_lo
@@ -29,6 +30,22 @@ constexpr int TN2 = 16, TN3 = 16;
 
 __device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t per) {
     return (bid % NXCD) * per + bid / NXCD;
+}
+
+// tile index -> (row block, j2 tile, j3 tile).  Within one row block the j2 x j3
+// tiles run in groups of GN2 j2 tiles with j3 slowest inside a group, so that the
+// workgroups one XCD holds at a time (consecutive tiles) cover a near-square block
+// of (j2, j3) tiles and share their V2 and V3 slices in that XCD's L2.
+constexpr int GN2 = 8;
+__device__ __forceinline__ void tile_coords(int64_t tile, int N2T, int N3T, int& mt, int& n2t, int& n3t) {
+    const int NT = N2T * N3T;
+    mt = (int)(tile / NT);
+    const int t = (int)(tile % NT);
+    const int g = t / (GN2 * N3T), first = g * GN2;
+    const int gs = min(N2T - first, GN2);
+    const int u = t - g * GN2 * N3T;
+    n2t = first + u % gs;
+    n3t = u / gs;
 }
 
 // beta entries are written as O: double, or float (the mixed cores' option)
@@ -106,9 +123,8 @@ __device__ __forceinline__ void core_tile_std(int r1, int r2, int r3, int ld1, i
     __shared__ T sA[2][KC][TM + 64 / sizeof(T)];
     __shared__ T s2[2][KC][TN2];
     __shared__ T s3[2][KC][TN3];
-    const int NT = N2T * N3T;
-    const int mt = (int)(tile / NT), nt = (int)(tile % NT);
-    const int n3t = nt / N2T, n2t = nt % N2T;
+    int mt, n2t, n3t;
+    tile_coords(tile, N2T, N3T, mt, n2t, n3t);
     const int m0 = mt * TM, b2 = n2t * TN2, b3 = n3t * TN3;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
 
@@ -247,9 +263,8 @@ __device__ __forceinline__ void core_tile_bf16x3_dma(int r1, int r2, int r3, int
     typedef DmaStage<NF> S;
     constexpr int TM = S::TM, NS = 3;
     __shared__ __attribute__((aligned(1024))) char ring[NS * S::BYTES];
-    const int NT = N2T * N3T;
-    const int mt = (int)(tile / NT), nt = (int)(tile % NT);
-    const int n3t = nt / N2T, n2t = nt % N2T;
+    int mt, n2t, n3t;
+    tile_coords(tile, N2T, N3T, mt, n2t, n3t);
     const int m0 = mt * TM, b2 = n2t * TN2, b3 = n3t * TN3;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int64_t nchunk = Kp / BKC;
