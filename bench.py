@@ -306,7 +306,8 @@ def bench_precision_study(args):
     FP64 core, and the certified total (Theorem 2.3 bound and core error, which
     are orthogonal).  The FP64 and BF16x3 paths run again with the deflated
     second Gram pass (refine_tails = 2), whose cut at eps = 1e-6 is the exact
-    one."""
+    one.  At eps = 1e-6 the BF16x3 precision runs the FP32 core (below the
+    split's floor, 1e-5); core_precision says which core ran."""
     import numpy as np
     import torch
     from paper_2201_12663_amd import inputs, rhosvd
@@ -329,7 +330,8 @@ def bench_precision_study(args):
                        core_tflops=round(2.0 * r1 * r2 * r3 * ci.R / (core_ms * 1e-3) / 1e12, 2),
                        phase_ms={k: round(v, 3) for k, v in avg.items()},
                        bound_rel=rep["bound"] / rep["a_norm"], refine_used=rep["refine_used"],
-                       anorm_method=rep["anorm_method"])
+                       anorm_method=rep["anorm_method"],
+                       core_precision=("fp64", "fp32", "bf16x3")[rep["core_precision"]])
             if prec == "fp64":
                 b64[refine] = beta
             elif refine in b64 and b64[refine].numel() == beta.numel():

@@ -54,14 +54,18 @@ typedef enum {
     RHOSVD_ERR_CAPACITY = -8     /* batched: a rank exceeds cap_rank, or r1 r2 r3 exceeds cap_beta */
 } rhosvd_status;
 
-/* Arithmetic of the projection and core contractions.  The column norms, the
- * Gram matrix, the eigensolver, the truncation decision and Z are FP64 in
- * every mode. */
+/* Arithmetic of the Khatri-Rao core contraction.  The column norms, the Gram
+ * matrix, the eigensolver, the truncation decision and Z are FP64 in every
+ * mode; the projection V = Z^T U~ is an FP64 MFMA product, rounded to FP32 for
+ * the FP32 and BF16x3 cores. */
 typedef enum {
     RHOSVD_FP64 = 0,    /* FP64 MFMA */
     RHOSVD_FP32 = 1,    /* FP32 MFMA, FP32 accumulation */
-    RHOSVD_BF16X3 = 2   /* core: a = a_hi + a_lo in bf16, a*b ~ hi*hi + hi*lo + lo*hi,
-                           FP32 accumulation (bf16 MFMA); projection in FP32 MFMA */
+    RHOSVD_BF16X3 = 2   /* a = a_hi + a_lo in bf16, a*b ~ hi*hi + hi*lo + lo*hi, FP32
+                           accumulation (bf16 MFMA).  Its error, about 2e-6 |A|, keeps the
+                           total within (eps + 1e-6) |A| only for eps >= 1e-5: below that
+                           the FP32 core runs in its place (the report's core_precision,
+                           word 5 of a batched result) */
 } rhosvd_precision;
 
 typedef struct {
@@ -181,6 +185,7 @@ typedef struct {
     int32_t anorm_method;  /* 1 exact identity, 2 probe lower bound */
     int32_t refine_used;   /* the refinement rhosvd_reduce ran: 0 none, 1 refined tails, 2 deflated
                               pass; plus 4 when R < n and it ran on the n x n Gram */
+    int32_t core_precision; /* rhosvd_precision of the core contraction (see RHOSVD_BF16X3) */
 } rhosvd_report;
 
 typedef struct rhosvd_ctx* rhosvd_handle;
@@ -295,7 +300,9 @@ rhosvd_status rhosvd_get_v(rhosvd_handle h, int32_t l, double* V);
  *                the batch; it is xi times the three column norms of each term.
  *   result     : int32[8]: r1, r2, r3, status (rhosvd_status of this problem:
  *                OK, ERR_NONFINITE, ERR_CAPACITY, or ERR_DEVICE when an
- *                eigensolver wait ran out), dropped terms, 3 reserved
+ *                eigensolver wait ran out), dropped terms, the core's
+ *                rhosvd_precision (one for the whole pass: FP32 in place of
+ *                BF16x3 when some problem's eps is below 1e-5), 2 reserved
  *   reserved0  : must be zero
  * Returns (host): OK once the pass is enqueued (per-problem outcomes are in
  * result), ARG for a bad descriptor (message names the problem), UNSUPPORTED,

@@ -106,6 +106,7 @@ struct rhosvd_ctx {
     double* V64a[3] = {};                // ALS on a mixed path: FP64 projections (zr_pad x R_pad)
     double* rfloor = nullptr;            // refine_tails: squared residuals (3)
     int vprec = 0;
+    double eps = 0;                      // tolerance of the last reduction (the core's precision)
     // R < n: Z = U~ W_r Lambda_r^-1/2, re-orthonormalized by (Z^T Z)^-1/2
     double* Wr[3] = {};                  // R_pad x zr_pad
     double* Zraw[3] = {};                // n_pad x zr_pad
@@ -833,6 +834,7 @@ rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R, const double*
         return fail(h, RHOSVD_ERR_UNSUPPORTED, "ALS sweeps need n <= R <= 16384");
     rhosvd_status s = layout(h, n, R);
     if (s != RHOSVD_OK) return s;
+    h->eps = eps;
     hipStream_t st = h->stream;
     const double* U[3] = {U1, U2, U3};
     mark(h, 0);
@@ -1045,6 +1047,9 @@ rhosvd_status rhosvd_get(rhosvd_handle h, double* Z1, double* Z2, double* Z3, vo
     if (!h->have) return fail(h, RHOSVD_ERR_STATE, "no successful rhosvd_reduce on this handle");
     hipStream_t st = h->stream;
     const bool any = h->ranks[0] > 0 && h->ranks[1] > 0 && h->ranks[2] > 0;
+    // the core's arithmetic: as the handle's precision, except BF16x3 below its
+    // tolerance floor (BF16X3_MIN_EPS), where the FP32 core runs on the same FP32 V
+    const int cprec = core_precision_for(h->vprec, h->eps);
     if (h->opt.profile && h->ev_ok) hipEventRecord(h->ev[7], st);
     if (beta && any) {
         CoreArgs ca{};
@@ -1056,9 +1061,9 @@ rhosvd_status rhosvd_get(rhosvd_handle h, double* Z1, double* Z2, double* Z3, vo
         ca.R_pad = h->R_pad;
         ca.xip = h->xip;
         ca.beta = beta;
-        ca.prec = h->vprec;
+        ca.prec = cprec;
         ca.beta_f32 = h->opt.beta_fp32 != 0;
-        if (h->vprec == RHOSVD_BF16X3) {
+        if (cprec == RHOSVD_BF16X3) {
             CK(h, launch_split_a(h->r_pad[0], h->R_pad, h->r_pad[0], (const float*)h->V[0], h->xip, h->Asplit, st));
             ca.Asplit = h->Asplit;
         }
@@ -1124,6 +1129,7 @@ rhosvd_status rhosvd_get(rhosvd_handle h, double* Z1, double* Z2, double* Z3, vo
         report->anorm_method = h->anorm_method;
         report->refine_used = h->refine_used;
         report->a_norm_upper = h->anorm_method == 2 ? h->a_upper : h->a_norm;
+        report->core_precision = cprec;
     }
     return RHOSVD_OK;
 }
@@ -1343,6 +1349,7 @@ rhosvd_status rhosvd_reduce_learned(rhosvd_handle h, int64_t n, int64_t R, const
     }
     rhosvd_status s = prologue(h, n, R, U1, U2, U3, xi, eps);
     if (s != RHOSVD_OK) return s;
+    h->eps = eps;
     hipStream_t st = h->stream;
     const int m = (int)h->m;
     const int p_cap = (int)std::min<int64_t>(round_up(m, 64), (int64_t)(omega_cols / 64) * 64);

@@ -46,7 +46,7 @@ __global__ void k_init_b(const BProb* __restrict__ P, int np, int* __restrict__ 
     }
 }
 
-// result words (r1, r2, r3, status, dropped terms) and the copy of Z (status 0
+// result words (r1, r2, r3, status, dropped terms, core precision) and the copy of Z (status 0
 // only); grid (problems, 3 modes, column groups)
 __global__ __launch_bounds__(256) void k_finish_b(const BProb* __restrict__ P) {
     const BProb& q = P[blockIdx.x];
@@ -57,6 +57,7 @@ __global__ __launch_bounds__(256) void k_finish_b(const BProb* __restrict__ P) {
         if (threadIdx.x < 3) v = q.ranks[threadIdx.x];
         else if (threadIdx.x == 3) v = st;
         else if (threadIdx.x == 4) v = q.flags[1];
+        else if (threadIdx.x == 5) v = q.core_prec;
         q.result[threadIdx.x] = v;
     }
     if (st != 0) return;
@@ -87,7 +88,7 @@ struct BatchPlan {
     std::vector<rhosvd_problem> key;
     int prec = 0;
     int prec_key = 0;
-    int core_key = 0;                    // prec_key & 63, + 32 when some R_pad exceeds core_flush_span()
+    int core_key = 0;                    // the core's precision | beta type, + 32 when some R_pad exceeds core_flush_span()
     int core_tile = 0;                   // rows per core tile: fixed by the caller, or chosen on the first run
     bool tune_pending = false;           // the first run times the tile candidates
     std::vector<BProb> hp;
@@ -336,8 +337,13 @@ BatchPlan* batch_plan_create(const rhosvd_problem* probs, int count, int prec, s
     // prec: the core precision, plus 16 when beta is written as float, plus the
     // caller's fixed core tile times 256 (0: tuned on the first run)
     B->key.assign(probs, probs + count);
-    B->prec = prec & 3;
     B->prec_key = prec;
+    // one core precision serves the whole pass: BF16x3 gives way to FP32 when some
+    // problem's eps lies below its floor (BF16X3_MIN_EPS)
+    double eps_min = probs[0].eps;
+    for (int p = 1; p < count; ++p) eps_min = std::min(eps_min, probs[p].eps);
+    prec = (prec & ~3) | core_precision_for(prec & 3, eps_min);
+    B->prec = prec & 3;
     B->hp.resize(count);
     for (int p = 0; p < count; ++p) {
         const rhosvd_problem& d = probs[p];
@@ -369,6 +375,7 @@ BatchPlan* batch_plan_create(const rhosvd_problem* probs, int count, int prec, s
         q.cap_beta = d.cap_beta;
         q.beta_f32 = (prec & 16) ? 1 : 0;
         q.result = d.result;
+        q.core_prec = B->prec;
     }
     const size_t need = carve_batch(*B, nullptr);
     if (!(B->ws = (char*)B->alloc.get(need))) {
@@ -421,7 +428,7 @@ BatchPlan* batch_plan_create(const rhosvd_problem* probs, int count, int prec, s
     }
     int64_t rmax = 0;
     for (const BProb& q : B->hp) rmax = std::max<int64_t>(rmax, q.R_pad);
-    B->core_key = (B->prec_key & 63) | (rmax > core_flush_span() ? 32 : 0);
+    B->core_key = (prec & 63) | (rmax > core_flush_span() ? 32 : 0);
     const int fixed = B->prec_key >> 8;
     bool any_beta = false;
     for (const BProb& q : B->hp) any_beta = any_beta || q.beta != nullptr;

@@ -29,6 +29,14 @@ struct DevAlloc {
 // Padding granularities shared by the workspace layout and the kernels.
 constexpr int PAD_N = 64;    // rows of U~, Z and the Gram side (n, m)
 constexpr int PAD_R = 64;    // canonical terms (columns of U~, K of the core)
+// The BF16x3 core runs for eps >= BF16X3_MIN_EPS only; below it the FP32 core runs
+// in its place.  Its error, about 2e-6 |A| (n = 1024, R = 4096 and R = 90000), lies
+// inside the Tucker subspace and so adds to the truncation error (orthogonal to
+// that subspace) in quadrature: the total stays within (eps + 1e-6) |A| when the
+// core error is below (2 eps 1e-6 + 1e-12)^(1/2) |A|, 4.6e-6 at eps = 1e-5 (2.3x the
+// measured error) but 1.7e-6 at eps = 1e-6.
+constexpr double BF16X3_MIN_EPS = 1e-5;
+inline int core_precision_for(int prec, double eps) { return (prec == 2 && eps < BF16X3_MIN_EPS) ? 1 : prec; }
 
 // a1: scaled column norms, xi' and normalized side matrices (all three modes).
 // U_l: n x R (ld n); Ut_l: n_pad x R_pad (ld n_pad), zero padded; xip: R_pad.
@@ -239,7 +247,8 @@ struct BProb {
     void* beta;            // caller output (double, or float when beta_f32) or null
     int64_t cap_beta;
     int beta_f32;
-    int* result;           // caller's int32[8]: r1, r2, r3, status
+    int* result;           // caller's int32[8]: r1, r2, r3, status, dropped, core precision
+    int core_prec;         // the core's arithmetic for the whole pass (rhosvd_precision)
 };
 enum { BK_COLNORM = 0, BK_ANORM = 1, BK_GRAM = 2, BK_PROJECT = 3, BK_SIGN = 4, BK_SPLIT = 5 };
 // the BF16x3 A planes of every problem (blocks: rcap_pad / 64 x R_pad / 64 each)

@@ -59,7 +59,8 @@ class Report(ctypes.Structure):
                 ("bound", ctypes.c_double), ("tail", ctypes.c_double * 3), ("ranks", ctypes.c_int32 * 3),
                 ("m", ctypes.c_int32), ("eig_sweeps", ctypes.c_int32), ("dropped", ctypes.c_int32),
                 ("certificate", ctypes.c_double), ("a_norm_upper", ctypes.c_double),
-                ("anorm_method", ctypes.c_int32), ("refine_used", ctypes.c_int32)]
+                ("anorm_method", ctypes.c_int32), ("refine_used", ctypes.c_int32),
+                ("core_precision", ctypes.c_int32)]
 
 
 class Problem(ctypes.Structure):
@@ -310,7 +311,8 @@ class Reducer:
         report = dict(xi_norm=rep.xi_norm, a_norm=rep.a_norm, tau=rep.tau, bound=rep.bound,
                       tail=list(rep.tail), ranks=list(rep.ranks), m=rep.m, eig_sweeps=rep.eig_sweeps,
                       dropped=rep.dropped, certificate=rep.certificate, a_norm_upper=rep.a_norm_upper,
-                      anorm_method=rep.anorm_method, refine_used=rep.refine_used)
+                      anorm_method=rep.anorm_method, refine_used=rep.refine_used,
+                      core_precision=rep.core_precision)
         beta_t = None
         if b is not None:
             beta_t = b.view(r3, r2, r1).permute(2, 1, 0) if b.numel() > 0 else b.view(r1, r2, r3)
@@ -542,7 +544,7 @@ class Reducer:
             bt = None
             if b is not None and all(x > 0 for x in r):
                 bt = b[: r[0] * r[1] * r[2]].view(r[2], r[1], r[0]).permute(2, 1, 0)
-            out.append(dict(ranks=r, status=int(rr[i, 3]), dropped=int(rr[i, 4]),
+            out.append(dict(ranks=r, status=int(rr[i, 3]), dropped=int(rr[i, 4]), core_precision=int(rr[i, 5]),
                             Z=[Z1[:, :r[0]], Z2[:, :r[1]], Z3[:, :r[2]]], beta=bt))
         return out, desc, res2, outs
 

@@ -96,6 +96,43 @@ def test_mixed_precision_parity(orc, prec):
     for gg, p in ((g, prec), (g64, "fp64")):
         w = gc.check_core_slabs(orc, Ut, xip, gg["Z"], gg["beta"], range(gg["ranks"][2]), p, what="n96 R300")
         _flush(f"{p}: worst entry at {w:.3f} of its bound")
+    assert g["report"]["core_precision"] == (1 if prec == "fp32" else 2)
+
+
+def test_bf16x3_below_its_floor_runs_the_fp32_core(orc):
+    """eps < 1e-5 with the BF16x3 precision: the split's own error (~2e-6 |A|)
+    would exceed the 1e-6 allowance, so the FP32 core runs on the same FP32 V.
+    Its beta equals the FP32 path's bit for bit (same kernel and tile), the report
+    says FP32, and the total error is within (eps + 1e-6) |A|; in a batch, one
+    problem below the floor moves the whole pass to the FP32 core."""
+    import torch
+    from paper_2201_12663_amd import rhosvd
+    ci = inputs.small_gaussian_sum(5, n=96, R=300, eps=1e-6)
+    o = orc.rhosvd(ci.U, ci.xi, ci.eps)
+    g32 = gc.run_gpu(ci, "fp32", core_tile=64)
+    g = gc.run_gpu(ci, "bf16x3", core_tile=64)
+    assert g["report"]["core_precision"] == 1 and g32["report"]["core_precision"] == 1
+    assert g["ranks"] == g32["ranks"]
+    assert np.array_equal(g["beta"], g32["beta"])
+    assert gc.recon_error(orc, ci, g["Z"], g["beta"]) <= (ci.eps + 1e-6) * o.a_norm
+    # batched: eps 1e-5 and 1e-6 together -> FP32 core for both; 1e-5 alone -> BF16x3
+    cj = inputs.small_gaussian_sum(6, n=80, R=250, eps=1e-5)
+    dev = []
+    for c in (ci, cj):
+        U = [rhosvd.to_device(u) for u in c.U]
+        dev.append((U[0], U[1], U[2], torch.from_numpy(np.ascontiguousarray(c.xi)).cuda(), c.eps))
+    red = rhosvd.Reducer(precision="bf16x3", core_tile=64)
+    both, _, _, _ = red.reduce_batched(dev)
+    alone, _, _, _ = red.reduce_batched(dev[1:])
+    torch.cuda.synchronize()
+    assert [b["core_precision"] for b in both] == [1, 1]
+    assert alone[0]["core_precision"] == 2
+    assert both[0]["ranks"] == g["ranks"]
+    Ut, xip, _, _ = orc.normalize(ci.U, ci.xi)
+    Zb = [z.cpu().numpy() for z in both[0]["Z"]]
+    gc.check_core_slabs(orc, Ut, xip, Zb, both[0]["beta"].cpu().numpy(), range(g["ranks"][2]), "fp32",
+                        what="batched n96 R300")
+    red.close()
 
 
 def test_degenerate_single_term(orc):
