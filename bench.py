@@ -307,7 +307,9 @@ def bench_precision_study(args):
     are orthogonal).  The FP64 and BF16x3 paths run again with the deflated
     second Gram pass (refine_tails = 2), whose cut at eps = 1e-6 is the exact
     one.  At eps = 1e-6 the BF16x3 precision runs the FP32 core (below the
-    split's floor, 1e-5); core_precision says which core ran."""
+    split's floor, 1e-5); core_precision says which core ran.  The last two rows
+    take the Gram in FP32 and in BF16x3 with the FP64 Rayleigh-Ritz step
+    (gram_precision; |A| then by the exact identity)."""
     import numpy as np
     import torch
     from paper_2201_12663_amd import inputs, rhosvd
@@ -318,14 +320,17 @@ def bench_precision_study(args):
     cases = []
     for eps in (1e-4, 1e-6):
         b64 = {}
-        for prec, refine in (("fp64", "auto"), ("fp32", "auto"), ("bf16x3", "auto"), ("fp64", 2), ("bf16x3", 2)):
-            red = rhosvd.Reducer(precision=prec, profile=True, refine_tails=refine)
+        for prec, refine, gram in (("fp64", "auto", "fp64"), ("fp32", "auto", "fp64"), ("bf16x3", "auto", "fp64"),
+                                   ("fp64", 2, "fp64"), ("bf16x3", 2, "fp64"),
+                                   ("bf16x3", "auto", "fp32"), ("bf16x3", "auto", "bf16x3")):
+            red = rhosvd.Reducer(precision=prec, profile=True, refine_tails=refine, gram_precision=gram)
             ranks = red.reduce(U[0], U[1], U[2], xi, eps)
             r1, r2, r3 = ranks
             beta = torch.empty(r1 * r2 * r3, dtype=torch.float64, device="cuda")
             ms, core_ms, avg = time_path(red, U, xi, eps, beta, args.precision_steps, 1)
             rep = red.get(beta=False, Z=False, sigma=False).report
-            row = dict(eps=eps, precision=prec, refine_tails=refine, ranks=list(ranks), ms=round(ms, 3), core_ms=round(core_ms, 3),
+            row = dict(eps=eps, precision=prec, refine_tails=refine, gram_precision=gram, ranks=list(ranks),
+                       ms=round(ms, 3), core_ms=round(core_ms, 3),
                        core_tile=red.last_core_tile(),
                        core_tflops=round(2.0 * r1 * r2 * r3 * ci.R / (core_ms * 1e-3) / 1e12, 2),
                        phase_ms={k: round(v, 3) for k, v in avg.items()},
@@ -334,7 +339,7 @@ def bench_precision_study(args):
                        core_precision=("fp64", "fp32", "bf16x3")[rep["core_precision"]])
             if prec == "fp64":
                 b64[refine] = beta
-            elif refine in b64 and b64[refine].numel() == beta.numel():
+            elif refine in b64 and b64[refine].numel() == beta.numel() and gram == "fp64":
                 row["core_err_rel"] = float(torch.linalg.vector_norm(beta - b64[refine]).item()) / rep["a_norm"]
                 row["err_bound_rel"] = math.hypot(row["bound_rel"], row["core_err_rel"])
                 row["within_eps_plus_1e-6"] = row["err_bound_rel"] <= eps + 1e-6

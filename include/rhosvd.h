@@ -164,6 +164,29 @@ typedef struct {
                                 holds.  n <= R <= 16384 (the R x R FP64 products);
                                 otherwise RHOSVD_ERR_UNSUPPORTED.  Not used by batched or
                                 learned reductions. */
+    int32_t gram_precision;  /* arithmetic of the Gram matrix (n <= R; other values: RHOSVD_ERR_ARG):
+                                0 (default) FP64 MFMA.
+                                1 FP32 MFMA or 2 BF16x3 (a_hi + a_lo split, three bf16 products),
+                                both accumulating in FP32 (summed in FP64 every 4096 terms).
+                                Its eigenvalues then carry noise of about u_32 |G| (2^-17 |G|
+                                for BF16x3), far above the FP64 route's, and a Rayleigh-Ritz
+                                step in FP64 recovers the accuracy: with Q the leading p
+                                eigenvectors of that Gram (p = min(m, r + r/8 + 16), r its
+                                own cut on tails that sum its eigenvalues with their signs,
+                                so that the noise largely cancels), B = Q^T U~ (FP64 MFMA),
+                                the residual |U~ - Q B|_F^2
+                                formed directly, and B B^T = Y S^2 Y^T (the FP64
+                                eigensolver), the cut is taken on
+                                t_r^2 = sum_{k>r} s_k^2 + |U~ - Q B|_F^2 and
+                                Z = Q Y[:, 0:r] (Theorem 2.3 holds for this orthonormal Z).
+                                Where no r <= p certifies, p grows (2p + 64, at most m) and
+                                the step repeats; at p = m the step is exact, at about the
+                                cost of the FP64 route twice.  The reduced-precision Gram pays
+                                where tau^2 lies well above its noise (loose eps, large R);
+                                the spectrum then holds the p Ritz values.  |A| comes from the
+                                exact identity and refine_tails is not used.  When R < n, and
+                                for batched and learned reductions, the Gram is FP64; the
+                                report's gram_precision says which ran. */
 } rhosvd_options;
 
 typedef struct {
@@ -186,6 +209,8 @@ typedef struct {
     int32_t refine_used;   /* the refinement rhosvd_reduce ran: 0 none, 1 refined tails, 2 deflated
                               pass; plus 4 when R < n and it ran on the n x n Gram */
     int32_t core_precision; /* rhosvd_precision of the core contraction (see RHOSVD_BF16X3) */
+    int32_t gram_precision; /* the Gram's arithmetic (rhosvd_options.gram_precision) as run: 0 FP64,
+                               1 FP32 or 2 BF16x3 followed by the FP64 Rayleigh-Ritz step */
 } rhosvd_report;
 
 typedef struct rhosvd_ctx* rhosvd_handle;

@@ -105,6 +105,13 @@ struct rhosvd_ctx {
     double* Tals = nullptr;              // ALS: U~_l P (n_pad x R_pad)
     double* V64a[3] = {};                // ALS on a mixed path: FP64 projections (zr_pad x R_pad)
     double* rfloor = nullptr;            // refine_tails: squared residuals (3)
+    // reduced-precision Gram (gram_precision 1, 2; n <= R): the Rayleigh-Ritz step uses
+    // Zraw (Q), Brr (B = Q^T U~, FP64), M2 (B B^T -> reflectors), P2 / Qn2 / Mg2 /
+    // lam2 / dd2 / ee2 / tau2 (its eigensolver), Pf (selected eigenvectors of B B^T)
+    double* Brr[3] = {};                 // zr_pad x R_pad
+    int* rr_order[3] = {};               // order of the Ritz values (the Gram's own order stays in order)
+    bool lp_gram = false;                // this reduction's Gram ran in reduced precision
+    int gram_used = 0;                   // report: the Gram's arithmetic as run
     int vprec = 0;
     double eps = 0;                      // tolerance of the last reduction (the core's precision)
     // R < n: Z = U~ W_r Lambda_r^-1/2, re-orthonormalized by (Z^T Z)^-1/2
@@ -189,6 +196,10 @@ rhosvd_status check_options(const rhosvd_options* o, std::string& msg) {
     if (o->anorm < 0 || o->anorm > 2) { msg = "anorm must be 0 (auto), 1 (exact) or 2 (probe)"; return RHOSVD_ERR_ARG; }
     if (o->als_sweeps < 0 || o->als_sweeps > 4) { msg = "als_sweeps must be 0..4"; return RHOSVD_ERR_ARG; }
     if (o->refine_tails < 0 || o->refine_tails > 3) { msg = "refine_tails must be 0 (auto), 1, 2 or 3 (off)"; return RHOSVD_ERR_ARG; }
+    if (o->gram_precision < 0 || o->gram_precision > 2) {
+        msg = "gram_precision must be 0 (FP64), 1 (FP32) or 2 (BF16x3)";
+        return RHOSVD_ERR_ARG;
+    }
     if (o->core_tile != 0 && !core_tile_valid(o->precision, o->core_tile)) {
         msg = "core_tile must be 0 (tuned), 64, or 128 (128 only for the FP32 and BF16x3 cores)";
         return RHOSVD_ERR_ARG;
@@ -239,8 +250,9 @@ size_t carve_all(rhosvd_ctx* h, char* base) {
         h->Z[l] = c.take<double>((size_t)np * zp);
         h->V[l] = (void*)c.take<char>((size_t)zp * Rp * esz);
     }
+    const bool lp = h->lp_gram;
     for (int l = 0; l < 3; ++l) {
-        const bool refine = h->opt.refine_tails != REFINE_OFF;   // auto may refine
+        const bool refine = h->opt.refine_tails != REFINE_OFF || lp;   // auto may refine
         const bool deflate = (h->opt.refine_tails == 2 || h->opt.refine_tails == REFINE_AUTO) && !h->rside;
         h->Vref[l] = (refine && esz == 4) ? c.take<double>((size_t)zp * Rp) : nullptr;
         h->rpart[l] = refine ? c.take<double>((size_t)(np / 64) * (Rp / 64)) : nullptr;
@@ -267,9 +279,13 @@ size_t carve_all(rhosvd_ctx* h, char* base) {
     h->anorm_part = c.take<double>(h->anorm_ntiles);
     h->ranks_dev = c.take<int>(16);
     h->scal = c.take<double>(16);
-    if (h->rside) {
+    for (int l = 0; l < 3; ++l) {
+        h->Brr[l] = lp ? c.take<double>((size_t)zp * Rp) : nullptr;
+        h->rr_order[l] = lp ? c.take<int>(zp) : nullptr;
+    }
+    if (h->rside || lp) {
         for (int l = 0; l < 3; ++l) {
-            h->Wr[l] = c.take<double>((size_t)Rp * zp);
+            h->Wr[l] = h->rside ? c.take<double>((size_t)Rp * zp) : nullptr;
             h->Zraw[l] = c.take<double>((size_t)np * zp);
             h->M2[l] = c.take<double>((size_t)zp * zp);
             h->P2[l] = c.take<double>((size_t)zp * zp);
@@ -293,6 +309,8 @@ rhosvd_status layout(rhosvd_ctx* h, int64_t n, int64_t R) {
     h->n_pad = round_up(n, PAD_N);
     h->R_pad = round_up(R, PAD_R);
     h->rside = R < n && !h->force_nside;
+    h->lp_gram = h->opt.gram_precision != 0 && n <= R;
+    h->gram_used = h->lp_gram ? h->opt.gram_precision : 0;
     h->m = h->rside ? R : n;                     // the Gram's size
     h->m_pad = h->rside ? h->R_pad : h->n_pad;   // Gram on the min(n, R) side
     h->zr_pad = round_up(h->m, RPAD_CORE);       // max padded rank
@@ -736,6 +754,91 @@ rhosvd_status deflate_pass(rhosvd_ctx* h, double eps) {
     return RHOSVD_OK;
 }
 
+// Reduced-precision Gram (rhosvd_options.gram_precision): the Rayleigh-Ritz step.
+// Q = the leading p eigenvectors of that Gram (its own cut r, p = min(m, r + r/8 + 16)),
+// B = Q^T U~ in FP64, the residual |U~ - Q B|_F^2 formed directly and B B^T
+// eigendecomposed by the FP64 eigensolver.  For orthonormal Q, with B B^T = Y S^2 Y^T,
+// |(I - (QY)_r (QY)_r^T) U~|_F^2 = sum_{k>r} s_k^2 + |U~ - Q B|_F^2, so the cut on those
+// tails is certified by Theorem 2.3 for Z = Q Y[:, 0:r], whatever the accuracy of Q.
+// Where no r <= p certifies (the residual alone exceeds tau), p grows (2p + 64, at
+// most m) and the step repeats.
+rhosvd_status rr_pass(rhosvd_ctx* h, double eps) {
+    hipStream_t st = h->stream;
+    const int64_t np = h->n_pad, Rp = h->R_pad, zp = h->zr_pad;
+    const int m = (int)h->m;
+    const int64_t ntl = (np / 64) * (Rp / 64);
+    int p[3], pp[3];
+    for (int l = 0; l < 3; ++l) p[l] = std::min(m, std::max(1, h->ranks[l]) + h->ranks[l] / 8 + 16);
+    for (;;) {
+        BtJob jobs[3];
+        for (int l = 0; l < 3; ++l) {
+            pp[l] = (int)round_up(p[l], RPAD_CORE);
+            jobs[l] = BtJob{m, (int)h->m_pad, h->G[l], h->htau[l], h->W[l], h->order[l], p[l], nullptr, h->Zraw[l],
+                            (int)np, (int)np, h->Tw[l]};
+        }
+        CK(h, launch_backtransform(jobs, 3, st));
+        EigMat em[3];
+        for (int l = 0; l < 3; ++l) {
+            if (pp[l] > p[l])
+                CK(h, hipMemsetAsync(h->Zraw[l] + (int64_t)p[l] * np, 0, (size_t)(pp[l] - p[l]) * np * 8, st));
+            CK(h, launch_project(np, Rp, pp[l], h->Zraw[l], h->Ut[l], h->Brr[l], nullptr, st));
+            CK(h, launch_resid_partials(np, Rp, pp[l], h->Zraw[l], h->Brr[l], h->Ut[l], h->rpart[l], st));
+            CK(h, launch_floor_sum(h->rpart[l], ntl, h->rfloor + l, st));
+            CK(h, launch_gemm64(false, false, pp[l], pp[l], Rp, h->Brr[l], pp[l], h->Brr[l], pp[l], h->M2[l], zp, 1.0,
+                                st));
+            em[l] = EigMat{h->M2[l], h->lam2[l], h->P2[l], h->Qn2[l], h->Mg2[l], h->dd2[l], h->ee2[l], h->tau2[l], p[l],
+                           (int)zp};
+        }
+        rhosvd_status ps = ensure_plan(h, 1, em, 3);
+        if (ps != RHOSVD_OK) return ps;
+        CK(h, eig_plan_enqueue(h->plan[1], h->flags + 2, st));
+        TruncArgs ta = trunc_args(h, eps);
+        for (int l = 0; l < 3; ++l) {
+            ta.lam[l] = h->lam2[l];
+            ta.m_mode[l] = p[l];
+            ta.order[l] = h->rr_order[l];
+            CK(h, hipMemsetAsync(h->sigma[l], 0, (size_t)(h->m_pad + 1) * 8, st));
+        }
+        ta.floor2 = h->rfloor;
+        CK(h, launch_truncate(ta, st));
+        CK(h, hipMemcpyAsync(h->host, h->ranks_dev, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
+        CK(h, hipMemcpyAsync(h->host + 6, h->flags + 2, sizeof(int), hipMemcpyDeviceToHost, st));
+        CK(h, hipStreamSynchronize(st));
+        if (h->host[6]) return fail(h, RHOSVD_ERR_DEVICE, "eigensolver: a cross-workgroup wait ran out");
+        bool again = false;
+        for (int l = 0; l < 3; ++l) {
+            if (h->host[l] < 1 || h->host[l] > p[l] + 1)
+                return fail(h, RHOSVD_ERR_DEVICE, "Rayleigh-Ritz cut returned rank " + std::to_string(h->host[l]) +
+                                                      " (internal error)");
+            if (h->host[l] > p[l] && p[l] < m) {
+                p[l] = (int)std::min<int64_t>(m, 2 * (int64_t)p[l] + 64);
+                again = true;
+            }
+        }
+        if (!again) break;
+    }
+    // Z = Q Y[:, order[0..r)], sign rule, zero padding
+    BtJob jobs[3];
+    for (int l = 0; l < 3; ++l) {
+        // p + 1 at p = m: not even the full basis certifies (tau below the residual's
+        // rounding); keep m, as the refined cut does
+        const int r = std::min(h->host[l], p[l]);
+        h->ranks[l] = r;
+        h->r_pad[l] = (int)round_up(r, RPAD_CORE);
+        jobs[l] = BtJob{p[l], (int)zp, h->M2[l], h->tau2[l], h->P2[l], h->rr_order[l], r, nullptr, h->Pf[l], (int)zp,
+                        (int)zp, h->Tw[l]};
+    }
+    CK(h, launch_backtransform(jobs, 3, st));
+    for (int l = 0; l < 3; ++l) {
+        const int r = h->ranks[l];
+        CK(h, launch_gemm64(false, true, np, h->r_pad[l], pp[l], h->Zraw[l], np, h->Pf[l], zp, h->Z[l], np, 1.0, st));
+        CK(h, launch_sign_cols((int)h->n, (int)np, r, h->Z[l], st));
+        if (h->r_pad[l] > r)
+            CK(h, hipMemsetAsync(h->Z[l] + (int64_t)r * np, 0, (size_t)(h->r_pad[l] - r) * np * 8, st));
+    }
+    return RHOSVD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -843,7 +946,7 @@ rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R, const double*
     mark(h, 1);
     // |A|: the exact identity now (when R < n its tiles are the Grams U~^T U~ on the
     // R side), or after the eigensolver by the probe (rhosvd_options.anorm)
-    const bool probe = !h->rside && h->opt.anorm != 1;
+    const bool probe = !h->rside && h->opt.anorm != 1 && !h->lp_gram;
     h->a2_part = h->anorm_part;
     h->a2_n = h->anorm_ntiles;
     h->anorm_method = 1;
@@ -854,7 +957,10 @@ rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R, const double*
                                     h->rside ? h->G : nullptr, st));
     }
     mark(h, 2);
-    if (!h->rside)
+    if (h->lp_gram)
+        CK(h, launch_gram_lp(h->opt.gram_precision, h->n_pad, h->R_pad, h->Ut, h->G, h->gram_part, h->gram_splits,
+                             st));
+    else if (!h->rside)
         CK(h, launch_gram_nt(h->n_pad, h->R_pad, h->Ut, h->G, h->gram_part, h->gram_splits, st));
     mark(h, 3);
     EigMat em[3];
@@ -870,7 +976,13 @@ rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R, const double*
         s = anorm_probe(h, h->opt.anorm, &z_all);
         if (s != RHOSVD_OK) return s;
     }
-    CK(h, launch_truncate(trunc_args(h, eps), st));
+    {
+        // a reduced-precision Gram's cut only sizes the Rayleigh-Ritz basis: its small
+        // eigenvalues are noise of either sign, summed with their signs
+        TruncArgs ta = trunc_args(h, eps);
+        ta.signed_tails = h->lp_gram ? 1 : 0;
+        CK(h, launch_truncate(ta, st));
+    }
     // the one host synchronization: ranks, flags, sweeps and norms
     CK(h, hipMemcpyAsync(h->host, h->ranks_dev, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
     CK(h, hipMemcpyAsync(h->host + 4, h->flags, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -885,7 +997,8 @@ rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R, const double*
     // Gram route's noise band, lambda_r <= NOISE_BAND u lambda_1; else none
     // (the deflated pass, mode 2, when tau^2 itself lies in that band: the first pass's
     // vectors near such a cut are inaccurate, and only the deflated Gram resolves it)
-    int refine_mode = h->opt.refine_tails;
+    // (a reduced-precision Gram takes its own Rayleigh-Ritz step instead)
+    int refine_mode = h->lp_gram ? REFINE_OFF : h->opt.refine_tails;
     if (refine_mode == REFINE_AUTO) {
         const double tau2 = h->hostd[2] * h->hostd[2];
         int want = 0;
@@ -924,8 +1037,14 @@ rhosvd_status rhosvd_reduce(rhosvd_handle h, int64_t n, int64_t R, const double*
         h->ranks[l] = h->host[l];
         h->r_pad[l] = (int)round_up(h->ranks[l] > 0 ? h->ranks[l] : 1, RPAD_CORE);
     }
-    // refine_tails = 2: the deflated second pass forms Z itself
+    // reduced-precision Gram: the Rayleigh-Ritz step cuts again and forms Z itself
     bool z_done = false;
+    if (h->lp_gram && h->ranks[0] > 0) {
+        rhosvd_status rs = rr_pass(h, eps);
+        if (rs != RHOSVD_OK) return rs;
+        z_done = true;
+    }
+    // refine_tails = 2: the deflated second pass forms Z itself
     if (refine_mode == 2 && !h->rside && h->ranks[0] > 0) {
         rhosvd_status ds = deflate_pass(h, eps);
         if (ds != RHOSVD_OK) return ds;
@@ -1130,6 +1249,7 @@ rhosvd_status rhosvd_get(rhosvd_handle h, double* Z1, double* Z2, double* Z3, vo
         report->refine_used = h->refine_used;
         report->a_norm_upper = h->anorm_method == 2 ? h->a_upper : h->a_norm;
         report->core_precision = cprec;
+        report->gram_precision = h->gram_used;
     }
     return RHOSVD_OK;
 }

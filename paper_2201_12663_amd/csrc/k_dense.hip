@@ -268,6 +268,11 @@ hipError_t launch_gram_nt(int64_t n_pad, int64_t R_pad, double* const Ut[3], dou
     return hipGetLastError();
 }
 
+hipError_t launch_gram_reduce(int64_t n_pad, const double* part, int splits, double* const G[3], hipStream_t st) {
+    hipLaunchKernelGGL(k_gram_reduce, dim3(1024, 3), dim3(256), 0, st, n_pad, part, splits, G[0], G[1], G[2]);
+    return hipGetLastError();
+}
+
 // ===========================================================================
 // |A|^2 = sum_{nu,mu} xi'_nu xi'_mu prod_l <u~_nu^(l), u~_mu^(l)>  (the inner
 // product of two canonical sums).  One block per lower-triangle tile (nu-tile

@@ -27,12 +27,15 @@ __device__ double block_sum(double v, double* red) {
 // one block per mode: sorted spectrum, tails, rank; mode 0 also writes the norms
 // floor2: a squared tail that every t_r carries in addition to the discarded
 // eigenvalues (the residual of a range finder; 0 on the Gram path).  When no
-// r <= m certifies t_r <= tau the rank is set to m + 1.
+// r <= m certifies t_r <= tau the rank is set to m + 1.  signed_tails: the tails sum
+// the eigenvalues with their signs (then clamp at zero) instead of their positive
+// parts: for a Gram whose small eigenvalues are rounding noise of either sign, the
+// noise then largely cancels in the tails instead of adding up.
 __device__ __forceinline__ void truncate_mode(int mode, const double* __restrict__ lam, int m, const double* __restrict__ xip,
                               int64_t R_pad, const double* __restrict__ anorm_part, int64_t anorm_ntiles, double eps,
                               double* __restrict__ sigma, int* __restrict__ order, double* __restrict__ tails,
                               int* __restrict__ ranks, double* __restrict__ scal, double floor2 = 0.0,
-                              bool presorted = false, double tau_fixed = 0.0) {
+                              bool presorted = false, double tau_fixed = 0.0, bool signed_tails = false) {
     __shared__ double key[MAXM];
     __shared__ int idx[MAXM];
     __shared__ double scan[MAXM + 1];
@@ -80,7 +83,7 @@ __device__ __forceinline__ void truncate_mode(int mode, const double* __restrict
         }
     }
     // suffix sums of max(lambda, 0): scan[r] = sum_{k >= r} lambda_k, scan[m] = 0
-    for (int i = t; i <= m; i += TB) scan[i] = (i < m) ? fmax(key[i], 0.0) : 0.0;
+    for (int i = t; i <= m; i += TB) scan[i] = (i < m) ? (signed_tails ? key[i] : fmax(key[i], 0.0)) : 0.0;
     __syncthreads();
     for (int off = 1; off < m; off <<= 1) {
         double add[2];
@@ -91,8 +94,8 @@ __device__ __forceinline__ void truncate_mode(int mode, const double* __restrict
         for (int i = t; i < m; i += TB) scan[i] += add[cnt++];
         __syncthreads();
     }
-    if (floor2 != 0.0) {
-        for (int i = t; i <= m; i += TB) scan[i] += floor2;
+    if (floor2 != 0.0 || signed_tails) {
+        for (int i = t; i <= m; i += TB) scan[i] = fmax(scan[i] + floor2, 0.0);
         __syncthreads();
     }
     if (t == 0) rmin = m + 1;
@@ -121,7 +124,7 @@ __global__ __launch_bounds__(TB) void k_truncate(TruncArgs a) {
     const int m = a.m_mode[mode] > 0 ? a.m_mode[mode] : a.m;
     truncate_mode(mode, a.lam[mode], m, a.xip, a.R_pad, a.anorm_part, a.anorm_ntiles, a.eps, a.sigma[mode],
                   a.order[mode], a.tails[mode], a.ranks, a.scal, a.floor2 ? a.floor2[mode] : 0.0, a.presorted != 0,
-                  a.tau_fixed);
+                  a.tau_fixed, a.signed_tails != 0);
 }
 
 // part[b] = sum of x[i]^2 over i = b, b + nparts, ... (one block per part, fixed order)

@@ -49,6 +49,14 @@ hipError_t launch_colnorm(int64_t n, int64_t R, int64_t n_pad, int64_t R_pad,
 // part: workspace of splits * 3 * n_pad^2 doubles (unused when splits == 1).
 hipError_t launch_gram_nt(int64_t n_pad, int64_t R_pad, double* const Ut[3], double* const G[3],
                           double* part, int splits, hipStream_t st);
+// split-K partials of the Gram (splits x 3 x n_pad^2) summed in a fixed order into
+// the lower triangle and mirrored
+hipError_t launch_gram_reduce(int64_t n_pad, const double* part, int splits, double* const G[3], hipStream_t st);
+// a2 in reduced precision (k_gram_lp.hip): prec 1 FP32 MFMA, 2 BF16x3; FP32
+// accumulation restarted every 4096 terms and summed in FP64; same split-K and
+// partial buffer as launch_gram_nt
+hipError_t launch_gram_lp(int prec, int64_t n_pad, int64_t R_pad, double* const Ut[3], double* const G[3],
+                          double* part, int splits, hipStream_t st);
 
 // |A|^2 = xi'^T (G1 o G2 o G3) xi' with G_l = U~_l^T U~_l, per-tile partial sums
 // written to part (ntiles doubles); the caller reduces them in a fixed order.
@@ -172,6 +180,7 @@ struct TruncArgs {
     const double* floor2;   // per-mode squared tail floor (device, 3 doubles) or null
     int presorted;          // nonzero: keep the given order (no sort; order = identity)
     double tau_fixed;       // > 0: use this tau instead of eps |A| / (3 |xi'|)
+    int signed_tails;       // nonzero: tails from the signed eigenvalues (clamped at zero)
 };
 hipError_t launch_truncate(const TruncArgs& a, hipStream_t st);
 // Sums of squares of x[0 .. count) into part[0 .. nparts), each over a fixed

@@ -51,7 +51,7 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("max_eig_sweeps", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("beta_fp32", ctypes.c_int32), ("refine_tails", ctypes.c_int32),
                 ("core_tile", ctypes.c_int32), ("certificate", ctypes.c_int32), ("anorm", ctypes.c_int32),
-                ("als_sweeps", ctypes.c_int32)]
+                ("als_sweeps", ctypes.c_int32), ("gram_precision", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -60,7 +60,7 @@ class Report(ctypes.Structure):
                 ("m", ctypes.c_int32), ("eig_sweeps", ctypes.c_int32), ("dropped", ctypes.c_int32),
                 ("certificate", ctypes.c_double), ("a_norm_upper", ctypes.c_double),
                 ("anorm_method", ctypes.c_int32), ("refine_used", ctypes.c_int32),
-                ("core_precision", ctypes.c_int32)]
+                ("core_precision", ctypes.c_int32), ("gram_precision", ctypes.c_int32)]
 
 
 class Problem(ctypes.Structure):
@@ -192,10 +192,11 @@ class Reducer:
 
     def __init__(self, precision="fp64", stream=None, max_eig_sweeps=0, profile=False, beta_fp32=False,
                  refine_tails="auto", core_tile=0, certificate=False, anorm="auto", als_sweeps=0,
-                 torch_allocator=True):
+                 gram_precision="fp64", torch_allocator=True):
         """torch_allocator: the handle's device workspace comes from PyTorch's
         caching allocator (rhosvd_create_with_allocator), so it is counted by
-        torch.cuda.memory_allocated and shares torch's pool; False: hipMalloc."""
+        torch.cuda.memory_allocated and shares torch's pool; False: hipMalloc.
+        gram_precision: "fp64" (default), "fp32" or "bf16x3" (rhosvd_options.gram_precision)."""
         import torch
         self.lib = load()
         self.opt = Options()
@@ -208,6 +209,8 @@ class Reducer:
             (int(refine_tails) if refine_tails in (0, 1, 2, 3) else -1)
         self.beta_dtype = torch.float32 if beta_fp32 else torch.float64
         self.opt.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        self.opt.gram_precision = PRECISIONS.get(gram_precision, -1) if isinstance(gram_precision, str) else \
+            int(gram_precision)
         self.opt.max_eig_sweeps = int(max_eig_sweeps)
         self.opt.profile = 1 if profile else 0
         if stream is None:
@@ -312,7 +315,7 @@ class Reducer:
                       tail=list(rep.tail), ranks=list(rep.ranks), m=rep.m, eig_sweeps=rep.eig_sweeps,
                       dropped=rep.dropped, certificate=rep.certificate, a_norm_upper=rep.a_norm_upper,
                       anorm_method=rep.anorm_method, refine_used=rep.refine_used,
-                      core_precision=rep.core_precision)
+                      core_precision=rep.core_precision, gram_precision=rep.gram_precision)
         beta_t = None
         if b is not None:
             beta_t = b.view(r3, r2, r1).permute(2, 1, 0) if b.numel() > 0 else b.view(r1, r2, r3)

@@ -47,7 +47,7 @@ def test_version_and_null_handle_errors(lib):
 
 def test_struct_layouts_match_header():
     from paper_2201_12663_amd import rhosvd
-    assert ctypes.sizeof(rhosvd.Options) == 36
+    assert ctypes.sizeof(rhosvd.Options) == 40
     # 4 doubles + 3 doubles + 3 int32 + 3 int32 + 2 doubles + 2 int32 = 56 + 24 + 16 + 8 = 104
     assert ctypes.sizeof(rhosvd.Report) == 112
 
