@@ -31,6 +31,13 @@ __device__ __forceinline__ f4_t mfma_bf16(bf8_t a, bf8_t b, f4_t c) {
 }
 
 __device__ __forceinline__ int c_row64(int lane, int i) { return 4 * i + (lane >> 4); }
+
+// LDS placement of bf16 MFMA operands held as 64-byte rows (32 k values in four
+// 16-byte groups): group q of row r sits in slot q ^ f(r), f(r) = ((r >> 1) ^ (r >> 2)) & 3.
+// The 16 rows of a fragment read with one group index then fall on distinct banks
+// both with 32 banks (8 lanes per cycle for a 16-byte read: rows 2 apart share
+// banks unless f separates them) and with 64 banks (16 lanes per cycle).
+__device__ __forceinline__ int lds_slot(int r, int q) { return q ^ (((r >> 1) ^ (r >> 2)) & 3); }
 __device__ __forceinline__ int c_row32(int lane, int i) { return 4 * (lane >> 4) + i; }
 __device__ __forceinline__ int c_col(int lane) { return lane & 15; }
 

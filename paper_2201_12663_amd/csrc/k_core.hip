@@ -241,7 +241,7 @@ __device__ __forceinline__ void split2(f2_t x, b2_t& hi, b2_t& lo) {
 // a ring of three K-chunk stages: chunk c+2 is in flight while chunk c is
 // multiplied.  Layouts (bytes within a stage), chosen so that the reads of a
 // K-chunk meet no bank conflicts:
-//   A plane (hi, lo): row r at 64 r, its 8-k group q (16 B) at slot q ^ ((r >> 2) & 3);
+//   A plane (hi, lo): row r at 64 r, its 8-k group q (16 B) at slot lds_slot(r, q);
 //   V2, V3: k row at 64 s(k), s(k) = 4 (k & 7) + (k >> 3), so that the four k
 //   rows a wave reads together (k, k+8, k+16, k+24) form one 256-byte block.
 template <int NF>
@@ -279,7 +279,7 @@ __device__ __forceinline__ void core_tile_bf16x3_dma(int r1, int r2, int r3, int
             const int blk = w + 4 * i;                    // 0 .. 2 TM / 16 - 1 over both planes
             const int plane = blk / (TM / 16), rb = (blk % (TM / 16)) * 16;
             const int r = rb + (lane >> 2);
-            const int q = (lane & 3) ^ ((r >> 2) & 3);
+            const int q = lds_slot(r, lane & 3);
             const __bf16* src = (plane ? Al : Ah) + (int64_t)(m0 + r) * Kp + k0 + 8 * q;
             __builtin_amdgcn_global_load_lds((const void*)src, (lds_void_ptr)(st + plane * S::A_BYTES + rb * 64), 16,
                                              0, 0);
@@ -341,7 +341,7 @@ __device__ __forceinline__ void core_tile_bf16x3_dma(int r1, int r2, int r3, int
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             const int row = 16 * f + (lane & 15);
-            const int off = row * 64 + 16 * (kq ^ ((row >> 2) & 3));
+            const int off = row * 64 + 16 * lds_slot(row, kq);
             const bf8_t ah = *reinterpret_cast<const bf8_t*>(st + off);
             const bf8_t al = *reinterpret_cast<const bf8_t*>(st + S::A_BYTES + off);
 #pragma unroll

@@ -30,7 +30,7 @@ union LpChunk {
     } f32;
     struct {
         // row r (64 bytes: 32 bf16 k values) of a plane; its 8-k group q at slot
-        // q ^ ((r >> 2) & 3)
+        // lds_slot(r, q)
         char ah[GT * 64], al[GT * 64], bh[GT * 64], bl[GT * 64];
     } b16;
 };
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(256) void k_gram_lp(int64_t n_pad, int64_t R_pad, c
             }
         } else {
             bf8_t h, l;
-            const int off = lr * 64 + 16 * (lq ^ ((lr >> 2) & 3));
+            const int off = lr * 64 + 16 * lds_slot(lr, lq);
             split8(xa, h, l);
             *reinterpret_cast<bf8_t*>(S.b16.ah + off) = h;
             *reinterpret_cast<bf8_t*>(S.b16.al + off) = l;
@@ -138,8 +138,8 @@ __global__ __launch_bounds__(256) void k_gram_lp(int64_t n_pad, int64_t R_pad, c
 #pragma unroll
             for (int f = 0; f < 2; ++f) {
                 const int ra = wr + 16 * f + (lane & 15), rb = wc + 16 * f + (lane & 15);
-                const int oa = ra * 64 + 16 * ((lane >> 4) ^ ((ra >> 2) & 3));
-                const int ob = rb * 64 + 16 * ((lane >> 4) ^ ((rb >> 2) & 3));
+                const int oa = ra * 64 + 16 * lds_slot(ra, lane >> 4);
+                const int ob = rb * 64 + 16 * lds_slot(rb, lane >> 4);
                 ah[f] = *reinterpret_cast<const bf8_t*>(S.b16.ah + oa);
                 al[f] = *reinterpret_cast<const bf8_t*>(S.b16.al + oa);
                 bh[f] = *reinterpret_cast<const bf8_t*>(S.b16.bh + ob);
