@@ -1009,6 +1009,7 @@ __global__ __launch_bounds__(BT_THREADS) void k_apply_wy(BtJobs J) {
     extern __shared__ double Xs[];              // mr x 16 when XL
     __shared__ double P[BT_H][NB][17];
     __shared__ double W2[NB][17];
+    __shared__ double Ts[NB][NB + 1];           // T_b of the current block, Ts[q][j] = T[j, q]
     const BtJob& jb = J.job[blockIdx.y];
     const int m = jb.m, ld = jb.ld, ldo = jb.ldo, nrows = jb.nrows;
     const int r = jb.r_dev ? min(*jb.r_dev, jb.r) : jb.r;
@@ -1033,6 +1034,11 @@ __global__ __launch_bounds__(BT_THREADS) void k_apply_wy(BtJobs J) {
     const int nblk = m >= 3 ? (m - 2 + NB - 1) / NB : 0;
     for (int b = nblk - 1; b >= 0; --b) {
         const int k0 = NB * b, kc = min(NB, (m - 2) - k0);
+        // T_b into LDS (used after the barrier that ends pass 1)
+        {
+            const double* T = jb.Tw + (int64_t)b * NB * NB;
+            for (int e = t; e < NB * NB; e += BT_THREADS) Ts[e / NB][e % NB] = T[e];
+        }
         // pass 1: wave w -> tile jt = w & 1 of Wm and the groups of 4 rows h, h + BT_H,
         // h + 2 BT_H, .. (h = w / 2); the reflector values of the next 8 groups are
         // loaded before this step's MFMAs, which alternate between two accumulators
@@ -1068,20 +1074,21 @@ __global__ __launch_bounds__(BT_THREADS) void k_apply_wy(BtJobs J) {
             for (int q = 0; q < 4; ++q) P[h][16 * jt + c_row64(lane, q)][c_col(lane)] = acc0[q] + acc1[q];
         }
         __syncthreads();
-        // W2 = T_b Wm (T_b upper triangular, column-major)
-        {
-            const double* T = jb.Tw + (int64_t)b * NB * NB;
-            for (int e = t; e < NB * CW; e += BT_THREADS) {
-                const int j = e % NB, c = e / NB;
-                double s = 0.0;
-                for (int q = j; q < kc; ++q) {
-                    double pq = 0.0;
+        // Wm = the sum of the wave groups' partial products (into P[0]), then
+        // W2 = T_b Wm (T_b upper triangular), both from LDS
+        for (int e = t; e < NB * CW; e += BT_THREADS) {
+            const int q = e % NB, c = e / NB;
+            double pq = P[0][q][c];
 #pragma unroll
-                    for (int hh = 0; hh < BT_H; ++hh) pq += P[hh][q][c];
-                    s += T[j + q * NB] * pq;
-                }
-                W2[j][c] = s;
-            }
+            for (int hh = 1; hh < BT_H; ++hh) pq += P[hh][q][c];
+            P[0][q][c] = pq;
+        }
+        __syncthreads();
+        for (int e = t; e < NB * CW; e += BT_THREADS) {
+            const int j = e % NB, c = e / NB;
+            double s = 0.0;
+            for (int q = j; q < kc; ++q) s += Ts[q][j] * P[0][q][c];
+            W2[j][c] = s;
         }
         __syncthreads();
         // pass 2: X[i, :] -= V_b[i, :] W2 for rows k0+1 .. m-1, 16-row tiles over the waves;
