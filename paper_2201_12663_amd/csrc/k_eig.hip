@@ -645,31 +645,57 @@ __global__ __launch_bounds__(256) void k_dc_prep(DCArgs a) {
         h->nrot = 0;
     }
     if (t == 0 && s_rot) {
+        // the scan over the undeflated entries (keep_s, in order: an entry that is
+        // not yet visited still has its original z, so the parallel deflation test
+        // holds for it); prev's values travel in registers, and the next eight
+        // entries are read from LDS ahead of the dependent arithmetic.  keep_s is
+        // rewritten in place: position k < q when entry q is read.
         double* rc = ns_rc(a, node);
         int* rp = ns_rp(a, node);
         double* Dl = key;
-        int k = 0, nrot = 0, prev = -1;
-        for (int i = 0; i < n; ++i) {
-            if (fabs(rho * zs[i]) <= tol) continue;   // deflated: eigenpair (D_i, e_i)
-            if (prev < 0) { prev = i; continue; }
-            const double tt = hypot(zs[prev], zs[i]);
-            const double c = zs[i] / tt, s = -zs[prev] / tt;
-            if (fabs((Dl[i] - Dl[prev]) * c * s) <= tol) {
-                // close poles: rotate so that z[prev] = 0 and deflate prev
-                const double dp = Dl[prev], di = Dl[i];
-                Dl[prev] = dp * c * c + di * s * s;
-                Dl[i] = dp * s * s + di * c * c;
-                zs[i] = tt;
-                zs[prev] = 0.0;
-                rp[2 * nrot] = prev;
-                rp[2 * nrot + 1] = i;
-                rc[2 * nrot] = c;
-                rc[2 * nrot + 1] = s;
-                ++nrot;
-                prev = i;
-            } else {
-                keep_s[k++] = prev;
-                prev = i;
+        const int K0 = s_k;
+        int k = 0, nrot = 0;
+        int prev = K0 > 0 ? keep_s[0] : -1;
+        double zp = prev >= 0 ? zs[prev] : 0.0, dp = prev >= 0 ? Dl[prev] : 0.0;
+        for (int q0 = 1; q0 < K0; q0 += 8) {
+            const int cnt = min(8, K0 - q0);
+            int ii[8];
+            double zz[8], dv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) ii[u] = u < cnt ? keep_s[q0 + u] : 0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                zz[u] = zs[ii[u]];
+                dv[u] = Dl[ii[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (u >= cnt) break;
+                const int i = ii[u];
+                const double zi = zz[u], di = dv[u];
+                const double tt = hypot(zp, zi);
+                const double c = zi / tt, s = -zp / tt;
+                if (fabs((di - dp) * c * s) <= tol) {
+                    // close poles: rotate so that z[prev] = 0 and deflate prev
+                    const double dnew = dp * s * s + di * c * c;
+                    Dl[prev] = dp * c * c + di * s * s;
+                    Dl[i] = dnew;
+                    zs[i] = tt;
+                    zs[prev] = 0.0;
+                    rp[2 * nrot] = prev;
+                    rp[2 * nrot + 1] = i;
+                    rc[2 * nrot] = c;
+                    rc[2 * nrot + 1] = s;
+                    ++nrot;
+                    prev = i;
+                    zp = tt;
+                    dp = dnew;
+                } else {
+                    keep_s[k++] = prev;
+                    prev = i;
+                    zp = zi;
+                    dp = di;
+                }
             }
         }
         if (prev >= 0) keep_s[k++] = prev;
