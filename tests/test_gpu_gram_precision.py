@@ -141,3 +141,23 @@ def test_gram_precision_option_is_checked():
     from paper_2201_12663_amd import rhosvd
     with pytest.raises(rhosvd.RhosvdError):
         rhosvd.Reducer(gram_precision=3)
+
+
+def test_with_als_sweeps_and_certificate(orc):
+    """ALS sweeps start from the Rayleigh-Ritz Z at its ranks and only lower the
+    error; the certificate (formed on the final Z) equals the oracle's certificate
+    of that Z and stays within the reported bound."""
+    ci = inputs.newton_centres(5, n=256, n_centres=32, eps=1e-4)
+    g0 = gc.run_gpu(ci, "fp64", gram_precision="fp32")
+    g1 = gc.run_gpu(ci, "fp64", gram_precision="fp32", als_sweeps=1, certificate=True)
+    assert g1["ranks"] == g0["ranks"]
+    Ut, xip, _, _ = orc.normalize(ci.U, ci.xi)
+    e0 = orc.error_gram(Ut, xip, g0["Z"])
+    e1 = orc.error_gram(Ut, xip, g1["Z"])
+    a = g1["report"]["a_norm"]
+    _flush(f"ALS after the Rayleigh-Ritz Z: error {e0 / a:.4e} -> {e1 / a:.4e} |A|")
+    assert e1 <= e0 * (1 + 1e-9) + 1e-12 * a
+    c = g1["report"]["certificate"]
+    co = orc.certificate(Ut, xip, g1["Z"])
+    assert abs(c - co) <= 1e-8 * co + 1e-13 * float(np.sum(np.abs(xip)))
+    assert c <= g1["report"]["bound"] * (1 + 1e-9)
