@@ -115,7 +115,7 @@ template <typename T, typename O, bool FLUSH, int NF>
 __device__ __forceinline__ void core_tile_std(int r1, int r2, int r3, int ld1, int ld2, int ld3, int64_t Kp,
                               const T* __restrict__ V1, const T* __restrict__ V2, const T* __restrict__ V3,
                               const double* __restrict__ xip, O* __restrict__ beta, int N2T, int N3T,
-                              int64_t tile) {
+                              int64_t tile, int mbase = 0) {
     constexpr int TM = 16 * NF, KC = 16;
     constexpr int PA = TM * KC / 256, AS = 256 / TM;   // A entries per thread, their k stride
     typedef typename MF<T>::acc_t acc_t;
@@ -125,7 +125,7 @@ __device__ __forceinline__ void core_tile_std(int r1, int r2, int r3, int ld1, i
     __shared__ T s3[2][KC][TN3];
     int mt, n2t, n3t;
     tile_coords(tile, N2T, N3T, mt, n2t, n3t);
-    const int m0 = mt * TM, b2 = n2t * TN2, b3 = n3t * TN3;
+    const int m0 = mbase + mt * TM, b2 = n2t * TN2, b3 = n3t * TN3;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
 
     // staging maps: A TM x 16 (PA per thread), V2/V3 16 x 16 (1 each)
@@ -210,10 +210,10 @@ __global__ __launch_bounds__(256, 2) void k_core_std(int r1, int r2, int r3, int
                                                   int64_t Kp, const T* __restrict__ V1,
                                                   const T* __restrict__ V2, const T* __restrict__ V3,
                                                   const double* __restrict__ xip, O* __restrict__ beta,
-                                                  int MT, int N2T, int N3T, int64_t per) {
+                                                  int MT, int N2T, int N3T, int64_t per, int mbase) {
     const int64_t tile = xcd_tile(blockIdx.x, per);
     if (tile >= (int64_t)MT * N2T * N3T) return;
-    core_tile_std<T, O, FLUSH, NF>(r1, r2, r3, ld1, ld2, ld3, Kp, V1, V2, V3, xip, beta, N2T, N3T, tile);
+    core_tile_std<T, O, FLUSH, NF>(r1, r2, r3, ld1, ld2, ld3, Kp, V1, V2, V3, xip, beta, N2T, N3T, tile, mbase);
 }
 
 // ---------------------------------------------------------------------------
@@ -259,13 +259,14 @@ template <typename O, bool FLUSH, int NF>
 __device__ __forceinline__ void core_tile_bf16x3_dma(int r1, int r2, int r3, int ld2, int ld3, int64_t Kp,
                                                      const __bf16* __restrict__ Ah, const __bf16* __restrict__ Al,
                                                      const float* __restrict__ V2, const float* __restrict__ V3,
-                                                     O* __restrict__ beta, int N2T, int N3T, int64_t tile) {
+                                                     O* __restrict__ beta, int N2T, int N3T, int64_t tile,
+                                                     int mbase = 0) {
     typedef DmaStage<NF> S;
     constexpr int TM = S::TM, NS = 3;
     __shared__ __attribute__((aligned(1024))) char ring[NS * S::BYTES];
     int mt, n2t, n3t;
     tile_coords(tile, N2T, N3T, mt, n2t, n3t);
-    const int m0 = mt * TM, b2 = n2t * TN2, b3 = n3t * TN3;
+    const int m0 = mbase + mt * TM, b2 = n2t * TN2, b3 = n3t * TN3;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int64_t nchunk = Kp / BKC;
 
@@ -388,10 +389,11 @@ template <typename O, bool FLUSH, int NF>
 __global__ __launch_bounds__(256, 2) void k_core_bf16x3(int r1, int r2, int r3, int ld2, int ld3, int64_t Kp,
                                                      const __bf16* __restrict__ Ah, const __bf16* __restrict__ Al,
                                                      const float* __restrict__ V2, const float* __restrict__ V3,
-                                                     O* __restrict__ beta, int MT, int N2T, int N3T, int64_t per) {
+                                                     O* __restrict__ beta, int MT, int N2T, int N3T, int64_t per,
+                                                     int mbase) {
     const int64_t tile = xcd_tile(blockIdx.x, per);
     if (tile >= (int64_t)MT * N2T * N3T) return;
-    core_tile_bf16x3_dma<O, FLUSH, NF>(r1, r2, r3, ld2, ld3, Kp, Ah, Al, V2, V3, beta, N2T, N3T, tile);
+    core_tile_bf16x3_dma<O, FLUSH, NF>(r1, r2, r3, ld2, ld3, Kp, Ah, Al, V2, V3, beta, N2T, N3T, tile, mbase);
 }
 
 
@@ -513,29 +515,31 @@ __global__ __launch_bounds__(256, PREC == 2 ? 2 : 1) void k_core_persist_b(const
 }  // namespace
 
 template <typename O, bool FLUSH, int NF>
-static void launch_core_t(const CoreArgs& a, dim3 grid, int MT, int N2T, int N3T, int64_t per, hipStream_t st) {
+static void launch_core_t(const CoreArgs& a, dim3 grid, int MT, int N2T, int N3T, int64_t per, int mbase,
+                          hipStream_t st) {
     O* beta = (O*)a.beta;
     if (a.prec == 0) {
         hipLaunchKernelGGL((k_core_std<double, O, false, 4>), grid, dim3(256), 0, st, a.r[0], a.r[1], a.r[2],
                            a.r_pad[0], a.r_pad[1], a.r_pad[2], a.R_pad, (const double*)a.V[0],
-                           (const double*)a.V[1], (const double*)a.V[2], a.xip, beta, MT, N2T, N3T, per);
+                           (const double*)a.V[1], (const double*)a.V[2], a.xip, beta, MT, N2T, N3T, per, mbase);
     } else if (a.prec == 1) {
         hipLaunchKernelGGL((k_core_std<float, O, FLUSH, NF>), grid, dim3(256), 0, st, a.r[0], a.r[1], a.r[2],
                            a.r_pad[0], a.r_pad[1], a.r_pad[2], a.R_pad, (const float*)a.V[0],
-                           (const float*)a.V[1], (const float*)a.V[2], a.xip, beta, MT, N2T, N3T, per);
+                           (const float*)a.V[1], (const float*)a.V[2], a.xip, beta, MT, N2T, N3T, per, mbase);
     } else {
         const __bf16* Ah = (const __bf16*)a.Asplit;
         hipLaunchKernelGGL((k_core_bf16x3<O, FLUSH, NF>), grid, dim3(256), 0, st, a.r[0], a.r[1], a.r[2],
                            a.r_pad[1], a.r_pad[2], a.R_pad, Ah, Ah + (int64_t)a.r_pad[0] * a.R_pad,
-                           (const float*)a.V[1], (const float*)a.V[2], beta, MT, N2T, N3T, per);
+                           (const float*)a.V[1], (const float*)a.V[2], beta, MT, N2T, N3T, per, mbase);
     }
 }
 
 template <typename O, bool FLUSH>
-static void launch_core_nf(const CoreArgs& a, int nf, dim3 grid, int MT, int N2T, int N3T, int64_t per,
-                           hipStream_t st) {
-    if (nf == 8) launch_core_t<O, FLUSH, 8>(a, grid, MT, N2T, N3T, per, st);
-    else launch_core_t<O, FLUSH, 4>(a, grid, MT, N2T, N3T, per, st);
+static void launch_core_nf(const CoreArgs& a, int nf, int MT, int N2T, int N3T, int mbase, hipStream_t st) {
+    const int64_t per = ceil_div((int64_t)MT * N2T * N3T, NXCD);
+    const dim3 grid((unsigned)(per * NXCD));
+    if (nf == 8) launch_core_t<O, FLUSH, 8>(a, grid, MT, N2T, N3T, per, mbase, st);
+    else launch_core_t<O, FLUSH, 4>(a, grid, MT, N2T, N3T, per, mbase, st);
 }
 
 int core_tile_default(int prec) { return (prec & 3) == 2 ? 128 : 64; }
@@ -554,17 +558,28 @@ hipError_t launch_core(const CoreArgs& a, hipStream_t st) {
     const int MT = (int)ceil_div(a.r[0], TMv), N2T = (int)ceil_div(a.r[1], TN2), N3T = (int)ceil_div(a.r[2], TN3);
     // the kernels read whole tiles: padded rows must exist (and be zero)
     if (a.r_pad[0] < MT * TMv || a.r_pad[1] < N2T * TN2 || a.r_pad[2] < N3T * TN3) return hipErrorInvalidValue;
-    const int64_t ntile = (int64_t)MT * N2T * N3T;
-    const int64_t per = ceil_div(ntile, NXCD);
-    dim3 grid((unsigned)(per * NXCD));
     const bool flush = a.R_pad > KFLUSH;   // the hand-over variants only where they act
-    const int nf = TMv / 16;
-    if (a.beta_f32) {
-        if (flush) launch_core_nf<float, true>(a, nf, grid, MT, N2T, N3T, per, st);
-        else launch_core_nf<float, false>(a, nf, grid, MT, N2T, N3T, per, st);
+    // 128-row tiles whose last row block holds at most 64 rows: that block runs as
+    // 64-row tiles in a second launch (656 rows: 5 x 128 + 1 x 64 row tiles, 704
+    // rows of MFMA work instead of 768)
+    const int rem = a.r[0] - (MT - 1) * TMv;
+    const bool split_last = TMv == 128 && MT > 1 && rem <= 64;
+    auto go = [&](int nf, int mt, int mbase) {
+        if (a.beta_f32) {
+            if (flush) launch_core_nf<float, true>(a, nf, mt, N2T, N3T, mbase, st);
+            else launch_core_nf<float, false>(a, nf, mt, N2T, N3T, mbase, st);
+        } else {
+            if (flush) launch_core_nf<double, true>(a, nf, mt, N2T, N3T, mbase, st);
+            else launch_core_nf<double, false>(a, nf, mt, N2T, N3T, mbase, st);
+        }
+    };
+    if (split_last) {
+        go(8, MT - 1, 0);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        go(4, 1, (MT - 1) * TMv);
     } else {
-        if (flush) launch_core_nf<double, true>(a, nf, grid, MT, N2T, N3T, per, st);
-        else launch_core_nf<double, false>(a, nf, grid, MT, N2T, N3T, per, st);
+        go(TMv / 16, MT, 0);
     }
     return hipGetLastError();
 }
