@@ -15,9 +15,10 @@ library's report), the core part is measured against the FP64 path's core, and
 the two are orthogonal.  The rate is the fastest of three modes that reproduce
 the sequential run's ranks and core bit for bit: one reduction at a time; two in
 flight (one host thread alternating two handles on two streams, so that the
-eigensolver phase of one overlaps the core of the other); four in flight (two
-host threads with two handles each, so that two eigensolver phases overlap as
-well).  Every mode's rate and the one-at-a-time latency are in "paths".
+eigensolver phase of one overlaps the core of the other); four in flight (four
+host threads with a handle each: a thread waits inside a reduction for its own
+eigensolver only, so another reduction's eigensolver is always queued).  Every
+mode's rate and the one-at-a-time latency are in "paths".
 
 The line also carries "learned": fresh problems of the rank-proposal workloads
 through the learned path (trained network, certified range finder, fallback)
@@ -517,8 +518,8 @@ def main():
                              refine_used=rep["refine_used"], anorm_method=rep["anorm_method"])
         betas[prec] = beta
         # the same path with reductions in flight: one host thread over two handles
-        # (two in flight), and two host threads over two handles each (four)
-        for key, th, ph in (("pipelined", 1, 2), ("inflight4", 2, 2)):
+        # (two in flight), and four host threads with a handle each (four)
+        for key, th, ph in (("pipelined", 1, 2), ("inflight4", 4, 1)):
             pms, pdiff, pseen = time_inflight(prec, U, xi, ci.eps, ranks, 2 * args.steps, args.warmup, beta, th, ph)
             results[prec].update({f"{key}_ms_per_reduction": pms, f"{key}_reductions_per_s": 1e3 / pms,
                                   f"{key}_max_abs_diff": pdiff, f"{key}_ranks": [list(r) for r in pseen]})
@@ -571,7 +572,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "n": 1024, "R": 4096, "eps": 1e-5, "precision": best,
                    "ranks": rb["ranks"], "parallelism": "single-gpu",
-                   "in_flight": in_flight, "host_threads": 2 if in_flight == 4 else 1},
+                   "in_flight": in_flight, "host_threads": 4 if in_flight == 4 else 1},
         "paths": results,
         # against the plain FP64 path's fastest mode (each path at its own best)
         "speedup_vs_plain_fp64": (rate / max(results["fp64"].get(k, 0.0) for k in
