@@ -313,9 +313,10 @@ __device__ __forceinline__ void core_tile_bf16x3_dma(int r1, int r2, int r3, int
         // wave's own LDS reads are done, then all waves meet: chunk c is visible
         // to all and the stage of chunk c-1 is free
         if (c + 1 < nchunk) {
-            static_assert(S::LOADS == 3 || S::LOADS == 5, "vmcnt of one chunk");
+            static_assert(S::LOADS == 2 || S::LOADS == 3 || S::LOADS == 5, "vmcnt of one chunk");
             if constexpr (S::LOADS == 5) asm volatile("s_waitcnt vmcnt(5) lgkmcnt(0)\n\ts_barrier" ::: "memory");
-            else asm volatile("s_waitcnt vmcnt(3) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+            else if constexpr (S::LOADS == 3) asm volatile("s_waitcnt vmcnt(3) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+            else asm volatile("s_waitcnt vmcnt(2) lgkmcnt(0)\n\ts_barrier" ::: "memory");
         } else {
             asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
         }
@@ -518,7 +519,12 @@ template <typename O, bool FLUSH, int NF>
 static void launch_core_t(const CoreArgs& a, dim3 grid, int MT, int N2T, int N3T, int64_t per, int mbase,
                           hipStream_t st) {
     O* beta = (O*)a.beta;
-    if (a.prec == 0) {
+    if constexpr (NF == 2) {   // 32-row tiles: the last row block of the BF16x3 core only
+        const __bf16* Ah = (const __bf16*)a.Asplit;
+        hipLaunchKernelGGL((k_core_bf16x3<O, FLUSH, 2>), grid, dim3(256), 0, st, a.r[0], a.r[1], a.r[2],
+                           a.r_pad[1], a.r_pad[2], a.R_pad, Ah, Ah + (int64_t)a.r_pad[0] * a.R_pad,
+                           (const float*)a.V[1], (const float*)a.V[2], beta, MT, N2T, N3T, per, mbase);
+    } else if (a.prec == 0) {
         hipLaunchKernelGGL((k_core_std<double, O, false, 4>), grid, dim3(256), 0, st, a.r[0], a.r[1], a.r[2],
                            a.r_pad[0], a.r_pad[1], a.r_pad[2], a.R_pad, (const double*)a.V[0],
                            (const double*)a.V[1], (const double*)a.V[2], a.xip, beta, MT, N2T, N3T, per, mbase);
@@ -539,7 +545,8 @@ static void launch_core_nf(const CoreArgs& a, int nf, int MT, int N2T, int N3T, 
     const int64_t per = ceil_div((int64_t)MT * N2T * N3T, NXCD);
     const dim3 grid((unsigned)(per * NXCD));
     if (nf == 8) launch_core_t<O, FLUSH, 8>(a, grid, MT, N2T, N3T, per, mbase, st);
-    else launch_core_t<O, FLUSH, 4>(a, grid, MT, N2T, N3T, per, mbase, st);
+    else if (nf == 4) launch_core_t<O, FLUSH, 4>(a, grid, MT, N2T, N3T, per, mbase, st);
+    else launch_core_t<O, FLUSH, 2>(a, grid, MT, N2T, N3T, per, mbase, st);
 }
 
 int core_tile_default(int prec) { return (prec & 3) == 2 ? 128 : 64; }
@@ -559,11 +566,17 @@ hipError_t launch_core(const CoreArgs& a, hipStream_t st) {
     // the kernels read whole tiles: padded rows must exist (and be zero)
     if (a.r_pad[0] < MT * TMv || a.r_pad[1] < N2T * TN2 || a.r_pad[2] < N3T * TN3) return hipErrorInvalidValue;
     const bool flush = a.R_pad > KFLUSH;   // the hand-over variants only where they act
-    // 128-row tiles whose last row block holds at most 64 rows: that block runs as
-    // 64-row tiles in a second launch (656 rows: 5 x 128 + 1 x 64 row tiles, 704
-    // rows of MFMA work instead of 768)
+    // a last row block that is mostly padding runs in a second launch with smaller
+    // tiles: at most 32 rows as 32-row tiles (BF16x3), else at most 64 rows of a
+    // 128-row tile as 64-row tiles (656 rows at 128: 5 x 128 + 1 x 32 row tiles,
+    // 672 rows of MFMA work instead of 768)
     const int rem = a.r[0] - (MT - 1) * TMv;
-    const bool split_last = TMv == 128 && MT > 1 && rem <= 64;
+    int nf_last = 0;
+    if (MT > 1) {
+        if (a.prec == 2 && rem <= 32) nf_last = 2;
+        else if (TMv == 128 && rem <= 64) nf_last = 4;
+    }
+    const bool split_last = nf_last != 0;
     auto go = [&](int nf, int mt, int mbase) {
         if (a.beta_f32) {
             if (flush) launch_core_nf<float, true>(a, nf, mt, N2T, N3T, mbase, st);
@@ -577,7 +590,7 @@ hipError_t launch_core(const CoreArgs& a, hipStream_t st) {
         go(8, MT - 1, 0);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        go(4, 1, (MT - 1) * TMv);
+        go(nf_last, 1, (MT - 1) * TMv);
     } else {
         go(TMv / 16, MT, 0);
     }
