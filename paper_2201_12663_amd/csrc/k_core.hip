@@ -577,6 +577,8 @@ hipError_t launch_core(const CoreArgs& a, hipStream_t st) {
         else if (TMv == 128 && rem <= 64) nf_last = 4;
     }
     const bool split_last = nf_last != 0;
+    // every launch reads rows mbase .. mbase + 16 nf mt - 1 of the A operand
+    if (split_last && (MT - 1) * TMv + 16 * nf_last > a.r_pad[0]) return hipErrorInvalidValue;
     auto go = [&](int nf, int mt, int mbase) {
         if (a.beta_f32) {
             if (flush) launch_core_nf<float, true>(a, nf, mt, N2T, N3T, mbase, st);
@@ -587,7 +589,7 @@ hipError_t launch_core(const CoreArgs& a, hipStream_t st) {
         }
     };
     if (split_last) {
-        go(8, MT - 1, 0);
+        go(TMv / 16, MT - 1, 0);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         go(nf_last, 1, (MT - 1) * TMv);
