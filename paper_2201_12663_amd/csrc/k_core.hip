@@ -519,11 +519,17 @@ template <typename O, bool FLUSH, int NF>
 static void launch_core_t(const CoreArgs& a, dim3 grid, int MT, int N2T, int N3T, int64_t per, int mbase,
                           hipStream_t st) {
     O* beta = (O*)a.beta;
-    if constexpr (NF == 2) {   // 32-row tiles: the last row block of the BF16x3 core only
-        const __bf16* Ah = (const __bf16*)a.Asplit;
-        hipLaunchKernelGGL((k_core_bf16x3<O, FLUSH, 2>), grid, dim3(256), 0, st, a.r[0], a.r[1], a.r[2],
-                           a.r_pad[1], a.r_pad[2], a.R_pad, Ah, Ah + (int64_t)a.r_pad[0] * a.R_pad,
-                           (const float*)a.V[1], (const float*)a.V[2], beta, MT, N2T, N3T, per, mbase);
+    if constexpr (NF == 2) {   // 32-row tiles: the last row block of the FP32 and BF16x3 cores only
+        if (a.prec == 1) {
+            hipLaunchKernelGGL((k_core_std<float, O, FLUSH, 2>), grid, dim3(256), 0, st, a.r[0], a.r[1], a.r[2],
+                               a.r_pad[0], a.r_pad[1], a.r_pad[2], a.R_pad, (const float*)a.V[0],
+                               (const float*)a.V[1], (const float*)a.V[2], a.xip, beta, MT, N2T, N3T, per, mbase);
+        } else {
+            const __bf16* Ah = (const __bf16*)a.Asplit;
+            hipLaunchKernelGGL((k_core_bf16x3<O, FLUSH, 2>), grid, dim3(256), 0, st, a.r[0], a.r[1], a.r[2],
+                               a.r_pad[1], a.r_pad[2], a.R_pad, Ah, Ah + (int64_t)a.r_pad[0] * a.R_pad,
+                               (const float*)a.V[1], (const float*)a.V[2], beta, MT, N2T, N3T, per, mbase);
+        }
     } else if (a.prec == 0) {
         hipLaunchKernelGGL((k_core_std<double, O, false, 4>), grid, dim3(256), 0, st, a.r[0], a.r[1], a.r[2],
                            a.r_pad[0], a.r_pad[1], a.r_pad[2], a.R_pad, (const double*)a.V[0],
@@ -567,13 +573,13 @@ hipError_t launch_core(const CoreArgs& a, hipStream_t st) {
     if (a.r_pad[0] < MT * TMv || a.r_pad[1] < N2T * TN2 || a.r_pad[2] < N3T * TN3) return hipErrorInvalidValue;
     const bool flush = a.R_pad > KFLUSH;   // the hand-over variants only where they act
     // a last row block that is mostly padding runs in a second launch with smaller
-    // tiles: at most 32 rows as 32-row tiles (BF16x3), else at most 64 rows of a
-    // 128-row tile as 64-row tiles (656 rows at 128: 5 x 128 + 1 x 32 row tiles,
+    // tiles: at most 32 rows as 32-row tiles (FP32, BF16x3), else at most 64 rows of
+    // a 128-row tile as 64-row tiles (656 rows at 128: 5 x 128 + 1 x 32 row tiles,
     // 672 rows of MFMA work instead of 768)
     const int rem = a.r[0] - (MT - 1) * TMv;
     int nf_last = 0;
     if (MT > 1) {
-        if (a.prec == 2 && rem <= 32) nf_last = 2;
+        if (a.prec != 0 && rem <= 32) nf_last = 2;
         else if (TMv == 128 && rem <= 64) nf_last = 4;
     }
     const bool split_last = nf_last != 0;
