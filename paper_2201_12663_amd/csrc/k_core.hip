@@ -575,12 +575,26 @@ hipError_t launch_core(const CoreArgs& a, hipStream_t st) {
     // a last row block that is mostly padding runs in a second launch with smaller
     // tiles: at most 32 rows as 32-row tiles (FP32, BF16x3), else at most 64 rows of
     // a 128-row tile as 64-row tiles (656 rows at 128: 5 x 128 + 1 x 32 row tiles,
-    // 672 rows of MFMA work instead of 768)
+    // 672 rows of MFMA work instead of 768).  Only where the launches run many
+    // rounds of workgroups: the second launch's last round is a tail of its own, and
+    // with few tiles per row block it costs more than the padding rows (274 x 271 x
+    // 270 at R = 90000, 289 tiles per row block: FP32 core 38.2 -> 40.7 ms split).
+    // Rounds of two workgroups per CU; a smaller tile's round counted as half.
     const int rem = a.r[0] - (MT - 1) * TMv;
     int nf_last = 0;
     if (MT > 1) {
         if (a.prec != 0 && rem <= 32) nf_last = 2;
         else if (TMv == 128 && rem <= 64) nf_last = 4;
+    }
+    if (nf_last) {
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+            ncu = 256;
+        const int64_t slots = 2 * (int64_t)ncu, n23 = (int64_t)N2T * N3T;
+        const int64_t whole = ceil_div((int64_t)MT * n23, slots);
+        const int64_t split2 = 2 * ceil_div((int64_t)(MT - 1) * n23, slots) + ceil_div(n23, slots);
+        if (split2 >= 2 * whole) nf_last = 0;   // split rounds (x2) not fewer than whole rounds (x2)
     }
     const bool split_last = nf_last != 0;
     // every launch reads rows mbase .. mbase + 16 nf mt - 1 of the A operand

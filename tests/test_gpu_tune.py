@@ -66,17 +66,18 @@ def test_every_tile_matches_oracle(orc, prec, tile, name, make):
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 @pytest.mark.parametrize("tile", [64, 128])
-def test_split_last_row_block_matches_oracle(orc, prec, tile):
-    """r1 = 145: the last row block holds 17 rows, so the core runs in two launches
-    at either tile, the second with 32-row tiles on rows 128..159 (64-row tile) or
-    128..159 of the second 128-row block.  Every slab against the oracle's core of
-    the path's own Z."""
+def test_ragged_last_row_block_matches_oracle(orc, prec, tile):
+    """r1 = 145: the last row block holds 17 rows (at 64 and at 128 rows per tile).
+    With 81 tiles per row block the core stays one launch; the split of such a
+    block into 32-row tiles, taken where the launch runs many rounds of workgroups,
+    is checked at the full 1024 x 4096 size (test_gpu_parity).  Every slab against
+    the oracle's core of the path's own Z."""
     ci = inputs.newton_centres(3, n=200, n_centres=24, eps=1e-4)
     (ranks, Z, beta, used), = run_single(ci, prec, tile)
     assert used == tile
     assert 128 < ranks[0] <= 160, ranks
     e = oracle_core_error(orc, ci, Z, beta, prec)
-    print(f"split last row block {prec} tile {tile}: ranks {ranks} core error {e:.3e} |xi'|", flush=True)
+    print(f"ragged last row block {prec} tile {tile}: ranks {ranks} core error {e:.3e} |xi'|", flush=True)
     assert e <= TOL[prec]
 
 
