@@ -8,13 +8,18 @@
 // operands, on the caller's stream with HIP events, alternating the candidates
 // over two rounds and keeping each one's fastest launch, and caches the winner
 // per shape class: precision, output type, long-contraction variant, r1 in
-// steps of 32, r2*r3 and R_pad in quarter octaves.  The FP64 core has one tile.
+// steps of 32, r2*r3 and R_pad in quarter octaves.  Each handle keeps its own
+// cache and also consults one shared by every handle of the process (per
+// device), so a shape class is timed once per process: later handles, possibly
+// created while others load the GPU, take the first measurement.  The FP64 core
+// has one tile.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <array>
 #include <cmath>
 #include <map>
+#include <mutex>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -39,6 +44,25 @@ int core_tuner_lookup(const CoreTuner* T, const std::array<int64_t, 6>& key) {
 }
 
 void core_tuner_store(CoreTuner* T, const std::array<int64_t, 6>& key, int tile) { T->best[key] = tile; }
+
+// the process-wide cache: shape class and device -> tile
+static std::mutex g_tune_mu;
+static std::map<std::pair<int, std::array<int64_t, 6>>, int> g_tune_best;
+
+static int shared_lookup(const std::array<int64_t, 6>& key) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune_best.find({dev, key});
+    return it == g_tune_best.end() ? 0 : it->second;
+}
+
+static void shared_store(const std::array<int64_t, 6>& key, int tile) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune_best.emplace(std::make_pair(dev, key), tile);   // the first measurement stays
+}
 
 hipError_t time_candidates(const int* tiles, int ncand, const std::function<hipError_t(int)>& launch,
                            hipStream_t st, int* best) {
@@ -86,7 +110,8 @@ hipError_t launch_core_tuned(CoreTuner* T, CoreArgs a, hipStream_t st, int* used
     }
     const auto key = core_tune_key(a.prec, a.beta_f32, a.R_pad > core_flush_span(), a.r[0],
                                    (int64_t)a.r[1] * a.r[2], a.R_pad);
-    const int known = core_tuner_lookup(T, key);
+    int known = core_tuner_lookup(T, key);
+    if (!known && (known = shared_lookup(key)) != 0) core_tuner_store(T, key, known);
     if (known) {
         a.tile = known;
         *used = known;
@@ -104,6 +129,7 @@ hipError_t launch_core_tuned(CoreTuner* T, CoreArgs a, hipStream_t st, int* used
         st, &best);
     if (e != hipSuccess) return e;
     core_tuner_store(T, key, best);
+    shared_store(key, best);
     *used = best;
     return hipSuccess;
 }

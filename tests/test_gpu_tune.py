@@ -88,10 +88,13 @@ def test_tuned_tile_reproduces_the_candidate(prec):
     t = tuned[0][3]
     assert t in (64, 128)
     assert tuned[1][3] == t                      # the shape class is cached
+    (_, _, b_other, t_other), = run_single(ci, prec, 0)
+    assert t_other == t                          # and shared with a later handle
     (ranks, Z, beta, used), = run_single(ci, prec, t)
     assert used == t
     for _, _, b, _ in tuned:
         assert np.array_equal(b, beta)
+    assert np.array_equal(b_other, beta)
 
 
 def test_fp64_core_has_one_tile():
