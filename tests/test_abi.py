@@ -92,3 +92,13 @@ def test_struct_offsets_match_a_c_compiler(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for fname, _ in py._fields_:
             assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
+    """No fallback: with the shared library absent, loading raises instead of
+    running anything else in its place."""
+    from paper_2201_12663_amd import rhosvd
+    monkeypatch.setattr(rhosvd, "_lib", None)
+    monkeypatch.setattr(rhosvd, "LIB_PATH", str(tmp_path / "librhosvd.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        rhosvd.load()
